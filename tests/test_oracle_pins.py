@@ -1,0 +1,384 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types an oracle formula: each compares the oracle with an
+independent computation (a library routine, a closed form derived by hand, a
+brute-force quantity, an inequality the paper proves) chosen so that a plausible
+mistake in the oracle (a dropped epsilon term, n instead of n - r, a wrong sign
+of eta, a wrong index of epsilon_t, a wrong normalisation) fails one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import meg_oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rand_spectrahedron(n, rng, rank=None):
+    rank = n if rank is None else rank
+    A = rng.standard_normal((n, rank))
+    X = A @ A.T
+    return X / np.trace(X)
+
+
+def rand_pd_spectrahedron(n, rng):
+    X = rand_spectrahedron(n, rng) + 1e-3 * np.eye(n)
+    return X / np.trace(X)
+
+
+def rand_sym(n, rng, scale=1.0):
+    A = rng.standard_normal((n, n))
+    return scale * (A + A.T) / 2
+
+
+# ---------------------------------------------------------------------------
+# golden values printed in the paper
+# ---------------------------------------------------------------------------
+def test_golden_epsilon_schedule():
+    """Section 7: eps_t = (4/5)/(t + c + 1)^2 with c = 10."""
+    with open(os.path.join(GOLDEN, "experiment_parameters.json")) as fh:
+        g = json.load(fh)
+    for t, want in g["eps_schedule"]["values"].items():
+        assert O.eps_schedule(int(t)) == pytest.approx(want, rel=1e-15)
+
+
+def test_lemma_eps_inequality():
+    """The approximation-error lemma (Section 3.1.1) uses log(1/(1-eps)) <= 2 eps
+    for eps <= 3/4 — the reason the library requires eps_0 in (0, 3/4]."""
+    e = np.linspace(1e-6, 0.75, 2000)
+    assert np.all(np.log(1.0 / (1.0 - e)) <= 2 * e + 1e-15)
+    assert math.log(1.0 / (1.0 - 0.8)) > 2 * 0.8  # fails beyond 3/4
+
+
+# ---------------------------------------------------------------------------
+# P8: Bregman distance of the von Neumann entropy (Section 2.2)
+# ---------------------------------------------------------------------------
+def test_bregman_commuting_is_kl():
+    """For commuting X, Y the distance is the KL divergence of the spectra."""
+    rng = np.random.default_rng(0)
+    n = 12
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    p = rng.random(n); p /= p.sum()
+    q = rng.random(n); q /= q.sum()
+    X = (Q * p) @ Q.T
+    Y = (Q * q) @ Q.T
+    kl = float(np.sum(p * np.log(p / q)))
+    assert O.bregman(X, Y) == pytest.approx(kl, rel=1e-10, abs=1e-13)
+    assert O.bregman(X, X) == pytest.approx(0.0, abs=1e-12)
+
+
+def test_bregman_strong_convexity_and_three_point():
+    """B(X,Y) >= 1/2 ||X-Y||_*^2 and the three-point identity with grad omega = log."""
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        n = int(rng.integers(3, 15))
+        X = rand_pd_spectrahedron(n, rng)
+        Y = rand_pd_spectrahedron(n, rng)
+        Z = rand_pd_spectrahedron(n, rng)
+        nuc = float(np.sum(np.abs(np.linalg.eigvalsh(X - Y))))
+        assert O.bregman(X, Y) >= 0.5 * nuc ** 2 - 1e-12
+        lhs = O.bregman(X, Y) + O.bregman(Y, Z) - O.bregman(X, Z)
+        rhs = float(np.sum((sla.logm(Z).real - sla.logm(Y).real) * (X - Y)))
+        assert lhs == pytest.approx(rhs, rel=1e-7, abs=1e-10)
+
+
+def test_matrix_functions_against_scipy():
+    rng = np.random.default_rng(2)
+    X = rand_pd_spectrahedron(9, rng)
+    A = rand_sym(9, rng)
+    np.testing.assert_allclose(O.mat_log(X), sla.logm(X).real, atol=1e-10)
+    np.testing.assert_allclose(O.mat_exp(A), sla.expm(A), rtol=1e-10, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# P1: exact MEG (Algorithm 1) on a linear objective from I/n
+# ---------------------------------------------------------------------------
+def test_exact_meg_linear_closed_form():
+    """With f = <C, X>, the exact MEG from Z_1 = I/n gives
+    Z_{t+1} = expm(-eta t C) / tr expm(-eta t C) (telescoping the mirror step)."""
+    rng = np.random.default_rng(3)
+    n, eta, T = 10, 0.37, 6
+    C = rand_sym(n, rng)
+    obj = O.LinearObjective(C)
+    Zs = O.run_exact_meg(obj, np.eye(n) / n, eta, T)
+    for t in range(1, T + 1):
+        E = sla.expm(-eta * t * C)
+        np.testing.assert_allclose(Zs[t], E / np.trace(E), atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# gradients against finite differences of the objective values
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["linear", "denoise", "masked", "quadmeas"])
+def test_gradients_match_finite_differences(kind):
+    rng = np.random.default_rng(4)
+    n = 9
+    X = rand_pd_spectrahedron(n, rng)
+    if kind == "linear":
+        obj = O.LinearObjective(rand_sym(n, rng))
+    elif kind == "denoise":
+        obj = O.DenoiseObjective(rand_sym(n, rng))
+    elif kind == "masked":
+        mask = np.triu(rng.random((n, n)) < 0.4)
+        mask = mask | mask.T
+        rows, cols = np.nonzero(mask)
+        rp = np.concatenate([[0], np.cumsum(mask.sum(1))])
+        M = rand_sym(n, rng)
+        obj = O.MaskedObjective(n, rp, cols, M[rows, cols])
+    else:
+        A = rng.standard_normal((n, 40))
+        b = rng.standard_normal(40)
+        obj = O.QuadMeasObjective(A, b)
+    G = obj.grad(X)
+    for _ in range(5):
+        H = rand_sym(n, rng)
+        h = 1e-5
+        fd = (obj.value(X + h * H) - obj.value(X - h * H)) / (2 * h)
+        assert float(np.sum(G * H)) == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# P2 / P6: low-rank MEG (Algorithm 2) on a linear objective, aligned start
+# ---------------------------------------------------------------------------
+def _closed_form_linear(n, r, eta, c, lam0, T, eps_params=(0.8, 10.0, 2.0)):
+    """Hand derivation: if V0 spans the eigenvectors of the r smallest
+    eigenvalues c_1..c_r of C and the order never changes, then
+    X_{t+1} = (1-eps_t) V0 diag(softmax(l0 - t eta c_{1:r})) V0^T + eps_t/(n-r) (I - V0 V0^T),
+    l0 = log((1 - eps_0) lam0 + eps_0/n), and the certificate uses
+    mu_i = log((1-eps_{t-1}) lt_{t-1,i}) - eta c_i,  mu_{r+1} = log(eps_{t-1}/(n-r)) - eta c_{r+1}
+    (t >= 2), with mu_i = l0_i - eta c_i, mu_{r+1} = log(eps_0/n) - eta c_{r+1} at t = 1."""
+    e = [O.eps_schedule(t, *eps_params) for t in range(T + 1)]
+    l0 = np.log((1 - e[0]) * lam0 + e[0] / n)
+    outs = []
+    lt_prev = None
+    for t in range(1, T + 1):
+        z = l0 - t * eta * c[:r]
+        lt = np.exp(z - z.max()); lt /= lt.sum()
+        alpha = e[t] / (n - r)
+        d = (1 - e[t]) * lt - alpha
+        if t == 1:
+            mu_top = l0 - eta * c[:r]
+            mu_next = math.log(e[0] / n) - eta * c[r]
+        else:
+            mu_top = np.log((1 - e[t - 1]) * lt_prev) - eta * c[:r]
+            mu_next = math.log(e[t - 1] / (n - r)) - eta * c[r]
+        mu = np.concatenate([mu_top, [mu_next]])
+        m = mu.max()
+        lse = m + math.log(np.sum(np.exp(mu - m)))
+        L = math.log(n - r) - math.log(e[t]) + mu_next - lse
+        outs.append((d, alpha, L))
+        lt_prev = lt
+    return outs
+
+
+@pytest.mark.parametrize("n,r", [(24, 1), (40, 3), (64, 5)])
+def test_lowrank_meg_linear_closed_form(n, r):
+    rng = np.random.default_rng(5 + n)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    c = np.concatenate([np.sort(rng.random(r)), 6.0 + np.sort(rng.random(n - r))])
+    C = (Q * c) @ Q.T
+    lam0 = rng.random(r) + 0.2; lam0 /= lam0.sum()
+    eta, T = 0.7, 12
+    V0 = Q[:, :r]
+    run = O.run_lowrank_meg(O.LinearObjective(C), V0, lam0, r, eta, T)
+    want = _closed_form_linear(n, r, eta, c, lam0, T)
+    P = V0 @ V0.T
+    for t in range(1, T + 1):
+        st = run["states"][t]
+        d, alpha, L = want[t - 1]
+        # X_{t+1} as a dense matrix, against the closed form
+        X_want = alpha * np.eye(n) + (V0 * d) @ V0.T
+        np.testing.assert_allclose(st.dense(), X_want, atol=1e-12)
+        assert run["L"][t - 1] == pytest.approx(L, rel=1e-9, abs=1e-9)
+        # P2 invariants: unit trace, positive definite, orthonormal V
+        Xd = st.dense()
+        assert np.trace(Xd) == pytest.approx(1.0, abs=1e-12)
+        assert np.linalg.eigvalsh(Xd).min() > 0
+        np.testing.assert_allclose(st.V.T @ st.V, np.eye(r), atol=1e-10)
+        np.testing.assert_allclose(st.V @ st.V.T, P, atol=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# P3: the approximation-error lemma of Section 3.1.1 (one step, small n)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(6))
+def test_lemma_error_bound_one_step(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(8, 20))
+    r = int(rng.integers(1, 4))
+    q = r
+    V, _ = np.linalg.qr(rng.standard_normal((n, q)))
+    lam = rng.random(q) + 0.05; lam /= lam.sum()
+    eps_prev = float(rng.uniform(0.05, 0.5))
+    it = O.FactoredIterate(V, (1 - eps_prev) * lam - eps_prev / (n - r), eps_prev / (n - r), 1)
+    # spectra kept within ~e^-20 of the top so dense FP64 logm stays accurate
+    G = rand_sym(n, rng, scale=float(rng.uniform(0.05, 0.6)))
+    eta = float(rng.uniform(0.1, 1.5))
+    eps = float(rng.uniform(0.01, 0.75))
+    new, info = O.lowrank_step(it, G, eta, eps, r)
+    Xp = new.dense()
+    Zp = info["Zplus"]
+    # Zp is the exact MEG step from the same point (independent: expm / logm)
+    A = sla.logm(it.dense()).real - eta * G
+    E = sla.expm(A)
+    np.testing.assert_allclose(Zp, E / np.trace(E), atol=1e-10)
+    bound = max(2 * eps, info["L_full"])
+    assert O.bregman(Zp, Xp) <= bound + 1e-10
+    for _ in range(3):  # any X* in the spectrahedron (the proof uses only that)
+        Xs = rand_spectrahedron(n, rng, rank=int(rng.integers(1, n)))
+        assert O.bregman(Xs, Xp) - O.bregman(Xs, Zp) <= bound + 1e-9
+    # spectrum of D = log Z_+ - log X_+ as derived in the lemma's proof
+    D = sla.logm(Zp).real - sla.logm(Xp).real
+    ev = np.linalg.eigvalsh(0.5 * (D + D.T))
+    mu = info["mu"]
+    b = np.exp(mu - mu.max()).sum()
+    a = np.exp(mu[:r] - mu.max()).sum()
+    top = np.full(r, math.log(a / b) + math.log(1 / (1 - eps)))
+    low = np.log((n - r) * np.exp(mu[r:] - mu.max()) / (eps * b))
+    want = np.sort(np.concatenate([top, low]))[::-1]
+    # eigenvalues of Z_+ below ~1e-9 carry dense-FP64 rounding; compare the
+    # well-conditioned top of the spectrum, which contains lambda_1(D)
+    m = int(np.sum(want > -12.0))
+    np.testing.assert_allclose(np.sort(ev)[::-1][:m], want[:m], atol=1e-7)
+    # cheap certificate is never looser than the full one (b_{r+1} <= b_n)
+    assert info["L"] >= info["L_full"] - 1e-12
+
+
+# ---------------------------------------------------------------------------
+# P4: the low-rank step is exact MEG when the lower spectrum is flat
+# ---------------------------------------------------------------------------
+def test_lowrank_equals_exact_when_tail_is_flat():
+    """If the n - r lower eigenvalues of M_t are equal and eps is the exact tail
+    mass, then D = 0 in the lemma's proof, i.e. X_+ = Z_+."""
+    rng = np.random.default_rng(7)
+    n, r = 16, 3
+    V, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    lam = rng.random(r) + 0.1; lam /= lam.sum()
+    e0 = 0.2
+    it = O.FactoredIterate(V, (1 - e0) * lam - e0 / (n - r), e0 / (n - r), 1)
+    g = rng.standard_normal(r)
+    G = (V * g) @ V.T  # gradient acting on span(V) only
+    eta = 0.9
+    mu_top = np.log((1 - e0) * lam) - eta * g
+    mu_low = math.log(e0 / (n - r))
+    allmu = np.concatenate([mu_top, np.full(n - r, mu_low)])
+    m = allmu.max()
+    tail = (n - r) * math.exp(mu_low - m) / np.exp(allmu - m).sum()
+    new, info = O.lowrank_step(it, G, eta, tail, r)
+    np.testing.assert_allclose(new.dense(), info["Zplus"], atol=1e-13)
+    E = sla.expm(sla.logm(it.dense()).real - eta * G)
+    np.testing.assert_allclose(new.dense(), E / np.trace(E), atol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# P5: gapped denoising — projection, convergence, certificate, Bregman decrease
+# ---------------------------------------------------------------------------
+def test_projection_kkt():
+    """X* = Pi_S(M) satisfies X* >= 0, tr X* = 1 and the variational
+    inequality <M - X*, Y - X*> <= 0 for all Y in S_n, i.e.
+    lambda_max(M - X*) <= <M - X*, X*>."""
+    rng = np.random.default_rng(8)
+    for _ in range(10):
+        n = int(rng.integers(4, 30))
+        M = rand_sym(n, rng, scale=float(rng.uniform(0.1, 3)))
+        Xs = O.project_spectrahedron(M)
+        w = np.linalg.eigvalsh(Xs)
+        assert w.min() > -1e-12
+        assert np.trace(Xs) == pytest.approx(1.0, abs=1e-12)
+        R = M - Xs
+        assert np.linalg.eigvalsh(R).max() <= float(np.sum(R * Xs)) + 1e-9
+
+
+def test_gapped_denoise_converges_with_certificate():
+    n, r, eta, T = 60, 1, 1.0, 40
+    rng = np.random.default_rng(9)
+    u = rng.standard_normal(n); u /= np.linalg.norm(u)
+    G = rng.standard_normal((n, n))
+    M = 2.0 * np.outer(u, u) + 0.01 * (G + G.T) / math.sqrt(2 * n)
+    obj = O.DenoiseObjective(M)
+    Xs = O.project_spectrahedron(M)
+    fstar = obj.value(Xs)
+    w, U = np.linalg.eigh(M)
+    run = O.run_lowrank_meg(obj, U[:, -1:], np.ones(1), r, eta, T)
+    f = np.array(run["f"])  # f[t-1] = f(X_t)
+    # every low-rank iterate keeps mass eps_{t-1} off the optimum, so the
+    # excess is first order in eps: f(X_t) - f* <= ||grad f(X*)||_2 ||X_t - X*||_*
+    # <= 2 eps_{t-1} ||grad f(X*)||_2 once V has converged
+    gnorm = float(np.abs(np.linalg.eigvalsh(Xs - M)).max())
+    eps_all = [O.eps_schedule(t) for t in range(T + 1)]
+    for t in range(2, T + 1):
+        assert f[t - 1] - fstar <= 2 * eps_all[t - 1] * gnorm + 1e-12
+    assert f[-1] - fstar < 0.1 * (f[0] - fstar)
+    # strict complementarity holds here: the cheap certificate holds throughout
+    L = np.array(run["L"])
+    eps = np.array(run["eps"])
+    assert np.all(L <= 2 * eps)
+    # Bregman near-monotonicity B(X*, X_{t+1}) <= B(X*, X_t) + 2 eps_t (soft)
+    B = [O.bregman(Xs, s.dense()) for s in run["states"]]
+    for t in range(1, T):
+        assert B[t + 1] <= B[t] + 2 * eps[t - 1] + 1e-9
+
+
+def test_certificate_cheap_vs_full_first_hold():
+    """Section 7 (table comparing b_t with b_t^{r+1}): the cheap certificate
+    never holds before the full one; on a strictly complementary instance both
+    hold from the first iteration."""
+    n, r, T = 50, 2, 15
+    rng = np.random.default_rng(10)
+    W = rng.standard_normal((n, r))
+    M = 1.5 * (W @ W.T) / np.sum(W * W) * r + 0.005 * rand_sym(n, rng)
+    obj = O.DenoiseObjective(M)
+    w, U = np.linalg.eigh(M)
+    lam0 = np.array([0.5, 0.5])
+    run = O.run_lowrank_meg(obj, U[:, -r:][:, ::-1], lam0, r, 1.0, T)
+    L = np.array(run["L"]); Lf = np.array(run["L_full"]); eps = np.array(run["eps"])
+    assert np.all(L >= Lf - 1e-12)
+    holds, holds_f = L <= 2 * eps, Lf <= 2 * eps
+    assert np.all(holds <= holds_f)
+    assert holds[0] and holds_f[0]
+
+
+def test_initial_iterate_levels():
+    """Algorithm 2 initialisation: complement level eps_0/n, unit trace."""
+    rng = np.random.default_rng(11)
+    n, q = 20, 2
+    V, _ = np.linalg.qr(rng.standard_normal((n, q)))
+    lam = np.array([0.7, 0.3])
+    it = O.initial_iterate(V, lam, 0.1)
+    X = it.dense()
+    X0 = (V * lam) @ V.T
+    np.testing.assert_allclose(X, 0.9 * X0 + 0.1 / n * np.eye(n), atol=1e-15)
+    assert np.trace(X) == pytest.approx(1.0)
+
+
+def test_factored_diff_matches_dense():
+    rng = np.random.default_rng(12)
+    n = 30
+    Va, _ = np.linalg.qr(rng.standard_normal((n, 4)))
+    Vb = rng.standard_normal((n, 3))  # not orthonormal on purpose
+    da, db = rng.random(4), rng.random(3)
+    Xa = 0.01 * np.eye(n) + (Va * da) @ Va.T
+    Xb = 0.02 * np.eye(n) + (Vb * db) @ Vb.T
+    assert O.factored_diff_frob(Va, da, 0.01, Vb, db, 0.02) == pytest.approx(np.linalg.norm(Xa - Xb), rel=1e-12)
+    assert O.factored_frob(Va, da, 0.01) == pytest.approx(np.linalg.norm(Xa), rel=1e-12)
+
+
+def test_lowrank_vs_exact_meg_trajectory_gapped():
+    """Section 7 compares low-rank and exact MEG trajectories: with strict
+    complementarity the Bregman distance between the iterates stays small."""
+    n, r, eta, T = 40, 1, 1.0, 20
+    rng = np.random.default_rng(13)
+    u = rng.standard_normal(n); u /= np.linalg.norm(u)
+    M = 2.0 * np.outer(u, u) + 0.01 * rand_sym(n, rng) / math.sqrt(n)
+    obj = O.DenoiseObjective(M)
+    w, U = np.linalg.eigh(M)
+    lr = O.run_lowrank_meg(obj, U[:, -1:], np.ones(1), r, eta, T)
+    ex = O.run_exact_meg(obj, lr["states"][0].dense(), eta, T)
+    for t in range(T + 1):
+        assert O.bregman(ex[t], lr["states"][t].dense()) < 0.05
+    assert abs(obj.value(ex[-1]) - obj.value(lr["states"][-1].dense())) < 1e-3
