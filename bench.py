@@ -1,0 +1,176 @@
+"""Benchmark: low-rank MEG iterations/s on one MI355X.
+
+Default workload: the matrix-completion objective at n = 4096, rank-5 ground
+truth, symmetric Bernoulli(0.1) mask (~1.68M stored entries, CSR), rank
+parameter r = 10, FP32 state, warm start of the paper's experiments.  One
+"step" is one full iteration t -> t+1 of the low-rank MEG method (gradient on
+the mask, warm-started block subspace iteration with Rayleigh-Ritz,
+exponentiation/normalisation, certificate).
+
+Prints ONE JSON line (see the contract in the repository documentation):
+metric/value/unit, ms_per_step, a roofline object for the dominant kernel
+(the CSR operator apply, HBM-bound) and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def matrix_completion_workload(n: int, r: int, seed: int):
+    import numpy as np
+
+    import workloads as W
+
+    t0 = time.time()
+    p = W.matrix_completion(n, seed=seed, rank=5, p=0.1, r=r, dtype=np.float32)
+    log(f"[bench] workload n={n} nnz={p.nnz} r={r} generated in {time.time() - t0:.1f}s")
+    return p
+
+
+def apply_bytes(n: int, nnz: int, k: int, r: int, es: int) -> int:
+    """Algorithmic HBM bytes of one CSR operator apply: every stored entry's
+    column index and gradient value once, the row pointers, the input block
+    Zin (n x k) once, the output block written once, and V (n x r) once."""
+    return nnz * (4 + es) + n * 4 + n * es * (2 * k + r)
+
+
+def cpu_baseline(p, r: int, samples: int):
+    """The FP64 oracle as it stands, on the same problem: `samples` iterations
+    (dense gradient, top-(r+1) LAPACK eigendecomposition)."""
+    import numpy as np
+
+    from oracle import meg_oracle as O
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    obj = O.MaskedObjective(p.n, p.row_ptr, p.col, p.val.astype(np.float64))
+    it = O.initial_iterate(p.V0, p.lam0, O.eps_schedule(0), p.n)
+    t0 = time.time()
+    done = 0
+    for t in range(1, samples + 1):
+        X = it.dense()
+        G = obj.grad(X)
+        it, _ = O.lowrank_step(it, G, 1.0, O.eps_schedule(t), r, full=False)
+        done += 1
+    dt = time.time() - t0
+    return {"value": done / dt, "unit": "iter/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done} iterations of the FP64 oracle (dense n x n gradient, LAPACK top-(r+1) eigh) "
+                      f"at n={p.n}, r={r} from the same warm start; {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--r", type=int, default=10)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--cpu-samples", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2012_10469_amd import meg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    p = matrix_completion_workload(args.n, args.r, args.seed)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    rp, col, val = dev(p.row_ptr.astype(np.int32)), dev(p.col.astype(np.int32)), dev(p.val)
+    stream = torch.cuda.Stream()  # default priority; graph replay needs a non-null stream
+    torch.cuda.synchronize()
+    g = meg.LowRankMEG(p.n, args.r, meg.MEG_GRAD_MASKED_CSR, p.V0, p.lam0, prec=meg.MEG_PREC_F32, eta=1.0,
+                       row_ptr=rp, col=col, val=val, max_inner=12, stream=stream.cuda_stream)
+    k = g.k
+    log(f"[bench] context ready k={k}; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        g.step(info=False)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.step(info=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    secs = t1 - t0
+    cert = g.certificate()
+    log(f"[bench] {args.steps} steps in {secs:.3f}s; last step inner sweeps {cert['inner_iters']} "
+        f"cert_L {cert['cert_L']:.4f} eps {cert['eps_t']:.3e}")
+
+    # per-kernel HIP-event timing on the same stream
+    sweeps, prep, fin, tot, act = [], [], [], [], []
+    for _ in range(args.profile_steps):
+        pr = g.profile_step()
+        a = pr["sweeps_active"]
+        sweeps += pr["sweep_ms"][:a]
+        prep.append(pr["prep_ms"])
+        fin.append(pr["finalize_ms"])
+        tot.append(pr["total_ms"])
+        act.append(a)
+    avg_apply_ms = float(np.mean(sweeps))
+    nbytes = apply_bytes(p.n, p.nnz, k, args.r, 4)
+    achieved = nbytes / (avg_apply_ms * 1e-3) / 1e9
+    log(f"[bench] apply avg {avg_apply_ms * 1e3:.1f} us over {len(sweeps)} launches; grad {np.mean(prep) * 1e3:.1f} us; "
+        f"finalize {np.mean(fin) * 1e3:.1f} us; eager step {np.mean(tot) * 1e3:.1f} us; sweeps/step {np.mean(act):.2f}")
+
+    base = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle baseline: {args.cpu_samples} iterations")
+        base = cpu_baseline(p, args.r, args.cpu_samples)
+    g.close()
+
+    out = {
+        "metric": "low-rank MEG iterations/s (matrix completion, n=4096, r=10, FP32)",
+        "value": args.steps / secs,
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "matrix_completion_csr", "n": p.n, "r": args.r, "k": k, "nnz": p.nnz,
+                   "mask_p": 0.1, "truth_rank": 5, "eta": 1.0, "eps": "0.8/(t+11)^2",
+                   "sweeps_per_step": float(np.mean(act))},
+        "roofline": {"bound": "hbm", "kernel": "k_apply_csr", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": nbytes, "avg_launch_us": avg_apply_ms * 1e3},
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

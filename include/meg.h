@@ -1,0 +1,222 @@
+/*
+ * meg.h - C ABI of the MI355X low-rank Matrix Exponentiated Gradient library.
+ *
+ * Method: D. Garber, A. Kaplan, "On the Efficient Implementation of the Matrix
+ * Exponentiated Gradient Algorithm for Low-Rank Matrix Optimization"
+ * (arXiv 2012.10469).  The library minimises a convex f over the spectrahedron
+ * S_n = {X symmetric, X >= 0, tr X = 1} (Section 1, problem (1)) with the
+ * low-rank MEG method (Section 3, Definition 1 and Algorithm 2): the iterate is
+ * kept in the factored form X_t = alpha I + V diag(d) V^T of Section 3, each
+ * step forms M_t = log X_t - eta grad f(X_t) implicitly, finds its top r + 1
+ * eigenpairs by warm-started block subspace iteration with Rayleigh-Ritz
+ * (Section 3, the subspace-iteration discussion), exponentiates and normalises
+ * the top r, and evaluates the cheap convergence certificate with b_{r+1}
+ * (Section 3.1.1 and Section 7).
+ *
+ * Conventions for every entry point:
+ *  - Every call returns meg_status; no C++ exception crosses the ABI.
+ *  - Pointers documented as DEVICE are HIP device pointers (e.g. a tensor's
+ *    data_ptr()); they are BORROWED: the caller keeps them alive and unchanged
+ *    until meg_destroy.  Pointers documented as HOST are read (or written)
+ *    during the call only.
+ *  - All device work is enqueued on the stream given to meg_init (a
+ *    hipStream_t passed as void*; NULL = the default stream).  Calls that
+ *    return host data synchronise that stream.
+ *  - One host thread at a time per context.  After MEG_ERR_DEVICE the context
+ *    is sticky-failed and further calls return MEG_ERR_STATE.
+ *  - A certificate that does not hold is data, not an error (Section 7.4 shows
+ *    it is expected without strict complementarity).
+ */
+#ifndef MEG_H
+#define MEG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct meg_ctx_s* meg_ctx;
+
+typedef enum {
+  MEG_OK = 0,
+  MEG_ERR_INVALID_ARG = 1,   /* bad size, pointer, parameter or kind         */
+  MEG_ERR_OUT_OF_MEMORY = 2, /* device allocation failed                     */
+  MEG_ERR_DEVICE = 3,        /* a HIP call failed; the context is now failed */
+  MEG_ERR_NUMERIC = 4,       /* a Ritz value or gradient became non-finite   */
+  MEG_ERR_NOT_CONVERGED = 5, /* strict mode: inner solver hit max_inner      */
+  MEG_ERR_STATE = 6,         /* context previously failed, or bad state blob */
+  MEG_ERR_UNSUPPORTED = 7    /* valid but not implemented combination        */
+} meg_status;
+
+/* Arithmetic of the operator apply.  Small k x k solves (Gram matrices,
+ * Rayleigh-Ritz, Cholesky, exponentiation, certificate) are always FP64. */
+typedef enum {
+  MEG_PREC_F64 = 0,       /* state and data in double                         */
+  MEG_PREC_F32 = 1,       /* state and data in float                          */
+  MEG_PREC_F32_BF16X3 = 2 /* float state; dense data given as two bf16 planes
+                             hi + lo, applied with three bf16 MFMA products
+                             (hi*hi + hi*lo + lo*hi) accumulated in FP32      */
+} meg_precision;
+
+/* Objective, i.e. how grad f(X_t) is represented (Section 3: the cost of a
+ * step is dominated by multiplying the gradient with an n x k block; the
+ * paper notes sparse and low-rank gradients make this cheaper). */
+typedef enum {
+  MEG_GRAD_LINEAR_DENSE = 0,  /* f = <C, X>;            C dense n x n          */
+  MEG_GRAD_DENOISE_DENSE = 1, /* f = 1/2 ||X - M||_F^2; M dense n x n          */
+  MEG_GRAD_LINEAR_CSR = 2,    /* f = <C, X>;            C sparse symmetric CSR */
+  MEG_GRAD_MASKED_CSR = 3,    /* f = 1/2 sum_{(i,j) in Omega} (X_ij - M_ij)^2,
+                                 Omega symmetric, both (i,j) and (j,i) stored;
+                                 grad f = P_Omega(X - M)                       */
+  MEG_GRAD_QUADMEAS = 4       /* f = 1/(2m) sum_i (a_i^T X a_i - b_i)^2; each
+                                 step uses the minibatch estimate
+                                 (1/L) sum_{i in B_t} (a_i^T X a_i - b_i) a_i a_i^T
+                                 (Section 6, stochastic oracle)                */
+} meg_grad_kind;
+
+#define MEG_FLAG_STRICT 1u   /* inner non-convergence -> MEG_ERR_NOT_CONVERGED */
+#define MEG_FLAG_NO_GRAPH 2u /* launch kernels eagerly instead of replaying a
+                                captured HIP graph of one step                */
+
+typedef struct {
+  int64_t n;          /* dimension, n >= k (see meg_block_size)               */
+  int32_t r;          /* rank parameter, 1 <= r <= n - 1 (Algorithm 2)        */
+  int32_t oversample; /* p >= 0; block size k = roundup16(r + 1 + p) <= 32    */
+  int32_t prec;       /* meg_precision                                        */
+  int32_t min_inner;  /* subspace sweeps per step: at least (>= 1) ...        */
+  int32_t max_inner;  /* ... and at most (>= min_inner, <= 64)               */
+  uint32_t flags;     /* MEG_FLAG_*                                           */
+  double eta;         /* step size eta_t = eta > 0 (Algorithm 2 input)        */
+  double eps_scale;   /* eps_t = eps_scale / (t + eps_c + 1)^eps_pow, t >= 0; */
+  double eps_c;       /* Section 7 uses 0.8, 10, 2.  eps_0 must lie in        */
+  double eps_pow;     /* (0, 3/4] (the approximation-error lemma's range).    */
+  double inner_tol;   /* residual tolerance of the top-r Ritz pairs relative
+                         to the largest Ritz value; 0 selects 1e-10 (F64) or
+                         1e-6 (F32 forms).  Residuals are estimated from FP64
+                         Gram matrices, which resolve them down to about
+                         3e-8 of the scale; below that the solver runs two
+                         more sweeps after the estimate reaches that floor.   */
+  uint64_t seed;      /* seeds the solver's extra start columns               */
+  double cert_tol;    /* absolute residual tolerance of the (r+1)-th Ritz pair,
+                         whose value enters the certificate; 0 = do not iterate
+                         for it (its Ritz value is then a lower bound of
+                         mu_{r+1}, i.e. the reported certificate is optimistic) */
+} meg_params;
+
+typedef struct {
+  int32_t kind;  /* meg_grad_kind */
+  int32_t batch; /* QUADMEAS: minibatch size L (>= 1)                         */
+  /* dense kinds: DEVICE, n x n symmetric, row-major with leading dimension
+   * ld >= n; element type double (F64) or float (F32).  F32_BF16X3: `dense`
+   * is the bf16 hi plane and `dense_lo` the bf16 lo plane (hi + lo ~ M). */
+  const void* dense;
+  const void* dense_lo;
+  int64_t ld;
+  /* CSR kinds: DEVICE, symmetric pattern, int32 row_ptr[n+1], col[nnz]
+   * (sorted within each row), values val[nnz] in the state's type. */
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const void* val;
+  int64_t nnz;
+  /* QUADMEAS: DEVICE pool A (m rows of length lda >= n: row i is a_i, float
+   * or double), b[m], and the minibatch indices batch_idx[batch_steps * batch]
+   * (int32 in [0, m)); step t uses row (t - 1) mod batch_steps.  The indices
+   * are an input so that a run is reproducible. */
+  const void* A;
+  int64_t lda;
+  const void* b;
+  int64_t m;
+  const int32_t* batch_idx;
+  int64_t batch_steps;
+} meg_objective;
+
+typedef struct {
+  int32_t q;              /* number of start columns, 1 <= q <= r              */
+  int32_t reserved;
+  const double* V0;       /* HOST, n x q column-major, orthonormal columns     */
+  const double* lambda0;  /* HOST, q weights >= 0 summing to 1: X_0 = V0 diag(lambda0) V0^T */
+} meg_start;
+
+typedef struct {
+  int64_t t;          /* iteration index t of the step just taken (gradient at X_t) */
+  double f;           /* f(X_t) when requested, else NaN                      */
+  double eps_t;       /* approximation parameter used to form X_{t+1}         */
+  double cert_L;      /* log((n-r) lambda_{r+1}(Y_t) / (eps_t b^{r+1}_t))     */
+  double cert_bound;  /* max(2 eps_t, cert_L): bound of the error lemma       */
+  int32_t cert_holds; /* cert_L <= 2 eps_t                                    */
+  int32_t inner_iters;/* subspace sweeps used                                 */
+  double ritz_gap;    /* mu_r - mu_{r+1} (eigenvalues of M_t)                 */
+  double resid_max;   /* max Ritz residual over the top r pairs               */
+  double mu_r1;       /* mu_{r+1}                                             */
+  double sigma;       /* spectral shift used by the solver                    */
+  int32_t converged;  /* inner solver met its tolerance                       */
+  int32_t reserved;
+  double resid_r1;    /* Ritz residual of the (r+1)-th pair (certificate)     */
+} meg_step_info;
+
+/* Block size k used for (r, oversample); returns 0 when k would exceed 32. */
+int32_t meg_block_size(int32_t r, int32_t oversample);
+
+/* Create a context: validate, allocate device state, build the first iterate
+ * X_1 = (1 - eps_0) X_0 + (eps_0/n) I (Algorithm 2, initialisation).  The
+ * objective's device arrays are borrowed.  *out is NULL on failure. */
+meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective* obj,
+                    const meg_start* start, void* stream);
+
+/* One iteration t of Algorithm 2: X_t -> X_{t+1}.  info == NULL: enqueue only
+ * (asynchronous; f is not evaluated).  info != NULL: also evaluate f(X_t),
+ * synchronise and fill *info. */
+meg_status meg_step(meg_ctx ctx, meg_step_info* info);
+
+/* Up to max_iters iterations; stops early after the first step whose
+ * certificate bound max(2 eps_t, cert_L) is <= tol (tol <= 0: never).
+ * *last (optional) receives the last step's info (f = NaN). */
+meg_status meg_solve(meg_ctx ctx, int64_t max_iters, double tol, meg_step_info* last);
+
+/* Info of the most recent step (certificate, eps_t, gap ...); no kernel runs. */
+meg_status meg_certificate(meg_ctx ctx, meg_step_info* out);
+
+/* f at the current iterate X_t (one pass over the data). */
+meg_status meg_objective_value(meg_ctx ctx, double* f);
+
+/* Current iterate X_t = alpha I + V diag(d) V^T.  HOST outputs: V n x r
+ * column-major, d[r]; any output may be NULL. */
+meg_status meg_get_iterate(meg_ctx ctx, double* V, double* d, double* alpha, int64_t* t);
+
+/* Replace the iterate by X = alpha I + V diag(d) V^T with q <= r HOST columns
+ * (orthonormal), 0 < alpha, alpha + d_i > 0, and set the iteration index to t
+ * (so the next step uses eps_t).  Used for teacher-forced comparisons. */
+meg_status meg_set_iterate(meg_ctx ctx, const double* V, int32_t q, const double* d, double alpha,
+                           int64_t t);
+
+/* Serialise / restore the full solver state (iterate, warm-start basis and
+ * counters) for bitwise resume.  meg_get_state with buf == NULL sets *bytes. */
+meg_status meg_get_state(meg_ctx ctx, void* buf, size_t* bytes);
+meg_status meg_set_state(meg_ctx ctx, const void* buf, size_t bytes);
+
+/* Per-kernel timing of one step (measurement entry point).  Runs one full
+ * iteration t -> t+1 exactly as meg_step does, but launches its kernels
+ * eagerly with a HIP event pair around each one on the context's stream, and
+ * synchronises.  HOST output; times in milliseconds.  sweep_ms[s-1] is the
+ * operator-apply sweep s (including its Rayleigh-Ritz tail); only the first
+ * `sweeps_active` sweeps did work (later ones exit at once). */
+typedef struct {
+  double prep_ms;       /* gradient pass (masked CSR) or scalar setup      */
+  double sweep_ms[64];
+  double finalize_ms;
+  double total_ms;      /* first event to last event                       */
+  int32_t sweeps_active;
+  int32_t max_inner;
+} meg_kernel_times;
+
+meg_status meg_profile_step(meg_ctx ctx, meg_kernel_times* out);
+
+void meg_destroy(meg_ctx ctx);
+const char* meg_status_str(meg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MEG_H */

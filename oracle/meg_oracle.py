@@ -393,8 +393,8 @@ def dual_gap(X: np.ndarray, G: np.ndarray, tau: float = 1.0) -> float:
 # comparisons of factored iterates (FP64, no n x n matrix)
 # ---------------------------------------------------------------------------
 def factored_frob(V: np.ndarray, d: np.ndarray, alpha: float) -> float:
-    """||alpha I + V diag(d) V^T||_F computed from r x r Gram matrices."""
-    return math.sqrt(max(factored_diff_frob2(V, d, alpha, np.zeros((V.shape[0], 0)), np.zeros(0), 0.0), 0.0))
+    """||alpha I + V diag(d) V^T||_F without forming the matrix."""
+    return factored_diff_frob(V, d, alpha, np.zeros((np.asarray(V).shape[0], 0)), np.zeros(0), 0.0)
 
 
 def factored_diff_frob2(Va, da, aa, Vb, db, ab) -> float:
@@ -419,5 +419,21 @@ def factored_diff_frob(Va, da, aa, Vb, db, ab) -> float:
     """||X_a - X_b||_F for X = alpha I + V diag(d) V^T without forming X.
 
     Compares iterates, not eigenvectors: V is defined only up to sign and
-    rotation inside equal eigenvalues, X is not."""
-    return math.sqrt(max(factored_diff_frob2(Va, da, aa, Vb, db, ab), 0.0))
+    rotation inside equal eigenvalues, X is not.  With U = [V_a V_b] = Q R
+    (thin QR) and D = diag(d_a, -d_b), X_a - X_b = dA I + Q (R D R^T) Q^T, so
+    the norm splits into the 2r x 2r block dA I + R D R^T (formed entry by
+    entry) and dA on the n - 2r dimensional complement.  No difference of
+    squared norms is taken, so nearly equal iterates are resolved to rounding
+    level rather than to its square root."""
+    Va = np.asarray(Va, dtype=np.float64)
+    Vb = np.asarray(Vb, dtype=np.float64)
+    n = Va.shape[0]
+    U = np.concatenate([Va, Vb], axis=1)
+    D = np.concatenate([np.asarray(da, dtype=np.float64), -np.asarray(db, dtype=np.float64)])
+    dA = float(aa) - float(ab)
+    if U.shape[1] == 0:
+        return math.sqrt(n) * abs(dA)
+    Q, R = np.linalg.qr(U)
+    K = (R * D) @ R.T + dA * np.eye(R.shape[0])
+    rest = max(n - R.shape[0], 0)
+    return math.sqrt(float(np.sum(K * K)) + rest * dA * dA)

@@ -1,0 +1,309 @@
+"""ctypes binding of the MI355X low-rank MEG library (include/meg.h).
+
+The functions here marshal arguments only; every step of the method runs in
+the HIP kernels of ``libmeg.so``.  Importing this module loads the library and
+fails loudly if it has not been built (``python -m paper_2012_10469_amd.build``).
+
+Low-level names mirror the C ABI (``meg_init``, ``meg_step``, ``meg_solve``,
+``meg_certificate``, ...).  ``LowRankMEG`` is a thin convenience wrapper that
+keeps the borrowed device arrays alive for the context's lifetime.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Any, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmeg.so")
+
+# ---- enums (include/meg.h) -------------------------------------------------
+MEG_OK = 0
+MEG_ERR_INVALID_ARG = 1
+MEG_ERR_OUT_OF_MEMORY = 2
+MEG_ERR_DEVICE = 3
+MEG_ERR_NUMERIC = 4
+MEG_ERR_NOT_CONVERGED = 5
+MEG_ERR_STATE = 6
+MEG_ERR_UNSUPPORTED = 7
+
+MEG_PREC_F64 = 0
+MEG_PREC_F32 = 1
+MEG_PREC_F32_BF16X3 = 2
+
+MEG_GRAD_LINEAR_DENSE = 0
+MEG_GRAD_DENOISE_DENSE = 1
+MEG_GRAD_LINEAR_CSR = 2
+MEG_GRAD_MASKED_CSR = 3
+MEG_GRAD_QUADMEAS = 4
+
+MEG_FLAG_STRICT = 1
+MEG_FLAG_NO_GRAPH = 2
+
+EXPORTED = [
+    "meg_block_size", "meg_init", "meg_step", "meg_solve", "meg_certificate", "meg_objective_value",
+    "meg_get_iterate", "meg_set_iterate", "meg_get_state", "meg_set_state", "meg_profile_step", "meg_destroy",
+    "meg_status_str",
+]
+
+
+class MegParams(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("r", ctypes.c_int32), ("oversample", ctypes.c_int32),
+        ("prec", ctypes.c_int32), ("min_inner", ctypes.c_int32), ("max_inner", ctypes.c_int32),
+        ("flags", ctypes.c_uint32), ("eta", ctypes.c_double), ("eps_scale", ctypes.c_double),
+        ("eps_c", ctypes.c_double), ("eps_pow", ctypes.c_double), ("inner_tol", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("cert_tol", ctypes.c_double),
+    ]
+
+
+class MegObjective(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("batch", ctypes.c_int32),
+        ("dense", ctypes.c_void_p), ("dense_lo", ctypes.c_void_p), ("ld", ctypes.c_int64),
+        ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p), ("nnz", ctypes.c_int64),
+        ("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("b", ctypes.c_void_p), ("m", ctypes.c_int64),
+        ("batch_idx", ctypes.c_void_p), ("batch_steps", ctypes.c_int64),
+    ]
+
+
+class MegStart(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("V0", ctypes.POINTER(ctypes.c_double)), ("lambda0", ctypes.POINTER(ctypes.c_double))]
+
+
+class MegStepInfo(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_int64), ("f", ctypes.c_double), ("eps_t", ctypes.c_double), ("cert_L", ctypes.c_double),
+        ("cert_bound", ctypes.c_double), ("cert_holds", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
+        ("ritz_gap", ctypes.c_double), ("resid_max", ctypes.c_double), ("mu_r1", ctypes.c_double),
+        ("sigma", ctypes.c_double), ("converged", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("resid_r1", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class MegKernelTimes(ctypes.Structure):
+    _fields_ = [("prep_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double * 64), ("finalize_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double), ("sweeps_active", ctypes.c_int32), ("max_inner", ctypes.c_int32)]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmeg.so and declare the C signatures (raises if missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libmeg.so not built: {path} (run python -m paper_2012_10469_amd.build)")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    sig = {
+        "meg_block_size": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
+        "meg_init": (ctypes.c_int, [P(vp), P(MegParams), P(MegObjective), P(MegStart), vp]),
+        "meg_step": (ctypes.c_int, [vp, P(MegStepInfo)]),
+        "meg_solve": (ctypes.c_int, [vp, ctypes.c_int64, ctypes.c_double, P(MegStepInfo)]),
+        "meg_certificate": (ctypes.c_int, [vp, P(MegStepInfo)]),
+        "meg_objective_value": (ctypes.c_int, [vp, P(ctypes.c_double)]),
+        "meg_get_iterate": (ctypes.c_int, [vp, P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double),
+                                           P(ctypes.c_int64)]),
+        "meg_set_iterate": (ctypes.c_int, [vp, P(ctypes.c_double), ctypes.c_int32, P(ctypes.c_double),
+                                           ctypes.c_double, ctypes.c_int64]),
+        "meg_get_state": (ctypes.c_int, [vp, vp, P(ctypes.c_size_t)]),
+        "meg_set_state": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
+        "meg_profile_step": (ctypes.c_int, [vp, P(MegKernelTimes)]),
+        "meg_destroy": (None, [vp]),
+        "meg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class MegError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = load_library()
+        super().__init__(f"{where}: {lib.meg_status_str(status).decode()} (status {status})")
+        self.status = status
+
+
+def _check(status: int, where: str) -> None:
+    if status != MEG_OK:
+        raise MegError(status, where)
+
+
+def _dptr(t: Any) -> Optional[int]:
+    """Device pointer of a torch tensor (or an int address, or None)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return int(t.data_ptr())
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _dblp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ---- thin wrappers with the C names ----------------------------------------
+def meg_block_size(r: int, oversample: int) -> int:
+    return int(load_library().meg_block_size(r, oversample))
+
+
+def meg_status_str(status: int) -> str:
+    return load_library().meg_status_str(status).decode()
+
+
+def make_params(n, r, prec=MEG_PREC_F32, eta=1.0, oversample=4, eps=(0.8, 10.0, 2.0), min_inner=1,
+                max_inner=12, inner_tol=0.0, seed=0, flags=0, cert_tol=0.0) -> MegParams:
+    return MegParams(n=n, r=r, oversample=oversample, prec=prec, min_inner=min_inner, max_inner=max_inner,
+                     flags=flags, eta=eta, eps_scale=eps[0], eps_c=eps[1], eps_pow=eps[2], inner_tol=inner_tol,
+                     seed=seed, cert_tol=cert_tol)
+
+
+def meg_init(params: MegParams, obj: MegObjective, V0, lam0, stream: Optional[int] = None):
+    """Returns (status, ctx_handle).  V0 is n x q (host), lam0 length q."""
+    lib = load_library()
+    V0 = np.asarray(V0, dtype=np.float64)
+    if V0.ndim == 1:
+        V0 = V0[:, None]
+    Vc = np.asfortranarray(V0)  # n x q column-major
+    lam = _f64(lam0)
+    start = MegStart(q=Vc.shape[1], reserved=0, V0=Vc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                     lambda0=_dblp(lam))
+    ctx = ctypes.c_void_p()
+    st = lib.meg_init(ctypes.byref(ctx), ctypes.byref(params), ctypes.byref(obj), ctypes.byref(start),
+                      ctypes.c_void_p(stream) if stream else None)
+    return st, ctx
+
+
+class LowRankMEG:
+    """One low-rank MEG problem instance on the current HIP stream.
+
+    Device arrays (torch tensors) are borrowed by the library and referenced
+    here until ``close()``.  Dense data: ``dense`` (n x n, float64 for F64,
+    float32 for F32).  CSR data: ``row_ptr``/``col`` int32, ``val``.
+    """
+
+    def __init__(self, n: int, r: int, kind: int, V0, lam0, *, prec: int = MEG_PREC_F32, eta: float = 1.0,
+                 dense=None, row_ptr=None, col=None, val=None, oversample: int = 4,
+                 eps=(0.8, 10.0, 2.0), min_inner: int = 1, max_inner: int = 12, inner_tol: float = 0.0,
+                 seed: int = 0, flags: int = 0, cert_tol: float = 0.0, stream: Optional[int] = None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("LowRankMEG needs a visible GPU")
+        self._lib = load_library()
+        self._keep = [dense, row_ptr, col, val]
+        self.n, self.r = int(n), int(r)
+        self.kind = kind
+        obj = MegObjective(kind=kind, batch=0, dense=_dptr(dense), dense_lo=None,
+                           ld=int(dense.stride(0)) if dense is not None else 0,
+                           row_ptr=_dptr(row_ptr), col=_dptr(col), val=_dptr(val),
+                           nnz=int(col.numel()) if col is not None else 0,
+                           A=None, lda=0, b=None, m=0, batch_idx=None, batch_steps=0)
+        params = make_params(n, r, prec, eta, oversample, eps, min_inner, max_inner, inner_tol, seed, flags,
+                             cert_tol)
+        if stream is None:
+            # a dedicated (default-priority) stream: graph capture needs a
+            # stream other than the legacy null stream
+            self._torch_stream = torch.cuda.Stream()
+            stream = self._torch_stream.cuda_stream
+        torch.cuda.synchronize()  # uploads on other streams are complete
+        self.stream = stream
+        st, ctx = meg_init(params, obj, V0, lam0, stream)
+        _check(st, "meg_init")
+        self._ctx = ctx
+        self.k = meg_block_size(r, oversample)
+
+    # -- C ABI calls --
+    def step(self, info: bool = True) -> Optional[dict]:
+        if not info:
+            _check(self._lib.meg_step(self._ctx, None), "meg_step")
+            return None
+        out = MegStepInfo()
+        _check(self._lib.meg_step(self._ctx, ctypes.byref(out)), "meg_step")
+        return out.as_dict()
+
+    def solve(self, max_iters: int, tol: float = 0.0) -> dict:
+        out = MegStepInfo()
+        _check(self._lib.meg_solve(self._ctx, int(max_iters), float(tol), ctypes.byref(out)), "meg_solve")
+        return out.as_dict()
+
+    def certificate(self) -> dict:
+        out = MegStepInfo()
+        _check(self._lib.meg_certificate(self._ctx, ctypes.byref(out)), "meg_certificate")
+        return out.as_dict()
+
+    def objective(self) -> float:
+        f = ctypes.c_double()
+        _check(self._lib.meg_objective_value(self._ctx, ctypes.byref(f)), "meg_objective_value")
+        return f.value
+
+    def get_iterate(self):
+        """Returns (V n x r float64, d r, alpha, t)."""
+        V = np.zeros((self.r, self.n), dtype=np.float64)  # column-major n x r == row-major r x n
+        d = np.zeros(self.r)
+        a = ctypes.c_double()
+        t = ctypes.c_int64()
+        _check(self._lib.meg_get_iterate(self._ctx, _dblp(V), _dblp(d), ctypes.byref(a), ctypes.byref(t)),
+               "meg_get_iterate")
+        return V.T.copy(), d, a.value, t.value
+
+    def set_iterate(self, V, d, alpha: float, t: int) -> None:
+        V = np.asarray(V, dtype=np.float64)
+        Vc = np.asfortranarray(V)
+        dd = _f64(d)
+        _check(self._lib.meg_set_iterate(self._ctx, Vc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         int(Vc.shape[1]), _dblp(dd), float(alpha), int(t)), "meg_set_iterate")
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_size_t()
+        _check(self._lib.meg_get_state(self._ctx, None, ctypes.byref(n)), "meg_get_state")
+        buf = ctypes.create_string_buffer(n.value)
+        _check(self._lib.meg_get_state(self._ctx, buf, ctypes.byref(n)), "meg_get_state")
+        return buf.raw[: n.value]
+
+    def set_state(self, blob: bytes) -> None:
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(self._lib.meg_set_state(self._ctx, buf, len(blob)), "meg_set_state")
+
+    def profile_step(self) -> dict:
+        """Run one step with per-kernel HIP event timing (milliseconds)."""
+        out = MegKernelTimes()
+        _check(self._lib.meg_profile_step(self._ctx, ctypes.byref(out)), "meg_profile_step")
+        return {"prep_ms": out.prep_ms, "sweep_ms": [out.sweep_ms[i] for i in range(out.max_inner)],
+                "finalize_ms": out.finalize_ms, "total_ms": out.total_ms, "sweeps_active": out.sweeps_active}
+
+    def close(self) -> None:
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self._lib.meg_destroy(self._ctx)
+            self._ctx = None
+        self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,70 @@
+"""Shared helpers of the GPU parity tests: device upload, running the HIP path
+through the C ABI, and comparing factored iterates with the oracle's."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from oracle import meg_oracle as O
+
+# tolerances (relative Frobenius error of X; relative objective error)
+TOL_X = {0: 1e-9, 1: 1e-5, 2: 1e-3}
+TOL_F = 1e-6
+UNIT = {0: 2.0 ** -53, 1: 2.0 ** -24, 2: 2.0 ** -24}
+
+
+def torch_dtype(prec):
+    import torch
+
+    return torch.float64 if prec == 0 else torch.float32
+
+
+def np_dtype(prec):
+    return np.float64 if prec == 0 else np.float32
+
+
+def dev(a, dtype=None):
+    import torch
+
+    t = torch.as_tensor(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda().contiguous()
+
+
+def make_dense(M_, kind, V0, lam0, r, prec, **kw):
+    from paper_2012_10469_amd import meg
+
+    D = dev(np.asarray(M_, dtype=np_dtype(prec)))
+    return meg.LowRankMEG(D.shape[0], r, kind, V0, lam0, prec=prec, dense=D, **kw)
+
+
+def make_csr(p, kind, r, prec, V0=None, lam0=None, **kw):
+    from paper_2012_10469_amd import meg
+    import torch
+
+    rp = dev(p.row_ptr.astype(np.int32))
+    col = dev(p.col.astype(np.int32))
+    val = dev(p.val.astype(np_dtype(prec)))
+    V0 = p.V0 if V0 is None else V0
+    lam0 = p.lam0 if lam0 is None else lam0
+    return meg.LowRankMEG(p.n, r, kind, V0, lam0, prec=prec, row_ptr=rp, col=col, val=val, **kw)
+
+
+def rel_x_err(gpu_state, it: O.FactoredIterate) -> float:
+    V, d, a, _ = gpu_state
+    num = O.factored_diff_frob(V, d, a, it.V, it.d, it.alpha)
+    return num / O.factored_frob(it.V, it.d, it.alpha)
+
+
+def f_tol(f_ref: float, gradnorm_f: float, xnorm_f: float, prec: int) -> float:
+    """|f_gpu - f_ref| allowance: TOL_F relative, plus the first-order effect of
+    rounding the iterate to the working precision (|<grad f, dX>| with
+    ||dX||_F <= 4 u ||X||_F)."""
+    return TOL_F * abs(f_ref) + 4.0 * UNIT[prec] * gradnorm_f * xnorm_f
+
+
+def oracle_state_at(run, t):
+    """Oracle iterate X_t (t >= 1)."""
+    return run["states"][t - 1]

@@ -1,0 +1,148 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/meg.h, the ctypes structures match the C layout (checked
+against a gcc-compiled probe), and argument validation rejects bad inputs
+before any device call."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "meg.h")
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2012_10469_amd import meg
+
+    if not os.path.exists(meg.LIB_PATH):
+        from paper_2012_10469_amd import build
+
+        build.build()
+    meg.load_library()
+    return meg
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:meg_status|int32_t|void|const char\*)\s+(meg_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(M):
+    names = declared_functions()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(M.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(M.EXPORTED) == names
+
+
+def test_struct_layout_matches_header(M):
+    probe = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "meg.h"
+#define P(T) printf(#T " %zu\n", sizeof(T));
+#define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  P(meg_params) P(meg_objective) P(meg_start) P(meg_step_info)
+  O(meg_params, eta) O(meg_params, seed) O(meg_params, flags) O(meg_params, inner_tol)
+  O(meg_objective, dense) O(meg_objective, ld) O(meg_objective, nnz) O(meg_objective, batch_idx)
+  O(meg_objective, batch_steps) O(meg_start, V0) O(meg_start, lambda0)
+  O(meg_step_info, cert_holds) O(meg_step_info, ritz_gap) O(meg_step_info, converged) O(meg_step_info, resid_r1)
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "p.c")
+        exe = os.path.join(d, "p")
+        open(c, "w").write(probe)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    want = {}
+    for line in out.strip().splitlines():
+        k, v = line.split()
+        want[k] = int(v)
+    S = {"meg_params": M.MegParams, "meg_objective": M.MegObjective, "meg_start": M.MegStart,
+         "meg_step_info": M.MegStepInfo, "meg_kernel_times": M.MegKernelTimes}
+    for k, v in want.items():
+        if "." in k:
+            s, f = k.split(".")
+            assert getattr(S[s], f).offset == v, k
+        else:
+            assert ctypes.sizeof(S[k]) == v, k
+
+
+def test_block_size_and_status_strings(M):
+    assert M.meg_block_size(10, 4) == 16
+    assert M.meg_block_size(5, 4) == 16
+    assert M.meg_block_size(16, 4) == 32
+    assert M.meg_block_size(27, 4) == 32
+    assert M.meg_block_size(28, 4) == 0
+    assert M.meg_block_size(0, 4) == 0
+    assert M.meg_block_size(3, -1) == 0
+    for s in range(8):
+        assert isinstance(M.meg_status_str(s), str) and M.meg_status_str(s)
+
+
+def _start(n, q=1):
+    V = np.zeros((n, q))
+    V[np.arange(q), np.arange(q)] = 1.0
+    return V, np.full(q, 1.0 / q)
+
+
+def _dense_obj(M, kind=0):
+    # fake (never dereferenced) device address: validation fails first
+    return M.MegObjective(kind=kind, dense=0x1000, ld=64)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n", 1), ("r", 0), ("r", 64), ("oversample", -1), ("r", 28), ("prec", 7), ("eta", 0.0),
+    ("eta", float("nan")), ("eps_scale", 0.0), ("eps_scale", 100.0), ("min_inner", 0), ("max_inner", 0),
+    ("max_inner", 65), ("inner_tol", -1.0),
+])
+def test_init_rejects_bad_params(M, field, value):
+    n = 64
+    p = M.make_params(n, 4)
+    setattr(p, field, value)
+    V, lam = _start(n)
+    st, ctx = M.meg_init(p, _dense_obj(M), V, lam)
+    assert st == M.MEG_ERR_INVALID_ARG
+    assert not ctx.value
+
+
+def test_init_rejects_bad_start_and_objective(M):
+    n = 64
+    p = M.make_params(n, 4)
+    V, lam = _start(n, 2)
+    assert M.meg_init(p, _dense_obj(M), V, np.array([0.7, 0.7]))[0] == M.MEG_ERR_INVALID_ARG  # sum != 1
+    assert M.meg_init(p, _dense_obj(M), V, np.array([1.2, -0.2]))[0] == M.MEG_ERR_INVALID_ARG  # negative
+    Vbad = V.copy(); Vbad[0, 1] = 0.5
+    assert M.meg_init(p, _dense_obj(M), Vbad, lam)[0] == M.MEG_ERR_INVALID_ARG  # not orthonormal
+    V5, lam5 = _start(n, 5)
+    assert M.meg_init(p, _dense_obj(M), V5, lam5)[0] == M.MEG_ERR_INVALID_ARG  # q > r
+    assert M.meg_init(p, M.MegObjective(kind=0, dense=None, ld=64), V, lam)[0] == M.MEG_ERR_INVALID_ARG
+    assert M.meg_init(p, M.MegObjective(kind=0, dense=0x1000, ld=10), V, lam)[0] == M.MEG_ERR_INVALID_ARG
+    assert M.meg_init(p, M.MegObjective(kind=9, dense=0x1000, ld=64), V, lam)[0] == M.MEG_ERR_INVALID_ARG
+    assert M.meg_init(p, M.MegObjective(kind=3, row_ptr=None), V, lam)[0] == M.MEG_ERR_INVALID_ARG
+    assert M.meg_init(p, M.MegObjective(kind=3, row_ptr=0x1000, nnz=5, col=None, val=0x1000), V, lam)[0] \
+        == M.MEG_ERR_INVALID_ARG
+    # k = 16 > n
+    p2 = M.make_params(12, 4)
+    assert M.meg_init(p2, M.MegObjective(kind=0, dense=0x1000, ld=12), _start(12)[0], _start(12)[1])[0] \
+        == M.MEG_ERR_INVALID_ARG
+
+
+def test_null_context_calls(M):
+    lib = M.load_library()
+    info = M.MegStepInfo()
+    assert lib.meg_step(None, ctypes.byref(info)) == M.MEG_ERR_INVALID_ARG
+    assert lib.meg_solve(None, 1, 0.0, None) == M.MEG_ERR_INVALID_ARG
+    assert lib.meg_certificate(None, ctypes.byref(info)) == M.MEG_ERR_INVALID_ARG
+    lib.meg_destroy(None)  # no-op

@@ -382,3 +382,22 @@ def test_lowrank_vs_exact_meg_trajectory_gapped():
     for t in range(T + 1):
         assert O.bregman(ex[t], lr["states"][t].dense()) < 0.05
     assert abs(obj.value(ex[-1]) - obj.value(lr["states"][-1].dense())) < 1e-3
+
+
+def test_factored_diff_resolves_tiny_differences():
+    """Nearly equal iterates: the difference is resolved to rounding level
+    (a difference-of-squares formula would floor near 1e-8 relative)."""
+    rng = np.random.default_rng(14)
+    n, r = 80, 4
+    V, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    d = rng.random(r)
+    a = 1e-3
+    for delta in (1e-9, 1e-12):
+        d2 = d.copy(); d2[0] += delta
+        got = O.factored_diff_frob(V, d, a, V, d2, a)
+        assert got == pytest.approx(delta, rel=1e-3)
+        G = rng.standard_normal((n, r)) * delta
+        V2, _ = np.linalg.qr(V + G)
+        Xa = a * np.eye(n) + (V * d) @ V.T
+        Xb = a * np.eye(n) + (V2 * d) @ V2.T
+        assert O.factored_diff_frob(V, d, a, V2, d, a) == pytest.approx(np.linalg.norm(Xa - Xb), rel=1e-2)
