@@ -49,6 +49,15 @@ def apply_bytes(n: int, nnz: int, k: int, r: int, es: int) -> int:
     return nnz * (4 + es) + n * 4 + n * es * (2 * k + r)
 
 
+def step_bytes(n: int, nnz: int, k: int, r: int, es: int, sweeps: float) -> float:
+    """Algorithmic HBM bytes of one iteration: the gradient pass (column index
+    and M_Omega read, gradient value written, row pointers, V read), `sweeps`
+    operator applies, and the basis update (read n x k, write n x k)."""
+    grad = nnz * (4 + es + es) + n * 4 + n * es * r
+    fin = 2 * n * k * es
+    return grad + sweeps * apply_bytes(n, nnz, k, r, es) + fin
+
+
 def cpu_baseline(p, r: int, samples: int):
     """The FP64 oracle as it stands, on the same problem: `samples` iterations
     (dense gradient, top-(r+1) LAPACK eigendecomposition)."""
@@ -88,6 +97,8 @@ def main() -> int:
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--cpu-samples", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch-steps", type=int, default=64,
+                    help="iterations per launch of the persistent step kernel (1: one meg_step per iteration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -110,14 +121,24 @@ def main() -> int:
     g = meg.LowRankMEG(p.n, args.r, meg.MEG_GRAD_MASKED_CSR, p.V0, p.lam0, prec=meg.MEG_PREC_F32, eta=1.0,
                        row_ptr=rp, col=col, val=val, max_inner=12, stream=stream.cuda_stream)
     k = g.k
+
+    def run(steps: int) -> None:
+        if args.launch_steps <= 1:
+            for _ in range(steps):
+                g.step(info=False)
+        else:
+            left = steps
+            while left > 0:
+                m = min(args.launch_steps, left)
+                g.solve(m)
+                left -= m
+
     log(f"[bench] context ready k={k}; warmup {args.warmup}")
-    for _ in range(args.warmup):
-        g.step(info=False)
+    run(args.warmup)
     torch.cuda.synchronize()
-    log(f"[bench] timing {args.steps} steps")
+    log(f"[bench] timing {args.steps} steps ({args.launch_steps} per launch)")
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g.step(info=False)
+    run(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     secs = t1 - t0
@@ -125,21 +146,25 @@ def main() -> int:
     log(f"[bench] {args.steps} steps in {secs:.3f}s; last step inner sweeps {cert['inner_iters']} "
         f"cert_L {cert['cert_L']:.4f} eps {cert['eps_t']:.3e}")
 
-    # per-kernel HIP-event timing on the same stream
-    sweeps, prep, fin, tot, act = [], [], [], [], []
+    # one-step launches with HIP events around the step kernel, on its stream,
+    # plus the kernel's own phase stamps
+    kms, prep, fin, act, app, small = [], [], [], [], [], []
     for _ in range(args.profile_steps):
         pr = g.profile_step()
-        a = pr["sweeps_active"]
-        sweeps += pr["sweep_ms"][:a]
+        kms.append(pr["kernel_ms"])
         prep.append(pr["prep_ms"])
         fin.append(pr["finalize_ms"])
-        tot.append(pr["total_ms"])
-        act.append(a)
-    avg_apply_ms = float(np.mean(sweeps))
-    nbytes = apply_bytes(p.n, p.nnz, k, args.r, 4)
-    achieved = nbytes / (avg_apply_ms * 1e-3) / 1e9
-    log(f"[bench] apply avg {avg_apply_ms * 1e3:.1f} us over {len(sweeps)} launches; grad {np.mean(prep) * 1e3:.1f} us; "
-        f"finalize {np.mean(fin) * 1e3:.1f} us; eager step {np.mean(tot) * 1e3:.1f} us; sweeps/step {np.mean(act):.2f}")
+        act.append(pr["sweeps_active"])
+        app += pr["apply_ms"]
+        small += pr["small_ms"]
+    avg_kernel_ms = float(np.mean(kms))
+    sweeps = float(np.mean(act))
+    nbytes = step_bytes(p.n, p.nnz, k, args.r, 4, sweeps)
+    achieved = nbytes / (avg_kernel_ms * 1e-3) / 1e9
+    apply_gbs = apply_bytes(p.n, p.nnz, k, args.r, 4) / (float(np.mean(app)) * 1e-3) / 1e9
+    log(f"[bench] step kernel {avg_kernel_ms * 1e3:.1f} us (grid {pr['workgroups']} WGs): grad {np.mean(prep) * 1e3:.1f} us, "
+        f"apply {np.mean(app) * 1e3:.1f} us x {sweeps:.2f} ({apply_gbs:.0f} GB/s), reduce+RR {np.mean(small) * 1e3:.1f} us, "
+        f"finalize {np.mean(fin) * 1e3:.1f} us")
 
     base = None
     if not args.no_cpu_baseline:
@@ -162,10 +187,11 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "matrix_completion_csr", "n": p.n, "r": args.r, "k": k, "nnz": p.nnz,
                    "mask_p": 0.1, "truth_rank": 5, "eta": 1.0, "eps": "0.8/(t+11)^2",
-                   "sweeps_per_step": float(np.mean(act))},
-        "roofline": {"bound": "hbm", "kernel": "k_apply_csr", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": nbytes, "avg_launch_us": avg_apply_ms * 1e3},
+                   "sweeps_per_step": sweeps, "steps_per_launch": args.launch_steps},
+        "roofline": {"bound": "hbm", "kernel": "k_step (persistent, one iteration per launch)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": nbytes, "avg_launch_us": avg_kernel_ms * 1e3,
+                     "apply_phase_gbs": apply_gbs},
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)

@@ -77,8 +77,6 @@ typedef enum {
 } meg_grad_kind;
 
 #define MEG_FLAG_STRICT 1u   /* inner non-convergence -> MEG_ERR_NOT_CONVERGED */
-#define MEG_FLAG_NO_GRAPH 2u /* launch kernels eagerly instead of replaying a
-                                captured HIP graph of one step                */
 
 typedef struct {
   int64_t n;          /* dimension, n >= k (see meg_block_size)               */
@@ -196,19 +194,19 @@ meg_status meg_set_iterate(meg_ctx ctx, const double* V, int32_t q, const double
 meg_status meg_get_state(meg_ctx ctx, void* buf, size_t* bytes);
 meg_status meg_set_state(meg_ctx ctx, const void* buf, size_t bytes);
 
-/* Per-kernel timing of one step (measurement entry point).  Runs one full
- * iteration t -> t+1 exactly as meg_step does, but launches its kernels
- * eagerly with a HIP event pair around each one on the context's stream, and
- * synchronises.  HOST output; times in milliseconds.  sweep_ms[s-1] is the
- * operator-apply sweep s (including its Rayleigh-Ritz tail); only the first
- * `sweeps_active` sweeps did work (later ones exit at once). */
+/* Timing of one step (measurement entry point).  Runs one full iteration
+ * t -> t+1 exactly as meg_step does (one launch of the persistent step
+ * kernel) with a HIP event pair around the launch on the context's stream,
+ * and with the kernel stamping the device wall clock at each of its grid
+ * barriers; synchronises.  HOST output; times in milliseconds. */
 typedef struct {
-  double prep_ms;       /* gradient pass (masked CSR) or scalar setup      */
-  double sweep_ms[64];
-  double finalize_ms;
-  double total_ms;      /* first event to last event                       */
-  int32_t sweeps_active;
-  int32_t max_inner;
+  double kernel_ms;      /* the step kernel, HIP events around the launch    */
+  double prep_ms;        /* gradient pass (masked CSR) or scalar setup       */
+  double apply_ms[64];   /* sweep s: operator apply + Gram partials          */
+  double small_ms[64];   /* sweep s: partial reduction + Rayleigh-Ritz/QR    */
+  double finalize_ms;    /* next basis + its orthonormalising transform      */
+  int32_t sweeps_active; /* sweeps the step used                             */
+  int32_t workgroups;    /* persistent grid size                             */
 } meg_kernel_times;
 
 meg_status meg_profile_step(meg_ctx ctx, meg_kernel_times* out);

@@ -1,10 +1,10 @@
 // Host runtime of the low-rank MEG library: the C ABI declared in include/meg.h.
 //
 // One context = one problem instance on one device stream.  The runtime
-// validates arguments, allocates the device state, builds the first iterate of
-// Algorithm 2 and enqueues the per-step kernels (meg_kernels.hpp).  A step is
-// captured once into a HIP graph (gradient/prep, max_inner sweeps, finalize)
-// and replayed; kernels of sweeps after convergence exit at once.
+// validates arguments, allocates the device state, estimates the spectral
+// bounds the solver's shift needs, builds the first iterate of Algorithm 2,
+// and launches the persistent step kernel (meg_kernels.hpp) cooperatively:
+// one launch runs one or many iterations with no host round trip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,13 +22,13 @@ using namespace meg;
 namespace {
 
 constexpr uint32_t kStateMagic = 0x4d454731u;  // "MEG1"
-constexpr int kApplyNT = 256;
-constexpr int kCsrRows = 8;
-constexpr int kFinNT = 256;
-constexpr int kFinRows = 16;
+constexpr int kStepNT = 512;                   // threads per persistent workgroup
+constexpr int kMaxWgPerCu = 2;
+constexpr int kMaxGrid = kBarGroupSize * kBarMaxGroups;  // barrier capacity
+constexpr int kChunkSteps = 64;                // iterations per launch in meg_solve
+constexpr int kTsSlots = 2 * 64 + 8;
 
-
-Red make_red(const meg_ctx_s* c, int nwg, int plen);
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
 
@@ -45,43 +45,17 @@ struct meg_ctx_s {
   Ctl* ctl = nullptr;
   double* part = nullptr;
   double* gpart = nullptr;
-  unsigned* cnt = nullptr;
-  size_t part_elems = 0, gpart_elems = 0, cnt_elems = 0;
-  Ctl* h_ctl = nullptr;  // pinned host mirror
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  bool use_graph = false;
+  double* sums = nullptr;
+  unsigned* bar = nullptr;
+  long long* ts = nullptr;
+  size_t part_elems = 0;
+  int P = 1;               // persistent grid size
+  int aux_nwg = 1;         // row-parallel auxiliary kernels
+  Ctl* h_ctl = nullptr;    // pinned host mirror
   bool failed = false;
 };
 
 namespace {
-
-inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
-
-Red make_red(const meg_ctx_s* c, int nwg, int plen) {
-  Red r;
-  r.part = c->part;
-  r.gpart = c->gpart;
-  r.cnt = c->cnt;
-  r.nwg = nwg;
-  r.gsz = std::max(1, (int)std::ceil(std::sqrt((double)nwg)));
-  r.ngroups = ceil_div(nwg, r.gsz);
-  r.plen = plen;
-  return r;
-}
-
-void red_need(int nwg, int plen, size_t& part, size_t& gpart, size_t& cnt) {
-  const int gsz = std::max(1, (int)std::ceil(std::sqrt((double)nwg)));
-  const int ng = ceil_div(nwg, gsz);
-  part = std::max(part, (size_t)nwg * plen);
-  gpart = std::max(gpart, (size_t)ng * plen);
-  cnt = std::max(cnt, (size_t)ng + 1);
-}
-
-int dense_rpw(int kb, size_t es) {
-  const size_t bytes = (size_t)kb * es;
-  return bytes <= 64 ? 4 : (bytes <= 128 ? 2 : 1);
-}
 
 // ---- small host PRNG (SplitMix64 + Box-Muller) for the extra start columns
 struct SplitMix {
@@ -139,142 +113,108 @@ meg_status hip_fail(meg_ctx c) {
   return MEG_ERR_DEVICE;
 }
 
-#define HIPCHK(ctx, x)                               \
-  do {                                               \
-    if ((x) != hipSuccess) return hip_fail(ctx);     \
+#define HIPCHK(ctx, x)                           \
+  do {                                           \
+    if ((x) != hipSuccess) return hip_fail(ctx); \
   } while (0)
 
 // ---------------------------------------------------------------------------
-// kernel launch helpers, dispatched on T (element type) and KB (block size)
+// launch helpers, dispatched on T (element type), KB (block size) and the
+// operator family
 // ---------------------------------------------------------------------------
 template <typename T, int KB>
 struct Launch {
-  static void* zbuf(meg_ctx c, int i) { return i == 0 ? c->Qw : (i == 1 ? c->Za : c->Zb); }
+  static Data<T> data(meg_ctx c) {
+    return Data<T>{c->obj.row_ptr, c->obj.col, (const T*)c->obj.val, (const T*)c->obj.dense};
+  }
+  static bool csr(meg_ctx c) { return c->cfg.kind == LINEAR_CSR || c->cfg.kind == MASKED_CSR; }
 
-  static void sizes(const Cfg& cfg, size_t& part, size_t& gpart, size_t& cnt) {
-    const int64_t n = cfg.n;
-    red_need(ceil_div(n, 4), 2, part, gpart, cnt);                    // grad / objective
-    red_need(ceil_div(n, kCsrRows), 3 * KB * KB, part, gpart, cnt);   // csr apply
-    const int rows = dense_rpw(KB, sizeof(T)) * (kApplyNT / 64);
-    red_need(ceil_div(n, rows), 3 * KB * KB, part, gpart, cnt);       // dense apply
-    red_need(ceil_div(n, kFinRows), KB * KB, part, gpart, cnt);       // finalize
-    red_need(1024, 2, part, gpart, cnt);                              // sumsq
+  template <int OPK>
+  static const void* kernel() {
+    return reinterpret_cast<const void*>(&k_step<T, KB, OPK, kStepNT>);
   }
 
-  static void prep(meg_ctx c) {
-    const Cfg& cfg = c->cfg;
-    if (cfg.kind == MASKED_CSR) {
-      const int nwg = ceil_div(cfg.n, 4);
-      hipLaunchKernelGGL((k_grad_masked<T, KB>), dim3(nwg), dim3(256), 0, c->stream, cfg, c->ctl,
-                         c->obj.row_ptr, c->obj.col, (const T*)c->obj.val, (const T*)c->Qw, (T*)c->g,
-                         make_red(c, nwg, 2));
-    } else {
-      hipLaunchKernelGGL(k_prep, dim3(1), dim3(64), 0, c->stream, cfg, c->ctl);
-    }
+  // persistent grid: co-resident workgroups, no more than there are row blocks
+  static int grid(meg_ctx c) {
+    int dev = 0, ncu = 1, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const void* k = csr(c) ? kernel<OP_CSR>() : kernel<OP_DENSE>();
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, kStepNT, 0) != hipSuccess || occ < 1) return 0;
+    const int rows = csr(c) ? StepShape<T, KB, OP_CSR, kStepNT>::ROWS : StepShape<T, KB, OP_DENSE, kStepNT>::ROWS;
+    const int nblk = ceil_div(c->cfg.n, rows);
+    return std::max(1, std::min(std::min(ncu * std::min(occ, kMaxWgPerCu), nblk), kMaxGrid));
   }
 
-  static void sweep(meg_ctx c, int s) {
-    const Cfg& cfg = c->cfg;
-    const int in = (s == 1) ? 0 : ((s % 2 == 0) ? 1 : 2);
-    const int out = (s == 1) ? 1 : ((s % 2 == 0) ? 2 : 1);
-    const T* Zin = (const T*)zbuf(c, in);
-    T* Zout = (T*)zbuf(c, out);
-    if (cfg.kind == MASKED_CSR || cfg.kind == LINEAR_CSR) {
-      const int nwg = ceil_div(cfg.n, kCsrRows);
-      const T* gv = (cfg.kind == MASKED_CSR) ? (const T*)c->g : (const T*)c->obj.val;
-      hipLaunchKernelGGL((k_apply_csr<T, KB, kCsrRows, kApplyNT>), dim3(nwg), dim3(kApplyNT), 0, c->stream, cfg,
-                         c->ctl, c->obj.row_ptr, c->obj.col, gv, (const T*)c->Qw, Zin, Zout,
-                         make_red(c, nwg, 3 * KB * KB), s, in);
-    } else {
-      const int rpw = dense_rpw(KB, sizeof(T));
-      const int rows = rpw * (kApplyNT / 64);
-      const int nwg = ceil_div(cfg.n, rows);
-      const Red red = make_red(c, nwg, 3 * KB * KB);
-      const T* D = (const T*)c->obj.dense;
-      if (rpw == 4)
-        hipLaunchKernelGGL((k_apply_dense<T, KB, 4, kApplyNT>), dim3(nwg), dim3(kApplyNT), 0, c->stream, cfg,
-                           c->ctl, D, (const T*)c->Qw, Zin, Zout, red, s, in);
-      else if (rpw == 2)
-        hipLaunchKernelGGL((k_apply_dense<T, KB, 2, kApplyNT>), dim3(nwg), dim3(kApplyNT), 0, c->stream, cfg,
-                           c->ctl, D, (const T*)c->Qw, Zin, Zout, red, s, in);
-      else
-        hipLaunchKernelGGL((k_apply_dense<T, KB, 1, kApplyNT>), dim3(nwg), dim3(kApplyNT), 0, c->stream, cfg,
-                           c->ctl, D, (const T*)c->Qw, Zin, Zout, red, s, in);
-    }
+  static size_t part_need(int P) {
+    return (size_t)P * std::max(3 * KB * KB, 2);
   }
 
-  static void finalize(meg_ctx c, int mode) {
-    const int nwg = ceil_div(c->cfg.n, kFinRows);
-    hipLaunchKernelGGL((k_finalize<T, KB, kFinRows, kFinNT>), dim3(nwg), dim3(kFinNT), 0, c->stream, c->cfg,
-                       c->ctl, (T*)c->Qw, (const T*)c->Za, (const T*)c->Zb, make_red(c, nwg, KB * KB), mode);
+  static hipError_t step(meg_ctx c, int nsteps, int mode, bool stamps) {
+    Cfg cfg = c->cfg;
+    Ctl* ctl = c->ctl;
+    Data<T> dat = data(c);
+    T* Qw = (T*)c->Qw;
+    T* Za = (T*)c->Za;
+    T* Zb = (T*)c->Zb;
+    T* g = (T*)c->g;
+    Bufs b{c->part, c->gpart, c->sums, c->bar, stamps ? c->ts : nullptr};
+    void* args[] = {&cfg, &ctl, &dat, &Qw, &Za, &Zb, &g, &b, &nsteps, &mode};
+    const void* k = csr(c) ? kernel<OP_CSR>() : kernel<OP_DENSE>();
+    return hipLaunchCooperativeKernel(k, dim3(c->P), dim3(kStepNT), args, 0, c->stream);
   }
 
-  static void objective(meg_ctx c) {
+  static hipError_t objective(meg_ctx c) {
     const Cfg& cfg = c->cfg;
     const int nwg = ceil_div(cfg.n, 4);
-    if (cfg.kind == LINEAR_DENSE || cfg.kind == DENOISE_DENSE)
-      hipLaunchKernelGGL((k_objective_dense<T, KB>), dim3(nwg), dim3(256), 0, c->stream, cfg, c->ctl,
-                         (const T*)c->obj.dense, (const T*)c->Qw, make_red(c, nwg, 2));
+    if (csr(c))
+      hipLaunchKernelGGL((k_objective_csr<T, KB>), dim3(nwg), dim3(256), 0, c->stream, cfg, c->ctl, c->obj.row_ptr,
+                         c->obj.col, (const T*)c->obj.val, (const T*)c->Qw, c->part);
     else
-      hipLaunchKernelGGL((k_objective_csr<T, KB>), dim3(nwg), dim3(256), 0, c->stream, cfg, c->ctl,
-                         c->obj.row_ptr, c->obj.col, (const T*)c->obj.val, (const T*)c->Qw,
-                         make_red(c, nwg, 2));
+      hipLaunchKernelGGL((k_objective_dense<T, KB>), dim3(nwg), dim3(256), 0, c->stream, cfg, c->ctl,
+                         (const T*)c->obj.dense, (const T*)c->Qw, c->part);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, c->stream, c->ctl, c->part, nwg, 0);
+    return hipGetLastError();
   }
 
-  static void data_norm(meg_ctx c) {
+  static hipError_t data_norm(meg_ctx c) {
     const Cfg& cfg = c->cfg;
     int64_t rows, cols, ld;
     const T* x;
-    if (cfg.kind == LINEAR_DENSE || cfg.kind == DENOISE_DENSE) {
+    if (!csr(c)) {
       rows = cfg.n; cols = cfg.n; ld = cfg.ld; x = (const T*)c->obj.dense;
     } else {
-      rows = 1; cols = std::max<int64_t>(cfg.nnz, 1); ld = 0; x = (const T*)c->obj.val;
-      if (cfg.nnz == 0) { rows = 0; }
+      rows = cfg.nnz > 0 ? 1 : 0; cols = std::max<int64_t>(cfg.nnz, 1); ld = 0; x = (const T*)c->obj.val;
     }
     const int64_t total = rows * cols;
     const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (total + 255) / 256));
-    hipLaunchKernelGGL((k_sumsq<T>), dim3(nwg), dim3(256), 0, c->stream, x, rows, cols, ld, c->ctl,
-                       make_red(c, nwg, 2));
-  }
-
-  static void step(meg_ctx c) {
-    prep(c);
-    for (int s = 1; s <= c->cfg.max_inner; ++s) sweep(c, s);
-    finalize(c, 0);
-  }
-};
-
-template <typename T, int KB>
-struct DoProfile {
-  static void run(meg_ctx c, hipEvent_t* ev) {
-    hipEventRecord(ev[0], c->stream);
-    Launch<T, KB>::prep(c);
-    hipEventRecord(ev[1], c->stream);
-    for (int s = 1; s <= c->cfg.max_inner; ++s) {
-      Launch<T, KB>::sweep(c, s);
-      hipEventRecord(ev[1 + s], c->stream);
-    }
-    Launch<T, KB>::finalize(c, 0);
-    hipEventRecord(ev[2 + c->cfg.max_inner], c->stream);
+    hipLaunchKernelGGL((k_sumsq<T>), dim3(nwg), dim3(256), 0, c->stream, x, rows, cols, ld, c->part);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, c->stream, c->ctl, c->part, nwg, 1);
+    return hipGetLastError();
   }
 };
 
 template <template <typename, int> class F, typename... Args>
-void dispatch(meg_ctx c, Args&&... args) {
+auto dispatch(meg_ctx c, Args&&... args) {
   const bool dbl = c->esize == 8;
-  if (c->cfg.k == 16) {
-    if (dbl) F<double, 16>::run(c, args...); else F<float, 16>::run(c, args...);
-  } else {
-    if (dbl) F<double, 32>::run(c, args...); else F<float, 32>::run(c, args...);
-  }
+  if (c->cfg.k == 16) return dbl ? F<double, 16>::run(c, args...) : F<float, 16>::run(c, args...);
+  return dbl ? F<double, 32>::run(c, args...) : F<float, 32>::run(c, args...);
 }
 
-template <typename T, int KB> struct DoStep { static void run(meg_ctx c) { Launch<T, KB>::step(c); } };
-template <typename T, int KB> struct DoFinalize { static void run(meg_ctx c, int m) { Launch<T, KB>::finalize(c, m); } };
-template <typename T, int KB> struct DoObjective { static void run(meg_ctx c) { Launch<T, KB>::objective(c); } };
-template <typename T, int KB> struct DoNorm { static void run(meg_ctx c) { Launch<T, KB>::data_norm(c); } };
-template <typename T, int KB> struct DoSizes {
-  static void run(meg_ctx c, size_t* p, size_t* g, size_t* n) { Launch<T, KB>::sizes(c->cfg, *p, *g, *n); }
+template <typename T, int KB> struct DoStep {
+  static hipError_t run(meg_ctx c, int nsteps, int mode, bool st) { return Launch<T, KB>::step(c, nsteps, mode, st); }
+};
+template <typename T, int KB> struct DoObjective {
+  static hipError_t run(meg_ctx c) { return Launch<T, KB>::objective(c); }
+};
+template <typename T, int KB> struct DoNorm {
+  static hipError_t run(meg_ctx c) { return Launch<T, KB>::data_norm(c); }
+};
+template <typename T, int KB> struct DoGrid {
+  static int run(meg_ctx c) { return Launch<T, KB>::grid(c); }
+};
+template <typename T, int KB> struct DoPartNeed {
+  static size_t run(meg_ctx c, int P) { return Launch<T, KB>::part_need(P); }
 };
 
 // Eigenvalues/vectors of a small symmetric matrix (host, cyclic Jacobi, FP64).
@@ -350,7 +290,10 @@ meg_status lanczos_extremes(meg_ctx c, double* lmin, double* lmax) {
   for (int j = 0; j < m; ++j) {
     const double* v = &Vs[(size_t)j * n];
     for (int64_t i = 0; i < n; ++i) xt[i] = (T)v[i];
-    if (hipMemcpy(dx, xt.data(), n * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) { st = hip_fail(c); break; }
+    if (hipMemcpy(dx, xt.data(), n * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+      st = hip_fail(c);
+      break;
+    }
     hipLaunchKernelGGL((k_matvec<T>), dim3(ceil_div(n, 4)), dim3(256), 0, c->stream, cfg, (const T*)c->obj.dense,
                        c->obj.row_ptr, c->obj.col, (const T*)c->obj.val, (const T*)dx, dy);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
@@ -410,6 +353,14 @@ meg_status copy_ctl_to_host(meg_ctx c) {
   return MEG_OK;
 }
 
+// barrier error flag set by the step kernel: the grid did not complete a barrier
+meg_status check_barrier(meg_ctx c) {
+  unsigned err = 0;
+  HIPCHK(c, hipMemcpy(&err, c->bar + kBarErr, sizeof(unsigned), hipMemcpyDeviceToHost));
+  if (err) return hip_fail(c);
+  return MEG_OK;
+}
+
 void fill_info(const Ctl& h, meg_step_info* o) {
   const Info& in = h.info;
   o->t = in.t;
@@ -443,8 +394,8 @@ meg_status upload_iterate(meg_ctx c, const double* V, int q, const double* d, do
     HIPCHK(c, hipMemcpyAsync(c->Qw, Bf.data(), cnt * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
-  HIPCHK(c, hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  meg_status st = copy_ctl_to_host(c);
+  if (st != MEG_OK) return st;
   Ctl& h = *c->h_ctl;
   h.alpha = alpha;
   for (int l = 0; l < KMAX; ++l) {
@@ -459,38 +410,14 @@ meg_status upload_iterate(meg_ctx c, const double* V, int q, const double* d, do
   h.stop = 0;
   h.status = 0;
   h.fvalid = 0;
+  h.polish = 0;
   h.solve_tol = 0.0;
   std::memset(&h.info, 0, sizeof(Info));
   h.info.t = t - 1;
   HIPCHK(c, hipMemcpyAsync(c->ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
-  dispatch<DoFinalize>(c, 1);
-  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, dispatch<DoStep>(c, 1, 1, false));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  return MEG_OK;
-}
-
-meg_status build_graph(meg_ctx c) {
-  if (!c->use_graph) return MEG_OK;
-  if (c->gexec) return MEG_OK;
-  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  dispatch<DoStep>(c);
-  hipGraph_t g = nullptr;
-  if (hipStreamEndCapture(c->stream, &g) != hipSuccess || !g) return hip_fail(c);
-  c->graph = g;
-  if (hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0) != hipSuccess) return hip_fail(c);
-  return MEG_OK;
-}
-
-meg_status enqueue_step(meg_ctx c) {
-  if (c->use_graph) {
-    meg_status s = build_graph(c);
-    if (s != MEG_OK) return s;
-    HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
-  } else {
-    dispatch<DoStep>(c);
-    HIPCHK(c, hipGetLastError());
-  }
-  return MEG_OK;
+  return check_barrier(c);
 }
 
 meg_status check_ctx(meg_ctx c) {
@@ -502,6 +429,7 @@ meg_status check_ctx(meg_ctx c) {
 meg_status validate(const meg_params* p, const meg_objective* o, const meg_start* s, int* kout) {
   if (!p || !o || !s) return MEG_ERR_INVALID_ARG;
   if (p->n < 2 || p->r < 1 || p->r > p->n - 1) return MEG_ERR_INVALID_ARG;
+  if (p->n > 2147483647LL) return MEG_ERR_INVALID_ARG;
   if (p->oversample < 0) return MEG_ERR_INVALID_ARG;
   const int k = meg_block_size(p->r, p->oversample);
   if (k == 0 || k > p->n) return MEG_ERR_INVALID_ARG;
@@ -537,8 +465,7 @@ meg_status validate(const meg_params* p, const meg_objective* o, const meg_start
     sum += s->lambda0[i];
   }
   if (std::fabs(sum - 1.0) > 1e-8) return MEG_ERR_INVALID_ARG;
-  // orthonormal start columns
-  for (int a = 0; a < s->q; ++a)
+  for (int a = 0; a < s->q; ++a)  // orthonormal start columns
     for (int b = a; b < s->q; ++b) {
       double dot = 0.0;
       for (int64_t i = 0; i < p->n; ++i) dot += s->V0[(size_t)a * p->n + i] * s->V0[(size_t)b * p->n + i];
@@ -550,9 +477,7 @@ meg_status validate(const meg_params* p, const meg_objective* o, const meg_start
 
 void free_ctx(meg_ctx c) {
   if (!c) return;
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
-  void* bufs[] = {c->Qw, c->Za, c->Zb, c->g, c->ctl, c->part, c->gpart, c->cnt};
+  void* bufs[] = {c->Qw, c->Za, c->Zb, c->g, c->ctl, c->part, c->gpart, c->sums, c->bar, c->ts};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
@@ -611,6 +536,7 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
   cfg.min_inner = params->min_inner;
   cfg.max_inner = params->max_inner;
   cfg.batch = obj->batch;
+  cfg.rr_from = std::min(2, (int)params->max_inner);
   cfg.eta = params->eta;
   cfg.eps_scale = params->eps_scale;
   cfg.eps_c = params->eps_c;
@@ -618,15 +544,28 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
   cfg.inner_tol = params->inner_tol > 0 ? params->inner_tol : (c->esize == 8 ? 1e-10 : 1e-6);
   cfg.unit_round = (c->esize == 8) ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
   cfg.cert_tol = params->cert_tol;
-  c->use_graph = !(params->flags & MEG_FLAG_NO_GRAPH) && stream != nullptr;
 
-  size_t pe = 0, ge = 0, ce = 0;
-  dispatch<DoSizes>(c, &pe, &ge, &ce);
+  int coop = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) {
+    (void)hipGetLastError();
+    delete c;
+    return MEG_ERR_DEVICE;
+  }
+  c->P = dispatch<DoGrid>(c);
+  if (c->P < 1) {
+    delete c;
+    return MEG_ERR_DEVICE;
+  }
+  c->aux_nwg = std::max(1024, ceil_div(cfg.n, 4));
+  const size_t pe = std::max(dispatch<DoPartNeed>(c, c->P), (size_t)c->aux_nwg);
   const size_t zbytes = (size_t)cfg.n * k * c->esize;
   auto alloc = [&](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 256)) == hipSuccess; };
   bool ok = alloc(&c->Qw, zbytes) && alloc(&c->Za, zbytes) && alloc(&c->Zb, zbytes) &&
             alloc((void**)&c->ctl, sizeof(Ctl)) && alloc((void**)&c->part, pe * 8) &&
-            alloc((void**)&c->gpart, ge * 8) && alloc((void**)&c->cnt, ce * sizeof(unsigned));
+            alloc((void**)&c->sums, 3 * KMAX * KMAX * 8) && alloc((void**)&c->bar, kBarWords * sizeof(unsigned)) &&
+            alloc((void**)&c->gpart, (size_t)kBarMaxGroups * 3 * KMAX * KMAX * 8) &&
+            alloc((void**)&c->ts, kTsSlots * sizeof(long long));
   if (ok && obj->kind == MEG_GRAD_MASKED_CSR) ok = alloc(&c->g, (size_t)std::max<int64_t>(obj->nnz, 1) * c->esize);
   if (ok) ok = hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl)) == hipSuccess;
   if (!ok) {
@@ -635,22 +574,24 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
     return MEG_ERR_OUT_OF_MEMORY;
   }
   c->part_elems = pe;
-  c->gpart_elems = ge;
-  c->cnt_elems = ce;
-  if (hipMemsetAsync(c->cnt, 0, ce * sizeof(unsigned), c->stream) != hipSuccess ||
-      hipMemsetAsync(c->ctl, 0, sizeof(Ctl), c->stream) != hipSuccess) {
+  if (hipMemsetAsync(c->bar, 0, kBarWords * sizeof(unsigned), c->stream) != hipSuccess ||
+      hipMemsetAsync(c->ctl, 0, sizeof(Ctl), c->stream) != hipSuccess ||
+      hipMemsetAsync(c->ts, 0, kTsSlots * sizeof(long long), c->stream) != hipSuccess) {
     free_ctx(c);
     return MEG_ERR_DEVICE;
   }
   // CSR structure check before any kernel reads through the indices
   if (obj->kind == MEG_GRAD_LINEAR_CSR || obj->kind == MEG_GRAD_MASKED_CSR) {
     int h_err = 0;
-    int* d_err = (int*)c->cnt;  // zeroed above; reset below
+    int* d_err = (int*)c->sums;
+    if (hipMemsetAsync(d_err, 0, sizeof(int), c->stream) != hipSuccess) {
+      free_ctx(c);
+      return MEG_ERR_DEVICE;
+    }
     hipLaunchKernelGGL(k_check_csr, dim3((unsigned)std::min<int64_t>(1024, (cfg.n + 255) / 256)), dim3(256), 0,
                        c->stream, obj->row_ptr, obj->col, cfg.n, cfg.nnz, d_err);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
-        hipMemcpy(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemset(c->cnt, 0, ce * sizeof(unsigned)) != hipSuccess) {
+        hipMemcpy(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
       free_ctx(c);
       return MEG_ERR_DEVICE;
     }
@@ -660,8 +601,7 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
     }
   }
   // data norm (sets ctl->data_norm)
-  dispatch<DoNorm>(c);
-  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+  if (dispatch<DoNorm>(c) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
     free_ctx(c);
     return MEG_ERR_DEVICE;
   }
@@ -697,14 +637,12 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
 meg_status meg_step(meg_ctx c, meg_step_info* info) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
-  if (info) {
-    dispatch<DoObjective>(c);
-    HIPCHK(c, hipGetLastError());
-  }
-  st = enqueue_step(c);
-  if (st != MEG_OK) return st;
+  // f(X_t): the masked objective's gradient phase computes it in the step
+  if (info && c->cfg.kind != MASKED_CSR) HIPCHK(c, dispatch<DoObjective>(c));
+  HIPCHK(c, dispatch<DoStep>(c, 1, 0, false));
   if (!info) return MEG_OK;
   st = copy_ctl_to_host(c);
+  if (st == MEG_OK) st = check_barrier(c);
   if (st != MEG_OK) return st;
   fill_info(*c->h_ctl, info);
   if (c->h_ctl->status) return (meg_status)c->h_ctl->status;
@@ -724,25 +662,20 @@ meg_status meg_solve(meg_ctx c, int64_t max_iters, double tol, meg_step_info* la
   HIPCHK(c, hipMemcpyAsync(&c->ctl->solve_tol, &c->h_ctl->solve_tol, sizeof(double), hipMemcpyHostToDevice,
                            c->stream));
   HIPCHK(c, hipMemcpyAsync(&c->ctl->stop, &c->h_ctl->stop, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-  const int64_t chunk = 16;
   int64_t done = 0;
   while (done < max_iters) {
-    const int64_t m = std::min<int64_t>(chunk, max_iters - done);
-    for (int64_t i = 0; i < m; ++i) {
-      st = enqueue_step(c);
-      if (st != MEG_OK) return st;
-    }
+    const int m = (int)std::min<int64_t>(kChunkSteps, max_iters - done);
+    HIPCHK(c, dispatch<DoStep>(c, m, 0, false));
     done += m;
-    if (tol > 0 || done >= max_iters) {
+    if (tol > 0 && done < max_iters) {
       st = copy_ctl_to_host(c);
       if (st != MEG_OK) return st;
       if (c->h_ctl->stop || c->h_ctl->status) break;
     }
   }
-  if (done == 0) {
-    st = copy_ctl_to_host(c);
-    if (st != MEG_OK) return st;
-  }
+  st = copy_ctl_to_host(c);
+  if (st == MEG_OK) st = check_barrier(c);
+  if (st != MEG_OK) return st;
   const int32_t status = c->h_ctl->status;
   if (last) {
     fill_info(*c->h_ctl, last);
@@ -772,8 +705,7 @@ meg_status meg_objective_value(meg_ctx c, double* f) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
   if (!f) return MEG_ERR_INVALID_ARG;
-  dispatch<DoObjective>(c);
-  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, dispatch<DoObjective>(c));
   st = copy_ctl_to_host(c);
   if (st != MEG_OK) return st;
   *f = c->h_ctl->f;
@@ -869,35 +801,41 @@ meg_status meg_profile_step(meg_ctx c, meg_kernel_times* out) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
   if (!out) return MEG_ERR_INVALID_ARG;
-  const int ne = c->cfg.max_inner + 3;
-  std::vector<hipEvent_t> ev(ne, nullptr);
-  for (int i = 0; i < ne; ++i)
-    if (hipEventCreate(&ev[i]) != hipSuccess) {
-      for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
-      return hip_fail(c);
-    }
-  dispatch<DoProfile>(c, ev.data());
-  const bool ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(c->stream) == hipSuccess;
   std::memset(out, 0, sizeof(*out));
-  float ms = 0.f;
-  if (ok) {
-    hipEventElapsedTime(&ms, ev[0], ev[1]);
-    out->prep_ms = ms;
-    for (int s = 1; s <= c->cfg.max_inner; ++s) {
-      hipEventElapsedTime(&ms, ev[s], ev[s + 1]);
-      out->sweep_ms[s - 1] = ms;
-    }
-    hipEventElapsedTime(&ms, ev[1 + c->cfg.max_inner], ev[2 + c->cfg.max_inner]);
-    out->finalize_ms = ms;
-    hipEventElapsedTime(&ms, ev[0], ev[2 + c->cfg.max_inner]);
-    out->total_ms = ms;
-    out->max_inner = c->cfg.max_inner;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(c);
   }
-  for (auto e : ev) (void)hipEventDestroy(e);
+  bool ok = hipMemsetAsync(c->ts, 0, kTsSlots * sizeof(long long), c->stream) == hipSuccess &&
+            hipEventRecord(e0, c->stream) == hipSuccess && dispatch<DoStep>(c, 1, 0, true) == hipSuccess &&
+            hipEventRecord(e1, c->stream) == hipSuccess && hipStreamSynchronize(c->stream) == hipSuccess;
+  float ms = 0.f;
+  if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (!ok) return hip_fail(c);
+  std::vector<long long> ts(kTsSlots);
+  HIPCHK(c, hipMemcpy(ts.data(), c->ts, kTsSlots * sizeof(long long), hipMemcpyDeviceToHost));
   st = copy_ctl_to_host(c);
+  if (st == MEG_OK) st = check_barrier(c);
   if (st != MEG_OK) return st;
-  out->sweeps_active = c->h_ctl->info.inner_iters;
+  int dev = 0, khz = 100000;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+  const double tick_ms = 1.0 / (double)std::max(khz, 1);
+  const int mi = c->cfg.max_inner;
+  const int used = std::max(1, std::min(mi, (int)c->h_ctl->info.inner_iters));
+  out->kernel_ms = ms;
+  out->prep_ms = (ts[1] - ts[0]) * tick_ms;
+  for (int s = 1; s <= used; ++s) {
+    out->apply_ms[s - 1] = (ts[2 * s] - ts[2 * s - 1]) * tick_ms;
+    out->small_ms[s - 1] = (ts[2 * s + 1] - ts[2 * s]) * tick_ms;
+  }
+  out->finalize_ms = (ts[2 * mi + 3] - ts[2 * used + 1]) * tick_ms;
+  out->sweeps_active = used;
+  out->workgroups = c->P;
   return c->h_ctl->status ? (meg_status)c->h_ctl->status : MEG_OK;
 }
 

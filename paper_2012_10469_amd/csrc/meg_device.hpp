@@ -6,7 +6,7 @@
 //   Za,Zb n x k ping-pong outputs of the operator apply, same layout
 //   g    nnz    gradient values on Omega (masked objective)
 //   Ctl  one control block (FP64 scalars and k x k transforms)
-//   Red  partial sums of the per-workgroup Gram matrices
+//   Bufs per-workgroup partial sums (FP64), their reduction, barrier words
 // Rows are 64 B (k = 16, float) or 128 B apart, so a row is read by one
 // aligned vector load per lane group and Gram partials stay row-local.
 #pragma once
@@ -29,7 +29,8 @@ struct Cfg {
   int64_t m;     // QUADMEAS pool size
   int64_t batch_steps;
   int32_t r, k, kind, prec;
-  int32_t min_inner, max_inner, batch, pad;
+  int32_t min_inner, max_inner, batch;
+  int32_t rr_from;    // first sweep with Rayleigh-Ritz (earlier sweeps only orthonormalise)
   double eta, eps_scale, eps_c, eps_pow;
   double inner_tol;   // relative Ritz residual tolerance (top r pairs)
   double unit_round;  // 2^-24 (float state) or 2^-53 (double state)
@@ -75,13 +76,25 @@ struct Ctl {
   Info info;
 };
 
-// Two-level deterministic reduction workspace ("last workgroup" tree).
-struct Red {
-  double* part;     // nwg x plen
-  double* gpart;    // ngroups x plen
-  unsigned* cnt;    // ngroups + 1 arrival counters (zero between launches)
-  int nwg, gsz, ngroups, plen;
+// Scratch of the persistent step kernel: per-workgroup partial sums, their
+// reduction, and the grid barrier words.
+struct Bufs {
+  double* part;     // gridDim.x x plen partial sums (FP64)
+  double* gpart;    // per-barrier-group sums of the partials (FP64)
+  double* sums;     // plen reduced sums
+  unsigned* bar;    // barrier words, one 128-byte line each (see grid_sync)
+  long long* ts;    // optional phase timestamps (wall clock), or null
 };
+
+// Barrier word layout (in unsigned units; 32 = one 128-byte line):
+//   bar[0]            top-level arrival count
+//   bar[32]           generation
+//   bar[64]           error flag
+//   bar[96 + 32 g]    arrival count of group g
+constexpr int kBarTop = 0, kBarGen = 32, kBarErr = 64, kBarGroup0 = 96, kBarStride = 32;
+constexpr int kBarGroupSize = 16;
+constexpr int kBarMaxGroups = 64;  // up to 1024 workgroups
+constexpr int kBarWords = kBarGroup0 + kBarStride * kBarMaxGroups;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -89,63 +102,118 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+// Bounded spin: a barrier that is never completed (which a co-resident,
+// cooperatively launched grid rules out) ends with the error flag set
+// instead of a hang.
+constexpr unsigned kSpinLimit = 1u << 22;
 
-// Agent-scope arrival counter (global memory atomic, vector memory path).
-__device__ __forceinline__ unsigned arrive(unsigned* c) {
-  return __hip_atomic_fetch_add(c, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void reset_counter(unsigned* c) {
-  __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Every workgroup contributes `plen` doubles (in LDS `mine`).  Returns true in
-// exactly one workgroup (the last to arrive), whose LDS `out` then holds the
-// sum over all workgroups, added in a fixed order (bitwise reproducible).
-// `out` may alias `mine`.  All threads of the workgroup must call this.
-template <int NT>
-__device__ bool tree_reduce(const Red& red, const double* mine, double* out) {
-  __shared__ int s_last;
+// Grid-wide barrier for a cooperatively launched grid (gridDim.x <= 1024).
+// Arrivals are counted in two levels (groups of kBarGroupSize workgroups,
+// then the groups) so that no counter sees more than ~32 contending atomics.
+// Every workgroup's writes before the barrier are visible to every workgroup
+// after it: each arrival is an agent-scope acquire-release RMW (the group's
+// last arriver carries the group's writes on to the top counter), and waiting
+// workgroups acquire after observing the new generation.  `serial` runs in the
+// last workgroup to arrive, with all of its threads, before anyone is
+// released; its writes are published by the generation bump.  Returns false
+// on a barrier error.
+// With plen > 0 the barrier also sums the per-workgroup partials
+// part[w * plen + e] into sums[e] on its way up the arrival tree: the last
+// arriver of each group adds its group's partials (in workgroup order) into
+// gpart, the last group adds the group sums (in group order).  The order is
+// fixed, so the sums are bitwise reproducible.  All threads call it.
+template <int NT, typename F>
+__device__ __forceinline__ bool grid_sync(const Bufs& b, int plen, F&& serial) {
+  __shared__ int s_role;  // 0: plain arrival, 1: last of its group, 2: last overall
+  __shared__ unsigned s_gen;
+  __shared__ int s_ok;
   const int tid = threadIdx.x;
-  const int wg = blockIdx.x;
-  const int plen = red.plen;
-  double* dst = red.part + (size_t)wg * plen;
-  for (int e = tid; e < plen; e += NT) dst[e] = mine[e];
-  __threadfence();
+  const unsigned P = gridDim.x;
+  const unsigned g = blockIdx.x / kBarGroupSize;
+  const unsigned ng = (P + kBarGroupSize - 1) / kBarGroupSize;
+  const unsigned g0 = g * kBarGroupSize;
+  const unsigned gsize = min((unsigned)kBarGroupSize, P - g0);
+  unsigned* gc = &b.bar[kBarGroup0 + kBarStride * g];
   __syncthreads();
-  const int g = wg / red.gsz;
-  const int g0 = g * red.gsz;
-  const int gn = min(red.gsz, red.nwg - g0);
-  if (tid == 0) s_last = (arrive(&red.cnt[g]) == (unsigned)(gn - 1));
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  double* gdst = red.gpart + (size_t)g * plen;
-  for (int e = tid; e < plen; e += NT) {
-    double s = 0.0;
-    for (int w = 0; w < gn; ++w) s += red.part[(size_t)(g0 + w) * plen + e];
-    gdst[e] = s;
+  if (tid == 0) {
+    s_ok = __hip_atomic_load(&b.bar[kBarErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    s_role = 0;
+    if (s_ok) {
+      s_gen = __hip_atomic_load(&b.bar[kBarGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned prev = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (prev == gsize - 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the group's writes
+        __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_role = 1;
+      }
+    }
   }
-  if (tid == 0) reset_counter(&red.cnt[g]);
-  __threadfence();
   __syncthreads();
-  if (tid == 0) s_last = (arrive(&red.cnt[red.ngroups]) == (unsigned)(red.ngroups - 1));
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  for (int e = tid; e < plen; e += NT) {
-    double s = 0.0;
-    for (int q = 0; q < red.ngroups; ++q) s += red.gpart[(size_t)q * plen + e];
-    out[e] = s;
+  if (!s_ok) return false;
+  if (s_role >= 1) {
+    if (plen > 0) {
+      // loads of the group's partials are unrolled so they are all in flight
+      for (int e = tid; e < plen; e += NT) {
+        double v[kBarGroupSize];
+#pragma unroll
+        for (int w = 0; w < kBarGroupSize; ++w)
+          v[w] = (w < (int)gsize) ? b.part[(size_t)(g0 + w) * plen + e] : 0.0;
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBarGroupSize; ++w) s += v[w];
+        b.gpart[(size_t)g * plen + e] = s;
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const unsigned top = __hip_atomic_fetch_add(&b.bar[kBarTop], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (top == ng - 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every group's writes
+        s_role = 2;
+      }
+    }
+    __syncthreads();
   }
-  if (tid == 0) reset_counter(&red.cnt[red.ngroups]);
+  if (s_role == 2) {
+    if (plen > 0) {
+      for (int e = tid; e < plen; e += NT) {
+        double s = 0.0;
+        for (unsigned q0 = 0; q0 < ng; q0 += 16) {
+          double v[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) v[q] = (q0 + q < ng) ? b.gpart[(size_t)(q0 + q) * plen + e] : 0.0;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) s += v[q];
+        }
+        b.sums[e] = s;
+      }
+      __syncthreads();
+    }
+    serial();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(&b.bar[kBarTop], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&b.bar[kBarGen], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (tid == 0) {
+    unsigned spins = 0;
+    while (__hip_atomic_load(&b.bar[kBarGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == s_gen) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit || __hip_atomic_load(&b.bar[kBarErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        __hip_atomic_fetch_or(&b.bar[kBarErr], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_ok = 0;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
   __syncthreads();
-  return true;
+  return s_ok != 0;
+}
+
+template <int NT>
+__device__ __forceinline__ bool grid_sync(const Bufs& b) {
+  return grid_sync<NT>(b, 0, [] {});
 }
 
 __device__ __forceinline__ double eps_at(const Cfg& cfg, int64_t t) {

@@ -1,23 +1,29 @@
-// HIP kernels of one low-rank MEG step (gfx950, wave64).
+// HIP kernels of the low-rank MEG step (gfx950, wave64).
 //
-// Step t (Algorithm 2, Section 3):
-//   grad  : gradient values of the masked objective on Omega at X_t, f(X_t),
-//           ||grad||_F  (the last workgroup sets the step's shift)
-//   apply : Zout = Yhat (Zin W) for the implicit orthonormal basis Q = Zin W,
-//           Yhat = V diag(ceff) V^T + opscale * Op + sdiag * I, with the
-//           Gram partials Zin^T Zout, Zout^T Zout, V^T Zout fused into the
-//           epilogue; the last workgroup runs Rayleigh-Ritz + Cholesky QR
-//   final : Qw <- Zsrc Wfin (Ritz basis = next warm start, first r columns =
-//           V_{t+1}) and its Gram, whose Cholesky factor orthonormalises the
-//           first sweep of the next step
-// Launch shapes are fixed per problem size; kernels that find the inner solve
-// finished (ctl->done) or the run stopped (ctl->stop) return immediately, so
-// a step can be captured once as a graph of max_inner sweeps.
+// One step t (Algorithm 2, Section 3) runs inside ONE persistent, cooperatively
+// launched kernel (k_step), phases separated by grid barriers:
+//   grad   : masked objective: gradient values on Omega at X_t, f(X_t) and the
+//            norms that set the solver's shift (other objectives: shift only)
+//   sweep s: apply   Zout = Yhat (Zin W) for the implicit orthonormal basis
+//                    Q = Zin W, Yhat = V diag(ceff) V^T + opscale*Op + sdiag*I,
+//                    with FP64 Gram partials Zin^T Zout, Zout^T Zout, V^T Zout
+//            barrier the partials are summed along the arrival tree
+//            small   Cholesky QR (sweep 1) or Rayleigh-Ritz + Cholesky QR in
+//                    FP64, one wavefront of the last workgroup to arrive;
+//                    stops the sweep loop when the Ritz residuals meet the
+//                    tolerance
+//   final  : Qw <- Zsrc Wfin (Ritz basis = next warm start; its first r
+//            columns are V_{t+1}) and its Gram, whose Cholesky factor
+//            orthonormalises the first sweep of step t+1
+// Cross-workgroup communication happens only at the barriers, so no
+// workgroup writes back or invalidates the L2 while others stream through it.
 #pragma once
 #include "meg_device.hpp"
 #include "meg_small.hpp"
 
 namespace meg {
+
+enum OpKind : int { OP_CSR = 0, OP_DENSE = 1 };
 
 // 16-byte vector of T (float4 / double2) used for row-chunk loads.
 template <typename T> struct V16;
@@ -41,361 +47,472 @@ __device__ __forceinline__ void vload(const T* p, T* out) {
   }
 }
 
-// Scratch doubles the last workgroup needs for the small solve.
+// Scratch doubles the small solves need (they reuse the apply's LDS).
 template <int KB>
 constexpr int small_scratch() { return 5 * KB * (KB + 1) + 8 * KB; }
 
-__device__ __forceinline__ bool step_skipped(const Ctl* ctl) {
-  return (ctl->stop | ctl->status) != 0;
-}
-
-// ---------------------------------------------------------------------------
-// prep: step scalars for objectives without a gradient pass
-// ---------------------------------------------------------------------------
-__global__ void k_prep(Cfg cfg, Ctl* ctl) {
-  if (step_skipped(ctl)) return;
-  if (threadIdx.x == 0) {
-    double gmax;
-    if (cfg.kind == DENOISE_DENSE) {
-      // lambda_max(X - M) <= lambda_max(X) - lambda_min(M), lambda_max(X) = alpha + max(0, max d)
-      double dmax = 0.0;
-      for (int l = 0; l < cfg.r; ++l) dmax = fmax(dmax, ctl->d[l]);
-      gmax = ctl->alpha + dmax - ctl->op_lmin;
-    } else {
-      gmax = ctl->op_lmax;  // G = C
-    }
-    setup_step(cfg, ctl, gmax);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// grad (masked CSR): g_e = X_ij - M_ij on Omega, f = 1/2 sum g^2
-// X_ij = alpha [i == j] + sum_l V_il d_l V_jl.  One wave per row.
-// ---------------------------------------------------------------------------
+// Rows per wave of the dense apply: keep RPW * KB accumulators per lane modest.
 template <typename T, int KB>
-__global__ __launch_bounds__(256) void k_grad_masked(Cfg cfg, Ctl* __restrict__ ctl, const int* __restrict__ rp,
-                                                     const int* __restrict__ col, const T* __restrict__ mval,
-                                                     const T* __restrict__ Qw, T* __restrict__ g, Red red) {
-  if (step_skipped(ctl)) return;
-  __shared__ T sd[KMAX];
-  __shared__ double sred[8];
+constexpr int dense_rpw() { return (KB * (int)sizeof(T) <= 64) ? 4 : ((KB * (int)sizeof(T) <= 128) ? 2 : 1); }
+
+template <typename T, int KB, int OPK, int NT>
+struct StepShape {
+  static constexpr int WAVES = NT / 64;
+  static constexpr int RPW = (OPK == OP_CSR) ? 1 : dense_rpw<T, KB>();
+  static constexpr int ROWS = WAVES * RPW;  // rows per apply block
+  static constexpr int FROWS = 2 * WAVES;   // rows per finalize block
+};
+
+template <typename T, int KB, int ROWS>
+struct ApplySmem {
+  static constexpr int LD = KB + 1;
+  // typed section (in units of T)
+  static constexpr int T_W = 0;                  // KB x LD
+  static constexpr int T_P = T_W + KB * LD;      // KB x KB (r rows used)
+  static constexpr int T_CE = T_P + KB * KB;     // KB
+  static constexpr int T_ZIN = T_CE + KB;        // ROWS x KB
+  static constexpr int T_V = T_ZIN + ROWS * KB;  // ROWS x KB
+  static constexpr int T_U = T_V + ROWS * KB;    // ROWS x KB
+  static constexpr int T_ZO = T_U + ROWS * KB;   // ROWS x KB
+  static constexpr int T_END = T_ZO + ROWS * KB;
+  static constexpr int TYPED_DOUBLES = (T_END * (int)sizeof(T) + 7) / 8;
+  static constexpr int PLEN = 3 * KB * KB;       // Gram accumulator (FP64)
+  static constexpr int SMALL = small_scratch<KB>();
+  static constexpr int BODY = TYPED_DOUBLES > SMALL ? TYPED_DOUBLES : SMALL;
+  static constexpr int TOTAL = PLEN + BODY;
+};
+
+// Operand pointers of the objective.
+template <typename T>
+struct Data {
+  const int* rp;
+  const int* col;
+  const T* val;  // CSR values (M_Omega or C)
+  const T* D;    // dense C or M
+};
+
+// ---------------------------------------------------------------------------
+// step scalars for objectives without a gradient pass (single thread)
+// ---------------------------------------------------------------------------
+__device__ inline void prep_scalars(const Cfg& cfg, Ctl* ctl, int lane) {
+  double gmax;
+  if (cfg.kind == DENOISE_DENSE) {
+    // lambda_max(X - M) <= lambda_max(X) - lambda_min(M), lambda_max(X) = alpha + max(0, max d)
+    const double dmax = wave_max(lane < cfg.r ? fmax(ctl->d[lane], 0.0) : 0.0);
+    gmax = ctl->alpha + dmax - ctl->op_lmin;
+  } else {
+    gmax = ctl->op_lmax;  // G = C
+  }
+  setup_step(cfg, ctl, gmax, lane);
+}
+
+// Sum of the 2-value per-workgroup partials of the gradient phase, in a fixed
+// order (one wavefront).
+__device__ inline void sum_pairs(const double* part, int P, int lane, double* s0, double* s1) {
+  double a = 0.0, b = 0.0;
+  for (int p0 = 0; p0 < P; p0 += 64 * 8) {  // P <= 1024: at most 2 rounds of 8 loads in flight
+    double va[8], vb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int p = p0 + lane + 64 * u;
+      va[u] = (p < P) ? part[2 * p] : 0.0;
+      vb[u] = (p < P) ? part[2 * p + 1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a += va[u];
+      b += vb[u];
+    }
+  }
+  *s0 = wave_sum(a);
+  *s1 = wave_sum(b);
+}
+
+// ---------------------------------------------------------------------------
+// gradient phase (masked CSR): g_e = X_ij - M_ij on Omega, with
+// X_ij = alpha [i == j] + sum_l V_il d_l V_jl; per-workgroup partials
+// (sum g^2, sum X_ij^2) -> part[wg * 2].  One wave per row, grid-stride.
+// ---------------------------------------------------------------------------
+template <typename T, int KB, int NT>
+__device__ __noinline__ void grad_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, const T* __restrict__ Qw,
+                           T* __restrict__ g, double* part, double* lds) {
+  constexpr int WAVES = NT / 64;
+  T* sd = reinterpret_cast<T*>(lds);      // KMAX
+  double* sred = lds + KMAX;               // 2 * WAVES
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = cfg.r;
   if (tid < KMAX) sd[tid] = (T)ctl->d[tid];
   const T alpha = (T)ctl->alpha;
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * 4 + wave;
+  constexpr int VN = V16<T>::N;
+  constexpr int U = 2;  // nonzeros per lane per iteration, loads issued together
   double acc = 0.0, accx = 0.0;
-  if (i < cfg.n) {
+  for (int64_t i = (int64_t)blockIdx.x * WAVES + wave; i < cfg.n; i += (int64_t)gridDim.x * WAVES) {
+    // vi_l = V_il d_l; d_l = 0 for l >= r, so whole k-wide rows can be used
     T vi[KB];
 #pragma unroll
     for (int l = 0; l < KB; ++l) vi[l] = (l < r) ? Qw[i * KB + l] * sd[l] : (T)0;
-    const int e0 = rp[i], e1 = rp[i + 1];
-    for (int e = e0 + lane; e < e1; e += 64) {
-      const int j = col[e];
-      const T* vj = Qw + (int64_t)j * KB;
-      T x = (j == i) ? alpha : (T)0;
+    const int e0 = dat.rp[i], e1 = dat.rp[i + 1];
+    for (int e = e0 + lane; e < e1; e += 64 * U) {
+      int jj[U];
+      T mv[U];
 #pragma unroll
-      for (int l = 0; l < KB; ++l)
-        if (l < r) x += vi[l] * vj[l];
-      const T gv = x - mval[e];
-      g[e] = gv;
-      acc += (double)gv * (double)gv;
-      accx += (double)x * (double)x;
+      for (int u = 0; u < U; ++u) {
+        const int eu = e + 64 * u;
+        const bool ok = eu < e1;
+        jj[u] = ok ? dat.col[eu] : (int)i;
+        mv[u] = ok ? dat.val[eu] : (T)0;
+      }
+      T vj[U][KB];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < KB / VN; ++c) vload<T>(Qw + (int64_t)jj[u] * KB + c * VN, &vj[u][c * VN]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int eu = e + 64 * u;
+        T x = (jj[u] == i) ? alpha : (T)0;
+#pragma unroll
+        for (int l = 0; l < KB; ++l) x += vi[l] * vj[u][l];
+        if (eu < e1) {
+          const T gvv = x - mv[u];
+          g[eu] = gvv;
+          acc += (double)gvv * (double)gvv;
+          accx += (double)x * (double)x;
+        }
+      }
     }
   }
   acc = wave_sum(acc);
   accx = wave_sum(accx);
   if (lane == 0) {
     sred[wave] = acc;
-    sred[4 + wave] = accx;
+    sred[WAVES + wave] = accx;
   }
   __syncthreads();
-  __shared__ double mine[2];
   if (tid == 0) {
-    mine[0] = sred[0] + sred[1] + sred[2] + sred[3];
-    mine[1] = sred[4] + sred[5] + sred[6] + sred[7];
-  }
-  __syncthreads();
-  if (tree_reduce<256>(red, mine, mine)) {
-    if (tid == 0) {
-      ctl->f = 0.5 * mine[0];
-      ctl->fvalid = 1;
-      // lambda_max(P(X) - P(M)) <= ||P(X)||_F - lambda_min(P(M)),  P = P_Omega
-      setup_step(cfg, ctl, sqrt(mine[1]) - ctl->op_lmin);
-    }
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < WAVES; ++w) { a += sred[w]; b += sred[WAVES + w]; }
+    part[(size_t)blockIdx.x * 2] = a;
+    part[(size_t)blockIdx.x * 2 + 1] = b;
   }
 }
 
 // ---------------------------------------------------------------------------
-// shared epilogue of the apply kernels
-//   sU  : ROWS x KB row sums (Op Zin) for the workgroup's rows
-//   out : Zout rows, plus Gram partials and (last workgroup) the small solve
+// apply phase: all row blocks of this workgroup, Gram partials -> part[wg]
 // ---------------------------------------------------------------------------
-template <typename T, int KB, int ROWS, int NT>
-struct ApplySmem {
-  static constexpr int LD = KB + 1;
-  // typed section (in units of T)
-  static constexpr int T_W = 0;                    // KB x LD
-  static constexpr int T_P = T_W + KB * LD;        // KB x KB (r rows used)
-  static constexpr int T_CE = T_P + KB * KB;       // KB
-  static constexpr int T_ZIN = T_CE + KB;          // ROWS x KB
-  static constexpr int T_V = T_ZIN + ROWS * KB;    // ROWS x KB
-  static constexpr int T_U = T_V + ROWS * KB;      // ROWS x KB
-  static constexpr int T_ZO = T_U + ROWS * KB;     // ROWS x KB
-  static constexpr int T_END = T_ZO + ROWS * KB;
-  static constexpr int TYPED_DOUBLES = (T_END * (int)sizeof(T) + 7) / 8;
-  static constexpr int PLEN = 3 * KB * KB;
-  static constexpr int SMALL = small_scratch<KB>();
-  static constexpr int TOTAL = PLEN + (TYPED_DOUBLES > SMALL ? TYPED_DOUBLES : SMALL);
-};
-
-template <typename T, int KB, int ROWS, int NT>
-__device__ void apply_prologue(const Cfg& cfg, const Ctl* ctl, T* tb, const T* __restrict__ Qw,
-                               const T* __restrict__ Zin, int64_t row0) {
-  using SM = ApplySmem<T, KB, ROWS, NT>;
+template <typename T, int KB, int OPK, int NT>
+__device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, const T* __restrict__ gv,
+                            const T* __restrict__ Qw, const T* __restrict__ Zin, T* __restrict__ Zout,
+                            double* part, double* smem) {
+  using SH = StepShape<T, KB, OPK, NT>;
+  constexpr int ROWS = SH::ROWS, RPW = SH::RPW;
+  using SM = ApplySmem<T, KB, ROWS>;
   constexpr int LD = SM::LD;
-  const int tid = threadIdx.x;
+  constexpr int VN = V16<T>::N;
+  T* tb = reinterpret_cast<T*>(smem + SM::PLEN);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = cfg.r;
+  const int64_t n = cfg.n;
+  // per-sweep coefficients
   for (int e = tid; e < KB * KB; e += NT) {
     tb[SM::T_W + (e / KB) * LD + (e % KB)] = (T)ctl->W[e];
     tb[SM::T_P + e] = (e / KB < r) ? (T)ctl->Pin[e] : (T)0;
   }
   if (tid < KB) tb[SM::T_CE + tid] = (T)ctl->ceff[tid];
-  for (int e = tid; e < ROWS * KB; e += NT) {
-    const int rr = e / KB, cc = e % KB;
-    const int64_t i = row0 + rr;
-    const bool ok = i < cfg.n;
-    tb[SM::T_ZIN + e] = ok ? Zin[i * KB + cc] : (T)0;
-    tb[SM::T_V + e] = (ok && cc < r) ? Qw[i * KB + cc] : (T)0;
-  }
-}
-
-// Given sU (Op Zin rows), form Zout rows, store them and run the reduction.
-template <typename T, int KB, int ROWS, int NT>
-__device__ void apply_epilogue(const Cfg& cfg, Ctl* ctl, double* smem, T* __restrict__ Zout, int64_t row0,
-                               const Red& red, int sweep, int in_buf) {
-  using SM = ApplySmem<T, KB, ROWS, NT>;
-  constexpr int LD = SM::LD;
-  T* tb = reinterpret_cast<T*>(smem + SM::PLEN);
-  const int tid = threadIdx.x;
-  const int r = cfg.r;
+  for (int e = tid; e < SM::PLEN; e += NT) smem[e] = 0.0;
   const T opscale = (T)ctl->opscale, sdiag = (T)ctl->sdiag;
-  // u = opscale*(Op Zin)_i + V_i diag(ceff) Pin + sdiag Zin_i     (in the Zin basis)
-  for (int e = tid; e < ROWS * KB; e += NT) {
-    const int rr = e / KB, a = e % KB;
-    T u = opscale * tb[SM::T_U + e] + sdiag * tb[SM::T_ZIN + e];
-    for (int l = 0; l < r; ++l) u += tb[SM::T_V + rr * KB + l] * tb[SM::T_CE + l] * tb[SM::T_P + l * KB + a];
-    tb[SM::T_ZO + e] = u;
-  }
-  __syncthreads();
-  // z = u W, store, keep in LDS (zero rows beyond n)
-  for (int e = tid; e < ROWS * KB; e += NT) {
-    const int rr = e / KB, b = e % KB;
-    T z = 0;
-#pragma unroll 8
-    for (int a = 0; a < KB; ++a) z += tb[SM::T_ZO + rr * KB + a] * tb[SM::T_W + a * LD + b];
-    const int64_t i = row0 + rr;
-    if (i < cfg.n) Zout[i * KB + b] = z; else z = 0;
-    tb[SM::T_U + e] = z;  // reuse U for Zout rows
-  }
-  __syncthreads();
-  // Gram partials in FP64 (products of working-precision values are exact)
-  for (int e = tid; e < KB * KB; e += NT) {
-    const int a = e / KB, b = e % KB;
-    double c = 0.0, gg = 0.0, p = 0.0;
-#pragma unroll 4
-    for (int rr = 0; rr < ROWS; ++rr) {
-      const double zb = (double)tb[SM::T_U + rr * KB + b];
-      c += (double)tb[SM::T_ZIN + rr * KB + a] * zb;
-      gg += (double)tb[SM::T_U + rr * KB + a] * zb;
-      p += (double)tb[SM::T_V + rr * KB + a] * zb;
+  const int64_t nblk = (n + ROWS - 1) / ROWS;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t row0 = blk * ROWS;
+    __syncthreads();  // previous block's LDS reads are done
+    for (int e = tid; e < ROWS * KB; e += NT) {
+      const int rr = e / KB, cc = e % KB;
+      const int64_t i = row0 + rr;
+      const bool ok = i < n;
+      tb[SM::T_ZIN + e] = ok ? Zin[i * KB + cc] : (T)0;
+      tb[SM::T_V + e] = (ok && cc < r) ? Qw[i * KB + cc] : (T)0;
     }
-    smem[e] = c;
-    smem[KB * KB + e] = gg;
-    smem[2 * KB * KB + e] = p;
-  }
-  __syncthreads();
-  if (tree_reduce<NT>(red, smem, smem)) {
-    small_sweep<KB, NT>(cfg, ctl, smem, smem + SM::PLEN, sweep, in_buf);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// apply, CSR operator (masked gradient values g, or linear C values)
-// ROWS rows per workgroup, one row per wave at a time.  A row's nonzeros are
-// split over lane groups of LPN lanes; each lane owns a 16-byte column chunk
-// of the gathered Zin row.
-// ---------------------------------------------------------------------------
-template <typename T, int KB, int ROWS, int NT>
-__global__ __launch_bounds__(NT) void k_apply_csr(Cfg cfg, Ctl* __restrict__ ctl, const int* __restrict__ rp,
-                                                  const int* __restrict__ col, const T* __restrict__ gv,
-                                                  const T* __restrict__ Qw, const T* __restrict__ Zin,
-                                                  T* __restrict__ Zout, Red red, int sweep, int in_buf) {
-  if (ctl->done || step_skipped(ctl)) return;
-  using SM = ApplySmem<T, KB, ROWS, NT>;
-  __shared__ double smem[SM::TOTAL];
-  T* tb = reinterpret_cast<T*>(smem + SM::PLEN);
-  constexpr int VN = V16<T>::N;
-  constexpr int LPN = KB / VN;       // lanes per nonzero
-  constexpr int NPI = 64 / LPN;      // nonzeros per wave iteration
-  constexpr int WAVES = NT / 64;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int sub = lane % LPN, grp = lane / LPN;
-  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
-  apply_prologue<T, KB, ROWS, NT>(cfg, ctl, tb, Qw, Zin, row0);
-  for (int rr = wave; rr < ROWS; rr += WAVES) {
-    const int64_t i = row0 + rr;
-    T acc[VN];
+    if constexpr (OPK == OP_CSR) {
+      // one row per wave; a row's nonzeros are split over lane groups of LPN
+      // lanes, each lane owning a 16-byte chunk of the gathered Zin row
+      constexpr int LPN = KB / VN;
+      constexpr int NPI = 64 / LPN;
+      const int sub = lane % LPN, grp = lane / LPN;
+      const int64_t i = row0 + wave;
+      T acc[VN];
 #pragma unroll
-    for (int v = 0; v < VN; ++v) acc[v] = 0;
-    if (i < cfg.n) {
-      const int e0 = rp[i], e1 = rp[i + 1];
-      for (int e = e0 + grp; e < e1; e += NPI) {
-        const int j = col[e];
-        const T w = gv[e];
-        T z[VN];
-        vload<T>(Zin + (int64_t)j * KB + sub * VN, z);
+      for (int v = 0; v < VN; ++v) acc[v] = 0;
+      if (i < n) {
+        // U nonzeros per lane group per iteration: all index/value loads,
+        // then all row gathers, are issued before the first use
+        constexpr int U = 4;
+        const int e0 = dat.rp[i], e1 = dat.rp[i + 1];
+        for (int e = e0 + grp; e < e1; e += NPI * U) {
+          int jj[U];
+          T ww[U];
 #pragma unroll
-        for (int v = 0; v < VN; ++v) acc[v] += w * z[v];
+          for (int u = 0; u < U; ++u) {
+            const int eu = e + u * NPI;
+            const bool ok = eu < e1;
+            jj[u] = ok ? dat.col[eu] : (int)i;  // in-range row, weight 0
+            ww[u] = ok ? gv[eu] : (T)0;
+          }
+          T z[U][VN];
+#pragma unroll
+          for (int u = 0; u < U; ++u) vload<T>(Zin + (int64_t)jj[u] * KB + sub * VN, z[u]);
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int v = 0; v < VN; ++v) acc[v] += ww[u] * z[u][v];
+        }
       }
+#pragma unroll
+      for (int o = LPN; o < 64; o <<= 1)
+#pragma unroll
+        for (int v = 0; v < VN; ++v) acc[v] += __shfl_xor(acc[v], o, 64);
+      if (grp == 0) {
+#pragma unroll
+        for (int v = 0; v < VN; ++v) tb[SM::T_U + wave * KB + sub * VN + v] = acc[v];
+      }
+    } else {
+      // dense: each wave owns RPW rows; column chunks of 64 with the matching
+      // 64 rows of Zin staged in LDS once for all rows of the block
+      T* zc = tb + SM::T_END;  // 64 x LD
+      T acc[RPW][KB];
+#pragma unroll
+      for (int q = 0; q < RPW; ++q)
+#pragma unroll
+        for (int c = 0; c < KB; ++c) acc[q][c] = 0;
+      for (int64_t j0 = 0; j0 < n; j0 += 64) {
+        __syncthreads();
+        for (int e = tid; e < 64 * KB; e += NT) {
+          const int jj = e / KB, c = e % KB;
+          const int64_t j = j0 + jj;
+          zc[jj * LD + c] = (j < n) ? Zin[j * KB + c] : (T)0;
+        }
+        __syncthreads();
+        const int64_t j = j0 + lane;
+        T dv[RPW];
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+          const int64_t i = row0 + wave * RPW + q;
+          dv[q] = (i < n && j < n) ? dat.D[i * cfg.ld + j] : (T)0;
+        }
+#pragma unroll
+        for (int c = 0; c < KB; ++c) {
+          const T z = zc[lane * LD + c];
+#pragma unroll
+          for (int q = 0; q < RPW; ++q) acc[q][c] += dv[q] * z;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RPW; ++q)
+#pragma unroll
+        for (int c = 0; c < KB; ++c) {
+          T v = acc[q][c];
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+          if (lane == 0) tb[SM::T_U + (wave * RPW + q) * KB + c] = v;
+        }
     }
-#pragma unroll
-    for (int o = LPN; o < 64; o <<= 1)
-#pragma unroll
-      for (int v = 0; v < VN; ++v) acc[v] += __shfl_xor(acc[v], o, 64);
-    if (grp == 0) {
-#pragma unroll
-      for (int v = 0; v < VN; ++v) tb[SM::T_U + rr * KB + sub * VN + v] = acc[v];
-    }
-  }
-  __syncthreads();
-  apply_epilogue<T, KB, ROWS, NT>(cfg, ctl, smem, Zout, row0, red, sweep, in_buf);
-}
-
-// ---------------------------------------------------------------------------
-// apply, dense operator (C or M, n x n row-major, leading dimension ld).
-// Each wave owns RPW rows; the workgroup streams column chunks of 64 and
-// stages the matching 64 rows of Zin in LDS once for all its rows.
-// ---------------------------------------------------------------------------
-template <typename T, int KB, int RPW, int NT>
-__global__ __launch_bounds__(NT) void k_apply_dense(Cfg cfg, Ctl* __restrict__ ctl, const T* __restrict__ D,
-                                                    const T* __restrict__ Qw, const T* __restrict__ Zin,
-                                                    T* __restrict__ Zout, Red red, int sweep, int in_buf) {
-  if (ctl->done || step_skipped(ctl)) return;
-  constexpr int WAVES = NT / 64;
-  constexpr int ROWS = RPW * WAVES;
-  using SM = ApplySmem<T, KB, ROWS, NT>;
-  __shared__ double smem[SM::TOTAL];
-  __shared__ T zc[64][KB + 1];
-  T* tb = reinterpret_cast<T*>(smem + SM::PLEN);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t n = cfg.n;
-  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
-  apply_prologue<T, KB, ROWS, NT>(cfg, ctl, tb, Qw, Zin, row0);
-  T acc[RPW][KB];
-#pragma unroll
-  for (int q = 0; q < RPW; ++q)
-#pragma unroll
-    for (int c = 0; c < KB; ++c) acc[q][c] = 0;
-  for (int64_t j0 = 0; j0 < n; j0 += 64) {
     __syncthreads();
-    for (int e = tid; e < 64 * KB; e += NT) {
-      const int jj = e / KB, c = e % KB;
-      const int64_t j = j0 + jj;
-      zc[jj][c] = (j < n) ? Zin[j * KB + c] : (T)0;
+    // u = opscale*(Op Zin)_i + V_i diag(ceff) Pin + sdiag Zin_i   (Zin basis)
+    for (int e = tid; e < ROWS * KB; e += NT) {
+      const int rr = e / KB, a = e % KB;
+      T u = opscale * tb[SM::T_U + e] + sdiag * tb[SM::T_ZIN + e];
+      for (int l = 0; l < r; ++l) u += tb[SM::T_V + rr * KB + l] * tb[SM::T_CE + l] * tb[SM::T_P + l * KB + a];
+      tb[SM::T_ZO + e] = u;
     }
     __syncthreads();
-    const int64_t j = j0 + lane;
-    T dv[RPW];
-#pragma unroll
-    for (int q = 0; q < RPW; ++q) {
-      const int64_t i = row0 + wave * RPW + q;
-      dv[q] = (i < n && j < n) ? D[i * cfg.ld + j] : (T)0;
-    }
-#pragma unroll
-    for (int c = 0; c < KB; ++c) {
-      const T z = zc[lane][c];
-#pragma unroll
-      for (int q = 0; q < RPW; ++q) acc[q][c] += dv[q] * z;
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < RPW; ++q)
-#pragma unroll
-    for (int c = 0; c < KB; ++c) {
-      T v = acc[q][c];
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-      if (lane == 0) tb[SM::T_U + (wave * RPW + q) * KB + c] = v;
-    }
-  __syncthreads();
-  apply_epilogue<T, KB, ROWS, NT>(cfg, ctl, smem, Zout, row0, red, sweep, in_buf);
-}
-
-// ---------------------------------------------------------------------------
-// finalize: Qw <- Zsrc Wfin, Gram of the new Qw, orthonormalising transform.
-// mode 0: end of a step (advance t); mode 1: fresh basis (init / set_iterate).
-// ---------------------------------------------------------------------------
-template <typename T, int KB, int ROWS, int NT>
-__global__ __launch_bounds__(NT) void k_finalize(Cfg cfg, Ctl* __restrict__ ctl, T* __restrict__ Qw,
-                                                 const T* __restrict__ Za, const T* __restrict__ Zb, Red red,
-                                                 int mode) {
-  if (mode == 0 && (!ctl->done || ctl->status)) return;
-  constexpr int LD = KB + 1;
-  constexpr int PLEN = KB * KB;
-  constexpr int SMALL = 2 * KB * LD + 64;
-  __shared__ double smem[PLEN + SMALL];
-  __shared__ T sWf[KB][LD];
-  __shared__ T rows_in[ROWS][KB];
-  __shared__ T rows_out[ROWS][KB];
-  const int tid = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * ROWS;
-  const int src = (mode == 0) ? ctl->src : 0;
-  const T* Zs = (src == 0) ? Qw : (src == 1 ? Za : Zb);
-  for (int e = tid; e < KB * KB; e += NT)
-    sWf[e / KB][e % KB] = (mode == 0) ? (T)ctl->Wfin[e] : (T)((e / KB) == (e % KB));
-  for (int e = tid; e < ROWS * KB; e += NT) {
-    const int64_t i = row0 + e / KB;
-    rows_in[e / KB][e % KB] = (i < cfg.n) ? Zs[i * KB + e % KB] : (T)0;
-  }
-  __syncthreads();
-  for (int e = tid; e < ROWS * KB; e += NT) {
-    const int rr = e / KB, b = e % KB;
-    T z = 0;
+    // z = u W (rows beyond n are zero)
+    for (int e = tid; e < ROWS * KB; e += NT) {
+      const int rr = e / KB, b = e % KB;
+      T z = 0;
 #pragma unroll 8
-    for (int a = 0; a < KB; ++a) z += rows_in[rr][a] * sWf[a][b];
-    const int64_t i = row0 + rr;
-    if (i < cfg.n) Qw[i * KB + b] = z; else z = 0;
-    rows_out[rr][b] = z;
-  }
-  __syncthreads();
-  for (int e = tid; e < KB * KB; e += NT) {
-    const int a = e / KB, b = e % KB;
-    double s = 0.0;
+      for (int a = 0; a < KB; ++a) z += tb[SM::T_ZO + rr * KB + a] * tb[SM::T_W + a * LD + b];
+      const int64_t i = row0 + rr;
+      if (i < n) Zout[i * KB + b] = z; else z = 0;
+      tb[SM::T_U + e] = z;
+    }
+    __syncthreads();
+    // FP64 Gram partials (products of working-precision values are exact)
+    for (int e = tid; e < KB * KB; e += NT) {
+      const int a = e / KB, b = e % KB;
+      double c = 0.0, gg = 0.0, p = 0.0;
 #pragma unroll 4
-    for (int rr = 0; rr < ROWS; ++rr) s += (double)rows_out[rr][a] * (double)rows_out[rr][b];
-    smem[e] = s;
+      for (int rr = 0; rr < ROWS; ++rr) {
+        const double zb = (double)tb[SM::T_U + rr * KB + b];
+        c += (double)tb[SM::T_ZIN + rr * KB + a] * zb;
+        gg += (double)tb[SM::T_U + rr * KB + a] * zb;
+        p += (double)tb[SM::T_V + rr * KB + a] * zb;
+      }
+      smem[e] += c;
+      smem[KB * KB + e] += gg;
+      smem[2 * KB * KB + e] += p;
+    }
   }
   __syncthreads();
-  if (tree_reduce<NT>(red, smem, smem)) {
-    basis_setup<KB, NT>(cfg, ctl, smem, smem + PLEN);
-    if (tid == 0 && mode == 0) ctl->t = ctl->t + 1;
-    if (tid == 0) ctl->fvalid = 0;
+  double* dst = part + (size_t)blockIdx.x * SM::PLEN;
+  for (int e = tid; e < SM::PLEN; e += NT) dst[e] = smem[e];
+}
+
+// ---------------------------------------------------------------------------
+// finalize phase: Qw <- Zsrc Wfin (row-local, in place when Zsrc == Qw) and
+// the Gram partial of the new Qw -> part[wg] (KB x KB)
+// mode 0: end of a step; mode 1: fresh basis (Wfin = I)
+// ---------------------------------------------------------------------------
+template <typename T, int KB, int FROWS, int NT>
+__device__ __noinline__ void finalize_phase(const Cfg& cfg, const Ctl* ctl, T* __restrict__ Qw, const T* Zs, int mode,
+                               double* part, double* smem) {
+  constexpr int LD = KB + 1;
+  double* acc = smem;                                   // KB * KB
+  T* sWf = reinterpret_cast<T*>(smem + KB * KB);        // KB x LD
+  T* rin = sWf + KB * LD;                               // FROWS x KB
+  T* rout = rin + FROWS * KB;                           // FROWS x KB
+  const int tid = threadIdx.x;
+  const int64_t n = cfg.n;
+  for (int e = tid; e < KB * KB; e += NT) {
+    sWf[(e / KB) * LD + (e % KB)] = (mode == 0) ? (T)ctl->Wfin[e] : (T)((e / KB) == (e % KB));
+    acc[e] = 0.0;
+  }
+  const int64_t nblk = (n + FROWS - 1) / FROWS;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t row0 = blk * FROWS;
+    __syncthreads();
+    for (int e = tid; e < FROWS * KB; e += NT) {
+      const int64_t i = row0 + e / KB;
+      rin[e] = (i < n) ? Zs[i * KB + e % KB] : (T)0;
+    }
+    __syncthreads();
+    for (int e = tid; e < FROWS * KB; e += NT) {
+      const int rr = e / KB, b = e % KB;
+      T z = 0;
+#pragma unroll 8
+      for (int a = 0; a < KB; ++a) z += rin[rr * KB + a] * sWf[a * LD + b];
+      const int64_t i = row0 + rr;
+      if (i < n) Qw[i * KB + b] = z; else z = 0;
+      rout[e] = z;
+    }
+    __syncthreads();
+    for (int e = tid; e < KB * KB; e += NT) {
+      const int a = e / KB, b = e % KB;
+      double s = 0.0;
+#pragma unroll 4
+      for (int rr = 0; rr < FROWS; ++rr) s += (double)rout[rr * KB + a] * (double)rout[rr * KB + b];
+      acc[e] += s;
+    }
+  }
+  __syncthreads();
+  double* dst = part + (size_t)blockIdx.x * KB * KB;
+  for (int e = tid; e < KB * KB; e += NT) dst[e] = acc[e];
+}
+
+template <typename T>
+__device__ __forceinline__ T* zbuf(T* Qw, T* Za, T* Zb, int i) {
+  return i == 0 ? Qw : (i == 1 ? Za : Zb);
+}
+
+__device__ __forceinline__ int ldi(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void stamp(const Bufs& b, int slot) {
+  if (b.ts && threadIdx.x == 0) b.ts[slot] = wall_clock64();
+}
+
+// ---------------------------------------------------------------------------
+// persistent step kernel: `nsteps` iterations of Algorithm 2, or (mode 1) a
+// fresh-basis setup only.  Launched cooperatively (all workgroups resident).
+// Grid barriers per iteration: one after the gradient, one per sweep (its
+// Gram partials are summed on the way through the barrier) and one after the
+// basis update.
+// ---------------------------------------------------------------------------
+template <typename T, int KB, int OPK, int NT>
+__global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Data<T> dat, T* __restrict__ Qw,
+                                             T* __restrict__ Za, T* __restrict__ Zb, T* __restrict__ g, Bufs b,
+                                             int nsteps, int mode) {
+  using SH = StepShape<T, KB, OPK, NT>;
+  using SM = ApplySmem<T, KB, SH::ROWS>;
+  constexpr int DENSE_STAGE = (OPK == OP_DENSE) ? (64 * (KB + 1) * (int)sizeof(T) + 7) / 8 : 0;
+  __shared__ double smem[SM::TOTAL + DENSE_STAGE];
+  const int tid = threadIdx.x;
+  const int P = gridDim.x;
+
+  if (mode == 1) {  // orthonormalising transform of a freshly uploaded basis
+    finalize_phase<T, KB, SH::FROWS, NT>(cfg, ctl, Qw, Qw, 1, b.part, smem);
+    grid_sync<NT>(b, KB * KB, [&] {
+      if (tid < 64) basis_setup<KB>(cfg, ctl, b.sums, smem, tid);
+    });
+    return;
+  }
+
+  for (int st = 0; st < nsteps; ++st) {
+    if (ldi(&ctl->stop) | ldi(&ctl->status)) break;
+    if (blockIdx.x == 0) stamp(b, 0);
+    // ---- gradient at X_t / step scalars
+    if (cfg.kind == MASKED_CSR) grad_phase<T, KB, NT>(cfg, ctl, dat, Qw, g, b.part, smem);
+    if (!grid_sync<NT>(b, 0, [&] {
+          if (tid < 64) {
+            if (cfg.kind == MASKED_CSR) {
+              double s0, s1;
+              sum_pairs(b.part, P, tid, &s0, &s1);
+              if (tid == 0) {
+                ctl->f = 0.5 * s0;
+                ctl->fvalid = 1;
+              }
+              // lambda_max(P(X) - P(M)) <= ||P(X)||_F - lambda_min(P(M)),  P = P_Omega
+              setup_step(cfg, ctl, sqrt(s1) - ctl->op_lmin, tid);
+            } else {
+              prep_scalars(cfg, ctl, tid);
+            }
+          }
+          stamp(b, 1);
+        }))
+      return;
+    // ---- block subspace sweeps with Rayleigh-Ritz
+    const T* gvals = (cfg.kind == MASKED_CSR) ? g : dat.val;
+    for (int s = 1; s <= cfg.max_inner; ++s) {
+      const int in = (s == 1) ? 0 : ((s % 2 == 0) ? 1 : 2);
+      const int out = (s == 1) ? 1 : ((s % 2 == 0) ? 2 : 1);
+      apply_phase<T, KB, OPK, NT>(cfg, ctl, dat, gvals, Qw, zbuf(Qw, Za, Zb, in), zbuf(Qw, Za, Zb, out), b.part,
+                                  smem);
+      if (!grid_sync<NT>(b, SM::PLEN, [&] {
+            stamp(b, 2 * s);
+            if (tid < 64) small_sweep<KB>(cfg, ctl, b.sums, smem, s, in, tid);
+            stamp(b, 2 * s + 1);
+          }))
+        return;
+      if (ldi(&ctl->done) | ldi(&ctl->status)) break;
+    }
+    if (ldi(&ctl->status)) break;
+    // ---- next warm-start basis and iterate
+    const T* Zs = zbuf(Qw, Za, Zb, ldi(&ctl->src));
+    finalize_phase<T, KB, SH::FROWS, NT>(cfg, ctl, Qw, Zs, 0, b.part, smem);
+    if (!grid_sync<NT>(b, KB * KB, [&] {
+          stamp(b, 2 * cfg.max_inner + 2);
+          if (tid < 64) basis_setup<KB>(cfg, ctl, b.sums, smem, tid);
+          if (tid == 0) {
+            ctl->t = ctl->t + 1;
+            ctl->fvalid = 0;
+          }
+          stamp(b, 2 * cfg.max_inner + 3);
+        }))
+      return;
   }
 }
 
+// ---------------------------------------------------------------------------
+// auxiliary kernels (ordinary launches; per-workgroup partials, then k_finish)
 // ---------------------------------------------------------------------------
 // objective at X_t, dense kinds: LINEAR sum C_ij X_ij, DENOISE 1/2 sum (X_ij - M_ij)^2
-// X_ij = alpha [i == j] + sum_l V_il d_l V_jl, accumulated in FP64.
-// One wave per row.
-// ---------------------------------------------------------------------------
+// X_ij = alpha [i == j] + sum_l V_il d_l V_jl, accumulated in FP64; one wave per row
 template <typename T, int KB>
-__global__ __launch_bounds__(256) void k_objective_dense(Cfg cfg, Ctl* __restrict__ ctl, const T* __restrict__ D,
-                                                         const T* __restrict__ Qw, Red red) {
+__global__ __launch_bounds__(256) void k_objective_dense(Cfg cfg, const Ctl* __restrict__ ctl,
+                                                         const T* __restrict__ D, const T* __restrict__ Qw,
+                                                         double* __restrict__ part) {
   __shared__ double sd[KMAX];
   __shared__ double sred[4];
-  __shared__ double mine[2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = cfg.r;
   if (tid < KMAX) sd[tid] = ctl->d[tid];
@@ -420,21 +537,16 @@ __global__ __launch_bounds__(256) void k_objective_dense(Cfg cfg, Ctl* __restric
   acc = wave_sum(acc);
   if (lane == 0) sred[wave] = acc;
   __syncthreads();
-  if (tid == 0) { mine[0] = sred[0] + sred[1] + sred[2] + sred[3]; mine[1] = 0.0; }
-  __syncthreads();
-  if (tree_reduce<256>(red, mine, mine)) {
-    if (tid == 0) { ctl->f = mine[0]; ctl->fvalid = 1; }
-  }
+  if (tid == 0) part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
 }
 
 // objective at X_t, CSR kinds (LINEAR: sum_Omega C_ij X_ij; MASKED: 1/2 sum_Omega (X_ij - M_ij)^2)
 template <typename T, int KB>
-__global__ __launch_bounds__(256) void k_objective_csr(Cfg cfg, Ctl* __restrict__ ctl, const int* __restrict__ rp,
+__global__ __launch_bounds__(256) void k_objective_csr(Cfg cfg, const Ctl* __restrict__ ctl, const int* __restrict__ rp,
                                                        const int* __restrict__ col, const T* __restrict__ val,
-                                                       const T* __restrict__ Qw, Red red) {
+                                                       const T* __restrict__ Qw, double* __restrict__ part) {
   __shared__ double sd[KMAX];
   __shared__ double sred[4];
-  __shared__ double mine[2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = cfg.r;
   if (tid < KMAX) sd[tid] = ctl->d[tid];
@@ -460,18 +572,54 @@ __global__ __launch_bounds__(256) void k_objective_csr(Cfg cfg, Ctl* __restrict_
   acc = wave_sum(acc);
   if (lane == 0) sred[wave] = acc;
   __syncthreads();
-  if (tid == 0) { mine[0] = sred[0] + sred[1] + sred[2] + sred[3]; mine[1] = 0.0; }
+  if (tid == 0) part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
+}
+
+// sum of squares of a strided matrix (rows x cols, ld) or a vector (rows = 1)
+template <typename T>
+__global__ __launch_bounds__(256) void k_sumsq(const T* __restrict__ x, int64_t rows, int64_t cols, int64_t ld,
+                                               double* __restrict__ part) {
+  __shared__ double sred[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double acc = 0.0;
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + tid; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / cols, j = e % cols;
+    const double v = (double)x[i * ld + j];
+    acc += v * v;
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) sred[wave] = acc;
   __syncthreads();
-  if (tree_reduce<256>(red, mine, mine)) {
-    if (tid == 0) { ctl->f = mine[0]; ctl->fvalid = 1; }
+  if (tid == 0) part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
+}
+
+// Sum nwg partials in a fixed order and store: what = 0 -> f (objective),
+// 1 -> data_norm = sqrt(sum).  One workgroup.
+__global__ __launch_bounds__(256) void k_finish(Ctl* __restrict__ ctl, const double* __restrict__ part, int nwg,
+                                                int what) {
+  __shared__ double s[256];
+  double a = 0.0;
+  for (int w = threadIdx.x; w < nwg; w += 256) a += part[w];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (what == 0) {
+      ctl->f = s[0];
+      ctl->fvalid = 1;
+    } else {
+      ctl->data_norm = sqrt(s[0]);
+    }
   }
 }
 
-// ---------------------------------------------------------------------------
 // y = Op x for the data operator (dense C/M or the CSR values), FP64 result.
 // Used once per context by the Lanczos estimate of the operator's extreme
 // eigenvalues.  One wave per row.
-// ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_matvec(Cfg cfg, const T* __restrict__ D, const int* __restrict__ rp,
                                                 const int* __restrict__ col, const T* __restrict__ val,
@@ -505,33 +653,6 @@ __global__ __launch_bounds__(256) void k_check_csr(const int* __restrict__ rp, c
         if (c < 0 || c >= n) { bad = 1; break; }
       }
     if (bad) atomicOr(err, 1);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// data norm: sqrt(sum of squares) of a strided matrix (rows x cols, ld) or a
-// vector (rows = 1); grid-stride, FP64.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_sumsq(const T* __restrict__ x, int64_t rows, int64_t cols, int64_t ld,
-                                               Ctl* __restrict__ ctl, Red red) {
-  __shared__ double sred[4];
-  __shared__ double mine[2];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double acc = 0.0;
-  const int64_t total = rows * cols;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + tid; e < total; e += (int64_t)gridDim.x * 256) {
-    const int64_t i = e / cols, j = e % cols;
-    const double v = (double)x[i * ld + j];
-    acc += v * v;
-  }
-  acc = wave_sum(acc);
-  if (lane == 0) sred[wave] = acc;
-  __syncthreads();
-  if (tid == 0) { mine[0] = sred[0] + sred[1] + sred[2] + sred[3]; mine[1] = 0.0; }
-  __syncthreads();
-  if (tree_reduce<256>(red, mine, mine)) {
-    if (tid == 0) ctl->data_norm = sqrt(mine[0]);
   }
 }
 

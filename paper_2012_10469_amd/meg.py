@@ -41,7 +41,6 @@ MEG_GRAD_MASKED_CSR = 3
 MEG_GRAD_QUADMEAS = 4
 
 MEG_FLAG_STRICT = 1
-MEG_FLAG_NO_GRAPH = 2
 
 EXPORTED = [
     "meg_block_size", "meg_init", "meg_step", "meg_solve", "meg_certificate", "meg_objective_value",
@@ -89,8 +88,9 @@ class MegStepInfo(ctypes.Structure):
 
 
 class MegKernelTimes(ctypes.Structure):
-    _fields_ = [("prep_ms", ctypes.c_double), ("sweep_ms", ctypes.c_double * 64), ("finalize_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double), ("sweeps_active", ctypes.c_int32), ("max_inner", ctypes.c_int32)]
+    _fields_ = [("kernel_ms", ctypes.c_double), ("prep_ms", ctypes.c_double), ("apply_ms", ctypes.c_double * 64),
+                ("small_ms", ctypes.c_double * 64), ("finalize_ms", ctypes.c_double),
+                ("sweeps_active", ctypes.c_int32), ("workgroups", ctypes.c_int32)]
 
 
 _lib: Optional[ctypes.CDLL] = None
@@ -284,11 +284,14 @@ class LowRankMEG:
         _check(self._lib.meg_set_state(self._ctx, buf, len(blob)), "meg_set_state")
 
     def profile_step(self) -> dict:
-        """Run one step with per-kernel HIP event timing (milliseconds)."""
+        """Run one step: HIP-event time of the step kernel and its phase times
+        from the kernel's own wall-clock stamps (milliseconds)."""
         out = MegKernelTimes()
         _check(self._lib.meg_profile_step(self._ctx, ctypes.byref(out)), "meg_profile_step")
-        return {"prep_ms": out.prep_ms, "sweep_ms": [out.sweep_ms[i] for i in range(out.max_inner)],
-                "finalize_ms": out.finalize_ms, "total_ms": out.total_ms, "sweeps_active": out.sweeps_active}
+        a = out.sweeps_active
+        return {"kernel_ms": out.kernel_ms, "prep_ms": out.prep_ms, "apply_ms": list(out.apply_ms[:a]),
+                "small_ms": list(out.small_ms[:a]), "finalize_ms": out.finalize_ms, "sweeps_active": a,
+                "workgroups": out.workgroups}
 
     def close(self) -> None:
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

@@ -165,18 +165,20 @@ def test_linear_csr_permuted_diagonal(meg):
             check_certificate(info, run["L"][t - 1], bulk_width=0.9)
 
 
-def test_resume_and_graph_bitwise(meg):
+def test_resume_and_batched_launch_bitwise(meg):
+    """Six single-step launches equal one six-step launch bit for bit, and a
+    saved state resumes bit for bit (reductions have a fixed order)."""
     n, r = 256, 4
-    print_case(test="resume_graph", n=n, r=r)
+    print_case(test="resume_batched", n=n, r=r)
     p = W.matrix_completion(n, seed=11, rank=3, p=0.2, r=r)
 
-    def fresh(flags=0):
-        return make_csr(p, meg.MEG_GRAD_MASKED_CSR, r, 1, eta=1.0, flags=flags)
+    def fresh():
+        return make_csr(p, meg.MEG_GRAD_MASKED_CSR, r, 1, eta=1.0)
 
-    with fresh() as a, fresh(meg.MEG_FLAG_NO_GRAPH) as b:
+    with fresh() as a, fresh() as b:
         for _ in range(6):
             a.step(info=False)
-            b.step(info=False)
+        b.solve(6)
         Va, da, aa, ta = a.get_iterate()
         Vb, db, ab, tb = b.get_iterate()
         assert ta == tb == 7
