@@ -7,10 +7,15 @@ parameter r = 10, FP32 state, warm start of the paper's experiments.  One
 the mask, warm-started block subspace iteration with Rayleigh-Ritz,
 exponentiation/normalisation, certificate).
 
-Prints ONE JSON line (see the contract in the repository documentation):
-metric/value/unit, ms_per_step, a roofline object for the dominant kernel
-(the CSR operator apply, HBM-bound) and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+Prints ONE JSON line: metric/value/unit, ms_per_step, a roofline object for
+the step kernel (the only kernel in the timed region; its average launch time
+comes from the library's HIP event pair around every launch on the context's
+stream, its algorithmic bytes from the iterations and operator applies the
+launches performed) and the FP64 CPU oracle timed on a bounded sample of the
+same workload.
+
+`--write-workload PATH` only writes the workload for the native driver
+paper_2012_10469_amd/meg_bench (used under rocprofv3) and exits.
 """
 from __future__ import annotations
 
@@ -58,6 +63,25 @@ def step_bytes(n: int, nnz: int, k: int, r: int, es: int, sweeps: float) -> floa
     return grad + sweeps * apply_bytes(n, nnz, k, r, es) + fin
 
 
+def write_workload(p, r: int, path: str) -> None:
+    """Binary workload of the native driver (layout in csrc/meg_bench.cpp)."""
+    import numpy as np
+
+    V0 = np.asarray(p.V0, dtype=np.float64)
+    lam0 = np.asarray(p.lam0, dtype=np.float64)
+    if V0.ndim == 1:
+        V0 = V0[:, None]
+    with open(path, "wb") as f:
+        f.write(b"MEGW0001")
+        f.write(np.array([p.n, p.nnz], dtype="<i8").tobytes())
+        f.write(np.array([r, V0.shape[1]], dtype="<i4").tobytes())
+        f.write(np.ascontiguousarray(p.row_ptr, dtype="<i4").tobytes())
+        f.write(np.ascontiguousarray(p.col, dtype="<i4").tobytes())
+        f.write(np.ascontiguousarray(p.val, dtype="<f4").tobytes())
+        f.write(np.asfortranarray(V0, dtype="<f8").tobytes(order="F"))
+        f.write(np.ascontiguousarray(lam0, dtype="<f8").tobytes())
+
+
 def cpu_baseline(p, r: int, samples: int):
     """The FP64 oracle as it stands, on the same problem: `samples` iterations
     (dense gradient, top-(r+1) LAPACK eigendecomposition)."""
@@ -89,8 +113,8 @@ def cpu_baseline(p, r: int, samples: int):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=512)
+    ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--r", type=int, default=10)
     ap.add_argument("--seed", type=int, default=1)
@@ -99,7 +123,15 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch-steps", type=int, default=64,
                     help="iterations per launch of the persistent step kernel (1: one meg_step per iteration)")
+    ap.add_argument("--write-workload", default=None, metavar="PATH",
+                    help="write the workload file of the native driver and exit (no GPU use)")
     args = ap.parse_args()
+
+    if args.write_workload:
+        p = matrix_completion_workload(args.n, args.r, args.seed)
+        write_workload(p, args.r, args.write_workload)
+        log(f"[bench] workload written to {args.write_workload}")
+        return 0
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -136,15 +168,26 @@ def main() -> int:
     log(f"[bench] context ready k={k}; warmup {args.warmup}")
     run(args.warmup)
     torch.cuda.synchronize()
+    g.counters(reset=True)
     log(f"[bench] timing {args.steps} steps ({args.launch_steps} per launch)")
     t0 = time.perf_counter()
     run(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     secs = t1 - t0
+    cnt = g.counters()
     cert = g.certificate()
     log(f"[bench] {args.steps} steps in {secs:.3f}s; last step inner sweeps {cert['inner_iters']} "
         f"cert_L {cert['cert_L']:.4f} eps {cert['eps_t']:.3e}")
+    assert cnt["iterations"] == args.steps, cnt
+    launches = cnt["launches"]
+    avg_launch_ms = cnt["kernel_ms"] / launches
+    iters_per_launch = cnt["iterations"] / launches
+    sweeps = cnt["applies"] / cnt["iterations"]
+    nbytes = step_bytes(p.n, p.nnz, k, args.r, 4, sweeps) * iters_per_launch
+    achieved = nbytes / (avg_launch_ms * 1e-3) / 1e9
+    log(f"[bench] step kernel: {launches} launches, {avg_launch_ms * 1e3:.1f} us each ({iters_per_launch:.1f} "
+        f"iterations, {sweeps:.2f} applies per iteration) -> {achieved:.0f} GB/s algorithmic")
 
     # one-step launches with HIP events around the step kernel, on its stream,
     # plus the kernel's own phase stamps
@@ -157,14 +200,16 @@ def main() -> int:
         act.append(pr["sweeps_active"])
         app += pr["apply_ms"]
         small += pr["small_ms"]
-    avg_kernel_ms = float(np.mean(kms))
-    sweeps = float(np.mean(act))
-    nbytes = step_bytes(p.n, p.nnz, k, args.r, 4, sweeps)
-    achieved = nbytes / (avg_kernel_ms * 1e-3) / 1e9
-    apply_gbs = apply_bytes(p.n, p.nnz, k, args.r, 4) / (float(np.mean(app)) * 1e-3) / 1e9
-    log(f"[bench] step kernel {avg_kernel_ms * 1e3:.1f} us (grid {pr['workgroups']} WGs): grad {np.mean(prep) * 1e3:.1f} us, "
-        f"apply {np.mean(app) * 1e3:.1f} us x {sweeps:.2f} ({apply_gbs:.0f} GB/s), reduce+RR {np.mean(small) * 1e3:.1f} us, "
-        f"finalize {np.mean(fin) * 1e3:.1f} us")
+    phases = None
+    if kms:
+        apply_gbs = apply_bytes(p.n, p.nnz, k, args.r, 4) / (float(np.mean(app)) * 1e-3) / 1e9
+        phases = {"one_iteration_launch_us": float(np.mean(kms)) * 1e3, "grad_us": float(np.mean(prep)) * 1e3,
+                  "apply_us": float(np.mean(app)) * 1e3, "apply_gbs": apply_gbs,
+                  "reduce_rr_us": float(np.mean(small)) * 1e3, "finalize_us": float(np.mean(fin)) * 1e3,
+                  "sweeps": float(np.mean(act))}
+        log(f"[bench] one-iteration launch {phases['one_iteration_launch_us']:.1f} us (grid {pr['workgroups']} WGs): "
+            f"grad {phases['grad_us']:.1f} us, apply {phases['apply_us']:.1f} us x {phases['sweeps']:.2f} "
+            f"({apply_gbs:.0f} GB/s), reduce+RR {phases['reduce_rr_us']:.1f} us, finalize {phases['finalize_us']:.1f} us")
 
     base = None
     if not args.no_cpu_baseline:
@@ -188,10 +233,11 @@ def main() -> int:
         "config": {"workload": "matrix_completion_csr", "n": p.n, "r": args.r, "k": k, "nnz": p.nnz,
                    "mask_p": 0.1, "truth_rank": 5, "eta": 1.0, "eps": "0.8/(t+11)^2",
                    "sweeps_per_step": sweeps, "steps_per_launch": args.launch_steps},
-        "roofline": {"bound": "hbm", "kernel": "k_step (persistent, one iteration per launch)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": nbytes, "avg_launch_us": avg_kernel_ms * 1e3,
-                     "apply_phase_gbs": apply_gbs},
+        "roofline": {"bound": "hbm", "kernel": "k_step", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": nbytes, "avg_launch_us": avg_launch_ms * 1e3,
+                     "iterations_per_launch": iters_per_launch, "applies_per_iteration": sweeps,
+                     "launches": launches, "phases": phases},
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)

@@ -211,6 +211,25 @@ typedef struct {
 
 meg_status meg_profile_step(meg_ctx ctx, meg_kernel_times* out);
 
+/* Work and time counters of the step kernel (measurement entry point),
+ * accumulated over every launch made by meg_step, meg_solve and
+ * meg_profile_step since meg_init or the last reset.  Each launch is
+ * bracketed by a HIP event pair on the context's stream; kernel_ms is the sum
+ * of those elapsed times.  Synchronises the stream.  HOST output.
+ * reset != 0: the counters restart from zero after being read.  The work
+ * counters travel with the context, not with a state blob (meg_set_state
+ * keeps them). */
+typedef struct {
+  int64_t launches;    /* step-kernel launches                                */
+  int64_t iterations;  /* iterations t -> t+1 they performed                  */
+  int64_t applies;     /* operator applies (subspace sweeps) they performed   */
+  int32_t workgroups;  /* persistent grid size                                */
+  int32_t reserved;
+  double kernel_ms;    /* GPU time of those launches, milliseconds            */
+} meg_counters;
+
+meg_status meg_get_counters(meg_ctx ctx, meg_counters* out, int32_t reset);
+
 void meg_destroy(meg_ctx ctx);
 const char* meg_status_str(meg_status s);
 

@@ -1,10 +1,12 @@
-"""Build the HIP library libmeg.so in-tree for gfx950.
+"""Build the HIP library libmeg.so, and the native driver meg_bench, in-tree
+for gfx950.
 
     python -m paper_2012_10469_amd.build
 
 The library is a plain shared object with the C ABI of include/meg.h; the
-Python binding loads it with ctypes.  Packed-FP32 instruction forms are
-disabled for every HIP translation unit.
+Python binding loads it with ctypes.  meg_bench links it (rpath $ORIGIN) and
+runs the benchmark workload without Python, for profilers.  Packed-FP32
+instruction forms are disabled for every HIP translation unit.
 """
 from __future__ import annotations
 
@@ -17,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmeg.so")
+DRIVER = os.path.join(HERE, "meg_bench")
 ARCH = os.environ.get("MEG_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["meg_api.hip"]
@@ -53,6 +56,16 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError(f"hipcc failed with exit code {res.returncode}")
     os.replace(tmp, LIB)
+    # host-only driver: no device code of its own
+    dcmd = [hipcc(), "-O2", "-std=c++17", "-Wno-unused-result", "-I", os.path.join(ROOT, "include"),
+            os.path.join(CSRC, "meg_bench.cpp"), "-L", HERE, "-lmeg", "-Wl,-rpath,$ORIGIN", "-o", DRIVER + ".tmp"]
+    if verbose:
+        print(" ".join(dcmd), flush=True)
+    res = subprocess.run(dcmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError(f"hipcc (meg_bench) failed with exit code {res.returncode}")
+    os.replace(DRIVER + ".tmp", DRIVER)
     return LIB
 
 

@@ -49,6 +49,16 @@ struct meg_ctx_s {
   unsigned* bar = nullptr;
   long long* ts = nullptr;
   size_t part_elems = 0;
+  // step-launch timing: a ring of HIP event pairs around each launch of the
+  // step kernel, harvested (elapsed time summed) when the ring is full or the
+  // counters are read
+  static constexpr int kEvRing = 32;
+  hipEvent_t ev_a[kEvRing] = {};
+  hipEvent_t ev_b[kEvRing] = {};
+  int ev_head = 0, ev_count = 0;
+  double kernel_ms = 0.0;
+  int64_t launches = 0;
+  int64_t base_iters = 0, base_applies = 0;  // device counters at the last reset
   int P = 1;               // persistent grid size
   int aux_nwg = 1;         // row-parallel auxiliary kernels
   Ctl* h_ctl = nullptr;    // pinned host mirror
@@ -150,7 +160,7 @@ struct Launch {
     return (size_t)P * std::max(3 * KB * KB, 2);
   }
 
-  static hipError_t step(meg_ctx c, int nsteps, int mode, bool stamps) {
+  static hipError_t step(meg_ctx c, int nsteps, bool stamps) {
     Cfg cfg = c->cfg;
     Ctl* ctl = c->ctl;
     Data<T> dat = data(c);
@@ -159,8 +169,20 @@ struct Launch {
     T* Zb = (T*)c->Zb;
     T* g = (T*)c->g;
     Bufs b{c->part, c->gpart, c->sums, c->bar, stamps ? c->ts : nullptr};
-    void* args[] = {&cfg, &ctl, &dat, &Qw, &Za, &Zb, &g, &b, &nsteps, &mode};
+    void* args[] = {&cfg, &ctl, &dat, &Qw, &Za, &Zb, &g, &b, &nsteps};
     const void* k = csr(c) ? kernel<OP_CSR>() : kernel<OP_DENSE>();
+    return hipLaunchCooperativeKernel(k, dim3(c->P), dim3(kStepNT), args, 0, c->stream);
+  }
+
+  // same grid as the step kernel (the barrier and partial buffers are sized for it)
+  static hipError_t basis(meg_ctx c) {
+    Cfg cfg = c->cfg;
+    Ctl* ctl = c->ctl;
+    T* Qw = (T*)c->Qw;
+    Bufs b{c->part, c->gpart, c->sums, c->bar, nullptr};
+    void* args[] = {&cfg, &ctl, &Qw, &b};
+    const void* k = csr(c) ? reinterpret_cast<const void*>(&k_basis<T, KB, OP_CSR, kStepNT>)
+                           : reinterpret_cast<const void*>(&k_basis<T, KB, OP_DENSE, kStepNT>);
     return hipLaunchCooperativeKernel(k, dim3(c->P), dim3(kStepNT), args, 0, c->stream);
   }
 
@@ -202,7 +224,10 @@ auto dispatch(meg_ctx c, Args&&... args) {
 }
 
 template <typename T, int KB> struct DoStep {
-  static hipError_t run(meg_ctx c, int nsteps, int mode, bool st) { return Launch<T, KB>::step(c, nsteps, mode, st); }
+  static hipError_t run(meg_ctx c, int nsteps, bool st) { return Launch<T, KB>::step(c, nsteps, st); }
+};
+template <typename T, int KB> struct DoBasis {
+  static hipError_t run(meg_ctx c) { return Launch<T, KB>::basis(c); }
 };
 template <typename T, int KB> struct DoObjective {
   static hipError_t run(meg_ctx c) { return Launch<T, KB>::objective(c); }
@@ -415,9 +440,38 @@ meg_status upload_iterate(meg_ctx c, const double* V, int q, const double* d, do
   std::memset(&h.info, 0, sizeof(Info));
   h.info.t = t - 1;
   HIPCHK(c, hipMemcpyAsync(c->ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, dispatch<DoStep>(c, 1, 1, false));
+  HIPCHK(c, dispatch<DoBasis>(c));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return check_barrier(c);
+}
+
+// Sum the elapsed time of the oldest timed launch into the counters.
+hipError_t harvest_one(meg_ctx c) {
+  const int h = c->ev_head;
+  hipError_t e = hipEventSynchronize(c->ev_b[h]);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev_a[h], c->ev_b[h]);
+  if (e != hipSuccess) return e;
+  c->kernel_ms += ms;
+  c->ev_head = (h + 1) % meg_ctx_s::kEvRing;
+  --c->ev_count;
+  return hipSuccess;
+}
+
+// One launch of the step kernel (nsteps iterations) between a HIP event pair.
+hipError_t launch_steps(meg_ctx c, int nsteps) {
+  if (c->ev_count == meg_ctx_s::kEvRing) {
+    const hipError_t e = harvest_one(c);
+    if (e != hipSuccess) return e;
+  }
+  const int slot = (c->ev_head + c->ev_count) % meg_ctx_s::kEvRing;
+  hipError_t e = hipEventRecord(c->ev_a[slot], c->stream);
+  if (e == hipSuccess) e = dispatch<DoStep>(c, nsteps, false);
+  if (e == hipSuccess) e = hipEventRecord(c->ev_b[slot], c->stream);
+  if (e != hipSuccess) return e;
+  ++c->ev_count;
+  ++c->launches;
+  return hipSuccess;
 }
 
 meg_status check_ctx(meg_ctx c) {
@@ -481,6 +535,10 @@ void free_ctx(meg_ctx c) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+  for (int i = 0; i < meg_ctx_s::kEvRing; ++i) {
+    if (c->ev_a[i]) (void)hipEventDestroy(c->ev_a[i]);
+    if (c->ev_b[i]) (void)hipEventDestroy(c->ev_b[i]);
+  }
   delete c;
 }
 
@@ -568,6 +626,8 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
             alloc((void**)&c->ts, kTsSlots * sizeof(long long));
   if (ok && obj->kind == MEG_GRAD_MASKED_CSR) ok = alloc(&c->g, (size_t)std::max<int64_t>(obj->nnz, 1) * c->esize);
   if (ok) ok = hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl)) == hipSuccess;
+  for (int i = 0; ok && i < meg_ctx_s::kEvRing; ++i)
+    ok = hipEventCreate(&c->ev_a[i]) == hipSuccess && hipEventCreate(&c->ev_b[i]) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     free_ctx(c);
@@ -639,7 +699,7 @@ meg_status meg_step(meg_ctx c, meg_step_info* info) {
   if (st != MEG_OK) return st;
   // f(X_t): the masked objective's gradient phase computes it in the step
   if (info && c->cfg.kind != MASKED_CSR) HIPCHK(c, dispatch<DoObjective>(c));
-  HIPCHK(c, dispatch<DoStep>(c, 1, 0, false));
+  HIPCHK(c, launch_steps(c, 1));
   if (!info) return MEG_OK;
   st = copy_ctl_to_host(c);
   if (st == MEG_OK) st = check_barrier(c);
@@ -665,7 +725,7 @@ meg_status meg_solve(meg_ctx c, int64_t max_iters, double tol, meg_step_info* la
   int64_t done = 0;
   while (done < max_iters) {
     const int m = (int)std::min<int64_t>(kChunkSteps, max_iters - done);
-    HIPCHK(c, dispatch<DoStep>(c, m, 0, false));
+    HIPCHK(c, launch_steps(c, m));
     done += m;
     if (tol > 0 && done < max_iters) {
       st = copy_ctl_to_host(c);
@@ -790,7 +850,12 @@ meg_status meg_set_state(meg_ctx c, const void* buf, size_t bytes) {
       hdr[3] != (uint32_t)(c->cfg.n >> 32) || hdr[4] != (uint32_t)c->cfg.k || hdr[5] != (uint32_t)c->cfg.r ||
       hdr[6] != (uint32_t)c->esize || hdr[7] != (uint32_t)sizeof(Ctl))
     return MEG_ERR_STATE;
+  st = copy_ctl_to_host(c);
+  if (st != MEG_OK) return st;
+  const int64_t iters = c->h_ctl->iters_done, applies = c->h_ctl->applies_done;
   std::memcpy(c->h_ctl, p + 32, sizeof(Ctl));
+  c->h_ctl->iters_done = iters;  // work counters describe this context, not the blob
+  c->h_ctl->applies_done = applies;
   HIPCHK(c, hipMemcpyAsync(c->ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->Qw, p + 32 + sizeof(Ctl), qbytes, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -809,13 +874,15 @@ meg_status meg_profile_step(meg_ctx c, meg_kernel_times* out) {
     return hip_fail(c);
   }
   bool ok = hipMemsetAsync(c->ts, 0, kTsSlots * sizeof(long long), c->stream) == hipSuccess &&
-            hipEventRecord(e0, c->stream) == hipSuccess && dispatch<DoStep>(c, 1, 0, true) == hipSuccess &&
+            hipEventRecord(e0, c->stream) == hipSuccess && dispatch<DoStep>(c, 1, true) == hipSuccess &&
             hipEventRecord(e1, c->stream) == hipSuccess && hipStreamSynchronize(c->stream) == hipSuccess;
   float ms = 0.f;
   if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (!ok) return hip_fail(c);
+  c->kernel_ms += ms;
+  ++c->launches;
   std::vector<long long> ts(kTsSlots);
   HIPCHK(c, hipMemcpy(ts.data(), c->ts, kTsSlots * sizeof(long long), hipMemcpyDeviceToHost));
   st = copy_ctl_to_host(c);
@@ -837,6 +904,29 @@ meg_status meg_profile_step(meg_ctx c, meg_kernel_times* out) {
   out->sweeps_active = used;
   out->workgroups = c->P;
   return c->h_ctl->status ? (meg_status)c->h_ctl->status : MEG_OK;
+}
+
+meg_status meg_get_counters(meg_ctx c, meg_counters* out, int32_t reset) {
+  meg_status st = check_ctx(c);
+  if (st != MEG_OK) return st;
+  if (!out) return MEG_ERR_INVALID_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  while (c->ev_count > 0) HIPCHK(c, harvest_one(c));
+  st = copy_ctl_to_host(c);
+  if (st != MEG_OK) return st;
+  std::memset(out, 0, sizeof(*out));
+  out->launches = c->launches;
+  out->iterations = c->h_ctl->iters_done - c->base_iters;
+  out->applies = c->h_ctl->applies_done - c->base_applies;
+  out->workgroups = c->P;
+  out->kernel_ms = c->kernel_ms;
+  if (reset) {
+    c->launches = 0;
+    c->kernel_ms = 0.0;
+    c->base_iters = c->h_ctl->iters_done;
+    c->base_applies = c->h_ctl->applies_done;
+  }
+  return MEG_OK;
 }
 
 void meg_destroy(meg_ctx c) {

@@ -1,0 +1,169 @@
+// meg_bench: native driver of the low-rank MEG library for profilers.
+//
+// Runs the masked matrix-completion workload (CSR mask, FP32 state) through
+// the C ABI only, without Python: warmup iterations, then a timed run of
+// meg_solve launches, then one JSON line with the library's step-kernel
+// counters (launches, iterations, operator applies, HIP-event GPU time) and
+// the host wall clock.  The workload file is written by `bench.py
+// --write-workload PATH` from the same seeded generator the benchmark uses.
+//
+// File layout (little-endian): "MEGW0001", int64 n, int64 nnz, int32 r,
+// int32 q, int32 row_ptr[n+1], int32 col[nnz], float val[nnz],
+// double V0[n*q] (column-major), double lambda0[q].
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "meg.h"
+
+namespace {
+
+struct Workload {
+  int64_t n = 0, nnz = 0;
+  int32_t r = 0, q = 0;
+  std::vector<int32_t> row_ptr, col;
+  std::vector<float> val;
+  std::vector<double> V0, lam0;
+};
+
+bool read_all(FILE* f, void* p, size_t bytes) { return bytes == 0 || std::fread(p, 1, bytes, f) == bytes; }
+
+bool load(const char* path, Workload& w) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return false;
+  char magic[8];
+  bool ok = read_all(f, magic, 8) && std::memcmp(magic, "MEGW0001", 8) == 0 && read_all(f, &w.n, 8) &&
+            read_all(f, &w.nnz, 8) && read_all(f, &w.r, 4) && read_all(f, &w.q, 4);
+  ok = ok && w.n > 0 && w.nnz >= 0 && w.r >= 1 && w.q >= 1 && w.q <= w.r && w.n < (int64_t)1 << 31 &&
+       w.nnz < (int64_t)1 << 31;
+  if (ok) {
+    w.row_ptr.resize(w.n + 1);
+    w.col.resize(w.nnz);
+    w.val.resize(w.nnz);
+    w.V0.resize((size_t)w.n * w.q);
+    w.lam0.resize(w.q);
+    ok = read_all(f, w.row_ptr.data(), w.row_ptr.size() * 4) && read_all(f, w.col.data(), w.col.size() * 4) &&
+         read_all(f, w.val.data(), w.val.size() * 4) && read_all(f, w.V0.data(), w.V0.size() * 8) &&
+         read_all(f, w.lam0.data(), w.lam0.size() * 8);
+  }
+  std::fclose(f);
+  return ok;
+}
+
+template <typename T>
+T* to_device(const std::vector<T>& h) {
+  T* d = nullptr;
+  if (hipMalloc((void**)&d, std::max<size_t>(h.size(), 1) * sizeof(T)) != hipSuccess) return nullptr;
+  if (!h.empty() && hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return nullptr;
+  }
+  return d;
+}
+
+int fail(const char* what, int code) {
+  std::fprintf(stderr, "meg_bench: %s\n", what);
+  return code;
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  if (argc < 2) return fail("usage: meg_bench WORKLOAD [--steps K] [--warmup W] [--launch-steps L] [--max-inner M]", 2);
+  int64_t steps = 512, warmup = 64, launch = 64;
+  int max_inner = 12;
+  for (int i = 2; i + 1 < argc; i += 2) {
+    const std::string a = argv[i];
+    const long long v = std::atoll(argv[i + 1]);
+    if (a == "--steps") steps = v;
+    else if (a == "--warmup") warmup = v;
+    else if (a == "--launch-steps") launch = v;
+    else if (a == "--max-inner") max_inner = (int)v;
+    else return fail("unknown option", 2);
+  }
+  if (steps < 1 || warmup < 0 || launch < 1 || max_inner < 1 || max_inner > 64) return fail("bad option value", 2);
+
+  Workload w;
+  if (!load(argv[1], w)) return fail("cannot read workload file", 2);
+  std::fprintf(stderr, "[meg_bench] n=%lld nnz=%lld r=%d q=%d\n", (long long)w.n, (long long)w.nnz, w.r, w.q);
+
+  int32_t* d_rp = to_device(w.row_ptr);
+  int32_t* d_col = to_device(w.col);
+  float* d_val = to_device(w.val);
+  if (!d_rp || !d_col || !d_val) return fail("device allocation or copy failed", 3);
+  hipStream_t stream = nullptr;
+  if (hipStreamCreate(&stream) != hipSuccess) return fail("hipStreamCreate failed", 3);
+
+  meg_params p;
+  std::memset(&p, 0, sizeof(p));
+  p.n = w.n;
+  p.r = w.r;
+  p.oversample = 4;
+  p.prec = MEG_PREC_F32;
+  p.min_inner = 1;
+  p.max_inner = max_inner;
+  p.eta = 1.0;
+  p.eps_scale = 0.8;
+  p.eps_c = 10.0;
+  p.eps_pow = 2.0;
+  p.seed = 0;
+  meg_objective o;
+  std::memset(&o, 0, sizeof(o));
+  o.kind = MEG_GRAD_MASKED_CSR;
+  o.row_ptr = d_rp;
+  o.col = d_col;
+  o.val = d_val;
+  o.nnz = w.nnz;
+  meg_start s;
+  std::memset(&s, 0, sizeof(s));
+  s.q = w.q;
+  s.V0 = w.V0.data();
+  s.lambda0 = w.lam0.data();
+
+  meg_ctx ctx = nullptr;
+  meg_status st = meg_init(&ctx, &p, &o, &s, (void*)stream);
+  if (st != MEG_OK) return fail(meg_status_str(st), 4);
+  auto run = [&](int64_t iters) -> meg_status {
+    for (int64_t done = 0; done < iters;) {
+      const int64_t m = std::min(launch, iters - done);
+      const meg_status e = meg_solve(ctx, m, 0.0, nullptr);
+      if (e != MEG_OK) return e;
+      done += m;
+    }
+    return MEG_OK;
+  };
+  std::fprintf(stderr, "[meg_bench] warmup %lld\n", (long long)warmup);
+  if ((st = run(warmup)) != MEG_OK) return fail(meg_status_str(st), 5);
+  meg_counters c;
+  if ((st = meg_get_counters(ctx, &c, 1)) != MEG_OK) return fail(meg_status_str(st), 5);
+  std::fprintf(stderr, "[meg_bench] timing %lld steps, %lld per launch\n", (long long)steps, (long long)launch);
+  const auto t0 = std::chrono::steady_clock::now();
+  if ((st = run(steps)) != MEG_OK) return fail(meg_status_str(st), 5);
+  if (hipStreamSynchronize(stream) != hipSuccess) return fail("hipStreamSynchronize failed", 5);
+  const auto t1 = std::chrono::steady_clock::now();
+  if ((st = meg_get_counters(ctx, &c, 0)) != MEG_OK) return fail(meg_status_str(st), 5);
+  meg_step_info info;
+  if ((st = meg_certificate(ctx, &info)) != MEG_OK) return fail(meg_status_str(st), 5);
+  const double wall_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  std::printf(
+      "{\"workload\": \"matrix_completion_csr\", \"n\": %lld, \"nnz\": %lld, \"r\": %d, \"steps\": %lld, "
+      "\"launch_steps\": %lld, \"launches\": %lld, \"iterations\": %lld, \"applies\": %lld, \"workgroups\": %d, "
+      "\"kernel_ms\": %.6f, \"avg_launch_us\": %.3f, \"wall_ms_per_step\": %.6f, \"iter_per_s\": %.3f, "
+      "\"t\": %lld, \"cert_L\": %.6e, \"eps_t\": %.6e}\n",
+      (long long)w.n, (long long)w.nnz, w.r, (long long)steps, (long long)launch, (long long)c.launches,
+      (long long)c.iterations, (long long)c.applies, c.workgroups, c.kernel_ms,
+      c.launches ? 1e3 * c.kernel_ms / (double)c.launches : 0.0, wall_ms / (double)steps,
+      1e3 * (double)steps / wall_ms, (long long)info.t, info.cert_L, info.eps_t);
+  std::fflush(stdout);
+  meg_destroy(ctx);
+  (void)hipStreamDestroy(stream);
+  (void)hipFree(d_rp);
+  (void)hipFree(d_col);
+  (void)hipFree(d_val);
+  return 0;
+}

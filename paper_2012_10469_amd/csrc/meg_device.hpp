@@ -73,6 +73,8 @@ struct Ctl {
   int32_t fvalid;
   int32_t polish;           // extra sweeps taken after reaching the residual floor
   int32_t pad_;
+  int64_t iters_done;       // iterations performed by step launches (counter)
+  int64_t applies_done;     // operator applies performed by step launches (counter)
   Info info;
 };
 

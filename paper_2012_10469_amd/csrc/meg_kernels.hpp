@@ -431,21 +431,13 @@ __device__ __forceinline__ void stamp(const Bufs& b, int slot) {
 template <typename T, int KB, int OPK, int NT>
 __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Data<T> dat, T* __restrict__ Qw,
                                              T* __restrict__ Za, T* __restrict__ Zb, T* __restrict__ g, Bufs b,
-                                             int nsteps, int mode) {
+                                             int nsteps) {
   using SH = StepShape<T, KB, OPK, NT>;
   using SM = ApplySmem<T, KB, SH::ROWS>;
   constexpr int DENSE_STAGE = (OPK == OP_DENSE) ? (64 * (KB + 1) * (int)sizeof(T) + 7) / 8 : 0;
   __shared__ double smem[SM::TOTAL + DENSE_STAGE];
   const int tid = threadIdx.x;
   const int P = gridDim.x;
-
-  if (mode == 1) {  // orthonormalising transform of a freshly uploaded basis
-    finalize_phase<T, KB, SH::FROWS, NT>(cfg, ctl, Qw, Qw, 1, b.part, smem);
-    grid_sync<NT>(b, KB * KB, [&] {
-      if (tid < 64) basis_setup<KB>(cfg, ctl, b.sums, smem, tid);
-    });
-    return;
-  }
 
   for (int st = 0; st < nsteps; ++st) {
     if (ldi(&ctl->stop) | ldi(&ctl->status)) break;
@@ -480,6 +472,7 @@ __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Dat
       if (!grid_sync<NT>(b, SM::PLEN, [&] {
             stamp(b, 2 * s);
             if (tid < 64) small_sweep<KB>(cfg, ctl, b.sums, smem, s, in, tid);
+            if (tid == 0) ctl->applies_done = ctl->applies_done + 1;
             stamp(b, 2 * s + 1);
           }))
         return;
@@ -494,12 +487,28 @@ __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Dat
           if (tid < 64) basis_setup<KB>(cfg, ctl, b.sums, smem, tid);
           if (tid == 0) {
             ctl->t = ctl->t + 1;
+            ctl->iters_done = ctl->iters_done + 1;
             ctl->fvalid = 0;
           }
           stamp(b, 2 * cfg.max_inner + 3);
         }))
       return;
   }
+}
+
+// Orthonormalising transform of a freshly uploaded basis Qw (cooperative
+// launch with the step kernel's grid): Gram of Qw, then the transform that
+// makes Qw W an orthonormal basis for the first sweep of the next step.
+template <typename T, int KB, int OPK, int NT>
+__global__ __launch_bounds__(NT) void k_basis(Cfg cfg, Ctl* __restrict__ ctl, T* __restrict__ Qw, Bufs b) {
+  using SH = StepShape<T, KB, OPK, NT>;
+  using SM = ApplySmem<T, KB, SH::ROWS>;
+  __shared__ double smem[SM::TOTAL];
+  const int tid = threadIdx.x;
+  finalize_phase<T, KB, SH::FROWS, NT>(cfg, ctl, Qw, Qw, 1, b.part, smem);
+  grid_sync<NT>(b, KB * KB, [&] {
+    if (tid < 64) basis_setup<KB>(cfg, ctl, b.sums, smem, tid);
+  });
 }
 
 // ---------------------------------------------------------------------------

@@ -45,7 +45,7 @@ MEG_FLAG_STRICT = 1
 EXPORTED = [
     "meg_block_size", "meg_init", "meg_step", "meg_solve", "meg_certificate", "meg_objective_value",
     "meg_get_iterate", "meg_set_iterate", "meg_get_state", "meg_set_state", "meg_profile_step", "meg_destroy",
-    "meg_status_str",
+    "meg_status_str", "meg_get_counters",
 ]
 
 
@@ -93,6 +93,11 @@ class MegKernelTimes(ctypes.Structure):
                 ("sweeps_active", ctypes.c_int32), ("workgroups", ctypes.c_int32)]
 
 
+class MegCounters(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("iterations", ctypes.c_int64), ("applies", ctypes.c_int64),
+                ("workgroups", ctypes.c_int32), ("reserved", ctypes.c_int32), ("kernel_ms", ctypes.c_double)]
+
+
 _lib: Optional[ctypes.CDLL] = None
 
 
@@ -120,6 +125,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "meg_get_state": (ctypes.c_int, [vp, vp, P(ctypes.c_size_t)]),
         "meg_set_state": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
         "meg_profile_step": (ctypes.c_int, [vp, P(MegKernelTimes)]),
+        "meg_get_counters": (ctypes.c_int, [vp, P(MegCounters), ctypes.c_int32]),
         "meg_destroy": (None, [vp]),
         "meg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     }
@@ -292,6 +298,14 @@ class LowRankMEG:
         return {"kernel_ms": out.kernel_ms, "prep_ms": out.prep_ms, "apply_ms": list(out.apply_ms[:a]),
                 "small_ms": list(out.small_ms[:a]), "finalize_ms": out.finalize_ms, "sweeps_active": a,
                 "workgroups": out.workgroups}
+
+    def counters(self, reset: bool = False) -> dict:
+        """Step-kernel launches, iterations, operator applies and their summed
+        HIP-event GPU time (ms) since init or the last reset; synchronises."""
+        out = MegCounters()
+        _check(self._lib.meg_get_counters(self._ctx, ctypes.byref(out), 1 if reset else 0), "meg_get_counters")
+        return {"launches": out.launches, "iterations": out.iterations, "applies": out.applies,
+                "workgroups": out.workgroups, "kernel_ms": out.kernel_ms}
 
     def close(self) -> None:
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

@@ -51,7 +51,9 @@ def test_struct_layout_matches_header(M):
 #define P(T) printf(#T " %zu\n", sizeof(T));
 #define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
 int main(void) {
-  P(meg_params) P(meg_objective) P(meg_start) P(meg_step_info)
+  P(meg_params) P(meg_objective) P(meg_start) P(meg_step_info) P(meg_kernel_times) P(meg_counters)
+  O(meg_kernel_times, apply_ms) O(meg_kernel_times, finalize_ms) O(meg_kernel_times, workgroups)
+  O(meg_counters, applies) O(meg_counters, workgroups) O(meg_counters, kernel_ms)
   O(meg_params, eta) O(meg_params, seed) O(meg_params, flags) O(meg_params, inner_tol)
   O(meg_objective, dense) O(meg_objective, ld) O(meg_objective, nnz) O(meg_objective, batch_idx)
   O(meg_objective, batch_steps) O(meg_start, V0) O(meg_start, lambda0)
@@ -70,7 +72,7 @@ int main(void) {
         k, v = line.split()
         want[k] = int(v)
     S = {"meg_params": M.MegParams, "meg_objective": M.MegObjective, "meg_start": M.MegStart,
-         "meg_step_info": M.MegStepInfo, "meg_kernel_times": M.MegKernelTimes}
+         "meg_step_info": M.MegStepInfo, "meg_kernel_times": M.MegKernelTimes, "meg_counters": M.MegCounters}
     for k, v in want.items():
         if "." in k:
             s, f = k.split(".")
@@ -145,4 +147,6 @@ def test_null_context_calls(M):
     assert lib.meg_step(None, ctypes.byref(info)) == M.MEG_ERR_INVALID_ARG
     assert lib.meg_solve(None, 1, 0.0, None) == M.MEG_ERR_INVALID_ARG
     assert lib.meg_certificate(None, ctypes.byref(info)) == M.MEG_ERR_INVALID_ARG
+    cnt = M.MegCounters()
+    assert lib.meg_get_counters(None, ctypes.byref(cnt), 0) == M.MEG_ERR_INVALID_ARG
     lib.meg_destroy(None)  # no-op

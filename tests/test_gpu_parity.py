@@ -183,6 +183,14 @@ def test_resume_and_batched_launch_bitwise(meg):
         Vb, db, ab, tb = b.get_iterate()
         assert ta == tb == 7
         assert np.array_equal(Va, Vb) and np.array_equal(da, db) and aa == ab
+        # work counters: same work either way, one launch vs six
+        ca, cb = a.counters(), b.counters(reset=True)
+        assert (ca["launches"], cb["launches"]) == (6, 1)
+        assert ca["iterations"] == cb["iterations"] == 6
+        assert ca["applies"] == cb["applies"] and 6 <= ca["applies"] <= 6 * 64
+        assert ca["kernel_ms"] > 0 and cb["kernel_ms"] > 0
+        assert b.counters() == {"launches": 0, "iterations": 0, "applies": 0, "workgroups": cb["workgroups"],
+                                "kernel_ms": 0.0}
         blob = a.get_state()
         for _ in range(3):
             a.step(info=False)
