@@ -47,20 +47,23 @@ def matrix_completion_workload(n: int, r: int, seed: int):
     return p
 
 
-def apply_bytes(n: int, nnz: int, k: int, r: int, es: int) -> int:
-    """Algorithmic HBM bytes of one CSR operator apply: every stored entry's
-    column index and gradient value once, the row pointers, the input block
-    Zin (n x k) once, the output block written once, and V (n x r) once."""
-    return nnz * (4 + es) + n * 4 + n * es * (2 * k + r)
+def apply_bytes(n: int, nnz: int, k: int, es: int, first: bool) -> int:
+    """Algorithmic HBM bytes of one sweep of the CSR operator apply: every
+    stored entry's column index and value once (the first sweep of a step
+    reads M_Omega and writes the gradient values; later sweeps read them
+    back), the row pointers, the input block Zin and the basis block B (the
+    same block in the first sweep) read once, and the output block written
+    once."""
+    if first:
+        return nnz * (4 + 2 * es) + 4 * (n + 1) + 2 * n * k * es
+    return nnz * (4 + es) + 4 * (n + 1) + 3 * n * k * es
 
 
-def step_bytes(n: int, nnz: int, k: int, r: int, es: int, sweeps: float) -> float:
-    """Algorithmic HBM bytes of one iteration: the gradient pass (column index
-    and M_Omega read, gradient value written, row pointers, V read), `sweeps`
-    operator applies, and the basis update (read n x k, write n x k)."""
-    grad = nnz * (4 + es + es) + n * 4 + n * es * r
-    fin = 2 * n * k * es
-    return grad + sweeps * apply_bytes(n, nnz, k, r, es) + fin
+def step_bytes(n: int, nnz: int, k: int, es: int, sweeps: float) -> float:
+    """Algorithmic HBM bytes of one iteration with `sweeps` operator applies
+    (the first one forms the gradient; the step has no other pass over the
+    data or the n x k blocks)."""
+    return apply_bytes(n, nnz, k, es, True) + (sweeps - 1.0) * apply_bytes(n, nnz, k, es, False)
 
 
 def write_workload(p, r: int, path: str) -> None:
@@ -184,16 +187,17 @@ def main() -> int:
     avg_launch_ms = cnt["kernel_ms"] / launches
     iters_per_launch = cnt["iterations"] / launches
     sweeps = cnt["applies"] / cnt["iterations"]
-    nbytes = step_bytes(p.n, p.nnz, k, args.r, 4, sweeps) * iters_per_launch
+    nbytes = step_bytes(p.n, p.nnz, k, 4, sweeps) * iters_per_launch
     achieved = nbytes / (avg_launch_ms * 1e-3) / 1e9
     log(f"[bench] step kernel: {launches} launches, {avg_launch_ms * 1e3:.1f} us each ({iters_per_launch:.1f} "
         f"iterations, {sweeps:.2f} applies per iteration) -> {achieved:.0f} GB/s algorithmic")
 
     # one-step launches with HIP events around the step kernel, on its stream,
     # plus the kernel's own phase stamps
-    kms, prep, fin, act, app, small = [], [], [], [], [], []
+    kms, prep, fin, act, app, small, wgs = [], [], [], [], [], [], []
     for _ in range(args.profile_steps):
         pr = g.profile_step()
+        wgs.append(pr)
         kms.append(pr["kernel_ms"])
         prep.append(pr["prep_ms"])
         fin.append(pr["finalize_ms"])
@@ -202,11 +206,26 @@ def main() -> int:
         small += pr["small_ms"]
     phases = None
     if kms:
-        apply_gbs = apply_bytes(p.n, p.nnz, k, args.r, 4) / (float(np.mean(app)) * 1e-3) / 1e9
+        apply_gbs = (apply_bytes(p.n, p.nnz, k, 4, True) + apply_bytes(p.n, p.nnz, k, 4, False)) / 2 \
+            / (float(np.mean(app)) * 1e-3) / 1e9
         phases = {"one_iteration_launch_us": float(np.mean(kms)) * 1e3, "grad_us": float(np.mean(prep)) * 1e3,
                   "apply_us": float(np.mean(app)) * 1e3, "apply_gbs": apply_gbs,
                   "reduce_rr_us": float(np.mean(small)) * 1e3, "finalize_us": float(np.mean(fin)) * 1e3,
                   "sweeps": float(np.mean(act))}
+        for sw in range(2):
+            rows = [w for w in wgs if len(w["wg_apply_ms"]) > sw]
+            if rows:
+                mn, av, mx = (float(np.mean([w["wg_apply_ms"][sw][q] for w in rows])) * 1e3 for q in range(3))
+                sk = float(np.mean([w["wg_skew_ms"][sw] for w in rows])) * 1e3
+                rd = float(np.mean([w["reduce_ms"][sw] for w in rows])) * 1e3
+                phases[f"sweep{sw + 1}_wg_us"] = {"min": mn, "mean": av, "max": mx, "start_skew": sk, "reduce": rd}
+                log(f"[bench]   sweep {sw + 1}: workgroup apply {mn:.1f}/{av:.1f}/{mx:.1f} us (min/mean/max), "
+                    f"start skew {sk:.1f} us, tree reduction {rd:.1f} us")
+        rr = np.mean([w["rr_ms"] for w in wgs], axis=0) * 1e3
+        js = float(np.mean([w["jacobi_sweeps"] for w in wgs]))
+        phases["rayleigh_ritz_us"] = {"pre": rr[0], "jacobi": rr[1], "test": rr[2], "tail": rr[3], "jacobi_sweeps": js}
+        log(f"[bench]   first Rayleigh-Ritz: pre {rr[0]:.1f} us, Jacobi {rr[1]:.1f} us ({js:.1f} sweeps), "
+            f"sort+residuals {rr[2]:.1f} us, tail {rr[3]:.1f} us")
         log(f"[bench] one-iteration launch {phases['one_iteration_launch_us']:.1f} us (grid {pr['workgroups']} WGs): "
             f"grad {phases['grad_us']:.1f} us, apply {phases['apply_us']:.1f} us x {phases['sweeps']:.2f} "
             f"({apply_gbs:.0f} GB/s), reduce+RR {phases['reduce_rr_us']:.1f} us, finalize {phases['finalize_us']:.1f} us")

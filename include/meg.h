@@ -201,12 +201,27 @@ meg_status meg_set_state(meg_ctx ctx, const void* buf, size_t bytes);
  * barriers; synchronises.  HOST output; times in milliseconds. */
 typedef struct {
   double kernel_ms;      /* the step kernel, HIP events around the launch    */
-  double prep_ms;        /* gradient pass (masked CSR) or scalar setup       */
-  double apply_ms[64];   /* sweep s: operator apply + Gram partials          */
+  double prep_ms;        /* work before the first sweep (0: the step scalars
+                            are set at the end of the previous step and the
+                            masked gradient is formed within sweep 1)        */
+  double apply_ms[64];   /* sweep s: operator apply + Gram partials; sweep 1
+                            of the masked objective also forms the gradient  */
   double small_ms[64];   /* sweep s: partial reduction + Rayleigh-Ritz/QR    */
   double finalize_ms;    /* next basis + its orthonormalising transform      */
   int32_t sweeps_active; /* sweeps the step used                             */
   int32_t workgroups;    /* persistent grid size                             */
+  /* sweeps 1 and 2 (zero when not run), per workgroup: */
+  double wg_apply_ms[2][3]; /* time from the workgroup's start of the sweep to
+                               its arrival at the sweep's barrier: min, mean, max */
+  double wg_skew_ms[2];     /* spread of the workgroups' start times          */
+  double reduce_ms[2];      /* last arrival -> start of the small solve (the
+                               partial sums reduced along the barrier tree)  */
+  /* first Rayleigh-Ritz sweep of the step: */
+  double rr_ms[3];          /* before the eigensolver (loads, T = W^T C), the
+                               Jacobi eigensolver, sort + residuals + test   */
+  double rr_tail_ms;        /* the rest: next transform, or the step's end  */
+  int32_t jacobi_sweeps;    /* Jacobi sweeps it took                          */
+  int32_t reserved;
 } meg_kernel_times;
 
 meg_status meg_profile_step(meg_ctx ctx, meg_kernel_times* out);

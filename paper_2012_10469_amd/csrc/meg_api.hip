@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -26,7 +27,7 @@ constexpr int kStepNT = 512;                   // threads per persistent workgro
 constexpr int kMaxWgPerCu = 2;
 constexpr int kMaxGrid = kBarGroupSize * kBarMaxGroups;  // barrier capacity
 constexpr int kChunkSteps = 64;                // iterations per launch in meg_solve
-constexpr int kTsSlots = 2 * 64 + 8;
+constexpr int kTsSlots = kTsTotal;
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
@@ -157,7 +158,7 @@ struct Launch {
   }
 
   static size_t part_need(int P) {
-    return (size_t)P * std::max(3 * KB * KB, 2);
+    return (size_t)P * (3 * KB * KB + 2);  // Gram partials + the objective's two partials
   }
 
   static hipError_t step(meg_ctx c, int nsteps, bool stamps) {
@@ -178,23 +179,30 @@ struct Launch {
   static hipError_t basis(meg_ctx c) {
     Cfg cfg = c->cfg;
     Ctl* ctl = c->ctl;
-    T* Qw = (T*)c->Qw;
+    T* Z0 = (T*)c->Qw;
+    T* Z1 = (T*)c->Za;
+    T* Z2 = (T*)c->Zb;
     Bufs b{c->part, c->gpart, c->sums, c->bar, nullptr};
-    void* args[] = {&cfg, &ctl, &Qw, &b};
+    void* args[] = {&cfg, &ctl, &Z0, &Z1, &Z2, &b};
     const void* k = csr(c) ? reinterpret_cast<const void*>(&k_basis<T, KB, OP_CSR, kStepNT>)
                            : reinterpret_cast<const void*>(&k_basis<T, KB, OP_DENSE, kStepNT>);
     return hipLaunchCooperativeKernel(k, dim3(c->P), dim3(kStepNT), args, 0, c->stream);
   }
 
+  // f(X_t): the basis is first written out explicitly (V = (B Wb)[:, :r])
   static hipError_t objective(meg_ctx c) {
     const Cfg& cfg = c->cfg;
     const int nwg = ceil_div(cfg.n, 4);
+    const int mwg = (int)std::min<int64_t>(4096, ceil_div(cfg.n * KB, 256));
+    hipLaunchKernelGGL((k_materialize<T, KB>), dim3(mwg), dim3(256), 0, c->stream, cfg, c->ctl, (T*)c->Qw, (T*)c->Za,
+                       (T*)c->Zb);
     if (csr(c))
       hipLaunchKernelGGL((k_objective_csr<T, KB>), dim3(nwg), dim3(256), 0, c->stream, cfg, c->ctl, c->obj.row_ptr,
-                         c->obj.col, (const T*)c->obj.val, (const T*)c->Qw, c->part);
+                         c->obj.col, (const T*)c->obj.val, (const T*)c->Qw, (const T*)c->Za, (const T*)c->Zb,
+                         c->part);
     else
       hipLaunchKernelGGL((k_objective_dense<T, KB>), dim3(nwg), dim3(256), 0, c->stream, cfg, c->ctl,
-                         (const T*)c->obj.dense, (const T*)c->Qw, c->part);
+                         (const T*)c->obj.dense, (const T*)c->Qw, (const T*)c->Za, (const T*)c->Zb, c->part);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, c->stream, c->ctl, c->part, nwg, 0);
     return hipGetLastError();
   }
@@ -372,6 +380,9 @@ meg_status lanczos_extremes(meg_ctx c, double* lmin, double* lmax) {
   return MEG_OK;
 }
 
+// n x k block i (0, 1, 2) of the context
+void* block(meg_ctx c, int i) { return i == 0 ? c->Qw : (i == 1 ? c->Za : c->Zb); }
+
 meg_status copy_ctl_to_host(meg_ctx c) {
   HIPCHK(c, hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -436,6 +447,8 @@ meg_status upload_iterate(meg_ctx c, const double* V, int q, const double* d, do
   h.status = 0;
   h.fvalid = 0;
   h.polish = 0;
+  h.pxvalid = 0;  // the shift falls back to the a-priori bound for the new iterate
+  h.dxnorm = 0.0;
   h.solve_tol = 0.0;
   std::memset(&h.info, 0, sizeof(Info));
   h.info.t = t - 1;
@@ -778,18 +791,25 @@ meg_status meg_get_iterate(meg_ctx c, double* V, double* d, double* alpha, int64
   const Cfg& cfg = c->cfg;
   st = copy_ctl_to_host(c);
   if (st != MEG_OK) return st;
-  if (V) {
-    const size_t cnt = (size_t)cfg.n * cfg.k;
+  if (V) {  // V = (B Wb)[:, :r], B = block src
+    const int k = cfg.k;
+    const size_t cnt = (size_t)cfg.n * k;
     std::vector<double> B(cnt);
+    const void* blk = block(c, c->h_ctl->src);
     if (c->esize == 8) {
-      HIPCHK(c, hipMemcpy(B.data(), c->Qw, cnt * 8, hipMemcpyDeviceToHost));
+      HIPCHK(c, hipMemcpy(B.data(), blk, cnt * 8, hipMemcpyDeviceToHost));
     } else {
       std::vector<float> Bf(cnt);
-      HIPCHK(c, hipMemcpy(Bf.data(), c->Qw, cnt * 4, hipMemcpyDeviceToHost));
+      HIPCHK(c, hipMemcpy(Bf.data(), blk, cnt * 4, hipMemcpyDeviceToHost));
       for (size_t i = 0; i < cnt; ++i) B[i] = Bf[i];
     }
-    for (int l = 0; l < cfg.r; ++l)
-      for (int64_t i = 0; i < cfg.n; ++i) V[(size_t)l * cfg.n + i] = B[(size_t)i * cfg.k + l];
+    const double* Wb = c->h_ctl->Wb;
+    for (int64_t i = 0; i < cfg.n; ++i)
+      for (int l = 0; l < cfg.r; ++l) {
+        double v = 0.0;
+        for (int q = 0; q < k; ++q) v += B[(size_t)i * k + q] * Wb[q * k + l];
+        V[(size_t)l * cfg.n + i] = v;
+      }
   }
   if (d)
     for (int l = 0; l < cfg.r; ++l) d[l] = c->h_ctl->d[l];
@@ -832,7 +852,7 @@ meg_status meg_get_state(meg_ctx c, void* buf, size_t* bytes) {
                      (uint32_t)c->cfg.r, (uint32_t)c->esize, (uint32_t)sizeof(Ctl)};
   std::memcpy(p, hdr, 32);
   std::memcpy(p + 32, c->h_ctl, sizeof(Ctl));
-  HIPCHK(c, hipMemcpy(p + 32 + sizeof(Ctl), c->Qw, qbytes, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(p + 32 + sizeof(Ctl), block(c, c->h_ctl->src), qbytes, hipMemcpyDeviceToHost));
   *bytes = need;
   return MEG_OK;
 }
@@ -857,7 +877,8 @@ meg_status meg_set_state(meg_ctx c, const void* buf, size_t bytes) {
   c->h_ctl->iters_done = iters;  // work counters describe this context, not the blob
   c->h_ctl->applies_done = applies;
   HIPCHK(c, hipMemcpyAsync(c->ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->Qw, p + 32 + sizeof(Ctl), qbytes, hipMemcpyHostToDevice, c->stream));
+  if (c->h_ctl->src < 0 || c->h_ctl->src > 2) return MEG_ERR_STATE;
+  HIPCHK(c, hipMemcpyAsync(block(c, c->h_ctl->src), p + 32 + sizeof(Ctl), qbytes, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return MEG_OK;
 }
@@ -900,9 +921,38 @@ meg_status meg_profile_step(meg_ctx c, meg_kernel_times* out) {
     out->apply_ms[s - 1] = (ts[2 * s] - ts[2 * s - 1]) * tick_ms;
     out->small_ms[s - 1] = (ts[2 * s + 1] - ts[2 * s]) * tick_ms;
   }
-  out->finalize_ms = (ts[2 * mi + 3] - ts[2 * used + 1]) * tick_ms;
+  out->finalize_ms = 0.0;  // the step ends inside its last sweep's small solve
   out->sweeps_active = used;
   out->workgroups = c->P;
+  const int P = c->P;
+  for (int s = 1; s <= std::min(used, kTsWgSweeps); ++s) {
+    const long long* st = &ts[kTsWg + (size_t)(2 * (s - 1)) * P];
+    const long long* ar = &ts[kTsWg + (size_t)(2 * (s - 1) + 1) * P];
+    long long dmin = LLONG_MAX, dmax = 0, smin = LLONG_MAX, smax = 0, amax = 0;
+    double dsum = 0.0;
+    for (int w = 0; w < P; ++w) {
+      const long long d = ar[w] - st[w];
+      dmin = std::min(dmin, d);
+      dmax = std::max(dmax, d);
+      dsum += (double)d;
+      smin = std::min(smin, st[w]);
+      smax = std::max(smax, st[w]);
+      amax = std::max(amax, ar[w]);
+    }
+    out->wg_apply_ms[s - 1][0] = dmin * tick_ms;
+    out->wg_apply_ms[s - 1][1] = dsum / P * tick_ms;
+    out->wg_apply_ms[s - 1][2] = dmax * tick_ms;
+    out->wg_skew_ms[s - 1] = (smax - smin) * tick_ms;
+    out->reduce_ms[s - 1] = (ts[2 * s] - amax) * tick_ms;
+  }
+  const int rs = c->cfg.rr_from;
+  if (used >= rs && ts[kTsRR + 3] > 0) {
+    out->rr_ms[0] = (ts[kTsRR] - ts[2 * rs]) * tick_ms;
+    out->rr_ms[1] = (ts[kTsRR + 1] - ts[kTsRR]) * tick_ms;
+    out->rr_ms[2] = (ts[kTsRR + 2] - ts[kTsRR + 1]) * tick_ms;
+    out->rr_tail_ms = (ts[kTsRR + 3] - ts[kTsRR + 2]) * tick_ms;
+    out->jacobi_sweeps = (int32_t)ts[kTsRR + 4];
+  }
   return c->h_ctl->status ? (meg_status)c->h_ctl->status : MEG_OK;
 }
 

@@ -1,9 +1,11 @@
 // Device-side data structures and helpers of the low-rank MEG library (gfx950).
 //
 // Layout in HBM (per context):
-//   Qw   n x k  row-major, stride k: the warm-start basis; its first r columns
-//               are V of the factored iterate X_t = alpha I + V diag(d) V^T
-//   Za,Zb n x k ping-pong outputs of the operator apply, same layout
+//   Z0,Z1,Z2 n x k row-major, stride k: three blocks.  One of them (index
+//               ctl->src) holds B, the warm-start basis in implicit form:
+//               Q_t = B Wb is orthonormal and V = Q_t[:, :r] is V of the
+//               factored iterate X_t = alpha I + V diag(d) V^T; the other two
+//               take the outputs of the operator applies in turn
 //   g    nnz    gradient values on Omega (masked objective)
 //   Ctl  one control block (FP64 scalars and k x k transforms)
 //   Bufs per-workgroup partial sums (FP64), their reduction, barrier words
@@ -16,6 +18,16 @@
 namespace meg {
 
 constexpr int KMAX = 32;
+
+// Pointer into LDS.  The explicit address space lets functions that are not
+// inlined into the kernel use LDS instructions; through a generic pointer
+// they would use flat accesses, which are slower.
+template <typename T>
+using lds = __attribute__((address_space(3))) T;
+// Pointer into global memory, for the same reason (flat accesses also wait
+// on both the vector-memory and the LDS counters).
+template <typename T>
+using gbl = __attribute__((address_space(1))) T;
 
 // Objective kinds (mirror meg_grad_kind).
 enum Kind : int32_t { LINEAR_DENSE = 0, DENOISE_DENSE = 1, LINEAR_CSR = 2, MASKED_CSR = 3, QUADMEAS = 4 };
@@ -49,9 +61,9 @@ struct Info {
 
 // Device control block: everything the step kernels exchange.
 struct Ctl {
-  double W[KMAX * KMAX];    // Q = Zin W is the (implicit, orthonormal) sweep basis
-  double Pin[KMAX * KMAX];  // V^T Zin (r x k, row l, column b)
-  double Wfin[KMAX * KMAX]; // final transform: Qw_next = Zsrc Wfin
+  double W[KMAX * KMAX];    // Q = Zin W is the (implicit, orthonormal) basis of the current sweep
+  double PW[KMAX * KMAX];   // V^T Q = V^T Zin W (r x k, row l, column b)
+  double Wb[KMAX * KMAX];   // basis transform: Q_t = B Wb, B = block `src`
   double theta[KMAX];       // Ritz values of the last Rayleigh-Ritz
   double resid[KMAX];       // Ritz residual norms
   double d[KMAX];           // X_t = alpha I + V diag(d) V^T
@@ -67,12 +79,14 @@ struct Ctl {
   int64_t t;                // current iteration index (X_t)
   int32_t done;             // inner solve of this step finished
   int32_t sweep;            // next sweep index (1-based)
-  int32_t src;              // buffer holding the input of the final sweep
+  int32_t src;              // block holding B
   int32_t stop;             // meg_solve reached its tolerance: skip work
   int32_t status;           // 0 ok, else a meg_status code (sticky)
   int32_t fvalid;
   int32_t polish;           // extra sweeps taken after reaching the residual floor
-  int32_t pad_;
+  int32_t pxvalid;          // pxnorm holds ||P_Omega X_t||_F of the current t
+  double pxnorm;            // ||P_Omega X_t||_F measured in sweep 1 (masked objective)
+  double dxnorm;            // ||X_{t+1} - X_t||_F of the last step
   int64_t iters_done;       // iterations performed by step launches (counter)
   int64_t applies_done;     // operator applies performed by step launches (counter)
   Info info;
@@ -97,6 +111,15 @@ constexpr int kBarTop = 0, kBarGen = 32, kBarErr = 64, kBarGroup0 = 96, kBarStri
 constexpr int kBarGroupSize = 16;
 constexpr int kBarMaxGroups = 64;  // up to 1024 workgroups
 constexpr int kBarWords = kBarGroup0 + kBarStride * kBarMaxGroups;
+
+// Phase timestamps (device wall clock) of a profiled launch: slots
+// [0, kTsWg) are stamped by one workgroup at phase boundaries; from kTsWg on,
+// every workgroup stamps the start of sweeps 1-2 and its arrival at their
+// barriers: ts[kTsWg + (2 (s - 1) + e) * gridDim.x + wg], e = 0 start, 1 arrival.
+constexpr int kTsRR = 140;  // 5 slots: parts of the first Rayleigh-Ritz sweep
+constexpr int kTsWg = 160;
+constexpr int kTsWgSweeps = 2;
+constexpr int kTsTotal = kTsWg + 2 * kTsWgSweeps * kBarGroupSize * kBarMaxGroups;
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

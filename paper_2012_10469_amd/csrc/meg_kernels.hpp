@@ -2,19 +2,20 @@
 //
 // One step t (Algorithm 2, Section 3) runs inside ONE persistent, cooperatively
 // launched kernel (k_step), phases separated by grid barriers:
-//   grad   : masked objective: gradient values on Omega at X_t, f(X_t) and the
-//            norms that set the solver's shift (other objectives: shift only)
 //   sweep s: apply   Zout = Yhat (Zin W) for the implicit orthonormal basis
 //                    Q = Zin W, Yhat = V diag(ceff) V^T + opscale*Op + sdiag*I,
-//                    with FP64 Gram partials Zin^T Zout, Zout^T Zout, V^T Zout
+//                    with FP64 Gram partials Zin^T Zout, Zout^T Zout, V^T Zout;
+//                    in sweep 1 of the masked objective the gradient values on
+//                    Omega at X_t (and f(X_t)) are formed from the same gathers
 //            barrier the partials are summed along the arrival tree
 //            small   Cholesky QR (sweep 1) or Rayleigh-Ritz + Cholesky QR in
 //                    FP64, one wavefront of the last workgroup to arrive;
 //                    stops the sweep loop when the Ritz residuals meet the
 //                    tolerance
-//   final  : Qw <- Zsrc Wfin (Ritz basis = next warm start; its first r
-//            columns are V_{t+1}) and its Gram, whose Cholesky factor
-//            orthonormalises the first sweep of step t+1
+// The step ends in the small solve of its last sweep: the Ritz basis of that
+// sweep, Zin (W S), is the next warm start, kept implicit as (B, Wb) = (Zin,
+// W S) so no pass over the n x k block is needed; the shift and
+// coefficients of step t+1 follow from the new factored iterate.
 // Cross-workgroup communication happens only at the barriers, so no
 // workgroup writes back or invalidates the L2 while others stream through it.
 #pragma once
@@ -47,6 +48,35 @@ __device__ __forceinline__ void vload(const T* p, T* out) {
   }
 }
 
+// Sum over aligned groups of G lanes (G a power of two <= 64); every lane of
+// a group receives its group's sum.  Exchanges within a quad use DPP quad
+// permutes (xor 1: [1,0,3,2], xor 2: [2,3,0,1]); wider ones use shuffles.
+__device__ __forceinline__ float dpp_xor(float v, int m) {
+  const int x = __float_as_int(v);
+  return __int_as_float(m == 1 ? __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true)
+                               : __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double dpp_xor(double v, int m) {
+  const long long b = __double_as_longlong(v);
+  int lo = (int)b, hi = (int)(b >> 32);
+  if (m == 1) {
+    lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, true);
+    hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, true);
+  } else {
+    lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, true);
+    hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, true);
+  }
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  if constexpr (G >= 2) v += dpp_xor(v, 1);
+  if constexpr (G >= 4) v += dpp_xor(v, 2);
+#pragma unroll
+  for (int o = 4; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // Scratch doubles the small solves need (they reuse the apply's LDS).
 template <int KB>
 constexpr int small_scratch() { return 5 * KB * (KB + 1) + 8 * KB; }
@@ -60,23 +90,28 @@ struct StepShape {
   static constexpr int WAVES = NT / 64;
   static constexpr int RPW = (OPK == OP_CSR) ? 1 : dense_rpw<T, KB>();
   static constexpr int ROWS = WAVES * RPW;  // rows per apply block
-  static constexpr int FROWS = 2 * WAVES;   // rows per finalize block
+  static constexpr int GROWS = 2 * WAVES;   // rows per block of the basis Gram
 };
 
 template <typename T, int KB, int ROWS>
 struct ApplySmem {
   static constexpr int LD = KB + 1;
+  static constexpr int WAVES_MAX = 16;
   // typed section (in units of T)
-  static constexpr int T_W = 0;                  // KB x LD
-  static constexpr int T_P = T_W + KB * LD;      // KB x KB (r rows used)
-  static constexpr int T_CE = T_P + KB * KB;     // KB
-  static constexpr int T_ZIN = T_CE + KB;        // ROWS x KB
-  static constexpr int T_V = T_ZIN + ROWS * KB;  // ROWS x KB
-  static constexpr int T_U = T_V + ROWS * KB;    // ROWS x KB
-  static constexpr int T_ZO = T_U + ROWS * KB;   // ROWS x KB
-  static constexpr int T_END = T_ZO + ROWS * KB;
+  static constexpr int T_W = 0;                   // KB x LD   sweep transform W
+  static constexpr int T_WB = T_W + KB * LD;      // KB x LD   basis transform Wb
+  static constexpr int T_PW = T_WB + KB * LD;     // KB x KB   V^T Q (r rows used)
+  static constexpr int T_CE = T_PW + KB * KB;     // KB
+  static constexpr int T_ZIN = T_CE + KB;         // ROWS x KB
+  static constexpr int T_B = T_ZIN + ROWS * KB;   // ROWS x KB basis rows
+  static constexpr int T_V = T_B + ROWS * KB;     // ROWS x KB V rows (zero beyond r)
+  static constexpr int T_U = T_V + ROWS * KB;     // ROWS x KB
+  static constexpr int T_ZO = T_U + ROWS * KB;    // ROWS x KB
+  static constexpr int T_GW = T_ZO + ROWS * KB;   // WAVES x 3 x KB, fused gradient
+  static constexpr int T_END = T_GW + 3 * WAVES_MAX * KB;
   static constexpr int TYPED_DOUBLES = (T_END * (int)sizeof(T) + 7) / 8;
   static constexpr int PLEN = 3 * KB * KB;       // Gram accumulator (FP64)
+  static constexpr int PSTRIDE = PLEN + 2;        // per-workgroup partials: Gram, sum g^2, sum X_ij^2
   static constexpr int SMALL = small_scratch<KB>();
   static constexpr int BODY = TYPED_DOUBLES > SMALL ? TYPED_DOUBLES : SMALL;
   static constexpr int TOTAL = PLEN + BODY;
@@ -92,179 +127,186 @@ struct Data {
 };
 
 // ---------------------------------------------------------------------------
-// step scalars for objectives without a gradient pass (single thread)
+// step scalars of the NEXT iteration t, set before it starts (one
+// wavefront).  gmax >= lambda_max(grad f(X_t)):
+//   linear   G = C:               lambda_max(C)
+//   denoise  G = X - M:           lambda_max(X) - lambda_min(M), lambda_max(X) = alpha + max(0, max d)
+//   masked   G = P(X) - P(M):     ||P(X_t)||_2 - lambda_min(P(M))   (P = P_Omega), with
+//            ||P(X_t)||_2 <= ||P(X_{t-1})||_F + ||X_t - X_{t-1}||_F  (both known
+//            from the previous step), or ||P(X_t)||_2 <= ||X_t||_F with
+//            ||X_t||_F^2 = (n - r) alpha^2 + sum_l (alpha + d_l)^2 after a new start
+// so the shift needs no pass over the data and the gradient can be formed
+// inside the first sweep.
 // ---------------------------------------------------------------------------
-__device__ inline void prep_scalars(const Cfg& cfg, Ctl* ctl, int lane) {
+__device__ inline void step_scalars(const Cfg& cfg, gbl<Ctl>* ctl, int lane) {
+  const double alpha = ctl->alpha;
+  const bool act = lane < cfg.r;
+  const double dl = act ? ctl->d[lane] : 0.0;
   double gmax;
   if (cfg.kind == DENOISE_DENSE) {
-    // lambda_max(X - M) <= lambda_max(X) - lambda_min(M), lambda_max(X) = alpha + max(0, max d)
-    const double dmax = wave_max(lane < cfg.r ? fmax(ctl->d[lane], 0.0) : 0.0);
-    gmax = ctl->alpha + dmax - ctl->op_lmin;
+    gmax = alpha + wave_max(act ? fmax(dl, 0.0) : 0.0) - ctl->op_lmin;
+  } else if (cfg.kind == MASKED_CSR) {
+    const double ev = alpha + dl;
+    const double fro2 = (double)(cfg.n - cfg.r) * alpha * alpha + wave_sum(act ? ev * ev : 0.0);
+    const double px = ctl->pxvalid ? fmin(ctl->pxnorm + ctl->dxnorm, sqrt(fro2)) : sqrt(fro2);
+    gmax = px - ctl->op_lmin;
   } else {
-    gmax = ctl->op_lmax;  // G = C
+    gmax = ctl->op_lmax;
   }
   setup_step(cfg, ctl, gmax, lane);
 }
 
-// Sum of the 2-value per-workgroup partials of the gradient phase, in a fixed
-// order (one wavefront).
-__device__ inline void sum_pairs(const double* part, int P, int lane, double* s0, double* s1) {
-  double a = 0.0, b = 0.0;
-  for (int p0 = 0; p0 < P; p0 += 64 * 8) {  // P <= 1024: at most 2 rounds of 8 loads in flight
-    double va[8], vb[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int p = p0 + lane + 64 * u;
-      va[u] = (p < P) ? part[2 * p] : 0.0;
-      vb[u] = (p < P) ? part[2 * p + 1] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      a += va[u];
-      b += vb[u];
-    }
-  }
-  *s0 = wave_sum(a);
-  *s1 = wave_sum(b);
-}
-
 // ---------------------------------------------------------------------------
-// gradient phase (masked CSR): g_e = X_ij - M_ij on Omega, with
-// X_ij = alpha [i == j] + sum_l V_il d_l V_jl; per-workgroup partials
-// (sum g^2, sum X_ij^2) -> part[wg * 2].  One wave per row, grid-stride.
+// apply phase: Zout = Yhat Q for the sweep basis Q = Zin W, over all row
+// blocks of this workgroup:
+//   Zout_i = (opscale (Op Zin)_i + sdiag Zin_i) W + V_i diag(ceff) PW,
+//   V_i = (B_i Wb)[:, :r],  PW = V^T Q,
+// with the FP64 Gram partials Zin^T Zout, Zout^T Zout, V^T Zout -> part[wg].
+// GRAD (masked objective, first sweep, where Zin = B): the gradient value
+// g_e = X_ij - M_ij is formed from the same gathered row j, as
+//   X_ij = alpha [i == j] + V_i diag(d) V_j^T = alpha [i == j] + B_j w_i,
+//   w_i = Wb[:, :r] diag(d) V_i^T,
+// stored for the later sweeps and used at once; sum g_e^2 and sum X_ij^2
+// over Omega go to part[wg * PSTRIDE + PLEN], part[wg * PSTRIDE + PLEN + 1].
 // ---------------------------------------------------------------------------
-template <typename T, int KB, int NT>
-__device__ __noinline__ void grad_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, const T* __restrict__ Qw,
-                           T* __restrict__ g, double* part, double* lds) {
-  constexpr int WAVES = NT / 64;
-  T* sd = reinterpret_cast<T*>(lds);      // KMAX
-  double* sred = lds + KMAX;               // 2 * WAVES
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r = cfg.r;
-  if (tid < KMAX) sd[tid] = (T)ctl->d[tid];
-  const T alpha = (T)ctl->alpha;
-  __syncthreads();
-  constexpr int VN = V16<T>::N;
-  constexpr int U = 2;  // nonzeros per lane per iteration, loads issued together
-  double acc = 0.0, accx = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * WAVES + wave; i < cfg.n; i += (int64_t)gridDim.x * WAVES) {
-    // vi_l = V_il d_l; d_l = 0 for l >= r, so whole k-wide rows can be used
-    T vi[KB];
-#pragma unroll
-    for (int l = 0; l < KB; ++l) vi[l] = (l < r) ? Qw[i * KB + l] * sd[l] : (T)0;
-    const int e0 = dat.rp[i], e1 = dat.rp[i + 1];
-    for (int e = e0 + lane; e < e1; e += 64 * U) {
-      int jj[U];
-      T mv[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int eu = e + 64 * u;
-        const bool ok = eu < e1;
-        jj[u] = ok ? dat.col[eu] : (int)i;
-        mv[u] = ok ? dat.val[eu] : (T)0;
-      }
-      T vj[U][KB];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int c = 0; c < KB / VN; ++c) vload<T>(Qw + (int64_t)jj[u] * KB + c * VN, &vj[u][c * VN]);
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int eu = e + 64 * u;
-        T x = (jj[u] == i) ? alpha : (T)0;
-#pragma unroll
-        for (int l = 0; l < KB; ++l) x += vi[l] * vj[u][l];
-        if (eu < e1) {
-          const T gvv = x - mv[u];
-          g[eu] = gvv;
-          acc += (double)gvv * (double)gvv;
-          accx += (double)x * (double)x;
-        }
-      }
-    }
-  }
-  acc = wave_sum(acc);
-  accx = wave_sum(accx);
-  if (lane == 0) {
-    sred[wave] = acc;
-    sred[WAVES + wave] = accx;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double a = 0.0, b = 0.0;
-    for (int w = 0; w < WAVES; ++w) { a += sred[w]; b += sred[WAVES + w]; }
-    part[(size_t)blockIdx.x * 2] = a;
-    part[(size_t)blockIdx.x * 2 + 1] = b;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// apply phase: all row blocks of this workgroup, Gram partials -> part[wg]
-// ---------------------------------------------------------------------------
-template <typename T, int KB, int OPK, int NT>
+template <typename T, int KB, int OPK, int NT, bool GRAD>
 __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, const T* __restrict__ gv,
-                            const T* __restrict__ Qw, const T* __restrict__ Zin, T* __restrict__ Zout,
-                            double* part, double* smem) {
+                            T* __restrict__ gout, const T* __restrict__ B, const T* __restrict__ Zin,
+                            T* __restrict__ Zout, double* part, double* smem) {
   using SH = StepShape<T, KB, OPK, NT>;
   constexpr int ROWS = SH::ROWS, RPW = SH::RPW;
   using SM = ApplySmem<T, KB, ROWS>;
   constexpr int LD = SM::LD;
   constexpr int VN = V16<T>::N;
+  constexpr int WAVES = NT / 64;
+  static_assert(ROWS * KB <= NT, "one staged element per thread");
+  static_assert(WAVES <= SM::WAVES_MAX, "per-wave scratch");
+  static_assert(!GRAD || OPK == OP_CSR, "the fused gradient is the masked (CSR) objective's");
   T* tb = reinterpret_cast<T*>(smem + SM::PLEN);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = cfg.r;
   const int64_t n = cfg.n;
   // per-sweep coefficients
   for (int e = tid; e < KB * KB; e += NT) {
-    tb[SM::T_W + (e / KB) * LD + (e % KB)] = (T)ctl->W[e];
-    tb[SM::T_P + e] = (e / KB < r) ? (T)ctl->Pin[e] : (T)0;
+    const int i = e / KB, j = e % KB;
+    tb[SM::T_W + i * LD + j] = (T)ctl->W[e];
+    tb[SM::T_WB + i * LD + j] = (T)ctl->Wb[e];
+    tb[SM::T_PW + e] = (i < r) ? (T)ctl->PW[e] : (T)0;
   }
   if (tid < KB) tb[SM::T_CE + tid] = (T)ctl->ceff[tid];
   for (int e = tid; e < SM::PLEN; e += NT) smem[e] = 0.0;
   const T opscale = (T)ctl->opscale, sdiag = (T)ctl->sdiag;
+  T alpha = 0, dl = 0;
+  if constexpr (GRAD) {
+    alpha = (T)ctl->alpha;
+    dl = (lane < r) ? (T)ctl->d[lane] : (T)0;
+  }
+  double accg = 0.0, accx = 0.0;  // GRAD: sums of g^2 and X_ij^2 over this lane's nonzeros
   const int64_t nblk = (n + ROWS - 1) / ROWS;
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
     const int64_t row0 = blk * ROWS;
-    __syncthreads();  // previous block's LDS reads are done
-    for (int e = tid; e < ROWS * KB; e += NT) {
-      const int rr = e / KB, cc = e % KB;
-      const int64_t i = row0 + rr;
-      const bool ok = i < n;
-      tb[SM::T_ZIN + e] = ok ? Zin[i * KB + cc] : (T)0;
-      tb[SM::T_V + e] = (ok && cc < r) ? Qw[i * KB + cc] : (T)0;
+    // this block's rows of Zin and B: loads issued now, stored to LDS after
+    // the gathers below (their latency overlaps)
+    T pz = 0, pb = 0;
+    if (tid < ROWS * KB) {
+      const int64_t i = row0 + tid / KB;
+      if (i < n) {
+        pz = Zin[i * KB + tid % KB];
+        pb = B[i * KB + tid % KB];
+      }
     }
+    __syncthreads();  // previous block's LDS reads are done; coefficients are visible
     if constexpr (OPK == OP_CSR) {
       // one row per wave; a row's nonzeros are split over lane groups of LPN
-      // lanes, each lane owning a 16-byte chunk of the gathered Zin row
+      // lanes, each lane owning a 16-byte chunk of the gathered row.  U slots
+      // of NPI nonzeros are in flight per iteration, and the next iteration's
+      // column indices and values are fetched before this one's rows are used.
       constexpr int LPN = KB / VN;
       constexpr int NPI = 64 / LPN;
+      constexpr int U = 8;
+      constexpr int STEP = NPI * U;
       const int sub = lane % LPN, grp = lane / LPN;
       const int64_t i = row0 + wave;
       T acc[VN];
 #pragma unroll
       for (int v = 0; v < VN; ++v) acc[v] = 0;
-      if (i < n) {
-        // U nonzeros per lane group per iteration: all index/value loads,
-        // then all row gathers, are issued before the first use
-        constexpr int U = 4;
+      if (i < n) {  // uniform per wave
         const int e0 = dat.rp[i], e1 = dat.rp[i + 1];
-        for (int e = e0 + grp; e < e1; e += NPI * U) {
+        T bi = 0;
+        if constexpr (GRAD) bi = (lane < KB) ? B[i * KB + lane] : (T)0;
+        const T* wsrc = GRAD ? dat.val : gv;  // M_Omega (GRAD) or the stored gradient
+        int jn[U];
+        T wn[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int eu = e0 + grp + u * NPI;
+          const bool ok = eu < e1;
+          jn[u] = ok ? dat.col[eu] : (int)i;  // in-range row, weight 0
+          wn[u] = ok ? wsrc[eu] : (T)0;
+        }
+        T wd[VN];  // GRAD: this lane's chunk of w_i
+        if constexpr (GRAD) {
+          // w_i = Wb[:, :r] diag(d) (B_i Wb[:, :r])^T in this wave's scratch
+          T* gw = tb + SM::T_GW + wave * 3 * KB;
+          if (lane < KB) gw[lane] = bi;
+          wsync();
+          if (lane < KB) {
+            T v = 0;
+            if (lane < r)
+#pragma unroll 8
+              for (int q = 0; q < KB; ++q) v += gw[q] * tb[SM::T_WB + q * LD + lane];
+            gw[KB + lane] = v * dl;  // V_il d_l, zero for l >= r
+          }
+          wsync();
+          if (lane < KB) {
+            T w = 0;
+            for (int l = 0; l < r; ++l) w += tb[SM::T_WB + lane * LD + l] * gw[KB + l];
+            gw[2 * KB + lane] = w;
+          }
+          wsync();
+#pragma unroll
+          for (int v = 0; v < VN; ++v) wd[v] = gw[2 * KB + sub * VN + v];
+        }
+        for (int base = e0; base < e1; base += STEP) {  // same trip count for all lanes
           int jj[U];
           T ww[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const int eu = e + u * NPI;
-            const bool ok = eu < e1;
-            jj[u] = ok ? dat.col[eu] : (int)i;  // in-range row, weight 0
-            ww[u] = ok ? gv[eu] : (T)0;
+            jj[u] = jn[u];
+            ww[u] = wn[u];
           }
           T z[U][VN];
 #pragma unroll
           for (int u = 0; u < U; ++u) vload<T>(Zin + (int64_t)jj[u] * KB + sub * VN, z[u]);
 #pragma unroll
-          for (int u = 0; u < U; ++u)
+          for (int u = 0; u < U; ++u) {
+            const int eu = base + STEP + grp + u * NPI;
+            const bool ok = eu < e1;
+            jn[u] = ok ? dat.col[eu] : (int)i;
+            wn[u] = ok ? wsrc[eu] : (T)0;
+          }
 #pragma unroll
-            for (int v = 0; v < VN; ++v) acc[v] += ww[u] * z[u][v];
+          for (int u = 0; u < U; ++u) {
+            T w = ww[u];
+            if constexpr (GRAD) {
+              T x = 0;
+#pragma unroll
+              for (int v = 0; v < VN; ++v) x += wd[v] * z[u][v];
+              x = group_sum<LPN>(x);
+              if (jj[u] == i) x += alpha;
+              const int eu = base + grp + u * NPI;
+              const bool ok = eu < e1;
+              const T gval = x - w;
+              w = ok ? gval : (T)0;
+              if (ok && sub == 0) {
+                gout[eu] = gval;
+                accg += (double)gval * (double)gval;
+                accx += (double)x * (double)x;
+              }
+            }
+#pragma unroll
+            for (int v = 0; v < VN; ++v) acc[v] += w * z[u][v];
+          }
         }
       }
 #pragma unroll
@@ -316,210 +358,272 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
           if (lane == 0) tb[SM::T_U + (wave * RPW + q) * KB + c] = v;
         }
     }
-    __syncthreads();
-    // u = opscale*(Op Zin)_i + V_i diag(ceff) Pin + sdiag Zin_i   (Zin basis)
-    for (int e = tid; e < ROWS * KB; e += NT) {
-      const int rr = e / KB, a = e % KB;
-      T u = opscale * tb[SM::T_U + e] + sdiag * tb[SM::T_ZIN + e];
-      for (int l = 0; l < r; ++l) u += tb[SM::T_V + rr * KB + l] * tb[SM::T_CE + l] * tb[SM::T_P + l * KB + a];
-      tb[SM::T_ZO + e] = u;
+    if (tid < ROWS * KB) {
+      tb[SM::T_ZIN + tid] = pz;
+      tb[SM::T_B + tid] = pb;
     }
     __syncthreads();
-    // z = u W (rows beyond n are zero)
+    // V_i = (B_i Wb)[:, :r] and y_i = opscale (Op Zin)_i + sdiag Zin_i
     for (int e = tid; e < ROWS * KB; e += NT) {
-      const int rr = e / KB, b = e % KB;
+      const int rr = e / KB, l = e % KB;
+      T v = 0;
+      if (l < r)
+#pragma unroll 8
+        for (int q = 0; q < KB; ++q) v += tb[SM::T_B + rr * KB + q] * tb[SM::T_WB + q * LD + l];
+      tb[SM::T_V + e] = v;
+      tb[SM::T_ZO + e] = opscale * tb[SM::T_U + e] + sdiag * tb[SM::T_ZIN + e];
+    }
+    __syncthreads();
+    // z_i = y_i W + V_i diag(ceff) PW (rows beyond n are zero)
+    for (int e = tid; e < ROWS * KB; e += NT) {
+      const int rr = e / KB, c = e % KB;
       T z = 0;
 #pragma unroll 8
-      for (int a = 0; a < KB; ++a) z += tb[SM::T_ZO + rr * KB + a] * tb[SM::T_W + a * LD + b];
+      for (int a = 0; a < KB; ++a) z += tb[SM::T_ZO + rr * KB + a] * tb[SM::T_W + a * LD + c];
+      for (int l = 0; l < r; ++l) z += tb[SM::T_V + rr * KB + l] * tb[SM::T_CE + l] * tb[SM::T_PW + l * KB + c];
       const int64_t i = row0 + rr;
-      if (i < n) Zout[i * KB + b] = z; else z = 0;
+      if (i < n) Zout[i * KB + c] = z; else z = 0;
       tb[SM::T_U + e] = z;
     }
     __syncthreads();
     // FP64 Gram partials (products of working-precision values are exact)
     for (int e = tid; e < KB * KB; e += NT) {
-      const int a = e / KB, b = e % KB;
-      double c = 0.0, gg = 0.0, p = 0.0;
+      const int a = e / KB, c = e % KB;
+      double cz = 0.0, gg = 0.0, p = 0.0;
 #pragma unroll 4
       for (int rr = 0; rr < ROWS; ++rr) {
-        const double zb = (double)tb[SM::T_U + rr * KB + b];
-        c += (double)tb[SM::T_ZIN + rr * KB + a] * zb;
+        const double zb = (double)tb[SM::T_U + rr * KB + c];
+        cz += (double)tb[SM::T_ZIN + rr * KB + a] * zb;
         gg += (double)tb[SM::T_U + rr * KB + a] * zb;
         p += (double)tb[SM::T_V + rr * KB + a] * zb;
       }
-      smem[e] += c;
+      smem[e] += cz;
       smem[KB * KB + e] += gg;
       smem[2 * KB * KB + e] += p;
     }
   }
+  // the objective's partials, in a fixed order (waves, then lanes)
+  double* sred = reinterpret_cast<double*>(tb);  // the typed area is free now
   __syncthreads();
-  double* dst = part + (size_t)blockIdx.x * SM::PLEN;
+  if constexpr (GRAD) {
+    accg = wave_sum(accg);
+    accx = wave_sum(accx);
+    if (lane == 0) {
+      sred[wave] = accg;
+      sred[WAVES + wave] = accx;
+    }
+  }
+  __syncthreads();
+  double* dst = part + (size_t)blockIdx.x * SM::PSTRIDE;
   for (int e = tid; e < SM::PLEN; e += NT) dst[e] = smem[e];
+  if (tid == 0) {
+    double sg = 0.0, sx = 0.0;
+    if constexpr (GRAD)
+      for (int w = 0; w < WAVES; ++w) {
+        sg += sred[w];
+        sx += sred[WAVES + w];
+      }
+    dst[SM::PLEN] = sg;
+    dst[SM::PLEN + 1] = sx;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// finalize phase: Qw <- Zsrc Wfin (row-local, in place when Zsrc == Qw) and
-// the Gram partial of the new Qw -> part[wg] (KB x KB)
-// mode 0: end of a step; mode 1: fresh basis (Wfin = I)
+// Gram partial B^T B of a basis block -> part[wg] (KB x KB), for the
+// orthonormalising transform of a freshly uploaded basis.
 // ---------------------------------------------------------------------------
-template <typename T, int KB, int FROWS, int NT>
-__device__ __noinline__ void finalize_phase(const Cfg& cfg, const Ctl* ctl, T* __restrict__ Qw, const T* Zs, int mode,
-                               double* part, double* smem) {
-  constexpr int LD = KB + 1;
-  double* acc = smem;                                   // KB * KB
-  T* sWf = reinterpret_cast<T*>(smem + KB * KB);        // KB x LD
-  T* rin = sWf + KB * LD;                               // FROWS x KB
-  T* rout = rin + FROWS * KB;                           // FROWS x KB
+template <typename T, int KB, int GROWS, int NT>
+__device__ __noinline__ void gram_phase(const Cfg& cfg, const gbl<T>* Bm, gbl<double>* part, lds<double>* smem) {
+  lds<double>* acc = smem;                                   // KB * KB
+  lds<T>* rows = reinterpret_cast<lds<T>*>(smem + KB * KB);  // GROWS x KB
   const int tid = threadIdx.x;
   const int64_t n = cfg.n;
-  for (int e = tid; e < KB * KB; e += NT) {
-    sWf[(e / KB) * LD + (e % KB)] = (mode == 0) ? (T)ctl->Wfin[e] : (T)((e / KB) == (e % KB));
-    acc[e] = 0.0;
-  }
-  const int64_t nblk = (n + FROWS - 1) / FROWS;
+  for (int e = tid; e < KB * KB; e += NT) acc[e] = 0.0;
+  const int64_t nblk = (n + GROWS - 1) / GROWS;
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t row0 = blk * FROWS;
+    const int64_t row0 = blk * GROWS;
     __syncthreads();
-    for (int e = tid; e < FROWS * KB; e += NT) {
+    for (int e = tid; e < GROWS * KB; e += NT) {
       const int64_t i = row0 + e / KB;
-      rin[e] = (i < n) ? Zs[i * KB + e % KB] : (T)0;
-    }
-    __syncthreads();
-    for (int e = tid; e < FROWS * KB; e += NT) {
-      const int rr = e / KB, b = e % KB;
-      T z = 0;
-#pragma unroll 8
-      for (int a = 0; a < KB; ++a) z += rin[rr * KB + a] * sWf[a * LD + b];
-      const int64_t i = row0 + rr;
-      if (i < n) Qw[i * KB + b] = z; else z = 0;
-      rout[e] = z;
+      rows[e] = (i < n) ? Bm[i * KB + e % KB] : (T)0;
     }
     __syncthreads();
     for (int e = tid; e < KB * KB; e += NT) {
-      const int a = e / KB, b = e % KB;
+      const int a = e / KB, c = e % KB;
       double s = 0.0;
 #pragma unroll 4
-      for (int rr = 0; rr < FROWS; ++rr) s += (double)rout[rr * KB + a] * (double)rout[rr * KB + b];
+      for (int rr = 0; rr < GROWS; ++rr) s += (double)rows[rr * KB + a] * (double)rows[rr * KB + c];
       acc[e] += s;
     }
   }
   __syncthreads();
-  double* dst = part + (size_t)blockIdx.x * KB * KB;
+  gbl<double>* dst = part + (size_t)blockIdx.x * KB * KB;
   for (int e = tid; e < KB * KB; e += NT) dst[e] = acc[e];
 }
 
 template <typename T>
-__device__ __forceinline__ T* zbuf(T* Qw, T* Za, T* Zb, int i) {
-  return i == 0 ? Qw : (i == 1 ? Za : Zb);
+__device__ __forceinline__ T* zbuf(T* Z0, T* Z1, T* Z2, int i) {
+  return i == 0 ? Z0 : (i == 1 ? Z1 : Z2);
 }
 
 __device__ __forceinline__ int ldi(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int64_t ldi64(const int64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Orders this workgroup's earlier global writes before its later reads
+// (values one lane of the serial wavefront wrote and another reads).
+__device__ __forceinline__ void wg_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 __device__ __forceinline__ void stamp(const Bufs& b, int slot) {
   if (b.ts && threadIdx.x == 0) b.ts[slot] = wall_clock64();
 }
 
+// per-workgroup stamp of sweep s (1-based), e = 0 start, 1 arrival at its barrier
+__device__ __forceinline__ void stamp_wg(const Bufs& b, int s, int e) {
+  if (b.ts && threadIdx.x == 0 && s <= kTsWgSweeps)
+    b.ts[kTsWg + (2 * (s - 1) + e) * gridDim.x + blockIdx.x] = wall_clock64();
+}
+
 // ---------------------------------------------------------------------------
-// persistent step kernel: `nsteps` iterations of Algorithm 2, or (mode 1) a
-// fresh-basis setup only.  Launched cooperatively (all workgroups resident).
-// Grid barriers per iteration: one after the gradient, one per sweep (its
-// Gram partials are summed on the way through the barrier) and one after the
-// basis update.
+// persistent step kernel: `nsteps` iterations of Algorithm 2.  Launched
+// cooperatively (all workgroups resident).  One grid barrier per sweep; its
+// Gram partials are summed on the way through the barrier, and the small
+// solve of the step's last sweep also ends the step (next basis, iterate,
+// certificate, step scalars).
 // ---------------------------------------------------------------------------
 template <typename T, int KB, int OPK, int NT>
-__global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Data<T> dat, T* __restrict__ Qw,
-                                             T* __restrict__ Za, T* __restrict__ Zb, T* __restrict__ g, Bufs b,
+__global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Data<T> dat, T* __restrict__ Z0,
+                                             T* __restrict__ Z1, T* __restrict__ Z2, T* __restrict__ g, Bufs b,
                                              int nsteps) {
   using SH = StepShape<T, KB, OPK, NT>;
   using SM = ApplySmem<T, KB, SH::ROWS>;
   constexpr int DENSE_STAGE = (OPK == OP_DENSE) ? (64 * (KB + 1) * (int)sizeof(T) + 7) / 8 : 0;
   __shared__ double smem[SM::TOTAL + DENSE_STAGE];
   const int tid = threadIdx.x;
-  const int P = gridDim.x;
 
+  const bool masked = cfg.kind == MASKED_CSR;
   for (int st = 0; st < nsteps; ++st) {
     if (ldi(&ctl->stop) | ldi(&ctl->status)) break;
-    if (blockIdx.x == 0) stamp(b, 0);
-    // ---- gradient at X_t / step scalars
-    if (cfg.kind == MASKED_CSR) grad_phase<T, KB, NT>(cfg, ctl, dat, Qw, g, b.part, smem);
-    if (!grid_sync<NT>(b, 0, [&] {
-          if (tid < 64) {
-            if (cfg.kind == MASKED_CSR) {
-              double s0, s1;
-              sum_pairs(b.part, P, tid, &s0, &s1);
-              if (tid == 0) {
-                ctl->f = 0.5 * s0;
-                ctl->fvalid = 1;
-              }
-              // lambda_max(P(X) - P(M)) <= ||P(X)||_F - lambda_min(P(M)),  P = P_Omega
-              setup_step(cfg, ctl, sqrt(s1) - ctl->op_lmin, tid);
-            } else {
-              prep_scalars(cfg, ctl, tid);
-            }
-          }
-          stamp(b, 1);
-        }))
-      return;
-    // ---- block subspace sweeps with Rayleigh-Ritz
-    const T* gvals = (cfg.kind == MASKED_CSR) ? g : dat.val;
+    if (blockIdx.x == 0) {
+      stamp(b, 0);
+      stamp(b, 1);  // no separate gradient phase: it is part of sweep 1
+    }
+    // the step scalars (shift, coefficients) and the basis (B, Wb) were set
+    // at the end of the previous iteration
+    const int64_t t0 = ldi64(&ctl->t);
+    const int src = ldi(&ctl->src);
+    const int o1 = (src + 1) % 3, o2 = (src + 2) % 3;
+    const T* Bm = zbuf(Z0, Z1, Z2, src);
+    const T* gvals = masked ? g : dat.val;
     for (int s = 1; s <= cfg.max_inner; ++s) {
-      const int in = (s == 1) ? 0 : ((s % 2 == 0) ? 1 : 2);
-      const int out = (s == 1) ? 1 : ((s % 2 == 0) ? 2 : 1);
-      apply_phase<T, KB, OPK, NT>(cfg, ctl, dat, gvals, Qw, zbuf(Qw, Za, Zb, in), zbuf(Qw, Za, Zb, out), b.part,
-                                  smem);
-      if (!grid_sync<NT>(b, SM::PLEN, [&] {
+      const int in = (s == 1) ? src : ((s % 2 == 0) ? o1 : o2);
+      const int out = (s % 2 == 1) ? o1 : o2;
+      const bool grad = masked && s == 1;
+      T* Zin = zbuf(Z0, Z1, Z2, in);
+      T* Zout = zbuf(Z0, Z1, Z2, out);
+      stamp_wg(b, s, 0);
+      if constexpr (OPK == OP_CSR) {
+        if (grad)
+          apply_phase<T, KB, OPK, NT, true>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem);
+        else
+          apply_phase<T, KB, OPK, NT, false>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem);
+      } else {
+        apply_phase<T, KB, OPK, NT, false>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem);
+      }
+      stamp_wg(b, s, 1);
+      if (!grid_sync<NT>(b, SM::PSTRIDE, [&] {
             stamp(b, 2 * s);
-            if (tid < 64) small_sweep<KB>(cfg, ctl, b.sums, smem, s, in, tid);
+            if (tid < 64) {
+              gbl<Ctl>* gc = (gbl<Ctl>*)ctl;
+              if (grad && tid == 0) {  // f(X_t) = 1/2 sum_Omega g^2, ||P_Omega X_t||_F
+                gc->f = 0.5 * b.sums[SM::PLEN];
+                gc->fvalid = 1;
+                gc->pxnorm = sqrt(b.sums[SM::PLEN + 1]);
+                gc->pxvalid = 1;
+              }
+              const bool fin = small_sweep<KB>(cfg, gc, (const gbl<double>*)b.sums, (lds<double>*)smem, s, in, tid,
+                                               (gbl<long long>*)b.ts);
+              if (fin) {  // the step ends: X_{t+1} is set, prepare step t + 1
+                if (tid == 0) {
+                  gc->t = gc->t + 1;
+                  gc->iters_done = gc->iters_done + 1;
+                  gc->fvalid = 0;
+                  gc->done = 0;
+                  gc->sweep = 1;
+                  gc->polish = 0;
+                }
+                wg_fence();  // finish_step's writes of d, alpha, c, by other lanes
+                step_scalars(cfg, gc, tid);
+              }
+            }
             if (tid == 0) ctl->applies_done = ctl->applies_done + 1;
             stamp(b, 2 * s + 1);
           }))
         return;
-      if (ldi(&ctl->done) | ldi(&ctl->status)) break;
+      if ((ldi64(&ctl->t) != t0) | ldi(&ctl->status)) break;
     }
     if (ldi(&ctl->status)) break;
-    // ---- next warm-start basis and iterate
-    const T* Zs = zbuf(Qw, Za, Zb, ldi(&ctl->src));
-    finalize_phase<T, KB, SH::FROWS, NT>(cfg, ctl, Qw, Zs, 0, b.part, smem);
-    if (!grid_sync<NT>(b, KB * KB, [&] {
-          stamp(b, 2 * cfg.max_inner + 2);
-          if (tid < 64) basis_setup<KB>(cfg, ctl, b.sums, smem, tid);
-          if (tid == 0) {
-            ctl->t = ctl->t + 1;
-            ctl->iters_done = ctl->iters_done + 1;
-            ctl->fvalid = 0;
-          }
-          stamp(b, 2 * cfg.max_inner + 3);
-        }))
-      return;
   }
 }
 
-// Orthonormalising transform of a freshly uploaded basis Qw (cooperative
-// launch with the step kernel's grid): Gram of Qw, then the transform that
-// makes Qw W an orthonormal basis for the first sweep of the next step.
+// Orthonormalising transform of a freshly uploaded basis B = block `src`
+// (cooperative launch with the step kernel's grid): Gram of B, then Wb = R^-1
+// (B^T B = R^T R), so that Q = B Wb is orthonormal, and the step scalars.
 template <typename T, int KB, int OPK, int NT>
-__global__ __launch_bounds__(NT) void k_basis(Cfg cfg, Ctl* __restrict__ ctl, T* __restrict__ Qw, Bufs b) {
+__global__ __launch_bounds__(NT) void k_basis(Cfg cfg, Ctl* __restrict__ ctl, T* __restrict__ Z0,
+                                              T* __restrict__ Z1, T* __restrict__ Z2, Bufs b) {
   using SH = StepShape<T, KB, OPK, NT>;
   using SM = ApplySmem<T, KB, SH::ROWS>;
   __shared__ double smem[SM::TOTAL];
   const int tid = threadIdx.x;
-  finalize_phase<T, KB, SH::FROWS, NT>(cfg, ctl, Qw, Qw, 1, b.part, smem);
+  const T* Bm = zbuf(Z0, Z1, Z2, ldi(&ctl->src));
+  gram_phase<T, KB, SH::GROWS, NT>(cfg, (const gbl<T>*)Bm, (gbl<double>*)b.part, (lds<double>*)smem);
   grid_sync<NT>(b, KB * KB, [&] {
-    if (tid < 64) basis_setup<KB>(cfg, ctl, b.sums, smem, tid);
+    if (tid < 64) {
+      basis_setup<KB>(cfg, (gbl<Ctl>*)ctl, (const gbl<double>*)b.sums, (lds<double>*)smem, tid);
+      wg_fence();
+      step_scalars(cfg, (gbl<Ctl>*)ctl, tid);
+    }
   });
+}
+
+// Q = B Wb written into the block after `src` (the next step's first output,
+// so free between steps): the factored iterate's V = Q[:, :r] in explicit
+// form, for the objective kernels.  One thread per element.
+template <typename T, int KB>
+__global__ __launch_bounds__(256) void k_materialize(Cfg cfg, const Ctl* __restrict__ ctl, T* __restrict__ Z0,
+                                                     T* __restrict__ Z1, T* __restrict__ Z2) {
+  const int src = ctl->src;
+  const T* Bm = zbuf(Z0, Z1, Z2, src);
+  T* Q = zbuf(Z0, Z1, Z2, (src + 1) % 3);
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cfg.n * KB; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / KB;
+    const int c = (int)(e % KB);
+    double z = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < KB; ++q) z += (double)Bm[i * KB + q] * ctl->Wb[q * KB + c];
+    Q[e] = (T)z;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // auxiliary kernels (ordinary launches; per-workgroup partials, then k_finish)
 // ---------------------------------------------------------------------------
 // objective at X_t, dense kinds: LINEAR sum C_ij X_ij, DENOISE 1/2 sum (X_ij - M_ij)^2
-// X_ij = alpha [i == j] + sum_l V_il d_l V_jl, accumulated in FP64; one wave per row
+// X_ij = alpha [i == j] + sum_l V_il d_l V_jl, accumulated in FP64; one wave
+// per row; V from k_materialize
 template <typename T, int KB>
 __global__ __launch_bounds__(256) void k_objective_dense(Cfg cfg, const Ctl* __restrict__ ctl,
-                                                         const T* __restrict__ D, const T* __restrict__ Qw,
+                                                         const T* __restrict__ D, const T* __restrict__ Z0,
+                                                         const T* __restrict__ Z1, const T* __restrict__ Z2,
                                                          double* __restrict__ part) {
+  const T* Qw = zbuf(Z0, Z1, Z2, (ctl->src + 1) % 3);  // written by k_materialize
   __shared__ double sd[KMAX];
   __shared__ double sred[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -553,7 +657,9 @@ __global__ __launch_bounds__(256) void k_objective_dense(Cfg cfg, const Ctl* __r
 template <typename T, int KB>
 __global__ __launch_bounds__(256) void k_objective_csr(Cfg cfg, const Ctl* __restrict__ ctl, const int* __restrict__ rp,
                                                        const int* __restrict__ col, const T* __restrict__ val,
-                                                       const T* __restrict__ Qw, double* __restrict__ part) {
+                                                       const T* __restrict__ Z0, const T* __restrict__ Z1,
+                                                       const T* __restrict__ Z2, double* __restrict__ part) {
+  const T* Qw = zbuf(Z0, Z1, Z2, (ctl->src + 1) % 3);  // written by k_materialize
   __shared__ double sd[KMAX];
   __shared__ double sred[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;

@@ -32,7 +32,7 @@ __device__ __forceinline__ double wave_min(double v) {
 
 // C = A^T B (all KB x KB, LDS stride KB + 1)
 template <int KB>
-__device__ __forceinline__ void mm_tn(const double* A, const double* B, double* C, int lane) {
+__device__ __forceinline__ void mm_tn(const lds<double>* A, const lds<double>* B, lds<double>* C, int lane) {
   constexpr int LD = KB + 1;
   for (int e = lane; e < KB * KB; e += 64) {
     const int i = e / KB, j = e % KB;
@@ -45,7 +45,7 @@ __device__ __forceinline__ void mm_tn(const double* A, const double* B, double* 
 
 // C = A B
 template <int KB>
-__device__ __forceinline__ void mm_nn(const double* A, const double* B, double* C, int lane) {
+__device__ __forceinline__ void mm_nn(const lds<double>* A, const lds<double>* B, lds<double>* C, int lane) {
   constexpr int LD = KB + 1;
   for (int e = lane; e < KB * KB; e += 64) {
     const int i = e / KB, j = e % KB;
@@ -56,10 +56,10 @@ __device__ __forceinline__ void mm_nn(const double* A, const double* B, double* 
   }
 }
 
-// dense KB x KB (stride KB, global or LDS) <-> LDS stride KB + 1; the loops
-// have compile-time trip counts so all loads are issued before any is used
+// dense KB x KB (stride KB, global) <-> LDS stride KB + 1; the loops have
+// compile-time trip counts so all loads are issued before any is used
 template <int KB>
-__device__ __forceinline__ void load_mat(const double* src, double* dst, int lane) {
+__device__ __forceinline__ void load_mat(const gbl<double>* src, lds<double>* dst, int lane) {
   constexpr int IT = KB * KB / 64;
   double v[IT];
 #pragma unroll
@@ -72,7 +72,7 @@ __device__ __forceinline__ void load_mat(const double* src, double* dst, int lan
 }
 
 template <int KB>
-__device__ __forceinline__ void store_mat(const double* src, double* dst, int lane) {
+__device__ __forceinline__ void store_mat(const lds<double>* src, gbl<double>* dst, int lane) {
 #pragma unroll
   for (int u = 0; u < KB * KB / 64; ++u) {
     const int e = lane + 64 * u;
@@ -82,7 +82,7 @@ __device__ __forceinline__ void store_mat(const double* src, double* dst, int la
 
 // dst[e] = src[e], e < KB * KB (global to global), all loads in flight
 template <int KB>
-__device__ __forceinline__ void copy_mat(const double* src, double* dst, int lane) {
+__device__ __forceinline__ void copy_mat(const gbl<double>* src, gbl<double>* dst, int lane) {
   constexpr int IT = KB * KB / 64;
   double v[IT];
 #pragma unroll
@@ -102,23 +102,50 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return y * (2.0 - x * y);
 }
 
+// Jacobi rotation zeroing A_pq of the 2 x 2 block [[app, apq], [apq, aqq]]:
+//   t = tan(angle) = 2 apq sign(delta) / (|delta| + sqrt(delta^2 + 4 apq^2)),
+//   delta = aqq - app, c = 1/sqrt(1 + t^2), s = t c
+// (the smaller of the two angles; no division by apq, so no overflow case).
+// Branch-free, so the rotations a lane needs interleave.  Identity when A_pq
+// is negligible.
+__device__ __forceinline__ void jacobi_rot(double app, double aqq, double apq, double& c, double& s) {
+  const bool act = apq * apq > 1e-36 * fabs(app * aqq) && fabs(apq) > 1e-300;
+  const double b = act ? apq : 0.0;
+  const double delta = aqq - app;
+  const double r2 = fmax(delta * delta + 4.0 * b * b, 1e-300);
+  const double r = r2 * rsqrt_nr(r2);
+  const double den = fmax(fabs(delta) + r, 1e-300);
+  const double t = 2.0 * (delta >= 0.0 ? b : -b) * rcp_nr(den);
+  c = rsqrt_nr(1.0 + t * t);
+  s = t * c;
+}
+
+// Circle-method ordering: slot j sits at position j in round 0; slot 0 stays
+// at 0, the others move up by one position per round, wrapping from KB - 1 to
+// 1.  Rotation m pairs the positions of slots m and KB - 1 - m.
+template <int KB>
+__device__ __forceinline__ int jacobi_next(int pos) { return pos == 0 ? 0 : (pos == KB - 1 ? 1 : pos + 1); }
+
 // Cyclic parallel Jacobi (round-robin ordering) for symmetric A in LDS.
 // On return A is (numerically) diagonal and A_in = S diag(A) S^T.  Stops
-// when the off-diagonal mass is below off2_tol of the total (squared norms).
-// Each round applies KB/2 disjoint rotations: lane m < KB/2 computes rotation
-// m (c^2 + s^2 = 1 to rounding, so S stays orthogonal however approximate
-// the angle), then every lane updates whole 2 x 2 blocks J_m^T A_{mm'} J_m'
-// and pairs of S columns, reading the parameters by shuffles.
+// when the off-diagonal mass is below off2_tol of the total (squared norms);
+// returns the number of sweeps taken.  Each round applies KB/2 disjoint
+// rotations J_m.  A lane owns whole 2 x 2 blocks (m1, m2) of A, updated as
+// J_m1^T A_{m1 m2} J_m2, and the S entries of rotation m1 in rows 2 m2 and
+// 2 m2 + 1; it computes the two rotations it needs itself from the pair's
+// diagonal block (the same inputs and operations in every lane, so every lane
+// derives the same rotation), so a round needs no cross-lane exchange.  All
+// loads of a round precede its stores.
 template <int KB>
-__device__ __noinline__ void jacobi(double* A, double* S, double off2_tol, int lane) {
+__device__ __noinline__ int jacobi(lds<double>* A, lds<double>* S, double off2_tol, int lane) {
   constexpr int LD = KB + 1;
   constexpr int NP = KB / 2;
-  static_assert((NP * NP) % 64 == 0 && (KB * NP) % 64 == 0, "block counts must fill the wavefront");
+  static_assert((NP * NP) % 64 == 0, "2 x 2 blocks must fill the wavefront");
   constexpr int BPL = NP * NP / 64;  // 2 x 2 blocks per lane
-  constexpr int SPL = KB * NP / 64;  // S column pairs per lane
   for (int e = lane; e < KB * KB; e += 64) S[(e / KB) * LD + (e % KB)] = (e / KB == e % KB) ? 1.0 : 0.0;
   wsync();
-  for (int sweep = 0; sweep < 30; ++sweep) {
+  int sweep = 0;
+  for (; sweep < 30; ++sweep) {
     double off = 0.0, dia = 0.0;
     for (int e = lane; e < KB * KB; e += 64) {
       const double v = A[(e / KB) * LD + (e % KB)];
@@ -127,61 +154,71 @@ __device__ __noinline__ void jacobi(double* A, double* S, double off2_tol, int l
     off = wave_sum(off);
     dia = wave_sum(dia);
     if (!(off > off2_tol * (off + dia))) break;  // also exits on NaN
+    int a1[BPL], b1[BPL], a2[BPL], b2[BPL];  // positions of the four slots
+#pragma unroll
+    for (int bi = 0; bi < BPL; ++bi) {
+      const int bl = lane + 64 * bi;
+      const int m1 = bl / NP, m2 = bl % NP;
+      a1[bi] = m1;
+      b1[bi] = KB - 1 - m1;
+      a2[bi] = m2;
+      b2[bi] = KB - 1 - m2;
+    }
     for (int round = 0; round < KB - 1; ++round) {
-      int p = 0, q = 1;
-      double c = 1.0, s = 0.0;
-      if (lane < NP) {
-        // circle method: slot 0 fixed, slots 1..KB-1 rotate by `round`
-        const int a = lane, b = KB - 1 - lane;
-        const int pa = (a == 0) ? 0 : 1 + ((a - 1 + round) % (KB - 1));
-        const int pb = 1 + ((b - 1 + round) % (KB - 1));
-        p = min(pa, pb);
-        q = max(pa, pb);
-        const double apq = A[p * LD + q], app = A[p * LD + p], aqq = A[q * LD + q];
-        if (apq * apq > 1e-36 * fabs(app * aqq) && fabs(apq) > 1e-300) {
-          // tangent of the rotation angle: t = sign(tau) / (|tau| + sqrt(1 + tau^2))
-          const double tau = 0.5 * (aqq - app) * rcp_nr(apq);
-          double t;
-          if (fabs(tau) > 1e100) {
-            t = 0.5 * rcp_nr(tau);
-          } else {
-            const double h = 1.0 + tau * tau;
-            t = rcp_nr(fabs(tau) + h * rsqrt_nr(h));
-            t = (tau >= 0.0) ? t : -t;
-          }
-          c = rsqrt_nr(1.0 + t * t);
-          s = t * c;
+      int p1[BPL], q1[BPL], p2[BPL], q2[BPL];
+      double blk[BPL][4], r1[BPL][3], r2[BPL][3], sx[BPL][2], sy[BPL][2];
+#pragma unroll
+      for (int bi = 0; bi < BPL; ++bi) {
+        const int m2 = (lane + 64 * bi) % NP;
+        p1[bi] = min(a1[bi], b1[bi]);
+        q1[bi] = max(a1[bi], b1[bi]);
+        p2[bi] = min(a2[bi], b2[bi]);
+        q2[bi] = max(a2[bi], b2[bi]);
+        a1[bi] = jacobi_next<KB>(a1[bi]);
+        b1[bi] = jacobi_next<KB>(b1[bi]);
+        a2[bi] = jacobi_next<KB>(a2[bi]);
+        b2[bi] = jacobi_next<KB>(b2[bi]);
+        blk[bi][0] = A[p1[bi] * LD + p2[bi]];
+        blk[bi][1] = A[p1[bi] * LD + q2[bi]];
+        blk[bi][2] = A[q1[bi] * LD + p2[bi]];
+        blk[bi][3] = A[q1[bi] * LD + q2[bi]];
+        r1[bi][0] = A[p1[bi] * LD + p1[bi]];
+        r1[bi][1] = A[q1[bi] * LD + q1[bi]];
+        r1[bi][2] = A[p1[bi] * LD + q1[bi]];
+        r2[bi][0] = A[p2[bi] * LD + p2[bi]];
+        r2[bi][1] = A[q2[bi] * LD + q2[bi]];
+        r2[bi][2] = A[p2[bi] * LD + q2[bi]];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int row = 2 * m2 + h;
+          sx[bi][h] = S[row * LD + p1[bi]];
+          sy[bi][h] = S[row * LD + q1[bi]];
         }
       }
 #pragma unroll
       for (int bi = 0; bi < BPL; ++bi) {
-        const int blk = lane + 64 * bi;
-        const int m1 = blk / NP, m2 = blk % NP;
-        const int p1 = __shfl(p, m1, 64), q1 = __shfl(q, m1, 64);
-        const int p2 = __shfl(p, m2, 64), q2 = __shfl(q, m2, 64);
-        const double c1 = __shfl(c, m1, 64), s1 = __shfl(s, m1, 64);
-        const double c2 = __shfl(c, m2, 64), s2 = __shfl(s, m2, 64);
-        const double a = A[p1 * LD + p2], b = A[p1 * LD + q2], cc = A[q1 * LD + p2], d = A[q1 * LD + q2];
+        const int m2 = (lane + 64 * bi) % NP;
+        double c1, s1, c2, s2;
+        jacobi_rot(r1[bi][0], r1[bi][1], r1[bi][2], c1, s1);
+        jacobi_rot(r2[bi][0], r2[bi][1], r2[bi][2], c2, s2);
+        const double a = blk[bi][0], b = blk[bi][1], cc = blk[bi][2], d = blk[bi][3];
         const double ra = c1 * a - s1 * cc, rb = c1 * b - s1 * d;  // rows: J1^T
         const double rc = s1 * a + c1 * cc, rd = s1 * b + c1 * d;
-        A[p1 * LD + p2] = c2 * ra - s2 * rb;                       // columns: J2
-        A[p1 * LD + q2] = s2 * ra + c2 * rb;
-        A[q1 * LD + p2] = c2 * rc - s2 * rd;
-        A[q1 * LD + q2] = s2 * rc + c2 * rd;
-      }
+        A[p1[bi] * LD + p2[bi]] = c2 * ra - s2 * rb;               // columns: J2
+        A[p1[bi] * LD + q2[bi]] = s2 * ra + c2 * rb;
+        A[q1[bi] * LD + p2[bi]] = c2 * rc - s2 * rd;
+        A[q1[bi] * LD + q2[bi]] = s2 * rc + c2 * rd;
 #pragma unroll
-      for (int si = 0; si < SPL; ++si) {
-        const int pr = lane + 64 * si;
-        const int i = pr / NP, m = pr % NP;
-        const int pp = __shfl(p, m, 64), qq = __shfl(q, m, 64);
-        const double cm = __shfl(c, m, 64), sm = __shfl(s, m, 64);
-        const double x = S[i * LD + pp], y = S[i * LD + qq];
-        S[i * LD + pp] = cm * x - sm * y;
-        S[i * LD + qq] = sm * x + cm * y;
+        for (int h = 0; h < 2; ++h) {  // S <- S J1 in rows 2 m2, 2 m2 + 1
+          const int row = 2 * m2 + h;
+          S[row * LD + p1[bi]] = c1 * sx[bi][h] - s1 * sy[bi][h];
+          S[row * LD + q1[bi]] = s1 * sx[bi][h] + c1 * sy[bi][h];
+        }
       }
       wsync();
     }
   }
+  return sweep;
 }
 
 // Value of v in lane l (l uniform across the wavefront), as a scalar.
@@ -198,7 +235,7 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 // compile-time lane index, so the factorisation touches no memory.  Tiny
 // pivots are floored to keep R invertible.
 template <int KB>
-__device__ __noinline__ void chol_inv(const double* A, double* Rinv, int lane) {
+__device__ __noinline__ void chol_inv(const lds<double>* A, lds<double>* Rinv, int lane) {
   constexpr int LD = KB + 1;
   double a[KB];  // column `lane` of A, overwritten by column `lane` of R
 #pragma unroll
@@ -242,7 +279,7 @@ __device__ __noinline__ void chol_inv(const double* A, double* Rinv, int lane) {
 // subspace iteration targets the algebraically largest eigenvalues.  A tight
 // gmax matters: the unwanted spectrum then starts near 0, which is what makes
 // the (r+1)-th pair converge.  One wavefront (all 64 lanes call it).
-__device__ inline void setup_step(const Cfg& cfg, Ctl* ctl, double gmax, int lane) {
+__device__ inline void setup_step(const Cfg& cfg, gbl<Ctl>* ctl, double gmax, int lane) {
   const int r = cfg.r;
   const bool act = lane < r;
   const double cl = act ? ctl->c[lane] : 0.0;
@@ -262,9 +299,6 @@ __device__ inline void setup_step(const Cfg& cfg, Ctl* ctl, double gmax, int lan
     ctl->sigma = sigma;
     ctl->sdiag = den ? sigma - cfg.eta * alpha : sigma;
     ctl->opscale = den ? cfg.eta : -cfg.eta;
-    ctl->info.t = ctl->t;
-    ctl->info.sigma = sigma;
-    ctl->info.f = ctl->fvalid ? ctl->f : __builtin_nan("");
   }
 }
 
@@ -272,7 +306,7 @@ __device__ inline void setup_step(const Cfg& cfg, Ctl* ctl, double gmax, int lan
 // the next factored iterate (alpha', d', c') and the certificate.  theta
 // (LDS) holds the sorted Ritz values of Yhat, rho their residuals.  One
 // wavefront.
-__device__ inline void finish_step(const Cfg& cfg, Ctl* ctl, const double* theta, const double* rho,
+__device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<double>* theta, const lds<double>* rho,
                                    double resid_max, int sweeps, int converged, int lane) {
   const int r = cfg.r;
   const double n = (double)cfg.n;
@@ -308,7 +342,7 @@ __device__ inline void finish_step(const Cfg& cfg, Ctl* ctl, const double* theta
   if (lane == 0) {
     ctl->alpha = alpha_n;
     const double L = log(n - r) - log(eps) + mu_r1 - lse_r1;
-    Info& in = ctl->info;
+    gbl<Info>& in = ctl->info;
     in.t = t;
     in.eps_t = eps;
     in.cert_L = L;
@@ -321,6 +355,7 @@ __device__ inline void finish_step(const Cfg& cfg, Ctl* ctl, const double* theta
     in.mu_r1 = mu_r1;
     in.sigma = sigma;
     in.converged = converged;
+    in.f = ctl->fvalid ? ctl->f : __builtin_nan("");
     if (!all_ok) ctl->status = 4;  // MEG_ERR_NUMERIC
     if (solve_tol > 0.0 && in.cert_bound <= solve_tol) ctl->stop = 1;
   }
@@ -328,40 +363,56 @@ __device__ inline void finish_step(const Cfg& cfg, Ctl* ctl, const double* theta
 
 // One Rayleigh-Ritz / orthonormalisation step.  `sums` (global) holds, stride KB:
 //   C = Zin^T Zout, G = Zout^T Zout, P = V^T Zout (first r rows)
-// where Zout = Yhat Q and Q = Zin W is orthonormal.  One wavefront (lanes
-// 0..63).  `scr` (LDS) needs 5 * KB * (KB + 1) + 8 * KB doubles.
+// where Zout = Yhat Q and Q = Zin W is orthonormal.  Sets the next sweep's
+// W and PW = V^T Q', or ends the step: the Ritz basis Zin (W S) becomes the
+// next warm start (B, Wb) = (Zin, W S).  Returns true when the step ended.
+// One wavefront (lanes 0..63).  `scr` (LDS) needs 5 * KB * (KB + 1) + 8 * KB
+// doubles.
 template <int KB>
-__device__ __noinline__ void small_sweep(const Cfg& cfg, Ctl* ctl, const double* sums, double* scr, int sweep,
-                                         int in_buf, int lane) {
+__device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gbl<double>* sums, lds<double>* scr,
+                                         int sweep, int in_buf, int lane, gbl<long long>* ts) {
   constexpr int LD = KB + 1;
   constexpr int MS = KB * LD;
-  double* A = scr;            // T, then diagonalised
-  double* S = scr + MS;       // Ritz vectors (unsorted)
-  double* B1 = scr + 2 * MS;  // W, then sorted S
-  double* B2 = scr + 3 * MS;  // C, then G S, then Rinv
-  double* B3 = scr + 4 * MS;  // G, then Ghat = S^T G S
-  double* vec = scr + 5 * MS; // 8 * KB
-  double* theta = vec;
-  double* rho = vec + KB;
-  int* perm = reinterpret_cast<int*>(vec + 6 * KB);
+  lds<double>* A = scr;            // T, then diagonalised
+  lds<double>* S = scr + MS;       // Ritz vectors (unsorted)
+  lds<double>* B1 = scr + 2 * MS;  // W, then sorted S
+  lds<double>* B2 = scr + 3 * MS;  // C, then G S, then Rinv
+  lds<double>* B3 = scr + 4 * MS;  // G, then Ghat = S^T G S
+  lds<double>* vec = scr + 5 * MS; // 8 * KB
+  lds<double>* theta = vec;
+  lds<double>* rho = vec + KB;
+  lds<int>* perm = reinterpret_cast<lds<int>*>(vec + 6 * KB);
   const int r = cfg.r;
 
   if (sweep < cfg.rr_from && sweep < cfg.max_inner) {
     // early sweep of a warm-started step: orthonormalise only,
-    // Q' = Zout R^{-1} with Zout^T Zout = R^T R
+    // Q' = Zout R^{-1} with Zout^T Zout = R^T R;  PW' = V^T Zout R^{-1}
     load_mat<KB>(sums + KB * KB, B3, lane);
-    copy_mat<KB>(sums + 2 * KB * KB, ctl->Pin, lane);  // V^T Zout
+    load_mat<KB>(sums + 2 * KB * KB, S, lane);
     wsync();
     chol_inv<KB>(B3, B2, lane);
+    mm_nn<KB>(S, B2, A, lane);
+    wsync();
     store_mat<KB>(B2, ctl->W, lane);
+    store_mat<KB>(A, ctl->PW, lane);
     if (lane == 0) ctl->sweep = sweep + 1;
-    return;
+    return false;
   }
 
   load_mat<KB>(ctl->W, B1, lane);
   load_mat<KB>(sums, B2, lane);
   load_mat<KB>(sums + KB * KB, B3, lane);
-  copy_mat<KB>(sums + 2 * KB * KB, ctl->Pin, lane);  // V^T Zout (next sweep)
+  // P = V^T Zout (for the next sweep's PW) and this sweep's PW = V^T Q, held
+  // in registers: the first is used only if another sweep follows, the
+  // second gives V_t^T V_{t+1} = PW S[:, :r] when the step ends here
+  constexpr int PE = (KB * KB + 63) / 64;
+  double pnew[PE], pold[PE];
+#pragma unroll
+  for (int m = 0; m < PE; ++m) {
+    const int e = lane + 64 * m;
+    pnew[m] = (e < KB * KB) ? sums[2 * KB * KB + e] : 0.0;
+    pold[m] = (e < KB * KB) ? ctl->PW[e] : 0.0;
+  }
   const int polish = ctl->polish;
   wsync();
   mm_tn<KB>(B1, B2, A, lane);  // T = W^T C = Q^T Yhat Q
@@ -375,8 +426,15 @@ __device__ __noinline__ void small_sweep(const Cfg& cfg, Ctl* ctl, const double*
     }
   }
   wsync();
+  // profiled launches: stamps of the first Rayleigh-Ritz sweep's parts
+  const bool prof = ts != nullptr && lane == 0 && sweep == cfg.rr_from;
+  if (prof) ts[kTsRR] = wall_clock64();
   // eigenvector accuracy needed: rounding level of the working precision
-  jacobi<KB>(A, S, cfg.unit_round < 1e-10 ? 1e-30 : 1e-22, lane);
+  const int jsweeps = jacobi<KB>(A, S, cfg.unit_round < 1e-10 ? 1e-30 : 1e-22, lane);
+  if (prof) {
+    ts[kTsRR + 1] = wall_clock64();
+    ts[kTsRR + 4] = jsweeps;
+  }
   // sort eigenvalues descending: rank of each diagonal entry, ties broken by
   // index; NaN ranks as -inf so the ranks always form a permutation (the NaN
   // itself is caught by the finiteness check below)
@@ -428,6 +486,7 @@ __device__ __noinline__ void small_sweep(const Cfg& cfg, Ctl* ctl, const double*
     conv = false;
   }
   wsync();
+  if (prof) ts[kTsRR + 2] = wall_clock64();
   const bool fin = !finite || (conv && sweep >= cfg.min_inner) || sweep >= cfg.max_inner;
   if (!finite) {
     if (lane == 0) {
@@ -435,45 +494,96 @@ __device__ __noinline__ void small_sweep(const Cfg& cfg, Ctl* ctl, const double*
       ctl->stop = 1;
       ctl->done = 1;
     }
-    return;
+    return false;
   }
   if (fin) {
+    const double a_old = ctl->alpha;
+    const double d_old = (lane < r) ? ctl->d[lane] : 0.0;
     finish_step(cfg, ctl, theta, rho, rmax, sweep, conv ? 1 : 0, lane);
-    // Ritz vectors of span(Q): Q S = Zin (W S)
+    // Ritz vectors of span(Q): Q S = Zin (W S), the next warm start; its
+    // first sweep uses W = Wb and PW = V^T Q = [I_r 0]
     load_mat<KB>(ctl->W, B2, lane);
     wsync();
     mm_nn<KB>(B2, B1, A, lane);
     wsync();
-    store_mat<KB>(A, ctl->Wfin, lane);
+    store_mat<KB>(A, ctl->Wb, lane);
+    store_mat<KB>(A, ctl->W, lane);
+    for (int e = lane; e < KB * KB; e += 64) ctl->PW[e] = (e / KB == e % KB && e / KB < r) ? 1.0 : 0.0;
+    // ||X_{t+1} - X_t||_F from the factored forms (V orthonormal):
+    //   n da^2 + 2 da (sum d_t - sum d_{t+1}) + |d_t|^2 + |d_{t+1}|^2
+    //   - 2 sum_ab d_t,a d_{t+1},b C_ab^2,   C = V_t^T V_{t+1} = PW S[:, :r]
+    lds<double>* Pm = S;   // free: the sorted Ritz vectors are in B1
+    lds<double>* dd = B3;  // free after the residuals: d_t, then d_{t+1}
+#pragma unroll
+    for (int m = 0; m < PE; ++m) {
+      const int e = lane + 64 * m;
+      if (e < KB * KB) Pm[(e / KB) * LD + (e % KB)] = pold[m];
+    }
+    const double d_new = (lane < r) ? ctl->d[lane] : 0.0;
+    if (lane < KB) {
+      dd[lane] = d_old;
+      dd[KB + lane] = d_new;
+    }
+    wsync();
+    double cross = 0.0;
+    for (int e = lane; e < r * r; e += 64) {
+      const int a = e / r, b = e % r;
+      double c = 0.0;
+#pragma unroll 4
+      for (int q = 0; q < KB; ++q) c += Pm[a * LD + q] * B1[q * LD + b];
+      cross += dd[a] * dd[KB + b] * c * c;
+    }
+    cross = wave_sum(cross);
+    const double a_new = ctl->alpha;
+    const double sd = wave_sum(d_old - d_new);
+    const double s2 = wave_sum(d_old * d_old + d_new * d_new);
+    const double da = a_old - a_new;
+    const double dx2 = (double)cfg.n * da * da + 2.0 * da * sd + s2 - 2.0 * cross;
     if (lane == 0) {
+      ctl->dxnorm = sqrt(fmax(dx2, 0.0));
       ctl->src = in_buf;
       ctl->done = 1;
     }
-    return;
+    if (prof) ts[kTsRR + 3] = wall_clock64();
+    return true;
   }
-  // Next basis Q' = Zout S R^{-1} with Ghat = R^T R (Cholesky QR, FP64)
+  // Next basis Q' = Zout S R^{-1} with Ghat = R^T R (Cholesky QR, FP64) and
+  // PW' = V^T Q' = P S R^{-1}
   chol_inv<KB>(B3, B2, lane);
   mm_nn<KB>(B1, B2, A, lane);  // W' = S R^{-1}
+#pragma unroll
+  for (int m = 0; m < PE; ++m) {
+    const int e = lane + 64 * m;
+    if (e < KB * KB) S[(e / KB) * LD + (e % KB)] = pnew[m];
+  }
+  wsync();
+  mm_nn<KB>(S, A, B3, lane);
   wsync();
   store_mat<KB>(A, ctl->W, lane);
+  store_mat<KB>(B3, ctl->PW, lane);
   if (lane == 0) {
     ctl->sweep = sweep + 1;
     if (do_polish) ctl->polish = polish + 1;
   }
+  if (prof) ts[kTsRR + 3] = wall_clock64();
+  return false;
 }
 
-// Orthonormalising transform of a fresh basis Qw with Gram H = Qw^T Qw:
-// W = R^{-1} (H = R^T R), Pin = V^T Qw = H[0:r, :].  One wavefront.
+// Orthonormalising transform of a fresh basis B with Gram H = B^T B:
+// Wb = W = R^{-1} (H = R^T R), so Q = B Wb is orthonormal and V = Q[:, :r];
+// PW = V^T Q = [I_r 0].  One wavefront.
 template <int KB>
-__device__ __noinline__ void basis_setup(const Cfg& cfg, Ctl* ctl, const double* gram, double* scr, int lane) {
+__device__ __noinline__ void basis_setup(const Cfg& cfg, gbl<Ctl>* ctl, const gbl<double>* gram, lds<double>* scr,
+                                         int lane) {
   constexpr int MS = KB * (KB + 1);
-  double* A = scr;
-  double* Rinv = scr + MS;
-  copy_mat<KB>(gram, ctl->Pin, lane);
+  lds<double>* A = scr;
+  lds<double>* Rinv = scr + MS;
   load_mat<KB>(gram, A, lane);
   wsync();
   chol_inv<KB>(A, Rinv, lane);
   store_mat<KB>(Rinv, ctl->W, lane);
+  store_mat<KB>(Rinv, ctl->Wb, lane);
+  for (int e = lane; e < KB * KB; e += 64) ctl->PW[e] = (e / KB == e % KB && e / KB < cfg.r) ? 1.0 : 0.0;
   if (lane == 0) {
     ctl->done = 0;
     ctl->sweep = 1;

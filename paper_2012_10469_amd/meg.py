@@ -90,7 +90,10 @@ class MegStepInfo(ctypes.Structure):
 class MegKernelTimes(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("prep_ms", ctypes.c_double), ("apply_ms", ctypes.c_double * 64),
                 ("small_ms", ctypes.c_double * 64), ("finalize_ms", ctypes.c_double),
-                ("sweeps_active", ctypes.c_int32), ("workgroups", ctypes.c_int32)]
+                ("sweeps_active", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("wg_apply_ms", (ctypes.c_double * 3) * 2), ("wg_skew_ms", ctypes.c_double * 2),
+                ("reduce_ms", ctypes.c_double * 2), ("rr_ms", ctypes.c_double * 3), ("rr_tail_ms", ctypes.c_double),
+                ("jacobi_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class MegCounters(ctypes.Structure):
@@ -297,7 +300,10 @@ class LowRankMEG:
         a = out.sweeps_active
         return {"kernel_ms": out.kernel_ms, "prep_ms": out.prep_ms, "apply_ms": list(out.apply_ms[:a]),
                 "small_ms": list(out.small_ms[:a]), "finalize_ms": out.finalize_ms, "sweeps_active": a,
-                "workgroups": out.workgroups}
+                "workgroups": out.workgroups,
+                "wg_apply_ms": [list(out.wg_apply_ms[s]) for s in range(min(a, 2))],
+                "wg_skew_ms": list(out.wg_skew_ms[:min(a, 2)]), "reduce_ms": list(out.reduce_ms[:min(a, 2)]),
+                "rr_ms": list(out.rr_ms) + [out.rr_tail_ms], "jacobi_sweeps": out.jacobi_sweeps}
 
     def counters(self, reset: bool = False) -> dict:
         """Step-kernel launches, iterations, operator applies and their summed

@@ -53,6 +53,8 @@ def test_struct_layout_matches_header(M):
 int main(void) {
   P(meg_params) P(meg_objective) P(meg_start) P(meg_step_info) P(meg_kernel_times) P(meg_counters)
   O(meg_kernel_times, apply_ms) O(meg_kernel_times, finalize_ms) O(meg_kernel_times, workgroups)
+  O(meg_kernel_times, wg_apply_ms) O(meg_kernel_times, wg_skew_ms) O(meg_kernel_times, reduce_ms)
+  O(meg_kernel_times, rr_ms) O(meg_kernel_times, rr_tail_ms) O(meg_kernel_times, jacobi_sweeps)
   O(meg_counters, applies) O(meg_counters, workgroups) O(meg_counters, kernel_ms)
   O(meg_params, eta) O(meg_params, seed) O(meg_params, flags) O(meg_params, inner_tol)
   O(meg_objective, dense) O(meg_objective, ld) O(meg_objective, nnz) O(meg_objective, batch_idx)
