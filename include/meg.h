@@ -77,6 +77,10 @@ typedef enum {
 } meg_grad_kind;
 
 #define MEG_FLAG_STRICT 1u   /* inner non-convergence -> MEG_ERR_NOT_CONVERGED */
+#define MEG_FLAG_NO_LDS_CACHE 2u /* CSR kinds: read the sparse data from global
+                                    memory in every sweep instead of keeping each
+                                    workgroup's rows in LDS (the cache is used
+                                    only when it fits; results are the same)  */
 
 typedef struct {
   int64_t n;          /* dimension, n >= k (see meg_block_size)               */

@@ -50,6 +50,7 @@ struct meg_ctx_s {
   unsigned* bar = nullptr;
   long long* ts = nullptr;
   size_t part_elems = 0;
+  size_t cache_bytes = 0;  // dynamic LDS of the step kernel (CSR cache)
   // step-launch timing: a ring of HIP event pairs around each launch of the
   // step kernel, harvested (elapsed time summed) when the ring is full or the
   // counters are read
@@ -140,9 +141,58 @@ struct Launch {
   }
   static bool csr(meg_ctx c) { return c->cfg.kind == LINEAR_CSR || c->cfg.kind == MASKED_CSR; }
 
-  template <int OPK>
+  template <int OPK, bool CACHE = false>
   static const void* kernel() {
-    return reinterpret_cast<const void*>(&k_step<T, KB, OPK, kStepNT>);
+    return reinterpret_cast<const void*>(&k_step<T, KB, OPK, kStepNT, CACHE>);
+  }
+
+  // Per-workgroup CSR cache in LDS: size it from the row pointers and enable
+  // it when it fits beside the kernel's static LDS and keeps the grid
+  // co-resident.  Sets cfg.cache_blocks / cache_nnz and c->cache_bytes.
+  static void setup_cache(meg_ctx c) {
+    Cfg& cfg = c->cfg;
+    cfg.cache_blocks = 0;
+    cfg.cache_nnz = 0;
+    c->cache_bytes = 0;
+    if (!csr(c) || (c->params.flags & MEG_FLAG_NO_LDS_CACHE)) return;
+    constexpr int ROWS = StepShape<T, KB, OP_CSR, kStepNT>::ROWS;
+    const int64_t n = cfg.n;
+    std::vector<int32_t> rp((size_t)n + 1);
+    if (hipMemcpy(rp.data(), c->obj.row_ptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) {
+      (void)hipGetLastError();
+      return;
+    }
+    const int64_t nblk = (n + ROWS - 1) / ROWS;
+    int64_t max_nnz = 0;
+    for (int w = 0; w < c->P; ++w) {
+      int64_t cnt = 0;
+      for (int64_t blk = w; blk < nblk; blk += c->P)
+        cnt += rp[std::min<int64_t>(n, (blk + 1) * ROWS)] - rp[blk * ROWS];
+      max_nnz = std::max(max_nnz, cnt);
+    }
+    const int blocks = (int)((nblk + c->P - 1) / c->P);
+    const CacheLayout L = cache_layout(blocks, ROWS, (int)std::min<int64_t>(max_nnz, INT32_MAX), (int)sizeof(T),
+                                       cfg.kind == MASKED_CSR);
+    int dev = 0, lds_max = 0, ncu = 1, occ = 0;
+    hipFuncAttributes fa{};
+    const void* k = kernel<OP_CSR, true>();
+    if (max_nnz > INT32_MAX / 4 || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipFuncGetAttributes(&fa, k) != hipSuccess) {
+      (void)hipGetLastError();
+      return;
+    }
+    if ((int64_t)fa.sharedSizeBytes + L.bytes > (int64_t)lds_max) return;
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.bytes) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, kStepNT, (size_t)L.bytes) != hipSuccess ||
+        (int64_t)ncu * occ < c->P) {
+      (void)hipGetLastError();
+      return;
+    }
+    cfg.cache_blocks = blocks;
+    cfg.cache_nnz = (int)max_nnz;
+    c->cache_bytes = (size_t)L.bytes;
   }
 
   // persistent grid: co-resident workgroups, no more than there are row blocks
@@ -171,6 +221,9 @@ struct Launch {
     T* g = (T*)c->g;
     Bufs b{c->part, c->gpart, c->sums, c->bar, stamps ? c->ts : nullptr};
     void* args[] = {&cfg, &ctl, &dat, &Qw, &Za, &Zb, &g, &b, &nsteps};
+    if (cfg.cache_blocks > 0)
+      return hipLaunchCooperativeKernel(kernel<OP_CSR, true>(), dim3(c->P), dim3(kStepNT), args, c->cache_bytes,
+                                        c->stream);
     const void* k = csr(c) ? kernel<OP_CSR>() : kernel<OP_DENSE>();
     return hipLaunchCooperativeKernel(k, dim3(c->P), dim3(kStepNT), args, 0, c->stream);
   }
@@ -245,6 +298,12 @@ template <typename T, int KB> struct DoNorm {
 };
 template <typename T, int KB> struct DoGrid {
   static int run(meg_ctx c) { return Launch<T, KB>::grid(c); }
+};
+template <typename T, int KB> struct DoCache {
+  static int run(meg_ctx c) {
+    Launch<T, KB>::setup_cache(c);
+    return 0;
+  }
 };
 template <typename T, int KB> struct DoPartNeed {
   static size_t run(meg_ctx c, int P) { return Launch<T, KB>::part_need(P); }
@@ -672,6 +731,7 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
       free_ctx(c);
       return MEG_ERR_INVALID_ARG;
     }
+    (void)dispatch<DoCache>(c);  // per-workgroup LDS copy of the CSR data, when it fits
   }
   // data norm (sets ctl->data_norm)
   if (dispatch<DoNorm>(c) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {

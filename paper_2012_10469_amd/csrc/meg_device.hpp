@@ -47,7 +47,30 @@ struct Cfg {
   double inner_tol;   // relative Ritz residual tolerance (top r pairs)
   double unit_round;  // 2^-24 (float state) or 2^-53 (double state)
   double cert_tol;    // absolute residual tolerance of the (r+1)-th pair (0: none)
+  // CSR kinds: each workgroup keeps its rows' slice of the sparse data in
+  // dynamic LDS (0: disabled, the data is read from global memory)
+  int32_t cache_blocks;  // row blocks per workgroup the cache holds
+  int32_t cache_nnz;     // stored entries per workgroup the cache holds
 };
+
+// Byte offsets of the per-workgroup CSR cache in dynamic LDS:
+//   rloc int[cache_blocks * (rows + 1)]  row starts, as positions in the cache
+//   col  int[cache_nnz]                  column indices
+//   val  T[cache_nnz]                    values (M_Omega or C)
+//   g    T[cache_nnz]                    gradient values (masked objective)
+struct CacheLayout {
+  int64_t rloc, col, val, g, bytes;
+};
+__host__ __device__ inline int64_t align16(int64_t x) { return (x + 15) & ~(int64_t)15; }
+__host__ __device__ inline CacheLayout cache_layout(int blocks, int rows, int nnz, int esize, bool with_g) {
+  CacheLayout L;
+  L.rloc = 0;
+  L.col = align16((int64_t)blocks * (rows + 1) * 4);
+  L.val = align16(L.col + (int64_t)nnz * 4);
+  L.g = align16(L.val + (int64_t)nnz * esize);
+  L.bytes = with_g ? align16(L.g + (int64_t)nnz * esize) : L.g;
+  return L;
+}
 
 // Step record copied back to the host (mirrors meg_step_info).
 struct Info {

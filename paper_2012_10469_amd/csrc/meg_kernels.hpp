@@ -88,7 +88,8 @@ constexpr int dense_rpw() { return (KB * (int)sizeof(T) <= 64) ? 4 : ((KB * (int
 template <typename T, int KB, int OPK, int NT>
 struct StepShape {
   static constexpr int WAVES = NT / 64;
-  static constexpr int RPW = (OPK == OP_CSR) ? 1 : dense_rpw<T, KB>();
+  // rows per wave: CSR rows are gathered concurrently (more loads in flight)
+  static constexpr int RPW = (OPK == OP_CSR) ? 2 : dense_rpw<T, KB>();
   static constexpr int ROWS = WAVES * RPW;  // rows per apply block
   static constexpr int GROWS = 2 * WAVES;   // rows per block of the basis Gram
 };
@@ -96,7 +97,6 @@ struct StepShape {
 template <typename T, int KB, int ROWS>
 struct ApplySmem {
   static constexpr int LD = KB + 1;
-  static constexpr int WAVES_MAX = 16;
   // typed section (in units of T)
   static constexpr int T_W = 0;                   // KB x LD   sweep transform W
   static constexpr int T_WB = T_W + KB * LD;      // KB x LD   basis transform Wb
@@ -107,8 +107,8 @@ struct ApplySmem {
   static constexpr int T_V = T_B + ROWS * KB;     // ROWS x KB V rows (zero beyond r)
   static constexpr int T_U = T_V + ROWS * KB;     // ROWS x KB
   static constexpr int T_ZO = T_U + ROWS * KB;    // ROWS x KB
-  static constexpr int T_GW = T_ZO + ROWS * KB;   // WAVES x 3 x KB, fused gradient
-  static constexpr int T_END = T_GW + 3 * WAVES_MAX * KB;
+  static constexpr int T_GW = T_ZO + ROWS * KB;   // ROWS x 3 x KB, fused gradient
+  static constexpr int T_END = T_GW + 3 * ROWS * KB;
   static constexpr int TYPED_DOUBLES = (T_END * (int)sizeof(T) + 7) / 8;
   static constexpr int PLEN = 3 * KB * KB;       // Gram accumulator (FP64)
   static constexpr int PSTRIDE = PLEN + 2;        // per-workgroup partials: Gram, sum g^2, sum X_ij^2
@@ -125,6 +125,47 @@ struct Data {
   const T* val;  // CSR values (M_Omega or C)
   const T* D;    // dense C or M
 };
+
+// This workgroup's slice of the CSR data in LDS (see cache_layout): row
+// starts as cache positions, column indices, values, and the values the
+// later sweeps apply (gradient values for the masked objective, else the
+// values themselves).
+template <typename T>
+struct CsrCache {
+  lds<int>* rloc;
+  lds<int>* col;
+  lds<T>* val;
+  lds<T>* g;
+  lds<T>* gv;
+};
+
+// Fill the cache at the start of a launch: the row blocks blockIdx.x,
+// blockIdx.x + gridDim.x, ... in order, their entries contiguous.  Rows past
+// n are empty.  All threads call it; ends with a workgroup barrier.
+template <typename T, int ROWS, int NT>
+__device__ void load_csr_cache(const Cfg& cfg, const Data<T>& dat, const CsrCache<T>& cc) {
+  const int tid = threadIdx.x;
+  const int64_t n = cfg.n;
+  const int64_t nblk = (n + ROWS - 1) / ROWS;
+  int off = 0;  // cache position of the current block's first entry
+  int jb = 0;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x, ++jb) {
+    const int64_t row0 = blk * ROWS;
+    const int64_t rend = (row0 + ROWS < n) ? row0 + ROWS : n;
+    const int base = dat.rp[row0];
+    const int cnt = dat.rp[rend] - base;
+    for (int t = tid; t <= ROWS; t += NT) {
+      const int64_t row = (row0 + t < rend) ? row0 + t : rend;
+      cc.rloc[jb * (ROWS + 1) + t] = off + (dat.rp[row] - base);
+    }
+    for (int e = tid; e < cnt; e += NT) {
+      cc.col[off + e] = dat.col[base + e];
+      cc.val[off + e] = dat.val[base + e];
+    }
+    off += cnt;
+  }
+  __syncthreads();
+}
 
 // ---------------------------------------------------------------------------
 // step scalars of the NEXT iteration t, set before it starts (one
@@ -169,10 +210,10 @@ __device__ inline void step_scalars(const Cfg& cfg, gbl<Ctl>* ctl, int lane) {
 // stored for the later sweeps and used at once; sum g_e^2 and sum X_ij^2
 // over Omega go to part[wg * PSTRIDE + PLEN], part[wg * PSTRIDE + PLEN + 1].
 // ---------------------------------------------------------------------------
-template <typename T, int KB, int OPK, int NT, bool GRAD>
+template <typename T, int KB, int OPK, int NT, bool GRAD, bool CACHE>
 __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, const T* __restrict__ gv,
                             T* __restrict__ gout, const T* __restrict__ B, const T* __restrict__ Zin,
-                            T* __restrict__ Zout, double* part, double* smem) {
+                            T* __restrict__ Zout, double* part, double* smem, const CsrCache<T>& cc) {
   using SH = StepShape<T, KB, OPK, NT>;
   constexpr int ROWS = SH::ROWS, RPW = SH::RPW;
   using SM = ApplySmem<T, KB, ROWS>;
@@ -180,7 +221,6 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
   constexpr int VN = V16<T>::N;
   constexpr int WAVES = NT / 64;
   static_assert(ROWS * KB <= NT, "one staged element per thread");
-  static_assert(WAVES <= SM::WAVES_MAX, "per-wave scratch");
   static_assert(!GRAD || OPK == OP_CSR, "the fused gradient is the masked (CSR) objective's");
   T* tb = reinterpret_cast<T*>(smem + SM::PLEN);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -203,7 +243,8 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
   }
   double accg = 0.0, accx = 0.0;  // GRAD: sums of g^2 and X_ij^2 over this lane's nonzeros
   const int64_t nblk = (n + ROWS - 1) / ROWS;
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+  int jb = 0;  // this workgroup's block counter (cache position)
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x, ++jb) {
     const int64_t row0 = blk * ROWS;
     // this block's rows of Zin and B: loads issued now, stored to LDS after
     // the gathers below (their latency overlaps)
@@ -217,105 +258,161 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
     }
     __syncthreads();  // previous block's LDS reads are done; coefficients are visible
     if constexpr (OPK == OP_CSR) {
-      // one row per wave; a row's nonzeros are split over lane groups of LPN
-      // lanes, each lane owning a 16-byte chunk of the gathered row.  U slots
-      // of NPI nonzeros are in flight per iteration, and the next iteration's
-      // column indices and values are fetched before this one's rows are used.
+      // RPW rows per wave, gathered together; a row's nonzeros are split over
+      // lane groups of LPN lanes, each lane owning a 16-byte chunk of the
+      // gathered row.  U slots of NPI nonzeros per row are in flight per
+      // iteration, and the next iteration's column indices and values are
+      // fetched before this one's rows are used.
       constexpr int LPN = KB / VN;
       constexpr int NPI = 64 / LPN;
-      constexpr int U = 8;
+      constexpr int U = 8 / RPW;
       constexpr int STEP = NPI * U;
       const int sub = lane % LPN, grp = lane / LPN;
-      const int64_t i = row0 + wave;
-      T acc[VN];
+      const T* wsrc = GRAD ? dat.val : gv;  // M_Omega (GRAD) or the stored gradient
+      // entry e's column index and value: cache positions (CACHE) or global
+      auto ld_col = [&](int e) -> int {
+        if constexpr (CACHE) return cc.col[e]; else return dat.col[e];
+      };
+      auto ld_w = [&](int e) -> T {
+        if constexpr (CACHE) return GRAD ? cc.val[e] : cc.gv[e]; else return wsrc[e];
+      };
+      int64_t iq[RPW];
+      int e0[RPW], e1[RPW];
+      int nit = 0;
 #pragma unroll
-      for (int v = 0; v < VN; ++v) acc[v] = 0;
-      if (i < n) {  // uniform per wave
-        const int e0 = dat.rp[i], e1 = dat.rp[i + 1];
-        T bi = 0;
-        if constexpr (GRAD) bi = (lane < KB) ? B[i * KB + lane] : (T)0;
-        const T* wsrc = GRAD ? dat.val : gv;  // M_Omega (GRAD) or the stored gradient
-        int jn[U];
-        T wn[U];
+      for (int q = 0; q < RPW; ++q) {
+        iq[q] = row0 + wave * RPW + q;
+        e0[q] = 0;
+        e1[q] = 0;
+        if (iq[q] < n) {  // uniform per wave
+          if constexpr (CACHE) {
+            e0[q] = cc.rloc[jb * (ROWS + 1) + wave * RPW + q];
+            e1[q] = cc.rloc[jb * (ROWS + 1) + wave * RPW + q + 1];
+          } else {
+            e0[q] = dat.rp[iq[q]];
+            e1[q] = dat.rp[iq[q] + 1];
+          }
+        }
+        nit = max(nit, (e1[q] - e0[q] + STEP - 1) / STEP);
+      }
+      T bi[RPW];
+      if constexpr (GRAD) {
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) bi[q] = (lane < KB && iq[q] < n) ? B[iq[q] * KB + lane] : (T)0;
+      }
+      int jn[RPW][U];
+      T wn[RPW][U];
+#pragma unroll
+      for (int q = 0; q < RPW; ++q)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int eu = e0 + grp + u * NPI;
-          const bool ok = eu < e1;
-          jn[u] = ok ? dat.col[eu] : (int)i;  // in-range row, weight 0
-          wn[u] = ok ? wsrc[eu] : (T)0;
+          const int eu = e0[q] + grp + u * NPI;
+          const bool ok = eu < e1[q];
+          jn[q][u] = ok ? ld_col(eu) : 0;  // in-range row, weight 0
+          wn[q][u] = ok ? ld_w(eu) : (T)0;
         }
-        T wd[VN];  // GRAD: this lane's chunk of w_i
-        if constexpr (GRAD) {
-          // w_i = Wb[:, :r] diag(d) (B_i Wb[:, :r])^T in this wave's scratch
-          T* gw = tb + SM::T_GW + wave * 3 * KB;
-          if (lane < KB) gw[lane] = bi;
-          wsync();
+      T wd[RPW][VN];  // GRAD: this lane's chunk of w_i
+      if constexpr (GRAD) {
+        // w_i = Wb[:, :r] diag(d) (B_i Wb[:, :r])^T in this wave's scratch
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+          T* gw = tb + SM::T_GW + (wave * RPW + q) * 3 * KB;
+          if (lane < KB) gw[lane] = bi[q];
+        }
+        wsync();
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+          T* gw = tb + SM::T_GW + (wave * RPW + q) * 3 * KB;
           if (lane < KB) {
             T v = 0;
             if (lane < r)
 #pragma unroll 8
-              for (int q = 0; q < KB; ++q) v += gw[q] * tb[SM::T_WB + q * LD + lane];
+              for (int c = 0; c < KB; ++c) v += gw[c] * tb[SM::T_WB + c * LD + lane];
             gw[KB + lane] = v * dl;  // V_il d_l, zero for l >= r
           }
-          wsync();
+        }
+        wsync();
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+          T* gw = tb + SM::T_GW + (wave * RPW + q) * 3 * KB;
           if (lane < KB) {
             T w = 0;
             for (int l = 0; l < r; ++l) w += tb[SM::T_WB + lane * LD + l] * gw[KB + l];
             gw[2 * KB + lane] = w;
           }
-          wsync();
-#pragma unroll
-          for (int v = 0; v < VN; ++v) wd[v] = gw[2 * KB + sub * VN + v];
         }
-        for (int base = e0; base < e1; base += STEP) {  // same trip count for all lanes
-          int jj[U];
-          T ww[U];
+        wsync();
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+          const T* gw = tb + SM::T_GW + (wave * RPW + q) * 3 * KB;
+#pragma unroll
+          for (int v = 0; v < VN; ++v) wd[q][v] = gw[2 * KB + sub * VN + v];
+        }
+      }
+      T acc[RPW][VN];
+#pragma unroll
+      for (int q = 0; q < RPW; ++q)
+#pragma unroll
+        for (int v = 0; v < VN; ++v) acc[q][v] = 0;
+      for (int it = 0; it < nit; ++it) {  // same trip count for all lanes of the wave
+        int jj[RPW][U];
+        T ww[RPW][U];
+#pragma unroll
+        for (int q = 0; q < RPW; ++q)
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            jj[u] = jn[u];
-            ww[u] = wn[u];
+            jj[q][u] = jn[q][u];
+            ww[q][u] = wn[q][u];
           }
-          T z[U][VN];
+        T z[RPW][U][VN];
 #pragma unroll
-          for (int u = 0; u < U; ++u) vload<T>(Zin + (int64_t)jj[u] * KB + sub * VN, z[u]);
+        for (int q = 0; q < RPW; ++q)
+#pragma unroll
+          for (int u = 0; u < U; ++u) vload<T>(Zin + (int64_t)jj[q][u] * KB + sub * VN, z[q][u]);
+#pragma unroll
+        for (int q = 0; q < RPW; ++q)
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const int eu = base + STEP + grp + u * NPI;
-            const bool ok = eu < e1;
-            jn[u] = ok ? dat.col[eu] : (int)i;
-            wn[u] = ok ? wsrc[eu] : (T)0;
+            const int eu = e0[q] + (it + 1) * STEP + grp + u * NPI;
+            const bool ok = eu < e1[q];
+            jn[q][u] = ok ? ld_col(eu) : 0;
+            wn[q][u] = ok ? ld_w(eu) : (T)0;
           }
 #pragma unroll
+        for (int q = 0; q < RPW; ++q)
+#pragma unroll
           for (int u = 0; u < U; ++u) {
-            T w = ww[u];
+            T w = ww[q][u];
             if constexpr (GRAD) {
               T x = 0;
 #pragma unroll
-              for (int v = 0; v < VN; ++v) x += wd[v] * z[u][v];
+              for (int v = 0; v < VN; ++v) x += wd[q][v] * z[q][u][v];
               x = group_sum<LPN>(x);
-              if (jj[u] == i) x += alpha;
-              const int eu = base + grp + u * NPI;
-              const bool ok = eu < e1;
+              if (jj[q][u] == iq[q]) x += alpha;
+              const int eu = e0[q] + it * STEP + grp + u * NPI;
+              const bool ok = eu < e1[q];
               const T gval = x - w;
               w = ok ? gval : (T)0;
               if (ok && sub == 0) {
-                gout[eu] = gval;
+                if constexpr (CACHE) cc.g[eu] = gval; else gout[eu] = gval;
                 accg += (double)gval * (double)gval;
                 accx += (double)x * (double)x;
               }
             }
 #pragma unroll
-            for (int v = 0; v < VN; ++v) acc[v] += w * z[u][v];
+            for (int v = 0; v < VN; ++v) acc[q][v] += w * z[q][u][v];
           }
-        }
       }
 #pragma unroll
-      for (int o = LPN; o < 64; o <<= 1)
+      for (int q = 0; q < RPW; ++q) {
 #pragma unroll
-        for (int v = 0; v < VN; ++v) acc[v] += __shfl_xor(acc[v], o, 64);
-      if (grp == 0) {
+        for (int o = LPN; o < 64; o <<= 1)
 #pragma unroll
-        for (int v = 0; v < VN; ++v) tb[SM::T_U + wave * KB + sub * VN + v] = acc[v];
+          for (int v = 0; v < VN; ++v) acc[q][v] += __shfl_xor(acc[q][v], o, 64);
+        if (grp == 0) {
+#pragma unroll
+          for (int v = 0; v < VN; ++v) tb[SM::T_U + (wave * RPW + q) * KB + sub * VN + v] = acc[q][v];
+        }
       }
     } else {
       // dense: each wave owns RPW rows; column chunks of 64 with the matching
@@ -497,17 +594,29 @@ __device__ __forceinline__ void stamp_wg(const Bufs& b, int s, int e) {
 // solve of the step's last sweep also ends the step (next basis, iterate,
 // certificate, step scalars).
 // ---------------------------------------------------------------------------
-template <typename T, int KB, int OPK, int NT>
+template <typename T, int KB, int OPK, int NT, bool CACHE>
 __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Data<T> dat, T* __restrict__ Z0,
                                              T* __restrict__ Z1, T* __restrict__ Z2, T* __restrict__ g, Bufs b,
                                              int nsteps) {
   using SH = StepShape<T, KB, OPK, NT>;
   using SM = ApplySmem<T, KB, SH::ROWS>;
+  static_assert(!CACHE || OPK == OP_CSR, "the LDS cache holds CSR data");
   constexpr int DENSE_STAGE = (OPK == OP_DENSE) ? (64 * (KB + 1) * (int)sizeof(T) + 7) / 8 : 0;
   __shared__ double smem[SM::TOTAL + DENSE_STAGE];
+  extern __shared__ __attribute__((aligned(16))) char dyn[];  // CSR cache (CACHE)
   const int tid = threadIdx.x;
 
   const bool masked = cfg.kind == MASKED_CSR;
+  CsrCache<T> cc{};
+  if constexpr (CACHE) {
+    const CacheLayout L = cache_layout(cfg.cache_blocks, SH::ROWS, cfg.cache_nnz, (int)sizeof(T), masked);
+    cc.rloc = (lds<int>*)(dyn + L.rloc);
+    cc.col = (lds<int>*)(dyn + L.col);
+    cc.val = (lds<T>*)(dyn + L.val);
+    cc.g = (lds<T>*)(dyn + L.g);
+    cc.gv = masked ? cc.g : cc.val;
+    load_csr_cache<T, SH::ROWS, NT>(cfg, dat, cc);
+  }
   for (int st = 0; st < nsteps; ++st) {
     if (ldi(&ctl->stop) | ldi(&ctl->status)) break;
     if (blockIdx.x == 0) {
@@ -530,11 +639,11 @@ __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Dat
       stamp_wg(b, s, 0);
       if constexpr (OPK == OP_CSR) {
         if (grad)
-          apply_phase<T, KB, OPK, NT, true>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem);
+          apply_phase<T, KB, OPK, NT, true, CACHE>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc);
         else
-          apply_phase<T, KB, OPK, NT, false>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem);
+          apply_phase<T, KB, OPK, NT, false, CACHE>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc);
       } else {
-        apply_phase<T, KB, OPK, NT, false>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem);
+        apply_phase<T, KB, OPK, NT, false, false>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc);
       }
       stamp_wg(b, s, 1);
       if (!grid_sync<NT>(b, SM::PSTRIDE, [&] {

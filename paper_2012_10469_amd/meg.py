@@ -41,6 +41,7 @@ MEG_GRAD_MASKED_CSR = 3
 MEG_GRAD_QUADMEAS = 4
 
 MEG_FLAG_STRICT = 1
+MEG_FLAG_NO_LDS_CACHE = 2
 
 EXPORTED = [
     "meg_block_size", "meg_init", "meg_step", "meg_solve", "meg_certificate", "meg_objective_value",

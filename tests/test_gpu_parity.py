@@ -204,6 +204,25 @@ def test_resume_and_batched_launch_bitwise(meg):
     assert np.array_equal(Va2, Vc) and np.array_equal(da2, dc) and aa2 == ac
 
 
+@pytest.mark.parametrize("prec,n,r,p_obs", [(1, 700, 6, 0.1), (0, 300, 4, 0.3)])
+def test_csr_lds_cache_is_bitwise_neutral(meg, prec, n, r, p_obs):
+    """The per-workgroup LDS copy of the CSR data changes where the data is
+    read from, not the arithmetic: iterates and certificates are bitwise equal
+    with and without it, over several launches of several iterations."""
+    print_case(test="lds_cache", prec=prec, n=n, r=r)
+    p = W.matrix_completion(n, seed=21, rank=3, p=p_obs, r=r, dtype=np_dtype(prec))
+    with make_csr(p, meg.MEG_GRAD_MASKED_CSR, r, prec, eta=1.0) as a, \
+            make_csr(p, meg.MEG_GRAD_MASKED_CSR, r, prec, eta=1.0, flags=meg.MEG_FLAG_NO_LDS_CACHE) as b:
+        for _ in range(3):
+            la, lb = a.solve(5), b.solve(5)
+            assert la["cert_L"] == lb["cert_L"] and la["inner_iters"] == lb["inner_iters"]
+        fa, fb = a.objective(), b.objective()
+        Va, da, aa, ta = a.get_iterate()
+        Vb, db, ab, tb = b.get_iterate()
+    assert ta == tb == 16
+    assert np.array_equal(Va, Vb) and np.array_equal(da, db) and aa == ab and fa == fb
+
+
 def test_solve_stops_on_certificate(meg):
     n = 200
     print_case(test="solve", n=n)
