@@ -155,6 +155,65 @@ __device__ __forceinline__ double wave_sum(double v) {
 // instead of a hang.
 constexpr unsigned kSpinLimit = 1u << 22;
 
+// Partial-sum elements per thread whose loads the barrier's reductions issue
+// together (a per-workgroup record of up to kRedU * NT doubles is reduced in
+// one round of loads).
+constexpr int kRedU = 2;
+
+// The two reduction levels of grid_sync (below), kept out of line so their
+// loads in flight do not add to the register pressure of the caller.
+// Group level: gpart[g] = sum over the group's workgroups w of part[w], in
+// workgroup order; kRedU elements per thread have their loads issued together.
+template <int NT>
+__device__ __noinline__ void reduce_group(const gbl<double>* part, gbl<double>* gpart, int plen, unsigned g,
+                                          unsigned g0, unsigned gsize) {
+  for (int e0 = threadIdx.x; e0 < plen; e0 += NT * kRedU) {
+    double v[kRedU][kBarGroupSize];
+#pragma unroll
+    for (int u = 0; u < kRedU; ++u)
+#pragma unroll
+      for (int w = 0; w < kBarGroupSize; ++w) {
+        const int e = e0 + u * NT;
+        v[u][w] = (w < (int)gsize && e < plen) ? part[(size_t)(g0 + w) * plen + e] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < kRedU; ++u) {
+      const int e = e0 + u * NT;
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < kBarGroupSize; ++w) s += v[u][w];
+      if (e < plen) gpart[(size_t)g * plen + e] = s;
+    }
+  }
+}
+
+// Top level: sums = sum over the ng groups of gpart, in group order.
+template <int NT>
+__device__ __noinline__ void reduce_top(const gbl<double>* gpart, gbl<double>* sums, int plen, unsigned ng) {
+  for (int e0 = threadIdx.x; e0 < plen; e0 += NT * kRedU) {
+    double s[kRedU];
+#pragma unroll
+    for (int u = 0; u < kRedU; ++u) s[u] = 0.0;
+    for (unsigned q0 = 0; q0 < ng; q0 += 16) {
+      double v[kRedU][16];
+#pragma unroll
+      for (int u = 0; u < kRedU; ++u)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int e = e0 + u * NT;
+          v[u][q] = (q0 + q < ng && e < plen) ? gpart[(size_t)(q0 + q) * plen + e] : 0.0;
+        }
+#pragma unroll
+      for (int u = 0; u < kRedU; ++u)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) s[u] += v[u][q];
+    }
+#pragma unroll
+    for (int u = 0; u < kRedU; ++u)
+      if (e0 + u * NT < plen) sums[e0 + u * NT] = s[u];
+  }
+}
+
 // Grid-wide barrier for a cooperatively launched grid (gridDim.x <= 1024).
 // Arrivals are counted in two levels (groups of kBarGroupSize workgroups,
 // then the groups) so that no counter sees more than ~32 contending atomics.
@@ -200,17 +259,7 @@ __device__ __forceinline__ bool grid_sync(const Bufs& b, int plen, F&& serial) {
   if (!s_ok) return false;
   if (s_role >= 1) {
     if (plen > 0) {
-      // loads of the group's partials are unrolled so they are all in flight
-      for (int e = tid; e < plen; e += NT) {
-        double v[kBarGroupSize];
-#pragma unroll
-        for (int w = 0; w < kBarGroupSize; ++w)
-          v[w] = (w < (int)gsize) ? b.part[(size_t)(g0 + w) * plen + e] : 0.0;
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kBarGroupSize; ++w) s += v[w];
-        b.gpart[(size_t)g * plen + e] = s;
-      }
+      reduce_group<NT>((const gbl<double>*)b.part, (gbl<double>*)b.gpart, plen, g, g0, gsize);
       __syncthreads();
     }
     if (tid == 0) {
@@ -224,17 +273,7 @@ __device__ __forceinline__ bool grid_sync(const Bufs& b, int plen, F&& serial) {
   }
   if (s_role == 2) {
     if (plen > 0) {
-      for (int e = tid; e < plen; e += NT) {
-        double s = 0.0;
-        for (unsigned q0 = 0; q0 < ng; q0 += 16) {
-          double v[16];
-#pragma unroll
-          for (int q = 0; q < 16; ++q) v[q] = (q0 + q < ng) ? b.gpart[(size_t)(q0 + q) * plen + e] : 0.0;
-#pragma unroll
-          for (int q = 0; q < 16; ++q) s += v[q];
-        }
-        b.sums[e] = s;
-      }
+      reduce_top<NT>((const gbl<double>*)b.gpart, (gbl<double>*)b.sums, plen, ng);
       __syncthreads();
     }
     serial();
