@@ -136,10 +136,32 @@ meg_status hip_fail(meg_ctx c) {
 // ---------------------------------------------------------------------------
 template <typename T, int KB>
 struct Launch {
+  static bool x3(meg_ctx c) { return c->cfg.prec == MEG_PREC_F32_BF16X3; }
   static Data<T> data(meg_ctx c) {
-    return Data<T>{c->obj.row_ptr, c->obj.col, (const T*)c->obj.val, (const T*)c->obj.dense};
+    if (x3(c))
+      return Data<T>{c->obj.row_ptr, c->obj.col, (const T*)c->obj.val, nullptr, (const uint16_t*)c->obj.dense,
+                     (const uint16_t*)c->obj.dense_lo};
+    return Data<T>{c->obj.row_ptr, c->obj.col, (const T*)c->obj.val, (const T*)c->obj.dense, nullptr, nullptr};
+  }
+  static DenseSrc<T> dense_src(meg_ctx c) {
+    if (x3(c)) return DenseSrc<T>{nullptr, (const uint16_t*)c->obj.dense, (const uint16_t*)c->obj.dense_lo};
+    return DenseSrc<T>{(const T*)c->obj.dense, nullptr, nullptr};
   }
   static bool csr(meg_ctx c) { return c->cfg.kind == LINEAR_CSR || c->cfg.kind == MASKED_CSR; }
+
+  // step kernel of the context's operator family (the matrix-core form
+  // exists for float state only, which validation guarantees)
+  static const void* step_kernel(meg_ctx c) {
+    if (csr(c)) return c->cfg.cache_blocks > 0 ? kernel<OP_CSR, true>() : kernel<OP_CSR>();
+    if constexpr (sizeof(T) == 4)
+      if (x3(c)) return kernel<OP_DENSE_X3>();
+    return kernel<OP_DENSE>();
+  }
+  static int rows_per_block(meg_ctx c) {
+    if (csr(c)) return StepShape<T, KB, OP_CSR, kStepNT>::ROWS;
+    if (x3(c)) return StepShape<T, KB, OP_DENSE_X3, kStepNT>::ROWS;
+    return StepShape<T, KB, OP_DENSE, kStepNT>::ROWS;
+  }
 
   template <int OPK, bool CACHE = false>
   static const void* kernel() {
@@ -200,10 +222,9 @@ struct Launch {
     int dev = 0, ncu = 1, occ = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    const void* k = csr(c) ? kernel<OP_CSR>() : kernel<OP_DENSE>();
+    const void* k = step_kernel(c);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, kStepNT, 0) != hipSuccess || occ < 1) return 0;
-    const int rows = csr(c) ? StepShape<T, KB, OP_CSR, kStepNT>::ROWS : StepShape<T, KB, OP_DENSE, kStepNT>::ROWS;
-    const int nblk = ceil_div(c->cfg.n, rows);
+    const int nblk = ceil_div(c->cfg.n, rows_per_block(c));
     return std::max(1, std::min(std::min(ncu * std::min(occ, kMaxWgPerCu), nblk), kMaxGrid));
   }
 
@@ -221,11 +242,8 @@ struct Launch {
     T* g = (T*)c->g;
     Bufs b{c->part, c->gpart, c->sums, c->bar, stamps ? c->ts : nullptr};
     void* args[] = {&cfg, &ctl, &dat, &Qw, &Za, &Zb, &g, &b, &nsteps};
-    if (cfg.cache_blocks > 0)
-      return hipLaunchCooperativeKernel(kernel<OP_CSR, true>(), dim3(c->P), dim3(kStepNT), args, c->cache_bytes,
-                                        c->stream);
-    const void* k = csr(c) ? kernel<OP_CSR>() : kernel<OP_DENSE>();
-    return hipLaunchCooperativeKernel(k, dim3(c->P), dim3(kStepNT), args, 0, c->stream);
+    return hipLaunchCooperativeKernel(step_kernel(c), dim3(c->P), dim3(kStepNT), args,
+                                      cfg.cache_blocks > 0 ? c->cache_bytes : 0, c->stream);
   }
 
   // same grid as the step kernel (the barrier and partial buffers are sized for it)
@@ -254,8 +272,8 @@ struct Launch {
                          c->obj.col, (const T*)c->obj.val, (const T*)c->Qw, (const T*)c->Za, (const T*)c->Zb,
                          c->part);
     else
-      hipLaunchKernelGGL((k_objective_dense<T, KB>), dim3(nwg), dim3(256), 0, c->stream, cfg, c->ctl,
-                         (const T*)c->obj.dense, (const T*)c->Qw, (const T*)c->Za, (const T*)c->Zb, c->part);
+      hipLaunchKernelGGL((k_objective_dense<T, KB>), dim3(nwg), dim3(256), 0, c->stream, cfg, c->ctl, dense_src(c),
+                         (const T*)c->Qw, (const T*)c->Za, (const T*)c->Zb, c->part);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, c->stream, c->ctl, c->part, nwg, 0);
     return hipGetLastError();
   }
@@ -263,11 +281,12 @@ struct Launch {
   static hipError_t data_norm(meg_ctx c) {
     const Cfg& cfg = c->cfg;
     int64_t rows, cols, ld;
-    const T* x;
+    DenseSrc<T> x;
     if (!csr(c)) {
-      rows = cfg.n; cols = cfg.n; ld = cfg.ld; x = (const T*)c->obj.dense;
+      rows = cfg.n; cols = cfg.n; ld = cfg.ld; x = dense_src(c);
     } else {
-      rows = cfg.nnz > 0 ? 1 : 0; cols = std::max<int64_t>(cfg.nnz, 1); ld = 0; x = (const T*)c->obj.val;
+      rows = cfg.nnz > 0 ? 1 : 0; cols = std::max<int64_t>(cfg.nnz, 1); ld = 0;
+      x = DenseSrc<T>{(const T*)c->obj.val, nullptr, nullptr};
     }
     const int64_t total = rows * cols;
     const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (total + 255) / 256));
@@ -386,7 +405,7 @@ meg_status lanczos_extremes(meg_ctx c, double* lmin, double* lmax) {
       st = hip_fail(c);
       break;
     }
-    hipLaunchKernelGGL((k_matvec<T>), dim3(ceil_div(n, 4)), dim3(256), 0, c->stream, cfg, (const T*)c->obj.dense,
+    hipLaunchKernelGGL((k_matvec<T>), dim3(ceil_div(n, 4)), dim3(256), 0, c->stream, cfg, Launch<T, 16>::dense_src(c),
                        c->obj.row_ptr, c->obj.col, (const T*)c->obj.val, (const T*)dx, dy);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
         hipMemcpy(y.data(), dy, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
@@ -571,7 +590,11 @@ meg_status validate(const meg_params* p, const meg_objective* o, const meg_start
     case MEG_GRAD_LINEAR_DENSE:
     case MEG_GRAD_DENOISE_DENSE:
       if (!o->dense || o->ld < p->n) return MEG_ERR_INVALID_ARG;
-      if (p->prec == MEG_PREC_F32_BF16X3) return MEG_ERR_UNSUPPORTED;
+      if (p->prec == MEG_PREC_F32_BF16X3) {
+        // two bf16 planes; rows start on 16-byte boundaries (8-element loads)
+        if (!o->dense_lo || o->ld % 8 != 0 || ((uintptr_t)o->dense % 16) != 0 || ((uintptr_t)o->dense_lo % 16) != 0)
+          return MEG_ERR_INVALID_ARG;
+      }
       break;
     case MEG_GRAD_LINEAR_CSR:
     case MEG_GRAD_MASKED_CSR:

@@ -24,7 +24,9 @@
 
 namespace meg {
 
-enum OpKind : int { OP_CSR = 0, OP_DENSE = 1 };
+// Operator families of the apply: sparse CSR, dense in the state's type, and
+// dense given as two bf16 planes hi + lo and applied on the matrix cores.
+enum OpKind : int { OP_CSR = 0, OP_DENSE = 1, OP_DENSE_X3 = 2 };
 
 // 16-byte vector of T (float4 / double2) used for row-chunk loads.
 template <typename T> struct V16;
@@ -88,13 +90,15 @@ constexpr int dense_rpw() { return (KB * (int)sizeof(T) <= 64) ? 4 : ((KB * (int
 template <typename T, int KB, int OPK, int NT>
 struct StepShape {
   static constexpr int WAVES = NT / 64;
-  // rows per wave: CSR rows are gathered concurrently (more loads in flight)
-  static constexpr int RPW = (OPK == OP_CSR) ? 2 : dense_rpw<T, KB>();
+  // rows per wave: CSR rows are gathered concurrently (more loads in flight);
+  // the matrix-core form works on 64-row blocks (two 32-row MFMA tiles)
+  static constexpr int RPW = (OPK == OP_CSR) ? 2 : (OPK == OP_DENSE_X3 ? 64 / WAVES : dense_rpw<T, KB>());
   static constexpr int ROWS = WAVES * RPW;  // rows per apply block
   static constexpr int GROWS = 2 * WAVES;   // rows per block of the basis Gram
+  static constexpr int GWROWS = (OPK == OP_CSR) ? ROWS : 0;  // fused-gradient scratch rows
 };
 
-template <typename T, int KB, int ROWS>
+template <typename T, int KB, int ROWS, int GWROWS = ROWS>
 struct ApplySmem {
   static constexpr int LD = KB + 1;
   // typed section (in units of T)
@@ -107,8 +111,8 @@ struct ApplySmem {
   static constexpr int T_V = T_B + ROWS * KB;     // ROWS x KB V rows (zero beyond r)
   static constexpr int T_U = T_V + ROWS * KB;     // ROWS x KB
   static constexpr int T_ZO = T_U + ROWS * KB;    // ROWS x KB
-  static constexpr int T_GW = T_ZO + ROWS * KB;   // ROWS x 3 x KB, fused gradient
-  static constexpr int T_END = T_GW + 3 * ROWS * KB;
+  static constexpr int T_GW = T_ZO + ROWS * KB;   // GWROWS x 3 x KB, fused gradient
+  static constexpr int T_END = T_GW + 3 * GWROWS * KB;
   static constexpr int TYPED_DOUBLES = (T_END * (int)sizeof(T) + 7) / 8;
   static constexpr int PLEN = 3 * KB * KB;       // Gram accumulator (FP64)
   static constexpr int PSTRIDE = PLEN + 2;        // per-workgroup partials: Gram, sum g^2, sum X_ij^2
@@ -122,8 +126,10 @@ template <typename T>
 struct Data {
   const int* rp;
   const int* col;
-  const T* val;  // CSR values (M_Omega or C)
-  const T* D;    // dense C or M
+  const T* val;          // CSR values (M_Omega or C)
+  const T* D;            // dense C or M
+  const uint16_t* Dhi;   // dense, as bf16 planes hi + lo (matrix-core form)
+  const uint16_t* Dlo;
 };
 
 // This workgroup's slice of the CSR data in LDS (see cache_layout): row
@@ -198,6 +204,166 @@ __device__ inline void step_scalars(const Cfg& cfg, gbl<Ctl>* ctl, int lane) {
 }
 
 // ---------------------------------------------------------------------------
+// Dense product on the matrix cores, three bf16 passes with FP32 accumulation:
+//   out = M[row0:row0+64, :] Zin,   M = Mhi + Mlo (two bf16 planes),
+//   Zin = Zhi + Zlo split in the same way as it is staged,
+//   M Zin ~ Mhi Zhi + Mhi Zlo + Mlo Zhi  (the Mlo Zlo term is below 2^-16).
+// 512 threads: wave w owns the 32-row tile w % 2 and the K quarter w / 2 of
+// every K chunk of 256.  K is traversed in an order of our choosing (the sum
+// does not depend on it): lane (i, h) of a wave reads 64 contiguous bytes of
+// row i of each plane per chunk, and the Zin chunk is staged in LDS as bf16
+// hi/lo in the matching B-fragment order, double buffered, one workgroup
+// barrier per chunk.  The A fragments of the next chunk are loaded while the
+// current one is multiplied.  v_mfma_f32_32x32x16_bf16 lane layout: A lane l
+// holds A[l % 32][8 (l / 32) + e], B lane l holds B[8 (l / 32) + e][l % 32],
+// result register v of lane l is C[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+constexpr int kX3Chunk = 256;                         // K per chunk
+constexpr int kX3StageBytes = 2 * 2 * (kX3Chunk / 8) * 32 * 16;  // [buffer][plane][k/8][column][8 bf16]
+
+// round to nearest even (finite inputs)
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+template <int KB, int NT>
+__device__ __noinline__ void dense_x3(int64_t n, int64_t ld, const gbl<uint16_t>* __restrict__ Mhi,
+                                      const gbl<uint16_t>* __restrict__ Mlo, const gbl<float>* __restrict__ Zin,
+                                      int64_t row0, lds<float>* out, lds<char>* xs) {
+  static_assert(NT == 512 && KB <= 32, "8 waves, at most 32 columns");
+  constexpr int KC = kX3Chunk;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rt = wave & 1, kq = wave >> 1;
+  const int li = lane & 31, h = lane >> 5;
+  const int64_t arow = row0 + 32 * rt + li;
+  const bool rowok = arow < n;
+  const int nchunk = (int)((n + KC - 1) / KC);
+  const gbl<uint16_t>* ph = Mhi + (rowok ? arow * ld : 0);
+  const gbl<uint16_t>* pl = Mlo + (rowok ? arow * ld : 0);
+  // A fragments of chunk c, branch-free: every 16-byte load reads inside the
+  // row (ld is a multiple of 8 and the group start is clamped below n), and
+  // elements past n or rows past n are masked to zero afterwards.
+  auto load_a = [&](int c, u16x8_t (&ah)[4], u16x8_t (&al)[4]) {
+    const int64_t k0 = (int64_t)c * KC + kq * 64 + h * 32;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t kk = k0 + 8 * s;
+      const int64_t ka = kk < n ? kk : 0;
+      ah[s] = *reinterpret_cast<const gbl<u16x8_t>*>(ph + ka);
+      al[s] = *reinterpret_cast<const gbl<u16x8_t>*>(pl + ka);
+      const int64_t left = rowok ? n - kk : 0;  // valid elements in this group
+      if (left < 8) {  // rare: the K tail, or a row past n
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          ah[s][e] = e < left ? ah[s][e] : (unsigned short)0;
+          al[s][e] = e < left ? al[s][e] : (unsigned short)0;
+        }
+      }
+    }
+  };
+  // staging of a Zin chunk: thread t < 32 * KB / 4 owns the 4 columns
+  // 4 (t % (KB/4)) .. + 3 of the 8 rows of k-group t / (KB/4): 8 16-byte loads,
+  // 4 columns x (hi, lo) fragments of 8 values written back
+  constexpr int CG = KB / 4;  // column groups of 4
+  const int scg = tid % CG, sg = tid / CG;
+  const bool stager = tid < (KC / 8) * CG;
+  auto load_b = [&](int c, f32x4_t (&zv)[8]) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t kk = (int64_t)c * KC + sg * 8 + e;
+      const bool ok = stager && kk < n;
+      const f32x4_t v = *reinterpret_cast<const gbl<f32x4_t>*>(Zin + (ok ? kk * KB + 4 * scg : 0));
+      zv[e] = ok ? v : f32x4_t{};
+    }
+  };
+  auto store_b = [&](int buf, const f32x4_t (&zv)[8]) {
+    if (!stager) return;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      u16x8_t hv, lv;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float x = zv[e][q];
+        const unsigned short hb = bf16_rne(x);
+        hv[e] = hb;
+        lv[e] = bf16_rne(x - bf16_val(hb));
+      }
+      const int j = 4 * scg + q;
+      *reinterpret_cast<lds<u16x8_t>*>(xs + (((buf * 2 + 0) * (KC / 8) + sg) * 32 + j) * 16) = hv;
+      *reinterpret_cast<lds<u16x8_t>*>(xs + (((buf * 2 + 1) * (KC / 8) + sg) * 32 + j) * 16) = lv;
+    }
+  };
+  f32x16_t acc = {};
+  auto multiply = [&](int buf, const u16x8_t (&ah)[4], const u16x8_t (&al)[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int g8 = kq * 8 + h * 4 + s;
+      const u16x8_t bh = *reinterpret_cast<const lds<u16x8_t>*>(xs + (((buf * 2 + 0) * (KC / 8) + g8) * 32 + li) * 16);
+      const u16x8_t bl = *reinterpret_cast<const lds<u16x8_t>*>(xs + (((buf * 2 + 1) * (KC / 8) + g8) * 32 + li) * 16);
+      const bf16x8_t a1 = __builtin_bit_cast(bf16x8_t, ah[s]), a2 = __builtin_bit_cast(bf16x8_t, al[s]);
+      const bf16x8_t b1 = __builtin_bit_cast(bf16x8_t, bh), b2 = __builtin_bit_cast(bf16x8_t, bl);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b2, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2, b1, acc, 0, 0, 0);
+    }
+  };
+  // columns beyond KB of the staged fragments stay zero
+  if constexpr (KB < 32)
+    for (int e = tid; e < 2 * 2 * (KC / 8) * (32 - KB); e += NT) {
+      const int j = KB + e % (32 - KB), rest = e / (32 - KB);
+      *reinterpret_cast<lds<u16x8_t>*>(xs + (rest * 32 + j) * 16) = u16x8_t{};
+    }
+  u16x8_t ah0[4], al0[4], ah1[4], al1[4];
+  f32x4_t zv[8];
+  load_b(0, zv);
+  load_a(0, ah0, al0);
+  store_b(0, zv);
+  __syncthreads();
+  // Stage c: issue the loads of Zin chunk c + 1 and then of A chunk c + 1
+  // (memory counters retire in order, so staging Zin waits for the Zin loads
+  // only and the A loads stay in flight across the barrier), multiply chunk
+  // c, stage Zin chunk c + 1 into LDS.  The prefetches past the last chunk
+  // read valid, masked addresses and are discarded; they keep the loop free
+  // of branches around the loads.
+  int c = 0;
+  auto stage = [&](const u16x8_t (&ah)[4], const u16x8_t (&al)[4], u16x8_t (&nh)[4], u16x8_t (&nl)[4]) {
+    load_b(c + 1, zv);
+    load_a(c + 1, nh, nl);
+    multiply(c & 1, ah, al);
+    store_b((c + 1) & 1, zv);
+    __syncthreads();
+    ++c;
+  };
+  while (true) {  // chunks in pairs so both register buffers are addressed statically
+    stage(ah0, al0, ah1, al1);
+    if (c >= nchunk) break;
+    stage(ah1, al1, ah0, al0);
+    if (c >= nchunk) break;
+  }
+  // sum the four K quarters of each row tile (the staging area is free now)
+  lds<float>* red = reinterpret_cast<lds<float>*>(xs);  // 8 waves x 64 lanes x 16
+#pragma unroll
+  for (int v = 0; v < 16; ++v) red[(wave * 64 + lane) * 16 + v] = acc[v];
+  __syncthreads();
+  for (int e = tid; e < 64 * KB; e += NT) {
+    const int rr = e / KB, j = e % KB;
+    const int t = rr / 32, i = rr % 32;
+    const int l = j + 32 * ((i / 4) % 2), v = 4 * (i / 8) + i % 4;
+    float sum = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sum += red[((t + 2 * q) * 64 + l) * 16 + v];
+    out[e] = sum;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // apply phase: Zout = Yhat Q for the sweep basis Q = Zin W, over all row
 // blocks of this workgroup:
 //   Zout_i = (opscale (Op Zin)_i + sdiag Zin_i) W + V_i diag(ceff) PW,
@@ -213,14 +379,15 @@ __device__ inline void step_scalars(const Cfg& cfg, gbl<Ctl>* ctl, int lane) {
 template <typename T, int KB, int OPK, int NT, bool GRAD, bool CACHE>
 __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, const T* __restrict__ gv,
                             T* __restrict__ gout, const T* __restrict__ B, const T* __restrict__ Zin,
-                            T* __restrict__ Zout, double* part, double* smem, const CsrCache<T>& cc) {
+                            T* __restrict__ Zout, double* part, double* smem, const CsrCache<T>& cc,
+                            lds<char>* xs) {
   using SH = StepShape<T, KB, OPK, NT>;
   constexpr int ROWS = SH::ROWS, RPW = SH::RPW;
-  using SM = ApplySmem<T, KB, ROWS>;
+  using SM = ApplySmem<T, KB, ROWS, SH::GWROWS>;
   constexpr int LD = SM::LD;
   constexpr int VN = V16<T>::N;
   constexpr int WAVES = NT / 64;
-  static_assert(ROWS * KB <= NT, "one staged element per thread");
+  constexpr int SE = (ROWS * KB + NT - 1) / NT;  // staged elements per thread
   static_assert(!GRAD || OPK == OP_CSR, "the fused gradient is the masked (CSR) objective's");
   T* tb = reinterpret_cast<T*>(smem + SM::PLEN);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -248,12 +415,16 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
     const int64_t row0 = blk * ROWS;
     // this block's rows of Zin and B: loads issued now, stored to LDS after
     // the gathers below (their latency overlaps)
-    T pz = 0, pb = 0;
-    if (tid < ROWS * KB) {
-      const int64_t i = row0 + tid / KB;
-      if (i < n) {
-        pz = Zin[i * KB + tid % KB];
-        pb = B[i * KB + tid % KB];
+    T pz[SE], pb[SE];
+#pragma unroll
+    for (int u = 0; u < SE; ++u) {
+      const int e = tid + u * NT;
+      const int64_t i = row0 + e / KB;
+      pz[u] = 0;
+      pb[u] = 0;
+      if (e < ROWS * KB && i < n) {
+        pz[u] = Zin[i * KB + e % KB];
+        pb[u] = B[i * KB + e % KB];
       }
     }
     __syncthreads();  // previous block's LDS reads are done; coefficients are visible
@@ -414,6 +585,11 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
           for (int v = 0; v < VN; ++v) tb[SM::T_U + (wave * RPW + q) * KB + sub * VN + v] = acc[q][v];
         }
       }
+    } else if constexpr (OPK == OP_DENSE_X3) {
+      static_assert(ROWS == 64, "two 32-row tiles per block");
+      static_assert(sizeof(T) == 4, "float state");
+      dense_x3<KB, NT>(n, cfg.ld, (const gbl<uint16_t>*)dat.Dhi, (const gbl<uint16_t>*)dat.Dlo,
+                       (const gbl<float>*)Zin, row0, (lds<float>*)(tb + SM::T_U), xs);
     } else {
       // dense: each wave owns RPW rows; column chunks of 64 with the matching
       // 64 rows of Zin staged in LDS once for all rows of the block
@@ -455,9 +631,13 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
           if (lane == 0) tb[SM::T_U + (wave * RPW + q) * KB + c] = v;
         }
     }
-    if (tid < ROWS * KB) {
-      tb[SM::T_ZIN + tid] = pz;
-      tb[SM::T_B + tid] = pb;
+#pragma unroll
+    for (int u = 0; u < SE; ++u) {
+      const int e = tid + u * NT;
+      if (e < ROWS * KB) {
+        tb[SM::T_ZIN + e] = pz[u];
+        tb[SM::T_B + e] = pb[u];
+      }
     }
     __syncthreads();
     // V_i = (B_i Wb)[:, :r] and y_i = opscale (Op Zin)_i + sdiag Zin_i
@@ -599,10 +779,11 @@ __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Dat
                                              T* __restrict__ Z1, T* __restrict__ Z2, T* __restrict__ g, Bufs b,
                                              int nsteps) {
   using SH = StepShape<T, KB, OPK, NT>;
-  using SM = ApplySmem<T, KB, SH::ROWS>;
+  using SM = ApplySmem<T, KB, SH::ROWS, SH::GWROWS>;
   static_assert(!CACHE || OPK == OP_CSR, "the LDS cache holds CSR data");
   constexpr int DENSE_STAGE = (OPK == OP_DENSE) ? (64 * (KB + 1) * (int)sizeof(T) + 7) / 8 : 0;
   __shared__ double smem[SM::TOTAL + DENSE_STAGE];
+  __shared__ __attribute__((aligned(16))) char xstage[OPK == OP_DENSE_X3 ? kX3StageBytes : 16];
   extern __shared__ __attribute__((aligned(16))) char dyn[];  // CSR cache (CACHE)
   const int tid = threadIdx.x;
 
@@ -639,11 +820,14 @@ __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Dat
       stamp_wg(b, s, 0);
       if constexpr (OPK == OP_CSR) {
         if (grad)
-          apply_phase<T, KB, OPK, NT, true, CACHE>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc);
+          apply_phase<T, KB, OPK, NT, true, CACHE>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc,
+                                                   (lds<char>*)xstage);
         else
-          apply_phase<T, KB, OPK, NT, false, CACHE>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc);
+          apply_phase<T, KB, OPK, NT, false, CACHE>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc,
+                                                    (lds<char>*)xstage);
       } else {
-        apply_phase<T, KB, OPK, NT, false, false>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc);
+        apply_phase<T, KB, OPK, NT, false, false>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc,
+                                                  (lds<char>*)xstage);
       }
       stamp_wg(b, s, 1);
       if (!grid_sync<NT>(b, SM::PSTRIDE, [&] {
@@ -688,7 +872,7 @@ template <typename T, int KB, int OPK, int NT>
 __global__ __launch_bounds__(NT) void k_basis(Cfg cfg, Ctl* __restrict__ ctl, T* __restrict__ Z0,
                                               T* __restrict__ Z1, T* __restrict__ Z2, Bufs b) {
   using SH = StepShape<T, KB, OPK, NT>;
-  using SM = ApplySmem<T, KB, SH::ROWS>;
+  using SM = ApplySmem<T, KB, SH::ROWS, SH::GWROWS>;
   __shared__ double smem[SM::TOTAL];
   const int tid = threadIdx.x;
   const T* Bm = zbuf(Z0, Z1, Z2, ldi(&ctl->src));
@@ -724,12 +908,24 @@ __global__ __launch_bounds__(256) void k_materialize(Cfg cfg, const Ctl* __restr
 // ---------------------------------------------------------------------------
 // auxiliary kernels (ordinary launches; per-workgroup partials, then k_finish)
 // ---------------------------------------------------------------------------
+// A dense operand in the state's type, or as bf16 planes hi + lo (their sum,
+// exact in FP64, is the matrix the matrix-core apply multiplies by).
+template <typename T>
+struct DenseSrc {
+  const T* D;
+  const uint16_t* hi;
+  const uint16_t* lo;
+  __device__ __forceinline__ double at(int64_t idx) const {
+    return hi ? (double)bf16_val(hi[idx]) + (double)bf16_val(lo[idx]) : (double)D[idx];
+  }
+};
+
 // objective at X_t, dense kinds: LINEAR sum C_ij X_ij, DENOISE 1/2 sum (X_ij - M_ij)^2
 // X_ij = alpha [i == j] + sum_l V_il d_l V_jl, accumulated in FP64; one wave
 // per row; V from k_materialize
 template <typename T, int KB>
 __global__ __launch_bounds__(256) void k_objective_dense(Cfg cfg, const Ctl* __restrict__ ctl,
-                                                         const T* __restrict__ D, const T* __restrict__ Z0,
+                                                         DenseSrc<T> D, const T* __restrict__ Z0,
                                                          const T* __restrict__ Z1, const T* __restrict__ Z2,
                                                          double* __restrict__ part) {
   const T* Qw = zbuf(Z0, Z1, Z2, (ctl->src + 1) % 3);  // written by k_materialize
@@ -751,7 +947,7 @@ __global__ __launch_bounds__(256) void k_objective_dense(Cfg cfg, const Ctl* __r
 #pragma unroll
       for (int l = 0; l < KB; ++l)
         if (l < r) x += vi[l] * (double)Qw[j * KB + l];
-      const double dij = (double)D[i * cfg.ld + j];
+      const double dij = D.at(i * cfg.ld + j);
       if (cfg.kind == LINEAR_DENSE) acc += dij * x;
       else acc += 0.5 * (x - dij) * (x - dij);
     }
@@ -801,7 +997,7 @@ __global__ __launch_bounds__(256) void k_objective_csr(Cfg cfg, const Ctl* __res
 
 // sum of squares of a strided matrix (rows x cols, ld) or a vector (rows = 1)
 template <typename T>
-__global__ __launch_bounds__(256) void k_sumsq(const T* __restrict__ x, int64_t rows, int64_t cols, int64_t ld,
+__global__ __launch_bounds__(256) void k_sumsq(DenseSrc<T> x, int64_t rows, int64_t cols, int64_t ld,
                                                double* __restrict__ part) {
   __shared__ double sred[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -809,7 +1005,7 @@ __global__ __launch_bounds__(256) void k_sumsq(const T* __restrict__ x, int64_t 
   const int64_t total = rows * cols;
   for (int64_t e = (int64_t)blockIdx.x * 256 + tid; e < total; e += (int64_t)gridDim.x * 256) {
     const int64_t i = e / cols, j = e % cols;
-    const double v = (double)x[i * ld + j];
+    const double v = x.at(i * ld + j);
     acc += v * v;
   }
   acc = wave_sum(acc);
@@ -845,7 +1041,7 @@ __global__ __launch_bounds__(256) void k_finish(Ctl* __restrict__ ctl, const dou
 // Used once per context by the Lanczos estimate of the operator's extreme
 // eigenvalues.  One wave per row.
 template <typename T>
-__global__ __launch_bounds__(256) void k_matvec(Cfg cfg, const T* __restrict__ D, const int* __restrict__ rp,
+__global__ __launch_bounds__(256) void k_matvec(Cfg cfg, DenseSrc<T> D, const int* __restrict__ rp,
                                                 const int* __restrict__ col, const T* __restrict__ val,
                                                 const T* __restrict__ x, double* __restrict__ y) {
   const int lane = threadIdx.x & 63;
@@ -853,7 +1049,7 @@ __global__ __launch_bounds__(256) void k_matvec(Cfg cfg, const T* __restrict__ D
   if (i >= cfg.n) return;
   double acc = 0.0;
   if (cfg.kind == LINEAR_DENSE || cfg.kind == DENOISE_DENSE) {
-    for (int64_t j = lane; j < cfg.n; j += 64) acc += (double)D[i * cfg.ld + j] * (double)x[j];
+    for (int64_t j = lane; j < cfg.n; j += 64) acc += D.at(i * cfg.ld + j) * (double)x[j];
   } else {
     for (int e = rp[i] + lane; e < rp[i + 1]; e += 64) acc += (double)val[e] * (double)x[col[e]];
   }

@@ -126,6 +126,71 @@ __device__ __forceinline__ void jacobi_rot(double app, double aqq, double apq, d
 template <int KB>
 __device__ __forceinline__ int jacobi_next(int pos) { return pos == 0 ? 0 : (pos == KB - 1 ? 1 : pos + 1); }
 
+// Cyclic parallel Jacobi as below, for blocks larger than 16: the KB/2
+// rotations of a round are computed once (lane m < KB/2 computes rotation m)
+// into LDS (`rot`, 2 * KB/2 doubles), then every lane updates its 2 x 2
+// blocks one after the other.  Blocks are disjoint, so once the rotations
+// are fixed the updates need no ordering among them.
+template <int KB>
+__device__ __noinline__ int jacobi_shared_rot(lds<double>* A, lds<double>* S, double off2_tol, int lane,
+                                              lds<double>* rot) {
+  constexpr int LD = KB + 1;
+  constexpr int NP = KB / 2;
+  constexpr int BPL = NP * NP / 64;
+  for (int e = lane; e < KB * KB; e += 64) S[(e / KB) * LD + (e % KB)] = (e / KB == e % KB) ? 1.0 : 0.0;
+  wsync();
+  int sweep = 0;
+  for (; sweep < 30; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int e = lane; e < KB * KB; e += 64) {
+      const double v = A[(e / KB) * LD + (e % KB)];
+      if (e / KB == e % KB) dia += v * v; else off += v * v;
+    }
+    off = wave_sum(off);
+    dia = wave_sum(dia);
+    if (!(off > off2_tol * (off + dia))) break;  // also exits on NaN
+    int am = lane, bm = KB - 1 - lane;  // positions of slots m and KB - 1 - m (lanes m < NP)
+    for (int round = 0; round < KB - 1; ++round) {
+      if (lane < NP) {
+        const int p = min(am, bm), q = max(am, bm);
+        double c, s;
+        jacobi_rot(A[p * LD + p], A[q * LD + q], A[p * LD + q], c, s);
+        rot[2 * lane] = c;
+        rot[2 * lane + 1] = s;
+        rot[KB + 2 * lane] = p;  // indices kept beside the rotation (exact in FP64)
+        rot[KB + 2 * lane + 1] = q;
+      }
+      am = jacobi_next<KB>(am);
+      bm = jacobi_next<KB>(bm);
+      wsync();
+#pragma unroll
+      for (int bi = 0; bi < BPL; ++bi) {
+        const int bl = lane + 64 * bi;
+        const int m1 = bl / NP, m2 = bl % NP;
+        const double c1 = rot[2 * m1], s1 = rot[2 * m1 + 1], c2 = rot[2 * m2], s2 = rot[2 * m2 + 1];
+        const int p1 = (int)rot[KB + 2 * m1], q1 = (int)rot[KB + 2 * m1 + 1];
+        const int p2 = (int)rot[KB + 2 * m2], q2 = (int)rot[KB + 2 * m2 + 1];
+        const double a = A[p1 * LD + p2], b = A[p1 * LD + q2], cc = A[q1 * LD + p2], d = A[q1 * LD + q2];
+        const double ra = c1 * a - s1 * cc, rb = c1 * b - s1 * d;  // rows: J1^T
+        const double rc = s1 * a + c1 * cc, rd = s1 * b + c1 * d;
+        A[p1 * LD + p2] = c2 * ra - s2 * rb;                       // columns: J2
+        A[p1 * LD + q2] = s2 * ra + c2 * rb;
+        A[q1 * LD + p2] = c2 * rc - s2 * rd;
+        A[q1 * LD + q2] = s2 * rc + c2 * rd;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {  // S <- S J1 in rows 2 m2, 2 m2 + 1
+          const int row = 2 * m2 + h;
+          const double x = S[row * LD + p1], y = S[row * LD + q1];
+          S[row * LD + p1] = c1 * x - s1 * y;
+          S[row * LD + q1] = s1 * x + c1 * y;
+        }
+      }
+      wsync();
+    }
+  }
+  return sweep;
+}
+
 // Cyclic parallel Jacobi (round-robin ordering) for symmetric A in LDS.
 // On return A is (numerically) diagonal and A_in = S diag(A) S^T.  Stops
 // when the off-diagonal mass is below off2_tol of the total (squared norms);
@@ -137,11 +202,12 @@ __device__ __forceinline__ int jacobi_next(int pos) { return pos == 0 ? 0 : (pos
 // derives the same rotation), so a round needs no cross-lane exchange.  All
 // loads of a round precede its stores.
 template <int KB>
-__device__ __noinline__ int jacobi(lds<double>* A, lds<double>* S, double off2_tol, int lane) {
+__device__ __noinline__ int jacobi(lds<double>* A, lds<double>* S, double off2_tol, int lane, lds<double>* rot) {
   constexpr int LD = KB + 1;
   constexpr int NP = KB / 2;
   static_assert((NP * NP) % 64 == 0, "2 x 2 blocks must fill the wavefront");
   constexpr int BPL = NP * NP / 64;  // 2 x 2 blocks per lane
+  if constexpr (BPL > 1) return jacobi_shared_rot<KB>(A, S, off2_tol, lane, rot);
   for (int e = lane; e < KB * KB; e += 64) S[(e / KB) * LD + (e % KB)] = (e / KB == e % KB) ? 1.0 : 0.0;
   wsync();
   int sweep = 0;
@@ -381,6 +447,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   lds<double>* vec = scr + 5 * MS; // 8 * KB
   lds<double>* theta = vec;
   lds<double>* rho = vec + KB;
+  lds<double>* jrot = vec + 2 * KB;  // 2 * KB: rotations of a Jacobi round (KB > 16)
   lds<int>* perm = reinterpret_cast<lds<int>*>(vec + 6 * KB);
   const int r = cfg.r;
 
@@ -430,7 +497,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   const bool prof = ts != nullptr && lane == 0 && sweep == cfg.rr_from;
   if (prof) ts[kTsRR] = wall_clock64();
   // eigenvector accuracy needed: rounding level of the working precision
-  const int jsweeps = jacobi<KB>(A, S, cfg.unit_round < 1e-10 ? 1e-30 : 1e-22, lane);
+  const int jsweeps = jacobi<KB>(A, S, cfg.unit_round < 1e-10 ? 1e-30 : 1e-22, lane, jrot);
   if (prof) {
     ts[kTsRR + 1] = wall_clock64();
     ts[kTsRR + 4] = jsweeps;

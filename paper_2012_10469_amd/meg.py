@@ -207,11 +207,13 @@ class LowRankMEG:
 
     Device arrays (torch tensors) are borrowed by the library and referenced
     here until ``close()``.  Dense data: ``dense`` (n x n, float64 for F64,
-    float32 for F32).  CSR data: ``row_ptr``/``col`` int32, ``val``.
+    float32 for F32; for F32_BF16X3 the bf16 hi plane as a 16-bit tensor,
+    with ``dense_lo`` the lo plane, rows of ``ld`` elements).  CSR data:
+    ``row_ptr``/``col`` int32, ``val``.
     """
 
     def __init__(self, n: int, r: int, kind: int, V0, lam0, *, prec: int = MEG_PREC_F32, eta: float = 1.0,
-                 dense=None, row_ptr=None, col=None, val=None, oversample: int = 4,
+                 dense=None, dense_lo=None, row_ptr=None, col=None, val=None, oversample: int = 4,
                  eps=(0.8, 10.0, 2.0), min_inner: int = 1, max_inner: int = 12, inner_tol: float = 0.0,
                  seed: int = 0, flags: int = 0, cert_tol: float = 0.0, stream: Optional[int] = None):
         import torch
@@ -219,10 +221,10 @@ class LowRankMEG:
         if not torch.cuda.is_available():
             raise RuntimeError("LowRankMEG needs a visible GPU")
         self._lib = load_library()
-        self._keep = [dense, row_ptr, col, val]
+        self._keep = [dense, dense_lo, row_ptr, col, val]
         self.n, self.r = int(n), int(r)
         self.kind = kind
-        obj = MegObjective(kind=kind, batch=0, dense=_dptr(dense), dense_lo=None,
+        obj = MegObjective(kind=kind, batch=0, dense=_dptr(dense), dense_lo=_dptr(dense_lo),
                            ld=int(dense.stride(0)) if dense is not None else 0,
                            row_ptr=_dptr(row_ptr), col=_dptr(col), val=_dptr(val),
                            nnz=int(col.numel()) if col is not None else 0,

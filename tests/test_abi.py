@@ -143,6 +143,21 @@ def test_init_rejects_bad_start_and_objective(M):
         == M.MEG_ERR_INVALID_ARG
 
 
+def test_init_rejects_bad_bf16_planes(M):
+    """The matrix-core form takes two 16-byte-aligned bf16 planes with a row
+    length that is a multiple of 8; CSR data has no such form."""
+    n = 64
+    p = M.make_params(n, 4, prec=M.MEG_PREC_F32_BF16X3)
+    V, lam = _start(n)
+    dense = lambda **kw: M.MegObjective(kind=M.MEG_GRAD_DENOISE_DENSE, **kw)  # noqa: E731
+    assert M.meg_init(p, dense(dense=0x1000, dense_lo=None, ld=64), V, lam)[0] == M.MEG_ERR_INVALID_ARG
+    assert M.meg_init(p, dense(dense=0x1000, dense_lo=0x2000, ld=68), V, lam)[0] == M.MEG_ERR_INVALID_ARG
+    assert M.meg_init(p, dense(dense=0x1008, dense_lo=0x2000, ld=64), V, lam)[0] == M.MEG_ERR_INVALID_ARG
+    assert M.meg_init(p, dense(dense=0x1000, dense_lo=0x2004, ld=64), V, lam)[0] == M.MEG_ERR_INVALID_ARG
+    csr = M.MegObjective(kind=M.MEG_GRAD_MASKED_CSR, row_ptr=0x1000, col=0x2000, val=0x3000, nnz=10)
+    assert M.meg_init(p, csr, V, lam)[0] == M.MEG_ERR_UNSUPPORTED
+
+
 def test_null_context_calls(M):
     lib = M.load_library()
     info = M.MegStepInfo()

@@ -119,6 +119,45 @@ def check_certificate(info, L_ref, bulk_width):
     assert dL >= -bulk_width, (info["cert_L"], L_ref, info["resid_r1"])
 
 
+@pytest.mark.parametrize("n,ld,rank,r", [(304, 312, 1, 1), (520, 520, 3, 3), (264, 264, 2, 16)])
+def test_denoise_bf16x3_planes(meg, n, ld, rank, r):
+    """Matrix-core form: M given as bf16 planes hi + lo (row length ld), the
+    apply on three bf16 MFMA products with FP32 accumulation.  The oracle runs
+    on the matrix the planes represent.  Teacher-forced steps: f(X_t) and
+    X_{t+1} against the oracle's step from the same X_t; then a free-running
+    trajectory.  Tolerance: the mixed-precision bound 1e-3."""
+    import torch
+
+    print_case(test="bf16x3", n=n, ld=ld, rank=rank, r=r)
+    M, V0, lam0 = gapped_spiked(n, rank, seed=n + 7 * rank)
+    hi, lo = W.bf16_planes(M.astype(np.float32), ld)
+    Meff = W.planes_value(hi, lo, n)
+    obj = O.DenoiseObjective(Meff)
+    T = 12  # the start has q = rank columns; the solver fills the rest of r
+    run = O.run_lowrank_meg(obj, V0, lam0, r, 1.0, T)
+    dh = torch.from_numpy(hi.view(np.int16)).cuda()
+    dl = torch.from_numpy(lo.view(np.int16)).cuda()
+    kw = dict(prec=meg.MEG_PREC_F32_BF16X3, eta=1.0, dense=dh, dense_lo=dl, max_inner=30)
+    with meg.LowRankMEG(n, r, meg.MEG_GRAD_DENOISE_DENSE, V0, lam0, **kw) as g:
+        for t in range(1, T + 1):
+            st = run["states"][t - 1]
+            g.set_iterate(st.V, st.d, st.alpha, t)
+            info = g.step()
+            X = st.dense()
+            tol = f_tol(run["f"][t - 1], np.linalg.norm(X - Meff), np.linalg.norm(X), 2)
+            assert abs(info["f"] - run["f"][t - 1]) <= tol, (t, info["f"], run["f"][t - 1])
+            err = rel_x_err(g.get_iterate(), run["states"][t])
+            assert err <= TOL_X[2], (t, err)
+            check_certificate(info, run["L"][t - 1], bulk_width=0.05)
+    worst = 0.0
+    with meg.LowRankMEG(n, r, meg.MEG_GRAD_DENOISE_DENSE, V0, lam0, **kw) as g:
+        for t in range(1, T + 1):
+            g.step(info=False)
+            worst = max(worst, rel_x_err(g.get_iterate(), run["states"][t]))
+    print(f"free-running worst rel X error {worst:.2e}")
+    assert worst <= TOL_X[2]
+
+
 @pytest.mark.parametrize("prec,n,r", [(1, 500, 10), (0, 300, 6), (1, 96, 3)])
 def test_masked_csr_teacher_forced(meg, prec, n, r):
     print_case(test="masked_csr_tf", prec=prec, n=n, r=r)

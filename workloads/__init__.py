@@ -248,6 +248,37 @@ def lowrank_noise_denoise(n: int, rank: int, seed: int, noise: float = 1e-3, r: 
     return DenseProblem("denoise", M, V0, lam0)
 
 
+def bf16_planes(M: np.ndarray, ld: Optional[int] = None) -> tuple[np.ndarray, np.ndarray]:
+    """Split a float32 matrix into bf16 planes hi + lo (bit patterns as uint16,
+    rows padded with zeros to ``ld`` columns): hi = bf16(M), lo = bf16(M - hi),
+    both rounded to nearest even.  This is the input format of the
+    matrix-core (F32_BF16X3) form; ``planes_value(hi, lo)`` is the matrix it
+    represents."""
+    M = np.ascontiguousarray(M, dtype=np.float32)
+    n, m = M.shape
+    ld = m if ld is None else ld
+
+    def rne(x):
+        u = x.view(np.uint32).astype(np.uint64)
+        u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+        return u.astype(np.uint16)
+
+    hi = rne(M)
+    lo = rne((M - (hi.astype(np.uint32) << 16).view(np.float32)).astype(np.float32))
+    H = np.zeros((n, ld), np.uint16)
+    L = np.zeros((n, ld), np.uint16)
+    H[:, :m] = hi
+    L[:, :m] = lo
+    return H, L
+
+
+def planes_value(hi: np.ndarray, lo: np.ndarray, cols: Optional[int] = None) -> np.ndarray:
+    """The float64 matrix hi + lo of two bf16 planes (exact)."""
+    f = lambda p: (p.astype(np.uint32) << 16).view(np.float32).astype(np.float64)  # noqa: E731
+    V = f(hi) + f(lo)
+    return V if cols is None else V[:, :cols]
+
+
 def _symmetric_bernoulli_pattern(n: int, p: float, g: np.random.Generator):
     """Upper triangle (diagonal included) Bernoulli(p), mirrored; CSR arrays."""
     rows_l, cols_l = [], []
