@@ -30,30 +30,44 @@ __device__ __forceinline__ double wave_min(double v) {
   return v;
 }
 
+// C = op(A) B for KB x KB matrices in LDS (stride KB + 1), op(A) = A or A^T,
+// on the FP64 matrix cores: 16 x 16 output tiles, v_mfma_f64_16x16x4f64 per
+// 4-wide K step.  Lane layout: A operand lane l holds A[l % 16][l / 16], B
+// operand lane l holds B[l / 16][l % 16], result register v of lane l is
+// C[l / 16 + 4 v][l % 16].  All 64 lanes must call it.  C may not alias A
+// or B (results are written after all reads of a tile).
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+template <int KB, bool TA>
+__device__ __forceinline__ void mm_mfma(const lds<double>* A, const lds<double>* B, lds<double>* C, int lane) {
+  constexpr int LD = KB + 1;
+  const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int ti = 0; ti < KB / 16; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < KB / 16; ++tj) {
+      f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < KB / 4; ++s) {
+        const int k = 4 * s + kq;
+        const double a = TA ? A[k * LD + 16 * ti + i] : A[(16 * ti + i) * LD + k];
+        const double b = B[k * LD + 16 * tj + i];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) C[(16 * ti + kq + 4 * v) * LD + 16 * tj + i] = acc[v];
+    }
+}
+
 // C = A^T B (all KB x KB, LDS stride KB + 1)
 template <int KB>
 __device__ __forceinline__ void mm_tn(const lds<double>* A, const lds<double>* B, lds<double>* C, int lane) {
-  constexpr int LD = KB + 1;
-  for (int e = lane; e < KB * KB; e += 64) {
-    const int i = e / KB, j = e % KB;
-    double s = 0.0;
-#pragma unroll
-    for (int l = 0; l < KB; ++l) s += A[l * LD + i] * B[l * LD + j];
-    C[i * LD + j] = s;
-  }
+  mm_mfma<KB, true>(A, B, C, lane);
 }
 
 // C = A B
 template <int KB>
 __device__ __forceinline__ void mm_nn(const lds<double>* A, const lds<double>* B, lds<double>* C, int lane) {
-  constexpr int LD = KB + 1;
-  for (int e = lane; e < KB * KB; e += 64) {
-    const int i = e / KB, j = e % KB;
-    double s = 0.0;
-#pragma unroll
-    for (int l = 0; l < KB; ++l) s += A[i * LD + l] * B[l * LD + j];
-    C[i * LD + j] = s;
-  }
+  mm_mfma<KB, false>(A, B, C, lane);
 }
 
 // dense KB x KB (stride KB, global) <-> LDS stride KB + 1; the loops have
