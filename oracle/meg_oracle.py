@@ -46,6 +46,7 @@ __all__ = [
     "FactoredIterate",
     "initial_iterate",
     "lowrank_step",
+    "lowrank_step_factored",
     "run_lowrank_meg",
     "certificate",
     "project_spectrahedron",
@@ -210,6 +211,25 @@ class QuadMeasObjective:
         w = self.residuals(X)
         return 0.5 * float(np.dot(w, w)) / self.m
 
+    def residuals_factored(self, it: "FactoredIterate", idx: Optional[np.ndarray] = None) -> np.ndarray:
+        """a_i^T X a_i - b_i for X = alpha I + V diag(d) V^T without forming X:
+        a_i^T X a_i = alpha ||a_i||^2 + sum_l d_l (v_l^T a_i)^2."""
+        A = self.A if idx is None else self.A[:, idx]
+        b = self.b if idx is None else self.b[idx]
+        P = it.V.T @ A  # q x L
+        x = it.alpha * np.sum(A * A, axis=0) + np.sum(it.d[:, None] * P * P, axis=0)
+        return x - b
+
+    def grad_factor(self, it: "FactoredIterate", batch: np.ndarray):
+        """The minibatch gradient in factored form F diag(c) F^T: F = A_B
+        (n x L), c_i = (a_i^T X a_i - b_i)/L."""
+        F = self.A[:, batch]
+        return F, self.residuals_factored(it, batch) / F.shape[1]
+
+    def value_factored(self, it: "FactoredIterate") -> float:
+        w = self.residuals_factored(it)
+        return 0.5 * float(np.dot(w, w)) / self.m
+
 
 # ---------------------------------------------------------------------------
 # exact MEG (Algorithm 1)
@@ -330,6 +350,58 @@ def lowrank_step(it: FactoredIterate, G: np.ndarray, eta: float, eps: float, r: 
     }
     if full:
         info["Zplus"] = (U * softmax(mu)) @ U.T
+    return new, info
+
+
+def lowrank_step_factored(it: FactoredIterate, F: np.ndarray, c: np.ndarray, eta: float, eps: float, r: int):
+    """lowrank_step for a gradient given as G = F diag(c) F^T (F n x p), without
+    any n x n matrix.  M_t - log(alpha) I = V diag(log(alpha + d) - log alpha) V^T
+    - eta F diag(c) F^T vanishes on the orthogonal complement of S = span[V, F],
+    so S is an invariant subspace: with U an orthonormal basis of S (dimension
+    s), the eigenvalues of M_t are those of U^T M_t U and log(alpha) with
+    multiplicity n - s, and the eigenvectors of the first kind are U times
+    those of the s x s matrix.  Same outputs as lowrank_step with full=True,
+    except that ``U``/``Zplus`` are omitted and ``L_full`` counts the n - s
+    eigenvalues log(alpha) analytically."""
+    n = it.n
+    if not (1 <= r <= n - 1):
+        raise ValueError("rank parameter r must lie in {1, ..., n-1}")
+    F = np.asarray(F, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    la = math.log(it.alpha)
+    basis = np.concatenate([it.V, F], axis=1)
+    Uq, sv, _ = np.linalg.svd(basis, full_matrices=False)
+    U = Uq[:, sv > sv[0] * 1e-12]
+    s = U.shape[1]
+    cv = np.log(it.alpha + it.d) - la
+    PV = U.T @ it.V
+    PF = U.T @ F
+    H = (PV * cv) @ PV.T - eta * (PF * c) @ PF.T + la * np.eye(s)
+    mu_s, S = eig_desc(H)
+    # merge with the n - s eigenvalues log(alpha) of the complement
+    if s < n:
+        mu = np.concatenate([mu_s, np.full(n - s, la)])
+        order = np.argsort(-mu, kind="stable")
+        mu = mu[order]
+    else:
+        order = np.arange(n)
+        mu = mu_s
+    if np.any(order[:r] >= s):
+        raise ValueError("a top-r eigenvalue of M_t lies on the complement of span[V, F]")
+    Vn = U @ S[:, order[:r]]
+    lam_tilde = softmax(mu[:r])
+    alpha_new = eps / (n - r)
+    d_new = (1.0 - eps) * lam_tilde - alpha_new
+    new = FactoredIterate(Vn, d_new, alpha_new, it.t + 1)
+    info = {
+        "mu": mu,
+        "gap": float(mu[r - 1] - mu[r]),
+        "L": certificate(mu, r, eps, n, r + 1),
+        "L_full": certificate(mu, r, eps, n, n),
+        "eps": eps,
+        "lam_tilde": lam_tilde,
+        "subspace_dim": s,
+    }
     return new, info
 
 

@@ -43,6 +43,7 @@ struct meg_ctx_s {
   void* Za = nullptr;
   void* Zb = nullptr;
   void* g = nullptr;
+  void* quad = nullptr;  // factored gradient scratch: y (L x k), K (L x L), w (L), ||a||^2 (L)
   Ctl* ctl = nullptr;
   double* part = nullptr;
   double* gpart = nullptr;
@@ -134,14 +135,47 @@ meg_status hip_fail(meg_ctx c) {
 // launch helpers, dispatched on T (element type), KB (block size) and the
 // operator family
 // ---------------------------------------------------------------------------
+// byte offsets of the factored-gradient scratch (one allocation)
+struct QuadLayout {
+  size_t y, k, w, na, bytes;
+};
+QuadLayout quad_layout(int64_t L, int k, size_t esize) {
+  QuadLayout q;
+  q.y = 0;
+  q.k = (size_t)align16((int64_t)(L * k * esize));
+  q.w = (size_t)align16((int64_t)(q.k + L * L * esize));
+  q.na = q.w + (size_t)L * 8;
+  q.bytes = q.na + (size_t)L * 8;
+  return q;
+}
+
 template <typename T, int KB>
 struct Launch {
   static bool x3(meg_ctx c) { return c->cfg.prec == MEG_PREC_F32_BF16X3; }
+  static bool quad(meg_ctx c) { return c->cfg.kind == QUADMEAS; }
   static Data<T> data(meg_ctx c) {
-    if (x3(c))
-      return Data<T>{c->obj.row_ptr, c->obj.col, (const T*)c->obj.val, nullptr, (const uint16_t*)c->obj.dense,
-                     (const uint16_t*)c->obj.dense_lo};
-    return Data<T>{c->obj.row_ptr, c->obj.col, (const T*)c->obj.val, (const T*)c->obj.dense, nullptr, nullptr};
+    Data<T> d{};
+    d.rp = c->obj.row_ptr;
+    d.col = c->obj.col;
+    d.val = (const T*)c->obj.val;
+    if (x3(c)) {
+      d.Dhi = (const uint16_t*)c->obj.dense;
+      d.Dlo = (const uint16_t*)c->obj.dense_lo;
+    } else {
+      d.D = (const T*)c->obj.dense;
+    }
+    if (quad(c)) {
+      const QuadLayout q = quad_layout(c->cfg.batch, c->cfg.k, sizeof(T));
+      char* base = (char*)c->quad;
+      d.A = (const T*)c->obj.A;
+      d.bq = (const T*)c->obj.b;
+      d.bidx = c->obj.batch_idx;
+      d.qy = (T*)(base + q.y);
+      d.qk = (T*)(base + q.k);
+      d.qw = (double*)(base + q.w);
+      d.qn = (double*)(base + q.na);
+    }
+    return d;
   }
   static DenseSrc<T> dense_src(meg_ctx c) {
     if (x3(c)) return DenseSrc<T>{nullptr, (const uint16_t*)c->obj.dense, (const uint16_t*)c->obj.dense_lo};
@@ -153,12 +187,14 @@ struct Launch {
   // exists for float state only, which validation guarantees)
   static const void* step_kernel(meg_ctx c) {
     if (csr(c)) return c->cfg.cache_blocks > 0 ? kernel<OP_CSR, true>() : kernel<OP_CSR>();
+    if (quad(c)) return kernel<OP_FACTOR>();
     if constexpr (sizeof(T) == 4)
       if (x3(c)) return kernel<OP_DENSE_X3>();
     return kernel<OP_DENSE>();
   }
   static int rows_per_block(meg_ctx c) {
     if (csr(c)) return StepShape<T, KB, OP_CSR, kStepNT>::ROWS;
+    if (quad(c)) return StepShape<T, KB, OP_FACTOR, kStepNT>::ROWS;
     if (x3(c)) return StepShape<T, KB, OP_DENSE_X3, kStepNT>::ROWS;
     return StepShape<T, KB, OP_DENSE, kStepNT>::ROWS;
   }
@@ -267,6 +303,15 @@ struct Launch {
     const int mwg = (int)std::min<int64_t>(4096, ceil_div(cfg.n * KB, 256));
     hipLaunchKernelGGL((k_materialize<T, KB>), dim3(mwg), dim3(256), 0, c->stream, cfg, c->ctl, (T*)c->Qw, (T*)c->Za,
                        (T*)c->Zb);
+    if (quad(c)) {
+      const int mb = sizeof(T) == 4 ? 4 : 2;  // measurements per wave (k_objective_quad)
+      const int qwg = (int)std::min<int64_t>(c->aux_nwg, std::max<int64_t>(1, (cfg.m + 4 * mb - 1) / (4 * mb)));
+      hipLaunchKernelGGL((k_objective_quad<T, KB>), dim3(qwg), dim3(256), 0, c->stream, cfg, c->ctl,
+                         (const T*)c->obj.A, (const T*)c->obj.b, (const T*)c->Qw, (const T*)c->Za, (const T*)c->Zb,
+                         c->part);
+      hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, c->stream, c->ctl, c->part, qwg, 0);
+      return hipGetLastError();
+    }
     if (csr(c))
       hipLaunchKernelGGL((k_objective_csr<T, KB>), dim3(nwg), dim3(256), 0, c->stream, cfg, c->ctl, c->obj.row_ptr,
                          c->obj.col, (const T*)c->obj.val, (const T*)c->Qw, (const T*)c->Za, (const T*)c->Zb,
@@ -602,8 +647,17 @@ meg_status validate(const meg_params* p, const meg_objective* o, const meg_start
       if (o->nnz > 2147483647LL) return MEG_ERR_INVALID_ARG;
       if (p->prec == MEG_PREC_F32_BF16X3) return MEG_ERR_UNSUPPORTED;
       break;
-    case MEG_GRAD_QUADMEAS:
-      return MEG_ERR_UNSUPPORTED;
+    case MEG_GRAD_QUADMEAS: {
+      if (!o->A || !o->b || !o->batch_idx || o->m < 1 || o->lda < p->n || o->batch_steps < 1) return MEG_ERR_INVALID_ARG;
+      if (o->batch < 1 || o->batch > kMaxBatch) return MEG_ERR_INVALID_ARG;
+      if (o->m > (int64_t)1 << 40 || o->lda > (int64_t)1 << 40 || o->batch_steps > ((int64_t)1 << 40) / o->batch)
+        return MEG_ERR_INVALID_ARG;
+      if (p->prec == MEG_PREC_F32_BF16X3) return MEG_ERR_UNSUPPORTED;
+      // rows of the pool start on 16-byte boundaries (vector loads)
+      const size_t es = (p->prec == MEG_PREC_F64) ? 8 : 4;
+      if (((uintptr_t)o->A % 16) != 0 || (o->lda * (int64_t)es) % 16 != 0) return MEG_ERR_INVALID_ARG;
+      break;
+    }
     default:
       return MEG_ERR_INVALID_ARG;
   }
@@ -626,7 +680,7 @@ meg_status validate(const meg_params* p, const meg_objective* o, const meg_start
 
 void free_ctx(meg_ctx c) {
   if (!c) return;
-  void* bufs[] = {c->Qw, c->Za, c->Zb, c->g, c->ctl, c->part, c->gpart, c->sums, c->bar, c->ts};
+  void* bufs[] = {c->Qw, c->Za, c->Zb, c->g, c->quad, c->ctl, c->part, c->gpart, c->sums, c->bar, c->ts};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
@@ -720,6 +774,7 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
             alloc((void**)&c->gpart, (size_t)kBarMaxGroups * 3 * KMAX * KMAX * 8) &&
             alloc((void**)&c->ts, kTsSlots * sizeof(long long));
   if (ok && obj->kind == MEG_GRAD_MASKED_CSR) ok = alloc(&c->g, (size_t)std::max<int64_t>(obj->nnz, 1) * c->esize);
+  if (ok && obj->kind == MEG_GRAD_QUADMEAS) ok = alloc(&c->quad, quad_layout(obj->batch, k, c->esize).bytes);
   if (ok) ok = hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl)) == hipSuccess;
   for (int i = 0; ok && i < meg_ctx_s::kEvRing; ++i)
     ok = hipEventCreate(&c->ev_a[i]) == hipSuccess && hipEventCreate(&c->ev_b[i]) == hipSuccess;
@@ -756,13 +811,36 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
     }
     (void)dispatch<DoCache>(c);  // per-workgroup LDS copy of the CSR data, when it fits
   }
-  // data norm (sets ctl->data_norm)
-  if (dispatch<DoNorm>(c) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+  // minibatch index check before any kernel reads the pool through them
+  if (obj->kind == MEG_GRAD_QUADMEAS) {
+    int h_err = 0;
+    int* d_err = (int*)c->sums;
+    const int64_t cnt = obj->batch_steps * (int64_t)obj->batch;
+    if (hipMemsetAsync(d_err, 0, sizeof(int), c->stream) != hipSuccess) {
+      free_ctx(c);
+      return MEG_ERR_DEVICE;
+    }
+    hipLaunchKernelGGL(k_check_idx, dim3((unsigned)std::min<int64_t>(1024, (cnt + 255) / 256)), dim3(256), 0,
+                       c->stream, obj->batch_idx, cnt, obj->m, d_err);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
+        hipMemcpy(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+      free_ctx(c);
+      return MEG_ERR_DEVICE;
+    }
+    if (h_err) {
+      free_ctx(c);
+      return MEG_ERR_INVALID_ARG;
+    }
+  }
+  // data norm (sets ctl->data_norm) and the extreme eigenvalues of the data
+  // operator (shift of the subspace iteration); the factored gradient
+  // changes every step and bounds its spectrum inside the step instead
+  if (obj->kind != MEG_GRAD_QUADMEAS &&
+      (dispatch<DoNorm>(c) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)) {
     free_ctx(c);
     return MEG_ERR_DEVICE;
   }
-  // extreme eigenvalues of the data operator (shift of the subspace iteration)
-  {
+  if (obj->kind != MEG_GRAD_QUADMEAS) {
     double lmin = 0.0, lmax = 0.0;
     st = (c->esize == 8) ? lanczos_extremes<double>(c, &lmin, &lmax) : lanczos_extremes<float>(c, &lmin, &lmax);
     if (st == MEG_OK) st = copy_ctl_to_host(c);

@@ -18,6 +18,7 @@
 namespace meg {
 
 constexpr int KMAX = 32;
+constexpr int kMaxBatch = 1024;  // largest minibatch of the factored gradient
 
 // Pointer into LDS.  The explicit address space lets functions that are not
 // inlined into the kernel use LDS instructions; through a generic pointer

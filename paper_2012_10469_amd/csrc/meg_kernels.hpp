@@ -19,14 +19,17 @@
 // Cross-workgroup communication happens only at the barriers, so no
 // workgroup writes back or invalidates the L2 while others stream through it.
 #pragma once
+#include <type_traits>
+
 #include "meg_device.hpp"
 #include "meg_small.hpp"
 
 namespace meg {
 
-// Operator families of the apply: sparse CSR, dense in the state's type, and
-// dense given as two bf16 planes hi + lo and applied on the matrix cores.
-enum OpKind : int { OP_CSR = 0, OP_DENSE = 1, OP_DENSE_X3 = 2 };
+// Operator families of the apply: sparse CSR, dense in the state's type,
+// dense given as two bf16 planes hi + lo and applied on the matrix cores, and
+// the factored minibatch gradient A_B^T diag(w / L) A_B.
+enum OpKind : int { OP_CSR = 0, OP_DENSE = 1, OP_DENSE_X3 = 2, OP_FACTOR = 3 };
 
 // 16-byte vector of T (float4 / double2) used for row-chunk loads.
 template <typename T> struct V16;
@@ -92,7 +95,8 @@ struct StepShape {
   static constexpr int WAVES = NT / 64;
   // rows per wave: CSR rows are gathered concurrently (more loads in flight);
   // the matrix-core form works on 64-row blocks (two 32-row MFMA tiles)
-  static constexpr int RPW = (OPK == OP_CSR) ? 2 : (OPK == OP_DENSE_X3 ? 64 / WAVES : dense_rpw<T, KB>());
+  static constexpr int RPW = (OPK == OP_CSR) ? 2
+                             : (OPK == OP_DENSE_X3 ? 64 / WAVES : (OPK == OP_FACTOR ? 32 / WAVES : dense_rpw<T, KB>()));
   static constexpr int ROWS = WAVES * RPW;  // rows per apply block
   static constexpr int GROWS = 2 * WAVES;   // rows per block of the basis Gram
   static constexpr int GWROWS = (OPK == OP_CSR) ? ROWS : 0;  // fused-gradient scratch rows
@@ -130,6 +134,14 @@ struct Data {
   const T* D;            // dense C or M
   const uint16_t* Dhi;   // dense, as bf16 planes hi + lo (matrix-core form)
   const uint16_t* Dlo;
+  // factored minibatch gradient (quadratic measurements)
+  const T* A;            // pool, measurement i = row i (stride lda)
+  const T* bq;           // measured values b[m]
+  const int* bidx;       // minibatch indices (batch_steps x L; the step's row in k_step)
+  T* qy;                 // L x KB: y_i = (w_i / L) a_i^T Zin
+  T* qk;                 // L x L: minibatch Gram matrix A_B A_B^T (first sweep)
+  double* qw;            // L: residuals w_i = a_i^T X_t a_i - b_i
+  double* qn;            // L: ||a_i||^2
 };
 
 // This workgroup's slice of the CSR data in LDS (see cache_layout): row
@@ -186,6 +198,8 @@ __device__ void load_csr_cache(const Cfg& cfg, const Data<T>& dat, const CsrCach
 // inside the first sweep.
 // ---------------------------------------------------------------------------
 __device__ inline void step_scalars(const Cfg& cfg, gbl<Ctl>* ctl, int lane) {
+  // the minibatch gradient's bound is known only inside sweep 1 (factor_shift)
+  if (cfg.kind == QUADMEAS) return;
   const double alpha = ctl->alpha;
   const bool act = lane < cfg.r;
   const double dl = act ? ctl->d[lane] : 0.0;
@@ -360,6 +374,335 @@ __device__ __noinline__ void dense_x3(int64_t n, int64_t ld, const gbl<uint16_t>
 #pragma unroll
     for (int q = 0; q < 4; ++q) sum += red[((t + 2 * q) * 64 + l) * 16 + v];
     out[e] = sum;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Factored minibatch gradient (quadratic measurements with the stochastic
+// gradient estimate of Section 6):
+//   G = (1/L) sum_{i in batch} w_i a_i a_i^T,   w_i = a_i^T X_t a_i - b_i,
+// so Op Zin = A_B^T diag(w / L) (A_B Zin) takes two passes over the L x n
+// minibatch A_B with a grid barrier between them:
+//   factor_rows  one workgroup per minibatch row i: y_i = (w_i / L) a_i^T Zin
+//   factor_cols  (in the apply's row blocks): (Op Zin)_j = sum_i a_ij y_i
+// In sweep 1, Zin = B, so a_i^T V = (a_i^T B) Wb[:, :r] comes out of the same
+// product and w_i = alpha ||a_i||^2 + sum_l d_l (a_i^T v_l)^2 - b_i is formed
+// there.  The shift needs an upper bound on lambda_max(G):
+//   G <= (1/L) sum_{w_i > 0} w_i a_i a_i^T = (1/L) A_+^T D A_+,
+// whose nonzero eigenvalues are those of D^1/2 A_+ A_+^T D^1/2; Gershgorin's
+// theorem on that L x L matrix gives
+//   lambda_max(G) <= max_i sqrt(w_i+) sum_j |K_ij| sqrt(w_j+) / L,  K = A_B A_B^T,
+// with |K_ij| widened by the rounding bound 2 n u ||a_i|| ||a_j||.  (The
+// trace bound sum w_i+ ||a_i||^2 / L is tens of times larger for Gaussian
+// measurements and would slow the subspace iteration accordingly.)
+// ---------------------------------------------------------------------------
+constexpr int kFacChunk = 256;  // minibatch rows staged per pass of factor_cols
+
+template <typename T, int KB>
+constexpr int fac_stage_bytes() {
+  constexpr int cols = kFacChunk * KB * (int)sizeof(T) + kFacChunk * 8;  // y chunk + pool offsets
+  constexpr int gram = 8 * 256 * (int)sizeof(T);                        // per-wave 16 x 16 tiles
+  constexpr int shift = (2 * kMaxBatch + 16) * 8;                        // sqrt(w+), ||a|| sqrt(w+), maxima
+  constexpr int rows = 9 * KB * (int)sizeof(T) + 128;
+  constexpr int a = cols > gram ? cols : gram;
+  constexpr int b = shift > rows ? shift : rows;
+  return a > b ? a : b;
+}
+
+// pool row of a minibatch index, clamped into the pool (indices are checked
+// when the context is created; the clamp keeps every access in bounds)
+__device__ __forceinline__ int64_t pool_row(int v, int64_t m) {
+  const int64_t q = v;
+  return q < 0 ? 0 : (q >= m ? m - 1 : q);
+}
+
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+
+// 16-byte load from global memory into 4 floats or 2 doubles
+template <typename T>
+__device__ __forceinline__ void vload_g(const gbl<T>* p, T* out) {
+  if constexpr (sizeof(T) == 4) {
+    const f32x4_t v = *reinterpret_cast<const gbl<f32x4_t>*>(p);
+    out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
+  } else {
+    const f64x2_t v = *reinterpret_cast<const gbl<f64x2_t>*>(p);
+    out[0] = v[0]; out[1] = v[1];
+  }
+}
+
+// Phase 1 of a factored apply, minibatch rows i = blockIdx.x, + gridDim.x, ...
+// t_i = a_i^T Zin (KB values) is accumulated by all threads over their
+// elements of a_i, reduced within each wave by a transposing butterfly
+// (each step halves the values a lane carries, so a wave needs KB - 1
+// exchanges instead of 6 KB) and then over the waves in a fixed order.
+template <typename T, int KB, int NT>
+__device__ __noinline__ void factor_rows(int64_t n, int64_t lda, int64_t m, int L, const gbl<T>* __restrict__ A,
+                                         const gbl<T>* __restrict__ bq, const gbl<int>* __restrict__ idx,
+                                         const gbl<T>* __restrict__ Zin, gbl<T>* __restrict__ qy,
+                                         gbl<double>* __restrict__ qw, gbl<double>* __restrict__ qn,
+                                         const gbl<Ctl>* ctl, int r, bool first, lds<char>* scr) {
+  constexpr int VN = V16<T>::N;
+  constexpr int WAVES = NT / 64;
+  constexpr int GL = 64 / KB;  // lanes that share a column after the butterfly
+  lds<T>* wsum = reinterpret_cast<lds<T>*>(scr);  // WAVES x KB
+  lds<double>* sred = reinterpret_cast<lds<double>*>(scr + align16(WAVES * KB * (int)sizeof(T)));  // WAVES
+  lds<T>* tv = reinterpret_cast<lds<T>*>(scr + align16(WAVES * KB * (int)sizeof(T)) + 8 * WAVES);   // KB
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = blockIdx.x; i < L; i += gridDim.x) {
+    const int64_t prow = pool_row(idx[i], m);
+    const gbl<T>* a = A + prow * lda;
+    T acc[KB];
+#pragma unroll
+    for (int c = 0; c < KB; ++c) acc[c] = 0;
+    double sa = 0.0;
+    for (int64_t j0 = (int64_t)VN * tid; j0 < n; j0 += (int64_t)VN * NT) {
+      T av[VN];
+      if (j0 + VN <= n) {
+        vload_g<T>(a + j0, av);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VN; ++e) av[e] = (j0 + e < n) ? a[j0 + e] : (T)0;
+      }
+#pragma unroll
+      for (int e = 0; e < VN; ++e) {
+        const int64_t j = (j0 + e < n) ? j0 + e : n - 1;  // av[e] = 0 past n
+        T z[KB];
+#pragma unroll
+        for (int q = 0; q < KB / VN; ++q) vload_g<T>(Zin + j * KB + q * VN, z + q * VN);
+#pragma unroll
+        for (int c = 0; c < KB; ++c) acc[c] += av[e] * z[c];
+        sa += (double)av[e] * (double)av[e];
+      }
+    }
+#pragma unroll
+    for (int st = 0; (KB >> st) > 1; ++st) {
+      const int h = KB >> (st + 1), o = 32 >> st;
+      const bool up = (lane & o) != 0;
+#pragma unroll
+      for (int q = 0; q < h; ++q) {
+        const T keep = up ? acc[q + h] : acc[q];
+        const T send = up ? acc[q] : acc[q + h];
+        acc[q] = keep + __shfl_xor(send, o, 64);
+      }
+    }
+    const T colsum = group_sum<GL>(acc[0]);  // column lane / GL of this wave's partial
+    if (lane % GL == 0) wsum[wave * KB + lane / GL] = colsum;
+    sa = wave_sum(sa);
+    if (lane == 0) sred[wave] = sa;
+    __syncthreads();
+    if (tid < KB) {
+      T s = 0;
+#pragma unroll
+      for (int w = 0; w < WAVES; ++w) s += wsum[w * KB + tid];
+      tv[tid] = s;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double w;
+      if (first) {
+        double na = 0.0;
+#pragma unroll
+        for (int q = 0; q < WAVES; ++q) na += sred[q];
+        double vl = 0.0;  // (a_i^T V)_l = sum_c t_c Wb[c][l]
+        if (lane < r)
+#pragma unroll 4
+          for (int c = 0; c < KB; ++c) vl += (double)tv[c] * ctl->Wb[c * KB + lane];
+        const double dl = (lane < r) ? ctl->d[lane] : 0.0;
+        const double x = ctl->alpha * na + wave_sum(dl * vl * vl);
+        w = x - (double)bq[prow];
+        if (lane == 0) {
+          qw[i] = w;
+          qn[i] = na;
+        }
+      } else {
+        w = qw[i];
+      }
+      if (lane < KB) qy[(int64_t)i * KB + lane] = (T)((w / (double)L) * (double)tv[lane]);
+    }
+    __syncthreads();  // the scratch is reused by the next row
+  }
+}
+
+// v_mfma_{f32,f64}_16x16x4: A lane l holds A[l % 16][l / 16], B lane l holds
+// B[l / 16][l % 16]; result register v of lane l is row mfma16_row(l / 16, v),
+// column l % 16.
+template <typename T>
+__device__ __forceinline__ int mfma16_row(int kq, int v) {
+  if constexpr (sizeof(T) == 8) return kq + 4 * v;
+  else return 4 * kq + v;
+}
+
+// Minibatch Gram matrix K = A_B A_B^T (sweep 1): 16 x 16 tiles (I, J), I <= J,
+// spread over the workgroups; each wave takes every WAVES-th K chunk of the
+// contraction, the waves' tiles are summed in a fixed order, and both K_IJ
+// and K_JI are stored.  A lane reads 16 contiguous bytes of its row per
+// chunk; within a chunk the K = 4 products take its elements in turn, the
+// same permutation of columns for both operands.
+template <typename T, int NT>
+__device__ __noinline__ void factor_gram(int64_t n, int64_t lda, int64_t m, int L, const gbl<T>* __restrict__ A,
+                                         const gbl<int>* __restrict__ idx, gbl<T>* __restrict__ qk, lds<T>* red) {
+  constexpr int VN = V16<T>::N;
+  constexpr int CW = 4 * VN;  // columns per chunk
+  constexpr int WAVES = NT / 64;
+  using AccT = typename std::conditional<sizeof(T) == 8, f64x4_t, f32x4_t>::type;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  const int nt = (L + 15) / 16;
+  const int ntiles = nt * (nt + 1) / 2;
+  const int64_t nch = (n + CW - 1) / CW;
+  for (int tau = blockIdx.x; tau < ntiles; tau += gridDim.x) {
+    int I = 0, rem = tau;
+    while (rem >= nt - I) {
+      rem -= nt - I;
+      ++I;
+    }
+    const int J = I + rem;
+    const int ri = 16 * I + li, rj = 16 * J + li;
+    const T mi = ri < L ? (T)1 : (T)0, mj = rj < L ? (T)1 : (T)0;
+    const gbl<T>* pa = A + pool_row(idx[ri < L ? ri : 0], m) * lda;
+    const gbl<T>* pb = A + pool_row(idx[rj < L ? rj : 0], m) * lda;
+    AccT acc = {};
+    for (int64_t ch = wave; ch < nch; ch += WAVES) {
+      const int64_t k0 = ch * CW + VN * kq;
+      T va[VN], vb[VN];
+      if (ch * CW + CW <= n) {
+        vload_g<T>(pa + k0, va);
+        vload_g<T>(pb + k0, vb);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VN; ++e) {
+          va[e] = (k0 + e < n) ? pa[k0 + e] : (T)0;
+          vb[e] = (k0 + e < n) ? pb[k0 + e] : (T)0;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < VN; ++e) {
+        if constexpr (sizeof(T) == 8)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[e] * mi, vb[e] * mj, acc, 0, 0, 0);
+        else
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(va[e] * mi, vb[e] * mj, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave * 256 + mfma16_row<T>(kq, v) * 16 + li] = acc[v];
+    __syncthreads();
+    for (int e = tid; e < 256; e += NT) {
+      T s = 0;
+#pragma unroll
+      for (int w = 0; w < WAVES; ++w) s += red[w * 256 + e];
+      const int gi = 16 * I + e / 16, gj = 16 * J + e % 16;
+      if (gi < L && gj < L) {
+        qk[(int64_t)gi * L + gj] = s;
+        if (I != J) qk[(int64_t)gj * L + gi] = s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Upper bound on lambda_max(G) for the shift (see above), from K, w and
+// ||a_i||^2; all threads of one workgroup, every thread gets the result.
+template <typename T, int NT>
+__device__ __noinline__ double factor_shift(int64_t n, int L, double unit_round, const gbl<T>* __restrict__ qk,
+                                            const gbl<double>* __restrict__ qw, const gbl<double>* __restrict__ qn,
+                                            lds<double>* s) {
+  constexpr int WAVES = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  lds<double>* sw = s;         // sqrt(w_i+)
+  lds<double>* sv = s + L;     // ||a_i|| sqrt(w_i+)
+  lds<double>* misc = s + 2 * L;
+  for (int i = tid; i < L; i += NT) {
+    const double wp = sqrt(fmax(qw[i], 0.0));
+    sw[i] = wp;
+    sv[i] = sqrt(qn[i]) * wp;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    double a = 0.0;
+    for (int i = lane; i < L; i += 64) a += sv[i];
+    a = wave_sum(a);
+    if (lane == 0) misc[0] = a;
+  }
+  __syncthreads();
+  const double S = misc[0];
+  const double gam = 2.0 * (double)n * unit_round;  // |fl(K_ij) - K_ij| <= gam ||a_i|| ||a_j||
+  double mx = 0.0;
+  for (int i = tid; i < L; i += NT) {
+    if (sw[i] > 0.0) {
+      const gbl<T>* row = qk + (int64_t)i * L;
+      double acc = 0.0;
+#pragma unroll 16
+      for (int j = 0; j < L; ++j) acc += fabs((double)row[j]) * sw[j];
+      mx = fmax(mx, sw[i] * (acc + gam * sqrt(qn[i]) * S));
+    }
+  }
+  mx = wave_max(mx);
+  if (lane == 0) misc[1 + wave] = mx;
+  __syncthreads();
+  double g = 0.0;
+#pragma unroll
+  for (int w = 0; w < WAVES; ++w) g = fmax(g, misc[1 + w]);
+  return g / (double)L;
+}
+
+// Phase 2 of a factored apply for the rows row0 .. row0 + ROWS - 1:
+// out[j][c] = sum_i a_i[row0 + j] y_i[c].  Thread (slice sl, row j) takes
+// the minibatch rows i = sl (mod NT / ROWS); a wave's load covers two
+// contiguous ROWS-element pieces of two pool rows.  The y_i are staged in LDS
+// in chunks; the slices are summed in a fixed order.
+template <typename T, int KB, int ROWS, int NT>
+__device__ __noinline__ void factor_cols(int64_t n, int64_t lda, int64_t m, int L, const gbl<T>* __restrict__ A,
+                                         const gbl<int>* __restrict__ idx, const gbl<T>* __restrict__ qy,
+                                         int64_t row0, lds<T>* out, lds<char>* scr) {
+  static_assert(ROWS == 32, "two slices per wave");
+  constexpr int SL = NT / ROWS;
+  constexpr int CH = kFacChunk;
+  constexpr int WAVES = NT / 64;
+  lds<T>* ys = reinterpret_cast<lds<T>*>(scr);                                     // CH x KB
+  lds<int64_t>* is = reinterpret_cast<lds<int64_t>*>(scr + CH * KB * (int)sizeof(T));  // CH pool offsets
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = tid % ROWS, sl = tid / ROWS;
+  const bool rowok = row0 + j < n;
+  const int64_t col = rowok ? row0 + j : 0;
+  const T msk = rowok ? (T)1 : (T)0;
+  T acc[KB];
+#pragma unroll
+  for (int c = 0; c < KB; ++c) acc[c] = 0;
+  for (int i0 = 0; i0 < L; i0 += CH) {
+    const int cnt = (L - i0 < CH) ? L - i0 : CH;
+    __syncthreads();
+    for (int e = tid; e < cnt * KB; e += NT) ys[e] = qy[(int64_t)i0 * KB + e];
+    for (int e = tid; e < cnt; e += NT) is[e] = pool_row(idx[i0 + e], m) * lda;
+    __syncthreads();
+    int ii = sl;
+    for (; ii + 3 * SL < cnt; ii += 4 * SL) {
+      T a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = A[is[ii + u * SL] + col] * msk;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < KB; ++c) acc[c] += a[u] * ys[(ii + u * SL) * KB + c];
+    }
+    for (; ii < cnt; ii += SL) {
+      const T a = A[is[ii] + col] * msk;
+#pragma unroll
+      for (int c = 0; c < KB; ++c) acc[c] += a * ys[ii * KB + c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < KB; ++c) acc[c] += __shfl_xor(acc[c], 32, 64);  // slices 2w and 2w + 1
+  __syncthreads();
+  lds<T>* red = reinterpret_cast<lds<T>*>(scr);  // WAVES x ROWS x KB
+  if (lane < 32)
+#pragma unroll
+    for (int c = 0; c < KB; ++c) red[(wave * ROWS + j) * KB + c] = acc[c];
+  __syncthreads();
+  for (int e = tid; e < ROWS * KB; e += NT) {
+    T s = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) s += red[w * ROWS * KB + e];
+    out[e] = s;
   }
 }
 
@@ -585,6 +928,9 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
           for (int v = 0; v < VN; ++v) tb[SM::T_U + (wave * RPW + q) * KB + sub * VN + v] = acc[q][v];
         }
       }
+    } else if constexpr (OPK == OP_FACTOR) {
+      factor_cols<T, KB, ROWS, NT>(n, cfg.lda, cfg.m, cfg.batch, (const gbl<T>*)dat.A, (const gbl<int>*)dat.bidx,
+                                   (const gbl<T>*)dat.qy, row0, (lds<T>*)(tb + SM::T_U), xs);
     } else if constexpr (OPK == OP_DENSE_X3) {
       static_assert(ROWS == 64, "two 32-row tiles per block");
       static_assert(sizeof(T) == 4, "float state");
@@ -783,7 +1129,8 @@ __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Dat
   static_assert(!CACHE || OPK == OP_CSR, "the LDS cache holds CSR data");
   constexpr int DENSE_STAGE = (OPK == OP_DENSE) ? (64 * (KB + 1) * (int)sizeof(T) + 7) / 8 : 0;
   __shared__ double smem[SM::TOTAL + DENSE_STAGE];
-  __shared__ __attribute__((aligned(16))) char xstage[OPK == OP_DENSE_X3 ? kX3StageBytes : 16];
+  __shared__ __attribute__((aligned(16))) char xstage[OPK == OP_DENSE_X3 ? kX3StageBytes
+                                                      : (OPK == OP_FACTOR ? fac_stage_bytes<T, KB>() : 16)];
   extern __shared__ __attribute__((aligned(16))) char dyn[];  // CSR cache (CACHE)
   const int tid = threadIdx.x;
 
@@ -811,6 +1158,11 @@ __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Dat
     const int o1 = (src + 1) % 3, o2 = (src + 2) % 3;
     const T* Bm = zbuf(Z0, Z1, Z2, src);
     const T* gvals = masked ? g : dat.val;
+    Data<T> dstep = dat;
+    if constexpr (OPK == OP_FACTOR) {  // this step's minibatch: row (t - 1) mod batch_steps
+      const int64_t bs = cfg.batch_steps;
+      dstep.bidx = dat.bidx + (((t0 - 1) % bs + bs) % bs) * cfg.batch;
+    }
     for (int s = 1; s <= cfg.max_inner; ++s) {
       const int in = (s == 1) ? src : ((s % 2 == 0) ? o1 : o2);
       const int out = (s % 2 == 1) ? o1 : o2;
@@ -818,6 +1170,28 @@ __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Dat
       T* Zin = zbuf(Z0, Z1, Z2, in);
       T* Zout = zbuf(Z0, Z1, Z2, out);
       stamp_wg(b, s, 0);
+      if constexpr (OPK == OP_FACTOR) {
+        // first pass over the minibatch; in sweep 1 also the residuals and
+        // the Gram matrix, from which the barrier's last arrival sets the shift
+        const bool first = s == 1;
+        factor_rows<T, KB, NT>(cfg.n, cfg.lda, cfg.m, cfg.batch, (const gbl<T>*)dstep.A, (const gbl<T>*)dstep.bq,
+                               (const gbl<int>*)dstep.bidx, (const gbl<T>*)Zin, (gbl<T>*)dstep.qy,
+                               (gbl<double>*)dstep.qw, (gbl<double>*)dstep.qn, (const gbl<Ctl>*)ctl, cfg.r, first,
+                               (lds<char>*)xstage);
+        if (first)
+          factor_gram<T, NT>(cfg.n, cfg.lda, cfg.m, cfg.batch, (const gbl<T>*)dstep.A, (const gbl<int>*)dstep.bidx,
+                             (gbl<T>*)dstep.qk, (lds<T>*)xstage);
+        if (!grid_sync<NT>(b, 0, [&] {
+              if (first) {
+                const double gmax =
+                    factor_shift<T, NT>(cfg.n, cfg.batch, cfg.unit_round, (const gbl<T>*)dstep.qk,
+                                        (const gbl<double>*)dstep.qw, (const gbl<double>*)dstep.qn,
+                                        (lds<double>*)xstage);
+                if (tid < 64) setup_step(cfg, (gbl<Ctl>*)ctl, gmax, tid);
+              }
+            }))
+          return;
+      }
       if constexpr (OPK == OP_CSR) {
         if (grad)
           apply_phase<T, KB, OPK, NT, true, CACHE>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc,
@@ -826,7 +1200,7 @@ __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Dat
           apply_phase<T, KB, OPK, NT, false, CACHE>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc,
                                                     (lds<char>*)xstage);
       } else {
-        apply_phase<T, KB, OPK, NT, false, false>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc,
+        apply_phase<T, KB, OPK, NT, false, false>(cfg, ctl, dstep, gvals, g, Bm, Zin, Zout, b.part, smem, cc,
                                                   (lds<char>*)xstage);
       }
       stamp_wg(b, s, 1);
@@ -1059,6 +1433,75 @@ __global__ __launch_bounds__(256) void k_matvec(Cfg cfg, DenseSrc<T> D, const in
 
 // CSR structure check: 0 = rp[0] <= rp[i] <= rp[i+1] <= rp[n] = nnz and every
 // column index in [0, n).  Row ranges are validated before col is read.
+// objective at X_t, quadratic measurements: 1/(2m) sum_i (a_i^T X a_i - b_i)^2
+// over the whole pool, a_i^T X a_i = alpha ||a_i||^2 + sum_l d_l (a_i^T v_l)^2.
+// Each wave takes MB measurements at a time so that a row of V read once
+// serves all of them; lane partials in the state's type, reductions in FP64.
+template <typename T, int KB>
+__global__ __launch_bounds__(256) void k_objective_quad(Cfg cfg, const Ctl* __restrict__ ctl, const T* __restrict__ A,
+                                                        const T* __restrict__ bq, const T* __restrict__ Z0,
+                                                        const T* __restrict__ Z1, const T* __restrict__ Z2,
+                                                        double* __restrict__ part) {
+  constexpr int MB = sizeof(T) == 4 ? 4 : 2;
+  const T* Qw = zbuf(Z0, Z1, Z2, (ctl->src + 1) % 3);  // written by k_materialize
+  __shared__ double sd[KMAX];
+  __shared__ double sred[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = cfg.r;
+  if (tid < KMAX) sd[tid] = ctl->d[tid];
+  __syncthreads();
+  const double alpha = ctl->alpha;
+  double acc = 0.0;
+  for (int64_t i0 = ((int64_t)blockIdx.x * 4 + wave) * MB; i0 < cfg.m; i0 += (int64_t)gridDim.x * 4 * MB) {
+    T p[MB][KB], sa[MB];
+#pragma unroll
+    for (int u = 0; u < MB; ++u) {
+      sa[u] = 0;
+#pragma unroll
+      for (int l = 0; l < KB; ++l) p[u][l] = 0;
+    }
+    for (int64_t j = lane; j < cfg.n; j += 64) {
+      T v[KB];
+#pragma unroll
+      for (int l = 0; l < KB; ++l) v[l] = (l < r) ? Qw[j * KB + l] : (T)0;
+#pragma unroll
+      for (int u = 0; u < MB; ++u) {
+        const int64_t i = (i0 + u < cfg.m) ? i0 + u : cfg.m - 1;
+        const T a = A[i * cfg.lda + j];
+        sa[u] += a * a;
+#pragma unroll
+        for (int l = 0; l < KB; ++l) p[u][l] += a * v[l];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < MB; ++u) {
+      double x = alpha * wave_sum((double)sa[u]);
+#pragma unroll
+      for (int l = 0; l < KB; ++l)
+        if (l < r) {
+          const double q = wave_sum((double)p[u][l]);
+          x += sd[l] * q * q;
+        }
+      if (i0 + u < cfg.m) {
+        const double res = x - (double)bq[i0 + u];
+        acc += 0.5 * res * res / (double)cfg.m;
+      }
+    }
+  }
+  if (lane == 0) sred[wave] = acc;  // identical in every lane
+  __syncthreads();
+  if (tid == 0) part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
+}
+
+// minibatch indices in [0, m)
+__global__ __launch_bounds__(256) void k_check_idx(const int* __restrict__ idx, int64_t cnt, int64_t m,
+                                                   int* __restrict__ err) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
+    const int v = idx[e];
+    if (v < 0 || (int64_t)v >= m) *err = 1;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_check_csr(const int* __restrict__ rp, const int* __restrict__ col,
                                                    int64_t n, int64_t nnz, int* __restrict__ err) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {

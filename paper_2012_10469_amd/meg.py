@@ -213,22 +213,28 @@ class LowRankMEG:
     """
 
     def __init__(self, n: int, r: int, kind: int, V0, lam0, *, prec: int = MEG_PREC_F32, eta: float = 1.0,
-                 dense=None, dense_lo=None, row_ptr=None, col=None, val=None, oversample: int = 4,
-                 eps=(0.8, 10.0, 2.0), min_inner: int = 1, max_inner: int = 12, inner_tol: float = 0.0,
-                 seed: int = 0, flags: int = 0, cert_tol: float = 0.0, stream: Optional[int] = None):
+                 dense=None, dense_lo=None, row_ptr=None, col=None, val=None, A=None, b=None, batch_idx=None,
+                 oversample: int = 4, eps=(0.8, 10.0, 2.0), min_inner: int = 1, max_inner: int = 12,
+                 inner_tol: float = 0.0, seed: int = 0, flags: int = 0, cert_tol: float = 0.0,
+                 stream: Optional[int] = None):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("LowRankMEG needs a visible GPU")
         self._lib = load_library()
-        self._keep = [dense, dense_lo, row_ptr, col, val]
+        self._keep = [dense, dense_lo, row_ptr, col, val, A, b, batch_idx]
         self.n, self.r = int(n), int(r)
         self.kind = kind
-        obj = MegObjective(kind=kind, batch=0, dense=_dptr(dense), dense_lo=_dptr(dense_lo),
+        # quadratic measurements: A is m x lda (row i = a_i), batch_idx int32
+        # batch_steps x L (step t uses row (t - 1) mod batch_steps)
+        obj = MegObjective(kind=kind, batch=int(batch_idx.shape[1]) if batch_idx is not None else 0,
+                           dense=_dptr(dense), dense_lo=_dptr(dense_lo),
                            ld=int(dense.stride(0)) if dense is not None else 0,
                            row_ptr=_dptr(row_ptr), col=_dptr(col), val=_dptr(val),
                            nnz=int(col.numel()) if col is not None else 0,
-                           A=None, lda=0, b=None, m=0, batch_idx=None, batch_steps=0)
+                           A=_dptr(A), lda=int(A.stride(0)) if A is not None else 0, b=_dptr(b),
+                           m=int(A.shape[0]) if A is not None else 0, batch_idx=_dptr(batch_idx),
+                           batch_steps=int(batch_idx.shape[0]) if batch_idx is not None else 0)
         params = make_params(n, r, prec, eta, oversample, eps, min_inner, max_inner, inner_tol, seed, flags,
                              cert_tol)
         if stream is None:

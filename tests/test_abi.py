@@ -158,6 +158,28 @@ def test_init_rejects_bad_bf16_planes(M):
     assert M.meg_init(p, csr, V, lam)[0] == M.MEG_ERR_UNSUPPORTED
 
 
+def test_init_rejects_bad_quadmeas(M):
+    """Quadratic measurements: pool rows of at least n elements on 16-byte
+    boundaries, 1 <= L <= 1024, at least one minibatch; no bf16-plane form."""
+    n = 64
+    p = M.make_params(n, 4)
+    V, lam = _start(n)
+
+    def q(**kw):
+        base = dict(kind=M.MEG_GRAD_QUADMEAS, A=0x1000, lda=64, b=0x2000, m=100, batch=32, batch_idx=0x3000,
+                    batch_steps=4)
+        base.update(kw)
+        return M.MegObjective(**base)
+
+    for bad in (dict(A=None), dict(b=None), dict(batch_idx=None), dict(m=0), dict(lda=60), dict(lda=66),
+                dict(A=0x1004), dict(batch=0), dict(batch=1025), dict(batch_steps=0)):
+        assert M.meg_init(p, q(**bad), V, lam)[0] == M.MEG_ERR_INVALID_ARG, bad
+    p3 = M.make_params(n, 4, prec=M.MEG_PREC_F32_BF16X3)
+    assert M.meg_init(p3, q(), V, lam)[0] == M.MEG_ERR_UNSUPPORTED
+    p64 = M.make_params(n, 4, prec=M.MEG_PREC_F64)
+    assert M.meg_init(p64, q(lda=65), V, lam)[0] == M.MEG_ERR_INVALID_ARG  # 65 doubles: rows not 16-byte aligned
+
+
 def test_null_context_calls(M):
     lib = M.load_library()
     info = M.MegStepInfo()

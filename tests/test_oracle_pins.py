@@ -401,3 +401,42 @@ def test_factored_diff_resolves_tiny_differences():
         Xa = a * np.eye(n) + (V * d) @ V.T
         Xb = a * np.eye(n) + (V2 * d) @ V2.T
         assert O.factored_diff_frob(V, d, a, V2, d, a) == pytest.approx(np.linalg.norm(Xa - Xb), rel=1e-2)
+
+
+# ---------------------------------------------------------------------------
+# factored forms used at sizes where no n x n matrix is formed: the
+# minibatch residuals without X, and the step through the invariant subspace
+# span[V, F], both against the dense brute force on small n
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,L,q,r", [(23, 5, 2, 3), (40, 12, 3, 3), (30, 40, 4, 5)])
+def test_factored_quadmeas_step_matches_dense(n, L, q, r):
+    rng = np.random.default_rng(11 + n)
+    m = 3 * L
+    A = rng.standard_normal((n, m))
+    F0 = rng.standard_normal((n, 2))
+    F0 /= np.linalg.norm(F0)
+    b = np.sum((F0.T @ A) ** 2, axis=0)
+    obj = O.QuadMeasObjective(A, b)
+    V0, _ = np.linalg.qr(rng.standard_normal((n, q)))
+    lam0 = rng.random(q) + 0.1
+    lam0 /= lam0.sum()
+    it = O.initial_iterate(V0, lam0, O.eps_schedule(0))
+    batch = rng.integers(0, m, size=L)
+    X = it.dense()
+    np.testing.assert_allclose(obj.residuals_factored(it, batch), obj.residuals(X, batch), rtol=1e-12, atol=1e-12)
+    assert obj.value_factored(it) == pytest.approx(obj.value(X), rel=1e-12)
+    eta, eps = 0.3, O.eps_schedule(1)
+    F, c = obj.grad_factor(it, batch)
+    np.testing.assert_allclose((F * c) @ F.T, obj.grad(X, batch), atol=1e-12)
+    for _ in range(3):  # a few steps, each from the brute-force iterate
+        G = obj.grad(it.dense(), batch)
+        ref, ri = O.lowrank_step(it, G, eta, eps, r)
+        F, c = obj.grad_factor(it, batch)
+        got, gi = O.lowrank_step_factored(it, F, c, eta, eps, r)
+        np.testing.assert_allclose(gi["mu"], ri["mu"], atol=1e-10)
+        assert gi["L"] == pytest.approx(ri["L"], abs=1e-10)
+        assert gi["L_full"] == pytest.approx(ri["L_full"], abs=1e-10)
+        assert O.factored_diff_frob(got.V, got.d, got.alpha, ref.V, ref.d, ref.alpha) < 1e-10
+        it = ref
+        batch = rng.integers(0, m, size=L)
+        eps = O.eps_schedule(it.t)

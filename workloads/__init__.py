@@ -393,3 +393,60 @@ def quadmeas_problem(n: int, m: int, seed: int, rank: int = 3, dtype=np.float32)
     proj = F.T @ Af  # rank x m
     b = _round(np.sum(proj * proj, axis=0), dtype)
     return A, b, F
+
+
+def quadmeas_rows(n: int, m: int, seed: int, rank: int = 3, dtype=np.float32, lda: Optional[int] = None):
+    """The pool of ``quadmeas_problem`` in the library's layout: an m x lda
+    array whose row i is a_i (columns n..lda-1 zero), with b and the factor
+    F of X* = F F^T (||F||_F = 1)."""
+    A, b, F = quadmeas_problem(n, m, seed, rank, dtype)
+    lda = n if lda is None else lda
+    rows = np.zeros((m, lda), dtype=A.dtype)
+    rows[:, :n] = A.T
+    return rows, b, F
+
+
+def quadmeas_batches(m: int, L: int, steps: int, seed: int) -> np.ndarray:
+    """Minibatch indices: `steps` rows of L draws, uniform with replacement
+    over the pool (int32)."""
+    return rng(3, 1, seed).integers(0, m, size=(steps, L)).astype(np.int32)
+
+
+def exp_init_quadmeas(rows: np.ndarray, b: np.ndarray, n: int, r: int, seed: int, tau: float = 1.0):
+    """Warm start (Section 7, initialisation equation) for quadratic
+    measurements, with the gradient taken over the given sample of
+    measurements (rows: s x >=n, row i = a_i):
+    -grad f(tau U U^T) = (1/s) sum_i (b_i - tau a_i^T U U^T a_i) a_i a_i^T."""
+    Ar = np.asarray(rows[:, :n], dtype=np.float64)
+    U = _unit_frob_gaussian(n, r, 9300, seed)
+    proj = Ar @ U
+    w = (np.asarray(b, dtype=np.float64) - tau * np.sum(proj * proj, axis=1)) / Ar.shape[0]
+
+    def mv(x):
+        x = np.asarray(x, dtype=np.float64).reshape(-1)
+        return Ar.T @ (w * (Ar @ x))
+
+    return exp_init_from_operator(mv, n, r, tau, seed)
+
+
+def quadmeas_pool_device(n: int, m: int, seed: int, rank: int = 3, chunk: int = 1 << 16):
+    """Full-size pool generated on the GPU (torch's counter-based generator,
+    seeded): A (m x n float32, row i = a_i, standard Gaussian), b_i =
+    a_i^T X* a_i with X* = F F^T, F n x rank Gaussian with ||F||_F = 1 (drawn
+    on the host), b accumulated in float64 and rounded to float32.
+    Returns (A, b, F) with A and b on the device."""
+    import torch
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(int(rng(3, 2, seed).integers(0, 2**62)))
+    F = rng(3, 3, seed).standard_normal((n, rank))
+    F /= np.linalg.norm(F)
+    A = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    b = torch.empty((m,), dtype=torch.float32, device="cuda")
+    Fd = torch.as_tensor(F, dtype=torch.float64, device="cuda")
+    for i0 in range(0, m, chunk):
+        i1 = min(m, i0 + chunk)
+        A[i0:i1].normal_(generator=g)
+        P = A[i0:i1].to(torch.float64) @ Fd
+        b[i0:i1] = (P * P).sum(dim=1).to(torch.float32)
+    return A, b, F
