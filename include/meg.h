@@ -122,10 +122,14 @@ typedef struct {
   const int32_t* col;
   const void* val;
   int64_t nnz;
-  /* QUADMEAS: DEVICE pool A (m rows of length lda >= n: row i is a_i, float
-   * or double), b[m], and the minibatch indices batch_idx[batch_steps * batch]
-   * (int32 in [0, m)); step t uses row (t - 1) mod batch_steps.  The indices
-   * are an input so that a run is reproducible. */
+  /* QUADMEAS: DEVICE pool A (m rows of length lda >= n: row i is a_i, in
+   * the state's type; A 16-byte aligned and lda * sizeof(type) a multiple of
+   * 16), b[m], and the minibatch indices batch_idx[batch_steps * batch]
+   * (int32 in [0, m), checked by meg_init; 1 <= batch <= 1024); step t uses
+   * row (t - 1) mod batch_steps.  The indices are an input so that a run is
+   * reproducible.  F64 and F32 only (the bf16-plane form is dense-only).
+   * Each step also forms the batch x batch Gram matrix of its minibatch to
+   * bound the spectrum of the gradient estimate (the solver's shift). */
   const void* A;
   int64_t lda;
   const void* b;
