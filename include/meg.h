@@ -256,6 +256,102 @@ meg_status meg_get_counters(meg_ctx ctx, meg_counters* out, int32_t reset);
 void meg_destroy(meg_ctx ctx);
 const char* meg_status_str(meg_status s);
 
+/* ---------------------------------------------------------------------------
+ * Batched serving: many independent instances of the dense denoising or
+ * linear objective (Section 1, problem (1); Algorithm 2 for each) advanced
+ * together by one persistent, cooperatively launched kernel.  Each launch
+ * runs every resident instance for up to `launch_steps` iterations on its
+ * own team of workgroups, with its own barrier words and partial sums, so
+ * an instance's arithmetic does not depend on what else is resident: its
+ * result is bitwise the same alone and in a mix.  Between launches the
+ * server retires finished instances (results copied to the host, device
+ * memory returned) and admits queued requests in arrival order as soon as
+ * a free team of workgroups and room in its device arena allow (admission
+ * by memory footprint: the bf16 planes of M, three n x k blocks, the
+ * control block and the reduction buffers).  The operator apply is the
+ * BF16x3 matrix-core form (FP32 state); M is split into its bf16 planes
+ * once, at admission.  The team size per n is chosen by a built-in
+ * autotuner that times the step kernel on a synthetic instance of that n
+ * with each candidate size (the smallest team within 15 % of the fastest).
+ * The solver's shift uses Gershgorin bounds of the planes' matrix (one pass
+ * at admission) instead of the single-instance path's Lanczos estimate.
+ * One host thread at a time per server; all work runs on its stream.
+ * ------------------------------------------------------------------------- */
+typedef struct meg_server_s* meg_server;
+
+typedef struct {
+  int64_t budget_bytes;  /* device arena for resident instances; 0: 4 GiB   */
+  int32_t launch_steps;  /* iterations per instance per launch, 1..1024;
+                            also the admission granularity                 */
+  int32_t max_resident;  /* instances resident at once, 1..256            */
+  uint32_t flags;        /* reserved, 0                                    */
+  int32_t reserved;
+} meg_server_params;
+
+typedef struct {
+  int32_t kind;          /* MEG_GRAD_DENOISE_DENSE or MEG_GRAD_LINEAR_DENSE  */
+  int32_t r;             /* 1 <= r, with r + 1 + oversample <= 16           */
+  int64_t n;             /* 16 <= n <= 32768                               */
+  const float* M;        /* DEVICE n x n row-major FP32 (C or M), leading
+                            dimension ld >= n.  BORROWED until the request
+                            leaves the queue (state >= 1): it is split into
+                            bf16 planes at admission                        */
+  int64_t ld;
+  int32_t q;             /* start columns, 1 <= q <= r                      */
+  int32_t max_iters;     /* iteration cap, >= 1                            */
+  const double* V0;      /* HOST n x q column-major orthonormal; copied     */
+  const double* lambda0; /* HOST q weights >= 0 summing to 1; copied        */
+  double eta;            /* step size > 0                                  */
+  double eps_scale, eps_c, eps_pow; /* as in meg_params                    */
+  double tol;            /* stop after the first step with
+                            max(2 eps_t, cert_L) <= tol (<= 0: never)      */
+  int32_t oversample;    /* p >= 0                                         */
+  int32_t max_inner;     /* subspace sweeps per step, 1..64                 */
+  uint64_t seed;         /* seeds the extra start columns                   */
+} meg_request;
+
+typedef struct {
+  int32_t state;         /* 0 queued, 1 resident, 2 done, 3 failed          */
+  int32_t status;        /* meg_status of a failed request, else MEG_OK      */
+  int64_t iterations;    /* iterations performed                           */
+  double submit_ms;      /* server clock (ms since meg_server_create) at
+                            submission, admission and retirement            */
+  double admit_ms;
+  double done_ms;
+  int32_t team;          /* workgroups of its team (resident or done)       */
+  int32_t reserved;
+  meg_step_info last;    /* last step's info (f = NaN)                      */
+} meg_request_status;
+
+typedef struct {
+  int64_t submitted, completed, failed;
+  int64_t launches;      /* serving-kernel launches                        */
+  int64_t iterations;    /* iterations over all instances                  */
+  double kernel_ms;      /* summed HIP-event time of the serving launches   */
+  int32_t resident, queued;
+  int32_t capacity_wg;   /* co-resident workgroups of the serving kernel    */
+  int32_t reserved;
+  int64_t arena_bytes, arena_used, arena_peak;
+} meg_server_stats;
+
+meg_status meg_server_create(meg_server* out, const meg_server_params* params, void* stream);
+/* Queue a request (validated here); *id identifies it from now on. */
+meg_status meg_server_submit(meg_server s, const meg_request* req, int64_t* id);
+/* `rounds` scheduling rounds: retire finished instances, admit queued
+ * requests, launch the serving kernel once (if anything is resident) and
+ * wait for it.  *pending (optional) = resident + queued requests after. */
+meg_status meg_server_run(meg_server s, int32_t rounds, int32_t* pending);
+meg_status meg_server_query(meg_server s, int64_t id, meg_request_status* out);
+/* Result of a done request: HOST V n x r column-major, d[r], alpha (any may
+ * be NULL), as meg_get_iterate. */
+meg_status meg_server_result(meg_server s, int64_t id, double* V, double* d, double* alpha);
+/* Forget a done or failed request (its host result). */
+meg_status meg_server_release(meg_server s, int64_t id);
+/* Team size the server uses for dimension n (autotuned on first use). */
+meg_status meg_server_team(meg_server s, int64_t n, int32_t* team);
+meg_status meg_server_get_stats(meg_server s, meg_server_stats* out);
+void meg_server_destroy(meg_server s);
+
 #ifdef __cplusplus
 }
 #endif

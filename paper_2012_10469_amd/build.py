@@ -22,8 +22,8 @@ LIB = os.path.join(HERE, "libmeg.so")
 DRIVER = os.path.join(HERE, "meg_bench")
 ARCH = os.environ.get("MEG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["meg_api.hip"]
-HEADERS = ["meg_device.hpp", "meg_small.hpp", "meg_kernels.hpp"]
+SOURCES = ["meg_api.hip", "meg_serve.hip"]
+HEADERS = ["meg_device.hpp", "meg_small.hpp", "meg_kernels.hpp", "meg_host.hpp"]
 
 HIP_FLAGS = [
     "-O3",

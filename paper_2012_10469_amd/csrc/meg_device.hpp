@@ -119,7 +119,7 @@ struct Ctl {
 // Scratch of the persistent step kernel: per-workgroup partial sums, their
 // reduction, and the grid barrier words.
 struct Bufs {
-  double* part;     // gridDim.x x plen partial sums (FP64)
+  double* part;     // (workgroups of the team) x plen partial sums (FP64)
   double* gpart;    // per-barrier-group sums of the partials (FP64)
   double* sums;     // plen reduced sums
   unsigned* bar;    // barrier words, one 128-byte line each (see grid_sync)
@@ -139,7 +139,7 @@ constexpr int kBarWords = kBarGroup0 + kBarStride * kBarMaxGroups;
 // Phase timestamps (device wall clock) of a profiled launch: slots
 // [0, kTsWg) are stamped by one workgroup at phase boundaries; from kTsWg on,
 // every workgroup stamps the start of sweeps 1-2 and its arrival at their
-// barriers: ts[kTsWg + (2 (s - 1) + e) * gridDim.x + wg], e = 0 start, 1 arrival.
+// barriers: ts[kTsWg + (2 (s - 1) + e) * nwg + wg], e = 0 start, 1 arrival.
 constexpr int kTsRR = 140;  // 5 slots: parts of the first Rayleigh-Ritz sweep
 constexpr int kTsWg = 160;
 constexpr int kTsWgSweeps = 2;
@@ -215,7 +215,15 @@ __device__ __noinline__ void reduce_top(const gbl<double>* gpart, gbl<double>* s
   }
 }
 
-// Grid-wide barrier for a cooperatively launched grid (gridDim.x <= 1024).
+// The workgroups that run one instance: this workgroup's rank and their
+// count.  A single-instance launch is one team (blockIdx.x, gridDim.x); the
+// batched kernel splits its grid into one team per resident instance.
+struct Team {
+  int wg, nwg;
+};
+__device__ __forceinline__ Team grid_team() { return Team{(int)blockIdx.x, (int)gridDim.x}; }
+
+// Barrier over one team of a cooperatively launched grid (<= 1024 workgroups).
 // Arrivals are counted in two levels (groups of kBarGroupSize workgroups,
 // then the groups) so that no counter sees more than ~32 contending atomics.
 // Every workgroup's writes before the barrier are visible to every workgroup
@@ -231,13 +239,13 @@ __device__ __noinline__ void reduce_top(const gbl<double>* gpart, gbl<double>* s
 // gpart, the last group adds the group sums (in group order).  The order is
 // fixed, so the sums are bitwise reproducible.  All threads call it.
 template <int NT, typename F>
-__device__ __forceinline__ bool grid_sync(const Bufs& b, int plen, F&& serial) {
+__device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& serial) {
   __shared__ int s_role;  // 0: plain arrival, 1: last of its group, 2: last overall
   __shared__ unsigned s_gen;
   __shared__ int s_ok;
   const int tid = threadIdx.x;
-  const unsigned P = gridDim.x;
-  const unsigned g = blockIdx.x / kBarGroupSize;
+  const unsigned P = (unsigned)tm.nwg;
+  const unsigned g = (unsigned)tm.wg / kBarGroupSize;
   const unsigned ng = (P + kBarGroupSize - 1) / kBarGroupSize;
   const unsigned g0 = g * kBarGroupSize;
   const unsigned gsize = min((unsigned)kBarGroupSize, P - g0);
@@ -300,8 +308,8 @@ __device__ __forceinline__ bool grid_sync(const Bufs& b, int plen, F&& serial) {
 }
 
 template <int NT>
-__device__ __forceinline__ bool grid_sync(const Bufs& b) {
-  return grid_sync<NT>(b, 0, [] {});
+__device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm) {
+  return grid_sync<NT>(b, tm, 0, [] {});
 }
 
 __device__ __forceinline__ double eps_at(const Cfg& cfg, int64_t t) {

@@ -157,17 +157,17 @@ struct CsrCache {
   lds<T>* gv;
 };
 
-// Fill the cache at the start of a launch: the row blocks blockIdx.x,
-// blockIdx.x + gridDim.x, ... in order, their entries contiguous.  Rows past
+// Fill the cache at the start of a launch: the row blocks tm.wg,
+// tm.wg + tm.nwg, ... in order, their entries contiguous.  Rows past
 // n are empty.  All threads call it; ends with a workgroup barrier.
 template <typename T, int ROWS, int NT>
-__device__ void load_csr_cache(const Cfg& cfg, const Data<T>& dat, const CsrCache<T>& cc) {
+__device__ void load_csr_cache(const Cfg& cfg, const Data<T>& dat, const CsrCache<T>& cc, Team tm) {
   const int tid = threadIdx.x;
   const int64_t n = cfg.n;
   const int64_t nblk = (n + ROWS - 1) / ROWS;
   int off = 0;  // cache position of the current block's first entry
   int jb = 0;
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x, ++jb) {
+  for (int64_t blk = tm.wg; blk < nblk; blk += tm.nwg, ++jb) {
     const int64_t row0 = blk * ROWS;
     const int64_t rend = (row0 + ROWS < n) ? row0 + ROWS : n;
     const int base = dat.rp[row0];
@@ -430,7 +430,7 @@ __device__ __forceinline__ void vload_g(const gbl<T>* p, T* out) {
   }
 }
 
-// Phase 1 of a factored apply, minibatch rows i = blockIdx.x, + gridDim.x, ...
+// Phase 1 of a factored apply, minibatch rows i = wg, wg + nwg, ...
 // t_i = a_i^T Zin (KB values) is accumulated by all threads over their
 // elements of a_i, reduced within each wave by a transposing butterfly
 // (each step halves the values a lane carries, so a wave needs KB - 1
@@ -440,7 +440,7 @@ __device__ __noinline__ void factor_rows(int64_t n, int64_t lda, int64_t m, int 
                                          const gbl<T>* __restrict__ bq, const gbl<int>* __restrict__ idx,
                                          const gbl<T>* __restrict__ Zin, gbl<T>* __restrict__ qy,
                                          gbl<double>* __restrict__ qw, gbl<double>* __restrict__ qn,
-                                         const gbl<Ctl>* ctl, int r, bool first, lds<char>* scr) {
+                                         const gbl<Ctl>* ctl, int r, bool first, lds<char>* scr, int wg, int nwg) {
   constexpr int VN = V16<T>::N;
   constexpr int WAVES = NT / 64;
   constexpr int GL = 64 / KB;  // lanes that share a column after the butterfly
@@ -448,7 +448,7 @@ __device__ __noinline__ void factor_rows(int64_t n, int64_t lda, int64_t m, int 
   lds<double>* sred = reinterpret_cast<lds<double>*>(scr + align16(WAVES * KB * (int)sizeof(T)));  // WAVES
   lds<T>* tv = reinterpret_cast<lds<T>*>(scr + align16(WAVES * KB * (int)sizeof(T)) + 8 * WAVES);   // KB
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = blockIdx.x; i < L; i += gridDim.x) {
+  for (int i = wg; i < L; i += nwg) {
     const int64_t prow = pool_row(idx[i], m);
     const gbl<T>* a = A + prow * lda;
     T acc[KB];
@@ -540,7 +540,8 @@ __device__ __forceinline__ int mfma16_row(int kq, int v) {
 // same permutation of columns for both operands.
 template <typename T, int NT>
 __device__ __noinline__ void factor_gram(int64_t n, int64_t lda, int64_t m, int L, const gbl<T>* __restrict__ A,
-                                         const gbl<int>* __restrict__ idx, gbl<T>* __restrict__ qk, lds<T>* red) {
+                                         const gbl<int>* __restrict__ idx, gbl<T>* __restrict__ qk, lds<T>* red,
+                                         int wg, int nwg) {
   constexpr int VN = V16<T>::N;
   constexpr int CW = 4 * VN;  // columns per chunk
   constexpr int WAVES = NT / 64;
@@ -550,7 +551,7 @@ __device__ __noinline__ void factor_gram(int64_t n, int64_t lda, int64_t m, int 
   const int nt = (L + 15) / 16;
   const int ntiles = nt * (nt + 1) / 2;
   const int64_t nch = (n + CW - 1) / CW;
-  for (int tau = blockIdx.x; tau < ntiles; tau += gridDim.x) {
+  for (int tau = wg; tau < ntiles; tau += nwg) {
     int I = 0, rem = tau;
     while (rem >= nt - I) {
       rem -= nt - I;
@@ -723,7 +724,7 @@ template <typename T, int KB, int OPK, int NT, bool GRAD, bool CACHE>
 __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, const T* __restrict__ gv,
                             T* __restrict__ gout, const T* __restrict__ B, const T* __restrict__ Zin,
                             T* __restrict__ Zout, double* part, double* smem, const CsrCache<T>& cc,
-                            lds<char>* xs) {
+                            lds<char>* xs, Team tm) {
   using SH = StepShape<T, KB, OPK, NT>;
   constexpr int ROWS = SH::ROWS, RPW = SH::RPW;
   using SM = ApplySmem<T, KB, ROWS, SH::GWROWS>;
@@ -754,7 +755,7 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
   double accg = 0.0, accx = 0.0;  // GRAD: sums of g^2 and X_ij^2 over this lane's nonzeros
   const int64_t nblk = (n + ROWS - 1) / ROWS;
   int jb = 0;  // this workgroup's block counter (cache position)
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x, ++jb) {
+  for (int64_t blk = tm.wg; blk < nblk; blk += tm.nwg, ++jb) {
     const int64_t row0 = blk * ROWS;
     // this block's rows of Zin and B: loads issued now, stored to LDS after
     // the gathers below (their latency overlaps)
@@ -1037,7 +1038,7 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
     }
   }
   __syncthreads();
-  double* dst = part + (size_t)blockIdx.x * SM::PSTRIDE;
+  double* dst = part + (size_t)tm.wg * SM::PSTRIDE;
   for (int e = tid; e < SM::PLEN; e += NT) dst[e] = smem[e];
   if (tid == 0) {
     double sg = 0.0, sx = 0.0;
@@ -1108,9 +1109,9 @@ __device__ __forceinline__ void stamp(const Bufs& b, int slot) {
 }
 
 // per-workgroup stamp of sweep s (1-based), e = 0 start, 1 arrival at its barrier
-__device__ __forceinline__ void stamp_wg(const Bufs& b, int s, int e) {
+__device__ __forceinline__ void stamp_wg(const Bufs& b, Team tm, int s, int e) {
   if (b.ts && threadIdx.x == 0 && s <= kTsWgSweeps)
-    b.ts[kTsWg + (2 * (s - 1) + e) * gridDim.x + blockIdx.x] = wall_clock64();
+    b.ts[kTsWg + (2 * (s - 1) + e) * tm.nwg + tm.wg] = wall_clock64();
 }
 
 // ---------------------------------------------------------------------------
@@ -1120,18 +1121,28 @@ __device__ __forceinline__ void stamp_wg(const Bufs& b, int s, int e) {
 // solve of the step's last sweep also ends the step (next basis, iterate,
 // certificate, step scalars).
 // ---------------------------------------------------------------------------
+// Static LDS of the step: the apply's typed scratch and partials (smem), and
+// the staging area of the matrix-core and factored applies (xstage).
+template <typename T, int KB, int OPK, int NT>
+struct StepLds {
+  using SH = StepShape<T, KB, OPK, NT>;
+  using SM = ApplySmem<T, KB, SH::ROWS, SH::GWROWS>;
+  static constexpr int DENSE_STAGE = (OPK == OP_DENSE) ? (64 * (KB + 1) * (int)sizeof(T) + 7) / 8 : 0;
+  static constexpr int SMEM_DOUBLES = SM::TOTAL + DENSE_STAGE;
+  static constexpr int XSTAGE_BYTES =
+      OPK == OP_DENSE_X3 ? kX3StageBytes : (OPK == OP_FACTOR ? fac_stage_bytes<T, KB>() : 16);
+};
+
+// `nsteps` iterations of one instance by the team `tm` (the body of k_step
+// and of each team of k_serve).
 template <typename T, int KB, int OPK, int NT, bool CACHE>
-__global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Data<T> dat, T* __restrict__ Z0,
-                                             T* __restrict__ Z1, T* __restrict__ Z2, T* __restrict__ g, Bufs b,
-                                             int nsteps) {
+__device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl, const Data<T>& dat,
+                                          T* __restrict__ Z0, T* __restrict__ Z1, T* __restrict__ Z2,
+                                          T* __restrict__ g, const Bufs& b, int nsteps, Team tm, double* smem,
+                                          char* xstage, char* dyn) {
   using SH = StepShape<T, KB, OPK, NT>;
   using SM = ApplySmem<T, KB, SH::ROWS, SH::GWROWS>;
   static_assert(!CACHE || OPK == OP_CSR, "the LDS cache holds CSR data");
-  constexpr int DENSE_STAGE = (OPK == OP_DENSE) ? (64 * (KB + 1) * (int)sizeof(T) + 7) / 8 : 0;
-  __shared__ double smem[SM::TOTAL + DENSE_STAGE];
-  __shared__ __attribute__((aligned(16))) char xstage[OPK == OP_DENSE_X3 ? kX3StageBytes
-                                                      : (OPK == OP_FACTOR ? fac_stage_bytes<T, KB>() : 16)];
-  extern __shared__ __attribute__((aligned(16))) char dyn[];  // CSR cache (CACHE)
   const int tid = threadIdx.x;
 
   const bool masked = cfg.kind == MASKED_CSR;
@@ -1143,11 +1154,11 @@ __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Dat
     cc.val = (lds<T>*)(dyn + L.val);
     cc.g = (lds<T>*)(dyn + L.g);
     cc.gv = masked ? cc.g : cc.val;
-    load_csr_cache<T, SH::ROWS, NT>(cfg, dat, cc);
+    load_csr_cache<T, SH::ROWS, NT>(cfg, dat, cc, tm);
   }
   for (int st = 0; st < nsteps; ++st) {
     if (ldi(&ctl->stop) | ldi(&ctl->status)) break;
-    if (blockIdx.x == 0) {
+    if (tm.wg == 0) {
       stamp(b, 0);
       stamp(b, 1);  // no separate gradient phase: it is part of sweep 1
     }
@@ -1169,7 +1180,7 @@ __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Dat
       const bool grad = masked && s == 1;
       T* Zin = zbuf(Z0, Z1, Z2, in);
       T* Zout = zbuf(Z0, Z1, Z2, out);
-      stamp_wg(b, s, 0);
+      stamp_wg(b, tm, s, 0);
       if constexpr (OPK == OP_FACTOR) {
         // first pass over the minibatch; in sweep 1 also the residuals and
         // the Gram matrix, from which the barrier's last arrival sets the shift
@@ -1177,11 +1188,11 @@ __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Dat
         factor_rows<T, KB, NT>(cfg.n, cfg.lda, cfg.m, cfg.batch, (const gbl<T>*)dstep.A, (const gbl<T>*)dstep.bq,
                                (const gbl<int>*)dstep.bidx, (const gbl<T>*)Zin, (gbl<T>*)dstep.qy,
                                (gbl<double>*)dstep.qw, (gbl<double>*)dstep.qn, (const gbl<Ctl>*)ctl, cfg.r, first,
-                               (lds<char>*)xstage);
+                               (lds<char>*)xstage, tm.wg, tm.nwg);
         if (first)
           factor_gram<T, NT>(cfg.n, cfg.lda, cfg.m, cfg.batch, (const gbl<T>*)dstep.A, (const gbl<int>*)dstep.bidx,
-                             (gbl<T>*)dstep.qk, (lds<T>*)xstage);
-        if (!grid_sync<NT>(b, 0, [&] {
+                             (gbl<T>*)dstep.qk, (lds<T>*)xstage, tm.wg, tm.nwg);
+        if (!grid_sync<NT>(b, tm, 0, [&] {
               if (first) {
                 const double gmax =
                     factor_shift<T, NT>(cfg.n, cfg.batch, cfg.unit_round, (const gbl<T>*)dstep.qk,
@@ -1195,16 +1206,16 @@ __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Dat
       if constexpr (OPK == OP_CSR) {
         if (grad)
           apply_phase<T, KB, OPK, NT, true, CACHE>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc,
-                                                   (lds<char>*)xstage);
+                                                   (lds<char>*)xstage, tm);
         else
           apply_phase<T, KB, OPK, NT, false, CACHE>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc,
-                                                    (lds<char>*)xstage);
+                                                    (lds<char>*)xstage, tm);
       } else {
         apply_phase<T, KB, OPK, NT, false, false>(cfg, ctl, dstep, gvals, g, Bm, Zin, Zout, b.part, smem, cc,
-                                                  (lds<char>*)xstage);
+                                                  (lds<char>*)xstage, tm);
       }
-      stamp_wg(b, s, 1);
-      if (!grid_sync<NT>(b, SM::PSTRIDE, [&] {
+      stamp_wg(b, tm, s, 1);
+      if (!grid_sync<NT>(b, tm, SM::PSTRIDE, [&] {
             stamp(b, 2 * s);
             if (tid < 64) {
               gbl<Ctl>* gc = (gbl<Ctl>*)ctl;
@@ -1239,11 +1250,60 @@ __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Dat
   }
 }
 
+template <typename T, int KB, int OPK, int NT, bool CACHE>
+static __global__ __launch_bounds__(NT) void k_step(Cfg cfg, Ctl* __restrict__ ctl, Data<T> dat, T* __restrict__ Z0,
+                                             T* __restrict__ Z1, T* __restrict__ Z2, T* __restrict__ g, Bufs b,
+                                             int nsteps) {
+  using L = StepLds<T, KB, OPK, NT>;
+  __shared__ double smem[L::SMEM_DOUBLES];
+  __shared__ __attribute__((aligned(16))) char xstage[L::XSTAGE_BYTES];
+  extern __shared__ __attribute__((aligned(16))) char dyn[];  // CSR cache (CACHE)
+  step_loop<T, KB, OPK, NT, CACHE>(cfg, ctl, dat, Z0, Z1, Z2, g, b, nsteps, grid_team(), smem, xstage, dyn);
+}
+
+// One resident instance of the batched step kernel.
+template <typename T>
+struct Slot {
+  Cfg cfg;
+  Ctl* ctl;
+  Data<T> dat;
+  T* Z0;
+  T* Z1;
+  T* Z2;
+  Bufs b;      // its own partials, reduction buffers and barrier words
+  int nwg;     // workgroups of its team
+  int nsteps;  // iterations it runs in this launch (0: none)
+};
+
+// Batched persistent step kernel: the grid is split into teams, one per
+// resident instance; team[w] = (slot, rank) of workgroup w (slot < 0: idle,
+// the workgroup exits).  Each team runs its instance exactly as k_step does
+// on a grid of nwg workgroups, with the instance's own barrier words and
+// partials, so an instance's arithmetic (and its reduction order) does not
+// depend on which other instances are resident.  Launched cooperatively.
+template <typename T, int KB, int OPK, int NT>
+static __global__ __launch_bounds__(NT) void k_serve(const Slot<T>* __restrict__ slots, const int2* __restrict__ team) {
+  using L = StepLds<T, KB, OPK, NT>;
+  __shared__ double smem[L::SMEM_DOUBLES];
+  __shared__ __attribute__((aligned(16))) char xstage[L::XSTAGE_BYTES];
+  const int slot = __builtin_amdgcn_readfirstlane(team[blockIdx.x].x);
+  const int rank = __builtin_amdgcn_readfirstlane(team[blockIdx.x].y);
+  if (slot < 0) return;
+  const Slot<T>* sl = slots + slot;
+  const int nsteps = sl->nsteps;
+  if (nsteps <= 0) return;
+  const Cfg cfg = sl->cfg;
+  const Data<T> dat = sl->dat;
+  const Bufs b = sl->b;
+  step_loop<T, KB, OPK, NT, false>(cfg, sl->ctl, dat, sl->Z0, sl->Z1, sl->Z2, nullptr, b, nsteps,
+                                   Team{rank, sl->nwg}, smem, xstage, nullptr);
+}
+
 // Orthonormalising transform of a freshly uploaded basis B = block `src`
 // (cooperative launch with the step kernel's grid): Gram of B, then Wb = R^-1
 // (B^T B = R^T R), so that Q = B Wb is orthonormal, and the step scalars.
 template <typename T, int KB, int OPK, int NT>
-__global__ __launch_bounds__(NT) void k_basis(Cfg cfg, Ctl* __restrict__ ctl, T* __restrict__ Z0,
+static __global__ __launch_bounds__(NT) void k_basis(Cfg cfg, Ctl* __restrict__ ctl, T* __restrict__ Z0,
                                               T* __restrict__ Z1, T* __restrict__ Z2, Bufs b) {
   using SH = StepShape<T, KB, OPK, NT>;
   using SM = ApplySmem<T, KB, SH::ROWS, SH::GWROWS>;
@@ -1251,7 +1311,7 @@ __global__ __launch_bounds__(NT) void k_basis(Cfg cfg, Ctl* __restrict__ ctl, T*
   const int tid = threadIdx.x;
   const T* Bm = zbuf(Z0, Z1, Z2, ldi(&ctl->src));
   gram_phase<T, KB, SH::GROWS, NT>(cfg, (const gbl<T>*)Bm, (gbl<double>*)b.part, (lds<double>*)smem);
-  grid_sync<NT>(b, KB * KB, [&] {
+  grid_sync<NT>(b, grid_team(), KB * KB, [&] {
     if (tid < 64) {
       basis_setup<KB>(cfg, (gbl<Ctl>*)ctl, (const gbl<double>*)b.sums, (lds<double>*)smem, tid);
       wg_fence();
@@ -1264,7 +1324,7 @@ __global__ __launch_bounds__(NT) void k_basis(Cfg cfg, Ctl* __restrict__ ctl, T*
 // so free between steps): the factored iterate's V = Q[:, :r] in explicit
 // form, for the objective kernels.  One thread per element.
 template <typename T, int KB>
-__global__ __launch_bounds__(256) void k_materialize(Cfg cfg, const Ctl* __restrict__ ctl, T* __restrict__ Z0,
+static __global__ __launch_bounds__(256) void k_materialize(Cfg cfg, const Ctl* __restrict__ ctl, T* __restrict__ Z0,
                                                      T* __restrict__ Z1, T* __restrict__ Z2) {
   const int src = ctl->src;
   const T* Bm = zbuf(Z0, Z1, Z2, src);
@@ -1298,7 +1358,7 @@ struct DenseSrc {
 // X_ij = alpha [i == j] + sum_l V_il d_l V_jl, accumulated in FP64; one wave
 // per row; V from k_materialize
 template <typename T, int KB>
-__global__ __launch_bounds__(256) void k_objective_dense(Cfg cfg, const Ctl* __restrict__ ctl,
+static __global__ __launch_bounds__(256) void k_objective_dense(Cfg cfg, const Ctl* __restrict__ ctl,
                                                          DenseSrc<T> D, const T* __restrict__ Z0,
                                                          const T* __restrict__ Z1, const T* __restrict__ Z2,
                                                          double* __restrict__ part) {
@@ -1334,7 +1394,7 @@ __global__ __launch_bounds__(256) void k_objective_dense(Cfg cfg, const Ctl* __r
 
 // objective at X_t, CSR kinds (LINEAR: sum_Omega C_ij X_ij; MASKED: 1/2 sum_Omega (X_ij - M_ij)^2)
 template <typename T, int KB>
-__global__ __launch_bounds__(256) void k_objective_csr(Cfg cfg, const Ctl* __restrict__ ctl, const int* __restrict__ rp,
+static __global__ __launch_bounds__(256) void k_objective_csr(Cfg cfg, const Ctl* __restrict__ ctl, const int* __restrict__ rp,
                                                        const int* __restrict__ col, const T* __restrict__ val,
                                                        const T* __restrict__ Z0, const T* __restrict__ Z1,
                                                        const T* __restrict__ Z2, double* __restrict__ part) {
@@ -1371,7 +1431,7 @@ __global__ __launch_bounds__(256) void k_objective_csr(Cfg cfg, const Ctl* __res
 
 // sum of squares of a strided matrix (rows x cols, ld) or a vector (rows = 1)
 template <typename T>
-__global__ __launch_bounds__(256) void k_sumsq(DenseSrc<T> x, int64_t rows, int64_t cols, int64_t ld,
+static __global__ __launch_bounds__(256) void k_sumsq(DenseSrc<T> x, int64_t rows, int64_t cols, int64_t ld,
                                                double* __restrict__ part) {
   __shared__ double sred[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1390,7 +1450,7 @@ __global__ __launch_bounds__(256) void k_sumsq(DenseSrc<T> x, int64_t rows, int6
 
 // Sum nwg partials in a fixed order and store: what = 0 -> f (objective),
 // 1 -> data_norm = sqrt(sum).  One workgroup.
-__global__ __launch_bounds__(256) void k_finish(Ctl* __restrict__ ctl, const double* __restrict__ part, int nwg,
+static __global__ __launch_bounds__(256) void k_finish(Ctl* __restrict__ ctl, const double* __restrict__ part, int nwg,
                                                 int what) {
   __shared__ double s[256];
   double a = 0.0;
@@ -1415,7 +1475,7 @@ __global__ __launch_bounds__(256) void k_finish(Ctl* __restrict__ ctl, const dou
 // Used once per context by the Lanczos estimate of the operator's extreme
 // eigenvalues.  One wave per row.
 template <typename T>
-__global__ __launch_bounds__(256) void k_matvec(Cfg cfg, DenseSrc<T> D, const int* __restrict__ rp,
+static __global__ __launch_bounds__(256) void k_matvec(Cfg cfg, DenseSrc<T> D, const int* __restrict__ rp,
                                                 const int* __restrict__ col, const T* __restrict__ val,
                                                 const T* __restrict__ x, double* __restrict__ y) {
   const int lane = threadIdx.x & 63;
@@ -1438,7 +1498,7 @@ __global__ __launch_bounds__(256) void k_matvec(Cfg cfg, DenseSrc<T> D, const in
 // Each wave takes MB measurements at a time so that a row of V read once
 // serves all of them; lane partials in the state's type, reductions in FP64.
 template <typename T, int KB>
-__global__ __launch_bounds__(256) void k_objective_quad(Cfg cfg, const Ctl* __restrict__ ctl, const T* __restrict__ A,
+static __global__ __launch_bounds__(256) void k_objective_quad(Cfg cfg, const Ctl* __restrict__ ctl, const T* __restrict__ A,
                                                         const T* __restrict__ bq, const T* __restrict__ Z0,
                                                         const T* __restrict__ Z1, const T* __restrict__ Z2,
                                                         double* __restrict__ part) {
@@ -1493,8 +1553,95 @@ __global__ __launch_bounds__(256) void k_objective_quad(Cfg cfg, const Ctl* __re
   if (tid == 0) part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
 }
 
+// ---------------------------------------------------------------------------
+// admission kernels of the batched server
+// ---------------------------------------------------------------------------
+// bf16 planes of an FP32 matrix: hi = RNE(x), lo = RNE(x - hi); columns n..ld-1 zero
+static __global__ __launch_bounds__(256) void k_split_bf16(const float* __restrict__ M, int64_t ldm, int64_t n,
+                                                    uint16_t* __restrict__ hi, uint16_t* __restrict__ lo,
+                                                    int64_t ld) {
+  const int64_t total = n * ld;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / ld, j = e % ld;
+    const float x = (j < n) ? M[i * ldm + j] : 0.0f;
+    const unsigned short h = bf16_rne(x);
+    hi[e] = h;
+    lo[e] = bf16_rne(x - bf16_val(h));
+  }
+}
+
+// Gershgorin bounds of the planes' matrix hi + lo: per workgroup the min of
+// a_ii - sum_{j != i} |a_ij| and the max of a_ii + sum_{j != i} |a_ij| over
+// its rows (one wave per row, FP64 sums) -> part[2 wg], part[2 wg + 1]
+static __global__ __launch_bounds__(256) void k_gersh(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo,
+                                               int64_t n, int64_t ld, double* __restrict__ part) {
+  __shared__ double sl[4], sh[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double lmin = __builtin_inf(), lmax = -__builtin_inf();
+  for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < n; i += (int64_t)gridDim.x * 4) {
+    double off = 0.0, dg = 0.0;
+    for (int64_t j = lane; j < n; j += 64) {
+      const double v = (double)bf16_val(hi[i * ld + j]) + (double)bf16_val(lo[i * ld + j]);
+      if (j == i) dg = v; else off += fabs(v);
+    }
+    off = wave_sum(off);
+    dg = wave_sum(dg);
+    lmin = fmin(lmin, dg - off);
+    lmax = fmax(lmax, dg + off);
+  }
+  if (lane == 0) {
+    sl[wave] = lmin;
+    sh[wave] = lmax;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    part[2 * blockIdx.x] = fmin(fmin(sl[0], sl[1]), fmin(sl[2], sl[3]));
+    part[2 * blockIdx.x + 1] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  }
+}
+
+static __global__ __launch_bounds__(64) void k_gersh_finish(Ctl* __restrict__ ctl, const double* __restrict__ part,
+                                                     int nwg) {
+  double lmin = __builtin_inf(), lmax = -__builtin_inf();
+  for (int w = threadIdx.x; w < nwg; w += 64) {
+    lmin = fmin(lmin, part[2 * w]);
+    lmax = fmax(lmax, part[2 * w + 1]);
+  }
+  lmin = wave_min(lmin);
+  lmax = wave_max(lmax);
+  if (threadIdx.x == 0) {
+    ctl->op_lmin = lmin;
+    ctl->op_lmax = lmax;
+  }
+}
+
+// What the server reads back after a launch, per slot.
+struct SlotSummary {
+  int64_t t;
+  int32_t stop, status;
+  int32_t barerr, reserved;  // the team's barrier error flag
+  Info info;
+};
+
+template <typename T>
+static __global__ __launch_bounds__(256) void k_serve_summary(const Slot<T>* __restrict__ slots, int nslots,
+                                                       SlotSummary* __restrict__ out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nslots) return;
+  const Ctl* c = slots[i].ctl;
+  if (!c) return;
+  SlotSummary s;
+  s.t = c->t;
+  s.stop = c->stop;
+  s.status = c->status;
+  s.barerr = (int32_t)slots[i].b.bar[kBarErr];
+  s.reserved = 0;
+  s.info = c->info;
+  out[i] = s;
+}
+
 // minibatch indices in [0, m)
-__global__ __launch_bounds__(256) void k_check_idx(const int* __restrict__ idx, int64_t cnt, int64_t m,
+static __global__ __launch_bounds__(256) void k_check_idx(const int* __restrict__ idx, int64_t cnt, int64_t m,
                                                    int* __restrict__ err) {
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * 256) {
     const int v = idx[e];
@@ -1502,7 +1649,7 @@ __global__ __launch_bounds__(256) void k_check_idx(const int* __restrict__ idx, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_check_csr(const int* __restrict__ rp, const int* __restrict__ col,
+static __global__ __launch_bounds__(256) void k_check_csr(const int* __restrict__ rp, const int* __restrict__ col,
                                                    int64_t n, int64_t nnz, int* __restrict__ err) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     const int64_t a = rp[i], b = rp[i + 1];

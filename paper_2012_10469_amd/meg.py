@@ -47,6 +47,8 @@ EXPORTED = [
     "meg_block_size", "meg_init", "meg_step", "meg_solve", "meg_certificate", "meg_objective_value",
     "meg_get_iterate", "meg_set_iterate", "meg_get_state", "meg_set_state", "meg_profile_step", "meg_destroy",
     "meg_status_str", "meg_get_counters",
+    "meg_server_create", "meg_server_submit", "meg_server_run", "meg_server_query", "meg_server_result",
+    "meg_server_release", "meg_server_team", "meg_server_get_stats", "meg_server_destroy",
 ]
 
 
@@ -102,6 +104,36 @@ class MegCounters(ctypes.Structure):
                 ("workgroups", ctypes.c_int32), ("reserved", ctypes.c_int32), ("kernel_ms", ctypes.c_double)]
 
 
+class MegServerParams(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("launch_steps", ctypes.c_int32),
+                ("max_resident", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+class MegRequest(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("r", ctypes.c_int32), ("n", ctypes.c_int64), ("M", ctypes.c_void_p),
+        ("ld", ctypes.c_int64), ("q", ctypes.c_int32), ("max_iters", ctypes.c_int32),
+        ("V0", ctypes.POINTER(ctypes.c_double)), ("lambda0", ctypes.POINTER(ctypes.c_double)),
+        ("eta", ctypes.c_double), ("eps_scale", ctypes.c_double), ("eps_c", ctypes.c_double),
+        ("eps_pow", ctypes.c_double), ("tol", ctypes.c_double), ("oversample", ctypes.c_int32),
+        ("max_inner", ctypes.c_int32), ("seed", ctypes.c_uint64),
+    ]
+
+
+class MegRequestStatus(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("iterations", ctypes.c_int64),
+                ("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double), ("done_ms", ctypes.c_double),
+                ("team", ctypes.c_int32), ("reserved", ctypes.c_int32), ("last", MegStepInfo)]
+
+
+class MegServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("iterations", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
+                ("resident", ctypes.c_int32), ("queued", ctypes.c_int32), ("capacity_wg", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("arena_bytes", ctypes.c_int64), ("arena_used", ctypes.c_int64),
+                ("arena_peak", ctypes.c_int64)]
+
+
 _lib: Optional[ctypes.CDLL] = None
 
 
@@ -132,6 +164,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "meg_get_counters": (ctypes.c_int, [vp, P(MegCounters), ctypes.c_int32]),
         "meg_destroy": (None, [vp]),
         "meg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+        "meg_server_create": (ctypes.c_int, [P(vp), P(MegServerParams), vp]),
+        "meg_server_submit": (ctypes.c_int, [vp, P(MegRequest), P(ctypes.c_int64)]),
+        "meg_server_run": (ctypes.c_int, [vp, ctypes.c_int32, P(ctypes.c_int32)]),
+        "meg_server_query": (ctypes.c_int, [vp, ctypes.c_int64, P(MegRequestStatus)]),
+        "meg_server_result": (ctypes.c_int, [vp, ctypes.c_int64, P(ctypes.c_double), P(ctypes.c_double),
+                                             P(ctypes.c_double)]),
+        "meg_server_release": (ctypes.c_int, [vp, ctypes.c_int64]),
+        "meg_server_team": (ctypes.c_int, [vp, ctypes.c_int64, P(ctypes.c_int32)]),
+        "meg_server_get_stats": (ctypes.c_int, [vp, P(MegServerStats)]),
+        "meg_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -327,6 +369,108 @@ class LowRankMEG:
             self._lib.meg_destroy(self._ctx)
             self._ctx = None
         self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class MegServer:
+    """Batched server (meg_server_* of the C ABI) on its own HIP stream.
+
+    ``submit`` takes a device FP32 matrix (torch tensor, n x n, row-major),
+    borrowed until the request is admitted; the start (V0, lam0) is host
+    data.  ``run(rounds)`` performs scheduling rounds (retire, admit, one
+    launch of the batched kernel) and returns the number of pending requests.
+    """
+
+    def __init__(self, budget_bytes: int = 0, launch_steps: int = 8, max_resident: int = 256,
+                 stream: Optional[int] = None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("MegServer needs a visible GPU")
+        self._lib = load_library()
+        if stream is None:
+            self._torch_stream = torch.cuda.Stream()
+            stream = self._torch_stream.cuda_stream
+        self.stream = stream
+        p = MegServerParams(budget_bytes=int(budget_bytes), launch_steps=int(launch_steps),
+                            max_resident=int(max_resident), flags=0, reserved=0)
+        h = ctypes.c_void_p()
+        _check(self._lib.meg_server_create(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(stream)),
+               "meg_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, M, V0, lam0, r: int, *, kind: int = MEG_GRAD_DENOISE_DENSE, eta: float = 1.0,
+               eps=(0.8, 10.0, 2.0), tol: float = 0.0, max_iters: int = 300, max_inner: int = 12,
+               oversample: int = 4, seed: int = 0) -> int:
+        V0 = np.asarray(V0, dtype=np.float64)
+        if V0.ndim == 1:
+            V0 = V0[:, None]
+        Vc = np.asfortranarray(V0)
+        lam = _f64(lam0)
+        n = int(M.shape[0])
+        req = MegRequest(kind=kind, r=int(r), n=n, M=_dptr(M), ld=int(M.stride(0)), q=int(Vc.shape[1]),
+                         max_iters=int(max_iters), V0=Vc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         lambda0=_dblp(lam), eta=float(eta), eps_scale=eps[0], eps_c=eps[1], eps_pow=eps[2],
+                         tol=float(tol), oversample=int(oversample), max_inner=int(max_inner), seed=int(seed))
+        rid = ctypes.c_int64()
+        _check(self._lib.meg_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)), "meg_server_submit")
+        self._keep[rid.value] = M  # borrowed until admitted
+        return rid.value
+
+    def run(self, rounds: int = 1) -> int:
+        pend = ctypes.c_int32()
+        _check(self._lib.meg_server_run(self._h, int(rounds), ctypes.byref(pend)), "meg_server_run")
+        for rid in list(self._keep):
+            if self.query(rid)["state"] >= 1:
+                del self._keep[rid]
+        return pend.value
+
+    def query(self, rid: int) -> dict:
+        st = MegRequestStatus()
+        _check(self._lib.meg_server_query(self._h, int(rid), ctypes.byref(st)), "meg_server_query")
+        out = {name: getattr(st, name) for name, _ in st._fields_ if name not in ("reserved", "last")}
+        out["last"] = st.last.as_dict()
+        return out
+
+    def result(self, rid: int, n: int, r: int):
+        """(V n x r, d, alpha) of a done request."""
+        V = np.zeros((r, n), dtype=np.float64)
+        d = np.zeros(r)
+        a = ctypes.c_double()
+        _check(self._lib.meg_server_result(self._h, int(rid), _dblp(V), _dblp(d), ctypes.byref(a)),
+               "meg_server_result")
+        return V.T.copy(), d, a.value
+
+    def release(self, rid: int) -> None:
+        _check(self._lib.meg_server_release(self._h, int(rid)), "meg_server_release")
+
+    def team(self, n: int) -> int:
+        t = ctypes.c_int32()
+        _check(self._lib.meg_server_team(self._h, int(n), ctypes.byref(t)), "meg_server_team")
+        return t.value
+
+    def stats(self) -> dict:
+        st = MegServerStats()
+        _check(self._lib.meg_server_get_stats(self._h, ctypes.byref(st)), "meg_server_get_stats")
+        return {name: getattr(st, name) for name, _ in st._fields_ if name != "reserved"}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.meg_server_destroy(self._h)
+            self._h = None
+        self._keep = {}
 
     def __del__(self):
         try:

@@ -68,3 +68,19 @@ def f_tol(f_ref: float, gradnorm_f: float, xnorm_f: float, prec: int) -> float:
 def oracle_state_at(run, t):
     """Oracle iterate X_t (t >= 1)."""
     return run["states"][t - 1]
+
+
+def gapped_spiked(n, rank, seed, noise=0.01):
+    """M = U diag(2, 1.8, ...) U^T + noise (G + G^T)/sqrt(2n) (rank <= 5,
+    strictly complementary at r = rank), with its top-`rank` eigenvectors as
+    the start."""
+    rng = np.random.default_rng([78, seed, n])
+    U, _ = np.linalg.qr(rng.standard_normal((n, rank)))
+    s = 2.0 - 0.2 * np.arange(rank)
+    G = rng.standard_normal((n, n))
+    M = (U * s) @ U.T + noise * (G + G.T) / math.sqrt(2 * n)
+    M = 0.5 * (M + M.T)
+    w, V = np.linalg.eigh(M)
+    V0 = V[:, ::-1][:, :rank].copy()
+    lam0 = np.full(rank, 1.0 / rank)
+    return M, V0, lam0

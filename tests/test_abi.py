@@ -60,6 +60,13 @@ int main(void) {
   O(meg_objective, dense) O(meg_objective, ld) O(meg_objective, nnz) O(meg_objective, batch_idx)
   O(meg_objective, batch_steps) O(meg_start, V0) O(meg_start, lambda0)
   O(meg_step_info, cert_holds) O(meg_step_info, ritz_gap) O(meg_step_info, converged) O(meg_step_info, resid_r1)
+  P(meg_server_params) P(meg_request) P(meg_request_status) P(meg_server_stats)
+  O(meg_server_params, max_resident) O(meg_server_params, flags)
+  O(meg_request, n) O(meg_request, M) O(meg_request, q) O(meg_request, V0) O(meg_request, eta)
+  O(meg_request, tol) O(meg_request, max_inner) O(meg_request, seed)
+  O(meg_request_status, iterations) O(meg_request_status, done_ms) O(meg_request_status, team)
+  O(meg_request_status, last)
+  O(meg_server_stats, kernel_ms) O(meg_server_stats, capacity_wg) O(meg_server_stats, arena_peak)
   return 0;
 }
 """
@@ -74,7 +81,9 @@ int main(void) {
         k, v = line.split()
         want[k] = int(v)
     S = {"meg_params": M.MegParams, "meg_objective": M.MegObjective, "meg_start": M.MegStart,
-         "meg_step_info": M.MegStepInfo, "meg_kernel_times": M.MegKernelTimes, "meg_counters": M.MegCounters}
+         "meg_step_info": M.MegStepInfo, "meg_kernel_times": M.MegKernelTimes, "meg_counters": M.MegCounters,
+         "meg_server_params": M.MegServerParams, "meg_request": M.MegRequest,
+         "meg_request_status": M.MegRequestStatus, "meg_server_stats": M.MegServerStats}
     for k, v in want.items():
         if "." in k:
             s, f = k.split(".")
@@ -178,6 +187,26 @@ def test_init_rejects_bad_quadmeas(M):
     assert M.meg_init(p3, q(), V, lam)[0] == M.MEG_ERR_UNSUPPORTED
     p64 = M.make_params(n, 4, prec=M.MEG_PREC_F64)
     assert M.meg_init(p64, q(lda=65), V, lam)[0] == M.MEG_ERR_INVALID_ARG  # 65 doubles: rows not 16-byte aligned
+
+
+def test_server_null_handle_and_bad_params(M):
+    """Server entry points reject a null handle and invalid parameters before
+    touching the device."""
+    lib = M.load_library()
+    st = M.MegRequestStatus()
+    assert lib.meg_server_query(None, 1, ctypes.byref(st)) == M.MEG_ERR_INVALID_ARG
+    assert lib.meg_server_run(None, 1, None) == M.MEG_ERR_INVALID_ARG
+    assert lib.meg_server_release(None, 1) == M.MEG_ERR_INVALID_ARG
+    stats = M.MegServerStats()
+    assert lib.meg_server_get_stats(None, ctypes.byref(stats)) == M.MEG_ERR_INVALID_ARG
+    h = ctypes.c_void_p()
+    for kw in (dict(launch_steps=0, max_resident=8), dict(launch_steps=8, max_resident=0),
+               dict(launch_steps=8, max_resident=257), dict(launch_steps=2000, max_resident=8),
+               dict(launch_steps=8, max_resident=8, budget_bytes=-1), dict(launch_steps=8, max_resident=8, flags=1)):
+        p = M.MegServerParams(**kw)
+        assert lib.meg_server_create(ctypes.byref(h), ctypes.byref(p), None) == M.MEG_ERR_INVALID_ARG, kw
+        assert not h.value
+    lib.meg_server_destroy(None)  # no-op
 
 
 def test_null_context_calls(M):

@@ -15,7 +15,7 @@ import pytest
 
 import workloads as W
 from oracle import meg_oracle as O
-from tests.helpers import TOL_X, dev, f_tol, make_csr, make_dense, np_dtype, rel_x_err
+from tests.helpers import TOL_X, dev, f_tol, gapped_spiked, make_csr, make_dense, np_dtype, rel_x_err
 
 pytestmark = pytest.mark.gpu
 
@@ -42,19 +42,6 @@ def linear_instance(n, r, seed, gap=4.0):
     lam0 = rng.random(r) + 0.3
     lam0 /= lam0.sum()
     return C, Q[:, :r].copy(), lam0
-
-
-def gapped_spiked(n, rank, seed, noise=0.01):
-    rng = np.random.default_rng([78, seed, n])
-    U, _ = np.linalg.qr(rng.standard_normal((n, rank)))
-    s = 2.0 - 0.2 * np.arange(rank)
-    G = rng.standard_normal((n, n))
-    M = (U * s) @ U.T + noise * (G + G.T) / math.sqrt(2 * n)
-    M = 0.5 * (M + M.T)
-    w, V = np.linalg.eigh(M)
-    V0 = V[:, ::-1][:, :rank].copy()
-    lam0 = np.full(rank, 1.0 / rank)
-    return M, V0, lam0
 
 
 # ---------------------------------------------------------------------------
