@@ -14,6 +14,10 @@ stream, its algorithmic bytes from the iterations and operator applies the
 launches performed) and the FP64 CPU oracle timed on a bounded sample of the
 same workload.
 
+The same line carries a "serving" object: the batched server on a stream of
+plain-configuration instances (Poisson arrivals, then saturation), against
+the single-instance FP32 path on a sample (`--no-serving` skips it).
+
 `--write-workload PATH` only writes the workload for the native driver
 paper_2012_10469_amd/meg_bench (used under rocprofv3) and exits.
 """
@@ -113,6 +117,117 @@ def cpu_baseline(p, r: int, samples: int):
                       f"at n={p.n}, r={r} from the same warm start; {dt:.1f} s"}
 
 
+def serving_bench(meg, torch, args) -> dict:
+    """Batched serving of the plain configuration's instances (spiked
+    denoising, top-1 warm start): n uniform over {256, 512, 1024, 2048}, r
+    uniform over 1..8, each run to max(2 eps_t, L_t) <= 1e-4 or 300
+    iterations; FP32 state, BF16x3 apply.  Inputs are drawn on the device
+    before any timing.  (1) Poisson arrivals at the offered rate: solves/s
+    and p50/p99 latency from arrival to the host seeing the result.  (2)
+    Saturation, everything arriving at once: solves/s and aggregate
+    algorithmic HBM traffic of the planes.  (3) The plain FP32 single-instance
+    path (meg_init/meg_solve per instance, dense FP32 apply) on a sample, at
+    the same stop rule."""
+    import numpy as np
+
+    import workloads as W
+
+    reqs = W.serving_stream(args.serve_count, args.seed, rate_hz=args.serve_rate)
+    t0 = time.time()
+    mats, starts = [], []
+    for q in reqs:
+        M, v = W.spiked_denoise_device(q["n"], q["seed"])
+        mats.append(M)
+        starts.append(v)
+    torch.cuda.synchronize()
+    log(f"[serve] {len(reqs)} instances drawn on the device in {time.time() - t0:.1f}s")
+    tol, cap = 1e-4, 300
+    lam = np.ones(1)
+    srv = meg.MegServer(budget_bytes=8 << 30, launch_steps=args.serve_launch_steps)
+    teams = {int(n): srv.team(int(n)) for n in sorted({q["n"] for q in reqs})}
+    log(f"[serve] team sizes (latency, throughput): {teams}")
+
+    def submit(i):
+        q = reqs[i]
+        return srv.submit(mats[i], starts[i], lam, q["r"], tol=tol, max_iters=cap, seed=q["seed"])
+
+    # (1) offered load
+    lat, iters, sweeps = [], [], []
+    outstanding = {}
+    i = 0
+    t0 = time.perf_counter()
+    while i < len(reqs) or outstanding:
+        now = time.perf_counter() - t0
+        while i < len(reqs) and reqs[i]["t_arrive"] <= now:
+            outstanding[submit(i)] = reqs[i]["t_arrive"]
+            i += 1
+        if not outstanding:
+            time.sleep(max(0.0, reqs[i]["t_arrive"] - (time.perf_counter() - t0)))
+            continue
+        srv.run(1)
+        done_t = time.perf_counter() - t0
+        for rid in list(outstanding):
+            st = srv.query(rid)
+            if st["state"] >= 2:
+                assert st["state"] == 2, st
+                lat.append(done_t - outstanding.pop(rid))
+                iters.append(st["iterations"])
+                sweeps.append(st["applies"] / max(1, st["iterations"]))
+                srv.release(rid)
+    wall1 = time.perf_counter() - t0
+    lat_ms = np.sort(np.asarray(lat)) * 1e3
+    offered = {"rate_hz": args.serve_rate, "requests": len(reqs), "wall_s": wall1,
+               "solves_per_s": len(reqs) / wall1, "p50_ms": float(np.percentile(lat_ms, 50)),
+               "p99_ms": float(np.percentile(lat_ms, 99)), "max_ms": float(lat_ms[-1]),
+               "mean_iterations": float(np.mean(iters)), "sweeps_per_iteration": float(np.mean(sweeps))}
+    log(f"[serve] offered {args.serve_rate:.0f}/s: {offered['solves_per_s']:.1f} solves/s, "
+        f"p50 {offered['p50_ms']:.1f} ms, p99 {offered['p99_ms']:.1f} ms, mean iterations {offered['mean_iterations']:.1f}, "
+        f"{offered['sweeps_per_iteration']:.2f} sweeps per iteration")
+
+    # (2) saturation
+    st0 = srv.stats()
+    t0 = time.perf_counter()
+    ids = [submit(j) for j in range(len(reqs))]
+    while srv.run(1) > 0:
+        pass
+    wall2 = time.perf_counter() - t0
+    st1 = srv.stats()
+    nbytes = 0.0
+    for j, rid in enumerate(ids):
+        st = srv.query(rid)
+        assert st["state"] == 2, st
+        n = reqs[j]["n"]
+        nbytes += st["applies"] * (4.0 * n * ((n + 7) // 8 * 8) + 2.0 * n * 16 * 4)
+        srv.release(rid)
+    gbs = nbytes / wall2 / 1e9
+    kms = st1["kernel_ms"] - st0["kernel_ms"]
+    saturated = {"wall_s": wall2, "solves_per_s": len(reqs) / wall2, "algorithmic_gbs": gbs,
+                 "frac_hbm": gbs / HBM_PEAK_GBS, "kernel_busy_frac": kms * 1e-3 / wall2,
+                 "launches": st1["launches"] - st0["launches"], "arena_peak_bytes": st1["arena_peak"]}
+    log(f"[serve] saturated: {saturated['solves_per_s']:.1f} solves/s, {gbs:.0f} GB/s of planes "
+        f"({100 * gbs / HBM_PEAK_GBS:.1f} % of HBM), kernel busy {100 * saturated['kernel_busy_frac']:.0f} %")
+    srv.close()
+
+    # (3) plain FP32 single-instance path on a sample
+    sample = min(args.serve_plain_sample, len(reqs))
+    t0 = time.perf_counter()
+    for j in range(sample):
+        q = reqs[j]
+        with meg.LowRankMEG(q["n"], q["r"], meg.MEG_GRAD_DENOISE_DENSE, starts[j], lam, prec=meg.MEG_PREC_F32,
+                            eta=1.0, dense=mats[j], max_inner=12) as g:
+            g.solve(cap, tol)
+    torch.cuda.synchronize()
+    wall3 = time.perf_counter() - t0
+    plain = {"sample": sample, "solves_per_s": sample / wall3,
+             "note": "one instance at a time through meg_init/meg_solve, dense FP32 apply, same stop rule"}
+    log(f"[serve] plain FP32 one-at-a-time: {plain['solves_per_s']:.1f} solves/s on {sample} instances")
+    return {"workload": "spiked denoising instances (plain configuration), n ~ U{256,512,1024,2048}, r ~ U{1..8}",
+            "stop": "max(2 eps_t, L_t) <= 1e-4 or 300 iterations", "dtype": "f32 state, bf16x3 apply",
+            "launch_steps": args.serve_launch_steps, "teams": {str(k): v for k, v in teams.items()},
+            "offered": offered, "saturated": saturated, "plain_f32": plain,
+            "speedup_vs_plain": saturated["solves_per_s"] / plain["solves_per_s"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +241,11 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch-steps", type=int, default=64,
                     help="iterations per launch of the persistent step kernel (1: one meg_step per iteration)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving measurement")
+    ap.add_argument("--serve-count", type=int, default=2048)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-launch-steps", type=int, default=8)
+    ap.add_argument("--serve-plain-sample", type=int, default=32)
     ap.add_argument("--write-workload", default=None, metavar="PATH",
                     help="write the workload file of the native driver and exit (no GPU use)")
     args = ap.parse_args()
@@ -235,6 +355,7 @@ def main() -> int:
         log(f"[bench] CPU oracle baseline: {args.cpu_samples} iterations")
         base = cpu_baseline(p, args.r, args.cpu_samples)
     g.close()
+    serving = None if args.no_serving else serving_bench(meg, torch, args)
 
     out = {
         "metric": "low-rank MEG iterations/s (matrix completion, n=4096, r=10, FP32)",
@@ -258,6 +379,7 @@ def main() -> int:
                      "iterations_per_launch": iters_per_launch, "applies_per_iteration": sweeps,
                      "launches": launches, "phases": phases},
         "cpu_baseline": base,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     return 0

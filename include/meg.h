@@ -272,7 +272,12 @@ const char* meg_status_str(meg_status s);
  * BF16x3 matrix-core form (FP32 state); M is split into its bf16 planes
  * once, at admission.  The team size per n is chosen by a built-in
  * autotuner that times the step kernel on a synthetic instance of that n
- * with each candidate size (the smallest team within 15 % of the fastest).
+ * with each candidate size: the latency choice is the smallest team within
+ * 15 % of the fastest, the throughput choice the team with the least
+ * workgroup time per iteration; a request is admitted with the throughput
+ * choice while others wait in the queue behind it, else with the latency
+ * choice.  (Results depend on the team size only through the order of the
+ * partial sums, i.e. within rounding.)
  * The solver's shift uses Gershgorin bounds of the planes' matrix (one pass
  * at admission) instead of the single-instance path's Lanczos estimate.
  * One host thread at a time per server; all work runs on its stream.
@@ -281,8 +286,11 @@ typedef struct meg_server_s* meg_server;
 
 typedef struct {
   int64_t budget_bytes;  /* device arena for resident instances; 0: 4 GiB   */
-  int32_t launch_steps;  /* iterations per instance per launch, 1..1024;
-                            also the admission granularity                 */
+  int32_t launch_steps;  /* iterations per launch of the fastest resident
+                            instance, 1..1024; slower ones run fewer (>= 1)
+                            so that all teams finish a launch together (by
+                            the autotuner's time per step); the launch is
+                            the admission granularity                      */
   int32_t max_resident;  /* instances resident at once, 1..256            */
   uint32_t flags;        /* reserved, 0                                    */
   int32_t reserved;
@@ -321,6 +329,7 @@ typedef struct {
   int32_t team;          /* workgroups of its team (resident or done)       */
   int32_t reserved;
   meg_step_info last;    /* last step's info (f = NaN)                      */
+  int64_t applies;       /* operator applies (subspace sweeps) performed    */
 } meg_request_status;
 
 typedef struct {
@@ -347,8 +356,9 @@ meg_status meg_server_query(meg_server s, int64_t id, meg_request_status* out);
 meg_status meg_server_result(meg_server s, int64_t id, double* V, double* d, double* alpha);
 /* Forget a done or failed request (its host result). */
 meg_status meg_server_release(meg_server s, int64_t id);
-/* Team size the server uses for dimension n (autotuned on first use). */
-meg_status meg_server_team(meg_server s, int64_t n, int32_t* team);
+/* Team sizes for dimension n (autotuned on first use): latency and
+ * throughput choices (either pointer may be NULL). */
+meg_status meg_server_team(meg_server s, int64_t n, int32_t* latency_team, int32_t* throughput_team);
 meg_status meg_server_get_stats(meg_server s, meg_server_stats* out);
 void meg_server_destroy(meg_server s);
 

@@ -244,6 +244,16 @@ __device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& 
   __shared__ unsigned s_gen;
   __shared__ int s_ok;
   const int tid = threadIdx.x;
+  if (tm.nwg == 1) {  // a team of one workgroup: its partials are the sums
+    __syncthreads();
+    if (plen > 0 && b.sums != b.part) {
+      for (int e = tid; e < plen; e += NT) b.sums[e] = b.part[e];
+      __syncthreads();
+    }
+    serial();
+    __syncthreads();
+    return true;
+  }
   const unsigned P = (unsigned)tm.nwg;
   const unsigned g = (unsigned)tm.wg / kBarGroupSize;
   const unsigned ng = (P + kBarGroupSize - 1) / kBarGroupSize;

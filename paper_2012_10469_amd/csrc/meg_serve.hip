@@ -110,6 +110,19 @@ struct Arena {
   }
 };
 
+// autotuned team sizes for one n, and the measured time per step (3 sweeps)
+// of every timed team size
+struct Tuned {
+  int lat = 1, thr = 1;
+  std::map<int, double> ms_per_step;
+  double step_ms(int P) const {  // nearest timed size, scaled by the team ratio
+    if (ms_per_step.empty()) return 1.0;
+    auto it = ms_per_step.lower_bound(P);
+    if (it == ms_per_step.end()) --it;
+    return it->second * (double)it->first / (double)P;
+  }
+};
+
 struct Req {
   meg_request r{};
   std::vector<double> V0, lam0;
@@ -117,7 +130,8 @@ struct Req {
   double t_submit = 0, t_admit = 0, t_done = 0;
   int slot = -1, nwg = 0;
   size_t off = 0, bytes = 0;
-  int64_t iters = 0;
+  int64_t iters = 0, applies = 0;
+  double step_ms = 1.0;  // autotuner's time per step at its team size (relative speed)
   meg_step_info last{};
   std::vector<double> V, d;
   double alpha = 0;
@@ -141,7 +155,7 @@ struct meg_server_s {
   std::vector<int64_t> slot_req;   // request resident in each slot, or -1
   std::map<int64_t, Req> reqs;
   std::deque<int64_t> queue;
-  std::map<int64_t, int> team;     // autotuned team size per n
+  std::map<int64_t, Tuned> team;  // autotuned team sizes per n
   int64_t next_id = 1;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   int64_t submitted = 0, completed = 0, failed_reqs = 0, launches = 0, iterations = 0;
@@ -215,6 +229,7 @@ meg_status setup_instance(meg_server s, const meg_request& q, const double* V0, 
   uint16_t* lo = (uint16_t*)(base + L.lo);
   Bufs b{(double*)(base + L.part), (double*)(base + L.gpart), (double*)(base + L.sums), (unsigned*)(base + L.bar),
          nullptr};
+  if (nwg == 1) b.sums = b.part;  // a one-workgroup team reads its own partials
   Cfg cfg{};
   cfg.n = n;
   cfg.ld = ld;
@@ -301,24 +316,23 @@ meg_status launch_serve(meg_server s, const std::vector<int>& slots, const std::
   return MEG_OK;
 }
 
-// Team size for n: time the batched kernel on a synthetic instance of that
+// Team sizes for n: time the batched kernel on a synthetic instance of that
 // n (a spiked denoising matrix, fixed 3 sweeps per step) for every
-// candidate team size; keep the smallest team within 15 % of the fastest.
-meg_status tune(meg_server s, int64_t n, int* out) {
+// candidate team size P (powers of two up to one 64-row block per
+// workgroup).  Latency choice: the smallest P within 15 % of the fastest;
+// throughput choice: the least workgroup time P t(P) per iteration.
+meg_status tune(meg_server s, int64_t n, int* lat, int* thr) {
   auto it = s->team.find(n);
   if (it != s->team.end()) {
-    *out = it->second;
+    *lat = it->second.lat;
+    *thr = it->second.thr;
     return MEG_OK;
   }
   const int pmax = max_team(s, n);
   std::vector<int> cand;
   for (int p = 1; p <= pmax; p *= 2) cand.push_back(p);
   if (cand.back() != pmax) cand.push_back(pmax);
-  if (cand.size() == 1) {
-    s->team[n] = cand[0];
-    *out = cand[0];
-    return MEG_OK;
-  }
+  const bool single = cand.size() == 1;
   // synthetic instance: M = u u^T + 0.01 (G + G^T) / sqrt(2n), FP32
   SplitMix rng{0x7475756e65ull ^ (uint64_t)n};
   std::vector<double> u(n);
@@ -373,17 +387,29 @@ meg_status tune(meg_server s, int64_t n, int* out) {
   double best = 1e30;
   for (double t : tper) best = std::min(best, t);
   if (best >= 1e29) {  // no candidate fitted the arena now: a default, not cached
-    *out = std::min(4, pmax);
+    *lat = *thr = single ? cand[0] : std::min(4, pmax);
     return MEG_OK;
   }
-  int pick = cand.back();
+  int pl = cand.back(), pt = cand[0];
   for (size_t ci = 0; ci < cand.size(); ++ci)
     if (tper[ci] <= 1.15 * best) {
-      pick = cand[ci];
+      pl = cand[ci];
       break;
     }
-  s->team[n] = pick;
-  *out = pick;
+  double wbest = 1e30;
+  for (size_t ci = 0; ci < cand.size(); ++ci)
+    if (tper[ci] < 1e29 && cand[ci] * tper[ci] < wbest) {
+      wbest = cand[ci] * tper[ci];
+      pt = cand[ci];
+    }
+  Tuned tu;
+  tu.lat = pl;
+  tu.thr = pt;
+  for (size_t ci = 0; ci < cand.size(); ++ci)
+    if (tper[ci] < 1e29) tu.ms_per_step[cand[ci]] = tper[ci];
+  s->team[n] = tu;
+  *lat = pl;
+  *thr = pt;
   return MEG_OK;
 }
 
@@ -415,6 +441,7 @@ meg_status retire(meg_server s) {
       }
     q.d.assign(h.d, h.d + r);
     q.alpha = h.alpha;
+    q.applies = h.applies_done;
     const Info& in = h.info;
     meg_step_info& o = q.last;
     o.t = in.t;
@@ -453,9 +480,10 @@ meg_status admit(meg_server s) {
   while (!s->queue.empty() && resident < s->p.max_resident) {
     const int64_t id = s->queue.front();
     Req& q = s->reqs[id];
-    int P = 0;
-    meg_status st = tune(s, q.r.n, &P);
+    int pl = 0, pt = 0;
+    meg_status st = tune(s, q.r.n, &pl, &pt);
     if (st != MEG_OK) return st;
+    const int P = s->queue.size() > 1 ? pt : pl;  // others waiting: the throughput choice
     if (P > s->free_wg) break;
     const Layout L = layout(q.r.n, P);
     size_t off = 0;
@@ -475,6 +503,7 @@ meg_status admit(meg_server s) {
     }
     q.slot = sl;
     q.nwg = P;
+    q.step_ms = s->team.count(q.r.n) ? s->team[q.r.n].step_ms(P) : 1.0;
     q.off = off;
     q.bytes = L.bytes;
     q.state = 1;
@@ -572,15 +601,27 @@ meg_status meg_server_run(meg_server s, int32_t rounds, int32_t* pending) {
   for (int rd = 0; rd < rounds; ++rd) {
     if ((st = retire(s)) != MEG_OK) return st;
     if ((st = admit(s)) != MEG_OK) return st;
+    // Steps per instance in this launch, balanced by the autotuner's time per
+    // step so that the teams finish together: the launch lasts about
+    // D = max(launch_steps x the fastest step, the slowest single step), and
+    // each instance runs floor(D / its step time) >= 1 steps.
     std::vector<int> slots, steps;
+    double tmin = 1e30, tmax = 0.0;
     for (int sl = 0; sl < kMaxSlots; ++sl) {
       const int64_t id = s->slot_req[sl];
       if (id < 0) continue;
       const Req& q = s->reqs[id];
       slots.push_back(sl);
-      steps.push_back((int)std::min<int64_t>(s->p.launch_steps, q.r.max_iters - q.iters));
+      tmin = std::min(tmin, q.step_ms);
+      tmax = std::max(tmax, q.step_ms);
     }
     if (slots.empty()) break;
+    const double D = std::max(s->p.launch_steps * tmin, tmax);
+    for (int sl : slots) {
+      const Req& q = s->reqs[s->slot_req[sl]];
+      const int64_t want = std::max<int64_t>(1, (int64_t)(D / q.step_ms));
+      steps.push_back((int)std::min<int64_t>({want, (int64_t)s->p.launch_steps * 64, q.r.max_iters - q.iters}));
+    }
     double ms = 0.0;
     if ((st = launch_serve(s, slots, steps, &ms)) != MEG_OK) return st;
     ++s->launches;
@@ -615,6 +656,7 @@ meg_status meg_server_query(meg_server s, int64_t id, meg_request_status* out) {
   out->done_ms = q.t_done;
   out->team = q.nwg;
   out->last = q.last;
+  out->applies = q.applies;
   return MEG_OK;
 }
 
@@ -639,14 +681,15 @@ meg_status meg_server_release(meg_server s, int64_t id) {
   return MEG_OK;
 }
 
-meg_status meg_server_team(meg_server s, int64_t n, int32_t* team) {
+meg_status meg_server_team(meg_server s, int64_t n, int32_t* latency_team, int32_t* throughput_team) {
   meg_status st = check_server(s);
   if (st != MEG_OK) return st;
-  if (!team || n < 16 || n > 32768) return MEG_ERR_INVALID_ARG;
-  int P = 0;
-  st = tune(s, n, &P);
+  if (n < 16 || n > 32768) return MEG_ERR_INVALID_ARG;
+  int pl = 0, pt = 0;
+  st = tune(s, n, &pl, &pt);
   if (st != MEG_OK) return st;
-  *team = P;
+  if (latency_team) *latency_team = pl;
+  if (throughput_team) *throughput_team = pt;
   return MEG_OK;
 }
 

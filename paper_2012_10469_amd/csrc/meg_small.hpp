@@ -559,7 +559,22 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   const bool finite = wave_min((lane < KB) ? ((isfinite(th) && isfinite(rh)) ? 1.0 : 0.0) : 1.0) > 0.5;
   const double rr1 = __shfl(rh, r, 64);
   const bool cert_ok = !(cfg.cert_tol > 0.0) || rr1 <= fmax(cfg.cert_tol, floor_est);
-  bool conv = rmax <= thr && cert_ok;
+  // A top-r pair enters X_{t+1} = alpha' I + V diag(d') V^T only through
+  // d'_l v_l v_l^T: even an entirely wrong v_l moves X by at most
+  // sqrt(2) |d'_l|, i.e. sqrt(2) w_l of ||X||_F with w_l = |d'_l| / max |d'|.
+  // Pairs with w_l <= inner_tol / 4 therefore need no residual test (in the
+  // noise bulk of M_t such pairs converge slowly and carry no weight).
+  // d' follows from the Ritz values exactly as finish_step forms it.
+  const double mu = (lane < r) ? th + log(ctl->alpha) - ctl->sigma : -__builtin_inf();
+  const double mmax = wave_max(mu);
+  const double ex = (lane < r) ? exp(mu - mmax) : 0.0;
+  const double esum = wave_sum(ex);
+  const double eps_t = eps_at(cfg, ctl->t);
+  const double dl_new = (lane < r) ? (1.0 - eps_t) * ex / esum - eps_t / (double)(cfg.n - r) : 0.0;
+  const double dmax = wave_max(fabs(dl_new));
+  const bool light = dmax > 0.0 && fabs(dl_new) <= 0.25 * cfg.inner_tol * dmax;
+  const bool pair_ok = lane >= r || rh <= thr || light;
+  bool conv = wave_min(pair_ok ? 1.0 : 0.0) > 0.5 && cert_ok;
   bool do_polish = false;
   // tolerance below the resolvable floor: two more sweeps once it is reached
   if (conv && cfg.inner_tol * scale < floor_est && polish < 2) {

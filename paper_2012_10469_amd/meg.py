@@ -123,7 +123,8 @@ class MegRequest(ctypes.Structure):
 class MegRequestStatus(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("iterations", ctypes.c_int64),
                 ("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double), ("done_ms", ctypes.c_double),
-                ("team", ctypes.c_int32), ("reserved", ctypes.c_int32), ("last", MegStepInfo)]
+                ("team", ctypes.c_int32), ("reserved", ctypes.c_int32), ("last", MegStepInfo),
+                ("applies", ctypes.c_int64)]
 
 
 class MegServerStats(ctypes.Structure):
@@ -171,7 +172,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "meg_server_result": (ctypes.c_int, [vp, ctypes.c_int64, P(ctypes.c_double), P(ctypes.c_double),
                                              P(ctypes.c_double)]),
         "meg_server_release": (ctypes.c_int, [vp, ctypes.c_int64]),
-        "meg_server_team": (ctypes.c_int, [vp, ctypes.c_int64, P(ctypes.c_int32)]),
+        "meg_server_team": (ctypes.c_int, [vp, ctypes.c_int64, P(ctypes.c_int32), P(ctypes.c_int32)]),
         "meg_server_get_stats": (ctypes.c_int, [vp, P(MegServerStats)]),
         "meg_server_destroy": (None, [vp]),
     }
@@ -456,10 +457,11 @@ class MegServer:
     def release(self, rid: int) -> None:
         _check(self._lib.meg_server_release(self._h, int(rid)), "meg_server_release")
 
-    def team(self, n: int) -> int:
-        t = ctypes.c_int32()
-        _check(self._lib.meg_server_team(self._h, int(n), ctypes.byref(t)), "meg_server_team")
-        return t.value
+    def team(self, n: int) -> tuple:
+        """(latency, throughput) team sizes for dimension n (autotuned on first use)."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.meg_server_team(self._h, int(n), ctypes.byref(a), ctypes.byref(b)), "meg_server_team")
+        return a.value, b.value
 
     def stats(self) -> dict:
         st = MegServerStats()

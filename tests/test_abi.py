@@ -65,7 +65,7 @@ int main(void) {
   O(meg_request, n) O(meg_request, M) O(meg_request, q) O(meg_request, V0) O(meg_request, eta)
   O(meg_request, tol) O(meg_request, max_inner) O(meg_request, seed)
   O(meg_request_status, iterations) O(meg_request_status, done_ms) O(meg_request_status, team)
-  O(meg_request_status, last)
+  O(meg_request_status, last) O(meg_request_status, applies)
   O(meg_server_stats, kernel_ms) O(meg_server_stats, capacity_wg) O(meg_server_stats, arena_peak)
   return 0;
 }

@@ -138,7 +138,7 @@ def test_serving_admits_as_memory_frees(meg):
 
     n, r = 1024, 3
     with meg.MegServer(launch_steps=4) as probe_srv:
-        team = probe_srv.team(n)
+        team = probe_srv.team(n)[1]
     # per-instance block: planes 4 n^2 + blocks and buffers (< 1 MB)
     budget = 2 * (4 * n * n + (1 << 20)) + (1 << 19)
     with meg.MegServer(budget_bytes=budget, launch_steps=4) as srv:

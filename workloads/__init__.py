@@ -450,3 +450,27 @@ def quadmeas_pool_device(n: int, m: int, seed: int, rank: int = 3, chunk: int = 
         P = A[i0:i1].to(torch.float64) @ Fd
         b[i0:i1] = (P * P).sum(dim=1).to(torch.float32)
     return A, b, F
+
+
+def spiked_denoise_device(n: int, seed: int, spike: float = 1.0, noise: float = 0.01, power_iters: int = 30):
+    """The plain-configuration denoising instance drawn on the GPU (torch's
+    seeded generator): M = spike u u^T + noise (G + G^T)/sqrt(2n) in FP32,
+    u a unit Gaussian vector.  Also returns the warm start of that
+    configuration, the top eigenvector of M, by power iteration from u (the
+    spike's gap makes a few dozen products enough).
+    Returns (M on the device, v0 host float64 n x 1)."""
+    import torch
+
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(int(rng(5, 1, seed).integers(0, 2**62)))
+    u = torch.randn(n, generator=gen, device="cuda", dtype=torch.float64)
+    u /= torch.linalg.norm(u)
+    G = torch.randn((n, n), generator=gen, device="cuda", dtype=torch.float32)
+    M = (G + G.T) * (noise / math.sqrt(2.0 * n))
+    M += (spike * torch.outer(u, u)).to(torch.float32)
+    v = u.clone()
+    Md = M.to(torch.float64)
+    for _ in range(power_iters):
+        v = Md @ v
+        v /= torch.linalg.norm(v)
+    return M.contiguous(), v.cpu().numpy().reshape(n, 1)
