@@ -35,6 +35,25 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
+# HBM traffic of one 64-iteration launch of the step kernel on the default
+# workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain
+# copy's readings (profiles/k_step_matrix_completion_n4096_r10_traffic.md);
+# valid only for the kernel sources it was measured on.
+TRAFFIC = {"bytes_per_launch": 942.9e6, "iterations_per_launch": 64, "applies_per_iteration": 3.0,
+           "fetch_bytes": 546.4e6, "write_bytes": 396.5e6, "fetch_factor": 2.0, "write_factor": 1.0,
+           "source_hash": "21af2ec4d84163b3"}
+KERNEL_SOURCES = ["meg_device.hpp", "meg_small.hpp", "meg_kernels.hpp", "meg_api.hip"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2012_10469_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
@@ -356,6 +375,13 @@ def main() -> int:
         base = cpu_baseline(p, args.r, args.cpu_samples)
     g.close()
     serving = None if args.no_serving else serving_bench(meg, torch, args)
+    # measured HBM bytes per launch (counter runs), only for the kernel they were taken on
+    traffic, traffic_note = None, "kernel sources changed since the counter runs"
+    if kernel_source_hash() == TRAFFIC["source_hash"] and args.launch_steps == TRAFFIC["iterations_per_launch"]:
+        traffic = TRAFFIC["bytes_per_launch"]
+        traffic_note = (f"HBM bytes per {TRAFFIC['iterations_per_launch']}-iteration launch "
+                        f"(FETCH_SIZE x {TRAFFIC['fetch_factor']} + WRITE_SIZE x {TRAFFIC['write_factor']}, "
+                        f"first timed launch, {TRAFFIC['applies_per_iteration']} applies per iteration)")
 
     out = {
         "metric": "low-rank MEG iterations/s (matrix completion, n=4096, r=10, FP32)",
@@ -374,7 +400,8 @@ def main() -> int:
                    "mask_p": 0.1, "truth_rank": 5, "eta": 1.0, "eps": "0.8/(t+11)^2",
                    "sweeps_per_step": sweeps, "steps_per_launch": args.launch_steps},
         "roofline": {"bound": "hbm", "kernel": "k_step", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_note": traffic_note,
                      "bytes_per_launch": nbytes, "avg_launch_us": avg_launch_ms * 1e3,
                      "iterations_per_launch": iters_per_launch, "applies_per_iteration": sweeps,
                      "launches": launches, "phases": phases},

@@ -1,5 +1,5 @@
-"""Build the HIP library libmeg.so, and the native driver meg_bench, in-tree
-for gfx950.
+"""Build the HIP library libmeg.so, the native driver meg_bench and the
+counter-calibration copy meg_copy, in-tree for gfx950.
 
     python -m paper_2012_10469_amd.build
 
@@ -20,6 +20,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmeg.so")
 DRIVER = os.path.join(HERE, "meg_bench")
+COPY = os.path.join(HERE, "meg_copy")
 ARCH = os.environ.get("MEG_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["meg_api.hip", "meg_serve.hip"]
@@ -66,6 +67,16 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError(f"hipcc (meg_bench) failed with exit code {res.returncode}")
     os.replace(DRIVER + ".tmp", DRIVER)
+    # calibration copy for the traffic counters (own device code, no library)
+    ccmd = [hipcc(), "-O2", "-std=c++17", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
+            "-packed-fp32-ops", "-Wno-unused-result", os.path.join(CSRC, "meg_copy.cpp"), "-o", COPY + ".tmp"]
+    if verbose:
+        print(" ".join(ccmd), flush=True)
+    res = subprocess.run(ccmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError(f"hipcc (meg_copy) failed with exit code {res.returncode}")
+    os.replace(COPY + ".tmp", COPY)
     return LIB
 
 
