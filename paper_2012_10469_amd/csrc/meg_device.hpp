@@ -113,6 +113,7 @@ struct Ctl {
   double dxnorm;            // ||X_{t+1} - X_t||_F of the last step
   int64_t iters_done;       // iterations performed by step launches (counter)
   int64_t applies_done;     // operator applies performed by step launches (counter)
+  int64_t pause_seq;        // batched launches: the launch whose time budget this instance used up
   Info info;
 };
 

@@ -1134,12 +1134,16 @@ struct StepLds {
 };
 
 // `nsteps` iterations of one instance by the team `tm` (the body of k_step
-// and of each team of k_serve).
+// and of each team of k_serve).  With a deadline (device wall clock, 0:
+// none) the team also stops at the first step boundary past it: the
+// workgroup that ends a step compares the clock and marks the instance
+// paused for launch `seq`, which every workgroup of the team reads after the
+// barrier, so the team decides as one.
 template <typename T, int KB, int OPK, int NT, bool CACHE>
 __device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl, const Data<T>& dat,
                                           T* __restrict__ Z0, T* __restrict__ Z1, T* __restrict__ Z2,
                                           T* __restrict__ g, const Bufs& b, int nsteps, Team tm, double* smem,
-                                          char* xstage, char* dyn) {
+                                          char* xstage, char* dyn, long long deadline = 0, int64_t seq = 0) {
   using SH = StepShape<T, KB, OPK, NT>;
   using SM = ApplySmem<T, KB, SH::ROWS, SH::GWROWS>;
   static_assert(!CACHE || OPK == OP_CSR, "the LDS cache holds CSR data");
@@ -1158,6 +1162,7 @@ __device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl,
   }
   for (int st = 0; st < nsteps; ++st) {
     if (ldi(&ctl->stop) | ldi(&ctl->status)) break;
+    if (deadline != 0 && ldi64(&ctl->pause_seq) == seq) break;
     if (tm.wg == 0) {
       stamp(b, 0);
       stamp(b, 1);  // no separate gradient phase: it is part of sweep 1
@@ -1238,6 +1243,7 @@ __device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl,
                 }
                 wg_fence();  // finish_step's writes of d, alpha, c, by other lanes
                 step_scalars(cfg, gc, tid);
+                if (deadline != 0 && tid == 0 && (long long)wall_clock64() >= deadline) gc->pause_seq = seq;
               }
             }
             if (tid == 0) ctl->applies_done = ctl->applies_done + 1;
@@ -1277,15 +1283,23 @@ struct Slot {
 
 // Batched persistent step kernel: the grid is split into teams, one per
 // resident instance; team[w] = (slot, rank) of workgroup w (slot < 0: idle,
-// the workgroup exits).  Each team runs its instance exactly as k_step does
+// the workgroup exits).  Every team runs until its instance's `nsteps` are
+// done or the launch's time budget (wall-clock ticks, 0: none) is used up,
+// whichever comes first; how steps fall into launches does not change an
+// instance's arithmetic.  Each team runs its instance exactly as k_step does
 // on a grid of nwg workgroups, with the instance's own barrier words and
 // partials, so an instance's arithmetic (and its reduction order) does not
 // depend on which other instances are resident.  Launched cooperatively.
 template <typename T, int KB, int OPK, int NT>
-static __global__ __launch_bounds__(NT) void k_serve(const Slot<T>* __restrict__ slots, const int2* __restrict__ team) {
+static __global__ __launch_bounds__(NT) void k_serve(const Slot<T>* __restrict__ slots, const int2* __restrict__ team,
+                                                     int64_t seq, long long budget) {
   using L = StepLds<T, KB, OPK, NT>;
   __shared__ double smem[L::SMEM_DOUBLES];
   __shared__ __attribute__((aligned(16))) char xstage[L::XSTAGE_BYTES];
+  __shared__ long long s_t0;
+  if (threadIdx.x == 0) s_t0 = (long long)wall_clock64();
+  __syncthreads();
+  const long long deadline = budget > 0 ? s_t0 + budget : 0;
   const int slot = __builtin_amdgcn_readfirstlane(team[blockIdx.x].x);
   const int rank = __builtin_amdgcn_readfirstlane(team[blockIdx.x].y);
   if (slot < 0) return;
@@ -1296,7 +1310,7 @@ static __global__ __launch_bounds__(NT) void k_serve(const Slot<T>* __restrict__
   const Data<T> dat = sl->dat;
   const Bufs b = sl->b;
   step_loop<T, KB, OPK, NT, false>(cfg, sl->ctl, dat, sl->Z0, sl->Z1, sl->Z2, nullptr, b, nsteps,
-                                   Team{rank, sl->nwg}, smem, xstage, nullptr);
+                                   Team{rank, sl->nwg}, smem, xstage, nullptr, deadline, seq);
 }
 
 // Orthonormalising transform of a freshly uploaded basis B = block `src`

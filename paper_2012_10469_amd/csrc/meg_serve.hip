@@ -34,6 +34,7 @@ constexpr int kKB = 16;
 constexpr int kMaxSlots = 256;
 constexpr int kProbeSlot = kMaxSlots;  // slot index used by the autotuner
 constexpr int kGershWg = 256;          // workgroups of the Gershgorin pass
+constexpr double kWallClockHz = 1.0e8; // device wall clock (wall_clock64) of gfx950
 using Shape = StepShape<float, kKB, OP_DENSE_X3, kNT>;
 using SMem = ApplySmem<float, kKB, Shape::ROWS, Shape::GWROWS>;
 
@@ -158,6 +159,8 @@ struct meg_server_s {
   std::map<int64_t, Tuned> team;  // autotuned team sizes per n
   int64_t next_id = 1;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  int64_t launch_seq = 0;
+  double last_launch_ms = 0.0;
   int64_t submitted = 0, completed = 0, failed_reqs = 0, launches = 0, iterations = 0;
   double kernel_ms = 0;
   std::chrono::steady_clock::time_point t0;
@@ -287,9 +290,10 @@ meg_status setup_instance(meg_server s, const meg_request& q, const double* V0, 
   return MEG_OK;
 }
 
-// one launch of the batched kernel over the slots listed, `steps` each;
-// returns the HIP-event time in ms
-meg_status launch_serve(meg_server s, const std::vector<int>& slots, const std::vector<int>& steps, double* ms) {
+// one launch of the batched kernel over the slots listed, at most `steps`
+// each, within a time budget (ms, <= 0: none); returns the HIP-event time in ms
+meg_status launch_serve(meg_server s, const std::vector<int>& slots, const std::vector<int>& steps, double* ms,
+                        double budget_ms = 0.0) {
   int w = 0;
   for (size_t i = 0; i < slots.size(); ++i) {
     Slot<float>& sl = s->h_slots[slots[i]];
@@ -301,7 +305,9 @@ meg_status launch_serve(meg_server s, const std::vector<int>& slots, const std::
                          s->stream));
   SCHK(s, hipMemcpyAsync(s->d_team, s->h_team, sizeof(int2) * w, hipMemcpyHostToDevice, s->stream));
   SCHK(s, hipEventRecord(s->ev_a, s->stream));
-  void* args[] = {&s->d_slots, &s->d_team};
+  int64_t seq = ++s->launch_seq;
+  long long budget = budget_ms > 0.0 ? (long long)(budget_ms * 1e-3 * kWallClockHz) : 0;
+  void* args[] = {&s->d_slots, &s->d_team, &seq, &budget};
   SCHK(s, hipLaunchCooperativeKernel(serve_kernel(), dim3(w), dim3(kNT), args, 0, s->stream));
   SCHK(s, hipEventRecord(s->ev_b, s->stream));
   hipLaunchKernelGGL((k_serve_summary<float>), dim3((kMaxSlots + 1 + 255) / 256), dim3(256), 0, s->stream,
@@ -601,10 +607,11 @@ meg_status meg_server_run(meg_server s, int32_t rounds, int32_t* pending) {
   for (int rd = 0; rd < rounds; ++rd) {
     if ((st = retire(s)) != MEG_OK) return st;
     if ((st = admit(s)) != MEG_OK) return st;
-    // Steps per instance in this launch, balanced by the autotuner's time per
-    // step so that the teams finish together: the launch lasts about
-    // D = max(launch_steps x the fastest step, the slowest single step), and
-    // each instance runs floor(D / its step time) >= 1 steps.
+    // Time budget of the launch: every team steps until it is used up (the
+    // device clock decides at step boundaries), so the teams finish
+    // together.  D = max(launch_steps x the fastest step, the slowest single
+    // step) by the autotuner's times, raised to 0.9 of the last launch (the
+    // autotuner times instances alone; under load steps take longer).
     std::vector<int> slots, steps;
     double tmin = 1e30, tmax = 0.0;
     for (int sl = 0; sl < kMaxSlots; ++sl) {
@@ -616,16 +623,16 @@ meg_status meg_server_run(meg_server s, int32_t rounds, int32_t* pending) {
       tmax = std::max(tmax, q.step_ms);
     }
     if (slots.empty()) break;
-    const double D = std::max(s->p.launch_steps * tmin, tmax);
+    const double D = std::max({s->p.launch_steps * tmin, tmax, 0.9 * s->last_launch_ms});
     for (int sl : slots) {
       const Req& q = s->reqs[s->slot_req[sl]];
-      const int64_t want = std::max<int64_t>(1, (int64_t)(D / q.step_ms));
-      steps.push_back((int)std::min<int64_t>({want, (int64_t)s->p.launch_steps * 64, q.r.max_iters - q.iters}));
+      steps.push_back((int)std::min<int64_t>((int64_t)s->p.launch_steps * 64, q.r.max_iters - q.iters));
     }
     double ms = 0.0;
-    if ((st = launch_serve(s, slots, steps, &ms)) != MEG_OK) return st;
+    if ((st = launch_serve(s, slots, steps, &ms, D)) != MEG_OK) return st;
     ++s->launches;
     s->kernel_ms += ms;
+    s->last_launch_ms = ms;
     for (size_t i = 0; i < slots.size(); ++i) {
       Req& q = s->reqs[s->slot_req[slots[i]]];
       const int64_t it = s->h_sum[slots[i]].t - 1;
