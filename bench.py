@@ -144,7 +144,8 @@ def serving_bench(meg, torch, args) -> dict:
     before any timing.  (1) Poisson arrivals at the offered rate: solves/s
     and p50/p99 latency from arrival to the host seeing the result.  (2)
     Saturation, everything arriving at once: solves/s and aggregate
-    algorithmic HBM traffic of the planes.  (3) The plain FP32 single-instance
+    algorithmic HBM traffic of the planes.  Each scheduling round replays
+    one captured hipGraph (graph mode of the server).  (3) The plain FP32 single-instance
     path (meg_init/meg_solve per instance, dense FP32 apply) on a sample, at
     the same stop rule."""
     import numpy as np
@@ -162,7 +163,7 @@ def serving_bench(meg, torch, args) -> dict:
     log(f"[serve] {len(reqs)} instances drawn on the device in {time.time() - t0:.1f}s")
     tol, cap = 1e-4, 300
     lam = np.ones(1)
-    srv = meg.MegServer(budget_bytes=8 << 30, launch_steps=args.serve_launch_steps)
+    srv = meg.MegServer(budget_bytes=8 << 30, launch_steps=args.serve_launch_steps, graph=True)
     teams = {int(n): srv.team(int(n)) for n in sorted({q["n"] for q in reqs})}
     log(f"[serve] team sizes (latency, throughput): {teams}")
 
@@ -221,6 +222,7 @@ def serving_bench(meg, torch, args) -> dict:
     gbs = nbytes / wall2 / 1e9
     kms = st1["kernel_ms"] - st0["kernel_ms"]
     saturated = {"wall_s": wall2, "solves_per_s": len(reqs) / wall2, "algorithmic_gbs": gbs,
+                 "graph_node": {0: "none", 1: "cooperative", 2: "ordinary"}[st1["graph_node"]],
                  "frac_hbm": gbs / HBM_PEAK_GBS, "kernel_busy_frac": kms * 1e-3 / wall2,
                  "launches": st1["launches"] - st0["launches"], "arena_peak_bytes": st1["arena_peak"]}
     log(f"[serve] saturated: {saturated['solves_per_s']:.1f} solves/s, {gbs:.0f} GB/s of planes "

@@ -284,6 +284,15 @@ const char* meg_status_str(meg_status s);
  * ------------------------------------------------------------------------- */
 typedef struct meg_server_s* meg_server;
 
+#define MEG_SERVER_FLAG_GRAPH 1u /* each scheduling round replays one captured
+                                    hipGraph: the slot and team tables and the
+                                    launch parameters copied from pinned host
+                                    memory, the batched kernel over the whole
+                                    workgroup capacity (workgroups without a
+                                    team exit), the summary and its read-back;
+                                    results are those of direct launches.
+                                    Needs a stream other than NULL           */
+
 typedef struct {
   int64_t budget_bytes;  /* device arena for resident instances; 0: 4 GiB   */
   int32_t launch_steps;  /* iterations per launch of the fastest resident
@@ -292,8 +301,10 @@ typedef struct {
                             the autotuner's time per step); the launch is
                             the admission granularity                      */
   int32_t max_resident;  /* instances resident at once, 1..256            */
-  uint32_t flags;        /* reserved, 0                                    */
-  int32_t reserved;
+  uint32_t flags;        /* MEG_SERVER_FLAG_*                               */
+  int32_t fixed_team;    /* > 0: every instance runs on this many workgroups
+                            (at most one 64-row block each) instead of the
+                            autotuner's choice; 0: autotune                */
 } meg_server_params;
 
 typedef struct {
@@ -339,7 +350,9 @@ typedef struct {
   double kernel_ms;      /* summed HIP-event time of the serving launches   */
   int32_t resident, queued;
   int32_t capacity_wg;   /* co-resident workgroups of the serving kernel    */
-  int32_t reserved;
+  int32_t graph_node;    /* graph mode: 0 not captured yet, 1 the captured
+                            kernel node is a cooperative launch, 2 an
+                            ordinary launch of at most capacity_wg         */
   int64_t arena_bytes, arena_used, arena_peak;
 } meg_server_stats;
 

@@ -1290,15 +1290,25 @@ struct Slot {
 // on a grid of nwg workgroups, with the instance's own barrier words and
 // partials, so an instance's arithmetic (and its reduction order) does not
 // depend on which other instances are resident.  Launched cooperatively.
+// Per-launch parameters of k_serve, read from device memory so that a
+// captured launch replays with new values: the launch number and its time
+// budget in wall-clock ticks (0: none).
+struct ServeParams {
+  int64_t seq;
+  long long budget;
+};
+
 template <typename T, int KB, int OPK, int NT>
 static __global__ __launch_bounds__(NT) void k_serve(const Slot<T>* __restrict__ slots, const int2* __restrict__ team,
-                                                     int64_t seq, long long budget) {
+                                                     const ServeParams* __restrict__ prm) {
   using L = StepLds<T, KB, OPK, NT>;
   __shared__ double smem[L::SMEM_DOUBLES];
   __shared__ __attribute__((aligned(16))) char xstage[L::XSTAGE_BYTES];
   __shared__ long long s_t0;
   if (threadIdx.x == 0) s_t0 = (long long)wall_clock64();
   __syncthreads();
+  const int64_t seq = prm->seq;
+  const long long budget = prm->budget;
   const long long deadline = budget > 0 ? s_t0 + budget : 0;
   const int slot = __builtin_amdgcn_readfirstlane(team[blockIdx.x].x);
   const int rank = __builtin_amdgcn_readfirstlane(team[blockIdx.x].y);

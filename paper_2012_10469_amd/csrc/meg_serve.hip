@@ -151,6 +151,13 @@ struct meg_server_s {
   int2* h_team = nullptr;          // pinned
   SlotSummary* d_sum = nullptr;
   SlotSummary* h_sum = nullptr;    // pinned
+  ServeParams* d_prm = nullptr;
+  ServeParams* h_prm = nullptr;    // pinned
+  // graph mode: the per-round sequence (table copies, the batched kernel on
+  // the whole capacity, the summary, its read-back) captured once, replayed
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool graph_coop = false;         // the captured kernel node is a cooperative launch
   int capacity = 0;                // co-resident workgroups of k_serve
   int free_wg = 0;
   std::vector<int64_t> slot_req;   // request resident in each slot, or -1
@@ -290,6 +297,55 @@ meg_status setup_instance(meg_server s, const meg_request& q, const double* V0, 
   return MEG_OK;
 }
 
+// Capture the per-round sequence once: slot table, team table (whole
+// capacity) and launch parameters copied from their pinned host mirrors,
+// the batched kernel over the whole capacity (workgroups without a team
+// exit at once), the summary kernel and its read-back.  The kernel node is
+// a cooperative launch when the runtime captures one, else an ordinary
+// launch of no more workgroups than are co-resident.
+meg_status capture_graph(meg_server s) {
+  for (int attempt = 0; attempt < 2 && !s->graph_exec; ++attempt) {
+    const bool coop = attempt == 0;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return fail(s);
+    bool ok = hipMemcpyAsync(s->d_slots, s->h_slots, sizeof(Slot<float>) * (kMaxSlots + 1), hipMemcpyHostToDevice,
+                             s->stream) == hipSuccess &&
+              hipMemcpyAsync(s->d_team, s->h_team, sizeof(int2) * s->capacity, hipMemcpyHostToDevice, s->stream) ==
+                  hipSuccess &&
+              hipMemcpyAsync(s->d_prm, s->h_prm, sizeof(ServeParams), hipMemcpyHostToDevice, s->stream) ==
+                  hipSuccess;
+    if (ok) {
+      void* args[] = {&s->d_slots, &s->d_team, &s->d_prm};
+      if (coop) {
+        ok = hipLaunchCooperativeKernel(serve_kernel(), dim3(s->capacity), dim3(kNT), args, 0, s->stream) ==
+             hipSuccess;
+      } else {
+        hipLaunchKernelGGL((k_serve<float, kKB, OP_DENSE_X3, kNT>), dim3(s->capacity), dim3(kNT), 0, s->stream,
+                           s->d_slots, s->d_team, s->d_prm);
+        ok = hipGetLastError() == hipSuccess;
+      }
+    }
+    if (ok) {
+      hipLaunchKernelGGL((k_serve_summary<float>), dim3((kMaxSlots + 1 + 255) / 256), dim3(256), 0, s->stream,
+                         s->d_slots, kMaxSlots + 1, s->d_sum);
+      ok = hipGetLastError() == hipSuccess &&
+           hipMemcpyAsync(s->h_sum, s->d_sum, sizeof(SlotSummary) * (kMaxSlots + 1), hipMemcpyDeviceToHost,
+                          s->stream) == hipSuccess;
+    }
+    const bool ended = hipStreamEndCapture(s->stream, &g) == hipSuccess;
+    (void)hipGetLastError();
+    if (ok && ended && g && hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0) == hipSuccess) {
+      s->graph = g;
+      s->graph_coop = coop;
+    } else {
+      if (g) (void)hipGraphDestroy(g);
+      s->graph_exec = nullptr;
+      (void)hipGetLastError();
+    }
+  }
+  return s->graph_exec ? MEG_OK : fail(s);
+}
+
 // one launch of the batched kernel over the slots listed, at most `steps`
 // each, within a time budget (ms, <= 0: none); returns the HIP-event time in ms
 meg_status launch_serve(meg_server s, const std::vector<int>& slots, const std::vector<int>& steps, double* ms,
@@ -301,20 +357,32 @@ meg_status launch_serve(meg_server s, const std::vector<int>& slots, const std::
     for (int k = 0; k < sl.nwg; ++k) s->h_team[w++] = make_int2(slots[i], k);
   }
   if (w == 0) return MEG_OK;
-  SCHK(s, hipMemcpyAsync(s->d_slots, s->h_slots, sizeof(Slot<float>) * (kMaxSlots + 1), hipMemcpyHostToDevice,
-                         s->stream));
-  SCHK(s, hipMemcpyAsync(s->d_team, s->h_team, sizeof(int2) * w, hipMemcpyHostToDevice, s->stream));
-  SCHK(s, hipEventRecord(s->ev_a, s->stream));
-  int64_t seq = ++s->launch_seq;
-  long long budget = budget_ms > 0.0 ? (long long)(budget_ms * 1e-3 * kWallClockHz) : 0;
-  void* args[] = {&s->d_slots, &s->d_team, &seq, &budget};
-  SCHK(s, hipLaunchCooperativeKernel(serve_kernel(), dim3(w), dim3(kNT), args, 0, s->stream));
-  SCHK(s, hipEventRecord(s->ev_b, s->stream));
-  hipLaunchKernelGGL((k_serve_summary<float>), dim3((kMaxSlots + 1 + 255) / 256), dim3(256), 0, s->stream,
-                     s->d_slots, kMaxSlots + 1, s->d_sum);
-  SCHK(s, hipGetLastError());
-  SCHK(s, hipMemcpyAsync(s->h_sum, s->d_sum, sizeof(SlotSummary) * (kMaxSlots + 1), hipMemcpyDeviceToHost,
-                         s->stream));
+  s->h_prm->seq = ++s->launch_seq;
+  s->h_prm->budget = budget_ms > 0.0 ? (long long)(budget_ms * 1e-3 * kWallClockHz) : 0;
+  if (s->p.flags & MEG_SERVER_FLAG_GRAPH) {
+    for (int k = w; k < s->capacity; ++k) s->h_team[k] = make_int2(-1, 0);  // idle workgroups exit
+    if (!s->graph_exec) {
+      meg_status st = capture_graph(s);
+      if (st != MEG_OK) return st;
+    }
+    SCHK(s, hipEventRecord(s->ev_a, s->stream));
+    SCHK(s, hipGraphLaunch(s->graph_exec, s->stream));
+    SCHK(s, hipEventRecord(s->ev_b, s->stream));
+  } else {
+    SCHK(s, hipMemcpyAsync(s->d_slots, s->h_slots, sizeof(Slot<float>) * (kMaxSlots + 1), hipMemcpyHostToDevice,
+                           s->stream));
+    SCHK(s, hipMemcpyAsync(s->d_team, s->h_team, sizeof(int2) * w, hipMemcpyHostToDevice, s->stream));
+    SCHK(s, hipMemcpyAsync(s->d_prm, s->h_prm, sizeof(ServeParams), hipMemcpyHostToDevice, s->stream));
+    SCHK(s, hipEventRecord(s->ev_a, s->stream));
+    void* args[] = {&s->d_slots, &s->d_team, &s->d_prm};
+    SCHK(s, hipLaunchCooperativeKernel(serve_kernel(), dim3(w), dim3(kNT), args, 0, s->stream));
+    SCHK(s, hipEventRecord(s->ev_b, s->stream));
+    hipLaunchKernelGGL((k_serve_summary<float>), dim3((kMaxSlots + 1 + 255) / 256), dim3(256), 0, s->stream,
+                       s->d_slots, kMaxSlots + 1, s->d_sum);
+    SCHK(s, hipGetLastError());
+    SCHK(s, hipMemcpyAsync(s->h_sum, s->d_sum, sizeof(SlotSummary) * (kMaxSlots + 1), hipMemcpyDeviceToHost,
+                           s->stream));
+  }
   SCHK(s, hipStreamSynchronize(s->stream));
   float e = 0.f;
   SCHK(s, hipEventElapsedTime(&e, s->ev_a, s->ev_b));
@@ -328,6 +396,10 @@ meg_status launch_serve(meg_server s, const std::vector<int>& slots, const std::
 // workgroup).  Latency choice: the smallest P within 15 % of the fastest;
 // throughput choice: the least workgroup time P t(P) per iteration.
 meg_status tune(meg_server s, int64_t n, int* lat, int* thr) {
+  if (s->p.fixed_team > 0) {  // set by the caller: no tuning
+    *lat = *thr = std::min(s->p.fixed_team, max_team(s, n));
+    return MEG_OK;
+  }
   auto it = s->team.find(n);
   if (it != s->team.end()) {
     *lat = it->second.lat;
@@ -539,7 +611,8 @@ meg_status meg_server_create(meg_server* out, const meg_server_params* params, v
   if (!out || !params) return MEG_ERR_INVALID_ARG;
   *out = nullptr;
   if (params->launch_steps < 1 || params->launch_steps > 1024 || params->max_resident < 1 ||
-      params->max_resident > kMaxSlots || params->budget_bytes < 0 || params->flags != 0)
+      params->max_resident > kMaxSlots || params->budget_bytes < 0 || (params->flags & ~MEG_SERVER_FLAG_GRAPH) != 0 ||
+      params->fixed_team < 0 || params->fixed_team > kBarGroupSize * kBarMaxGroups)
     return MEG_ERR_INVALID_ARG;
   int dev = 0, coop = 0, ncu = 0, occ = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -549,6 +622,7 @@ meg_status meg_server_create(meg_server* out, const meg_server_params* params, v
     (void)hipGetLastError();
     return MEG_ERR_DEVICE;
   }
+  if ((params->flags & MEG_SERVER_FLAG_GRAPH) && !stream) return MEG_ERR_INVALID_ARG;  // capture needs a stream
   meg_server s = new (std::nothrow) meg_server_s();
   if (!s) return MEG_ERR_OUT_OF_MEMORY;
   s->p = *params;
@@ -561,6 +635,8 @@ meg_status meg_server_create(meg_server* out, const meg_server_params* params, v
             hipMalloc((void**)&s->d_slots, sizeof(Slot<float>) * (kMaxSlots + 1)) == hipSuccess &&
             hipMalloc((void**)&s->d_team, sizeof(int2) * s->capacity) == hipSuccess &&
             hipMalloc((void**)&s->d_sum, sizeof(SlotSummary) * (kMaxSlots + 1)) == hipSuccess &&
+            hipMalloc((void**)&s->d_prm, sizeof(ServeParams)) == hipSuccess &&
+            hipHostMalloc((void**)&s->h_prm, sizeof(ServeParams)) == hipSuccess &&
             hipHostMalloc((void**)&s->h_slots, sizeof(Slot<float>) * (kMaxSlots + 1)) == hipSuccess &&
             hipHostMalloc((void**)&s->h_team, sizeof(int2) * s->capacity) == hipSuccess &&
             hipHostMalloc((void**)&s->h_sum, sizeof(SlotSummary) * (kMaxSlots + 1)) == hipSuccess &&
@@ -573,6 +649,9 @@ meg_status meg_server_create(meg_server* out, const meg_server_params* params, v
   s->arena.init(budget);
   for (int i = 0; i <= kMaxSlots; ++i) s->h_slots[i] = Slot<float>{};
   std::memset(s->h_sum, 0, sizeof(SlotSummary) * (kMaxSlots + 1));
+  for (int k = 0; k < s->capacity; ++k) s->h_team[k] = make_int2(-1, 0);
+  s->h_prm->seq = 0;
+  s->h_prm->budget = 0;
   s->t0 = std::chrono::steady_clock::now();
   *out = s;
   return MEG_OK;
@@ -714,6 +793,7 @@ meg_status meg_server_get_stats(meg_server s, meg_server_stats* out) {
   out->resident = res;
   out->queued = (int32_t)s->queue.size();
   out->capacity_wg = s->capacity;
+  out->graph_node = s->graph_exec ? (s->graph_coop ? 1 : 2) : 0;
   out->arena_bytes = (int64_t)s->arena.size;
   out->arena_used = (int64_t)s->arena.used;
   out->arena_peak = (int64_t)s->arena.peak;
@@ -723,6 +803,10 @@ meg_status meg_server_get_stats(meg_server s, meg_server_stats* out) {
 void meg_server_destroy(meg_server s) {
   if (!s) return;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->d_prm) (void)hipFree(s->d_prm);
+  if (s->h_prm) (void)hipHostFree(s->h_prm);
   if (s->arena_base) (void)hipFree(s->arena_base);
   if (s->d_slots) (void)hipFree(s->d_slots);
   if (s->d_team) (void)hipFree(s->d_team);

@@ -42,6 +42,7 @@ MEG_GRAD_QUADMEAS = 4
 
 MEG_FLAG_STRICT = 1
 MEG_FLAG_NO_LDS_CACHE = 2
+MEG_SERVER_FLAG_GRAPH = 1
 
 EXPORTED = [
     "meg_block_size", "meg_init", "meg_step", "meg_solve", "meg_certificate", "meg_objective_value",
@@ -106,7 +107,7 @@ class MegCounters(ctypes.Structure):
 
 class MegServerParams(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("launch_steps", ctypes.c_int32),
-                ("max_resident", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+                ("max_resident", ctypes.c_int32), ("flags", ctypes.c_uint32), ("fixed_team", ctypes.c_int32)]
 
 
 class MegRequest(ctypes.Structure):
@@ -131,7 +132,7 @@ class MegServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("launches", ctypes.c_int64), ("iterations", ctypes.c_int64), ("kernel_ms", ctypes.c_double),
                 ("resident", ctypes.c_int32), ("queued", ctypes.c_int32), ("capacity_wg", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("arena_bytes", ctypes.c_int64), ("arena_used", ctypes.c_int64),
+                ("graph_node", ctypes.c_int32), ("arena_bytes", ctypes.c_int64), ("arena_used", ctypes.c_int64),
                 ("arena_peak", ctypes.c_int64)]
 
 
@@ -394,7 +395,7 @@ class MegServer:
     """
 
     def __init__(self, budget_bytes: int = 0, launch_steps: int = 8, max_resident: int = 256,
-                 stream: Optional[int] = None):
+                 graph: bool = False, fixed_team: int = 0, stream: Optional[int] = None):
         import torch
 
         if not torch.cuda.is_available():
@@ -405,7 +406,8 @@ class MegServer:
             stream = self._torch_stream.cuda_stream
         self.stream = stream
         p = MegServerParams(budget_bytes=int(budget_bytes), launch_steps=int(launch_steps),
-                            max_resident=int(max_resident), flags=0, reserved=0)
+                            max_resident=int(max_resident), flags=MEG_SERVER_FLAG_GRAPH if graph else 0,
+                            fixed_team=int(fixed_team))
         h = ctypes.c_void_p()
         _check(self._lib.meg_server_create(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(stream)),
                "meg_server_create")

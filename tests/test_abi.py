@@ -61,12 +61,13 @@ int main(void) {
   O(meg_objective, batch_steps) O(meg_start, V0) O(meg_start, lambda0)
   O(meg_step_info, cert_holds) O(meg_step_info, ritz_gap) O(meg_step_info, converged) O(meg_step_info, resid_r1)
   P(meg_server_params) P(meg_request) P(meg_request_status) P(meg_server_stats)
-  O(meg_server_params, max_resident) O(meg_server_params, flags)
+  O(meg_server_params, max_resident) O(meg_server_params, flags) O(meg_server_params, fixed_team)
   O(meg_request, n) O(meg_request, M) O(meg_request, q) O(meg_request, V0) O(meg_request, eta)
   O(meg_request, tol) O(meg_request, max_inner) O(meg_request, seed)
   O(meg_request_status, iterations) O(meg_request_status, done_ms) O(meg_request_status, team)
   O(meg_request_status, last) O(meg_request_status, applies)
-  O(meg_server_stats, kernel_ms) O(meg_server_stats, capacity_wg) O(meg_server_stats, arena_peak)
+  O(meg_server_stats, kernel_ms) O(meg_server_stats, capacity_wg) O(meg_server_stats, graph_node)
+  O(meg_server_stats, arena_peak)
   return 0;
 }
 """
@@ -202,7 +203,8 @@ def test_server_null_handle_and_bad_params(M):
     h = ctypes.c_void_p()
     for kw in (dict(launch_steps=0, max_resident=8), dict(launch_steps=8, max_resident=0),
                dict(launch_steps=8, max_resident=257), dict(launch_steps=2000, max_resident=8),
-               dict(launch_steps=8, max_resident=8, budget_bytes=-1), dict(launch_steps=8, max_resident=8, flags=1)):
+               dict(launch_steps=8, max_resident=8, budget_bytes=-1), dict(launch_steps=8, max_resident=8, flags=2),
+               dict(launch_steps=8, max_resident=8, fixed_team=-1)):
         p = M.MegServerParams(**kw)
         assert lib.meg_server_create(ctypes.byref(h), ctypes.byref(p), None) == M.MEG_ERR_INVALID_ARG, kw
         assert not h.value

@@ -201,3 +201,33 @@ def test_serving_stop_rule_and_rejects(meg):
         with pytest.raises(meg.MegError) as e:
             srv.submit(dM, V, np.array([0.5]), r)  # weights do not sum to 1
         assert e.value.status == meg.MEG_ERR_INVALID_ARG
+
+
+def test_serving_graph_replay_matches_direct_launches(meg):
+    """Graph mode (one captured round replayed with new tables each time,
+    host work between replays) gives bitwise the results of direct
+    cooperative launches, for every instance of a mix."""
+    import torch
+
+    specs = [(256, 2, 11), (384, 4, 9), (520, 6, 13), (1000, 3, 7), (300, 8, 10)]
+    inst = [(_instance(30 + i, n, r), n, r, it) for i, (n, r, it) in enumerate(specs)]
+    keep = [device_f32(M) for (M, _, _), _, _, _ in inst]
+    torch.cuda.synchronize()
+    out = {}
+    for graph in (False, True):
+        print_case(test="serving_graph", graph=graph)
+        with meg.MegServer(launch_steps=2, graph=graph, fixed_team=2) as srv:
+            ids = [srv.submit(keep[i], V, l, r, max_iters=it, seed=i)
+                   for i, ((M, V, l), n, r, it) in enumerate(inst)]
+            rounds = 0
+            while srv.run(1) > 0:
+                rounds += 1
+            assert rounds >= 3  # several replays
+            if graph:
+                print(f"  graph node: {srv.stats()['graph_node']} (1 cooperative, 2 ordinary)", flush=True)
+                assert srv.stats()["graph_node"] in (1, 2)
+            out[graph] = [(srv.result(rid, n, r), srv.query(rid)) for rid, (_, n, r, _) in zip(ids, inst)]
+    for (ra, sa), (rb, sb) in zip(out[False], out[True]):
+        assert sa["iterations"] == sb["iterations"] and sa["team"] == sb["team"] == 2
+        assert np.array_equal(ra[0], rb[0]) and np.array_equal(ra[1], rb[1]) and ra[2] == rb[2]
+        assert sa["last"]["cert_L"] == sb["last"]["cert_L"]
