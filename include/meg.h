@@ -70,10 +70,13 @@ typedef enum {
   MEG_GRAD_MASKED_CSR = 3,    /* f = 1/2 sum_{(i,j) in Omega} (X_ij - M_ij)^2,
                                  Omega symmetric, both (i,j) and (j,i) stored;
                                  grad f = P_Omega(X - M)                       */
-  MEG_GRAD_QUADMEAS = 4       /* f = 1/(2m) sum_i (a_i^T X a_i - b_i)^2; each
+  MEG_GRAD_QUADMEAS = 4,      /* f = 1/(2m) sum_i (a_i^T X a_i - b_i)^2; each
                                  step uses the minibatch estimate
                                  (1/L) sum_{i in B_t} (a_i^T X a_i - b_i) a_i a_i^T
                                  (Section 6, stochastic oracle)                */
+  MEG_GRAD_EXTERNAL = 5       /* the caller supplies the gradient (or an
+                                 unbiased estimate of it, Section 6) at X_t
+                                 for every step: meg_step_external         */
 } meg_grad_kind;
 
 #define MEG_FLAG_STRICT 1u   /* inner non-convergence -> MEG_ERR_NOT_CONVERGED */
@@ -175,6 +178,18 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
  * (asynchronous; f is not evaluated).  info != NULL: also evaluate f(X_t),
  * synchronise and fill *info. */
 meg_status meg_step(meg_ctx ctx, meg_step_info* info);
+
+/* One iteration t of Algorithm 2 with a caller-supplied gradient G_t at the
+ * current iterate X_t (read it with meg_get_iterate), for a context created
+ * with kind MEG_GRAD_EXTERNAL: M_t = log X_t - eta G_t.  `grad` describes
+ * G_t as a symmetric operator: kind MEG_GRAD_LINEAR_DENSE (dense, ld) or
+ * MEG_GRAD_LINEAR_CSR (row_ptr, col, val, nnz), in the state's type (F64 or
+ * F32; the bf16-plane form is not offered here).  Its DEVICE arrays are
+ * read during the call only: the call synchronises the stream before it
+ * returns.  The solver's shift bounds lambda_max(G_t) by Gershgorin's
+ * theorem (one pass over G_t).  info (optional) as meg_step, with f = NaN.
+ * meg_step and meg_solve return MEG_ERR_INVALID_ARG on such a context. */
+meg_status meg_step_external(meg_ctx ctx, const meg_objective* grad, meg_step_info* info);
 
 /* Up to max_iters iterations; stops early after the first step whose
  * certificate bound max(2 eps_t, cert_L) is <= tol (tol <= 0: never).

@@ -66,6 +66,7 @@ struct meg_ctx_s {
   int P = 1;               // persistent grid size
   int aux_nwg = 1;         // row-parallel auxiliary kernels
   Ctl* h_ctl = nullptr;    // pinned host mirror
+  bool external = false;   // the caller supplies G_t every step (meg_step_external)
   bool failed = false;
 };
 
@@ -597,6 +598,9 @@ meg_status validate(const meg_params* p, const meg_objective* o, const meg_start
       if (o->nnz > 2147483647LL) return MEG_ERR_INVALID_ARG;
       if (p->prec == MEG_PREC_F32_BF16X3) return MEG_ERR_UNSUPPORTED;
       break;
+    case MEG_GRAD_EXTERNAL:
+      if (p->prec == MEG_PREC_F32_BF16X3) return MEG_ERR_UNSUPPORTED;
+      break;
     case MEG_GRAD_QUADMEAS: {
       if (!o->A || !o->b || !o->batch_idx || o->m < 1 || o->lda < p->n || o->batch_steps < 1) return MEG_ERR_INVALID_ARG;
       if (o->batch < 1 || o->batch > kMaxBatch) return MEG_ERR_INVALID_ARG;
@@ -701,6 +705,10 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
   cfg.inner_tol = params->inner_tol > 0 ? params->inner_tol : (c->esize == 8 ? 1e-10 : 1e-6);
   cfg.unit_round = (c->esize == 8) ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
   cfg.cert_tol = params->cert_tol;
+  if (obj->kind == MEG_GRAD_EXTERNAL) {  // the operator family is chosen per step; dense until then
+    c->external = true;
+    cfg.kind = LINEAR_DENSE;
+  }
 
   int coop = 0, dev = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -710,6 +718,11 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
     return MEG_ERR_DEVICE;
   }
   c->P = dispatch<DoGrid>(c);
+  if (c->external) {  // a grid that both operator families can launch cooperatively
+    cfg.kind = LINEAR_CSR;
+    c->P = std::min(c->P, dispatch<DoGrid>(c));
+    cfg.kind = LINEAR_DENSE;
+  }
   if (c->P < 1) {
     delete c;
     return MEG_ERR_DEVICE;
@@ -785,12 +798,12 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
   // data norm (sets ctl->data_norm) and the extreme eigenvalues of the data
   // operator (shift of the subspace iteration); the factored gradient
   // changes every step and bounds its spectrum inside the step instead
-  if (obj->kind != MEG_GRAD_QUADMEAS &&
-      (dispatch<DoNorm>(c) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)) {
+  const bool has_data = obj->kind != MEG_GRAD_QUADMEAS && obj->kind != MEG_GRAD_EXTERNAL;
+  if (has_data && (dispatch<DoNorm>(c) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)) {
     free_ctx(c);
     return MEG_ERR_DEVICE;
   }
-  if (obj->kind != MEG_GRAD_QUADMEAS) {
+  if (has_data) {
     double lmin = 0.0, lmax = 0.0;
     st = (c->esize == 8) ? lanczos_extremes<double>(c, &lmin, &lmax) : lanczos_extremes<float>(c, &lmin, &lmax);
     if (st == MEG_OK) st = copy_ctl_to_host(c);
@@ -821,6 +834,7 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
 meg_status meg_step(meg_ctx c, meg_step_info* info) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
+  if (c->external) return MEG_ERR_INVALID_ARG;
   // f(X_t): the masked objective's gradient phase computes it in the step
   if (info && c->cfg.kind != MASKED_CSR) HIPCHK(c, dispatch<DoObjective>(c));
   HIPCHK(c, launch_steps(c, 1));
@@ -834,9 +848,85 @@ meg_status meg_step(meg_ctx c, meg_step_info* info) {
   return MEG_OK;
 }
 
+meg_status meg_step_external(meg_ctx c, const meg_objective* grad, meg_step_info* info) {
+  meg_status st = check_ctx(c);
+  if (st != MEG_OK) return st;
+  if (!c->external || !grad) return MEG_ERR_INVALID_ARG;
+  Cfg& cfg = c->cfg;
+  const int64_t n = cfg.n;
+  if (grad->kind == MEG_GRAD_LINEAR_DENSE) {
+    if (!grad->dense || grad->ld < n) return MEG_ERR_INVALID_ARG;
+  } else if (grad->kind == MEG_GRAD_LINEAR_CSR) {
+    if (!grad->row_ptr || grad->nnz < 0 || grad->nnz > 2147483647LL || (grad->nnz > 0 && (!grad->col || !grad->val)))
+      return MEG_ERR_INVALID_ARG;
+    // structure check before any kernel reads through the indices
+    int h_err = 0;
+    int* d_err = (int*)c->sums;
+    HIPCHK(c, hipMemsetAsync(d_err, 0, sizeof(int), c->stream));
+    hipLaunchKernelGGL(k_check_csr, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0,
+                       c->stream, grad->row_ptr, grad->col, n, grad->nnz, d_err);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost));
+    if (h_err) return MEG_ERR_INVALID_ARG;
+  } else {
+    return MEG_ERR_UNSUPPORTED;
+  }
+  // this step's operator
+  if (grad->kind == MEG_GRAD_LINEAR_DENSE) {
+    c->obj.dense = grad->dense;
+    c->obj.ld = grad->ld;
+    cfg.ld = grad->ld;
+    cfg.kind = LINEAR_DENSE;
+  } else {
+    c->obj.row_ptr = grad->row_ptr;
+    c->obj.col = grad->col;
+    c->obj.val = grad->val;
+    c->obj.nnz = grad->nnz;
+    cfg.nnz = grad->nnz;
+    cfg.kind = LINEAR_CSR;
+  }
+  cfg.cache_blocks = 0;  // the pattern may change from step to step
+  cfg.cache_nnz = 0;
+  // Gershgorin bounds of G_t, then the shift and coefficients of this step
+  const int gw = (int)std::max<int64_t>(1, std::min<int64_t>(512, (n + 3) / 4));
+  const bool dbl = c->esize == 8;
+  if (cfg.kind == LINEAR_DENSE) {
+    if (dbl)
+      hipLaunchKernelGGL((k_gersh_dense<double>), dim3(gw), dim3(256), 0, c->stream, (const double*)grad->dense, n,
+                         grad->ld, c->part);
+    else
+      hipLaunchKernelGGL((k_gersh_dense<float>), dim3(gw), dim3(256), 0, c->stream, (const float*)grad->dense, n,
+                         grad->ld, c->part);
+  } else {
+    if (dbl)
+      hipLaunchKernelGGL((k_gersh_csr<double>), dim3(gw), dim3(256), 0, c->stream, grad->row_ptr, grad->col,
+                         (const double*)grad->val, n, c->part);
+    else
+      hipLaunchKernelGGL((k_gersh_csr<float>), dim3(gw), dim3(256), 0, c->stream, grad->row_ptr, grad->col,
+                         (const float*)grad->val, n, c->part);
+  }
+  hipLaunchKernelGGL(k_external_setup, dim3(1), dim3(64), 0, c->stream, cfg, c->ctl, c->part, gw);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, launch_steps(c, 1));
+  // the caller's arrays are read during the call only
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  st = copy_ctl_to_host(c);
+  if (st == MEG_OK) st = check_barrier(c);
+  if (st != MEG_OK) return st;
+  if (info) {
+    fill_info(*c->h_ctl, info);
+    info->f = __builtin_nan("");
+  }
+  if (c->h_ctl->status) return (meg_status)c->h_ctl->status;
+  if (info && (c->params.flags & MEG_FLAG_STRICT) && !info->converged) return MEG_ERR_NOT_CONVERGED;
+  return MEG_OK;
+}
+
 meg_status meg_solve(meg_ctx c, int64_t max_iters, double tol, meg_step_info* last) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
+  if (c->external) return MEG_ERR_INVALID_ARG;
   if (max_iters < 0) return MEG_ERR_INVALID_ARG;
   // arm the device-side stop rule
   st = copy_ctl_to_host(c);
@@ -888,6 +978,7 @@ meg_status meg_certificate(meg_ctx c, meg_step_info* out) {
 meg_status meg_objective_value(meg_ctx c, double* f) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
+  if (c->external) return MEG_ERR_UNSUPPORTED;  // f is the caller's
   if (!f) return MEG_ERR_INVALID_ARG;
   HIPCHK(c, dispatch<DoObjective>(c));
   st = copy_ctl_to_host(c);

@@ -31,7 +31,7 @@ template <typename T>
 using gbl = __attribute__((address_space(1))) T;
 
 // Objective kinds (mirror meg_grad_kind).
-enum Kind : int32_t { LINEAR_DENSE = 0, DENOISE_DENSE = 1, LINEAR_CSR = 2, MASKED_CSR = 3, QUADMEAS = 4 };
+enum Kind : int32_t { LINEAR_DENSE = 0, DENOISE_DENSE = 1, LINEAR_CSR = 2, MASKED_CSR = 3, QUADMEAS = 4, EXTERNAL = 5 };
 
 // Immutable per-context configuration, passed by value to every kernel.
 struct Cfg {

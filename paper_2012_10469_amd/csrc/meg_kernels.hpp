@@ -195,7 +195,9 @@ __device__ void load_csr_cache(const Cfg& cfg, const Data<T>& dat, const CsrCach
 //            from the previous step), or ||P(X_t)||_2 <= ||X_t||_F with
 //            ||X_t||_F^2 = (n - r) alpha^2 + sum_l (alpha + d_l)^2 after a new start
 // so the shift needs no pass over the data and the gradient can be formed
-// inside the first sweep.
+// inside the first sweep.  A caller-supplied G_t (external gradient) is a
+// linear operator for the step: lambda_max is its Gershgorin bound, from one
+// pass over G_t before the step (k_gersh_dense / k_gersh_csr).
 // ---------------------------------------------------------------------------
 __device__ inline void step_scalars(const Cfg& cfg, gbl<Ctl>* ctl, int lane) {
   // the minibatch gradient's bound is known only inside sweep 1 (factor_shift)
@@ -455,24 +457,36 @@ __device__ __noinline__ void factor_rows(int64_t n, int64_t lda, int64_t m, int 
 #pragma unroll
     for (int c = 0; c < KB; ++c) acc[c] = 0;
     double sa = 0.0;
-    for (int64_t j0 = (int64_t)VN * tid; j0 < n; j0 += (int64_t)VN * NT) {
-      T av[VN];
-      if (j0 + VN <= n) {
-        vload_g<T>(a + j0, av);
-      } else {
+    // GU groups of VN elements per iteration, all their loads issued first
+    // (GU = 2 spills at k = 16; the compiler overlaps iterations by itself)
+    constexpr int GU = 1;
+    for (int64_t j0 = (int64_t)VN * tid; j0 < n; j0 += (int64_t)GU * VN * NT) {
+      T av[GU][VN];
+      T z[GU][VN][KB];
 #pragma unroll
-        for (int e = 0; e < VN; ++e) av[e] = (j0 + e < n) ? a[j0 + e] : (T)0;
+      for (int h = 0; h < GU; ++h) {
+        const int64_t jh = j0 + (int64_t)h * VN * NT;
+        if (jh + VN <= n) {
+          vload_g<T>(a + jh, av[h]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < VN; ++e) av[h][e] = (jh + e < n) ? a[jh + e] : (T)0;
+        }
+#pragma unroll
+        for (int e = 0; e < VN; ++e) {
+          const int64_t j = (jh + e < n) ? jh + e : n - 1;  // av = 0 past n
+#pragma unroll
+          for (int q = 0; q < KB / VN; ++q) vload_g<T>(Zin + j * KB + q * VN, z[h][e] + q * VN);
+        }
       }
 #pragma unroll
-      for (int e = 0; e < VN; ++e) {
-        const int64_t j = (j0 + e < n) ? j0 + e : n - 1;  // av[e] = 0 past n
-        T z[KB];
+      for (int h = 0; h < GU; ++h)
 #pragma unroll
-        for (int q = 0; q < KB / VN; ++q) vload_g<T>(Zin + j * KB + q * VN, z + q * VN);
+        for (int e = 0; e < VN; ++e) {
 #pragma unroll
-        for (int c = 0; c < KB; ++c) acc[c] += av[e] * z[c];
-        sa += (double)av[e] * (double)av[e];
-      }
+          for (int c = 0; c < KB; ++c) acc[c] += av[h][e] * z[h][e][c];
+          sa += (double)av[h][e] * (double)av[h][e];
+        }
     }
 #pragma unroll
     for (int st = 0; (KB >> st) > 1; ++st) {
@@ -675,20 +689,23 @@ __device__ __noinline__ void factor_cols(int64_t n, int64_t lda, int64_t m, int 
     for (int e = tid; e < cnt * KB; e += NT) ys[e] = qy[(int64_t)i0 * KB + e];
     for (int e = tid; e < cnt; e += NT) is[e] = pool_row(idx[i0 + e], m) * lda;
     __syncthreads();
-    int ii = sl;
-    for (; ii + 3 * SL < cnt; ii += 4 * SL) {
-      T a[4];
+    // UB loads in flight per thread (all of a 256-row chunk's share at
+    // NT / ROWS = 16 slices), clamped into the chunk and masked past its end
+    constexpr int UB = CH / SL;
+    for (int ii = sl; ii < cnt; ii += UB * SL) {
+      T a[UB];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = A[is[ii + u * SL] + col] * msk;
+      for (int u = 0; u < UB; ++u) {
+        const int iu = ii + u * SL;
+        const bool ok = iu < cnt;
+        a[u] = A[is[ok ? iu : cnt - 1] + col] * (ok ? msk : (T)0);
+      }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < UB; ++u) {
+        const int iu = ii + u * SL < cnt ? ii + u * SL : cnt - 1;
 #pragma unroll
-        for (int c = 0; c < KB; ++c) acc[c] += a[u] * ys[(ii + u * SL) * KB + c];
-    }
-    for (; ii < cnt; ii += SL) {
-      const T a = A[is[ii] + col] * msk;
-#pragma unroll
-      for (int c = 0; c < KB; ++c) acc[c] += a * ys[ii * KB + c];
+        for (int c = 0; c < KB; ++c) acc[c] += a[u] * ys[iu * KB + c];
+      }
     }
   }
 #pragma unroll
@@ -1662,6 +1679,89 @@ static __global__ __launch_bounds__(256) void k_serve_summary(const Slot<T>* __r
   s.reserved = 0;
   s.info = c->info;
   out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// caller-supplied gradient: Gershgorin bounds of G_t (per workgroup min of
+// g_ii - sum_{j != i} |g_ij| and max of g_ii + sum_{j != i} |g_ij|, FP64
+// sums, one wave per row) -> part[2 wg], part[2 wg + 1]; then the step
+// scalars of the step with those bounds
+// ---------------------------------------------------------------------------
+template <typename T>
+static __global__ __launch_bounds__(256) void k_gersh_dense(const T* __restrict__ D, int64_t n, int64_t ld,
+                                                            double* __restrict__ part) {
+  __shared__ double sl[4], sh[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double lmin = __builtin_inf(), lmax = -__builtin_inf();
+  for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < n; i += (int64_t)gridDim.x * 4) {
+    double off = 0.0, dg = 0.0;
+    for (int64_t j = lane; j < n; j += 64) {
+      const double v = (double)D[i * ld + j];
+      if (j == i) dg = v; else off += fabs(v);
+    }
+    off = wave_sum(off);
+    dg = wave_sum(dg);
+    lmin = fmin(lmin, dg - off);
+    lmax = fmax(lmax, dg + off);
+  }
+  if (lane == 0) {
+    sl[wave] = lmin;
+    sh[wave] = lmax;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    part[2 * blockIdx.x] = fmin(fmin(sl[0], sl[1]), fmin(sl[2], sl[3]));
+    part[2 * blockIdx.x + 1] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  }
+}
+
+template <typename T>
+static __global__ __launch_bounds__(256) void k_gersh_csr(const int* __restrict__ rp, const int* __restrict__ col,
+                                                          const T* __restrict__ val, int64_t n,
+                                                          double* __restrict__ part) {
+  __shared__ double sl[4], sh[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double lmin = __builtin_inf(), lmax = -__builtin_inf();
+  for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < n; i += (int64_t)gridDim.x * 4) {
+    double off = 0.0, dg = 0.0;
+    for (int e = rp[i] + lane; e < rp[i + 1]; e += 64) {
+      const double v = (double)val[e];
+      if (col[e] == i) dg += v; else off += fabs(v);
+    }
+    off = wave_sum(off);
+    dg = wave_sum(dg);
+    lmin = fmin(lmin, dg - off);
+    lmax = fmax(lmax, dg + off);
+  }
+  if (lane == 0) {
+    sl[wave] = lmin;
+    sh[wave] = lmax;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    part[2 * blockIdx.x] = fmin(fmin(sl[0], sl[1]), fmin(sl[2], sl[3]));
+    part[2 * blockIdx.x + 1] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  }
+}
+
+// op_lmin/op_lmax of this step's G_t from the partial bounds, then the step
+// scalars (shift and coefficients) for it; one wavefront
+static __global__ __launch_bounds__(64) void k_external_setup(Cfg cfg, Ctl* __restrict__ ctl,
+                                                              const double* __restrict__ part, int nwg) {
+  const int lane = threadIdx.x;
+  double lmin = __builtin_inf(), lmax = -__builtin_inf();
+  for (int w = lane; w < nwg; w += 64) {
+    lmin = fmin(lmin, part[2 * w]);
+    lmax = fmax(lmax, part[2 * w + 1]);
+  }
+  lmin = wave_min(lmin);
+  lmax = wave_max(lmax);
+  if (lane == 0) {
+    ctl->op_lmin = lmin;
+    ctl->op_lmax = lmax;
+  }
+  wg_fence();
+  step_scalars(cfg, (gbl<Ctl>*)ctl, lane);
 }
 
 // minibatch indices in [0, m)

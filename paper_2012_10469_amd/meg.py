@@ -39,6 +39,7 @@ MEG_GRAD_DENOISE_DENSE = 1
 MEG_GRAD_LINEAR_CSR = 2
 MEG_GRAD_MASKED_CSR = 3
 MEG_GRAD_QUADMEAS = 4
+MEG_GRAD_EXTERNAL = 5
 
 MEG_FLAG_STRICT = 1
 MEG_FLAG_NO_LDS_CACHE = 2
@@ -47,7 +48,7 @@ MEG_SERVER_FLAG_GRAPH = 1
 EXPORTED = [
     "meg_block_size", "meg_init", "meg_step", "meg_solve", "meg_certificate", "meg_objective_value",
     "meg_get_iterate", "meg_set_iterate", "meg_get_state", "meg_set_state", "meg_profile_step", "meg_destroy",
-    "meg_status_str", "meg_get_counters",
+    "meg_status_str", "meg_get_counters", "meg_step_external",
     "meg_server_create", "meg_server_submit", "meg_server_run", "meg_server_query", "meg_server_result",
     "meg_server_release", "meg_server_team", "meg_server_get_stats", "meg_server_destroy",
 ]
@@ -153,6 +154,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "meg_block_size": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
         "meg_init": (ctypes.c_int, [P(vp), P(MegParams), P(MegObjective), P(MegStart), vp]),
         "meg_step": (ctypes.c_int, [vp, P(MegStepInfo)]),
+        "meg_step_external": (ctypes.c_int, [vp, P(MegObjective), P(MegStepInfo)]),
         "meg_solve": (ctypes.c_int, [vp, ctypes.c_int64, ctypes.c_double, P(MegStepInfo)]),
         "meg_certificate": (ctypes.c_int, [vp, P(MegStepInfo)]),
         "meg_objective_value": (ctypes.c_int, [vp, P(ctypes.c_double)]),
@@ -301,6 +303,20 @@ class LowRankMEG:
         out = MegStepInfo()
         _check(self._lib.meg_step(self._ctx, ctypes.byref(out)), "meg_step")
         return out.as_dict()
+
+    def step_external(self, dense=None, row_ptr=None, col=None, val=None, info: bool = True) -> Optional[dict]:
+        """One step with the caller's gradient G_t at the current iterate
+        (context created with kind MEG_GRAD_EXTERNAL): dense n x n, or CSR
+        (row_ptr, col, val), device tensors in the state's type."""
+        if dense is not None:
+            g = MegObjective(kind=MEG_GRAD_LINEAR_DENSE, dense=_dptr(dense), ld=int(dense.stride(0)))
+        else:
+            g = MegObjective(kind=MEG_GRAD_LINEAR_CSR, row_ptr=_dptr(row_ptr), col=_dptr(col), val=_dptr(val),
+                             nnz=int(col.numel()))
+        out = MegStepInfo()
+        _check(self._lib.meg_step_external(self._ctx, ctypes.byref(g), ctypes.byref(out) if info else None),
+               "meg_step_external")
+        return out.as_dict() if info else None
 
     def solve(self, max_iters: int, tol: float = 0.0) -> dict:
         out = MegStepInfo()

@@ -186,6 +186,7 @@ def test_init_rejects_bad_quadmeas(M):
         assert M.meg_init(p, q(**bad), V, lam)[0] == M.MEG_ERR_INVALID_ARG, bad
     p3 = M.make_params(n, 4, prec=M.MEG_PREC_F32_BF16X3)
     assert M.meg_init(p3, q(), V, lam)[0] == M.MEG_ERR_UNSUPPORTED
+    assert M.meg_init(p3, M.MegObjective(kind=M.MEG_GRAD_EXTERNAL), V, lam)[0] == M.MEG_ERR_UNSUPPORTED
     p64 = M.make_params(n, 4, prec=M.MEG_PREC_F64)
     assert M.meg_init(p64, q(lda=65), V, lam)[0] == M.MEG_ERR_INVALID_ARG  # 65 doubles: rows not 16-byte aligned
 
@@ -219,4 +220,6 @@ def test_null_context_calls(M):
     assert lib.meg_certificate(None, ctypes.byref(info)) == M.MEG_ERR_INVALID_ARG
     cnt = M.MegCounters()
     assert lib.meg_get_counters(None, ctypes.byref(cnt), 0) == M.MEG_ERR_INVALID_ARG
+    g = M.MegObjective(kind=M.MEG_GRAD_LINEAR_DENSE, dense=0x1000, ld=64)
+    assert lib.meg_step_external(None, ctypes.byref(g), None) == M.MEG_ERR_INVALID_ARG
     lib.meg_destroy(None)  # no-op
