@@ -406,6 +406,7 @@ def main() -> int:
                      "traffic_note": traffic_note,
                      "bytes_per_launch": nbytes, "avg_launch_us": avg_launch_ms * 1e3,
                      "iterations_per_launch": iters_per_launch, "applies_per_iteration": sweeps,
+                     "jacobi_sweeps_per_iteration": cnt["jacobi_sweeps"] / cnt["iterations"],
                      "launches": launches, "phases": phases},
         "cpu_baseline": base,
         "serving": serving,

@@ -262,7 +262,8 @@ typedef struct {
   int64_t iterations;  /* iterations t -> t+1 they performed                  */
   int64_t applies;     /* operator applies (subspace sweeps) they performed   */
   int32_t workgroups;  /* persistent grid size                                */
-  int32_t reserved;
+  int32_t jacobi_sweeps; /* Jacobi sweeps of their Rayleigh-Ritz solves
+                            (saturates at INT32_MAX)                          */
   double kernel_ms;    /* GPU time of those launches, milliseconds            */
 } meg_counters;
 

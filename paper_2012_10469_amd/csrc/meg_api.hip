@@ -62,7 +62,7 @@ struct meg_ctx_s {
   int ev_head = 0, ev_count = 0;
   double kernel_ms = 0.0;
   int64_t launches = 0;
-  int64_t base_iters = 0, base_applies = 0;  // device counters at the last reset
+  int64_t base_iters = 0, base_applies = 0, base_jacobi = 0;  // device counters at the last reset
   int P = 1;               // persistent grid size
   int aux_nwg = 1;         // row-parallel auxiliary kernels
   Ctl* h_ctl = nullptr;    // pinned host mirror
@@ -1074,10 +1074,11 @@ meg_status meg_set_state(meg_ctx c, const void* buf, size_t bytes) {
     return MEG_ERR_STATE;
   st = copy_ctl_to_host(c);
   if (st != MEG_OK) return st;
-  const int64_t iters = c->h_ctl->iters_done, applies = c->h_ctl->applies_done;
+  const int64_t iters = c->h_ctl->iters_done, applies = c->h_ctl->applies_done, jac = c->h_ctl->jacobi_done;
   std::memcpy(c->h_ctl, p + 32, sizeof(Ctl));
   c->h_ctl->iters_done = iters;  // work counters describe this context, not the blob
   c->h_ctl->applies_done = applies;
+  c->h_ctl->jacobi_done = jac;
   HIPCHK(c, hipMemcpyAsync(c->ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
   if (c->h_ctl->src < 0 || c->h_ctl->src > 2) return MEG_ERR_STATE;
   HIPCHK(c, hipMemcpyAsync(block(c, c->h_ctl->src), p + 32 + sizeof(Ctl), qbytes, hipMemcpyHostToDevice, c->stream));
@@ -1171,12 +1172,14 @@ meg_status meg_get_counters(meg_ctx c, meg_counters* out, int32_t reset) {
   out->iterations = c->h_ctl->iters_done - c->base_iters;
   out->applies = c->h_ctl->applies_done - c->base_applies;
   out->workgroups = c->P;
+  out->jacobi_sweeps = (int32_t)std::min<int64_t>(c->h_ctl->jacobi_done - c->base_jacobi, INT32_MAX);
   out->kernel_ms = c->kernel_ms;
   if (reset) {
     c->launches = 0;
     c->kernel_ms = 0.0;
     c->base_iters = c->h_ctl->iters_done;
     c->base_applies = c->h_ctl->applies_done;
+    c->base_jacobi = c->h_ctl->jacobi_done;
   }
   return MEG_OK;
 }

@@ -113,6 +113,7 @@ struct Ctl {
   double dxnorm;            // ||X_{t+1} - X_t||_F of the last step
   int64_t iters_done;       // iterations performed by step launches (counter)
   int64_t applies_done;     // operator applies performed by step launches (counter)
+  int64_t jacobi_done;      // Jacobi sweeps of the Rayleigh-Ritz solves (counter)
   int64_t pause_seq;        // batched launches: the launch whose time budget this instance used up
   Info info;
 };
@@ -146,10 +147,41 @@ constexpr int kTsWg = 160;
 constexpr int kTsWgSweeps = 2;
 constexpr int kTsTotal = kTsWg + 2 * kTsWgSweeps * kBarGroupSize * kBarMaxGroups;
 
+// Wavefront reductions (all 64 lanes active).  Within each row of 16 lanes
+// four DPP exchanges combine lane pairs, quads, the two quads of a half-row
+// (half-row mirror) and the two halves of the row (row mirror); both
+// partners of every exchange compute the same value.  The four row results
+// are then read as scalars and combined in a fixed order, so every lane gets
+// the same, run-to-run reproducible result.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename Op>
+__device__ __forceinline__ double wave_reduce(double v, Op op) {
+  v = op(v, dpp_f64<0xB1>(v));   // quad_perm [1, 0, 3, 2]: lane ^ 1
+  v = op(v, dpp_f64<0x4E>(v));   // quad_perm [2, 3, 0, 1]: lane ^ 2
+  v = op(v, dpp_f64<0x141>(v));  // row_half_mirror
+  v = op(v, dpp_f64<0x140>(v));  // row_mirror
+  return op(op(lane_f64(v, 0), lane_f64(v, 16)), op(lane_f64(v, 32), lane_f64(v, 48)));
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  return wave_reduce(v, [](double a, double b) { return a + b; });
+}
+__device__ __forceinline__ double wave_max(double v) {
+  return wave_reduce(v, [](double a, double b) { return fmax(a, b); });
+}
+__device__ __forceinline__ double wave_min(double v) {
+  return wave_reduce(v, [](double a, double b) { return fmin(a, b); });
 }
 
 // Bounded spin: a barrier that is never completed (which a co-resident,

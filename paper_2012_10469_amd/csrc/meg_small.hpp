@@ -18,18 +18,6 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
 // C = op(A) B for KB x KB matrices in LDS (stride KB + 1), op(A) = A or A^T,
 // on the FP64 matrix cores: 16 x 16 output tiles, v_mfma_f64_16x16x4f64 per
 // 4-wide K step.  Lane layout: A operand lane l holds A[l % 16][l / 16], B
@@ -387,7 +375,7 @@ __device__ inline void setup_step(const Cfg& cfg, gbl<Ctl>* ctl, double gmax, in
 // (LDS) holds the sorted Ritz values of Yhat, rho their residuals.  One
 // wavefront.
 __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<double>* theta, const lds<double>* rho,
-                                   double resid_max, int sweeps, int converged, int lane) {
+                                   double resid_max, int sweeps, int converged, double eps, int lane) {
   const int r = cfg.r;
   const double n = (double)cfg.n;
   const double alpha = ctl->alpha, sigma = ctl->sigma, solve_tol = ctl->solve_tol;
@@ -400,9 +388,8 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
   const double sr1 = wave_sum(e);
   const double lse_r = m + log(sr);    // log a_t
   const double lse_r1 = m + log(sr1);  // log b^{r+1}_t
-  const double mu_r1 = __shfl(mu, r, 64);
-  const double mu_r = __shfl(mu, r - 1, 64);
-  const double eps = eps_at(cfg, t);
+  const double mu_r1 = lane_f64(mu, r);
+  const double mu_r = lane_f64(mu, r - 1);
   const double alpha_n = eps / (n - r);
   const double l1e = log1p(-eps);
   const double la_n = log(alpha_n);
@@ -510,8 +497,12 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   // profiled launches: stamps of the first Rayleigh-Ritz sweep's parts
   const bool prof = ts != nullptr && lane == 0 && sweep == cfg.rr_from;
   if (prof) ts[kTsRR] = wall_clock64();
-  // eigenvector accuracy needed: rounding level of the working precision
-  const int jsweeps = jacobi<KB>(A, S, cfg.unit_round < 1e-10 ? 1e-30 : 1e-22, lane, jrot);
+  // Off-diagonal mass left by Jacobi, relative: 1e-8 for an FP32 state
+  // (below its unit roundoff 6e-8; the eigenvectors then carry errors of
+  // off/gap, and the residual test sees at most 1e-8 of the scale), 1e-15
+  // for FP64.  The tolerance is on squared norms.
+  const int jsweeps = jacobi<KB>(A, S, cfg.unit_round < 1e-10 ? 1e-30 : 1e-16, lane, jrot);
+  if (lane == 0) ctl->jacobi_done = ctl->jacobi_done + jsweeps;
   if (prof) {
     ts[kTsRR + 1] = wall_clock64();
     ts[kTsRR + 4] = jsweeps;
@@ -550,14 +541,14 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     ctl->theta[lane] = th;
     ctl->resid[lane] = rh;
   }
-  const double scale = fmax(fabs(__shfl(th, 0, 64)), 1e-300);
+  const double scale = fmax(fabs(lane_f64(th, 0)), 1e-300);
   // Residuals come from Ghat_ii - theta_i^2 in FP64: resolvable down to
   // ~sqrt(2^-53) of the scale; working-precision rounding sets another floor.
   const double floor_est = fmax(3e-8, 8.0 * cfg.unit_round) * scale;
   const double thr = fmax(cfg.inner_tol * scale, floor_est);
   const double rmax = wave_max(lane < r ? rh : 0.0);
   const bool finite = wave_min((lane < KB) ? ((isfinite(th) && isfinite(rh)) ? 1.0 : 0.0) : 1.0) > 0.5;
-  const double rr1 = __shfl(rh, r, 64);
+  const double rr1 = lane_f64(rh, r);
   const bool cert_ok = !(cfg.cert_tol > 0.0) || rr1 <= fmax(cfg.cert_tol, floor_est);
   // A top-r pair enters X_{t+1} = alpha' I + V diag(d') V^T only through
   // d'_l v_l v_l^T: even an entirely wrong v_l moves X by at most
@@ -569,7 +560,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   const double mmax = wave_max(mu);
   const double ex = (lane < r) ? exp(mu - mmax) : 0.0;
   const double esum = wave_sum(ex);
-  const double eps_t = eps_at(cfg, ctl->t);
+  const double eps_t = eps_at(cfg, ctl->t);  // once per sweep: finish_step reuses it
   const double dl_new = (lane < r) ? (1.0 - eps_t) * ex / esum - eps_t / (double)(cfg.n - r) : 0.0;
   const double dmax = wave_max(fabs(dl_new));
   const bool light = dmax > 0.0 && fabs(dl_new) <= 0.25 * cfg.inner_tol * dmax;
@@ -595,7 +586,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   if (fin) {
     const double a_old = ctl->alpha;
     const double d_old = (lane < r) ? ctl->d[lane] : 0.0;
-    finish_step(cfg, ctl, theta, rho, rmax, sweep, conv ? 1 : 0, lane);
+    finish_step(cfg, ctl, theta, rho, rmax, sweep, conv ? 1 : 0, eps_t, lane);
     // Ritz vectors of span(Q): Q S = Zin (W S), the next warm start; its
     // first sweep uses W = Wb and PW = V^T Q = [I_r 0]
     load_mat<KB>(ctl->W, B2, lane);

@@ -103,7 +103,7 @@ class MegKernelTimes(ctypes.Structure):
 
 class MegCounters(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("iterations", ctypes.c_int64), ("applies", ctypes.c_int64),
-                ("workgroups", ctypes.c_int32), ("reserved", ctypes.c_int32), ("kernel_ms", ctypes.c_double)]
+                ("workgroups", ctypes.c_int32), ("jacobi_sweeps", ctypes.c_int32), ("kernel_ms", ctypes.c_double)]
 
 
 class MegServerParams(ctypes.Structure):
@@ -375,12 +375,13 @@ class LowRankMEG:
                 "rr_ms": list(out.rr_ms) + [out.rr_tail_ms], "jacobi_sweeps": out.jacobi_sweeps}
 
     def counters(self, reset: bool = False) -> dict:
-        """Step-kernel launches, iterations, operator applies and their summed
-        HIP-event GPU time (ms) since init or the last reset; synchronises."""
+        """Step-kernel launches, iterations, operator applies, Jacobi sweeps and
+        their summed HIP-event GPU time (ms) since init or the last reset;
+        synchronises."""
         out = MegCounters()
         _check(self._lib.meg_get_counters(self._ctx, ctypes.byref(out), 1 if reset else 0), "meg_get_counters")
         return {"launches": out.launches, "iterations": out.iterations, "applies": out.applies,
-                "workgroups": out.workgroups, "kernel_ms": out.kernel_ms}
+                "workgroups": out.workgroups, "jacobi_sweeps": out.jacobi_sweeps, "kernel_ms": out.kernel_ms}
 
     def close(self) -> None:
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

@@ -55,7 +55,7 @@ int main(void) {
   O(meg_kernel_times, apply_ms) O(meg_kernel_times, finalize_ms) O(meg_kernel_times, workgroups)
   O(meg_kernel_times, wg_apply_ms) O(meg_kernel_times, wg_skew_ms) O(meg_kernel_times, reduce_ms)
   O(meg_kernel_times, rr_ms) O(meg_kernel_times, rr_tail_ms) O(meg_kernel_times, jacobi_sweeps)
-  O(meg_counters, applies) O(meg_counters, workgroups) O(meg_counters, kernel_ms)
+  O(meg_counters, applies) O(meg_counters, workgroups) O(meg_counters, jacobi_sweeps) O(meg_counters, kernel_ms)
   O(meg_params, eta) O(meg_params, seed) O(meg_params, flags) O(meg_params, inner_tol)
   O(meg_objective, dense) O(meg_objective, ld) O(meg_objective, nnz) O(meg_objective, batch_idx)
   O(meg_objective, batch_steps) O(meg_start, V0) O(meg_start, lambda0)
