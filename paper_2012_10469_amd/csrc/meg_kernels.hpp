@@ -202,21 +202,11 @@ __device__ void load_csr_cache(const Cfg& cfg, const Data<T>& dat, const CsrCach
 __device__ inline void step_scalars(const Cfg& cfg, gbl<Ctl>* ctl, int lane) {
   // the minibatch gradient's bound is known only inside sweep 1 (factor_shift)
   if (cfg.kind == QUADMEAS) return;
-  const double alpha = ctl->alpha;
   const bool act = lane < cfg.r;
-  const double dl = act ? ctl->d[lane] : 0.0;
-  double gmax;
-  if (cfg.kind == DENOISE_DENSE) {
-    gmax = alpha + wave_max(act ? fmax(dl, 0.0) : 0.0) - ctl->op_lmin;
-  } else if (cfg.kind == MASKED_CSR) {
-    const double ev = alpha + dl;
-    const double fro2 = (double)(cfg.n - cfg.r) * alpha * alpha + wave_sum(act ? ev * ev : 0.0);
-    const double px = ctl->pxvalid ? fmin(ctl->pxnorm + ctl->dxnorm, sqrt(fro2)) : sqrt(fro2);
-    gmax = px - ctl->op_lmin;
-  } else {
-    gmax = ctl->op_lmax;
-  }
-  setup_step(cfg, ctl, gmax, lane);
+  const double alpha = ctl->alpha, dl = act ? ctl->d[lane] : 0.0, cl = act ? ctl->c[lane] : 0.0;
+  const double gmax =
+      grad_bound(cfg, alpha, dl, ctl->op_lmin, ctl->op_lmax, ctl->pxvalid, ctl->pxnorm, ctl->dxnorm, lane);
+  setup_step_v(cfg, ctl, gmax, alpha, dl, cl, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1247,23 +1237,12 @@ __device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl,
                 gc->pxnorm = sqrt(b.sums[SM::PLEN + 1]);
                 gc->pxvalid = 1;
               }
+              // the step ends here when it returns true: X_{t+1}, t + 1 and
+              // the scalars of step t + 1 are set
               const bool fin = small_sweep<KB>(cfg, gc, (const gbl<double>*)b.sums, (lds<double>*)smem, s, in, tid,
                                                (gbl<long long>*)b.ts);
-              if (fin) {  // the step ends: X_{t+1} is set, prepare step t + 1
-                if (tid == 0) {
-                  gc->t = gc->t + 1;
-                  gc->iters_done = gc->iters_done + 1;
-                  gc->fvalid = 0;
-                  gc->done = 0;
-                  gc->sweep = 1;
-                  gc->polish = 0;
-                }
-                wg_fence();  // finish_step's writes of d, alpha, c, by other lanes
-                step_scalars(cfg, gc, tid);
-                if (deadline != 0 && tid == 0 && (long long)wall_clock64() >= deadline) gc->pause_seq = seq;
-              }
+              if (fin && deadline != 0 && tid == 0 && (long long)wall_clock64() >= deadline) gc->pause_seq = seq;
             }
-            if (tid == 0) ctl->applies_done = ctl->applies_done + 1;
             stamp(b, 2 * s + 1);
           }))
         return;

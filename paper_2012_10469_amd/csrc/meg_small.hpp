@@ -347,16 +347,16 @@ __device__ __noinline__ void chol_inv(const lds<double>* A, lds<double>* Rinv, i
 // subspace iteration targets the algebraically largest eigenvalues.  A tight
 // gmax matters: the unwanted spectrum then starts near 0, which is what makes
 // the (r+1)-th pair converge.  One wavefront (all 64 lanes call it).
-__device__ inline void setup_step(const Cfg& cfg, gbl<Ctl>* ctl, double gmax, int lane) {
+// setup_step_v takes the iterate's alpha, d_l and c_l (lane l < r; zero
+// elsewhere) from the caller, setup_step reads them from ctl.
+__device__ inline void setup_step_v(const Cfg& cfg, gbl<Ctl>* ctl, double gmax, double alpha, double dl, double cl,
+                                    int lane) {
   const int r = cfg.r;
   const bool act = lane < r;
-  const double cl = act ? ctl->c[lane] : 0.0;
-  const double dl = act ? ctl->d[lane] : 0.0;
   const double cmin = wave_min(act ? fmin(cl, 0.0) : 0.0);
   const double cmax = wave_max(act ? fmax(cl, 0.0) : 0.0);
   const double base = cfg.eta * gmax - cmin;
   const double sigma = base + 1e-3 * (fabs(base) + cmax) + 1e-30;
-  const double alpha = ctl->alpha;
   const bool den = cfg.kind == DENOISE_DENSE;
   if (lane < KMAX) {
     // denoising, G = X - M:  V c V^T - eta(alpha I + V d V^T - M) + sigma I
@@ -369,17 +369,66 @@ __device__ inline void setup_step(const Cfg& cfg, gbl<Ctl>* ctl, double gmax, in
     ctl->opscale = den ? cfg.eta : -cfg.eta;
   }
 }
+__device__ inline void setup_step(const Cfg& cfg, gbl<Ctl>* ctl, double gmax, int lane) {
+  const bool act = lane < cfg.r;
+  setup_step_v(cfg, ctl, gmax, ctl->alpha, act ? ctl->d[lane] : 0.0, act ? ctl->c[lane] : 0.0, lane);
+}
+
+// gmax >= lambda_max(grad f(X_t)) for the objectives whose bound needs no pass
+// over the data (the bounds are derived at step_scalars); dl = d_l (lane
+// l < r, zero elsewhere).  One wavefront.
+__device__ inline double grad_bound(const Cfg& cfg, double alpha, double dl, double op_lmin, double op_lmax,
+                                    int pxvalid, double pxnorm, double dxnorm, int lane) {
+  const bool act = lane < cfg.r;
+  if (cfg.kind == DENOISE_DENSE) return alpha + wave_max(act ? fmax(dl, 0.0) : 0.0) - op_lmin;
+  if (cfg.kind == MASKED_CSR) {
+    const double ev = alpha + dl;
+    const double fro2 = (double)(cfg.n - cfg.r) * alpha * alpha + wave_sum(act ? ev * ev : 0.0);
+    const double px = pxvalid ? fmin(pxnorm + dxnorm, sqrt(fro2)) : sqrt(fro2);
+    return px - op_lmin;
+  }
+  return op_lmax;
+}
+
+// The step's scalars that the small solve reads, loaded once at its start
+// (together with its matrices) instead of at their points of use, where
+// each read would be a separate round trip to memory.
+struct SolveScalars {
+  double alpha, sigma, solve_tol, f, pxnorm, op_lmin, op_lmax, dl;  // dl: d_l of this lane (l < r)
+  int64_t t, iters, applies, jacobi;
+  int fvalid, pxvalid, polish;
+};
+__device__ __forceinline__ SolveScalars load_scalars(const Cfg& cfg, const gbl<Ctl>* ctl, int lane) {
+  SolveScalars s;
+  s.alpha = ctl->alpha;
+  s.sigma = ctl->sigma;
+  s.solve_tol = ctl->solve_tol;
+  s.f = ctl->f;
+  s.pxnorm = ctl->pxnorm;
+  s.op_lmin = ctl->op_lmin;
+  s.op_lmax = ctl->op_lmax;
+  s.dl = (lane < cfg.r) ? ctl->d[lane] : 0.0;
+  s.t = ctl->t;
+  s.iters = ctl->iters_done;
+  s.applies = ctl->applies_done;
+  s.jacobi = ctl->jacobi_done;
+  s.fvalid = ctl->fvalid;
+  s.pxvalid = ctl->pxvalid;
+  s.polish = ctl->polish;
+  return s;
+}
 
 // End of the inner solve: exponentiate and normalise (Definition 1), build
 // the next factored iterate (alpha', d', c') and the certificate.  theta
 // (LDS) holds the sorted Ritz values of Yhat, rho their residuals.  One
 // wavefront.
 __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<double>* theta, const lds<double>* rho,
-                                   double resid_max, int sweeps, int converged, double eps, int lane) {
+                                   double resid_max, int sweeps, int converged, double eps, const SolveScalars& sc,
+                                   int lane, double& d_out, double& c_out, double& alpha_out) {
   const int r = cfg.r;
   const double n = (double)cfg.n;
-  const double alpha = ctl->alpha, sigma = ctl->sigma, solve_tol = ctl->solve_tol;
-  const int64_t t = ctl->t;
+  const double alpha = sc.alpha, sigma = sc.sigma, solve_tol = sc.solve_tol;
+  const int64_t t = sc.t;
   const double la = log(alpha);
   const double mu = (lane <= r) ? theta[lane] + la - sigma : -__builtin_inf();  // eigenvalues of M_t
   const double m = wave_max(mu);
@@ -394,17 +443,20 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
   const double l1e = log1p(-eps);
   const double la_n = log(alpha_n);
   bool ok = true;
+  double dl = 0.0, cl = 0.0;
+  if (lane < r) {
+    const double lt = mu - lse_r;              // log lambda~_l = mu_l - log a_t
+    dl = (1.0 - eps) * exp(lt) - alpha_n;
+    cl = l1e + lt - la_n;                      // log((1-eps) lambda~_l) - log(alpha')
+    ok = isfinite(dl) && isfinite(cl);
+  }
   if (lane < KMAX) {
-    double dl = 0.0, cl = 0.0;
-    if (lane < r) {
-      const double lt = mu - lse_r;              // log lambda~_l = mu_l - log a_t
-      dl = (1.0 - eps) * exp(lt) - alpha_n;
-      cl = l1e + lt - la_n;                      // log((1-eps) lambda~_l) - log(alpha')
-      ok = isfinite(dl) && isfinite(cl);
-    }
     ctl->d[lane] = dl;
     ctl->c[lane] = cl;
   }
+  d_out = dl;
+  c_out = cl;
+  alpha_out = alpha_n;
   const bool all_ok = wave_min(ok ? 1.0 : 0.0) > 0.5 && isfinite(lse_r1);
   if (lane == 0) {
     ctl->alpha = alpha_n;
@@ -422,7 +474,7 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
     in.mu_r1 = mu_r1;
     in.sigma = sigma;
     in.converged = converged;
-    in.f = ctl->fvalid ? ctl->f : __builtin_nan("");
+    in.f = sc.fvalid ? sc.f : __builtin_nan("");
     if (!all_ok) ctl->status = 4;  // MEG_ERR_NUMERIC
     if (solve_tol > 0.0 && in.cert_bound <= solve_tol) ctl->stop = 1;
   }
@@ -432,7 +484,9 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
 //   C = Zin^T Zout, G = Zout^T Zout, P = V^T Zout (first r rows)
 // where Zout = Yhat Q and Q = Zin W is orthonormal.  Sets the next sweep's
 // W and PW = V^T Q', or ends the step: the Ritz basis Zin (W S) becomes the
-// next warm start (B, Wb) = (Zin, W S).  Returns true when the step ended.
+// next warm start (B, Wb) = (Zin, W S), advances t and sets the next step's
+// shift and coefficients.  Counts the apply (and the Jacobi sweeps) in ctl.
+// Returns true when the step ended.
 // One wavefront (lanes 0..63).  `scr` (LDS) needs 5 * KB * (KB + 1) + 8 * KB
 // doubles.
 template <int KB>
@@ -455,6 +509,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   if (sweep < cfg.rr_from && sweep < cfg.max_inner) {
     // early sweep of a warm-started step: orthonormalise only,
     // Q' = Zout R^{-1} with Zout^T Zout = R^T R;  PW' = V^T Zout R^{-1}
+    const int64_t applies = ctl->applies_done;
     load_mat<KB>(sums + KB * KB, B3, lane);
     load_mat<KB>(sums + 2 * KB * KB, S, lane);
     wsync();
@@ -463,11 +518,24 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     wsync();
     store_mat<KB>(B2, ctl->W, lane);
     store_mat<KB>(A, ctl->PW, lane);
-    if (lane == 0) ctl->sweep = sweep + 1;
+    if (lane == 0) {
+      ctl->sweep = sweep + 1;
+      ctl->applies_done = applies + 1;
+    }
     return false;
   }
 
-  load_mat<KB>(ctl->W, B1, lane);
+  const SolveScalars sc = load_scalars(cfg, ctl, lane);
+  // W stays in registers too: the step's end forms W S from it
+  constexpr int WE = KB * KB / 64;
+  double wreg[WE];
+#pragma unroll
+  for (int u = 0; u < WE; ++u) wreg[u] = ctl->W[lane + 64 * u];
+#pragma unroll
+  for (int u = 0; u < WE; ++u) {
+    const int e = lane + 64 * u;
+    B1[(e / KB) * LD + (e % KB)] = wreg[u];
+  }
   load_mat<KB>(sums, B2, lane);
   load_mat<KB>(sums + KB * KB, B3, lane);
   // P = V^T Zout (for the next sweep's PW) and this sweep's PW = V^T Q, held
@@ -481,7 +549,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     pnew[m] = (e < KB * KB) ? sums[2 * KB * KB + e] : 0.0;
     pold[m] = (e < KB * KB) ? ctl->PW[e] : 0.0;
   }
-  const int polish = ctl->polish;
+  const int polish = sc.polish;
   wsync();
   mm_tn<KB>(B1, B2, A, lane);  // T = W^T C = Q^T Yhat Q
   wsync();
@@ -502,7 +570,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   // off/gap, and the residual test sees at most 1e-8 of the scale), 1e-15
   // for FP64.  The tolerance is on squared norms.
   const int jsweeps = jacobi<KB>(A, S, cfg.unit_round < 1e-10 ? 1e-30 : 1e-16, lane, jrot);
-  if (lane == 0) ctl->jacobi_done = ctl->jacobi_done + jsweeps;
+  if (lane == 0) ctl->jacobi_done = sc.jacobi + jsweeps;
   if (prof) {
     ts[kTsRR + 1] = wall_clock64();
     ts[kTsRR + 4] = jsweeps;
@@ -556,11 +624,11 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   // Pairs with w_l <= inner_tol / 4 therefore need no residual test (in the
   // noise bulk of M_t such pairs converge slowly and carry no weight).
   // d' follows from the Ritz values exactly as finish_step forms it.
-  const double mu = (lane < r) ? th + log(ctl->alpha) - ctl->sigma : -__builtin_inf();
+  const double mu = (lane < r) ? th + log(sc.alpha) - sc.sigma : -__builtin_inf();
   const double mmax = wave_max(mu);
   const double ex = (lane < r) ? exp(mu - mmax) : 0.0;
   const double esum = wave_sum(ex);
-  const double eps_t = eps_at(cfg, ctl->t);  // once per sweep: finish_step reuses it
+  const double eps_t = eps_at(cfg, sc.t);  // once per sweep: finish_step reuses it
   const double dl_new = (lane < r) ? (1.0 - eps_t) * ex / esum - eps_t / (double)(cfg.n - r) : 0.0;
   const double dmax = wave_max(fabs(dl_new));
   const bool light = dmax > 0.0 && fabs(dl_new) <= 0.25 * cfg.inner_tol * dmax;
@@ -580,16 +648,22 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
       ctl->status = 4;  // MEG_ERR_NUMERIC
       ctl->stop = 1;
       ctl->done = 1;
+      ctl->applies_done = sc.applies + 1;
     }
     return false;
   }
   if (fin) {
-    const double a_old = ctl->alpha;
-    const double d_old = (lane < r) ? ctl->d[lane] : 0.0;
-    finish_step(cfg, ctl, theta, rho, rmax, sweep, conv ? 1 : 0, eps_t, lane);
+    const double a_old = sc.alpha;
+    const double d_old = sc.dl;
+    double d_new, c_new, a_new;
+    finish_step(cfg, ctl, theta, rho, rmax, sweep, conv ? 1 : 0, eps_t, sc, lane, d_new, c_new, a_new);
     // Ritz vectors of span(Q): Q S = Zin (W S), the next warm start; its
     // first sweep uses W = Wb and PW = V^T Q = [I_r 0]
-    load_mat<KB>(ctl->W, B2, lane);
+#pragma unroll
+    for (int u = 0; u < WE; ++u) {
+      const int e = lane + 64 * u;
+      B2[(e / KB) * LD + (e % KB)] = wreg[u];
+    }
     wsync();
     mm_nn<KB>(B2, B1, A, lane);
     wsync();
@@ -606,7 +680,6 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
       const int e = lane + 64 * m;
       if (e < KB * KB) Pm[(e / KB) * LD + (e % KB)] = pold[m];
     }
-    const double d_new = (lane < r) ? ctl->d[lane] : 0.0;
     if (lane < KB) {
       dd[lane] = d_old;
       dd[KB + lane] = d_new;
@@ -621,15 +694,28 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
       cross += dd[a] * dd[KB + b] * c * c;
     }
     cross = wave_sum(cross);
-    const double a_new = ctl->alpha;
     const double sd = wave_sum(d_old - d_new);
     const double s2 = wave_sum(d_old * d_old + d_new * d_new);
     const double da = a_old - a_new;
     const double dx2 = (double)cfg.n * da * da + 2.0 * da * sd + s2 - 2.0 * cross;
+    const double dxnorm = sqrt(fmax(dx2, 0.0));
+    // step t + 1 begins: its counters, then its shift and coefficients from
+    // the values in registers
     if (lane == 0) {
-      ctl->dxnorm = sqrt(fmax(dx2, 0.0));
+      ctl->dxnorm = dxnorm;
       ctl->src = in_buf;
-      ctl->done = 1;
+      ctl->t = sc.t + 1;
+      ctl->iters_done = sc.iters + 1;
+      ctl->applies_done = sc.applies + 1;
+      ctl->fvalid = 0;
+      ctl->done = 0;
+      ctl->sweep = 1;
+      ctl->polish = 0;
+    }
+    if (cfg.kind != QUADMEAS) {  // the minibatch bound is set inside the next step's first sweep
+      const double gmax =
+          grad_bound(cfg, a_new, d_new, sc.op_lmin, sc.op_lmax, sc.pxvalid, sc.pxnorm, dxnorm, lane);
+      setup_step_v(cfg, ctl, gmax, a_new, d_new, c_new, lane);
     }
     if (prof) ts[kTsRR + 3] = wall_clock64();
     return true;
@@ -650,6 +736,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   store_mat<KB>(B3, ctl->PW, lane);
   if (lane == 0) {
     ctl->sweep = sweep + 1;
+    ctl->applies_done = sc.applies + 1;
     if (do_polish) ctl->polish = polish + 1;
   }
   if (prof) ts[kTsRR + 3] = wall_clock64();
