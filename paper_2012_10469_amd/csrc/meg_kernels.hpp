@@ -253,11 +253,25 @@ __device__ __noinline__ void dense_x3(int64_t n, int64_t ld, const gbl<uint16_t>
   const int nchunk = (int)((n + KC - 1) / KC);
   const gbl<uint16_t>* ph = Mhi + (rowok ? arow * ld : 0);
   const gbl<uint16_t>* pl = Mlo + (rowok ? arow * ld : 0);
-  // A fragments of chunk c, branch-free: every 16-byte load reads inside the
-  // row (ld is a multiple of 8 and the group start is clamped below n), and
-  // elements past n or rows past n are masked to zero afterwards.
+  // A fragments of chunk c.  A chunk of a block whose rows and columns all lie
+  // inside the matrix (the common case, uniform over the workgroup) is read
+  // as four 16-byte loads at constant offsets from one address per plane.
+  // Otherwise every 16-byte load reads inside the row (ld is a multiple of 8
+  // and the group start is clamped below n), and elements past n or rows past
+  // n are masked to zero afterwards.
+  const bool block_in = row0 + 64 <= n;
   auto load_a = [&](int c, u16x8_t (&ah)[4], u16x8_t (&al)[4]) {
     const int64_t k0 = (int64_t)c * KC + kq * 64 + h * 32;
+    if (block_in && (int64_t)(c + 1) * KC <= n) {
+      const gbl<u16x8_t>* qh = reinterpret_cast<const gbl<u16x8_t>*>(ph + k0);
+      const gbl<u16x8_t>* ql = reinterpret_cast<const gbl<u16x8_t>*>(pl + k0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        ah[s] = qh[s];
+        al[s] = ql[s];
+      }
+      return;
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int64_t kk = k0 + 8 * s;
