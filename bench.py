@@ -39,9 +39,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain
 # copy's readings (profiles/k_step_matrix_completion_n4096_r10_traffic.md);
 # valid only for the kernel sources it was measured on.
-TRAFFIC = {"bytes_per_launch": 942.9e6, "iterations_per_launch": 64, "applies_per_iteration": 3.0,
-           "fetch_bytes": 546.4e6, "write_bytes": 396.5e6, "fetch_factor": 2.0, "write_factor": 1.0,
-           "source_hash": "21af2ec4d84163b3"}
+TRAFFIC = {"bytes_per_launch": 943.0e6, "iterations_per_launch": 64, "applies_per_iteration": 3.0,
+           "fetch_bytes": 546.5e6, "write_bytes": 396.5e6, "fetch_factor": 2.0, "write_factor": 1.0,
+           "source_hash": "3461ee25a4e9f128"}
 KERNEL_SOURCES = ["meg_device.hpp", "meg_small.hpp", "meg_kernels.hpp", "meg_api.hip"]
 
 
