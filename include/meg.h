@@ -188,7 +188,12 @@ meg_status meg_step(meg_ctx ctx, meg_step_info* info);
  * read during the call only: the call synchronises the stream before it
  * returns.  The solver's shift bounds lambda_max(G_t) by Gershgorin's
  * theorem (one pass over G_t).  info (optional) as meg_step, with f = NaN.
- * meg_step and meg_solve return MEG_ERR_INVALID_ARG on such a context. */
+ * Errors: MEG_ERR_INVALID_ARG for a context of another kind, a NULL or
+ * malformed grad (ld < n, CSR structure or column out of range; checked
+ * before any kernel reads through it), MEG_ERR_UNSUPPORTED for another grad
+ * kind.  meg_step, meg_solve and meg_profile_step return MEG_ERR_INVALID_ARG
+ * on an external context, meg_objective_value MEG_ERR_UNSUPPORTED (f is the
+ * caller's). */
 meg_status meg_step_external(meg_ctx ctx, const meg_objective* grad, meg_step_info* info);
 
 /* Up to max_iters iterations; stops early after the first step whose

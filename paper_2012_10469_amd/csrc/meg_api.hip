@@ -1089,7 +1089,7 @@ meg_status meg_set_state(meg_ctx c, const void* buf, size_t bytes) {
 meg_status meg_profile_step(meg_ctx c, meg_kernel_times* out) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
-  if (!out) return MEG_ERR_INVALID_ARG;
+  if (!out || c->external) return MEG_ERR_INVALID_ARG;  // an external G_t is borrowed for one call only
   std::memset(out, 0, sizeof(*out));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(c, hipEventCreate(&e0));

@@ -145,6 +145,15 @@ def test_external_rejects(meg):
         with pytest.raises(meg.MegError) as e:
             g.solve(3)
         assert e.value.status == meg.MEG_ERR_INVALID_ARG
+        with pytest.raises(meg.MegError) as e:
+            g.profile_step()
+        assert e.value.status == meg.MEG_ERR_INVALID_ARG
+        with pytest.raises(meg.MegError) as e:
+            g.objective()
+        assert e.value.status == meg.MEG_ERR_UNSUPPORTED
+        with pytest.raises(meg.MegError) as e:  # a dense G_t with ld < n
+            g.step_external(dense=dev(np.zeros((n, n - 1), dtype=np.float32)))
+        assert e.value.status == meg.MEG_ERR_INVALID_ARG
         G = np.eye(n, dtype=np.float32)
         rp, col, val = csr_of(G)
         col[5] = n  # one past the last column
