@@ -440,3 +440,45 @@ def test_factored_quadmeas_step_matches_dense(n, L, q, r):
         it = ref
         batch = rng.integers(0, m, size=L)
         eps = O.eps_schedule(it.t)
+
+
+# ---------------------------------------------------------------------------
+# the dual gap of Section 7
+# ---------------------------------------------------------------------------
+def test_dual_gap_is_the_max_over_the_spectrahedron():
+    """<X, G> - lambda_min(G) equals max_Z <X - Z, G> over Z >= 0, tr Z = 1.
+    The maximum of a linear function over the spectrahedron is attained at an
+    extreme point z z^T; brute force over a fine grid of unit z in R^3 (no
+    eigensolver) matches it to the grid's resolution."""
+    rng = np.random.default_rng(21)
+    th = np.linspace(0.0, math.pi, 241)
+    ph = np.linspace(0.0, 2.0 * math.pi, 481)
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    Zs = np.stack([np.sin(T) * np.cos(P), np.sin(T) * np.sin(P), np.cos(T)], axis=-1).reshape(-1, 3)
+    for _ in range(5):
+        G = rand_sym(3, rng)
+        w = rng.random(3)
+        U, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+        X = (U * (w / w.sum())) @ U.T
+        brute = float(np.sum(X * G)) - float(np.min(np.einsum("pi,ij,pj->p", Zs, G, Zs)))
+        assert O.dual_gap(X, G) == pytest.approx(brute, abs=2e-4 * float(np.abs(G).max()))
+
+
+def test_dual_gap_vanishes_at_the_projection_and_bounds_suboptimality():
+    """Denoising f = 1/2 ||X - M||^2: at X* = Pi_S(M) (pinned by its KKT
+    conditions above) the gap is zero; at any other feasible X it is at least
+    f(X) - f(X*) >= 0 (convexity), and positive."""
+    rng = np.random.default_rng(22)
+    for _ in range(6):
+        n = int(rng.integers(5, 25))
+        M = rand_sym(n, rng, scale=float(rng.uniform(0.2, 2.0)))
+        obj = O.DenoiseObjective(M)
+        Xs = O.project_spectrahedron(M)
+        assert abs(O.dual_gap(Xs, obj.grad(Xs))) <= 1e-9 * (1.0 + float(np.abs(M).max()))
+        w = rng.random(n) ** 3
+        U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        X = (U * (w / w.sum())) @ U.T
+        gap = O.dual_gap(X, obj.grad(X))
+        sub = obj.value(X) - obj.value(Xs)
+        assert sub >= -1e-12
+        assert gap >= sub - 1e-12 and gap > 0.0
