@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # valid only for the kernel sources it was measured on.
 TRAFFIC = {"bytes_per_launch": 943.0e6, "iterations_per_launch": 64, "applies_per_iteration": 3.0,
            "fetch_bytes": 546.5e6, "write_bytes": 396.5e6, "fetch_factor": 2.0, "write_factor": 1.0,
-           "source_hash": "612841f118920ac2"}
+           "source_hash": "328dbdd05fa8c413"}
 KERNEL_SOURCES = ["meg_device.hpp", "meg_small.hpp", "meg_kernels.hpp", "meg_api.hip"]
 
 
@@ -371,6 +371,13 @@ def main() -> int:
             f"grad {phases['grad_us']:.1f} us, apply {phases['apply_us']:.1f} us x {phases['sweeps']:.2f} "
             f"({apply_gbs:.0f} GB/s), reduce+RR {phases['reduce_rr_us']:.1f} us, finalize {phases['finalize_us']:.1f} us")
 
+    # dual gap of the final iterate (Section 7's near-optimality measure), not timed with the steps
+    t0 = time.perf_counter()
+    dg = g.dual_gap(max_steps=256, tol=1e-8)
+    dg["ms"] = (time.perf_counter() - t0) * 1e3
+    log(f"[bench] dual gap at t={dg['t']}: {dg['gap']:.4e} (<X,G> {dg['x_dot_g']:.4e}, lambda_min {dg['lambda_min']:.4e}, "
+        f"{dg['steps']} Lanczos steps, {dg['ms']:.1f} ms)")
+
     base = None
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline: {args.cpu_samples} iterations")
@@ -408,6 +415,7 @@ def main() -> int:
                      "iterations_per_launch": iters_per_launch, "applies_per_iteration": sweeps,
                      "jacobi_sweeps_per_iteration": cnt["jacobi_sweeps"] / cnt["iterations"],
                      "launches": launches, "phases": phases},
+        "dual_gap": dg,
         "cpu_baseline": base,
         "serving": serving,
     }

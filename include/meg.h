@@ -274,6 +274,32 @@ typedef struct {
 
 meg_status meg_get_counters(meg_ctx ctx, meg_counters* out, int32_t reset);
 
+/* Dual gap at the current iterate X_t (Section 7, the near-optimality measure
+ * of the experiments): with G = grad f(X_t) and trace bound 1,
+ *   gap = max_{Z >= 0, tr Z = 1} <X_t - Z, G> = <X_t, G> - lambda_min(G),
+ * which bounds f(X_t) - f* from above for convex f.  <X_t, G> is accumulated
+ * in FP64 over the matrix (dense) or the pattern (CSR); lambda_min(G) is the
+ * smallest Ritz value of a Lanczos run with full reorthogonalisation on G
+ * (host recurrence, device products with G; seeded start), stopped once its
+ * Ritz residual is <= tol * max |Ritz value| (checked every 8 steps) or
+ * after max_steps steps.  Objectives: linear (G = C), denoising
+ * (G = X_t - M, also with M as bf16 planes) and masked (G = P_Omega(X_t - M);
+ * the call overwrites the context's stored gradient values, which the next
+ * step recomputes).  MEG_ERR_UNSUPPORTED for the minibatch and external
+ * kinds; MEG_ERR_INVALID_ARG for max_steps < 1, tol < 0 or out == NULL.
+ * Synchronises; HOST output. */
+typedef struct {
+  double gap;         /* <X_t, G> - lambda_min                                  */
+  double x_dot_g;     /* <X_t, G>                                                */
+  double lambda_min;  /* smallest Ritz value of G                                */
+  double resid;       /* its Ritz residual ||G s - theta s|| (|beta_m s_m|)      */
+  int64_t t;          /* index of the iterate                                    */
+  int32_t steps;      /* Lanczos steps taken                                     */
+  int32_t converged;  /* resid <= tol * max |Ritz value|                         */
+} meg_dual_gap_info;
+
+meg_status meg_dual_gap(meg_ctx ctx, int32_t max_steps, double tol, meg_dual_gap_info* out);
+
 void meg_destroy(meg_ctx ctx);
 const char* meg_status_str(meg_status s);
 

@@ -274,6 +274,24 @@ struct Launch {
     return hipGetLastError();
   }
 
+  // <X_t, grad f(X_t)> partials (one per group of 4 rows) into c->part, after
+  // writing V out explicitly; masked: the gradient values into c->g
+  static hipError_t xdotg(meg_ctx c) {
+    const Cfg& cfg = c->cfg;
+    const int nwg = ceil_div(cfg.n, 4);
+    const int mwg = (int)std::min<int64_t>(4096, ceil_div(cfg.n * KB, 256));
+    hipLaunchKernelGGL((k_materialize<T, KB>), dim3(mwg), dim3(256), 0, c->stream, cfg, c->ctl, (T*)c->Qw, (T*)c->Za,
+                       (T*)c->Zb);
+    if (csr(c))
+      hipLaunchKernelGGL((k_xdotg_csr<T, KB>), dim3(nwg), dim3(256), 0, c->stream, cfg, c->ctl, c->obj.row_ptr,
+                         c->obj.col, (const T*)c->obj.val, (T*)c->g, (const T*)c->Qw, (const T*)c->Za,
+                         (const T*)c->Zb, c->part);
+    else
+      hipLaunchKernelGGL((k_xdotg_dense<T, KB>), dim3(nwg), dim3(256), 0, c->stream, cfg, c->ctl, dense_src(c),
+                         (const T*)c->Qw, (const T*)c->Za, (const T*)c->Zb, c->part);
+    return hipGetLastError();
+  }
+
   static hipError_t data_norm(meg_ctx c) {
     const Cfg& cfg = c->cfg;
     int64_t rows, cols, ld;
@@ -319,6 +337,9 @@ template <typename T, int KB> struct DoCache {
     Launch<T, KB>::setup_cache(c);
     return 0;
   }
+};
+template <typename T, int KB> struct DoXdotG {
+  static hipError_t run(meg_ctx c) { return Launch<T, KB>::xdotg(c); }
 };
 template <typename T, int KB> struct DoPartNeed {
   static size_t run(meg_ctx c, int P) { return Launch<T, KB>::part_need(P); }
@@ -460,6 +481,129 @@ void* block(meg_ctx c, int i) { return i == 0 ? c->Qw : (i == 1 ? c->Za : c->Zb)
 meg_status copy_ctl_to_host(meg_ctx c) {
   HIPCHK(c, hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MEG_OK;
+}
+
+// Smallest eigenvalue of the gradient G = grad f(X_t) by Lanczos (full
+// reorthogonalisation, host recurrence in FP64, products with G on the
+// device): linear G = C, denoising G = alpha I + V diag(d) V^T - M (the
+// low-rank part on the host from the materialised V), masked G = the CSR
+// pattern with the values xdotg wrote into c->g.
+template <typename T>
+meg_status lanczos_grad_min(meg_ctx c, int max_steps, double tol, meg_dual_gap_info* out) {
+  const Cfg& cfg = c->cfg;
+  const int64_t n = cfg.n;
+  const int r = cfg.r, KB = cfg.k;
+  const int m = (int)std::min<int64_t>(n, max_steps);
+  const bool den = cfg.kind == DENOISE_DENSE;
+  const bool masked = cfg.kind == MASKED_CSR;
+  std::vector<double> Vh, dh(c->h_ctl->d, c->h_ctl->d + r);
+  const double alpha = c->h_ctl->alpha;
+  if (den) {  // V = first r columns of the materialised basis (block (src + 1) mod 3)
+    std::vector<T> Q((size_t)n * KB);
+    HIPCHK(c, hipMemcpy(Q.data(), block(c, (c->h_ctl->src + 1) % 3), Q.size() * sizeof(T), hipMemcpyDeviceToHost));
+    Vh.resize((size_t)n * r);
+    for (int64_t i = 0; i < n; ++i)
+      for (int l = 0; l < r; ++l) Vh[(size_t)i * r + l] = (double)Q[(size_t)i * KB + l];
+  }
+  T* dx = nullptr;
+  double* dy = nullptr;
+  if (hipMalloc((void**)&dx, n * sizeof(T)) != hipSuccess) return MEG_ERR_OUT_OF_MEMORY;
+  if (hipMalloc((void**)&dy, n * sizeof(double)) != hipSuccess) {
+    (void)hipFree(dx);
+    return MEG_ERR_OUT_OF_MEMORY;
+  }
+  auto apply = [&](const double* v, std::vector<double>& y, std::vector<T>& xt) -> meg_status {
+    for (int64_t i = 0; i < n; ++i) xt[i] = (T)v[i];
+    if (hipMemcpy(dx, xt.data(), n * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return hip_fail(c);
+    hipLaunchKernelGGL((k_matvec<T>), dim3(ceil_div(n, 4)), dim3(256), 0, c->stream, cfg,
+                       Launch<T, 16>::dense_src(c), c->obj.row_ptr, c->obj.col,
+                       masked ? (const T*)c->g : (const T*)c->obj.val, (const T*)dx, dy);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
+        hipMemcpy(y.data(), dy, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      return hip_fail(c);
+    if (den) {  // y = alpha x + V diag(d) V^T x - M x, with x as the device saw it
+      std::vector<double> p(r, 0.0);
+      for (int64_t i = 0; i < n; ++i)
+        for (int l = 0; l < r; ++l) p[l] += Vh[(size_t)i * r + l] * (double)xt[i];
+      for (int l = 0; l < r; ++l) p[l] *= dh[l];
+      for (int64_t i = 0; i < n; ++i) {
+        double s = alpha * (double)xt[i] - y[i];
+        for (int l = 0; l < r; ++l) s += Vh[(size_t)i * r + l] * p[l];
+        y[i] = s;
+      }
+    }
+    return MEG_OK;
+  };
+  std::vector<double> Vs((size_t)(m + 1) * n), y(n), w(n);
+  std::vector<T> xt(n);
+  std::vector<double> al(m, 0.0), be(m, 0.0);
+  SplitMix rng{c->params.seed ^ 0x6475616c67617021ull ^ (uint64_t)c->h_ctl->t};
+  double nrm = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    Vs[i] = rng.normal();
+    nrm += Vs[i] * Vs[i];
+  }
+  nrm = std::sqrt(nrm);
+  for (int64_t i = 0; i < n; ++i) Vs[i] /= nrm;
+  // smallest Ritz pair of the (j + 1) x (j + 1) tridiagonal
+  auto ritz_min = [&](int j1, double& theta, double& res, double& scale) {
+    std::vector<double> Tm((size_t)j1 * j1, 0.0), ev, S;
+    for (int j = 0; j < j1; ++j) {
+      Tm[(size_t)j * j1 + j] = al[j];
+      if (j + 1 < j1) Tm[(size_t)j * j1 + j + 1] = Tm[(size_t)(j + 1) * j1 + j] = be[j];
+    }
+    host_sym_eig(Tm, j1, ev, S);
+    int imin = 0;
+    scale = 0.0;
+    for (int i = 0; i < j1; ++i) {
+      if (ev[i] < ev[imin]) imin = i;
+      scale = std::max(scale, std::fabs(ev[i]));
+    }
+    theta = ev[imin];
+    res = std::fabs(be[j1 - 1] * S[(size_t)(j1 - 1) * j1 + imin]);
+  };
+  meg_status st = MEG_OK;
+  double theta = 0.0, res = 0.0, scale = 0.0;
+  int done = 0;
+  bool conv = false;
+  for (int j = 0; j < m; ++j) {
+    const double* v = &Vs[(size_t)j * n];
+    st = apply(v, y, xt);
+    if (st != MEG_OK) break;
+    double a = 0.0;
+    for (int64_t i = 0; i < n; ++i) a += y[i] * v[i];
+    for (int64_t i = 0; i < n; ++i) w[i] = y[i] - a * v[i] - (j > 0 ? be[j - 1] * Vs[(size_t)(j - 1) * n + i] : 0.0);
+    for (int pass = 0; pass < 2; ++pass)
+      for (int l = 0; l <= j; ++l) {
+        const double* u = &Vs[(size_t)l * n];
+        double s = 0.0;
+        for (int64_t i = 0; i < n; ++i) s += u[i] * w[i];
+        for (int64_t i = 0; i < n; ++i) w[i] -= s * u[i];
+      }
+    double b = 0.0;
+    for (int64_t i = 0; i < n; ++i) b += w[i] * w[i];
+    b = std::sqrt(b);
+    al[j] = a;
+    be[j] = b;
+    done = j + 1;
+    const bool invariant = !(b > 1e-14 * (std::fabs(a) + 1e-300));
+    if (invariant) be[j] = 0.0;
+    if (invariant || done % 8 == 0 || done == m) {
+      ritz_min(done, theta, res, scale);
+      conv = res <= tol * scale;
+      if (conv || invariant) break;
+    }
+    double* vn = &Vs[(size_t)(j + 1) * n];
+    for (int64_t i = 0; i < n; ++i) vn[i] = w[i] / b;
+  }
+  (void)hipFree(dx);
+  (void)hipFree(dy);
+  if (st != MEG_OK) return st;
+  out->lambda_min = theta;
+  out->resid = res;
+  out->steps = done;
+  out->converged = conv ? 1 : 0;
   return MEG_OK;
 }
 
@@ -1157,6 +1301,30 @@ meg_status meg_profile_step(meg_ctx c, meg_kernel_times* out) {
     out->jacobi_sweeps = (int32_t)ts[kTsRR + 4];
   }
   return c->h_ctl->status ? (meg_status)c->h_ctl->status : MEG_OK;
+}
+
+meg_status meg_dual_gap(meg_ctx c, int32_t max_steps, double tol, meg_dual_gap_info* out) {
+  meg_status st = check_ctx(c);
+  if (st != MEG_OK) return st;
+  if (!out || max_steps < 1 || !(tol >= 0.0)) return MEG_ERR_INVALID_ARG;
+  if (c->external || c->cfg.kind == QUADMEAS) return MEG_ERR_UNSUPPORTED;
+  std::memset(out, 0, sizeof(*out));
+  HIPCHK(c, dispatch<DoXdotG>(c));
+  const int nwg = ceil_div(c->cfg.n, 4);
+  std::vector<double> part(nwg);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(part.data(), c->part, nwg * sizeof(double), hipMemcpyDeviceToHost));
+  double xg = 0.0;
+  for (int w = 0; w < nwg; ++w) xg += part[w];
+  st = copy_ctl_to_host(c);
+  if (st != MEG_OK) return st;
+  st = (c->esize == 8) ? lanczos_grad_min<double>(c, max_steps, tol, out)
+                       : lanczos_grad_min<float>(c, max_steps, tol, out);
+  if (st != MEG_OK) return st;
+  out->x_dot_g = xg;
+  out->gap = xg - out->lambda_min;
+  out->t = c->h_ctl->t;
+  return MEG_OK;
 }
 
 meg_status meg_get_counters(meg_ctx c, meg_counters* out, int32_t reset) {

@@ -1463,6 +1463,86 @@ static __global__ __launch_bounds__(256) void k_objective_csr(Cfg cfg, const Ctl
   if (tid == 0) part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
 }
 
+// <X_t, G_t> for the dual gap (Section 7), G_t = grad f(X_t), accumulated in
+// FP64 like the objective: LINEAR sum C_ij X_ij; DENOISE sum X_ij (X_ij - M_ij).
+// One wave per row; V from k_materialize.
+template <typename T, int KB>
+static __global__ __launch_bounds__(256) void k_xdotg_dense(Cfg cfg, const Ctl* __restrict__ ctl, DenseSrc<T> D,
+                                                            const T* __restrict__ Z0, const T* __restrict__ Z1,
+                                                            const T* __restrict__ Z2, double* __restrict__ part) {
+  const T* Qw = zbuf(Z0, Z1, Z2, (ctl->src + 1) % 3);
+  __shared__ double sd[KMAX];
+  __shared__ double sred[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = cfg.r;
+  if (tid < KMAX) sd[tid] = ctl->d[tid];
+  __syncthreads();
+  const double alpha = ctl->alpha;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wave;
+  double acc = 0.0;
+  if (i < cfg.n) {
+    double vi[KB];
+#pragma unroll
+    for (int l = 0; l < KB; ++l) vi[l] = (l < r) ? (double)Qw[i * KB + l] * sd[l] : 0.0;
+    for (int64_t j = lane; j < cfg.n; j += 64) {
+      double x = (j == i) ? alpha : 0.0;
+#pragma unroll
+      for (int l = 0; l < KB; ++l)
+        if (l < r) x += vi[l] * (double)Qw[j * KB + l];
+      const double dij = D.at(i * cfg.ld + j);
+      acc += (cfg.kind == LINEAR_DENSE) ? dij * x : x * (x - dij);
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) sred[wave] = acc;
+  __syncthreads();
+  if (tid == 0) part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
+}
+
+// <X_t, G_t> on the pattern: LINEAR sum_Omega C_ij X_ij; MASKED
+// sum_Omega X_ij (X_ij - M_ij), with the gradient values X_ij - M_ij also
+// written to gout (the operator the dual gap's Lanczos run multiplies by).
+template <typename T, int KB>
+static __global__ __launch_bounds__(256) void k_xdotg_csr(Cfg cfg, const Ctl* __restrict__ ctl,
+                                                          const int* __restrict__ rp, const int* __restrict__ col,
+                                                          const T* __restrict__ val, T* __restrict__ gout,
+                                                          const T* __restrict__ Z0, const T* __restrict__ Z1,
+                                                          const T* __restrict__ Z2, double* __restrict__ part) {
+  const T* Qw = zbuf(Z0, Z1, Z2, (ctl->src + 1) % 3);
+  __shared__ double sd[KMAX];
+  __shared__ double sred[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = cfg.r;
+  if (tid < KMAX) sd[tid] = ctl->d[tid];
+  __syncthreads();
+  const double alpha = ctl->alpha;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wave;
+  double acc = 0.0;
+  if (i < cfg.n) {
+    double vi[KB];
+#pragma unroll
+    for (int l = 0; l < KB; ++l) vi[l] = (l < r) ? (double)Qw[i * KB + l] * sd[l] : 0.0;
+    for (int e = rp[i] + lane; e < rp[i + 1]; e += 64) {
+      const int64_t j = col[e];
+      double x = (j == i) ? alpha : 0.0;
+#pragma unroll
+      for (int l = 0; l < KB; ++l)
+        if (l < r) x += vi[l] * (double)Qw[j * KB + l];
+      const double v = (double)val[e];
+      if (cfg.kind == LINEAR_CSR) {
+        acc += v * x;
+      } else {
+        acc += x * (x - v);
+        gout[e] = (T)(x - v);
+      }
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) sred[wave] = acc;
+  __syncthreads();
+  if (tid == 0) part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
+}
+
 // sum of squares of a strided matrix (rows x cols, ld) or a vector (rows = 1)
 template <typename T>
 static __global__ __launch_bounds__(256) void k_sumsq(DenseSrc<T> x, int64_t rows, int64_t cols, int64_t ld,
@@ -1506,8 +1586,10 @@ static __global__ __launch_bounds__(256) void k_finish(Ctl* __restrict__ ctl, co
 }
 
 // y = Op x for the data operator (dense C/M or the CSR values), FP64 result.
-// Used once per context by the Lanczos estimate of the operator's extreme
-// eigenvalues.  One wave per row.
+// Used by the Lanczos estimate of the data operator's extreme eigenvalues
+// (once per context) and by the dual gap's Lanczos run for lambda_min of the
+// gradient (there with the gradient values as the CSR values).  One wave per
+// row.
 template <typename T>
 static __global__ __launch_bounds__(256) void k_matvec(Cfg cfg, DenseSrc<T> D, const int* __restrict__ rp,
                                                 const int* __restrict__ col, const T* __restrict__ val,

@@ -48,7 +48,7 @@ MEG_SERVER_FLAG_GRAPH = 1
 EXPORTED = [
     "meg_block_size", "meg_init", "meg_step", "meg_solve", "meg_certificate", "meg_objective_value",
     "meg_get_iterate", "meg_set_iterate", "meg_get_state", "meg_set_state", "meg_profile_step", "meg_destroy",
-    "meg_status_str", "meg_get_counters", "meg_step_external",
+    "meg_status_str", "meg_get_counters", "meg_step_external", "meg_dual_gap",
     "meg_server_create", "meg_server_submit", "meg_server_run", "meg_server_query", "meg_server_result",
     "meg_server_release", "meg_server_team", "meg_server_get_stats", "meg_server_destroy",
 ]
@@ -104,6 +104,15 @@ class MegKernelTimes(ctypes.Structure):
 class MegCounters(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("iterations", ctypes.c_int64), ("applies", ctypes.c_int64),
                 ("workgroups", ctypes.c_int32), ("jacobi_sweeps", ctypes.c_int32), ("kernel_ms", ctypes.c_double)]
+
+
+class MegDualGapInfo(ctypes.Structure):
+    _fields_ = [("gap", ctypes.c_double), ("x_dot_g", ctypes.c_double), ("lambda_min", ctypes.c_double),
+                ("resid", ctypes.c_double), ("t", ctypes.c_int64), ("steps", ctypes.c_int32),
+                ("converged", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class MegServerParams(ctypes.Structure):
@@ -166,6 +175,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "meg_set_state": (ctypes.c_int, [vp, vp, ctypes.c_size_t]),
         "meg_profile_step": (ctypes.c_int, [vp, P(MegKernelTimes)]),
         "meg_get_counters": (ctypes.c_int, [vp, P(MegCounters), ctypes.c_int32]),
+        "meg_dual_gap": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_double, P(MegDualGapInfo)]),
         "meg_destroy": (None, [vp]),
         "meg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
         "meg_server_create": (ctypes.c_int, [P(vp), P(MegServerParams), vp]),
@@ -382,6 +392,13 @@ class LowRankMEG:
         _check(self._lib.meg_get_counters(self._ctx, ctypes.byref(out), 1 if reset else 0), "meg_get_counters")
         return {"launches": out.launches, "iterations": out.iterations, "applies": out.applies,
                 "workgroups": out.workgroups, "jacobi_sweeps": out.jacobi_sweeps, "kernel_ms": out.kernel_ms}
+
+    def dual_gap(self, max_steps: int = 128, tol: float = 1e-10) -> dict:
+        """Dual gap <X_t, G> - lambda_min(G) at the current iterate (G its
+        gradient), with the Lanczos run's step count and residual; synchronises."""
+        out = MegDualGapInfo()
+        _check(self._lib.meg_dual_gap(self._ctx, int(max_steps), float(tol), ctypes.byref(out)), "meg_dual_gap")
+        return out.as_dict()
 
     def close(self) -> None:
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

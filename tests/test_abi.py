@@ -51,11 +51,12 @@ def test_struct_layout_matches_header(M):
 #define P(T) printf(#T " %zu\n", sizeof(T));
 #define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
 int main(void) {
-  P(meg_params) P(meg_objective) P(meg_start) P(meg_step_info) P(meg_kernel_times) P(meg_counters)
+  P(meg_params) P(meg_objective) P(meg_start) P(meg_step_info) P(meg_kernel_times) P(meg_counters) P(meg_dual_gap_info)
   O(meg_kernel_times, apply_ms) O(meg_kernel_times, finalize_ms) O(meg_kernel_times, workgroups)
   O(meg_kernel_times, wg_apply_ms) O(meg_kernel_times, wg_skew_ms) O(meg_kernel_times, reduce_ms)
   O(meg_kernel_times, rr_ms) O(meg_kernel_times, rr_tail_ms) O(meg_kernel_times, jacobi_sweeps)
   O(meg_counters, applies) O(meg_counters, workgroups) O(meg_counters, jacobi_sweeps) O(meg_counters, kernel_ms)
+  O(meg_dual_gap_info, lambda_min) O(meg_dual_gap_info, t) O(meg_dual_gap_info, steps) O(meg_dual_gap_info, converged)
   O(meg_params, eta) O(meg_params, seed) O(meg_params, flags) O(meg_params, inner_tol)
   O(meg_objective, dense) O(meg_objective, ld) O(meg_objective, nnz) O(meg_objective, batch_idx)
   O(meg_objective, batch_steps) O(meg_start, V0) O(meg_start, lambda0)
@@ -82,7 +83,7 @@ int main(void) {
         k, v = line.split()
         want[k] = int(v)
     S = {"meg_params": M.MegParams, "meg_objective": M.MegObjective, "meg_start": M.MegStart,
-         "meg_step_info": M.MegStepInfo, "meg_kernel_times": M.MegKernelTimes, "meg_counters": M.MegCounters,
+         "meg_step_info": M.MegStepInfo, "meg_kernel_times": M.MegKernelTimes, "meg_counters": M.MegCounters, "meg_dual_gap_info": M.MegDualGapInfo,
          "meg_server_params": M.MegServerParams, "meg_request": M.MegRequest,
          "meg_request_status": M.MegRequestStatus, "meg_server_stats": M.MegServerStats}
     for k, v in want.items():
@@ -222,4 +223,6 @@ def test_null_context_calls(M):
     assert lib.meg_get_counters(None, ctypes.byref(cnt), 0) == M.MEG_ERR_INVALID_ARG
     g = M.MegObjective(kind=M.MEG_GRAD_LINEAR_DENSE, dense=0x1000, ld=64)
     assert lib.meg_step_external(None, ctypes.byref(g), None) == M.MEG_ERR_INVALID_ARG
+    dg = M.MegDualGapInfo()
+    assert lib.meg_dual_gap(None, 64, 1e-10, ctypes.byref(dg)) == M.MEG_ERR_INVALID_ARG
     lib.meg_destroy(None)  # no-op
