@@ -300,6 +300,16 @@ typedef struct {
 
 meg_status meg_dual_gap(meg_ctx ctx, int32_t max_steps, double tol, meg_dual_gap_info* out);
 
+/* Iterate until the dual gap of the current iterate is <= tol (the stopping
+ * rule of Section 7's measure) or max_iters iterations are done: the gap is
+ * evaluated first, then after every check_every iterations (1..64, launched
+ * together) as meg_dual_gap(ctx, 256, 1e-8, .) does.  *last (optional) as
+ * meg_solve's; *gap (optional) the last evaluation.  Objectives as
+ * meg_dual_gap (MEG_ERR_UNSUPPORTED otherwise); MEG_ERR_INVALID_ARG for
+ * max_iters < 0, tol <= 0 or check_every outside 1..64.  Synchronises. */
+meg_status meg_solve_to_gap(meg_ctx ctx, int64_t max_iters, double tol, int32_t check_every, meg_step_info* last,
+                            meg_dual_gap_info* gap);
+
 void meg_destroy(meg_ctx ctx);
 const char* meg_status_str(meg_status s);
 

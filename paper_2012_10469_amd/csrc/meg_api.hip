@@ -1327,6 +1327,36 @@ meg_status meg_dual_gap(meg_ctx c, int32_t max_steps, double tol, meg_dual_gap_i
   return MEG_OK;
 }
 
+meg_status meg_solve_to_gap(meg_ctx c, int64_t max_iters, double tol, int32_t check_every, meg_step_info* last,
+                            meg_dual_gap_info* gap) {
+  meg_status st = check_ctx(c);
+  if (st != MEG_OK) return st;
+  if (max_iters < 0 || !(tol > 0.0) || check_every < 1 || check_every > kChunkSteps) return MEG_ERR_INVALID_ARG;
+  if (c->external || c->cfg.kind == QUADMEAS) return MEG_ERR_UNSUPPORTED;
+  meg_dual_gap_info g{};
+  st = meg_dual_gap(c, 256, 1e-8, &g);
+  int64_t done = 0;
+  while (st == MEG_OK && done < max_iters && g.gap > tol) {
+    const int m = (int)std::min<int64_t>(check_every, max_iters - done);
+    HIPCHK(c, launch_steps(c, m));
+    done += m;
+    st = copy_ctl_to_host(c);
+    if (st == MEG_OK) st = check_barrier(c);
+    if (st != MEG_OK) return st;
+    if (c->h_ctl->status) return (meg_status)c->h_ctl->status;
+    st = meg_dual_gap(c, 256, 1e-8, &g);
+  }
+  if (st != MEG_OK) return st;
+  st = copy_ctl_to_host(c);
+  if (st != MEG_OK) return st;
+  if (last) {
+    fill_info(*c->h_ctl, last);
+    last->f = __builtin_nan("");
+  }
+  if (gap) *gap = g;
+  return MEG_OK;
+}
+
 meg_status meg_get_counters(meg_ctx c, meg_counters* out, int32_t reset) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;

@@ -48,7 +48,7 @@ MEG_SERVER_FLAG_GRAPH = 1
 EXPORTED = [
     "meg_block_size", "meg_init", "meg_step", "meg_solve", "meg_certificate", "meg_objective_value",
     "meg_get_iterate", "meg_set_iterate", "meg_get_state", "meg_set_state", "meg_profile_step", "meg_destroy",
-    "meg_status_str", "meg_get_counters", "meg_step_external", "meg_dual_gap",
+    "meg_status_str", "meg_get_counters", "meg_step_external", "meg_dual_gap", "meg_solve_to_gap",
     "meg_server_create", "meg_server_submit", "meg_server_run", "meg_server_query", "meg_server_result",
     "meg_server_release", "meg_server_team", "meg_server_get_stats", "meg_server_destroy",
 ]
@@ -176,6 +176,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "meg_profile_step": (ctypes.c_int, [vp, P(MegKernelTimes)]),
         "meg_get_counters": (ctypes.c_int, [vp, P(MegCounters), ctypes.c_int32]),
         "meg_dual_gap": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_double, P(MegDualGapInfo)]),
+        "meg_solve_to_gap": (ctypes.c_int, [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, P(MegStepInfo),
+                                            P(MegDualGapInfo)]),
         "meg_destroy": (None, [vp]),
         "meg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
         "meg_server_create": (ctypes.c_int, [P(vp), P(MegServerParams), vp]),
@@ -399,6 +401,14 @@ class LowRankMEG:
         out = MegDualGapInfo()
         _check(self._lib.meg_dual_gap(self._ctx, int(max_steps), float(tol), ctypes.byref(out)), "meg_dual_gap")
         return out.as_dict()
+
+    def solve_to_gap(self, max_iters: int, tol: float, check_every: int = 8) -> tuple:
+        """Iterate until the dual gap is <= tol (checked every check_every
+        iterations) or max_iters; returns (last step info, last gap)."""
+        info, gap = MegStepInfo(), MegDualGapInfo()
+        _check(self._lib.meg_solve_to_gap(self._ctx, int(max_iters), float(tol), int(check_every), ctypes.byref(info),
+                                          ctypes.byref(gap)), "meg_solve_to_gap")
+        return info.as_dict(), gap.as_dict()
 
     def close(self) -> None:
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

@@ -225,4 +225,5 @@ def test_null_context_calls(M):
     assert lib.meg_step_external(None, ctypes.byref(g), None) == M.MEG_ERR_INVALID_ARG
     dg = M.MegDualGapInfo()
     assert lib.meg_dual_gap(None, 64, 1e-10, ctypes.byref(dg)) == M.MEG_ERR_INVALID_ARG
+    assert lib.meg_solve_to_gap(None, 10, 1e-3, 4, None, ctypes.byref(dg)) == M.MEG_ERR_INVALID_ARG
     lib.meg_destroy(None)  # no-op

@@ -140,3 +140,30 @@ def test_dual_gap_rejects(meg):
         with pytest.raises(meg.MegError) as e:
             g2.dual_gap(max_steps=0)
         assert e.value.status == meg.MEG_ERR_INVALID_ARG
+
+
+def test_solve_to_gap_stops_at_the_first_small_gap(meg):
+    """meg_solve_to_gap with a check after every iteration stops at the first
+    iterate whose dual gap is <= tol: the same iterate that stepping one
+    iteration at a time and evaluating the gap reaches (the launches give
+    bitwise the same trajectory), and its gap is <= tol by the oracle."""
+    prec, n, rank, tol = 0, 96, 2, 2e-3
+    print_case(test="solve_to_gap", n=n, tol=tol)
+    M, V0, lam0 = gapped_spiked(n, rank, seed=800)
+    with make_dense(M, meg.MEG_GRAD_DENOISE_DENSE, V0, lam0, rank, prec, eta=1.0, max_inner=40) as a, \
+            make_dense(M, meg.MEG_GRAD_DENOISE_DENSE, V0, lam0, rank, prec, eta=1.0, max_inner=40) as b:
+        info, gap = a.solve_to_gap(200, tol, check_every=1)
+        steps = 0
+        while b.dual_gap(256, 1e-8)["gap"] > tol:
+            b.step(info=False)
+            steps += 1
+            assert steps < 200
+        ta, tb = a.get_iterate()[3], b.get_iterate()[3]
+        print(f"  stopped at t={ta} (stepwise t={tb}), gap={gap['gap']:.4e}", flush=True)
+        assert ta == tb == steps + 1 and gap["t"] == ta and gap["gap"] <= tol
+        out, ref = compare(a, lambda X: X - M, prec, "at stop")
+        assert ref <= tol * (1 + 1e-9)
+        # coarser checks stop at or after that point
+        with make_dense(M, meg.MEG_GRAD_DENOISE_DENSE, V0, lam0, rank, prec, eta=1.0, max_inner=40) as c:
+            _, gc = c.solve_to_gap(200, tol, check_every=5)
+            assert gc["gap"] <= tol and gc["t"] >= ta and (gc["t"] - 1) % 5 == 0
