@@ -130,17 +130,21 @@ __device__ __forceinline__ int jacobi_next(int pos) { return pos == 0 ? 0 : (pos
 
 // Cyclic parallel Jacobi as below, for blocks larger than 16: the KB/2
 // rotations of a round are computed once (lane m < KB/2 computes rotation m)
-// into LDS (`rot`, 2 * KB/2 doubles), then every lane updates its 2 x 2
-// blocks one after the other.  Blocks are disjoint, so once the rotations
-// are fixed the updates need no ordering among them.
+// into LDS (`rot`, 2 * KB doubles: c, s, then the pair's positions), then
+// every lane updates its 2 x 2 blocks.  Lane l owns the blocks (m1, m2) with
+// m2 = l % (KB/2) and m1 = l / (KB/2) + (64 / (KB/2)) b, so it reads rotation
+// m2 once per round.  Blocks are disjoint, so all of a lane's reads precede
+// its writes.
 template <int KB>
 __device__ __noinline__ int jacobi_shared_rot(lds<double>* A, lds<double>* S, double off2_tol, int lane,
                                               lds<double>* rot) {
   constexpr int LD = KB + 1;
   constexpr int NP = KB / 2;
   constexpr int BPL = NP * NP / 64;
+  static_assert(64 % NP == 0, "whole rows of blocks per lane group");
   for (int e = lane; e < KB * KB; e += 64) S[(e / KB) * LD + (e % KB)] = (e / KB == e % KB) ? 1.0 : 0.0;
   wsync();
+  const int m2 = lane % NP;
   int sweep = 0;
   for (; sweep < 30; ++sweep) {
     double off = 0.0, dia = 0.0;
@@ -165,26 +169,44 @@ __device__ __noinline__ int jacobi_shared_rot(lds<double>* A, lds<double>* S, do
       am = jacobi_next<KB>(am);
       bm = jacobi_next<KB>(bm);
       wsync();
+      const double c2 = rot[2 * m2], s2 = rot[2 * m2 + 1];
+      const int p2 = (int)rot[KB + 2 * m2], q2 = (int)rot[KB + 2 * m2 + 1];
+      double c1[BPL], s1[BPL], a[BPL], b[BPL], cc[BPL], d[BPL], sx[BPL][2], sy[BPL][2];
+      int p1[BPL], q1[BPL];
 #pragma unroll
       for (int bi = 0; bi < BPL; ++bi) {
-        const int bl = lane + 64 * bi;
-        const int m1 = bl / NP, m2 = bl % NP;
-        const double c1 = rot[2 * m1], s1 = rot[2 * m1 + 1], c2 = rot[2 * m2], s2 = rot[2 * m2 + 1];
-        const int p1 = (int)rot[KB + 2 * m1], q1 = (int)rot[KB + 2 * m1 + 1];
-        const int p2 = (int)rot[KB + 2 * m2], q2 = (int)rot[KB + 2 * m2 + 1];
-        const double a = A[p1 * LD + p2], b = A[p1 * LD + q2], cc = A[q1 * LD + p2], d = A[q1 * LD + q2];
-        const double ra = c1 * a - s1 * cc, rb = c1 * b - s1 * d;  // rows: J1^T
-        const double rc = s1 * a + c1 * cc, rd = s1 * b + c1 * d;
-        A[p1 * LD + p2] = c2 * ra - s2 * rb;                       // columns: J2
-        A[p1 * LD + q2] = s2 * ra + c2 * rb;
-        A[q1 * LD + p2] = c2 * rc - s2 * rd;
-        A[q1 * LD + q2] = s2 * rc + c2 * rd;
+        const int m1 = lane / NP + (64 / NP) * bi;
+        c1[bi] = rot[2 * m1];
+        s1[bi] = rot[2 * m1 + 1];
+        p1[bi] = (int)rot[KB + 2 * m1];
+        q1[bi] = (int)rot[KB + 2 * m1 + 1];
+      }
+#pragma unroll
+      for (int bi = 0; bi < BPL; ++bi) {
+        a[bi] = A[p1[bi] * LD + p2];
+        b[bi] = A[p1[bi] * LD + q2];
+        cc[bi] = A[q1[bi] * LD + p2];
+        d[bi] = A[q1[bi] * LD + q2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {  // S <- S J1 in rows 2 m2, 2 m2 + 1
           const int row = 2 * m2 + h;
-          const double x = S[row * LD + p1], y = S[row * LD + q1];
-          S[row * LD + p1] = c1 * x - s1 * y;
-          S[row * LD + q1] = s1 * x + c1 * y;
+          sx[bi][h] = S[row * LD + p1[bi]];
+          sy[bi][h] = S[row * LD + q1[bi]];
+        }
+      }
+#pragma unroll
+      for (int bi = 0; bi < BPL; ++bi) {
+        const double ra = c1[bi] * a[bi] - s1[bi] * cc[bi], rb = c1[bi] * b[bi] - s1[bi] * d[bi];  // rows: J1^T
+        const double rc = s1[bi] * a[bi] + c1[bi] * cc[bi], rd = s1[bi] * b[bi] + c1[bi] * d[bi];
+        A[p1[bi] * LD + p2] = c2 * ra - s2 * rb;                                                // columns: J2
+        A[p1[bi] * LD + q2] = s2 * ra + c2 * rb;
+        A[q1[bi] * LD + p2] = c2 * rc - s2 * rd;
+        A[q1[bi] * LD + q2] = s2 * rc + c2 * rd;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int row = 2 * m2 + h;
+          S[row * LD + p1[bi]] = c1[bi] * sx[bi][h] - s1[bi] * sy[bi][h];
+          S[row * LD + q1[bi]] = s1[bi] * sx[bi][h] + c1[bi] * sy[bi][h];
         }
       }
       wsync();
