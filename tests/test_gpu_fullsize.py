@@ -1,0 +1,131 @@
+"""Parity at the full sizes, in the launch configuration the benchmark times.
+
+- Matrix completion, n = 4096, r = 10 (k = 16), the benchmark's workload and
+  solver settings (FP32 state, eta = 1, at most 12 sweeps, 256 persistent
+  workgroups with the CSR slices in LDS): teacher-forced steps from the warm
+  start and from the GPU's own iterate after a 64-iteration launch, compared
+  with the oracle's step (dense gradient, LAPACK top-(r+1) eigenpairs) to the
+  FP32 tolerance, with f(X_t) and the certificate.
+- Precision form, n = 16384, r = 16 (k = 32), M as bf16 planes: one step from
+  the warm start, checked on what the oracle can compute one vector at a
+  time: the returned eigenvectors' residuals against the exact M_1 (products
+  with the dense M in FP64), and the properties of X_2 (unit trace,
+  positivity, orthonormal V).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import meg_oracle as O
+from tests.helpers import TOL_X, dev, f_tol, rel_x_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def meg():
+    from paper_2012_10469_amd import meg as m
+
+    m.load_library()
+    return m
+
+
+def print_case(**kw):
+    print("CASE " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def test_matrix_completion_full_size(meg):
+    n, r = 4096, 10
+    print_case(test="mc_full_size", n=n, r=r)
+    p = W.matrix_completion(n, seed=1, rank=5, p=0.1, r=r, dtype=np.float32)
+    obj = O.MaskedObjective(n, p.row_ptr, p.col, p.val.astype(np.float64))
+    g = meg.LowRankMEG(n, r, meg.MEG_GRAD_MASKED_CSR, p.V0, p.lam0, prec=meg.MEG_PREC_F32, eta=1.0,
+                       row_ptr=dev(p.row_ptr.astype(np.int32)), col=dev(p.col.astype(np.int32)),
+                       val=dev(p.val.astype(np.float32)), max_inner=12)
+    try:
+        assert g.counters()["workgroups"] == 256
+
+        def teacher_forced_step():
+            V, d, a, t = g.get_iterate()
+            it = O.FactoredIterate(V, d, a, t)
+            X = it.dense()
+            G = obj.grad(X)
+            ref, ri = O.lowrank_step(it, G, 1.0, O.eps_schedule(t), r, full=False)
+            info = g.step()
+            err = rel_x_err(g.get_iterate(), ref)
+            f_ref = obj.value(X)
+            print(f"  t={t} err={err:.2e} gap={ri['gap']:.3f} sweeps={info['inner_iters']} conv={info['converged']} "
+                  f"f={info['f']:.8e}/{f_ref:.8e} L={info['cert_L']:.5f}/{ri['L']:.5f}", flush=True)
+            assert abs(info["f"] - f_ref) <= f_tol(f_ref, np.linalg.norm(G), np.linalg.norm(X), 1)
+            assert info["converged"] == 1
+            assert err <= TOL_X[1]
+            # mu_{r+1} is the (r+1)-th Ritz value: by interlacing not above the
+            # true eigenvalue, so the GPU certificate is never more pessimistic;
+            # with r = 10 > rank 5 that eigenvalue lies in the bulk of the
+            # spectrum, known only to within the bulk's width
+            dL = info["cert_L"] - ri["L"]
+            assert -0.1 <= dL <= 1e-5 + 2.0 * info["resid_max"]
+
+        teacher_forced_step()  # from the warm start (t = 1)
+        teacher_forced_step()
+        g.solve(64)            # one 64-iteration launch, as the benchmark times it
+        teacher_forced_step()  # from the GPU's own X_67
+    finally:
+        g.close()
+
+
+def test_precision_form_full_size(meg):
+    import torch
+
+    n, r, rank = 16384, 16, 8
+    print_case(test="bf16x3_full_size", n=n, r=r)
+    prob = W.lowrank_noise_denoise(n, rank=rank, seed=1, noise=1e-3, r=r, dtype=np.float32)
+    hi, lo = W.bf16_planes(prob.M)
+    del prob.M
+    Mp = W.planes_value(hi, lo, n)  # the matrix the planes represent, FP64
+    dhi = torch.from_numpy(hi.view(np.int16)).cuda()
+    dlo = torch.from_numpy(lo.view(np.int16)).cuda()
+    del hi, lo
+    torch.cuda.synchronize()
+    g = meg.LowRankMEG(n, r, meg.MEG_GRAD_DENOISE_DENSE, prob.V0, prob.lam0, prec=meg.MEG_PREC_F32_BF16X3,
+                       eta=1.0, dense=dhi, dense_lo=dlo, max_inner=40)
+    try:
+        assert g.k == 32
+        V1, d1, a1, t1 = g.get_iterate()
+        info = g.step()
+        V, d, a, t = g.get_iterate()
+        print(f"  step: sweeps={info['inner_iters']} conv={info['converged']} sigma={info['sigma']:.4f} "
+              f"L={info['cert_L']:.4f} gap={info['ritz_gap']:.4f}", flush=True)
+        assert t == t1 + 1 and info["converged"] == 1
+        # X_2 lies in the spectrahedron and V is orthonormal
+        assert abs(n * a + float(np.sum(d)) - 1.0) <= 1e-6
+        assert a > 0 and float(np.min(a + d)) > 0
+        assert np.max(np.abs(V.T @ V - np.eye(r))) <= 1e-5
+        # residuals of the returned eigenvectors against the exact
+        # M_1 = log X_1 - eta (X_1 - M), X_1 = a1 I + V1 diag(d1) V1^T
+        c1 = np.log(a1 + d1) - math.log(a1)
+
+        def M1(Y):
+            logx = math.log(a1) * Y + V1 @ (c1[:, None] * (V1.T @ Y))
+            x1 = a1 * Y + V1 @ (d1[:, None] * (V1.T @ Y))
+            return logx - (x1 - Mp @ Y)
+
+        MV = M1(V)
+        rq = np.einsum("ij,ij->j", V, MV)
+        res = np.linalg.norm(MV - V * rq, axis=0)
+        # the solver's threshold is relative to the largest Ritz value of the
+        # shifted operator; pairs of negligible weight in X_2 are exempt
+        theta1 = float(rq.max()) - math.log(a1) + info["sigma"]
+        w = np.abs(d) / np.abs(d).max()
+        print(f"  residuals (weight > 1e-6): max {res[w > 1e-6].max():.2e}, theta1 {theta1:.3f}", flush=True)
+        assert np.all(res[w > 1e-6] <= 2e-5 * theta1)
+        # the returned weights follow the Rayleigh quotients: d' = (1-eps) softmax(mu) - alpha'
+        eps = O.eps_schedule(t1)
+        d_ref = (1.0 - eps) * O.softmax(rq) - eps / (n - r)
+        assert np.max(np.abs(d - d_ref)) <= 1e-5 * np.abs(d).max()
+    finally:
+        g.close()
+        del dhi, dlo
+        torch.cuda.empty_cache()
