@@ -484,11 +484,13 @@ meg_status copy_ctl_to_host(meg_ctx c) {
   return MEG_OK;
 }
 
-// Smallest eigenvalue of the gradient G = grad f(X_t) by Lanczos (full
-// reorthogonalisation, host recurrence in FP64, products with G on the
-// device): linear G = C, denoising G = alpha I + V diag(d) V^T - M (the
-// low-rank part on the host from the materialised V), masked G = the CSR
-// pattern with the values xdotg wrote into c->g.
+// Smallest eigenvalue of the gradient G = grad f(X_t) by Lanczos with full
+// reorthogonalisation (two classical Gram-Schmidt passes).  The basis, the
+// recurrence and the products with G run on the device (products: k_matvec
+// with C, M, or the pattern holding the gradient values xdotg wrote into
+// c->g; denoising adds alpha x + V diag(d) V^T x from the materialised
+// basis); the host only draws the start vector and, every 8 steps, solves
+// the small tridiagonal eigenproblem for the convergence test.
 template <typename T>
 meg_status lanczos_grad_min(meg_ctx c, int max_steps, double tol, meg_dual_gap_info* out) {
   const Cfg& cfg = c->cfg;
@@ -497,108 +499,99 @@ meg_status lanczos_grad_min(meg_ctx c, int max_steps, double tol, meg_dual_gap_i
   const int m = (int)std::min<int64_t>(n, max_steps);
   const bool den = cfg.kind == DENOISE_DENSE;
   const bool masked = cfg.kind == MASKED_CSR;
-  std::vector<double> Vh, dh(c->h_ctl->d, c->h_ctl->d + r);
-  const double alpha = c->h_ctl->alpha;
-  if (den) {  // V = first r columns of the materialised basis (block (src + 1) mod 3)
-    std::vector<T> Q((size_t)n * KB);
-    HIPCHK(c, hipMemcpy(Q.data(), block(c, (c->h_ctl->src + 1) % 3), Q.size() * sizeof(T), hipMemcpyDeviceToHost));
-    Vh.resize((size_t)n * r);
-    for (int64_t i = 0; i < n; ++i)
-      for (int l = 0; l < r; ++l) Vh[(size_t)i * r + l] = (double)Q[(size_t)i * KB + l];
-  }
-  T* dx = nullptr;
-  double* dy = nullptr;
-  if (hipMalloc((void**)&dx, n * sizeof(T)) != hipSuccess) return MEG_ERR_OUT_OF_MEMORY;
-  if (hipMalloc((void**)&dy, n * sizeof(double)) != hipSuccess) {
-    (void)hipFree(dx);
+  const T* Qm = (const T*)block(c, (c->h_ctl->src + 1) % 3);  // materialised basis (xdotg)
+  double *V = nullptr, *y = nullptr, *w = nullptr, *h = nullptr, *ab = nullptr, *lp = nullptr;
+  T* xt = nullptr;
+  auto al = [&](void** q, size_t bytes) { return hipMalloc(q, std::max<size_t>(bytes, 256)) == hipSuccess; };
+  bool ok = al((void**)&V, (size_t)(m + 1) * n * 8) && al((void**)&y, n * 8) && al((void**)&w, n * 8) &&
+            al((void**)&h, (size_t)(m + 1) * 8) && al((void**)&ab, (size_t)2 * m * 8) && al((void**)&lp, KMAX * 8) &&
+            al((void**)&xt, n * sizeof(T));
+  auto release = [&]() {
+    for (void* q : {(void*)V, (void*)y, (void*)w, (void*)h, (void*)ab, (void*)lp, (void*)xt})
+      if (q) (void)hipFree(q);
+  };
+  if (!ok) {
+    (void)hipGetLastError();
+    release();
     return MEG_ERR_OUT_OF_MEMORY;
   }
-  auto apply = [&](const double* v, std::vector<double>& y, std::vector<T>& xt) -> meg_status {
-    for (int64_t i = 0; i < n; ++i) xt[i] = (T)v[i];
-    if (hipMemcpy(dx, xt.data(), n * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return hip_fail(c);
-    hipLaunchKernelGGL((k_matvec<T>), dim3(ceil_div(n, 4)), dim3(256), 0, c->stream, cfg,
-                       Launch<T, 16>::dense_src(c), c->obj.row_ptr, c->obj.col,
-                       masked ? (const T*)c->g : (const T*)c->obj.val, (const T*)dx, dy);
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
-        hipMemcpy(y.data(), dy, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
-      return hip_fail(c);
-    if (den) {  // y = alpha x + V diag(d) V^T x - M x, with x as the device saw it
-      std::vector<double> p(r, 0.0);
-      for (int64_t i = 0; i < n; ++i)
-        for (int l = 0; l < r; ++l) p[l] += Vh[(size_t)i * r + l] * (double)xt[i];
-      for (int l = 0; l < r; ++l) p[l] *= dh[l];
-      for (int64_t i = 0; i < n; ++i) {
-        double s = alpha * (double)xt[i] - y[i];
-        for (int l = 0; l < r; ++l) s += Vh[(size_t)i * r + l] * p[l];
-        y[i] = s;
-      }
-    }
-    return MEG_OK;
-  };
-  std::vector<double> Vs((size_t)(m + 1) * n), y(n), w(n);
-  std::vector<T> xt(n);
-  std::vector<double> al(m, 0.0), be(m, 0.0);
+  // seeded start vector, normalised on the host
+  std::vector<double> v0(n);
   SplitMix rng{c->params.seed ^ 0x6475616c67617021ull ^ (uint64_t)c->h_ctl->t};
   double nrm = 0.0;
   for (int64_t i = 0; i < n; ++i) {
-    Vs[i] = rng.normal();
-    nrm += Vs[i] * Vs[i];
+    v0[i] = rng.normal();
+    nrm += v0[i] * v0[i];
   }
   nrm = std::sqrt(nrm);
-  for (int64_t i = 0; i < n; ++i) Vs[i] /= nrm;
-  // smallest Ritz pair of the (j + 1) x (j + 1) tridiagonal
-  auto ritz_min = [&](int j1, double& theta, double& res, double& scale) {
+  for (int64_t i = 0; i < n; ++i) v0[i] /= nrm;
+  meg_status st = MEG_OK;
+  std::vector<double> abh(2 * (size_t)m);
+  double theta = 0.0, res = 0.0;
+  int done = 0;
+  bool conv = false;
+  const int gv = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256));
+  const hipStream_t sm = c->stream;
+  if (hipMemcpyAsync(V, v0.data(), n * 8, hipMemcpyHostToDevice, sm) != hipSuccess) st = hip_fail(c);
+  for (int j = 0; st == MEG_OK && j < m; ++j) {
+    const double* vj = V + (int64_t)j * n;
+    // y = G v_j
+    hipLaunchKernelGGL((k_lz_cast<T>), dim3(gv), dim3(256), 0, sm, vj, n, xt);
+    hipLaunchKernelGGL((k_matvec<T>), dim3(ceil_div(n, 4)), dim3(256), 0, sm, cfg, Launch<T, 16>::dense_src(c),
+                       c->obj.row_ptr, c->obj.col, masked ? (const T*)c->g : (const T*)c->obj.val, (const T*)xt, y);
+    if (den) {
+      hipLaunchKernelGGL((k_lz_lr_dots<T>), dim3(r), dim3(256), 0, sm, Qm, KB, (const T*)xt, n, lp);
+      hipLaunchKernelGGL((k_lz_lr_update<T>), dim3(gv), dim3(256), 0, sm, (const Ctl*)c->ctl, Qm, KB, r,
+                         (const T*)xt, (const double*)lp, n, y);
+    }
+    // alpha_j, the three-term recurrence, two reorthogonalisation passes, beta_j and v_{j+1}
+    hipLaunchKernelGGL(k_lz_dots, dim3(1), dim3(256), 0, sm, vj, (const double*)y, n, ab + j);
+    hipLaunchKernelGGL(k_lz_three_term, dim3(gv), dim3(256), 0, sm, (const double*)V, (const double*)y,
+                       (const double*)ab, j, m, n, w);
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(k_lz_dots, dim3(j + 1), dim3(256), 0, sm, (const double*)V, (const double*)w, n, h);
+      hipLaunchKernelGGL(k_lz_sub, dim3(gv), dim3(256), 0, sm, (const double*)V, (const double*)h, j + 1, n, w);
+    }
+    hipLaunchKernelGGL(k_lz_next, dim3(1), dim3(256), 0, sm, (const double*)w, j, m, n, ab, V);
+    if (hipGetLastError() != hipSuccess) {
+      st = hip_fail(c);
+      break;
+    }
+    done = j + 1;
+    if (done % 8 != 0 && done != m) continue;
+    if (hipMemcpyAsync(abh.data(), ab, abh.size() * 8, hipMemcpyDeviceToHost, sm) != hipSuccess ||
+        hipStreamSynchronize(sm) != hipSuccess) {
+      st = hip_fail(c);
+      break;
+    }
+    // the Krylov space is invariant at the first vanishing beta
+    int j1 = done;
+    bool invariant = false;
+    for (int q = 0; q < done; ++q)
+      if (abh[m + q] == 0.0) {
+        j1 = q + 1;
+        invariant = true;
+        break;
+      }
     std::vector<double> Tm((size_t)j1 * j1, 0.0), ev, S;
-    for (int j = 0; j < j1; ++j) {
-      Tm[(size_t)j * j1 + j] = al[j];
-      if (j + 1 < j1) Tm[(size_t)j * j1 + j + 1] = Tm[(size_t)(j + 1) * j1 + j] = be[j];
+    for (int q = 0; q < j1; ++q) {
+      Tm[(size_t)q * j1 + q] = abh[q];
+      if (q + 1 < j1) Tm[(size_t)q * j1 + q + 1] = Tm[(size_t)(q + 1) * j1 + q] = abh[m + q];
     }
     host_sym_eig(Tm, j1, ev, S);
     int imin = 0;
-    scale = 0.0;
-    for (int i = 0; i < j1; ++i) {
-      if (ev[i] < ev[imin]) imin = i;
-      scale = std::max(scale, std::fabs(ev[i]));
+    double scale = 0.0;
+    for (int q = 0; q < j1; ++q) {
+      if (ev[q] < ev[imin]) imin = q;
+      scale = std::max(scale, std::fabs(ev[q]));
     }
     theta = ev[imin];
-    res = std::fabs(be[j1 - 1] * S[(size_t)(j1 - 1) * j1 + imin]);
-  };
-  meg_status st = MEG_OK;
-  double theta = 0.0, res = 0.0, scale = 0.0;
-  int done = 0;
-  bool conv = false;
-  for (int j = 0; j < m; ++j) {
-    const double* v = &Vs[(size_t)j * n];
-    st = apply(v, y, xt);
-    if (st != MEG_OK) break;
-    double a = 0.0;
-    for (int64_t i = 0; i < n; ++i) a += y[i] * v[i];
-    for (int64_t i = 0; i < n; ++i) w[i] = y[i] - a * v[i] - (j > 0 ? be[j - 1] * Vs[(size_t)(j - 1) * n + i] : 0.0);
-    for (int pass = 0; pass < 2; ++pass)
-      for (int l = 0; l <= j; ++l) {
-        const double* u = &Vs[(size_t)l * n];
-        double s = 0.0;
-        for (int64_t i = 0; i < n; ++i) s += u[i] * w[i];
-        for (int64_t i = 0; i < n; ++i) w[i] -= s * u[i];
-      }
-    double b = 0.0;
-    for (int64_t i = 0; i < n; ++i) b += w[i] * w[i];
-    b = std::sqrt(b);
-    al[j] = a;
-    be[j] = b;
-    done = j + 1;
-    const bool invariant = !(b > 1e-14 * (std::fabs(a) + 1e-300));
-    if (invariant) be[j] = 0.0;
-    if (invariant || done % 8 == 0 || done == m) {
-      ritz_min(done, theta, res, scale);
-      conv = res <= tol * scale;
-      if (conv || invariant) break;
-    }
-    double* vn = &Vs[(size_t)(j + 1) * n];
-    for (int64_t i = 0; i < n; ++i) vn[i] = w[i] / b;
+    res = std::fabs(abh[m + j1 - 1] * S[(size_t)(j1 - 1) * j1 + imin]);
+    conv = res <= tol * scale;
+    done = j1;
+    if (conv || invariant) break;
   }
-  (void)hipFree(dx);
-  (void)hipFree(dy);
+  release();
   if (st != MEG_OK) return st;
   out->lambda_min = theta;
   out->resid = res;

@@ -1607,6 +1607,100 @@ static __global__ __launch_bounds__(256) void k_matvec(Cfg cfg, DenseSrc<T> D, c
   if (lane == 0) y[i] = acc;
 }
 
+// ---------------------------------------------------------------------------
+// Lanczos vectors of the dual gap's lambda_min run, all in FP64 on the device
+// (V: the basis, row l = vector l of length n).  Reductions are per workgroup
+// (256 threads) in a fixed order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum256(double v, double* sred) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) sred[wave] = v;
+  __syncthreads();
+  return (sred[0] + sred[1]) + (sred[2] + sred[3]);
+}
+
+// out[l] = V[l] . w for l < cnt: one workgroup per vector
+static __global__ __launch_bounds__(256) void k_lz_dots(const double* __restrict__ V, const double* __restrict__ w,
+                                                        int64_t n, double* __restrict__ out) {
+  __shared__ double sred[4];
+  const double* v = V + (int64_t)blockIdx.x * n;
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) a += v[i] * w[i];
+  a = block_sum256(a, sred);
+  if (threadIdx.x == 0) out[blockIdx.x] = a;
+}
+
+// w -= sum_{l < cnt} h[l] V[l]  (one reorthogonalisation pass)
+static __global__ __launch_bounds__(256) void k_lz_sub(const double* __restrict__ V, const double* __restrict__ h,
+                                                       int cnt, int64_t n, double* __restrict__ w) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double s = 0.0;
+    for (int l = 0; l < cnt; ++l) s += h[l] * V[(int64_t)l * n + i];
+    w[i] -= s;
+  }
+}
+
+// x (the product's input, in the state's type) = (T) V[j]
+template <typename T>
+static __global__ __launch_bounds__(256) void k_lz_cast(const double* __restrict__ v, int64_t n, T* __restrict__ x) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) x[i] = (T)v[i];
+}
+
+// denoising gradient G = alpha I + V diag(d) V^T - M: p[l] = sum_i Q[i][l] x[i]
+// for the first r columns of the materialised basis Q (row stride KB), one
+// workgroup per column
+template <typename T>
+static __global__ __launch_bounds__(256) void k_lz_lr_dots(const T* __restrict__ Q, int KB, const T* __restrict__ x,
+                                                           int64_t n, double* __restrict__ p) {
+  __shared__ double sred[4];
+  const int l = blockIdx.x;
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) a += (double)Q[i * KB + l] * (double)x[i];
+  a = block_sum256(a, sred);
+  if (threadIdx.x == 0) p[l] = a;
+}
+// y <- alpha x + sum_l Q[i][l] d_l p[l] - y   (y held M x)
+template <typename T>
+static __global__ __launch_bounds__(256) void k_lz_lr_update(const Ctl* __restrict__ ctl, const T* __restrict__ Q, int KB,
+                                                             int r, const T* __restrict__ x,
+                                                             const double* __restrict__ p, int64_t n,
+                                                             double* __restrict__ y) {
+  const double alpha = ctl->alpha;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double s = alpha * (double)x[i] - y[i];
+    for (int l = 0; l < r; ++l) s += (double)Q[i * KB + l] * ctl->d[l] * p[l];
+    y[i] = s;
+  }
+}
+
+// w = y - alpha_j v_j - beta_{j-1} v_{j-1}, with alpha_j = ab[j] (from
+// k_lz_dots of v_j and y) and beta_{j-1} = ab[m + j - 1]
+static __global__ __launch_bounds__(256) void k_lz_three_term(const double* __restrict__ V, const double* __restrict__ y,
+                                                              const double* __restrict__ ab, int j, int m, int64_t n,
+                                                              double* __restrict__ w) {
+  const double a = ab[j], b = j > 0 ? ab[m + j - 1] : 0.0;
+  const double* v = V + (int64_t)j * n;
+  const double* vp = V + (int64_t)(j > 0 ? j - 1 : 0) * n;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    w[i] = y[i] - a * v[i] - b * vp[i];
+}
+
+// beta_j = ||w|| into ab[m + j]; v_{j+1} = w / beta_j, or zero once the
+// Krylov space is invariant (beta_j <= 1e-14 |alpha_j|): one workgroup
+static __global__ __launch_bounds__(256) void k_lz_next(const double* __restrict__ w, int j, int m, int64_t n,
+                                                        double* __restrict__ ab, double* __restrict__ V) {
+  __shared__ double sred[4];
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) a += w[i] * w[i];
+  const double b = sqrt(block_sum256(a, sred));
+  const bool live = b > 1e-14 * (fabs(ab[j]) + 1e-300);
+  if (threadIdx.x == 0) ab[m + j] = live ? b : 0.0;
+  double* vn = V + (int64_t)(j + 1) * n;
+  const double ib = live ? 1.0 / b : 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) vn[i] = w[i] * ib;
+}
+
 // CSR structure check: 0 = rp[0] <= rp[i] <= rp[i+1] <= rp[n] = nnz and every
 // column index in [0, n).  Row ranges are validated before col is read.
 // objective at X_t, quadratic measurements: 1/(2m) sum_i (a_i^T X a_i - b_i)^2
