@@ -280,9 +280,11 @@ meg_status meg_get_counters(meg_ctx ctx, meg_counters* out, int32_t reset);
  * which bounds f(X_t) - f* from above for convex f.  <X_t, G> is accumulated
  * in FP64 over the matrix (dense) or the pattern (CSR); lambda_min(G) is the
  * smallest Ritz value of a Lanczos run with full reorthogonalisation on G
- * (host recurrence, device products with G; seeded start), stopped once its
- * Ritz residual is <= tol * max |Ritz value| (checked every 8 steps) or
- * after max_steps steps.  Objectives: linear (G = C), denoising
+ * (FP64 basis, recurrence and products on the device; seeded start; the
+ * host solves the small tridiagonal problem), stopped once its Ritz residual
+ * is <= tol * max |Ritz value| (checked every 8 steps) or after max_steps
+ * steps.  Allocates its Lanczos basis ((max_steps + 1) x n doubles) for the
+ * call.  Objectives: linear (G = C), denoising
  * (G = X_t - M, also with M as bf16 planes) and masked (G = P_Omega(X_t - M);
  * the call overwrites the context's stored gradient values, which the next
  * step recomputes).  MEG_ERR_UNSUPPORTED for the minibatch and external
