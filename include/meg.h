@@ -280,8 +280,10 @@ meg_status meg_get_counters(meg_ctx ctx, meg_counters* out, int32_t reset);
  * which bounds f(X_t) - f* from above for convex f.  <X_t, G> is accumulated
  * in FP64 over the matrix (dense) or the pattern (CSR); lambda_min(G) is the
  * smallest Ritz value of a Lanczos run with full reorthogonalisation on G
- * (FP64 basis, recurrence and products on the device; seeded start; the
- * host solves the small tridiagonal problem), stopped once its Ritz residual
+ * (FP64 basis, recurrence and products on the device; the host solves the
+ * small tridiagonal problem), started from the previous call's lambda_min
+ * Ritz vector plus 1e-3 of a seeded Gaussian vector (the Gaussian vector
+ * alone on the first call), stopped once its Ritz residual
  * is <= tol * max |Ritz value| (checked every 8 steps) or after max_steps
  * steps.  Allocates its Lanczos basis ((max_steps + 1) x n doubles) for the
  * call.  Objectives: linear (G = C), denoising

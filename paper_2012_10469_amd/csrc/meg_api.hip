@@ -47,6 +47,7 @@ struct meg_ctx_s {
   void* quad = nullptr;  // factored gradient scratch: y (L x k), K (L x L), w (L), ||a||^2 (L)
   Ctl* ctl = nullptr;
   double* part = nullptr;
+  double* lz_prev = nullptr;  // the dual gap's last lambda_min Ritz vector (n doubles), its next start
   double* gpart = nullptr;
   double* sums = nullptr;
   unsigned* bar = nullptr;
@@ -515,18 +516,29 @@ meg_status lanczos_grad_min(meg_ctx c, int max_steps, double tol, meg_dual_gap_i
     release();
     return MEG_ERR_OUT_OF_MEMORY;
   }
-  // seeded start vector, normalised on the host
+  // start vector: the previous call's lambda_min Ritz vector (the gradient
+  // changes little between nearby iterates) plus 1e-3 of a seeded Gaussian
+  // vector, or the Gaussian vector alone; normalised on the host
   std::vector<double> v0(n);
   SplitMix rng{c->params.seed ^ 0x6475616c67617021ull ^ (uint64_t)c->h_ctl->t};
-  double nrm = 0.0;
-  for (int64_t i = 0; i < n; ++i) {
-    v0[i] = rng.normal();
-    nrm += v0[i] * v0[i];
+  for (int64_t i = 0; i < n; ++i) v0[i] = rng.normal();
+  if (c->lz_prev) {
+    std::vector<double> u(n);
+    if (hipMemcpy(u.data(), c->lz_prev, n * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+      release();
+      return hip_fail(c);
+    }
+    double gn = 0.0;
+    for (int64_t i = 0; i < n; ++i) gn += v0[i] * v0[i];
+    gn = std::sqrt(gn);
+    for (int64_t i = 0; i < n; ++i) v0[i] = u[i] + 1e-3 * v0[i] / gn;
   }
+  double nrm = 0.0;
+  for (int64_t i = 0; i < n; ++i) nrm += v0[i] * v0[i];
   nrm = std::sqrt(nrm);
   for (int64_t i = 0; i < n; ++i) v0[i] /= nrm;
   meg_status st = MEG_OK;
-  std::vector<double> abh(2 * (size_t)m);
+  std::vector<double> abh(2 * (size_t)m), smin;
   double theta = 0.0, res = 0.0;
   int done = 0;
   bool conv = false;
@@ -589,7 +601,25 @@ meg_status lanczos_grad_min(meg_ctx c, int max_steps, double tol, meg_dual_gap_i
     res = std::fabs(abh[m + j1 - 1] * S[(size_t)(j1 - 1) * j1 + imin]);
     conv = res <= tol * scale;
     done = j1;
+    smin.assign(j1, 0.0);
+    for (int q = 0; q < j1; ++q) smin[q] = S[(size_t)q * j1 + imin];
     if (conv || invariant) break;
+  }
+  // keep the Ritz vector V s of lambda_min for the next call's start
+  if (st == MEG_OK && !smin.empty()) {
+    if (!c->lz_prev && hipMalloc((void**)&c->lz_prev, std::max<size_t>(n * 8, 256)) != hipSuccess) {
+      (void)hipGetLastError();
+      c->lz_prev = nullptr;  // no warm start next time; not an error
+    }
+    if (c->lz_prev) {
+      if (hipMemcpyAsync(h, smin.data(), smin.size() * 8, hipMemcpyHostToDevice, sm) != hipSuccess) {
+        st = hip_fail(c);
+      } else {
+        hipLaunchKernelGGL(k_lz_combine, dim3(gv), dim3(256), 0, sm, (const double*)V, (const double*)h,
+                           (int)smin.size(), n, c->lz_prev);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(sm) != hipSuccess) st = hip_fail(c);
+      }
+    }
   }
   release();
   if (st != MEG_OK) return st;
@@ -771,7 +801,7 @@ meg_status validate(const meg_params* p, const meg_objective* o, const meg_start
 
 void free_ctx(meg_ctx c) {
   if (!c) return;
-  void* bufs[] = {c->Qw, c->Za, c->Zb, c->g, c->quad, c->ctl, c->part, c->gpart, c->sums, c->bar, c->ts};
+  void* bufs[] = {c->Qw, c->Za, c->Zb, c->g, c->quad, c->ctl, c->part, c->gpart, c->sums, c->bar, c->ts, c->lz_prev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);

@@ -1641,6 +1641,16 @@ static __global__ __launch_bounds__(256) void k_lz_sub(const double* __restrict_
   }
 }
 
+// u = sum_{l < cnt} s[l] V[l]  (a Ritz vector from the basis)
+static __global__ __launch_bounds__(256) void k_lz_combine(const double* __restrict__ V, const double* __restrict__ s,
+                                                           int cnt, int64_t n, double* __restrict__ u) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double a = 0.0;
+    for (int l = 0; l < cnt; ++l) a += s[l] * V[(int64_t)l * n + i];
+    u[i] = a;
+  }
+}
+
 // x (the product's input, in the state's type) = (T) V[j]
 template <typename T>
 static __global__ __launch_bounds__(256) void k_lz_cast(const double* __restrict__ v, int64_t n, T* __restrict__ x) {
