@@ -19,7 +19,10 @@ plain-configuration instances (Poisson arrivals, then saturation), against
 the single-instance FP32 path on a sample (`--no-serving` skips it).
 
 `--write-workload PATH` only writes the workload for the native driver
-paper_2012_10469_amd/meg_bench (used under rocprofv3) and exits.
+paper_2012_10469_amd/meg_bench (used under rocprofv3) and exits;
+`--write-dense-workload PATH` writes the precision-form workload of the same
+driver (n = 16384, r = 16, M = W W^T/||W||_F^2 + 1e-3 symmetric noise split
+into bf16 planes, top-eigenvector start) and exits.
 """
 from __future__ import annotations
 
@@ -106,6 +109,31 @@ def write_workload(p, r: int, path: str) -> None:
         f.write(np.ascontiguousarray(p.val, dtype="<f4").tobytes())
         f.write(np.asfortranarray(V0, dtype="<f8").tobytes(order="F"))
         f.write(np.ascontiguousarray(lam0, dtype="<f8").tobytes())
+
+
+def write_dense_workload(path: str, n: int = 16384, r: int = 16, seed: int = 1) -> None:
+    """Precision-form workload of the native driver: "MEGD0001", int64 n,
+    int64 ld, int32 r, int32 q, uint16 hi[n*ld], uint16 lo[n*ld],
+    double V0[n*q] (column-major), double lambda0[q]."""
+    import numpy as np
+
+    import workloads as W
+
+    t0 = time.time()
+    prob = W.lowrank_noise_denoise(n, rank=8, seed=seed, noise=1e-3, r=r, dtype=np.float32, start="top1")
+    hi, lo = W.bf16_planes(prob.M)
+    V0 = np.asarray(prob.V0, dtype=np.float64)
+    if V0.ndim == 1:
+        V0 = V0[:, None]
+    with open(path, "wb") as f:
+        f.write(b"MEGD0001")
+        f.write(np.array([n, hi.shape[1]], dtype="<i8").tobytes())
+        f.write(np.array([r, V0.shape[1]], dtype="<i4").tobytes())
+        f.write(np.ascontiguousarray(hi, dtype="<u2").tobytes())
+        f.write(np.ascontiguousarray(lo, dtype="<u2").tobytes())
+        f.write(np.asfortranarray(V0, dtype="<f8").tobytes(order="F"))
+        f.write(np.ascontiguousarray(prob.lam0, dtype="<f8").tobytes())
+    log(f"[bench] dense workload n={n} written in {time.time() - t0:.1f}s")
 
 
 def cpu_baseline(p, r: int, samples: int):
@@ -269,7 +297,13 @@ def main() -> int:
     ap.add_argument("--serve-plain-sample", type=int, default=32)
     ap.add_argument("--write-workload", default=None, metavar="PATH",
                     help="write the workload file of the native driver and exit (no GPU use)")
+    ap.add_argument("--write-dense-workload", default=None, metavar="PATH",
+                    help="write the precision-form workload file of the native driver and exit (no GPU use)")
     args = ap.parse_args()
+
+    if args.write_dense_workload:
+        write_dense_workload(args.write_dense_workload, seed=args.seed)
+        return 0
 
     if args.write_workload:
         p = matrix_completion_workload(args.n, args.r, args.seed)

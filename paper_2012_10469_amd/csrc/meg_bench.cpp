@@ -1,15 +1,19 @@
 // meg_bench: native driver of the low-rank MEG library for profilers.
 //
-// Runs the masked matrix-completion workload (CSR mask, FP32 state) through
+// Runs the masked matrix-completion workload (CSR mask, FP32 state), or the
+// precision-form denoising workload (M as bf16 planes, FP32 state), through
 // the C ABI only, without Python: warmup iterations, then a timed run of
 // meg_solve launches, then one JSON line with the library's step-kernel
 // counters (launches, iterations, operator applies, HIP-event GPU time) and
-// the host wall clock.  The workload file is written by `bench.py
-// --write-workload PATH` from the same seeded generator the benchmark uses.
+// the host wall clock.  The workload files are written by `bench.py
+// --write-workload PATH` / `--write-dense-workload PATH` from the seeded
+// generators the benchmark and the tests use.
 //
-// File layout (little-endian): "MEGW0001", int64 n, int64 nnz, int32 r,
-// int32 q, int32 row_ptr[n+1], int32 col[nnz], float val[nnz],
-// double V0[n*q] (column-major), double lambda0[q].
+// File layouts (little-endian):
+//   "MEGW0001", int64 n, int64 nnz, int32 r, int32 q, int32 row_ptr[n+1],
+//   int32 col[nnz], float val[nnz], double V0[n*q] (column-major), double lambda0[q];
+//   "MEGD0001", int64 n, int64 ld, int32 r, int32 q, uint16 hi[n*ld],
+//   uint16 lo[n*ld], double V0[n*q] (column-major), double lambda0[q].
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -24,10 +28,12 @@
 namespace {
 
 struct Workload {
-  int64_t n = 0, nnz = 0;
+  bool dense = false;
+  int64_t n = 0, nnz = 0, ld = 0;
   int32_t r = 0, q = 0;
   std::vector<int32_t> row_ptr, col;
   std::vector<float> val;
+  std::vector<uint16_t> hi, lo;
   std::vector<double> V0, lam0;
 };
 
@@ -37,19 +43,27 @@ bool load(const char* path, Workload& w) {
   FILE* f = std::fopen(path, "rb");
   if (!f) return false;
   char magic[8];
-  bool ok = read_all(f, magic, 8) && std::memcmp(magic, "MEGW0001", 8) == 0 && read_all(f, &w.n, 8) &&
-            read_all(f, &w.nnz, 8) && read_all(f, &w.r, 4) && read_all(f, &w.q, 4);
+  bool ok = read_all(f, magic, 8);
+  w.dense = ok && std::memcmp(magic, "MEGD0001", 8) == 0;
+  ok = ok && (w.dense || std::memcmp(magic, "MEGW0001", 8) == 0) && read_all(f, &w.n, 8) &&
+       read_all(f, w.dense ? &w.ld : &w.nnz, 8) && read_all(f, &w.r, 4) && read_all(f, &w.q, 4);
   ok = ok && w.n > 0 && w.nnz >= 0 && w.r >= 1 && w.q >= 1 && w.q <= w.r && w.n < (int64_t)1 << 31 &&
-       w.nnz < (int64_t)1 << 31;
-  if (ok) {
+       w.nnz < (int64_t)1 << 31 && (!w.dense || (w.ld >= w.n && w.ld < (int64_t)1 << 31));
+  if (ok && w.dense) {
+    w.hi.resize((size_t)w.n * w.ld);
+    w.lo.resize((size_t)w.n * w.ld);
+    ok = read_all(f, w.hi.data(), w.hi.size() * 2) && read_all(f, w.lo.data(), w.lo.size() * 2);
+  } else if (ok) {
     w.row_ptr.resize(w.n + 1);
     w.col.resize(w.nnz);
     w.val.resize(w.nnz);
+    ok = read_all(f, w.row_ptr.data(), w.row_ptr.size() * 4) && read_all(f, w.col.data(), w.col.size() * 4) &&
+         read_all(f, w.val.data(), w.val.size() * 4);
+  }
+  if (ok) {
     w.V0.resize((size_t)w.n * w.q);
     w.lam0.resize(w.q);
-    ok = read_all(f, w.row_ptr.data(), w.row_ptr.size() * 4) && read_all(f, w.col.data(), w.col.size() * 4) &&
-         read_all(f, w.val.data(), w.val.size() * 4) && read_all(f, w.V0.data(), w.V0.size() * 8) &&
-         read_all(f, w.lam0.data(), w.lam0.size() * 8);
+    ok = read_all(f, w.V0.data(), w.V0.size() * 8) && read_all(f, w.lam0.data(), w.lam0.size() * 8);
   }
   std::fclose(f);
   return ok;
@@ -90,12 +104,26 @@ int main(int argc, char** argv) {
 
   Workload w;
   if (!load(argv[1], w)) return fail("cannot read workload file", 2);
-  std::fprintf(stderr, "[meg_bench] n=%lld nnz=%lld r=%d q=%d\n", (long long)w.n, (long long)w.nnz, w.r, w.q);
+  std::fprintf(stderr, "[meg_bench] %s n=%lld nnz=%lld ld=%lld r=%d q=%d\n", w.dense ? "dense bf16 planes" : "csr",
+               (long long)w.n, (long long)w.nnz, (long long)w.ld, w.r, w.q);
 
-  int32_t* d_rp = to_device(w.row_ptr);
-  int32_t* d_col = to_device(w.col);
-  float* d_val = to_device(w.val);
-  if (!d_rp || !d_col || !d_val) return fail("device allocation or copy failed", 3);
+  int32_t* d_rp = nullptr;
+  int32_t* d_col = nullptr;
+  float* d_val = nullptr;
+  uint16_t* d_hi = nullptr;
+  uint16_t* d_lo = nullptr;
+  if (w.dense) {
+    d_hi = to_device(w.hi);
+    d_lo = to_device(w.lo);
+    if (!d_hi || !d_lo) return fail("device allocation or copy failed", 3);
+    std::vector<uint16_t>().swap(w.hi);
+    std::vector<uint16_t>().swap(w.lo);
+  } else {
+    d_rp = to_device(w.row_ptr);
+    d_col = to_device(w.col);
+    d_val = to_device(w.val);
+    if (!d_rp || !d_col || !d_val) return fail("device allocation or copy failed", 3);
+  }
   hipStream_t stream = nullptr;
   if (hipStreamCreate(&stream) != hipSuccess) return fail("hipStreamCreate failed", 3);
 
@@ -104,7 +132,7 @@ int main(int argc, char** argv) {
   p.n = w.n;
   p.r = w.r;
   p.oversample = 4;
-  p.prec = MEG_PREC_F32;
+  p.prec = w.dense ? MEG_PREC_F32_BF16X3 : MEG_PREC_F32;
   p.min_inner = 1;
   p.max_inner = max_inner;
   p.eta = 1.0;
@@ -114,11 +142,18 @@ int main(int argc, char** argv) {
   p.seed = 0;
   meg_objective o;
   std::memset(&o, 0, sizeof(o));
-  o.kind = MEG_GRAD_MASKED_CSR;
-  o.row_ptr = d_rp;
-  o.col = d_col;
-  o.val = d_val;
-  o.nnz = w.nnz;
+  if (w.dense) {
+    o.kind = MEG_GRAD_DENOISE_DENSE;
+    o.dense = d_hi;
+    o.dense_lo = d_lo;
+    o.ld = w.ld;
+  } else {
+    o.kind = MEG_GRAD_MASKED_CSR;
+    o.row_ptr = d_rp;
+    o.col = d_col;
+    o.val = d_val;
+    o.nnz = w.nnz;
+  }
   meg_start s;
   std::memset(&s, 0, sizeof(s));
   s.q = w.q;
@@ -151,19 +186,18 @@ int main(int argc, char** argv) {
   if ((st = meg_certificate(ctx, &info)) != MEG_OK) return fail(meg_status_str(st), 5);
   const double wall_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   std::printf(
-      "{\"workload\": \"matrix_completion_csr\", \"n\": %lld, \"nnz\": %lld, \"r\": %d, \"steps\": %lld, "
+      "{\"workload\": \"%s\", \"n\": %lld, \"nnz\": %lld, \"r\": %d, \"steps\": %lld, "
       "\"launch_steps\": %lld, \"launches\": %lld, \"iterations\": %lld, \"applies\": %lld, \"workgroups\": %d, "
       "\"kernel_ms\": %.6f, \"avg_launch_us\": %.3f, \"wall_ms_per_step\": %.6f, \"iter_per_s\": %.3f, "
       "\"t\": %lld, \"cert_L\": %.6e, \"eps_t\": %.6e}\n",
-      (long long)w.n, (long long)w.nnz, w.r, (long long)steps, (long long)launch, (long long)c.launches,
+      w.dense ? "denoise_bf16x3" : "matrix_completion_csr", (long long)w.n, (long long)w.nnz, w.r, (long long)steps, (long long)launch, (long long)c.launches,
       (long long)c.iterations, (long long)c.applies, c.workgroups, c.kernel_ms,
       c.launches ? 1e3 * c.kernel_ms / (double)c.launches : 0.0, wall_ms / (double)steps,
       1e3 * (double)steps / wall_ms, (long long)info.t, info.cert_L, info.eps_t);
   std::fflush(stdout);
   meg_destroy(ctx);
   (void)hipStreamDestroy(stream);
-  (void)hipFree(d_rp);
-  (void)hipFree(d_col);
-  (void)hipFree(d_val);
+  for (void* q : {(void*)d_rp, (void*)d_col, (void*)d_val, (void*)d_hi, (void*)d_lo})
+    if (q) (void)hipFree(q);
   return 0;
 }
