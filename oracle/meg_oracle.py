@@ -53,6 +53,8 @@ __all__ = [
     "factored_diff_frob",
     "factored_frob",
     "dual_gap",
+    "trace_exp_deflated",
+    "certificate_from_log_b",
 ]
 
 
@@ -459,6 +461,51 @@ def project_spectrahedron(A: np.ndarray, tau: float = 1.0) -> np.ndarray:
 def dual_gap(X: np.ndarray, G: np.ndarray, tau: float = 1.0) -> float:
     """max_{Z in tau-spectrahedron} <X - Z, G> = <X, G> - tau lambda_min(G) (Section 7)."""
     return float(np.sum(X * G)) - tau * float(np.linalg.eigvalsh(sym(G))[0])
+
+
+# ---------------------------------------------------------------------------
+# the full-trace certificate: b_n = tr exp(M_t) (Section 3.1.1)
+# ---------------------------------------------------------------------------
+def trace_exp_deflated(Mt: np.ndarray, Q: Optional[np.ndarray], probes: np.ndarray, weight: float) -> dict:
+    """Deflated randomised estimate of b_n = tr exp(M_t), the sum of all
+    eigenvalues of Y_t = exp(M_t) in the certificate of Section 3.1.1.
+
+    Section 3.1.1 notes (footnote) that b_n could instead be estimated from
+    E_u[u^T Y u] = tr Y over Gaussian u (Hutchinson's estimator), with the
+    products exp(M)u from Lanczos.  The estimate here splits the trace by an
+    orthonormal basis Q of a k-dimensional subspace: with P = I - Q Q^T,
+        tr A = tr(Q^T A Q) + tr(P A P)      (any orthonormal Q),
+    computes the first term and estimates the second by
+        weight * sum_j (P u_j)^T A (P u_j)
+    (the deflation used by Hutch++: Meyer, Musco, Musco, Woodruff, 2021).
+    It is exact for the n canonical basis vectors as probes with weight 1,
+    and unbiased for E[u u^T] = I with weight = 1/p.
+
+    Q: n x k, any full-column-rank basis (only its span matters), None or
+    k = 0 for no deflation; probes: n x p.  Returns b, b_defl = tr(Q^T A Q),
+    b_tail, the p terms (P u_j)^T A (P u_j), and the standard error of
+    b_tail, weight * sqrt(p) * (sample standard deviation of the terms)
+    (NaN for p < 2)."""
+    A = mat_exp(Mt)
+    n = A.shape[0]
+    U = np.asarray(probes, dtype=np.float64).reshape(n, -1)
+    if Q is None or np.asarray(Q).size == 0:
+        Qo = np.zeros((n, 0))
+    else:
+        Qo, _ = np.linalg.qr(np.asarray(Q, dtype=np.float64).reshape(n, -1))
+    b_defl = float(np.trace(Qo.T @ A @ Qo))
+    PU = U - Qo @ (Qo.T @ U)
+    terms = np.einsum("ij,ij->j", PU, A @ PU)
+    p = terms.size
+    b_tail = float(weight) * float(np.sum(terms))
+    se = float(weight) * math.sqrt(p) * float(np.std(terms, ddof=1)) if p >= 2 else float("nan")
+    return {"b": b_defl + b_tail, "b_defl": b_defl, "b_tail": b_tail, "terms": terms, "stderr": se}
+
+
+def certificate_from_log_b(mu_r1: float, log_b: float, r: int, eps: float, n: int) -> float:
+    """log((n - r) lambda_{r+1}(Y) / (eps b)) with lambda_{r+1}(Y) = exp(mu_{r+1})
+    and a given log b (Section 3.1.1): the certificate for an estimate of b_n."""
+    return math.log(n - r) + float(mu_r1) - math.log(eps) - float(log_b)
 
 
 # ---------------------------------------------------------------------------

@@ -482,3 +482,65 @@ def test_dual_gap_vanishes_at_the_projection_and_bounds_suboptimality():
         sub = obj.value(X) - obj.value(Xs)
         assert sub >= -1e-12
         assert gap >= sub - 1e-12 and gap > 0.0
+
+
+# ---------------------------------------------------------------------------
+# the full-trace certificate (Section 3.1.1): b_n = tr exp(M_t)
+# ---------------------------------------------------------------------------
+def test_trace_exp_canonical_probes_is_the_trace():
+    """With the n canonical basis vectors as probes and weight 1 the deflated
+    estimate is tr exp(M) for any deflation basis (even a non-orthonormal one):
+    checked against SciPy's Pade scaling-and-squaring exponential, which shares
+    no step with the oracle's eigendecomposition."""
+    rng = np.random.default_rng(31)
+    for n, k in [(12, 0), (20, 3), (33, 8)]:
+        M = rand_sym(n, rng, scale=2.0) - 5.0 * np.eye(n)
+        Q = rng.standard_normal((n, k))
+        est = O.trace_exp_deflated(M, Q, np.eye(n), 1.0)
+        exact = float(np.trace(sla.expm(M)))
+        assert est["b"] == pytest.approx(exact, rel=1e-12)
+        # the certificate from the exact log b is the all-eigenvalue one
+        mu = np.sort(np.linalg.eigvalsh(M))[::-1]
+        r, eps = 2, 0.01
+        assert O.certificate_from_log_b(mu[r], math.log(exact), r, eps, n) == pytest.approx(
+            O.certificate(mu, r, eps, n, n), abs=1e-10)
+
+
+def test_trace_exp_diagonal_closed_form():
+    """M diagonal and Q the first k canonical vectors: tr(Q^T e^M Q) is the sum
+    of the first k e^{m_i}, and each probe term is sum_{i >= k} u_i^2 e^{m_i}."""
+    rng = np.random.default_rng(32)
+    n, k, p = 15, 4, 6
+    m = rng.uniform(-6.0, 1.0, n)
+    U = rng.standard_normal((n, p))
+    est = O.trace_exp_deflated(np.diag(m), np.eye(n)[:, :k], U, 0.5)
+    assert est["b_defl"] == pytest.approx(sum(math.exp(m[i]) for i in range(k)), rel=1e-13)
+    for j in range(p):
+        want = sum(U[i, j] ** 2 * math.exp(m[i]) for i in range(k, n))
+        assert est["terms"][j] == pytest.approx(want, rel=1e-12)
+    assert est["b_tail"] == pytest.approx(0.5 * sum(est["terms"]), rel=1e-13)
+
+
+def test_trace_exp_gaussian_probes_are_unbiased_and_deflation_cuts_the_error():
+    """Gaussian probes with weight 1/p: the error is within 5 standard errors
+    of Hutchinson's variance 2 ||A||_F^2 / p (A = P e^M P), and the reported
+    standard error matches that variance; deflating by the top eigenvectors
+    shrinks the error on a spectrum dominated by a few eigenvalues."""
+    rng = np.random.default_rng(33)
+    n, p = 40, 4000
+    w = np.concatenate([[0.0, -0.3, -0.5, -0.9], rng.uniform(-8.0, -4.0, n - 4)])
+    U0, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    M = (U0 * w) @ U0.T
+    exact = float(np.sum(np.exp(w)))
+    G = rng.standard_normal((n, p))
+    for k in (0, 4):
+        Q = U0[:, :k]
+        est = O.trace_exp_deflated(M, Q, G, 1.0 / p)
+        Pm = np.eye(n) - Q @ Q.T
+        A = Pm @ sla.expm(M) @ Pm
+        sd = math.sqrt(2.0 * float(np.sum(A * A)) / p)
+        assert abs(est["b"] - exact) <= 5.0 * sd
+        assert 0.8 * sd <= est["stderr"] <= 1.25 * sd
+        if k == 0:
+            sd0 = sd
+    assert sd < 0.1 * sd0
