@@ -44,7 +44,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # valid only for the kernel sources it was measured on.
 TRAFFIC = {"bytes_per_launch": 943.0e6, "iterations_per_launch": 64, "applies_per_iteration": 3.0,
            "fetch_bytes": 546.5e6, "write_bytes": 396.5e6, "fetch_factor": 2.0, "write_factor": 1.0,
-           "source_hash": "69a9411020596799"}
+           "source_hash": "80854b3fc381ebf6"}
 KERNEL_SOURCES = ["meg_device.hpp", "meg_small.hpp", "meg_kernels.hpp", "meg_api.hip"]
 
 
@@ -412,6 +412,22 @@ def main() -> int:
     log(f"[bench] dual gap at t={dg['t']}: {dg['gap']:.4e} (<X,G> {dg['x_dot_g']:.4e}, lambda_min {dg['lambda_min']:.4e}, "
         f"{dg['steps']} Lanczos steps, {dg['ms']:.1f} ms)")
 
+    # the all-eigenvalue certificate of the next step (Section 3.1.1): b_n = tr exp(M_t) from the
+    # solver block plus 48 Gaussian probes (one 64-vector Lanczos batch), then that step's L_full
+    # next to its cheap b^{r+1} certificate; not timed with the steps
+    U = torch.from_numpy(np.random.default_rng([17, p.n]).standard_normal((p.n, 48))).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tri, tr = g.trace_exp(U, max_steps=64, tol=1e-8)
+    tri["ms"] = (time.perf_counter() - t0) * 1e3
+    st = g.step()
+    L_full, holds = g.certificate_full(tr)
+    tri.update({"probes": 48, "cert_L_full": L_full, "cert_holds_full": holds, "cert_L": st["cert_L"],
+                "eps_t": st["eps_t"]})
+    log(f"[bench] trace of exp(M_t) at t={tri['t']}: log b_n {tri['log_b']:.6f} (block {tri['log_b_defl']:.6f}, "
+        f"probes {tri['log_b_tail']:.4f}, rel. std. error {tri['tail_rel_stderr']:.2e}), {tri['steps']} Lanczos "
+        f"steps, {tri['ms']:.1f} ms; certificate L_full {L_full:.4f} vs L {st['cert_L']:.4f} (2 eps {2 * st['eps_t']:.2e})")
+
     base = None
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline: {args.cpu_samples} iterations")
@@ -450,6 +466,7 @@ def main() -> int:
                      "jacobi_sweeps_per_iteration": cnt["jacobi_sweeps"] / cnt["iterations"],
                      "launches": launches, "phases": phases},
         "dual_gap": dg,
+        "trace_exp": tri,
         "cpu_baseline": base,
         "serving": serving,
     }

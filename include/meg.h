@@ -314,6 +314,69 @@ meg_status meg_dual_gap(meg_ctx ctx, int32_t max_steps, double tol, meg_dual_gap
 meg_status meg_solve_to_gap(meg_ctx ctx, int64_t max_iters, double tol, int32_t check_every, meg_step_info* last,
                             meg_dual_gap_info* gap);
 
+/* The sum b_n = tr exp(M_t) of all eigenvalues of Y_t = exp(M_t), for the
+ * all-eigenvalue form of the certificate (Section 3.1.1: the approximation-
+ * error lemma's condition uses b_n; the cheap certificate of meg_step uses
+ * b^{r+1} <= b_n instead), following the randomised route the section
+ * mentions: quadratic forms u^T exp(M_t) u from Lanczos runs, averaged over
+ * probe vectors.  M_t = log X_t - eta grad f(X_t) at the CURRENT iterate X_t,
+ * i.e. the matrix the next meg_step decomposes.
+ *
+ * The estimate splits the trace by the context's k-column solver block Q
+ * (orthonormalised in FP64): with P = I - Q Q^T,
+ *   b_n = tr(Q^T exp(M_t) Q) + tr(P exp(M_t) P)    (exact for any orthonormal Q);
+ * the first term is computed, the second estimated as
+ *   weight * sum_j (P u_j)^T exp(M_t) (P u_j)
+ * over the caller's probes u_j (the deflation of Hutch++, Meyer et al.,
+ * 2021).  weight = 1/p with Gaussian or Rademacher probes gives an unbiased
+ * estimate; the n canonical basis vectors with weight = 1 give b_n itself.
+ * Each quadratic form v^T exp(M_t) v is ||v||^2 e_1^T exp(T) e_1 for the
+ * tridiagonal T of a Lanczos run from v (Gauss quadrature, with the plain
+ * three-term recurrence: Lanczos for matrix functions is stable without
+ * reorthogonalisation, Musco, Musco and Sidford, 2018): the runs
+ * advance 64 vectors at a time in lockstep on the device (FP64 vectors, the
+ * operator's data in the state's type), and stop when every estimate has
+ * changed by at most tol (relative) over the last 8 steps, or after
+ * max_steps steps; the host evaluates e_1^T exp(T) e_1 from T's eigenvalues
+ * and first eigenvector components.
+ *
+ * probes: DEVICE, n x p column-major FP64 (probe j at probes + j * n), read
+ * during the call only; p >= 0 (p = 0: the deflated term alone, a lower
+ * bound of b_n).  weight > 0.  Objectives as meg_dual_gap (linear,
+ * denoising, also with bf16 planes, and masked; the call overwrites the
+ * masked kind's stored gradient values, which the next step recomputes);
+ * MEG_ERR_UNSUPPORTED for the minibatch and external kinds;
+ * MEG_ERR_INVALID_ARG for p < 0, p > 0 with probes == NULL, weight <= 0,
+ * max_steps < 1, tol < 0 or out == NULL.  Allocates five blocks of 64 x n
+ * doubles (and 2 x 64 x max_steps) for the call.  Synchronises; HOST output. */
+typedef struct {
+  double log_b;           /* log of the estimate of b_n = tr exp(M_t)          */
+  double log_b_defl;      /* log tr(Q^T exp(M_t) Q)                             */
+  double log_b_tail;      /* log of the probe estimate of tr(P exp(M_t) P);
+                             -inf for p = 0 or when every P u_j is zero        */
+  double tail_rel_stderr; /* standard error of the probe estimate (weight *
+                             sqrt(p) * sample std of the p terms) divided by
+                             the estimate of b_n; NaN for p < 2                */
+  int64_t t;              /* index of the iterate                               */
+  int32_t kd;             /* deflation columns kept (rank of the block)         */
+  int32_t steps;          /* Lanczos steps of the longest run                   */
+  int32_t converged;      /* every quadrature met tol                           */
+  int32_t batches;        /* lockstep batches of up to 64 vectors               */
+} meg_trace_info;
+
+meg_status meg_trace_exp(meg_ctx ctx, const double* probes, int32_t p, double weight, int32_t max_steps, double tol,
+                         meg_trace_info* out);
+
+/* The certificate with an estimate of b_n in place of b^{r+1} (Section 3.1.1):
+ *   L_full = log((n - r) lambda_{r+1}(Y_t) / (eps_t b_n))
+ *          = log(n - r) + mu_{r+1} - log eps_t - log_b,
+ * from the most recent step's mu_{r+1} and eps_t and tr->log_b, which must be
+ * the estimate for that step's M_t (meg_trace_exp called at the iterate the
+ * step started from: tr->t equals the step's t).  *holds = L_full <= 2 eps_t.
+ * MEG_ERR_INVALID_ARG when no step has run since, when tr->t differs, or for
+ * NULL pointers.  No kernel runs. */
+meg_status meg_certificate_full(meg_ctx ctx, const meg_trace_info* tr, double* cert_L_full, int32_t* holds);
+
 void meg_destroy(meg_ctx ctx);
 const char* meg_status_str(meg_status s);
 

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <vector>
 
@@ -627,6 +628,346 @@ meg_status lanczos_grad_min(meg_ctx c, int max_steps, double tol, meg_dual_gap_i
   out->resid = res;
   out->steps = done;
   out->converged = conv ? 1 : 0;
+  return MEG_OK;
+}
+
+// Eigenvalues of the symmetric tridiagonal T (diagonal a[0..m), off-diagonal
+// b[0..m-1)) and the first components z of its unit eigenvectors, by implicit
+// QR steps with Wilkinson's shift on the trailing unreduced block (Golub and
+// Van Loan, Matrix Computations, Section 8.3), accumulating only the first
+// column of the rotation product.  These are the nodes and weights z_i^2 of
+// the Gauss quadrature of the Lanczos run (Golub and Welsch).  a and b are
+// destroyed; a returns the eigenvalues.
+void tridiag_eig_first(std::vector<double>& a, std::vector<double>& b, std::vector<double>& z) {
+  const int m = (int)a.size();
+  z.assign(m, 0.0);
+  if (m == 0) return;
+  z[0] = 1.0;
+  double tnorm = 0.0;
+  for (int i = 0; i < m; ++i)
+    tnorm = std::max(tnorm, std::fabs(a[i]) + (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0));
+  auto negligible = [&](int i) {
+    return std::fabs(b[i]) <= 2.3e-16 * (std::fabs(a[i]) + std::fabs(a[i + 1])) || std::fabs(b[i]) <= 1e-18 * tnorm;
+  };
+  int hi = m - 1, iters = 0;
+  while (hi > 0 && iters < 60 * m) {
+    if (negligible(hi - 1)) {
+      b[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && !negligible(lo - 1)) --lo;
+    if (lo > 0) b[lo - 1] = 0.0;
+    ++iters;
+    // shift: the eigenvalue of the trailing 2 x 2 block nearer to a[hi]
+    const double d = 0.5 * (a[hi - 1] - a[hi]), e = b[hi - 1];
+    const double mu = a[hi] - e * (e / (d + std::copysign(std::hypot(d, e), d)));
+    // one QR step on rows lo..hi: rotation k acts on rows/columns k, k + 1,
+    // zeroing the bulge (k + 1, k - 1) the previous rotation left
+    double x = a[lo] - mu, y = b[lo];
+    for (int k = lo; k < hi; ++k) {
+      const double rr = std::hypot(x, y);
+      const double c = rr > 0.0 ? x / rr : 1.0, s = rr > 0.0 ? y / rr : 0.0;
+      if (k > lo) b[k - 1] = rr;
+      const double ak = a[k], ak1 = a[k + 1], bk = b[k];
+      a[k] = c * c * ak + 2.0 * c * s * bk + s * s * ak1;
+      a[k + 1] = s * s * ak - 2.0 * c * s * bk + c * c * ak1;
+      b[k] = c * s * (ak1 - ak) + (c * c - s * s) * bk;
+      const double zk = z[k], zk1 = z[k + 1];
+      z[k] = c * zk + s * zk1;
+      z[k + 1] = c * zk1 - s * zk;
+      if (k + 1 < hi) {
+        x = b[k];
+        y = s * b[k + 1];
+        b[k + 1] *= c;
+      }
+    }
+  }
+}
+
+// log(e_1^T exp(T) e_1) = log sum_i z_i^2 exp(theta_i) for the tridiagonal T
+// with diagonal a and off-diagonal b (copies)
+double log_quad_exp(std::vector<double> a, std::vector<double> b) {
+  std::vector<double> z;
+  tridiag_eig_first(a, b, z);
+  double mx = -std::numeric_limits<double>::infinity();
+  for (size_t i = 0; i < a.size(); ++i)
+    if (z[i] != 0.0) mx = std::max(mx, a[i] + 2.0 * std::log(std::fabs(z[i])));
+  if (!std::isfinite(mx)) return mx;
+  double s = 0.0;
+  for (size_t i = 0; i < a.size(); ++i)
+    if (z[i] != 0.0) s += std::exp(a[i] + 2.0 * std::log(std::fabs(z[i])) - mx);
+  return mx + std::log(s);
+}
+
+double log_sum_exp(const std::vector<double>& v) {
+  double mx = -std::numeric_limits<double>::infinity();
+  for (double x : v) mx = std::max(mx, x);
+  if (!std::isfinite(mx)) return mx;
+  double s = 0.0;
+  for (double x : v) s += std::exp(x - mx);
+  return mx + std::log(s);
+}
+
+// Cholesky G = R^T R of the kq x kq Gram matrix G[l * 64 + b] with columns
+// whose remaining pivot is <= 1e-12 of the largest diagonal dropped (their row
+// and column of R^{-1} are zero); Rinv (64 x 64, row-major) = R^{-1}.
+// Returns the number of columns kept.
+int chol_inv_drop(const std::vector<double>& G, int kq, std::vector<double>& Rinv) {
+  std::vector<double> R((size_t)kq * kq, 0.0);
+  std::vector<char> keep(kq, 0);
+  double dmax = 0.0;
+  for (int j = 0; j < kq; ++j) dmax = std::max(dmax, G[(size_t)j * kTrW + j]);
+  int kept = 0;
+  for (int j = 0; j < kq; ++j) {
+    double dj = G[(size_t)j * kTrW + j];
+    for (int l = 0; l < j; ++l)
+      if (keep[l]) dj -= R[(size_t)l * kq + j] * R[(size_t)l * kq + j];
+    if (!(dj > 1e-12 * dmax)) continue;
+    keep[j] = 1;
+    ++kept;
+    const double rjj = std::sqrt(dj);
+    R[(size_t)j * kq + j] = rjj;
+    for (int c = j + 1; c < kq; ++c) {
+      double v = G[(size_t)j * kTrW + c];
+      for (int l = 0; l < j; ++l)
+        if (keep[l]) v -= R[(size_t)l * kq + j] * R[(size_t)l * kq + c];
+      R[(size_t)j * kq + c] = v / rjj;
+    }
+  }
+  // R X = I on the kept indices, by back substitution per column
+  Rinv.assign((size_t)kTrW * kTrW, 0.0);
+  for (int c = 0; c < kq; ++c) {
+    if (!keep[c]) continue;
+    for (int i = c; i >= 0; --i) {
+      if (!keep[i]) continue;
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int l = i + 1; l <= c; ++l)
+        if (keep[l]) s -= R[(size_t)i * kq + l] * Rinv[(size_t)l * kTrW + c];
+      Rinv[(size_t)i * kTrW + c] = s / R[(size_t)i * kq + i];
+    }
+  }
+  return kept;
+}
+
+// out[l * 64 + b] = sum_i A[i * lda + l] X[i][b] (l < na) and out[b] =
+// sum_i A[i][b] B[i][b]: partial sums over G workgroups, then their sum in order
+template <typename TA>
+void tr_gram(hipStream_t sm, const TA* A, int64_t lda, int na, const double* X, int64_t n, int G, double* part,
+             double* out) {
+  hipLaunchKernelGGL((k_tr_gram_part<TA>), dim3(G), dim3(256), 0, sm, A, lda, na, X, n, part);
+  hipLaunchKernelGGL(k_tr_part_sum, dim3(ceil_div(na * kTrW, 4)), dim3(256), 0, sm, (const double*)part, G,
+                     na * kTrW, out);
+}
+void tr_cdot(hipStream_t sm, const double* A, const double* B, int64_t n, int G, double* part, double* out) {
+  hipLaunchKernelGGL(k_tr_cdot_part, dim3(G), dim3(256), 0, sm, A, B, n, part);
+  hipLaunchKernelGGL(k_tr_part_sum, dim3(kTrW / 4), dim3(256), 0, sm, (const double*)part, G, kTrW, out);
+}
+
+// The deflated probe estimate of tr exp(M_t) (see meg_trace_exp).  Up to 64
+// vectors per lockstep Lanczos batch: batch 0 holds the orthonormalised block
+// columns and the first probes, later batches 64 probes each.
+template <typename T>
+meg_status trace_exp_run(meg_ctx c, const double* probes, int p, double weight, int max_steps, double tol,
+                         meg_trace_info* out) {
+  const Cfg& cfg = c->cfg;
+  const int64_t n = cfg.n;
+  const int r = cfg.r, KB = cfg.k;
+  const int kq = (int)std::min<int64_t>(KB, n);
+  const int m = (int)std::min<int64_t>(max_steps, n);
+  const bool den = cfg.kind == DENOISE_DENSE, masked = cfg.kind == MASKED_CSR;
+  const bool csr = masked || cfg.kind == LINEAR_CSR;
+  const T* Qm = (const T*)block(c, (c->h_ctl->src + 1) % 3);  // materialised basis (xdotg)
+  // M_t x = s Op x + c0 x + V diag(cv) V^T x: log X_t = log(alpha) I +
+  // V diag(log(alpha + d) - log alpha) V^T, and -eta G with G = C (linear),
+  // X_t - M (denoising) or the gradient values on the pattern (masked)
+  const Ctl& h = *c->h_ctl;
+  const double la = std::log(h.alpha);
+  double c0 = la, sop = -cfg.eta;
+  std::vector<double> cv(KMAX, 0.0);
+  for (int l = 0; l < r; ++l) cv[l] = std::log(h.alpha + h.d[l]) - la;
+  if (den) {
+    c0 = la - cfg.eta * h.alpha;
+    sop = cfg.eta;
+    for (int l = 0; l < r; ++l) cv[l] -= cfg.eta * h.d[l];
+  }
+  const size_t vbytes = (size_t)n * kTrW * 8;
+  double *Qd = nullptr, *B0 = nullptr, *B1 = nullptr, *B2 = nullptr, *Y = nullptr, *al = nullptr, *bb = nullptr;
+  double *P = nullptr, *Mx = nullptr, *dcv = nullptr, *sm1 = nullptr, *sm2 = nullptr, *part = nullptr;
+  const int GR = (int)std::min<int64_t>(kTrRedWG, ceil_div(n, 4));
+  auto alloc = [&](double** q, size_t bytes) { return hipMalloc((void**)q, std::max<size_t>(bytes, 256)) == hipSuccess; };
+  bool ok = alloc(&Qd, vbytes) && alloc(&B0, vbytes) && alloc(&B1, vbytes) && alloc(&B2, vbytes) &&
+            alloc(&Y, vbytes) && alloc(&al, (size_t)m * kTrW * 8) && alloc(&bb, (size_t)m * kTrW * 8) &&
+            alloc(&P, (size_t)kTrW * kTrW * 8) && alloc(&Mx, (size_t)kTrW * kTrW * 8) && alloc(&dcv, KMAX * 8) &&
+            alloc(&sm1, kTrW * 8) && alloc(&sm2, kTrW * 8) && alloc(&part, (size_t)GR * 32 * kTrW * 8);
+  auto release = [&]() {
+    for (double* q : {Qd, B0, B1, B2, Y, al, bb, P, Mx, dcv, sm1, sm2, part})
+      if (q) (void)hipFree(q);
+  };
+  if (!ok) {
+    (void)hipGetLastError();
+    release();
+    return MEG_ERR_OUT_OF_MEMORY;
+  }
+  const hipStream_t sm = c->stream;
+  const int ge = (int)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n * kTrW, 256)));
+  const int gw = ceil_div(n, 4);
+  meg_status st = MEG_OK;
+  auto fail = [&]() {
+    st = hip_fail(c);
+    release();
+    return st;
+  };
+  if (hipMemcpyAsync(dcv, cv.data(), KMAX * 8, hipMemcpyHostToDevice, sm) != hipSuccess) return fail();
+  // orthonormal FP64 deflation basis: the block's kq columns, Cholesky QR twice
+  hipLaunchKernelGGL((k_tr_load<T>), dim3(ge), dim3(256), 0, sm, Qm, KB, (const double*)nullptr, kq,
+                     (const double*)nullptr, 0, n, Qd);
+  int kd = kq;
+  std::vector<double> Gh((size_t)kTrW * kTrW), Rinv;
+  for (int pass = 0; pass < 2 && kq > 0; ++pass) {
+    tr_gram<double>(sm, Qd, kTrW, kq, Qd, n, GR, part, P);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(Gh.data(), P, (size_t)kq * kTrW * 8, hipMemcpyDeviceToHost, sm) != hipSuccess ||
+        hipStreamSynchronize(sm) != hipSuccess)
+      return fail();
+    kd = chol_inv_drop(Gh, kq, Rinv);
+    if (hipMemcpyAsync(Mx, Rinv.data(), (size_t)kTrW * kTrW * 8, hipMemcpyHostToDevice, sm) != hipSuccess)
+      return fail();
+    hipLaunchKernelGGL(k_tr_rowmix, dim3(gw), dim3(256), 0, sm, (const double*)Qd, (const double*)Mx, kq, 0, kq, 0,
+                       n, Qd);
+  }
+  std::vector<double> defl, tail(p, -std::numeric_limits<double>::infinity());
+  std::vector<double> abh((size_t)m * kTrW), bbh((size_t)m * kTrW), nsq(kTrW), nsq0(kTrW), sc(kTrW);
+  bool all_conv = true;
+  int max_done = 0, batches = 0;
+  int next_probe = 0;
+  for (int batch = 0; batch == 0 || next_probe < p; ++batch) {
+    const int nq = batch == 0 ? kq : 0;
+    const int np_b = std::min(p - next_probe, kTrW - nq);
+    ++batches;
+    // start vectors: block columns, then the probes projected by I - Qd Qd^T
+    // (two passes), then normalised
+    hipLaunchKernelGGL((k_tr_load<T>), dim3(ge), dim3(256), 0, sm, (const T*)nullptr, KB, (const double*)Qd, nq,
+                       np_b > 0 ? probes + (int64_t)next_probe * n : (const double*)nullptr, np_b, n, B0);
+    tr_cdot(sm, B0, B0, n, GR, part, sm2);
+    for (int pass = 0; pass < 2 && kq > 0 && np_b > 0; ++pass) {
+      tr_gram<double>(sm, Qd, kTrW, kq, B0, n, GR, part, P);
+      hipLaunchKernelGGL(k_tr_rowmix, dim3(gw), dim3(256), 0, sm, (const double*)Qd, (const double*)P, kq, nq,
+                         nq + np_b, 1, n, B0);
+    }
+    tr_cdot(sm, B0, B0, n, GR, part, sm1);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(nsq0.data(), sm2, kTrW * 8, hipMemcpyDeviceToHost, sm) != hipSuccess ||
+        hipMemcpyAsync(nsq.data(), sm1, kTrW * 8, hipMemcpyDeviceToHost, sm) != hipSuccess ||
+        hipStreamSynchronize(sm) != hipSuccess)
+      return fail();
+    // a probe the projection reduced to rounding error lies in span(Q): zero
+    for (int b = 0; b < kTrW; ++b) {
+      if (!(nsq[b] > 1e-26 * nsq0[b]) || !(nsq[b] > 1e-300)) nsq[b] = 0.0;
+      sc[b] = nsq[b] > 0.0 ? 1.0 / std::sqrt(nsq[b]) : 0.0;
+    }
+    if (hipMemcpyAsync(sm2, sc.data(), kTrW * 8, hipMemcpyHostToDevice, sm) != hipSuccess) return fail();
+    hipLaunchKernelGGL(k_tr_scale, dim3(ge), dim3(256), 0, sm, (const double*)sm2, n, B0);
+    // lockstep Lanczos: Xc the current vectors, Xp the previous ones
+    double *Xp = B2, *Xc = B0, *Wn = B1;
+    std::vector<double> lq(kTrW, -std::numeric_limits<double>::infinity()), lq_prev(kTrW);
+    std::vector<char> conv(kTrW, 0);
+    bool batch_conv = false;
+    int done = 0;
+    for (int j = 0; j < m; ++j) {
+      if (csr)
+        hipLaunchKernelGGL((k_tr_matvec_csr<T>), dim3(gw), dim3(256), 0, sm, n, c->obj.row_ptr, c->obj.col,
+                           masked ? (const T*)c->g : (const T*)c->obj.val, (const double*)Xc, Y);
+      else
+        hipLaunchKernelGGL((k_tr_matvec_dense<T>), dim3(ceil_div(n, 32)), dim3(256), 0, sm, n, (int64_t)cfg.ld,
+                           Launch<T, 16>::dense_src(c), (const double*)Xc, Y);
+      if (r > 0)
+        tr_gram<T>(sm, Qm, KB, r, Xc, n, GR, part, P);
+      hipLaunchKernelGGL((k_tr_opfix<T>), dim3(ge), dim3(256), 0, sm, Qm, KB, r, (const double*)dcv,
+                         (const double*)P, sop, c0, (const double*)Xc, n, Y);
+      double* alj = al + (size_t)j * kTrW;
+      const double* bprev = j > 0 ? bb + (size_t)(j - 1) * kTrW : nullptr;
+      tr_cdot(sm, Xc, Y, n, GR, part, alj);
+      hipLaunchKernelGGL(k_tr_three, dim3(ge), dim3(256), 0, sm, (const double*)Y, (const double*)Xc,
+                         (const double*)Xp, (const double*)alj, bprev, n, Wn);
+      tr_cdot(sm, Wn, Wn, n, GR, part, sm1);
+      hipLaunchKernelGGL(k_tr_next, dim3(ge), dim3(256), 0, sm, (const double*)sm1, (const double*)alj, bprev, n,
+                         bb + (size_t)j * kTrW, Wn);
+      if (hipGetLastError() != hipSuccess) return fail();
+      double* old = Xp;
+      Xp = Xc;
+      Xc = Wn;
+      Wn = old;
+      done = j + 1;
+      if (done % 8 != 0 && done != m) continue;
+      if (hipMemcpyAsync(abh.data(), al, (size_t)done * kTrW * 8, hipMemcpyDeviceToHost, sm) != hipSuccess ||
+          hipMemcpyAsync(bbh.data(), bb, (size_t)done * kTrW * 8, hipMemcpyDeviceToHost, sm) != hipSuccess ||
+          hipStreamSynchronize(sm) != hipSuccess)
+        return fail();
+      batch_conv = true;
+      for (int b = 0; b < nq + np_b; ++b) {
+        if (!(nsq[b] > 0.0)) {
+          conv[b] = 1;
+          continue;
+        }
+        // T of vector b, truncated at its first vanishing beta (invariant space)
+        int len = done;
+        bool invariant = false;
+        for (int q = 0; q < done; ++q)
+          if (bbh[(size_t)q * kTrW + b] == 0.0) {
+            len = q + 1;
+            invariant = true;
+            break;
+          }
+        std::vector<double> ta(len), tb(std::max(len - 1, 0));
+        for (int q = 0; q < len; ++q) ta[q] = abh[(size_t)q * kTrW + b];
+        for (int q = 0; q + 1 < len; ++q) tb[q] = bbh[(size_t)q * kTrW + b];
+        lq_prev[b] = lq[b];
+        lq[b] = std::log(nsq[b]) + log_quad_exp(ta, tb);
+        // n steps span the whole space: the quadrature is then exact
+        conv[b] = invariant || done >= n || (std::isfinite(lq_prev[b]) && std::fabs(lq[b] - lq_prev[b]) <= tol);
+        batch_conv = batch_conv && conv[b];
+      }
+      if (batch_conv) break;
+    }
+    all_conv = all_conv && batch_conv;
+    max_done = std::max(max_done, done);
+    for (int b = 0; b < nq; ++b)
+      if (nsq[b] > 0.0) defl.push_back(lq[b]);
+    for (int b = nq; b < nq + np_b; ++b)
+      tail[next_probe + b - nq] = nsq[b] > 0.0 ? lq[b] : -std::numeric_limits<double>::infinity();
+    next_probe += np_b;
+  }
+  release();
+  const double ninf = -std::numeric_limits<double>::infinity();
+  const double lb_defl = defl.empty() ? ninf : log_sum_exp(defl);
+  const double lb_tail = p > 0 ? std::log(weight) + log_sum_exp(tail) : ninf;
+  const double lb = log_sum_exp({lb_defl, lb_tail});
+  double rel_se = std::numeric_limits<double>::quiet_NaN();
+  if (p >= 2) {
+    double S = ninf;
+    for (double v : tail) S = std::max(S, v);
+    if (std::isfinite(S)) {
+      double mean = 0.0;
+      for (double v : tail) mean += std::exp(v - S);
+      mean /= p;
+      double var = 0.0;
+      for (double v : tail) var += (std::exp(v - S) - mean) * (std::exp(v - S) - mean);
+      var /= (p - 1);
+      rel_se = var > 0.0 ? std::exp(std::log(weight) + 0.5 * std::log((double)p) + S + 0.5 * std::log(var) - lb) : 0.0;
+    } else {
+      rel_se = 0.0;
+    }
+  }
+  out->log_b = lb;
+  out->log_b_defl = lb_defl;
+  out->log_b_tail = lb_tail;
+  out->tail_rel_stderr = rel_se;
+  out->kd = kd;
+  out->steps = max_done;
+  out->converged = all_conv ? 1 : 0;
+  out->batches = batches;
   return MEG_OK;
 }
 
@@ -1347,6 +1688,39 @@ meg_status meg_dual_gap(meg_ctx c, int32_t max_steps, double tol, meg_dual_gap_i
   out->x_dot_g = xg;
   out->gap = xg - out->lambda_min;
   out->t = c->h_ctl->t;
+  return MEG_OK;
+}
+
+meg_status meg_trace_exp(meg_ctx c, const double* probes, int32_t p, double weight, int32_t max_steps, double tol,
+                         meg_trace_info* out) {
+  meg_status st = check_ctx(c);
+  if (st != MEG_OK) return st;
+  if (!out || p < 0 || (p > 0 && !probes) || !(weight > 0.0) || max_steps < 1 || !(tol >= 0.0))
+    return MEG_ERR_INVALID_ARG;
+  if (c->external || c->cfg.kind == QUADMEAS) return MEG_ERR_UNSUPPORTED;
+  std::memset(out, 0, sizeof(*out));
+  HIPCHK(c, dispatch<DoXdotG>(c));  // materialises the basis; masked: the gradient values
+  st = copy_ctl_to_host(c);
+  if (st != MEG_OK) return st;
+  st = (c->esize == 8) ? trace_exp_run<double>(c, probes, p, weight, max_steps, tol, out)
+                       : trace_exp_run<float>(c, probes, p, weight, max_steps, tol, out);
+  if (st != MEG_OK) return st;
+  out->t = c->h_ctl->t;
+  return MEG_OK;
+}
+
+meg_status meg_certificate_full(meg_ctx c, const meg_trace_info* tr, double* cert_L_full, int32_t* holds) {
+  meg_status st = check_ctx(c);
+  if (st != MEG_OK) return st;
+  if (!tr || !cert_L_full || !holds) return MEG_ERR_INVALID_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  st = copy_ctl_to_host(c);
+  if (st != MEG_OK) return st;
+  const Info& in = c->h_ctl->info;
+  if (in.t != tr->t || !(in.eps_t > 0.0)) return MEG_ERR_INVALID_ARG;
+  const double L = std::log((double)(c->cfg.n - c->cfg.r)) + in.mu_r1 - std::log(in.eps_t) - tr->log_b;
+  *cert_L_full = L;
+  *holds = (L <= 2.0 * in.eps_t) ? 1 : 0;
   return MEG_OK;
 }
 

@@ -5,7 +5,10 @@
 // the C ABI only, without Python: warmup iterations, then a timed run of
 // meg_solve launches, then one JSON line with the library's step-kernel
 // counters (launches, iterations, operator applies, HIP-event GPU time) and
-// the host wall clock.  The workload files are written by `bench.py
+// the host wall clock.  `--trace P` then estimates tr exp(M_t) at the final
+// iterate (meg_trace_exp, the solver block plus P seeded Gaussian probes,
+// weight 1/P) `--trace-reps` times and adds the last call's estimate and
+// the mean wall time per call.  The workload files are written by `bench.py
 // --write-workload PATH` / `--write-dense-workload PATH` from the seeded
 // generators the benchmark and the tests use.
 //
@@ -17,9 +20,11 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -88,9 +93,11 @@ int fail(const char* what, int code) {
 }  // namespace
 
 int main(int argc, char** argv) {
-  if (argc < 2) return fail("usage: meg_bench WORKLOAD [--steps K] [--warmup W] [--launch-steps L] [--max-inner M]", 2);
+  if (argc < 2)
+    return fail("usage: meg_bench WORKLOAD [--steps K] [--warmup W] [--launch-steps L] [--max-inner M] [--trace P] "
+                "[--trace-reps R]", 2);
   int64_t steps = 512, warmup = 64, launch = 64;
-  int max_inner = 12;
+  int max_inner = 12, trace_p = -1, trace_reps = 3;
   for (int i = 2; i + 1 < argc; i += 2) {
     const std::string a = argv[i];
     const long long v = std::atoll(argv[i + 1]);
@@ -98,9 +105,12 @@ int main(int argc, char** argv) {
     else if (a == "--warmup") warmup = v;
     else if (a == "--launch-steps") launch = v;
     else if (a == "--max-inner") max_inner = (int)v;
+    else if (a == "--trace") trace_p = (int)v;
+    else if (a == "--trace-reps") trace_reps = (int)v;
     else return fail("unknown option", 2);
   }
-  if (steps < 1 || warmup < 0 || launch < 1 || max_inner < 1 || max_inner > 64) return fail("bad option value", 2);
+  if (steps < 1 || warmup < 0 || launch < 1 || max_inner < 1 || max_inner > 64 || trace_p > 4096 || trace_reps < 1)
+    return fail("bad option value", 2);
 
   Workload w;
   if (!load(argv[1], w)) return fail("cannot read workload file", 2);
@@ -185,15 +195,40 @@ int main(int argc, char** argv) {
   meg_step_info info;
   if ((st = meg_certificate(ctx, &info)) != MEG_OK) return fail(meg_status_str(st), 5);
   const double wall_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  meg_trace_info tr;
+  std::memset(&tr, 0, sizeof(tr));
+  double trace_ms = 0.0;
+  if (trace_p >= 0) {
+    std::vector<double> U((size_t)w.n * std::max(trace_p, 1));
+    std::mt19937_64 gen(17);
+    std::normal_distribution<double> nd;
+    for (double& u : U) u = nd(gen);
+    double* d_u = nullptr;
+    if (hipMalloc((void**)&d_u, U.size() * 8) != hipSuccess ||
+        hipMemcpy(d_u, U.data(), U.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return fail("probe upload failed", 6);
+    std::fprintf(stderr, "[meg_bench] trace estimate: %d probes, %d calls\n", trace_p, trace_reps);
+    for (int rep = 0; rep < trace_reps; ++rep) {
+      const auto a0 = std::chrono::steady_clock::now();
+      st = meg_trace_exp(ctx, d_u, trace_p, trace_p > 0 ? 1.0 / trace_p : 1.0, 64, 1e-8, &tr);
+      const auto a1 = std::chrono::steady_clock::now();
+      if (st != MEG_OK) return fail(meg_status_str(st), 6);
+      if (rep > 0 || trace_reps == 1) trace_ms += std::chrono::duration<double, std::milli>(a1 - a0).count();
+    }
+    trace_ms /= (trace_reps > 1 ? trace_reps - 1 : 1);
+    (void)hipFree(d_u);
+  }
   std::printf(
       "{\"workload\": \"%s\", \"n\": %lld, \"nnz\": %lld, \"r\": %d, \"steps\": %lld, "
       "\"launch_steps\": %lld, \"launches\": %lld, \"iterations\": %lld, \"applies\": %lld, \"workgroups\": %d, "
       "\"kernel_ms\": %.6f, \"avg_launch_us\": %.3f, \"wall_ms_per_step\": %.6f, \"iter_per_s\": %.3f, "
-      "\"t\": %lld, \"cert_L\": %.6e, \"eps_t\": %.6e}\n",
+      "\"t\": %lld, \"cert_L\": %.6e, \"eps_t\": %.6e, \"trace_probes\": %d, \"trace_log_b\": %.10e, "
+      "\"trace_steps\": %d, \"trace_ms_per_call\": %.4f}\n",
       w.dense ? "denoise_bf16x3" : "matrix_completion_csr", (long long)w.n, (long long)w.nnz, w.r, (long long)steps, (long long)launch, (long long)c.launches,
       (long long)c.iterations, (long long)c.applies, c.workgroups, c.kernel_ms,
       c.launches ? 1e3 * c.kernel_ms / (double)c.launches : 0.0, wall_ms / (double)steps,
-      1e3 * (double)steps / wall_ms, (long long)info.t, info.cert_L, info.eps_t);
+      1e3 * (double)steps / wall_ms, (long long)info.t, info.cert_L, info.eps_t, trace_p, tr.log_b, tr.steps,
+      trace_ms);
   std::fflush(stdout);
   meg_destroy(ctx);
   (void)hipStreamDestroy(stream);

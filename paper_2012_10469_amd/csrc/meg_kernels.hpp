@@ -1711,6 +1711,259 @@ static __global__ __launch_bounds__(256) void k_lz_next(const double* __restrict
   for (int64_t i = threadIdx.x; i < n; i += 256) vn[i] = w[i] * ib;
 }
 
+// ---------------------------------------------------------------------------
+// Batched Lanczos runs of the full-trace estimate: up to 64 vectors advance
+// in lockstep, stored interleaved (element (i, b) at i * 64 + b), so lane b of
+// a wave owns vector b and one read of an operator row serves all of them.
+// Reductions over rows are per workgroup in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kTrW = 64;
+
+// Y = Op X for a CSR operator (values: C, M or the gradient values on the
+// pattern): one wave per row, lane = vector.  The row's column indices and
+// values are read 64 at a time (lane j holds entry j) and broadcast by
+// shuffles, so the loads of the X rows they select do not wait on each other.
+template <typename T>
+static __global__ __launch_bounds__(256) void k_tr_matvec_csr(int64_t n, const int* __restrict__ rp,
+                                                              const int* __restrict__ col, const T* __restrict__ val,
+                                                              const double* __restrict__ X, double* __restrict__ Y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const int e1 = rp[i + 1];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  for (int e0 = rp[i]; e0 < e1; e0 += 64) {
+    const int cnt = min(64, e1 - e0);
+    // entries past the row's end select row 0 with weight 0
+    const int cj = lane < cnt ? col[e0 + lane] : 0;
+    const double vj = lane < cnt ? (double)val[e0 + lane] : 0.0;
+    for (int j = 0; j < cnt; j += 8) {
+      const int c0 = __shfl(cj, j), c1 = __shfl(cj, j + 1), c2 = __shfl(cj, j + 2), c3 = __shfl(cj, j + 3);
+      const int c4 = __shfl(cj, j + 4), c5 = __shfl(cj, j + 5), c6 = __shfl(cj, j + 6), c7 = __shfl(cj, j + 7);
+      const double x0 = X[(int64_t)c0 * kTrW + lane], x1 = X[(int64_t)c1 * kTrW + lane];
+      const double x2 = X[(int64_t)c2 * kTrW + lane], x3 = X[(int64_t)c3 * kTrW + lane];
+      const double x4 = X[(int64_t)c4 * kTrW + lane], x5 = X[(int64_t)c5 * kTrW + lane];
+      const double x6 = X[(int64_t)c6 * kTrW + lane], x7 = X[(int64_t)c7 * kTrW + lane];
+      a0 += __shfl(vj, j) * x0 + __shfl(vj, j + 4) * x4;
+      a1 += __shfl(vj, j + 1) * x1 + __shfl(vj, j + 5) * x5;
+      a2 += __shfl(vj, j + 2) * x2 + __shfl(vj, j + 6) * x6;
+      a3 += __shfl(vj, j + 3) * x3 + __shfl(vj, j + 7) * x7;
+    }
+  }
+  Y[i * kTrW + lane] = (a0 + a1) + (a2 + a3);
+}
+
+// Y = D X for a dense operator (n x n, stride ld; the state's type or bf16
+// planes): a workgroup computes 32 rows x 64 vectors, staging 32-column
+// chunks of D and the matching 32 rows of X in LDS (FP64); a thread holds
+// 2 rows x 4 vectors.
+template <typename T>
+static __global__ __launch_bounds__(256) void k_tr_matvec_dense(int64_t n, int64_t ld, DenseSrc<T> D,
+                                                                const double* __restrict__ X,
+                                                                double* __restrict__ Y) {
+  __shared__ double Ds[32][33];
+  __shared__ double Xs[32][kTrW];
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  const int64_t row0 = (int64_t)blockIdx.x * 32;
+  double acc[2][4] = {};
+  for (int64_t k0 = 0; k0 < n; k0 += 32) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int e = tid + 256 * s, rr = e >> 5, kk = e & 31;
+      const int64_t gi = row0 + rr, gk = k0 + kk;
+      Ds[rr][kk] = (gi < n && gk < n) ? D.at(gi * ld + gk) : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int e = tid + 256 * s, kk = e >> 6, b = e & 63;
+      const int64_t gk = k0 + kk;
+      Xs[kk][b] = gk < n ? X[gk * kTrW + b] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < 32; ++kk) {
+      const double d0 = Ds[2 * ty][kk], d1 = Ds[2 * ty + 1][kk];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double x = Xs[kk][tx + 16 * q];
+        acc[0][q] += d0 * x;
+        acc[1][q] += d1 * x;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int64_t gi = row0 + 2 * ty + a;
+    if (gi < n) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Y[gi * kTrW + tx + 16 * q] = acc[a][q];
+    }
+  }
+}
+
+// Column dot products, in two passes for a fixed summation order: workgroup
+// g of the partial kernels takes rows g*4 + w + 4*G*q (w its wave, lane = the
+// vector) and writes one partial per output; k_tr_part_sum adds the G
+// partials of each output in order.  kTrRedWG bounds G.
+constexpr int kTrRedWG = 256;
+
+// part[(g * na + l) * 64 + b] = sum over workgroup g's rows i of
+// A[i * lda + l] X[i * 64 + b], l < na <= 32 (A: the state's basis, or the
+// interleaved FP64 deflation basis)
+template <typename TA>
+static __global__ __launch_bounds__(256) void k_tr_gram_part(const TA* __restrict__ A, int64_t lda, int na,
+                                                             const double* __restrict__ X, int64_t n,
+                                                             double* __restrict__ part) {
+  __shared__ double s[4][kTrW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double acc[32];
+#pragma unroll
+  for (int l = 0; l < 32; ++l) acc[l] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < n; i += (int64_t)gridDim.x * 4) {
+    const double x = X[i * kTrW + lane];
+    const TA* a = A + i * lda;
+#pragma unroll
+    for (int l = 0; l < 32; ++l)
+      if (l < na) acc[l] += (double)a[l] * x;
+  }
+#pragma unroll
+  for (int l = 0; l < 32; ++l) {
+    if (l >= na) break;
+    s[w][lane] = acc[l];
+    __syncthreads();
+    if (w == 0) part[((int64_t)blockIdx.x * na + l) * kTrW + lane] = (s[0][lane] + s[1][lane]) + (s[2][lane] + s[3][lane]);
+    __syncthreads();
+  }
+}
+
+// part[g * 64 + b] = sum over workgroup g's rows i of A[i][b] B[i][b]
+static __global__ __launch_bounds__(256) void k_tr_cdot_part(const double* __restrict__ A,
+                                                             const double* __restrict__ B, int64_t n,
+                                                             double* __restrict__ part) {
+  __shared__ double s[4][kTrW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double a0 = 0.0, a1 = 0.0;
+  int64_t i = (int64_t)blockIdx.x * 4 + w;
+  const int64_t st = (int64_t)gridDim.x * 4;
+  for (; i + st < n; i += 2 * st) {
+    a0 += A[i * kTrW + lane] * B[i * kTrW + lane];
+    a1 += A[(i + st) * kTrW + lane] * B[(i + st) * kTrW + lane];
+  }
+  if (i < n) a0 += A[i * kTrW + lane] * B[i * kTrW + lane];
+  s[w][lane] = a0 + a1;
+  __syncthreads();
+  if (w == 0) part[(int64_t)blockIdx.x * kTrW + lane] = (s[0][lane] + s[1][lane]) + (s[2][lane] + s[3][lane]);
+}
+
+// out[o] = sum_{g < G} part[g * cnt + o] for o < cnt (cnt = na * 64): one
+// wave per output, lane j adding partials j, j + 64, ... in order, then the
+// wave's fixed-order reduction
+static __global__ __launch_bounds__(256) void k_tr_part_sum(const double* __restrict__ part, int G, int cnt,
+                                                            double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (o >= cnt) return;
+  double a = 0.0;
+  for (int g = lane; g < G; g += 64) a += part[(int64_t)g * cnt + o];
+  a = wave_sum(a);
+  if (lane == 0) out[o] = a;
+}
+
+// Y[i][b] = s Y[i][b] + c0 X[i][b] + sum_{l < r} Q[i][l] cv[l] P[l][b]: with
+// Y = Op X on entry this makes Y = M_t X (the data term, the identity term and
+// the low-rank term of log X_t; P from the column dots of the basis).
+template <typename T>
+static __global__ __launch_bounds__(256) void k_tr_opfix(const T* __restrict__ Q, int KB, int r,
+                                                         const double* __restrict__ cv,
+                                                         const double* __restrict__ P, double s, double c0,
+                                                         const double* __restrict__ X, int64_t n,
+                                                         double* __restrict__ Y) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n * kTrW; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e >> 6;
+    const int b = (int)(e & 63);
+    double a = s * Y[e] + c0 * X[e];
+    for (int l = 0; l < r; ++l) a += (double)Q[i * KB + l] * cv[l] * P[l * kTrW + b];
+    Y[e] = a;
+  }
+}
+
+// W = Y - alpha_b X - beta_b Xp with alpha_b = al[b] and beta_b = be[b] (the
+// previous step's beta; be = nullptr at the first step)
+static __global__ __launch_bounds__(256) void k_tr_three(const double* __restrict__ Y, const double* __restrict__ X,
+                                                         const double* __restrict__ Xp,
+                                                         const double* __restrict__ al,
+                                                         const double* __restrict__ be, int64_t n,
+                                                         double* __restrict__ W) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n * kTrW; e += (int64_t)gridDim.x * 256) {
+    const int b = (int)(e & 63);
+    double w = Y[e] - al[b] * X[e];
+    if (be) w -= be[b] * Xp[e];
+    W[e] = w;
+  }
+}
+
+// beta_b = sqrt(bsq[b]) (zero once vector b's Krylov space is invariant:
+// beta_b <= 1e-14 (|alpha_b| + |beta_prev_b|), or the vector is zero); be[b]
+// receives beta_b, and W becomes the next Lanczos vector W / beta_b
+static __global__ __launch_bounds__(256) void k_tr_next(const double* __restrict__ bsq,
+                                                        const double* __restrict__ al,
+                                                        const double* __restrict__ bprev, int64_t n,
+                                                        double* __restrict__ be, double* __restrict__ W) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n * kTrW; e += (int64_t)gridDim.x * 256) {
+    const int b = (int)(e & 63);
+    const double bt = sqrt(fmax(bsq[b], 0.0));
+    const double ref = fabs(al[b]) + (bprev ? fabs(bprev[b]) : 0.0);
+    const bool live = bt > 1e-14 * ref && bt > 1e-300;
+    if (e < kTrW) be[b] = live ? bt : 0.0;
+    W[e] = live ? W[e] / bt : 0.0;
+  }
+}
+
+// Start block: columns [0, kq) from the FP64 interleaved basis Qd or, when Qd
+// is null, from the state's basis Q (n x KB, the state's type); columns
+// [kq, kq + np) from probes (n x np column-major FP64, probe j at
+// probes + j * n); the rest zero.
+template <typename T>
+static __global__ __launch_bounds__(256) void k_tr_load(const T* __restrict__ Q, int KB,
+                                                        const double* __restrict__ Qd, int kq,
+                                                        const double* __restrict__ probes, int np, int64_t n,
+                                                        double* __restrict__ X) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n * kTrW; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e >> 6;
+    const int b = (int)(e & 63);
+    double v = 0.0;
+    if (b < kq) v = Qd ? Qd[e] : (double)Q[i * KB + b];
+    else if (b < kq + np) v = probes[(int64_t)(b - kq) * n + i];
+    X[e] = v;
+  }
+}
+
+// Row mix: Y[i][b] = (sub ? Y[i][b] - s : s) for b in [b0, b1), with
+// s = sum_{l < nl} A[i][l] Mx[l][b] (Mx row-major 64 x 64).  A and Y may be the
+// same buffer: a wave reads its row whole before it writes.  One wave per row.
+static __global__ __launch_bounds__(256) void k_tr_rowmix(const double* A, const double* __restrict__ Mx, int nl,
+                                                          int b0, int b1, int sub, int64_t n, double* Y) {
+  __shared__ double Ms[kTrW * kTrW];
+  for (int e = threadIdx.x; e < nl * kTrW; e += 256) Ms[e] = Mx[e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const double a = A[i * kTrW + lane];
+  const double y = Y[i * kTrW + lane];
+  double s = 0.0;
+  for (int l = 0; l < nl; ++l) s += __shfl(a, l) * Ms[l * kTrW + lane];
+  if (lane >= b0 && lane < b1) Y[i * kTrW + lane] = sub ? y - s : s;
+}
+
+// X[i][b] *= sc[b]
+static __global__ __launch_bounds__(256) void k_tr_scale(const double* __restrict__ sc, int64_t n,
+                                                         double* __restrict__ X) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n * kTrW; e += (int64_t)gridDim.x * 256)
+    X[e] *= sc[e & 63];
+}
+
 // CSR structure check: 0 = rp[0] <= rp[i] <= rp[i+1] <= rp[n] = nnz and every
 // column index in [0, n).  Row ranges are validated before col is read.
 // objective at X_t, quadratic measurements: 1/(2m) sum_i (a_i^T X a_i - b_i)^2

@@ -49,6 +49,7 @@ EXPORTED = [
     "meg_block_size", "meg_init", "meg_step", "meg_solve", "meg_certificate", "meg_objective_value",
     "meg_get_iterate", "meg_set_iterate", "meg_get_state", "meg_set_state", "meg_profile_step", "meg_destroy",
     "meg_status_str", "meg_get_counters", "meg_step_external", "meg_dual_gap", "meg_solve_to_gap",
+    "meg_trace_exp", "meg_certificate_full",
     "meg_server_create", "meg_server_submit", "meg_server_run", "meg_server_query", "meg_server_result",
     "meg_server_release", "meg_server_team", "meg_server_get_stats", "meg_server_destroy",
 ]
@@ -115,6 +116,15 @@ class MegDualGapInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class MegTraceInfo(ctypes.Structure):
+    _fields_ = [("log_b", ctypes.c_double), ("log_b_defl", ctypes.c_double), ("log_b_tail", ctypes.c_double),
+                ("tail_rel_stderr", ctypes.c_double), ("t", ctypes.c_int64), ("kd", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("converged", ctypes.c_int32), ("batches", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class MegServerParams(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("launch_steps", ctypes.c_int32),
                 ("max_resident", ctypes.c_int32), ("flags", ctypes.c_uint32), ("fixed_team", ctypes.c_int32)]
@@ -176,6 +186,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "meg_profile_step": (ctypes.c_int, [vp, P(MegKernelTimes)]),
         "meg_get_counters": (ctypes.c_int, [vp, P(MegCounters), ctypes.c_int32]),
         "meg_dual_gap": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_double, P(MegDualGapInfo)]),
+        "meg_trace_exp": (ctypes.c_int, [vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                         P(MegTraceInfo)]),
+        "meg_certificate_full": (ctypes.c_int, [vp, P(MegTraceInfo), P(ctypes.c_double), P(ctypes.c_int32)]),
         "meg_solve_to_gap": (ctypes.c_int, [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, P(MegStepInfo),
                                             P(MegDualGapInfo)]),
         "meg_destroy": (None, [vp]),
@@ -401,6 +414,38 @@ class LowRankMEG:
         out = MegDualGapInfo()
         _check(self._lib.meg_dual_gap(self._ctx, int(max_steps), float(tol), ctypes.byref(out)), "meg_dual_gap")
         return out.as_dict()
+
+    def trace_exp(self, probes=None, weight: Optional[float] = None, max_steps: int = 64, tol: float = 1e-10):
+        """Estimate of b_n = tr exp(M_t) for the current iterate (the matrix the
+        next step decomposes): the solver block's span exactly, the rest from
+        the probes (a float64 device tensor n x p, probe j = probes[:, j]; the
+        library reads it column by column, so it is passed as its transpose's
+        contiguous copy).  weight defaults to 1/p.  Returns the info dict and
+        the MegTraceInfo for certificate_full."""
+        p = 0 if probes is None else int(probes.shape[1])
+        ptr = None
+        if p > 0:
+            import torch
+
+            if probes.dtype != torch.float64 or not probes.is_cuda or probes.dim() != 2:
+                raise ValueError("probes must be a 2-D float64 device tensor (n x p)")
+            pt = probes.t().contiguous()
+            self._keep_probe = pt
+            ptr = _dptr(pt)
+        w = (1.0 / p if p > 0 else 1.0) if weight is None else float(weight)
+        out = MegTraceInfo()
+        _check(self._lib.meg_trace_exp(self._ctx, ptr, p, w, int(max_steps), float(tol), ctypes.byref(out)),
+               "meg_trace_exp")
+        self._keep_probe = None
+        return out.as_dict(), out
+
+    def certificate_full(self, trace: "MegTraceInfo") -> tuple:
+        """(L_full, holds) of the most recent step from a trace estimate taken
+        at the iterate that step started from."""
+        L, h = ctypes.c_double(), ctypes.c_int32()
+        _check(self._lib.meg_certificate_full(self._ctx, ctypes.byref(trace), ctypes.byref(L), ctypes.byref(h)),
+               "meg_certificate_full")
+        return L.value, h.value
 
     def solve_to_gap(self, max_iters: int, tol: float, check_every: int = 8) -> tuple:
         """Iterate until the dual gap is <= tol (checked every check_every

@@ -52,6 +52,8 @@ def test_struct_layout_matches_header(M):
 #define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
 int main(void) {
   P(meg_params) P(meg_objective) P(meg_start) P(meg_step_info) P(meg_kernel_times) P(meg_counters) P(meg_dual_gap_info)
+  P(meg_trace_info) O(meg_trace_info, tail_rel_stderr) O(meg_trace_info, t) O(meg_trace_info, kd)
+  O(meg_trace_info, converged) O(meg_trace_info, batches)
   O(meg_kernel_times, apply_ms) O(meg_kernel_times, finalize_ms) O(meg_kernel_times, workgroups)
   O(meg_kernel_times, wg_apply_ms) O(meg_kernel_times, wg_skew_ms) O(meg_kernel_times, reduce_ms)
   O(meg_kernel_times, rr_ms) O(meg_kernel_times, rr_tail_ms) O(meg_kernel_times, jacobi_sweeps)
@@ -84,6 +86,7 @@ int main(void) {
         want[k] = int(v)
     S = {"meg_params": M.MegParams, "meg_objective": M.MegObjective, "meg_start": M.MegStart,
          "meg_step_info": M.MegStepInfo, "meg_kernel_times": M.MegKernelTimes, "meg_counters": M.MegCounters, "meg_dual_gap_info": M.MegDualGapInfo,
+         "meg_trace_info": M.MegTraceInfo,
          "meg_server_params": M.MegServerParams, "meg_request": M.MegRequest,
          "meg_request_status": M.MegRequestStatus, "meg_server_stats": M.MegServerStats}
     for k, v in want.items():
@@ -226,4 +229,8 @@ def test_null_context_calls(M):
     dg = M.MegDualGapInfo()
     assert lib.meg_dual_gap(None, 64, 1e-10, ctypes.byref(dg)) == M.MEG_ERR_INVALID_ARG
     assert lib.meg_solve_to_gap(None, 10, 1e-3, 4, None, ctypes.byref(dg)) == M.MEG_ERR_INVALID_ARG
+    tr = M.MegTraceInfo()
+    assert lib.meg_trace_exp(None, None, 0, 1.0, 32, 1e-10, ctypes.byref(tr)) == M.MEG_ERR_INVALID_ARG
+    L, h = ctypes.c_double(), ctypes.c_int32()
+    assert lib.meg_certificate_full(None, ctypes.byref(tr), ctypes.byref(L), ctypes.byref(h)) == M.MEG_ERR_INVALID_ARG
     lib.meg_destroy(None)  # no-op
