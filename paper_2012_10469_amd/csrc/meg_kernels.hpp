@@ -1721,8 +1721,8 @@ constexpr int kTrW = 64;
 
 // Y = Op X for a CSR operator (values: C, M or the gradient values on the
 // pattern): one wave per row, lane = vector.  The row's column indices and
-// values are read 64 at a time (lane j holds entry j) and broadcast by
-// shuffles, so the loads of the X rows they select do not wait on each other.
+// values are read 64 at a time (lane j holds entry j) and broadcast with
+// readlane, so the loads of the X rows they select do not wait on each other.
 template <typename T>
 static __global__ __launch_bounds__(256) void k_tr_matvec_csr(int64_t n, const int* __restrict__ rp,
                                                               const int* __restrict__ col, const T* __restrict__ val,
@@ -1737,17 +1737,15 @@ static __global__ __launch_bounds__(256) void k_tr_matvec_csr(int64_t n, const i
     // entries past the row's end select row 0 with weight 0
     const int cj = lane < cnt ? col[e0 + lane] : 0;
     const double vj = lane < cnt ? (double)val[e0 + lane] : 0.0;
-    for (int j = 0; j < cnt; j += 8) {
-      const int c0 = __shfl(cj, j), c1 = __shfl(cj, j + 1), c2 = __shfl(cj, j + 2), c3 = __shfl(cj, j + 3);
-      const int c4 = __shfl(cj, j + 4), c5 = __shfl(cj, j + 5), c6 = __shfl(cj, j + 6), c7 = __shfl(cj, j + 7);
+    for (int j = 0; j < cnt; j += 4) {
+      const int c0 = __builtin_amdgcn_readlane(cj, j), c1 = __builtin_amdgcn_readlane(cj, j + 1);
+      const int c2 = __builtin_amdgcn_readlane(cj, j + 2), c3 = __builtin_amdgcn_readlane(cj, j + 3);
       const double x0 = X[(int64_t)c0 * kTrW + lane], x1 = X[(int64_t)c1 * kTrW + lane];
       const double x2 = X[(int64_t)c2 * kTrW + lane], x3 = X[(int64_t)c3 * kTrW + lane];
-      const double x4 = X[(int64_t)c4 * kTrW + lane], x5 = X[(int64_t)c5 * kTrW + lane];
-      const double x6 = X[(int64_t)c6 * kTrW + lane], x7 = X[(int64_t)c7 * kTrW + lane];
-      a0 += __shfl(vj, j) * x0 + __shfl(vj, j + 4) * x4;
-      a1 += __shfl(vj, j + 1) * x1 + __shfl(vj, j + 5) * x5;
-      a2 += __shfl(vj, j + 2) * x2 + __shfl(vj, j + 6) * x6;
-      a3 += __shfl(vj, j + 3) * x3 + __shfl(vj, j + 7) * x7;
+      a0 += readlane_d(vj, j) * x0;
+      a1 += readlane_d(vj, j + 1) * x1;
+      a2 += readlane_d(vj, j + 2) * x2;
+      a3 += readlane_d(vj, j + 3) * x3;
     }
   }
   Y[i * kTrW + lane] = (a0 + a1) + (a2 + a3);
