@@ -41,6 +41,7 @@ __all__ = [
     "DenoiseObjective",
     "MaskedObjective",
     "QuadMeasObjective",
+    "BilinearObjective",
     "exact_meg_step",
     "run_exact_meg",
     "FactoredIterate",
@@ -436,6 +437,32 @@ def run_lowrank_meg(obj, V0, lam0, r: int, eta: float, T: int, eps_params=(0.8, 
     if not keep_states:
         out["states"].append(it.copy())
     return out
+
+
+class BilinearObjective:
+    """f(X) = 1/2 sum_i (a_i^T X b_i - y_i)^2, the recovery problem from
+    quadratic measurements of Section 7 (full, deterministic gradients).
+
+    grad f = sum_i r_i a_i b_i^T with r_i = a_i^T X b_i - y_i; the method uses
+    its symmetric part (Section 1), 1/2 sum_i r_i (a_i b_i^T + b_i a_i^T).
+    A, B: m x n, rows a_i and b_i."""
+
+    def __init__(self, A: np.ndarray, B: np.ndarray, y: np.ndarray):
+        self.A = np.asarray(A, dtype=np.float64)
+        self.B = np.asarray(B, dtype=np.float64)
+        self.y = np.asarray(y, dtype=np.float64)
+
+    def residuals(self, X: np.ndarray) -> np.ndarray:
+        return np.sum((self.A @ X) * self.B, axis=1) - self.y
+
+    def grad(self, X: np.ndarray) -> np.ndarray:
+        r = self.residuals(X)
+        H = self.A.T @ (r[:, None] * self.B)
+        return 0.5 * (H + H.T)
+
+    def value(self, X: np.ndarray) -> float:
+        r = self.residuals(X)
+        return 0.5 * float(np.dot(r, r))
 
 
 # ---------------------------------------------------------------------------

@@ -429,6 +429,88 @@ def exp_init_quadmeas(rows: np.ndarray, b: np.ndarray, n: int, r: int, seed: int
     return exp_init_from_operator(mv, n, r, tau, seed)
 
 
+@dataclasses.dataclass
+class BilinearProblem:
+    """The recovery problem of the experiments (Section 7): ground truth
+    M = (sqrt(n) W)(sqrt(n) W)^T, W n x rank Gaussian with ||W||_F = 1 (so
+    tr M = n); m = 20 n rank pairs (a_i, b_i) of uniform unit vectors;
+    y = y0 + kappa ||y0|| v with y0_i = a_i^T M b_i and v a uniform unit vector;
+    trace bound tau (0.5 tr M for rank 1 and 5, 0.65 tr M for rank 20);
+    smoothness beta = 0.4 sqrt(rank n), step size 1/beta.
+
+    The unit-trace method runs on X' = X / tau: f(tau X') has the gradient
+    tau * grad g(X') with g the same objective on y' = y / tau, so the
+    library and the oracle take y' and the step size tau / beta."""
+    n: int
+    rank: int
+    A: np.ndarray       # m x n, rows a_i
+    B: np.ndarray       # m x n, rows b_i
+    y: np.ndarray       # m, the noisy measurements
+    M: np.ndarray       # n x n ground truth
+    tau: float
+    beta: float
+    U: np.ndarray       # n x rank, the start's Gaussian block (||U||_F = 1)
+
+    @property
+    def m(self) -> int:
+        return self.A.shape[0]
+
+    @property
+    def y_unit(self) -> np.ndarray:
+        return self.y / self.tau
+
+    @property
+    def eta_unit(self) -> float:
+        return self.tau / self.beta
+
+
+def bilinear_recovery(n: int, rank: int, seed: int, kappa: float = 0.5) -> BilinearProblem:
+    g = rng(11, seed, n, rank)
+    W_ = g.standard_normal((n, rank))
+    W_ /= np.linalg.norm(W_)
+    M = n * (W_ @ W_.T)
+    m = 20 * n * rank
+    A = g.standard_normal((m, n))
+    A /= np.linalg.norm(A, axis=1, keepdims=True)
+    B = g.standard_normal((m, n))
+    B /= np.linalg.norm(B, axis=1, keepdims=True)
+    y0 = np.sum((A @ M) * B, axis=1)
+    v = g.standard_normal(m)
+    v /= np.linalg.norm(v)
+    y = y0 + kappa * np.linalg.norm(y0) * v
+    tau = (0.65 if rank >= 20 else 0.5) * float(np.trace(M))
+    U = g.standard_normal((n, rank))
+    U /= np.linalg.norm(U)
+    return BilinearProblem(n, rank, A, B, y, M, tau, 0.4 * math.sqrt(rank * n), U)
+
+
+def exp_init_bilinear(p: BilinearProblem, r: int):
+    """Warm start (Section 7, initialisation equation) of the recovery
+    problem, as printed: (V_r, Lambda_r) the top-r eigenpairs of
+    -grad f(tau U U^T) (symmetric part), weights the projection of -Lambda_r
+    onto the tau-simplex, divided by tau.  The sign as printed favours the
+    smallest of the r eigenvalues; Table 1's initialisation errors (rank 5
+    and 20) match it and not the other sign."""
+    X = p.tau * (p.U @ p.U.T)
+    res = np.sum((p.A @ X) * p.B, axis=1) - p.y
+    H = p.A.T @ (res[:, None] * p.B)
+    Gm = -0.5 * (H + H.T)
+    w, Q = np.linalg.eigh(Gm)
+    w, Q = w[::-1][:r], Q[:, ::-1][:, :r]
+    lam = _simplex_projection(-w, p.tau) / p.tau
+    return np.ascontiguousarray(Q), lam
+
+
+def bilinear_rows(p: BilinearProblem, dtype=np.float32, lda: Optional[int] = None) -> np.ndarray:
+    """The library's layout of the measurement vectors: 2m rows of length
+    lda >= n, rows a_1..a_m then b_1..b_m (columns n..lda-1 zero)."""
+    lda = p.n if lda is None else lda
+    rows = np.zeros((2 * p.m, lda), dtype=dtype)
+    rows[: p.m, : p.n] = p.A
+    rows[p.m :, : p.n] = p.B
+    return rows
+
+
 def quadmeas_pool_device(n: int, m: int, seed: int, rank: int = 3, chunk: int = 1 << 16):
     """Full-size pool generated on the GPU (torch's counter-based generator,
     seeded): A (m x n float32, row i = a_i, standard Gaussian), b_i =
