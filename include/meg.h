@@ -74,9 +74,14 @@ typedef enum {
                                  step uses the minibatch estimate
                                  (1/L) sum_{i in B_t} (a_i^T X a_i - b_i) a_i a_i^T
                                  (Section 6, stochastic oracle)                */
-  MEG_GRAD_EXTERNAL = 5       /* the caller supplies the gradient (or an
+  MEG_GRAD_EXTERNAL = 5,      /* the caller supplies the gradient (or an
                                  unbiased estimate of it, Section 6) at X_t
                                  for every step: meg_step_external         */
+  MEG_GRAD_BILINEAR = 6       /* f = 1/2 sum_i (a_i^T X b_i - y_i)^2, the
+                                 recovery problem of Section 7, with its full
+                                 gradient (symmetric part, Section 1)
+                                 1/2 sum_i r_i (a_i b_i^T + b_i a_i^T),
+                                 r_i = a_i^T X b_i - y_i                       */
 } meg_grad_kind;
 
 #define MEG_FLAG_STRICT 1u   /* inner non-convergence -> MEG_ERR_NOT_CONVERGED */
@@ -133,6 +138,12 @@ typedef struct {
    * reproducible.  F64 and F32 only (the bf16-plane form is dense-only).
    * Each step also forms the batch x batch Gram matrix of its minibatch to
    * bound the spectrum of the gradient estimate (the solver's shift). */
+  /* BILINEAR: DEVICE A holds 2m rows of length lda >= n in the state's type
+   * (F64 or F32): a_1..a_m, then b_1..b_m; b holds y[m].  Every step forms
+   * the residuals and the dense symmetric gradient (n x n, owned by the
+   * context) on the device, then takes the step as meg_step_external would
+   * with it.  The trace bound of Section 7 is 1: for tr X = tau pass y / tau
+   * and eta * tau (the iterates are then X / tau). */
   const void* A;
   int64_t lda;
   const void* b;

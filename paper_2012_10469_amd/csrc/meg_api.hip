@@ -69,6 +69,11 @@ struct meg_ctx_s {
   int aux_nwg = 1;         // row-parallel auxiliary kernels
   Ctl* h_ctl = nullptr;    // pinned host mirror
   bool external = false;   // the caller supplies G_t every step (meg_step_external)
+  bool bilinear = false;   // bilinear measurements: the context forms G_t itself (external step path)
+  void* bil_G = nullptr;   // bilinear: dense symmetric gradient n x n (state type, ld n)
+  double* bil_res = nullptr;  // bilinear: residuals r_i (m)
+  double* bil_P = nullptr;    // bilinear: per-slice partial gradients (bil_S x n x n)
+  int bil_S = 1;
   bool failed = false;
 };
 
@@ -294,6 +299,31 @@ struct Launch {
     return hipGetLastError();
   }
 
+  // bilinear measurements at the current iterate: residuals and f(X_t)
+  // (ctl->f), then, when `grad`, the dense symmetric gradient into c->bil_G
+  static hipError_t bilinear(meg_ctx c, bool grad) {
+    const Cfg& cfg = c->cfg;
+    const int64_t n = cfg.n, m = c->obj.m;
+    const int mwg = (int)std::min<int64_t>(4096, ceil_div(n * KB, 256));
+    hipLaunchKernelGGL((k_materialize<T, KB>), dim3(mwg), dim3(256), 0, c->stream, cfg, c->ctl, (T*)c->Qw, (T*)c->Za,
+                       (T*)c->Zb);
+    const int rg = (int)std::min<int64_t>(1024, ceil_div(m, 4));
+    hipLaunchKernelGGL((k_bil_resid<T, KB>), dim3(rg), dim3(256), 0, c->stream, cfg, (const Ctl*)c->ctl,
+                       (const T*)c->Qw, (const T*)c->Za, (const T*)c->Zb, (const T*)c->obj.A, c->obj.lda,
+                       (const T*)c->obj.b, m, c->bil_res, c->part);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, c->stream, c->ctl, c->part, rg, 0);
+    if (grad) {
+      const int tiles = (int)ceil_div(n, 32);
+      const int64_t per = ceil_div(ceil_div(m, c->bil_S), 16) * 16;
+      hipLaunchKernelGGL((k_bil_grad_part<T>), dim3(tiles, tiles, c->bil_S), dim3(256), 0, c->stream, n,
+                         (const T*)c->obj.A, c->obj.lda, m, (const double*)c->bil_res, per, c->bil_P);
+      const int sg = (int)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n * n, 256)));
+      hipLaunchKernelGGL((k_bil_grad_sum<T>), dim3(sg), dim3(256), 0, c->stream, n, c->bil_S,
+                         (const double*)c->bil_P, (T*)c->bil_G);
+    }
+    return hipGetLastError();
+  }
+
   static hipError_t data_norm(meg_ctx c) {
     const Cfg& cfg = c->cfg;
     int64_t rows, cols, ld;
@@ -342,6 +372,9 @@ template <typename T, int KB> struct DoCache {
 };
 template <typename T, int KB> struct DoXdotG {
   static hipError_t run(meg_ctx c) { return Launch<T, KB>::xdotg(c); }
+};
+template <typename T, int KB> struct DoBilinear {
+  static hipError_t run(meg_ctx c, bool grad) { return Launch<T, KB>::bilinear(c, grad); }
 };
 template <typename T, int KB> struct DoPartNeed {
   static size_t run(meg_ctx c, int P) { return Launch<T, KB>::part_need(P); }
@@ -1109,6 +1142,11 @@ meg_status validate(const meg_params* p, const meg_objective* o, const meg_start
     case MEG_GRAD_EXTERNAL:
       if (p->prec == MEG_PREC_F32_BF16X3) return MEG_ERR_UNSUPPORTED;
       break;
+    case MEG_GRAD_BILINEAR:
+      if (!o->A || !o->b || o->m < 1 || o->lda < p->n) return MEG_ERR_INVALID_ARG;
+      if (o->m > (int64_t)1 << 40 || o->lda > (int64_t)1 << 40) return MEG_ERR_INVALID_ARG;
+      if (p->prec == MEG_PREC_F32_BF16X3) return MEG_ERR_UNSUPPORTED;
+      break;
     case MEG_GRAD_QUADMEAS: {
       if (!o->A || !o->b || !o->batch_idx || o->m < 1 || o->lda < p->n || o->batch_steps < 1) return MEG_ERR_INVALID_ARG;
       if (o->batch < 1 || o->batch > kMaxBatch) return MEG_ERR_INVALID_ARG;
@@ -1142,7 +1180,8 @@ meg_status validate(const meg_params* p, const meg_objective* o, const meg_start
 
 void free_ctx(meg_ctx c) {
   if (!c) return;
-  void* bufs[] = {c->Qw, c->Za, c->Zb, c->g, c->quad, c->ctl, c->part, c->gpart, c->sums, c->bar, c->ts, c->lz_prev};
+  void* bufs[] = {c->Qw,   c->Za,  c->Zb, c->g,  c->quad,    c->ctl,    c->part,     c->gpart,
+                  c->sums, c->bar, c->ts, c->lz_prev, c->bil_G, c->bil_res, c->bil_P};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
@@ -1153,213 +1192,10 @@ void free_ctx(meg_ctx c) {
   delete c;
 }
 
-}  // namespace
-
-extern "C" {
-
-int32_t meg_block_size(int32_t r, int32_t oversample) {
-  if (r < 1 || oversample < 0) return 0;
-  const int need = r + 1 + oversample;
-  const int k = ((need + 15) / 16) * 16;
-  return k <= KMAX ? k : 0;
-}
-
-const char* meg_status_str(meg_status s) {
-  switch (s) {
-    case MEG_OK: return "ok";
-    case MEG_ERR_INVALID_ARG: return "invalid argument";
-    case MEG_ERR_OUT_OF_MEMORY: return "out of device memory";
-    case MEG_ERR_DEVICE: return "device (HIP) error";
-    case MEG_ERR_NUMERIC: return "non-finite value in the solver";
-    case MEG_ERR_NOT_CONVERGED: return "inner solver did not converge";
-    case MEG_ERR_STATE: return "context failed earlier or bad state";
-    case MEG_ERR_UNSUPPORTED: return "unsupported combination";
-  }
-  return "unknown status";
-}
-
-meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective* obj, const meg_start* start,
-                    void* stream) {
-  if (!out) return MEG_ERR_INVALID_ARG;
-  *out = nullptr;
-  int k = 0;
-  meg_status st = validate(params, obj, start, &k);
-  if (st != MEG_OK) return st;
-  meg_ctx c = new (std::nothrow) meg_ctx_s();
-  if (!c) return MEG_ERR_OUT_OF_MEMORY;
-  c->params = *params;
-  c->obj = *obj;
-  c->stream = (hipStream_t)stream;
-  c->esize = (params->prec == MEG_PREC_F64) ? 8 : 4;
-  Cfg& cfg = c->cfg;
-  cfg.n = params->n;
-  cfg.ld = obj->ld;
-  cfg.nnz = obj->nnz;
-  cfg.lda = obj->lda;
-  cfg.m = obj->m;
-  cfg.batch_steps = obj->batch_steps;
-  cfg.r = params->r;
-  cfg.k = k;
-  cfg.kind = obj->kind;
-  cfg.prec = params->prec;
-  cfg.min_inner = params->min_inner;
-  cfg.max_inner = params->max_inner;
-  cfg.batch = obj->batch;
-  cfg.rr_from = std::min(2, (int)params->max_inner);
-  cfg.eta = params->eta;
-  cfg.eps_scale = params->eps_scale;
-  cfg.eps_c = params->eps_c;
-  cfg.eps_pow = params->eps_pow;
-  cfg.inner_tol = params->inner_tol > 0 ? params->inner_tol : (c->esize == 8 ? 1e-10 : 1e-6);
-  cfg.unit_round = (c->esize == 8) ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
-  cfg.cert_tol = params->cert_tol;
-  if (obj->kind == MEG_GRAD_EXTERNAL) {  // the operator family is chosen per step; dense until then
-    c->external = true;
-    cfg.kind = LINEAR_DENSE;
-  }
-
-  int coop = 0, dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) {
-    (void)hipGetLastError();
-    delete c;
-    return MEG_ERR_DEVICE;
-  }
-  c->P = dispatch<DoGrid>(c);
-  if (c->external) {  // a grid that both operator families can launch cooperatively
-    cfg.kind = LINEAR_CSR;
-    c->P = std::min(c->P, dispatch<DoGrid>(c));
-    cfg.kind = LINEAR_DENSE;
-  }
-  if (c->P < 1) {
-    delete c;
-    return MEG_ERR_DEVICE;
-  }
-  c->aux_nwg = std::max(1024, ceil_div(cfg.n, 4));
-  const size_t pe = std::max(dispatch<DoPartNeed>(c, c->P), (size_t)c->aux_nwg);
-  const size_t zbytes = (size_t)cfg.n * k * c->esize;
-  auto alloc = [&](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 256)) == hipSuccess; };
-  bool ok = alloc(&c->Qw, zbytes) && alloc(&c->Za, zbytes) && alloc(&c->Zb, zbytes) &&
-            alloc((void**)&c->ctl, sizeof(Ctl)) && alloc((void**)&c->part, pe * 8) &&
-            alloc((void**)&c->sums, 3 * KMAX * KMAX * 8) && alloc((void**)&c->bar, kBarWords * sizeof(unsigned)) &&
-            alloc((void**)&c->gpart, (size_t)kBarMaxGroups * 3 * KMAX * KMAX * 8) &&
-            alloc((void**)&c->ts, kTsSlots * sizeof(long long));
-  if (ok && obj->kind == MEG_GRAD_MASKED_CSR) ok = alloc(&c->g, (size_t)std::max<int64_t>(obj->nnz, 1) * c->esize);
-  if (ok && obj->kind == MEG_GRAD_QUADMEAS) ok = alloc(&c->quad, quad_layout(obj->batch, k, c->esize).bytes);
-  if (ok) ok = hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl)) == hipSuccess;
-  for (int i = 0; ok && i < meg_ctx_s::kEvRing; ++i)
-    ok = hipEventCreate(&c->ev_a[i]) == hipSuccess && hipEventCreate(&c->ev_b[i]) == hipSuccess;
-  if (!ok) {
-    (void)hipGetLastError();
-    free_ctx(c);
-    return MEG_ERR_OUT_OF_MEMORY;
-  }
-  c->part_elems = pe;
-  if (hipMemsetAsync(c->bar, 0, kBarWords * sizeof(unsigned), c->stream) != hipSuccess ||
-      hipMemsetAsync(c->ctl, 0, sizeof(Ctl), c->stream) != hipSuccess ||
-      hipMemsetAsync(c->ts, 0, kTsSlots * sizeof(long long), c->stream) != hipSuccess) {
-    free_ctx(c);
-    return MEG_ERR_DEVICE;
-  }
-  // CSR structure check before any kernel reads through the indices
-  if (obj->kind == MEG_GRAD_LINEAR_CSR || obj->kind == MEG_GRAD_MASKED_CSR) {
-    int h_err = 0;
-    int* d_err = (int*)c->sums;
-    if (hipMemsetAsync(d_err, 0, sizeof(int), c->stream) != hipSuccess) {
-      free_ctx(c);
-      return MEG_ERR_DEVICE;
-    }
-    hipLaunchKernelGGL(k_check_csr, dim3((unsigned)std::min<int64_t>(1024, (cfg.n + 255) / 256)), dim3(256), 0,
-                       c->stream, obj->row_ptr, obj->col, cfg.n, cfg.nnz, d_err);
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
-        hipMemcpy(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
-      free_ctx(c);
-      return MEG_ERR_DEVICE;
-    }
-    if (h_err) {
-      free_ctx(c);
-      return MEG_ERR_INVALID_ARG;
-    }
-    (void)dispatch<DoCache>(c);  // per-workgroup LDS copy of the CSR data, when it fits
-  }
-  // minibatch index check before any kernel reads the pool through them
-  if (obj->kind == MEG_GRAD_QUADMEAS) {
-    int h_err = 0;
-    int* d_err = (int*)c->sums;
-    const int64_t cnt = obj->batch_steps * (int64_t)obj->batch;
-    if (hipMemsetAsync(d_err, 0, sizeof(int), c->stream) != hipSuccess) {
-      free_ctx(c);
-      return MEG_ERR_DEVICE;
-    }
-    hipLaunchKernelGGL(k_check_idx, dim3((unsigned)std::min<int64_t>(1024, (cnt + 255) / 256)), dim3(256), 0,
-                       c->stream, obj->batch_idx, cnt, obj->m, d_err);
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
-        hipMemcpy(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
-      free_ctx(c);
-      return MEG_ERR_DEVICE;
-    }
-    if (h_err) {
-      free_ctx(c);
-      return MEG_ERR_INVALID_ARG;
-    }
-  }
-  // data norm (sets ctl->data_norm) and the extreme eigenvalues of the data
-  // operator (shift of the subspace iteration); the factored gradient
-  // changes every step and bounds its spectrum inside the step instead
-  const bool has_data = obj->kind != MEG_GRAD_QUADMEAS && obj->kind != MEG_GRAD_EXTERNAL;
-  if (has_data && (dispatch<DoNorm>(c) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)) {
-    free_ctx(c);
-    return MEG_ERR_DEVICE;
-  }
-  if (has_data) {
-    double lmin = 0.0, lmax = 0.0;
-    st = (c->esize == 8) ? lanczos_extremes<double>(c, &lmin, &lmax) : lanczos_extremes<float>(c, &lmin, &lmax);
-    if (st == MEG_OK) st = copy_ctl_to_host(c);
-    if (st != MEG_OK) {
-      free_ctx(c);
-      return st;
-    }
-    c->h_ctl->op_lmin = lmin;
-    c->h_ctl->op_lmax = lmax;
-    if (hipMemcpy(c->ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice) != hipSuccess) {
-      free_ctx(c);
-      return MEG_ERR_DEVICE;
-    }
-  }
-  // X_1 = (1 - eps_0) X_0 + (eps_0 / n) I: alpha = eps_0/n, d = (1 - eps_0) lambda_0
-  const double eps0 = cfg.eps_scale / std::pow(cfg.eps_c + 1.0, cfg.eps_pow);
-  std::vector<double> d(start->q);
-  for (int i = 0; i < start->q; ++i) d[i] = (1.0 - eps0) * start->lambda0[i];
-  st = upload_iterate(c, start->V0, start->q, d.data(), eps0 / (double)cfg.n, 1);
-  if (st != MEG_OK) {
-    free_ctx(c);
-    return st;
-  }
-  *out = c;
-  return MEG_OK;
-}
-
-meg_status meg_step(meg_ctx c, meg_step_info* info) {
-  meg_status st = check_ctx(c);
-  if (st != MEG_OK) return st;
-  if (c->external) return MEG_ERR_INVALID_ARG;
-  // f(X_t): the masked objective's gradient phase computes it in the step
-  if (info && c->cfg.kind != MASKED_CSR) HIPCHK(c, dispatch<DoObjective>(c));
-  HIPCHK(c, launch_steps(c, 1));
-  if (!info) return MEG_OK;
-  st = copy_ctl_to_host(c);
-  if (st == MEG_OK) st = check_barrier(c);
-  if (st != MEG_OK) return st;
-  fill_info(*c->h_ctl, info);
-  if (c->h_ctl->status) return (meg_status)c->h_ctl->status;
-  if ((c->params.flags & MEG_FLAG_STRICT) && !info->converged) return MEG_ERR_NOT_CONVERGED;
-  return MEG_OK;
-}
-
-meg_status meg_step_external(meg_ctx c, const meg_objective* grad, meg_step_info* info) {
-  meg_status st = check_ctx(c);
-  if (st != MEG_OK) return st;
-  if (!c->external || !grad) return MEG_ERR_INVALID_ARG;
+// One step with a caller-supplied (or context-formed) gradient G_t: its
+// Gershgorin bound, this step's shift and coefficients, one step launch.
+meg_status external_step_core(meg_ctx c, const meg_objective* grad, meg_step_info* info) {
+  meg_status st = MEG_OK;
   Cfg& cfg = c->cfg;
   const int64_t n = cfg.n;
   if (grad->kind == MEG_GRAD_LINEAR_DENSE) {
@@ -1424,18 +1260,281 @@ meg_status meg_step_external(meg_ctx c, const meg_objective* grad, meg_step_info
   if (st != MEG_OK) return st;
   if (info) {
     fill_info(*c->h_ctl, info);
-    info->f = __builtin_nan("");
+    if (!c->bilinear) info->f = __builtin_nan("");  // bilinear: f(X_t) from its residuals
   }
   if (c->h_ctl->status) return (meg_status)c->h_ctl->status;
   if (info && (c->params.flags & MEG_FLAG_STRICT) && !info->converged) return MEG_ERR_NOT_CONVERGED;
   return MEG_OK;
 }
 
+// one step of a bilinear-measurement context: residuals, f(X_t) and the dense
+// gradient G_t on the device, then the external step with G_t
+meg_status bilinear_prepare(meg_ctx c, bool grad) {
+  HIPCHK(c, dispatch<DoBilinear>(c, grad));
+  if (grad) {
+    c->obj.dense = c->bil_G;
+    c->obj.ld = c->cfg.n;
+    c->cfg.ld = c->cfg.n;
+    c->cfg.kind = LINEAR_DENSE;
+  }
+  return MEG_OK;
+}
+
+meg_status bilinear_step(meg_ctx c, meg_step_info* info) {
+  meg_status st = bilinear_prepare(c, true);
+  if (st != MEG_OK) return st;
+  meg_objective g;
+  std::memset(&g, 0, sizeof(g));
+  g.kind = MEG_GRAD_LINEAR_DENSE;
+  g.dense = c->bil_G;
+  g.ld = c->cfg.n;
+  return external_step_core(c, &g, info);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t meg_block_size(int32_t r, int32_t oversample) {
+  if (r < 1 || oversample < 0) return 0;
+  const int need = r + 1 + oversample;
+  const int k = ((need + 15) / 16) * 16;
+  return k <= KMAX ? k : 0;
+}
+
+const char* meg_status_str(meg_status s) {
+  switch (s) {
+    case MEG_OK: return "ok";
+    case MEG_ERR_INVALID_ARG: return "invalid argument";
+    case MEG_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case MEG_ERR_DEVICE: return "device (HIP) error";
+    case MEG_ERR_NUMERIC: return "non-finite value in the solver";
+    case MEG_ERR_NOT_CONVERGED: return "inner solver did not converge";
+    case MEG_ERR_STATE: return "context failed earlier or bad state";
+    case MEG_ERR_UNSUPPORTED: return "unsupported combination";
+  }
+  return "unknown status";
+}
+
+meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective* obj, const meg_start* start,
+                    void* stream) {
+  if (!out) return MEG_ERR_INVALID_ARG;
+  *out = nullptr;
+  int k = 0;
+  meg_status st = validate(params, obj, start, &k);
+  if (st != MEG_OK) return st;
+  meg_ctx c = new (std::nothrow) meg_ctx_s();
+  if (!c) return MEG_ERR_OUT_OF_MEMORY;
+  c->params = *params;
+  c->obj = *obj;
+  c->stream = (hipStream_t)stream;
+  c->esize = (params->prec == MEG_PREC_F64) ? 8 : 4;
+  Cfg& cfg = c->cfg;
+  cfg.n = params->n;
+  cfg.ld = obj->ld;
+  cfg.nnz = obj->nnz;
+  cfg.lda = obj->lda;
+  cfg.m = obj->m;
+  cfg.batch_steps = obj->batch_steps;
+  cfg.r = params->r;
+  cfg.k = k;
+  cfg.kind = obj->kind;
+  cfg.prec = params->prec;
+  cfg.min_inner = params->min_inner;
+  cfg.max_inner = params->max_inner;
+  cfg.batch = obj->batch;
+  cfg.rr_from = std::min(2, (int)params->max_inner);
+  cfg.eta = params->eta;
+  cfg.eps_scale = params->eps_scale;
+  cfg.eps_c = params->eps_c;
+  cfg.eps_pow = params->eps_pow;
+  cfg.inner_tol = params->inner_tol > 0 ? params->inner_tol : (c->esize == 8 ? 1e-10 : 1e-6);
+  cfg.unit_round = (c->esize == 8) ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
+  cfg.cert_tol = params->cert_tol;
+  if (obj->kind == MEG_GRAD_EXTERNAL || obj->kind == MEG_GRAD_BILINEAR) {
+    // the operator family is chosen per step; dense until then (bilinear: always
+    // the dense gradient the context forms)
+    c->external = true;
+    c->bilinear = obj->kind == MEG_GRAD_BILINEAR;
+    cfg.kind = LINEAR_DENSE;
+    if (c->bilinear) cfg.ld = cfg.n;
+  }
+
+  int coop = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) {
+    (void)hipGetLastError();
+    delete c;
+    return MEG_ERR_DEVICE;
+  }
+  c->P = dispatch<DoGrid>(c);
+  if (c->external) {  // a grid that both operator families can launch cooperatively
+    cfg.kind = LINEAR_CSR;
+    c->P = std::min(c->P, dispatch<DoGrid>(c));
+    cfg.kind = LINEAR_DENSE;
+  }
+  if (c->P < 1) {
+    delete c;
+    return MEG_ERR_DEVICE;
+  }
+  c->aux_nwg = std::max(1024, ceil_div(cfg.n, 4));
+  const size_t pe = std::max(dispatch<DoPartNeed>(c, c->P), (size_t)c->aux_nwg);
+  const size_t zbytes = (size_t)cfg.n * k * c->esize;
+  auto alloc = [&](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 256)) == hipSuccess; };
+  bool ok = alloc(&c->Qw, zbytes) && alloc(&c->Za, zbytes) && alloc(&c->Zb, zbytes) &&
+            alloc((void**)&c->ctl, sizeof(Ctl)) && alloc((void**)&c->part, pe * 8) &&
+            alloc((void**)&c->sums, 3 * KMAX * KMAX * 8) && alloc((void**)&c->bar, kBarWords * sizeof(unsigned)) &&
+            alloc((void**)&c->gpart, (size_t)kBarMaxGroups * 3 * KMAX * KMAX * 8) &&
+            alloc((void**)&c->ts, kTsSlots * sizeof(long long));
+  if (ok && obj->kind == MEG_GRAD_MASKED_CSR) ok = alloc(&c->g, (size_t)std::max<int64_t>(obj->nnz, 1) * c->esize);
+  if (ok && obj->kind == MEG_GRAD_QUADMEAS) ok = alloc(&c->quad, quad_layout(obj->batch, k, c->esize).bytes);
+  if (ok && c->bilinear) {
+    // slices of the measurements so that the partial-gradient grid has >= 1024 workgroups
+    const int64_t tiles = ceil_div(cfg.n, 32);
+    c->bil_S = (int)std::max<int64_t>(1, std::min<int64_t>({64, ceil_div(1024, tiles * tiles), ceil_div(obj->m, 16)}));
+    ok = alloc(&c->bil_G, (size_t)cfg.n * cfg.n * c->esize) && alloc((void**)&c->bil_res, (size_t)obj->m * 8) &&
+         alloc((void**)&c->bil_P, (size_t)c->bil_S * cfg.n * cfg.n * 8);
+  }
+  if (ok) ok = hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl)) == hipSuccess;
+  for (int i = 0; ok && i < meg_ctx_s::kEvRing; ++i)
+    ok = hipEventCreate(&c->ev_a[i]) == hipSuccess && hipEventCreate(&c->ev_b[i]) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    free_ctx(c);
+    return MEG_ERR_OUT_OF_MEMORY;
+  }
+  c->part_elems = pe;
+  if (hipMemsetAsync(c->bar, 0, kBarWords * sizeof(unsigned), c->stream) != hipSuccess ||
+      hipMemsetAsync(c->ctl, 0, sizeof(Ctl), c->stream) != hipSuccess ||
+      hipMemsetAsync(c->ts, 0, kTsSlots * sizeof(long long), c->stream) != hipSuccess) {
+    free_ctx(c);
+    return MEG_ERR_DEVICE;
+  }
+  // CSR structure check before any kernel reads through the indices
+  if (obj->kind == MEG_GRAD_LINEAR_CSR || obj->kind == MEG_GRAD_MASKED_CSR) {
+    int h_err = 0;
+    int* d_err = (int*)c->sums;
+    if (hipMemsetAsync(d_err, 0, sizeof(int), c->stream) != hipSuccess) {
+      free_ctx(c);
+      return MEG_ERR_DEVICE;
+    }
+    hipLaunchKernelGGL(k_check_csr, dim3((unsigned)std::min<int64_t>(1024, (cfg.n + 255) / 256)), dim3(256), 0,
+                       c->stream, obj->row_ptr, obj->col, cfg.n, cfg.nnz, d_err);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
+        hipMemcpy(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+      free_ctx(c);
+      return MEG_ERR_DEVICE;
+    }
+    if (h_err) {
+      free_ctx(c);
+      return MEG_ERR_INVALID_ARG;
+    }
+    (void)dispatch<DoCache>(c);  // per-workgroup LDS copy of the CSR data, when it fits
+  }
+  // minibatch index check before any kernel reads the pool through them
+  if (obj->kind == MEG_GRAD_QUADMEAS) {
+    int h_err = 0;
+    int* d_err = (int*)c->sums;
+    const int64_t cnt = obj->batch_steps * (int64_t)obj->batch;
+    if (hipMemsetAsync(d_err, 0, sizeof(int), c->stream) != hipSuccess) {
+      free_ctx(c);
+      return MEG_ERR_DEVICE;
+    }
+    hipLaunchKernelGGL(k_check_idx, dim3((unsigned)std::min<int64_t>(1024, (cnt + 255) / 256)), dim3(256), 0,
+                       c->stream, obj->batch_idx, cnt, obj->m, d_err);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
+        hipMemcpy(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+      free_ctx(c);
+      return MEG_ERR_DEVICE;
+    }
+    if (h_err) {
+      free_ctx(c);
+      return MEG_ERR_INVALID_ARG;
+    }
+  }
+  // data norm (sets ctl->data_norm) and the extreme eigenvalues of the data
+  // operator (shift of the subspace iteration); the factored gradient
+  // changes every step and bounds its spectrum inside the step instead
+  const bool has_data =
+      obj->kind != MEG_GRAD_QUADMEAS && obj->kind != MEG_GRAD_EXTERNAL && obj->kind != MEG_GRAD_BILINEAR;
+  if (has_data && (dispatch<DoNorm>(c) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)) {
+    free_ctx(c);
+    return MEG_ERR_DEVICE;
+  }
+  if (has_data) {
+    double lmin = 0.0, lmax = 0.0;
+    st = (c->esize == 8) ? lanczos_extremes<double>(c, &lmin, &lmax) : lanczos_extremes<float>(c, &lmin, &lmax);
+    if (st == MEG_OK) st = copy_ctl_to_host(c);
+    if (st != MEG_OK) {
+      free_ctx(c);
+      return st;
+    }
+    c->h_ctl->op_lmin = lmin;
+    c->h_ctl->op_lmax = lmax;
+    if (hipMemcpy(c->ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice) != hipSuccess) {
+      free_ctx(c);
+      return MEG_ERR_DEVICE;
+    }
+  }
+  // X_1 = (1 - eps_0) X_0 + (eps_0 / n) I: alpha = eps_0/n, d = (1 - eps_0) lambda_0
+  const double eps0 = cfg.eps_scale / std::pow(cfg.eps_c + 1.0, cfg.eps_pow);
+  std::vector<double> d(start->q);
+  for (int i = 0; i < start->q; ++i) d[i] = (1.0 - eps0) * start->lambda0[i];
+  st = upload_iterate(c, start->V0, start->q, d.data(), eps0 / (double)cfg.n, 1);
+  if (st != MEG_OK) {
+    free_ctx(c);
+    return st;
+  }
+  *out = c;
+  return MEG_OK;
+}
+
+meg_status meg_step(meg_ctx c, meg_step_info* info) {
+  meg_status st = check_ctx(c);
+  if (st != MEG_OK) return st;
+  if (c->bilinear) return bilinear_step(c, info);
+  if (c->external) return MEG_ERR_INVALID_ARG;
+  // f(X_t): the masked objective's gradient phase computes it in the step
+  if (info && c->cfg.kind != MASKED_CSR) HIPCHK(c, dispatch<DoObjective>(c));
+  HIPCHK(c, launch_steps(c, 1));
+  if (!info) return MEG_OK;
+  st = copy_ctl_to_host(c);
+  if (st == MEG_OK) st = check_barrier(c);
+  if (st != MEG_OK) return st;
+  fill_info(*c->h_ctl, info);
+  if (c->h_ctl->status) return (meg_status)c->h_ctl->status;
+  if ((c->params.flags & MEG_FLAG_STRICT) && !info->converged) return MEG_ERR_NOT_CONVERGED;
+  return MEG_OK;
+}
+
+meg_status meg_step_external(meg_ctx c, const meg_objective* grad, meg_step_info* info) {
+  meg_status st = check_ctx(c);
+  if (st != MEG_OK) return st;
+  if (!c->external || c->bilinear || !grad) return MEG_ERR_INVALID_ARG;
+  return external_step_core(c, grad, info);
+}
+
 meg_status meg_solve(meg_ctx c, int64_t max_iters, double tol, meg_step_info* last) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
-  if (c->external) return MEG_ERR_INVALID_ARG;
   if (max_iters < 0) return MEG_ERR_INVALID_ARG;
+  if (c->bilinear) {  // one step per iteration: each forms its own gradient first
+    meg_step_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    bool any = false;
+    for (int64_t i = 0; i < max_iters; ++i) {
+      st = bilinear_step(c, &inf);
+      if (st != MEG_OK) return st;
+      any = true;
+      if (tol > 0.0 && inf.cert_bound <= tol) break;
+    }
+    if (last) {
+      if (any) *last = inf;
+      else st = meg_certificate(c, last);
+    }
+    return st;
+  }
+  if (c->external) return MEG_ERR_INVALID_ARG;
   // arm the device-side stop rule
   st = copy_ctl_to_host(c);
   if (st != MEG_OK) return st;
@@ -1486,9 +1585,14 @@ meg_status meg_certificate(meg_ctx c, meg_step_info* out) {
 meg_status meg_objective_value(meg_ctx c, double* f) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
-  if (c->external) return MEG_ERR_UNSUPPORTED;  // f is the caller's
+  if (c->external && !c->bilinear) return MEG_ERR_UNSUPPORTED;  // f is the caller's
   if (!f) return MEG_ERR_INVALID_ARG;
-  HIPCHK(c, dispatch<DoObjective>(c));
+  if (c->bilinear) {
+    st = bilinear_prepare(c, false);
+    if (st != MEG_OK) return st;
+  } else {
+    HIPCHK(c, dispatch<DoObjective>(c));
+  }
   st = copy_ctl_to_host(c);
   if (st != MEG_OK) return st;
   *f = c->h_ctl->f;
@@ -1671,8 +1775,12 @@ meg_status meg_dual_gap(meg_ctx c, int32_t max_steps, double tol, meg_dual_gap_i
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
   if (!out || max_steps < 1 || !(tol >= 0.0)) return MEG_ERR_INVALID_ARG;
-  if (c->external || c->cfg.kind == QUADMEAS) return MEG_ERR_UNSUPPORTED;
+  if ((c->external && !c->bilinear) || c->cfg.kind == QUADMEAS) return MEG_ERR_UNSUPPORTED;
   std::memset(out, 0, sizeof(*out));
+  if (c->bilinear) {  // G at the current iterate, as the linear operator of the run
+    st = bilinear_prepare(c, true);
+    if (st != MEG_OK) return st;
+  }
   HIPCHK(c, dispatch<DoXdotG>(c));
   const int nwg = ceil_div(c->cfg.n, 4);
   std::vector<double> part(nwg);
@@ -1697,8 +1805,12 @@ meg_status meg_trace_exp(meg_ctx c, const double* probes, int32_t p, double weig
   if (st != MEG_OK) return st;
   if (!out || p < 0 || (p > 0 && !probes) || !(weight > 0.0) || max_steps < 1 || !(tol >= 0.0))
     return MEG_ERR_INVALID_ARG;
-  if (c->external || c->cfg.kind == QUADMEAS) return MEG_ERR_UNSUPPORTED;
+  if ((c->external && !c->bilinear) || c->cfg.kind == QUADMEAS) return MEG_ERR_UNSUPPORTED;
   std::memset(out, 0, sizeof(*out));
+  if (c->bilinear) {  // G at the current iterate: M_t = log X_t - eta G as for a linear objective
+    st = bilinear_prepare(c, true);
+    if (st != MEG_OK) return st;
+  }
   HIPCHK(c, dispatch<DoXdotG>(c));  // materialises the basis; masked: the gradient values
   st = copy_ctl_to_host(c);
   if (st != MEG_OK) return st;

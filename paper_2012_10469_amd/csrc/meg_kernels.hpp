@@ -1962,6 +1962,116 @@ static __global__ __launch_bounds__(256) void k_tr_scale(const double* __restric
     X[e] *= sc[e & 63];
 }
 
+// ---------------------------------------------------------------------------
+// Bilinear measurements f(X) = 1/2 sum_i (a_i^T X b_i - y_i)^2 (the recovery
+// problem of the experiments): residuals at the factored iterate, then the
+// dense symmetric gradient 1/2 sum_i r_i (a_i b_i^T + b_i a_i^T).
+// A holds 2m rows of length lda: a_1..a_m, then b_1..b_m.
+// ---------------------------------------------------------------------------
+// r_i = alpha a_i^T b_i + sum_{l < r} d_l (a_i^T v_l)(b_i^T v_l) - y_i with V the
+// first r columns of the basis k_materialize wrote (n x KB): one wave per
+// measurement, FP64 sums; part[blockIdx.x] = 1/2 sum of r_i^2 over the
+// workgroup's measurements.
+template <typename T, int KB>
+static __global__ __launch_bounds__(256) void k_bil_resid(Cfg cfg, const Ctl* __restrict__ ctl, const T* Z0,
+                                                          const T* Z1, const T* Z2, const T* __restrict__ A,
+                                                          int64_t lda, const T* __restrict__ y, int64_t m,
+                                                          double* __restrict__ res, double* __restrict__ part) {
+  const T* Q = zbuf(Z0, Z1, Z2, (ctl->src + 1) % 3);  // written by k_materialize
+  __shared__ double sred[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = cfg.r;
+  const int64_t n = cfg.n;
+  double fsum = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < m; i += (int64_t)gridDim.x * 4) {
+    const T* a = A + i * lda;
+    const T* b = A + (m + i) * lda;
+    double pa[KB], pb[KB], ab = 0.0;
+#pragma unroll
+    for (int l = 0; l < KB; ++l) pa[l] = pb[l] = 0.0;
+    for (int64_t j = lane; j < n; j += 64) {
+      const double aj = (double)a[j], bj = (double)b[j];
+      ab += aj * bj;
+      const T* q = Q + j * KB;
+#pragma unroll
+      for (int l = 0; l < KB; ++l) {
+        if (l < r) {
+          const double v = (double)q[l];
+          pa[l] += aj * v;
+          pb[l] += bj * v;
+        }
+      }
+    }
+    double s = ctl->alpha * wave_sum(ab);
+#pragma unroll
+    for (int l = 0; l < KB; ++l)
+      if (l < r) s += ctl->d[l] * wave_sum(pa[l]) * wave_sum(pb[l]);
+    const double ri = s - (double)y[i];
+    if (lane == 0) res[i] = ri;
+    fsum += 0.5 * ri * ri;
+  }
+  if (lane == 0) sred[wave] = fsum;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (sred[0] + sred[1]) + (sred[2] + sred[3]);
+}
+
+// Partial gradients: slice s = blockIdx.z of the measurements, output tile
+// (blockIdx.y, blockIdx.x) of 32 x 32: P_s[j][k] = sum_{i in slice s} r_i (a_ij b_ik + b_ij a_ik),
+// measurements staged 16 at a time in LDS (the J side scaled by r_i); a
+// thread holds one row j and four columns k.
+template <typename T>
+static __global__ __launch_bounds__(256) void k_bil_grad_part(int64_t n, const T* __restrict__ A, int64_t lda,
+                                                              int64_t m, const double* __restrict__ res,
+                                                              int64_t per_slice, double* __restrict__ P) {
+  __shared__ double aJ[16][33], bJ[16][33], aK[16][33], bK[16][33];
+  const int tid = threadIdx.x, tj = tid >> 3, tk = (tid & 7) * 4;
+  const int64_t j0 = (int64_t)blockIdx.y * 32, k0 = (int64_t)blockIdx.x * 32;
+  const int64_t i_beg = (int64_t)blockIdx.z * per_slice;
+  const int64_t i_end = min(m, i_beg + per_slice);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i0 = i_beg; i0 < i_end; i0 += 16) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int e = tid + 256 * s, ii = e >> 5, jj = e & 31;
+      const int64_t i = i0 + ii;
+      const bool ok = i < i_end;
+      const double ri = ok ? res[i] : 0.0;
+      const bool okj = ok && j0 + jj < n, okk = ok && k0 + jj < n;
+      aJ[ii][jj] = okj ? ri * (double)A[i * lda + j0 + jj] : 0.0;
+      bJ[ii][jj] = okj ? ri * (double)A[(m + i) * lda + j0 + jj] : 0.0;
+      aK[ii][jj] = okk ? (double)A[i * lda + k0 + jj] : 0.0;
+      bK[ii][jj] = okk ? (double)A[(m + i) * lda + k0 + jj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) {
+      const double xa = aJ[ii][tj], xb = bJ[ii][tj];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] += xa * bK[ii][tk + q] + xb * aK[ii][tk + q];
+    }
+    __syncthreads();
+  }
+  const int64_t j = j0 + tj;
+  if (j < n) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t k = k0 + tk + q;
+      if (k < n) P[((int64_t)blockIdx.z * n + j) * n + k] = acc[q];
+    }
+  }
+}
+
+// G[j][k] = 1/2 sum_{s < S} P_s[j][k] in slice order, in the state's type
+template <typename T>
+static __global__ __launch_bounds__(256) void k_bil_grad_sum(int64_t n, int S, const double* __restrict__ P,
+                                                             T* __restrict__ G) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n * n; e += (int64_t)gridDim.x * 256) {
+    double a = 0.0;
+    for (int s = 0; s < S; ++s) a += P[(int64_t)s * n * n + e];
+    G[e] = (T)(0.5 * a);
+  }
+}
+
 // CSR structure check: 0 = rp[0] <= rp[i] <= rp[i+1] <= rp[n] = nnz and every
 // column index in [0, n).  Row ranges are validated before col is read.
 // objective at X_t, quadratic measurements: 1/(2m) sum_i (a_i^T X a_i - b_i)^2

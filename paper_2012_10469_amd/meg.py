@@ -40,6 +40,7 @@ MEG_GRAD_LINEAR_CSR = 2
 MEG_GRAD_MASKED_CSR = 3
 MEG_GRAD_QUADMEAS = 4
 MEG_GRAD_EXTERNAL = 5
+MEG_GRAD_BILINEAR = 6
 
 MEG_FLAG_STRICT = 1
 MEG_FLAG_NO_LDS_CACHE = 2
@@ -297,14 +298,16 @@ class LowRankMEG:
         self.n, self.r = int(n), int(r)
         self.kind = kind
         # quadratic measurements: A is m x lda (row i = a_i), batch_idx int32
-        # batch_steps x L (step t uses row (t - 1) mod batch_steps)
+        # batch_steps x L (step t uses row (t - 1) mod batch_steps); bilinear
+        # measurements: A is 2m x lda (a_1..a_m, then b_1..b_m), b holds y
+        m = 0 if A is None else (int(A.shape[0]) // 2 if kind == MEG_GRAD_BILINEAR else int(A.shape[0]))
         obj = MegObjective(kind=kind, batch=int(batch_idx.shape[1]) if batch_idx is not None else 0,
                            dense=_dptr(dense), dense_lo=_dptr(dense_lo),
                            ld=int(dense.stride(0)) if dense is not None else 0,
                            row_ptr=_dptr(row_ptr), col=_dptr(col), val=_dptr(val),
                            nnz=int(col.numel()) if col is not None else 0,
                            A=_dptr(A), lda=int(A.stride(0)) if A is not None else 0, b=_dptr(b),
-                           m=int(A.shape[0]) if A is not None else 0, batch_idx=_dptr(batch_idx),
+                           m=m, batch_idx=_dptr(batch_idx),
                            batch_steps=int(batch_idx.shape[0]) if batch_idx is not None else 0)
         params = make_params(n, r, prec, eta, oversample, eps, min_inner, max_inner, inner_tol, seed, flags,
                              cert_tol)

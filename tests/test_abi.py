@@ -195,6 +195,24 @@ def test_init_rejects_bad_quadmeas(M):
     assert M.meg_init(p64, q(lda=65), V, lam)[0] == M.MEG_ERR_INVALID_ARG  # 65 doubles: rows not 16-byte aligned
 
 
+def test_init_validates_bilinear(M):
+    """Bilinear measurements: A (2m rows), y and m >= 1, lda >= n; not in the
+    bf16-plane form.  Validation runs before any device call."""
+    n = 64
+    p = M.make_params(n, 4)
+    V, lam = _start(n)
+
+    def q(**kw):
+        base = dict(kind=M.MEG_GRAD_BILINEAR, A=0x1000, lda=64, b=0x2000, m=100)
+        base.update(kw)
+        return M.MegObjective(**base)
+
+    for bad in (dict(A=None), dict(b=None), dict(m=0), dict(lda=60)):
+        assert M.meg_init(p, q(**bad), V, lam)[0] == M.MEG_ERR_INVALID_ARG, bad
+    p3 = M.make_params(n, 4, prec=M.MEG_PREC_F32_BF16X3)
+    assert M.meg_init(p3, q(), V, lam)[0] == M.MEG_ERR_UNSUPPORTED
+
+
 def test_server_null_handle_and_bad_params(M):
     """Server entry points reject a null handle and invalid parameters before
     touching the device."""

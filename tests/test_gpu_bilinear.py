@@ -1,0 +1,183 @@
+"""The recovery problem from quadratic measurements (Section 7) on the GPU:
+objective kind MEG_GRAD_BILINEAR, whose steps form the residuals and the dense
+symmetric gradient on the device.
+
+Parity: from the experiments' start, GPU steps against the FP64 oracle's
+(X within 1e-8 for an FP64 state and 1e-5 for FP32 after each step, f(X_t)
+within 1e-6 plus the rounding allowance).  The FP64 bar is looser than the
+1e-9 of the other kinds: the solver's shift comes from the Gershgorin bound of
+the dense gradient, several times lambda_max(G) for these random measurement
+sums, and the Ritz residuals resolve to about 3e-8 of the shifted scale, so
+the eigenvectors are accurate to that over the eigengap.  The dual gap and the trace of
+exp(M_t) of a bilinear context against the oracle at an oracle-built iterate.
+Then Table 1's experiment on the GPU: 20 instances per row, 200 iterations,
+the averages against the printed ones.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import meg_oracle as O
+from tests.helpers import TOL_X, f_tol, rel_x_err, torch_dtype
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_recovery.json")
+
+
+@pytest.fixture(scope="module")
+def meg():
+    from paper_2012_10469_amd import meg as m
+
+    m.load_library()
+    return m
+
+
+def print_case(**kw):
+    print("CASE " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def make_ctx(meg, p, r, prec, **kw):
+    import torch
+
+    dt = torch_dtype(prec)
+    A = torch.from_numpy(W.bilinear_rows(p, np.float64)).to(dt).cuda()
+    y = torch.from_numpy(p.y_unit).to(dt).cuda()
+    V0, lam0 = W.exp_init_bilinear(p, r)
+    kw.setdefault("max_inner", 40)
+    return meg.LowRankMEG(p.n, r, meg.MEG_GRAD_BILINEAR, V0, lam0, prec=prec, eta=p.eta_unit, A=A, b=y, **kw), V0, lam0
+
+
+def data_in(p, prec):
+    """The measurements as the device holds them (rounded to the state's type)."""
+    dt = np.float64 if prec == 0 else np.float32
+    A = p.A.astype(dt).astype(np.float64)
+    B = p.B.astype(dt).astype(np.float64)
+    y = p.y_unit.astype(dt).astype(np.float64)
+    return O.BilinearObjective(A, B, y)
+
+
+@pytest.mark.parametrize("prec,n,rank", [(0, 100, 1), (1, 100, 1), (1, 120, 5)])
+def test_bilinear_steps_match_the_oracle(meg, prec, n, rank):
+    print_case(test="bilinear_steps", prec=prec, n=n, rank=rank)
+    p = W.bilinear_recovery(n, rank, seed=40 + n + rank)
+    obj = data_in(p, prec)
+    g, V0, lam0 = make_ctx(meg, p, rank, prec, inner_tol=1e-12 if prec == 0 else 0.0)
+    try:
+        it = O.initial_iterate(V0, lam0, O.eps_schedule(0))
+        assert g.objective() == pytest.approx(obj.value(it.dense()), rel=1e-6 if prec else 1e-12)
+        for _ in range(6):
+            if prec == 0:  # FP64: each step from the oracle's iterate (teacher forcing)
+                g.set_iterate(it.V, it.d, it.alpha, it.t)
+            X = it.dense()
+            f_ref = obj.value(X)
+            Gr = obj.grad(X)
+            it, _ = O.lowrank_step(it, Gr, p.eta_unit, O.eps_schedule(it.t), rank, full=False)
+            info = g.step()
+            err = rel_x_err(g.get_iterate(), it)
+            ftol = f_tol(f_ref, float(np.linalg.norm(Gr)), float(np.linalg.norm(X)), prec)
+            print(f"  t={info['t']}: rel X err {err:.2e}, f {info['f']:.10e} / {f_ref:.10e}, sweeps "
+                  f"{info['inner_iters']}, sigma {info['sigma']:.3e}, gap {info['ritz_gap']:.3e}, cert_L "
+                  f"{info['cert_L']:.3e}", flush=True)
+            assert err <= (1e-8 if prec == 0 else TOL_X[prec])
+            assert abs(info["f"] - f_ref) <= ftol
+            assert info["converged"] == 1
+    finally:
+        g.close()
+
+
+def test_bilinear_dual_gap_and_trace(meg):
+    """At an oracle iterate (3 oracle steps, uploaded): the dual gap of the
+    context and tr exp(M_t) with canonical probes against the oracle."""
+    import torch
+
+    prec, n, rank = 0, 100, 2
+    print_case(test="bilinear_gap_trace", n=n)
+    p = W.bilinear_recovery(n, rank, seed=77)
+    obj = data_in(p, prec)
+    g, V0, lam0 = make_ctx(meg, p, rank, prec)
+    try:
+        it = O.initial_iterate(V0, lam0, O.eps_schedule(0))
+        for _ in range(3):
+            it, _ = O.lowrank_step(it, obj.grad(it.dense()), p.eta_unit, O.eps_schedule(it.t), rank, full=False)
+        g.set_iterate(it.V, it.d, it.alpha, it.t)
+        X = it.dense()
+        G = obj.grad(X)
+        ref = O.dual_gap(X, G)
+        dg = g.dual_gap(max_steps=100, tol=1e-12)
+        scale = abs(float(np.sum(X * G))) + float(np.abs(np.linalg.eigvalsh(G)).max())
+        print(f"  gap {dg['gap']:.12e} / {ref:.12e}", flush=True)
+        assert abs(dg["gap"] - ref) <= 1e-9 * scale
+        Mt = it.log_dense() - p.eta_unit * G
+        exact = O.logsumexp(np.linalg.eigvalsh(Mt))
+        tr, _ = g.trace_exp(torch.eye(n, dtype=torch.float64, device="cuda"), weight=1.0, max_steps=100,
+                            tol=1e-12)
+        print(f"  log b {tr['log_b']:.12f} / {exact:.12f}", flush=True)
+        assert abs(tr["log_b"] - exact) <= 1e-9
+        # the step after them still matches the oracle's
+        info = g.step()
+        nxt, _ = O.lowrank_step(it, G, p.eta_unit, O.eps_schedule(it.t), rank, full=False)
+        assert rel_x_err(g.get_iterate(), nxt) <= TOL_X[prec] and info["t"] == it.t
+    finally:
+        g.close()
+
+
+def table1_row(meg, rank, n, runs, prec=1):
+    """Table 1's quantities for `runs` instances (rows: recovery error, gap
+    lambda_{n-r} - lambda_n of grad f(X*), dual gap in the original scale, and
+    the first iteration whose all-eigenvalue certificate holds, from the exact
+    b_n of canonical probes, checked over the first 40 iterations)."""
+    import torch
+
+    out = []
+    for seed in range(runs):
+        p = W.bilinear_recovery(n, rank, seed)
+        g, V0, lam0 = make_ctx(meg, p, rank, prec)
+        try:
+            eye = torch.eye(n, dtype=torch.float64, device="cuda")
+            first = None
+            for t in range(200):
+                if first is None and t < 40:
+                    _, tr = g.trace_exp(eye, weight=1.0, max_steps=n, tol=1e-10)
+                    info = g.step()
+                    L, holds = g.certificate_full(tr)
+                    if holds:
+                        first = t + 1
+                else:
+                    g.step(info=False)
+            dg = g.dual_gap(max_steps=200, tol=1e-10)
+            V, d, a, _ = g.get_iterate()
+            Xs = p.tau * (a * np.eye(n) + (V * d) @ V.T)
+            rec = np.linalg.norm(n / p.tau * Xs - p.M) ** 2 / np.linalg.norm(p.M) ** 2
+            G = O.BilinearObjective(p.A, p.B, p.y).grad(Xs)
+            ev = np.linalg.eigvalsh(G)
+            out.append((rec, ev[rank] - ev[0], p.tau ** 2 * dg["gap"], first if first else 41))
+        finally:
+            g.close()
+    return np.array(out, dtype=float)
+
+
+@pytest.mark.parametrize("rank,n", [(1, 100), (1, 200), (5, 100), (5, 200), (20, 100)])
+def test_table1_on_the_gpu(meg, rank, n):
+    print_case(test="table1", rank=rank, n=n)
+    ref = next(r for r in json.load(open(GOLDEN))["rows"] if r["rank"] == rank and r["n"] == n)
+    rows = table1_row(meg, rank, n, runs=20)
+    rec, gap, dual, first = rows.mean(axis=0)
+    dual_med = float(np.median(rows[:, 2]))
+    print(f"  rank {rank} n {n}: recovery {rec:.4f} ({ref['rec_err']}), gap {gap:.4f} ({ref['grad_gap']}), "
+          f"dual gap mean {dual:.4f} median {dual_med:.4f} ({ref['dual_gap']}), first certified {first:.2f} "
+          f"({ref['first_cert']})", flush=True)
+    assert rec == pytest.approx(ref["rec_err"], rel=0.25)
+    assert gap == pytest.approx(ref["grad_gap"], rel=0.1)
+    # the median: an instance where the method stalls far from the optimum
+    # (rank 5, n = 100, seed 16: dual gap 393 in FP32 and FP64 alike) moves
+    # the mean by orders of magnitude
+    assert ref["dual_gap"] / 2 <= dual_med <= 2 * ref["dual_gap"]
+    if ref["first_cert"] == 1:
+        assert first <= 1.2
+    else:
+        assert first == pytest.approx(ref["first_cert"], rel=0.35)
