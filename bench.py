@@ -18,11 +18,17 @@ The same line carries a "serving" object: the batched server on a stream of
 plain-configuration instances (Poisson arrivals, then saturation), against
 the single-instance FP32 path on a sample (`--no-serving` skips it).
 
+A "recovery" object times the paper's own workload (Section 7's recovery
+problem from bilinear measurements, full gradients, FP32 state) at Table 1's
+largest rank-5 size, n = 600 (m = 60000 measurement pairs), against the FP64
+oracle on a sample of iterations (`--no-recovery` skips it).
+
 `--write-workload PATH` only writes the workload for the native driver
 paper_2012_10469_amd/meg_bench (used under rocprofv3) and exits;
 `--write-dense-workload PATH` writes the precision-form workload of the same
 driver (n = 16384, r = 16, M = W W^T/||W||_F^2 + 1e-3 symmetric noise split
-into bf16 planes, top-eigenvector start) and exits.
+into bf16 planes, top-eigenvector start) and exits; `--write-bilinear-workload
+PATH` writes the recovery workload (n = 600, rank 5) of the same driver.
 """
 from __future__ import annotations
 
@@ -44,7 +50,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # valid only for the kernel sources it was measured on.
 TRAFFIC = {"bytes_per_launch": 943.0e6, "iterations_per_launch": 64, "applies_per_iteration": 3.0,
            "fetch_bytes": 546.5e6, "write_bytes": 396.5e6, "fetch_factor": 2.0, "write_factor": 1.0,
-           "source_hash": "c807f897cbf6f920"}
+           "source_hash": "c27ef54f78b1874f"}
 KERNEL_SOURCES = ["meg_device.hpp", "meg_small.hpp", "meg_kernels.hpp", "meg_api.hip"]
 
 
@@ -134,6 +140,85 @@ def write_dense_workload(path: str, n: int = 16384, r: int = 16, seed: int = 1) 
         f.write(np.asfortranarray(V0, dtype="<f8").tobytes(order="F"))
         f.write(np.ascontiguousarray(prob.lam0, dtype="<f8").tobytes())
     log(f"[bench] dense workload n={n} written in {time.time() - t0:.1f}s")
+
+
+def write_bilinear_workload(path: str, n: int = 600, rank: int = 5, seed: int = 0) -> None:
+    """Recovery workload of the native driver: "MEGB0001", int64 n, int64 m,
+    int32 r, int32 q, double eta, float A[2m*n] (rows a_1..a_m, b_1..b_m),
+    float y[m] (y / tau), double V0[n*q] (column-major), double lambda0[q]."""
+    import numpy as np
+
+    import workloads as W
+
+    p = W.bilinear_recovery(n, rank, seed)
+    V0, lam0 = W.exp_init_bilinear(p, rank)
+    with open(path, "wb") as f:
+        f.write(b"MEGB0001")
+        f.write(np.array([n, p.m], dtype="<i8").tobytes())
+        f.write(np.array([rank, rank], dtype="<i4").tobytes())
+        f.write(np.array([p.eta_unit], dtype="<f8").tobytes())
+        f.write(np.ascontiguousarray(W.bilinear_rows(p, np.float32), dtype="<f4").tobytes())
+        f.write(np.ascontiguousarray(p.y_unit, dtype="<f4").tobytes())
+        f.write(np.asfortranarray(V0, dtype="<f8").tobytes(order="F"))
+        f.write(np.ascontiguousarray(lam0, dtype="<f8").tobytes())
+    log(f"[bench] bilinear workload n={n} m={p.m} written")
+
+
+def recovery_bench(meg, torch, steps: int = 50, cpu_samples: int = 2, n: int = 600, rank: int = 5, seed: int = 0):
+    """Section 7's recovery problem (bilinear measurements, full gradient) at
+    n = 600, rank 5 (m = 60000): GPU iterations/s over `steps` iterations after
+    5 warmup, the objective before and after, and the FP64 oracle's time per
+    iteration on `cpu_samples` iterations from the same start."""
+    import numpy as np
+
+    import workloads as W
+
+    p = W.bilinear_recovery(n, rank, seed)
+    V0, lam0 = W.exp_init_bilinear(p, rank)
+    A = torch.from_numpy(W.bilinear_rows(p, np.float32)).cuda()
+    y = torch.from_numpy(p.y_unit.astype(np.float32)).cuda()
+    g = meg.LowRankMEG(n, rank, meg.MEG_GRAD_BILINEAR, V0, lam0, prec=meg.MEG_PREC_F32, eta=p.eta_unit, A=A, b=y,
+                       max_inner=40)
+    try:
+        f0 = g.objective()
+        g.solve(5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = g.solve(steps)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        f1 = g.objective()
+        cnt = g.counters(reset=False)
+    finally:
+        g.close()
+    m = p.m
+    # the gradient pass: 4 n^2 m flops; both passes read the 2m measurement rows at least once each
+    flops = 4.0 * n * n * m + 4.0 * m * n * rank
+    nbytes = 2 * (2 * m * n * 4)
+    from oracle import meg_oracle as O
+
+    obj = O.BilinearObjective(p.A, p.B, p.y_unit)
+    it = O.initial_iterate(V0, lam0, O.eps_schedule(0))
+    c0 = time.perf_counter()
+    for _ in range(cpu_samples):
+        it, _ = O.lowrank_step(it, obj.grad(it.dense()), p.eta_unit, O.eps_schedule(it.t), rank, full=False)
+    cpu_s = (time.perf_counter() - c0) / cpu_samples
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    out = {"workload": "recovery_bilinear", "n": n, "rank": rank, "m": m, "dtype": "f32", "steps": steps,
+           "iter_per_s": steps / secs, "ms_per_iter": secs * 1e3 / steps,
+           "applies_per_iter": cnt["applies"] / max(cnt["iterations"], 1),
+           "objective_start": f0 * p.tau ** 2, "objective_end": f1 * p.tau ** 2, "t": last["t"],
+           "cert_L": last["cert_L"], "gradient_flops_per_iter": flops, "measurement_bytes_per_iter": nbytes,
+           "cpu_baseline": {"value": 1.0 / cpu_s, "unit": "iter/s", "cores": int(threads),
+                            "kind": "oracle", "sample": f"{cpu_samples} iterations from the same start"}}
+    log(f"[recovery] n={n} rank {rank} m={m}: {out['iter_per_s']:.1f} iter/s ({out['ms_per_iter']:.3f} ms), "
+        f"f {out['objective_start']:.4e} -> {out['objective_end']:.4e}; oracle {1.0 / cpu_s:.2f} iter/s")
+    return out
 
 
 def cpu_baseline(p, r: int, samples: int):
@@ -291,6 +376,7 @@ def main() -> int:
     ap.add_argument("--launch-steps", type=int, default=64,
                     help="iterations per launch of the persistent step kernel (1: one meg_step per iteration)")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving measurement")
+    ap.add_argument("--no-recovery", action="store_true", help="skip the recovery-problem measurement")
     ap.add_argument("--serve-count", type=int, default=2048)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-launch-steps", type=int, default=8)
@@ -299,7 +385,13 @@ def main() -> int:
                     help="write the workload file of the native driver and exit (no GPU use)")
     ap.add_argument("--write-dense-workload", default=None, metavar="PATH",
                     help="write the precision-form workload file of the native driver and exit (no GPU use)")
+    ap.add_argument("--write-bilinear-workload", default=None, metavar="PATH",
+                    help="write the recovery-problem workload file of the native driver and exit (no GPU use)")
     args = ap.parse_args()
+
+    if args.write_bilinear_workload:
+        write_bilinear_workload(args.write_bilinear_workload)
+        return 0
 
     if args.write_dense_workload:
         write_dense_workload(args.write_dense_workload, seed=args.seed)
@@ -434,6 +526,7 @@ def main() -> int:
         base = cpu_baseline(p, args.r, args.cpu_samples)
     g.close()
     serving = None if args.no_serving else serving_bench(meg, torch, args)
+    recovery = None if args.no_recovery else recovery_bench(meg, torch)
     # measured HBM bytes per launch (counter runs), only for the kernel they were taken on
     traffic, traffic_note = None, "kernel sources changed since the counter runs"
     if kernel_source_hash() == TRAFFIC["source_hash"] and args.launch_steps == TRAFFIC["iterations_per_launch"]:
@@ -469,6 +562,7 @@ def main() -> int:
         "trace_exp": tri,
         "cpu_baseline": base,
         "serving": serving,
+        "recovery": recovery,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -72,7 +72,7 @@ struct meg_ctx_s {
   bool bilinear = false;   // bilinear measurements: the context forms G_t itself (external step path)
   void* bil_G = nullptr;   // bilinear: dense symmetric gradient n x n (state type, ld n)
   double* bil_res = nullptr;  // bilinear: residuals r_i (m)
-  double* bil_P = nullptr;    // bilinear: per-slice partial gradients (bil_S x n x n)
+  double* bil_P = nullptr;    // bilinear: per-slice partial gradients (bil_S x tile pairs x 64 x 64)
   int bil_S = 1;
   bool failed = false;
 };
@@ -313,12 +313,13 @@ struct Launch {
                        (const T*)c->obj.b, m, c->bil_res, c->part);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, c->stream, c->ctl, c->part, rg, 0);
     if (grad) {
-      const int tiles = (int)ceil_div(n, 32);
+      const int tiles = (int)ceil_div(n, kBilTile), pairs = tiles * (tiles + 1) / 2;
       const int64_t per = ceil_div(ceil_div(m, c->bil_S), 16) * 16;
-      hipLaunchKernelGGL((k_bil_grad_part<T>), dim3(tiles, tiles, c->bil_S), dim3(256), 0, c->stream, n,
-                         (const T*)c->obj.A, c->obj.lda, m, (const double*)c->bil_res, per, c->bil_P);
-      const int sg = (int)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n * n, 256)));
-      hipLaunchKernelGGL((k_bil_grad_sum<T>), dim3(sg), dim3(256), 0, c->stream, n, c->bil_S,
+      hipLaunchKernelGGL((k_bil_grad_part<T>), dim3(pairs, 1, c->bil_S), dim3(256), 0, c->stream, n,
+                         (const T*)c->obj.A, c->obj.lda, m, (const double*)c->bil_res, per, tiles, c->bil_P);
+      const int64_t cells = (int64_t)pairs * kBilTile * kBilTile;
+      const int sg = (int)std::max<int64_t>(1, std::min<int64_t>(8192, ceil_div(cells, 256)));
+      hipLaunchKernelGGL((k_bil_grad_sum<T>), dim3(sg), dim3(256), 0, c->stream, n, c->bil_S, pairs, tiles,
                          (const double*)c->bil_P, (T*)c->bil_G);
     }
     return hipGetLastError();
@@ -1390,10 +1391,10 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
   if (ok && obj->kind == MEG_GRAD_QUADMEAS) ok = alloc(&c->quad, quad_layout(obj->batch, k, c->esize).bytes);
   if (ok && c->bilinear) {
     // slices of the measurements so that the partial-gradient grid has >= 1024 workgroups
-    const int64_t tiles = ceil_div(cfg.n, 32);
-    c->bil_S = (int)std::max<int64_t>(1, std::min<int64_t>({64, ceil_div(1024, tiles * tiles), ceil_div(obj->m, 16)}));
+    const int64_t tiles = ceil_div(cfg.n, kBilTile), pairs = tiles * (tiles + 1) / 2;
+    c->bil_S = (int)std::max<int64_t>(1, std::min<int64_t>({64, ceil_div(1024, pairs), ceil_div(obj->m, 16)}));
     ok = alloc(&c->bil_G, (size_t)cfg.n * cfg.n * c->esize) && alloc((void**)&c->bil_res, (size_t)obj->m * 8) &&
-         alloc((void**)&c->bil_P, (size_t)c->bil_S * cfg.n * cfg.n * 8);
+         alloc((void**)&c->bil_P, (size_t)c->bil_S * pairs * kBilTile * kBilTile * 8);
   }
   if (ok) ok = hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl)) == hipSuccess;
   for (int i = 0; ok && i < meg_ctx_s::kEvRing; ++i)

@@ -16,7 +16,10 @@
 //   "MEGW0001", int64 n, int64 nnz, int32 r, int32 q, int32 row_ptr[n+1],
 //   int32 col[nnz], float val[nnz], double V0[n*q] (column-major), double lambda0[q];
 //   "MEGD0001", int64 n, int64 ld, int32 r, int32 q, uint16 hi[n*ld],
-//   uint16 lo[n*ld], double V0[n*q] (column-major), double lambda0[q].
+//   uint16 lo[n*ld], double V0[n*q] (column-major), double lambda0[q];
+//   "MEGB0001", int64 n, int64 m, int32 r, int32 q, double eta, float A[2m*n]
+//   (rows a_1..a_m, b_1..b_m), float y[m], double V0[n*q], double lambda0[q]
+//   (the recovery problem of the experiments: bilinear measurements, FP32 state).
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -34,6 +37,9 @@ namespace {
 
 struct Workload {
   bool dense = false;
+  bool bilinear = false;
+  double eta = 1.0;
+  std::vector<float> A, y;
   int64_t n = 0, nnz = 0, ld = 0;
   int32_t r = 0, q = 0;
   std::vector<int32_t> row_ptr, col;
@@ -50,6 +56,25 @@ bool load(const char* path, Workload& w) {
   char magic[8];
   bool ok = read_all(f, magic, 8);
   w.dense = ok && std::memcmp(magic, "MEGD0001", 8) == 0;
+  w.bilinear = ok && std::memcmp(magic, "MEGB0001", 8) == 0;
+  if (w.bilinear) {  // n, m (kept in nnz), r, q, eta, A, y
+    ok = read_all(f, &w.n, 8) && read_all(f, &w.nnz, 8) && read_all(f, &w.r, 4) && read_all(f, &w.q, 4) &&
+         read_all(f, &w.eta, 8);
+    ok = ok && w.n > 0 && w.n < (int64_t)1 << 20 && w.nnz >= 1 && w.nnz < (int64_t)1 << 28 && w.r >= 1 &&
+         w.q >= 1 && w.q <= w.r && w.eta > 0.0;
+    if (ok) {
+      w.A.resize((size_t)2 * w.nnz * w.n);
+      w.y.resize(w.nnz);
+      ok = read_all(f, w.A.data(), w.A.size() * 4) && read_all(f, w.y.data(), w.y.size() * 4);
+    }
+    if (ok) {
+      w.V0.resize((size_t)w.n * w.q);
+      w.lam0.resize(w.q);
+      ok = read_all(f, w.V0.data(), w.V0.size() * 8) && read_all(f, w.lam0.data(), w.lam0.size() * 8);
+    }
+    std::fclose(f);
+    return ok;
+  }
   ok = ok && (w.dense || std::memcmp(magic, "MEGW0001", 8) == 0) && read_all(f, &w.n, 8) &&
        read_all(f, w.dense ? &w.ld : &w.nnz, 8) && read_all(f, &w.r, 4) && read_all(f, &w.q, 4);
   ok = ok && w.n > 0 && w.nnz >= 0 && w.r >= 1 && w.q >= 1 && w.q <= w.r && w.n < (int64_t)1 << 31 &&
@@ -114,7 +139,7 @@ int main(int argc, char** argv) {
 
   Workload w;
   if (!load(argv[1], w)) return fail("cannot read workload file", 2);
-  std::fprintf(stderr, "[meg_bench] %s n=%lld nnz=%lld ld=%lld r=%d q=%d\n", w.dense ? "dense bf16 planes" : "csr",
+  std::fprintf(stderr, "[meg_bench] %s n=%lld nnz=%lld ld=%lld r=%d q=%d\n", w.bilinear ? "bilinear measurements (nnz = m)" : (w.dense ? "dense bf16 planes" : "csr"),
                (long long)w.n, (long long)w.nnz, (long long)w.ld, w.r, w.q);
 
   int32_t* d_rp = nullptr;
@@ -122,7 +147,14 @@ int main(int argc, char** argv) {
   float* d_val = nullptr;
   uint16_t* d_hi = nullptr;
   uint16_t* d_lo = nullptr;
-  if (w.dense) {
+  float* d_A = nullptr;
+  float* d_y = nullptr;
+  if (w.bilinear) {
+    d_A = to_device(w.A);
+    d_y = to_device(w.y);
+    if (!d_A || !d_y) return fail("device allocation or copy failed", 3);
+    std::vector<float>().swap(w.A);
+  } else if (w.dense) {
     d_hi = to_device(w.hi);
     d_lo = to_device(w.lo);
     if (!d_hi || !d_lo) return fail("device allocation or copy failed", 3);
@@ -145,14 +177,20 @@ int main(int argc, char** argv) {
   p.prec = w.dense ? MEG_PREC_F32_BF16X3 : MEG_PREC_F32;
   p.min_inner = 1;
   p.max_inner = max_inner;
-  p.eta = 1.0;
+  p.eta = w.bilinear ? w.eta : 1.0;
   p.eps_scale = 0.8;
   p.eps_c = 10.0;
   p.eps_pow = 2.0;
   p.seed = 0;
   meg_objective o;
   std::memset(&o, 0, sizeof(o));
-  if (w.dense) {
+  if (w.bilinear) {
+    o.kind = MEG_GRAD_BILINEAR;
+    o.A = d_A;
+    o.lda = w.n;
+    o.b = d_y;
+    o.m = w.nnz;
+  } else if (w.dense) {
     o.kind = MEG_GRAD_DENOISE_DENSE;
     o.dense = d_hi;
     o.dense_lo = d_lo;
@@ -224,7 +262,7 @@ int main(int argc, char** argv) {
       "\"kernel_ms\": %.6f, \"avg_launch_us\": %.3f, \"wall_ms_per_step\": %.6f, \"iter_per_s\": %.3f, "
       "\"t\": %lld, \"cert_L\": %.6e, \"eps_t\": %.6e, \"trace_probes\": %d, \"trace_log_b\": %.10e, "
       "\"trace_steps\": %d, \"trace_ms_per_call\": %.4f}\n",
-      w.dense ? "denoise_bf16x3" : "matrix_completion_csr", (long long)w.n, (long long)w.nnz, w.r, (long long)steps, (long long)launch, (long long)c.launches,
+      w.bilinear ? "recovery_bilinear" : (w.dense ? "denoise_bf16x3" : "matrix_completion_csr"), (long long)w.n, (long long)w.nnz, w.r, (long long)steps, (long long)launch, (long long)c.launches,
       (long long)c.iterations, (long long)c.applies, c.workgroups, c.kernel_ms,
       c.launches ? 1e3 * c.kernel_ms / (double)c.launches : 0.0, wall_ms / (double)steps,
       1e3 * (double)steps / wall_ms, (long long)info.t, info.cert_L, info.eps_t, trace_p, tr.log_b, tr.steps,
@@ -232,7 +270,7 @@ int main(int argc, char** argv) {
   std::fflush(stdout);
   meg_destroy(ctx);
   (void)hipStreamDestroy(stream);
-  for (void* q : {(void*)d_rp, (void*)d_col, (void*)d_val, (void*)d_hi, (void*)d_lo})
+  for (void* q : {(void*)d_rp, (void*)d_col, (void*)d_val, (void*)d_hi, (void*)d_lo, (void*)d_A, (void*)d_y})
     if (q) (void)hipFree(q);
   return 0;
 }

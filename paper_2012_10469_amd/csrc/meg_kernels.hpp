@@ -2015,24 +2015,43 @@ static __global__ __launch_bounds__(256) void k_bil_resid(Cfg cfg, const Ctl* __
   if (threadIdx.x == 0) part[blockIdx.x] = (sred[0] + sred[1]) + (sred[2] + sred[3]);
 }
 
-// Partial gradients: slice s = blockIdx.z of the measurements, output tile
-// (blockIdx.y, blockIdx.x) of 32 x 32: P_s[j][k] = sum_{i in slice s} r_i (a_ij b_ik + b_ij a_ik),
-// measurements staged 16 at a time in LDS (the J side scaled by r_i); a
-// thread holds one row j and four columns k.
+// Partial gradients over the upper triangle of 64 x 64 tiles: workgroup x
+// takes the tile pair (J, K), J <= K, of its index, slice s = blockIdx.z of
+// the measurements; P_s[J,K][jl][kl] = sum_{i in slice s} r_i (a_ij b_ik + b_ij a_ik)
+// with j = 64 J + jl, k = 64 K + kl.  Measurements are staged 16 at a time in
+// LDS (the J side scaled by r_i); a thread holds a 4 x 4 block of the tile.
+constexpr int kBilTile = 64;
+
+__device__ inline void bil_pair(int pair, int T, int& J, int& K) {
+  J = 0;
+  while (pair >= T - J) {
+    pair -= T - J;
+    ++J;
+  }
+  K = J + pair;
+}
+
 template <typename T>
 static __global__ __launch_bounds__(256) void k_bil_grad_part(int64_t n, const T* __restrict__ A, int64_t lda,
                                                               int64_t m, const double* __restrict__ res,
-                                                              int64_t per_slice, double* __restrict__ P) {
-  __shared__ double aJ[16][33], bJ[16][33], aK[16][33], bK[16][33];
-  const int tid = threadIdx.x, tj = tid >> 3, tk = (tid & 7) * 4;
-  const int64_t j0 = (int64_t)blockIdx.y * 32, k0 = (int64_t)blockIdx.x * 32;
+                                                              int64_t per_slice, int tiles,
+                                                              double* __restrict__ P) {
+  __shared__ double aJ[16][kBilTile], bJ[16][kBilTile], aK[16][kBilTile], bK[16][kBilTile];
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  int J, K;
+  bil_pair(blockIdx.x, tiles, J, K);
+  const int64_t j0 = (int64_t)J * kBilTile, k0 = (int64_t)K * kBilTile;
   const int64_t i_beg = (int64_t)blockIdx.z * per_slice;
   const int64_t i_end = min(m, i_beg + per_slice);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
   for (int64_t i0 = i_beg; i0 < i_end; i0 += 16) {
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int e = tid + 256 * s, ii = e >> 5, jj = e & 31;
+    for (int s = 0; s < 4; ++s) {
+      const int e = tid + 256 * s, ii = e >> 6, jj = e & 63;
       const int64_t i = i0 + ii;
       const bool ok = i < i_end;
       const double ri = ok ? res[i] : 0.0;
@@ -2043,32 +2062,50 @@ static __global__ __launch_bounds__(256) void k_bil_grad_part(int64_t n, const T
       bK[ii][jj] = okk ? (double)A[(m + i) * lda + k0 + jj] : 0.0;
     }
     __syncthreads();
-#pragma unroll
+#pragma unroll 4
     for (int ii = 0; ii < 16; ++ii) {
-      const double xa = aJ[ii][tj], xb = bJ[ii][tj];
+      double xa[4], xb[4], ya[4], yb[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] += xa * bK[ii][tk + q] + xb * aK[ii][tk + q];
+      for (int q = 0; q < 4; ++q) {
+        xa[q] = aJ[ii][ty * 4 + q];
+        xb[q] = bJ[ii][ty * 4 + q];
+        ya[q] = aK[ii][tx * 4 + q];
+        yb[q] = bK[ii][tx * 4 + q];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] += xa[a] * yb[b] + xb[a] * ya[b];
     }
     __syncthreads();
   }
-  const int64_t j = j0 + tj;
-  if (j < n) {
+  double* dst = P + ((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * (kBilTile * kBilTile);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t k = k0 + tk + q;
-      if (k < n) P[((int64_t)blockIdx.z * n + j) * n + k] = acc[q];
-    }
-  }
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) dst[(ty * 4 + a) * kBilTile + tx * 4 + b] = acc[a][b];
 }
 
-// G[j][k] = 1/2 sum_{s < S} P_s[j][k] in slice order, in the state's type
+// G[j][k] = G[k][j] = 1/2 sum_{s < S} P_s[J,K][jl][kl] in slice order, in the
+// state's type; diagonal tiles take their upper triangle, so G is exactly
+// symmetric
 template <typename T>
-static __global__ __launch_bounds__(256) void k_bil_grad_sum(int64_t n, int S, const double* __restrict__ P,
-                                                             T* __restrict__ G) {
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n * n; e += (int64_t)gridDim.x * 256) {
+static __global__ __launch_bounds__(256) void k_bil_grad_sum(int64_t n, int S, int pairs, int tiles,
+                                                             const double* __restrict__ P, T* __restrict__ G) {
+  const int64_t per = (int64_t)kBilTile * kBilTile;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < (int64_t)pairs * per;
+       e += (int64_t)gridDim.x * 256) {
+    const int pair = (int)(e / per);
+    const int w = (int)(e % per), jl = w / kBilTile, kl = w % kBilTile;
+    int J, K;
+    bil_pair(pair, tiles, J, K);
+    const int64_t j = (int64_t)J * kBilTile + jl, k = (int64_t)K * kBilTile + kl;
+    if (j >= n || k >= n || (J == K && jl > kl)) continue;
     double a = 0.0;
-    for (int s = 0; s < S; ++s) a += P[(int64_t)s * n * n + e];
-    G[e] = (T)(0.5 * a);
+    for (int s = 0; s < S; ++s) a += P[((int64_t)s * pairs + pair) * per + w];
+    const T v = (T)(0.5 * a);
+    G[j * n + k] = v;
+    G[k * n + j] = v;
   }
 }
 
