@@ -192,8 +192,9 @@ def recovery_bench(meg, torch, steps: int = 50, cpu_samples: int = 2, n: int = 6
     finally:
         g.close()
     m = p.m
-    # the gradient pass: 4 n^2 m flops; both passes read the 2m measurement rows at least once each
-    flops = 4.0 * n * n * m + 4.0 * m * n * rank
+    # the gradient's n(n+1)/2 distinct entries take 4m flops each, the residuals 4 n rank flops per
+    # measurement; both passes read the 2m measurement rows at least once
+    flops = 2.0 * n * (n + 1) * m + 4.0 * m * n * rank
     nbytes = 2 * (2 * m * n * 4)
     from oracle import meg_oracle as O
 

@@ -161,7 +161,8 @@ def table1_row(meg, rank, n, runs, prec=1):
     return np.array(out, dtype=float)
 
 
-@pytest.mark.parametrize("rank,n", [(1, 100), (1, 200), (5, 100), (5, 200), (20, 100)])
+@pytest.mark.parametrize("rank,n", [(1, 100), (1, 200), (1, 400), (1, 600), (5, 100), (5, 200), (5, 400),
+                                    (20, 100), (20, 200)])
 def test_table1_on_the_gpu(meg, rank, n):
     print_case(test="table1", rank=rank, n=n)
     ref = next(r for r in json.load(open(GOLDEN))["rows"] if r["rank"] == rank and r["n"] == n)
