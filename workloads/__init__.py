@@ -464,12 +464,17 @@ class BilinearProblem:
         return self.tau / self.beta
 
 
-def bilinear_recovery(n: int, rank: int, seed: int, kappa: float = 0.5) -> BilinearProblem:
+def bilinear_recovery(n: int, rank: int, seed: int, kappa: float = 0.5, r: Optional[int] = None,
+                      m_rank: Optional[int] = None) -> BilinearProblem:
+    """``r``: the rank parameter when it exceeds rank(M) (the start's block U
+    has r columns; Table 2); ``m_rank``: the rank in m = 20 n m_rank
+    (default rank(M))."""
+    r = rank if r is None else r
     g = rng(11, seed, n, rank)
     W_ = g.standard_normal((n, rank))
     W_ /= np.linalg.norm(W_)
     M = n * (W_ @ W_.T)
-    m = 20 * n * rank
+    m = 20 * n * (rank if m_rank is None else m_rank)
     A = g.standard_normal((m, n))
     A /= np.linalg.norm(A, axis=1, keepdims=True)
     B = g.standard_normal((m, n))
@@ -479,9 +484,9 @@ def bilinear_recovery(n: int, rank: int, seed: int, kappa: float = 0.5) -> Bilin
     v /= np.linalg.norm(v)
     y = y0 + kappa * np.linalg.norm(y0) * v
     tau = (0.65 if rank >= 20 else 0.5) * float(np.trace(M))
-    U = g.standard_normal((n, rank))
+    U = g.standard_normal((n, r))
     U /= np.linalg.norm(U)
-    return BilinearProblem(n, rank, A, B, y, M, tau, 0.4 * math.sqrt(rank * n), U)
+    return BilinearProblem(n, rank, A, B, y, M, tau, 0.4 * math.sqrt(r * n), U)
 
 
 def exp_init_bilinear(p: BilinearProblem, r: int):
