@@ -77,11 +77,12 @@ typedef enum {
   MEG_GRAD_EXTERNAL = 5,      /* the caller supplies the gradient (or an
                                  unbiased estimate of it, Section 6) at X_t
                                  for every step: meg_step_external         */
-  MEG_GRAD_BILINEAR = 6       /* f = 1/2 sum_i (a_i^T X b_i - y_i)^2, the
-                                 recovery problem of Section 7, with its full
-                                 gradient (symmetric part, Section 1)
-                                 1/2 sum_i r_i (a_i b_i^T + b_i a_i^T),
-                                 r_i = a_i^T X b_i - y_i                       */
+  MEG_GRAD_BILINEAR = 6       /* f = 1/2 sum_i (tr(A_i^T X B_i) - y_i)^2, the
+                                 recovery problem of Section 7 (A_i = a_i,
+                                 B_i = b_i for rank-1 measurements), with its
+                                 full gradient (symmetric part, Section 1)
+                                 1/2 sum_i r_i (A_i B_i^T + B_i A_i^T),
+                                 r_i = tr(A_i^T X B_i) - y_i                   */
 } meg_grad_kind;
 
 #define MEG_FLAG_STRICT 1u   /* inner non-convergence -> MEG_ERR_NOT_CONVERGED */
@@ -138,8 +139,10 @@ typedef struct {
    * reproducible.  F64 and F32 only (the bf16-plane form is dense-only).
    * Each step also forms the batch x batch Gram matrix of its minibatch to
    * bound the spectrum of the gradient estimate (the solver's shift). */
-  /* BILINEAR: DEVICE A holds 2m rows of length lda >= n in the state's type
-   * (F64 or F32): a_1..a_m, then b_1..b_m; b holds y[m].  Every step forms
+  /* BILINEAR: measurements tr(A_i^T X B_i) with A_i, B_i n x p (p = `batch`,
+   * 0 or 1 for a_i^T X b_i; at most 4096).  DEVICE A holds 2mp rows of length
+   * lda >= n in the state's type (F64 or F32): row i p + q is column q of A_i,
+   * row m p + i p + q column q of B_i; b holds y[m].  Every step forms
    * the residuals and the dense symmetric gradient (n x n, owned by the
    * context) on the device, then takes the step as meg_step_external would
    * with it.  The trace bound of Section 7 is 1: for tr X = tau pass y / tau

@@ -440,23 +440,28 @@ def run_lowrank_meg(obj, V0, lam0, r: int, eta: float, T: int, eps_params=(0.8, 
 
 
 class BilinearObjective:
-    """f(X) = 1/2 sum_i (a_i^T X b_i - y_i)^2, the recovery problem from
-    quadratic measurements of Section 7 (full, deterministic gradients).
+    """f(X) = 1/2 sum_i (tr(A_i^T X B_i) - y_i)^2, the recovery problem of
+    Section 7 (full, deterministic gradients): rank-1 measurements a_i^T X b_i
+    (A, B: m x n, rows a_i, b_i), or measurement matrices A_i, B_i with p
+    columns (A, B: m x p x n, A[i, q] the q-th column of A_i).
 
-    grad f = sum_i r_i a_i b_i^T with r_i = a_i^T X b_i - y_i; the method uses
-    its symmetric part (Section 1), 1/2 sum_i r_i (a_i b_i^T + b_i a_i^T).
-    A, B: m x n, rows a_i and b_i."""
+    grad f = sum_i r_i A_i B_i^T with r_i = tr(A_i^T X B_i) - y_i; the method
+    uses its symmetric part (Section 1), 1/2 sum_i r_i (A_i B_i^T + B_i A_i^T)."""
 
     def __init__(self, A: np.ndarray, B: np.ndarray, y: np.ndarray):
-        self.A = np.asarray(A, dtype=np.float64)
-        self.B = np.asarray(B, dtype=np.float64)
+        A = np.asarray(A, dtype=np.float64)
+        B = np.asarray(B, dtype=np.float64)
+        self.p = 1 if A.ndim == 2 else A.shape[1]
+        self.A = A.reshape(-1, A.shape[-1])  # (m p) x n, rows grouped by measurement
+        self.B = B.reshape(-1, B.shape[-1])
         self.y = np.asarray(y, dtype=np.float64)
 
     def residuals(self, X: np.ndarray) -> np.ndarray:
-        return np.sum((self.A @ X) * self.B, axis=1) - self.y
+        t = np.sum((self.A @ X) * self.B, axis=1)
+        return t.reshape(-1, self.p).sum(axis=1) - self.y
 
     def grad(self, X: np.ndarray) -> np.ndarray:
-        r = self.residuals(X)
+        r = np.repeat(self.residuals(X), self.p)
         H = self.A.T @ (r[:, None] * self.B)
         return 0.5 * (H + H.T)
 

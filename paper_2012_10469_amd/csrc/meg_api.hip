@@ -304,19 +304,21 @@ struct Launch {
   static hipError_t bilinear(meg_ctx c, bool grad) {
     const Cfg& cfg = c->cfg;
     const int64_t n = cfg.n, m = c->obj.m;
+    const int p = std::max(1, (int)c->obj.batch);  // columns per measurement matrix
     const int mwg = (int)std::min<int64_t>(4096, ceil_div(n * KB, 256));
     hipLaunchKernelGGL((k_materialize<T, KB>), dim3(mwg), dim3(256), 0, c->stream, cfg, c->ctl, (T*)c->Qw, (T*)c->Za,
                        (T*)c->Zb);
     const int rg = (int)std::min<int64_t>(1024, ceil_div(m, 4));
     hipLaunchKernelGGL((k_bil_resid<T, KB>), dim3(rg), dim3(256), 0, c->stream, cfg, (const Ctl*)c->ctl,
                        (const T*)c->Qw, (const T*)c->Za, (const T*)c->Zb, (const T*)c->obj.A, c->obj.lda,
-                       (const T*)c->obj.b, m, c->bil_res, c->part);
+                       (const T*)c->obj.b, m, p, c->bil_res, c->part);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, c->stream, c->ctl, c->part, rg, 0);
     if (grad) {
       const int tiles = (int)ceil_div(n, kBilTile), pairs = tiles * (tiles + 1) / 2;
-      const int64_t per = ceil_div(ceil_div(m, c->bil_S), 16) * 16;
+      const int64_t rows = m * p;
+      const int64_t per = ceil_div(ceil_div(rows, c->bil_S), 16) * 16;
       hipLaunchKernelGGL((k_bil_grad_part<T>), dim3(pairs, 1, c->bil_S), dim3(256), 0, c->stream, n,
-                         (const T*)c->obj.A, c->obj.lda, m, (const double*)c->bil_res, per, tiles, c->bil_P);
+                         (const T*)c->obj.A, c->obj.lda, rows, p, (const double*)c->bil_res, per, tiles, c->bil_P);
       const int64_t cells = (int64_t)pairs * kBilTile * kBilTile;
       const int sg = (int)std::max<int64_t>(1, std::min<int64_t>(8192, ceil_div(cells, 256)));
       hipLaunchKernelGGL((k_bil_grad_sum<T>), dim3(sg), dim3(256), 0, c->stream, n, c->bil_S, pairs, tiles,
@@ -1144,8 +1146,8 @@ meg_status validate(const meg_params* p, const meg_objective* o, const meg_start
       if (p->prec == MEG_PREC_F32_BF16X3) return MEG_ERR_UNSUPPORTED;
       break;
     case MEG_GRAD_BILINEAR:
-      if (!o->A || !o->b || o->m < 1 || o->lda < p->n) return MEG_ERR_INVALID_ARG;
-      if (o->m > (int64_t)1 << 40 || o->lda > (int64_t)1 << 40) return MEG_ERR_INVALID_ARG;
+      if (!o->A || !o->b || o->m < 1 || o->lda < p->n || o->batch < 0 || o->batch > 4096) return MEG_ERR_INVALID_ARG;
+      if (o->m > (int64_t)1 << 36 || o->lda > (int64_t)1 << 40) return MEG_ERR_INVALID_ARG;
       if (p->prec == MEG_PREC_F32_BF16X3) return MEG_ERR_UNSUPPORTED;
       break;
     case MEG_GRAD_QUADMEAS: {
@@ -1392,7 +1394,8 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
   if (ok && c->bilinear) {
     // slices of the measurements so that the partial-gradient grid has >= 1024 workgroups
     const int64_t tiles = ceil_div(cfg.n, kBilTile), pairs = tiles * (tiles + 1) / 2;
-    c->bil_S = (int)std::max<int64_t>(1, std::min<int64_t>({64, ceil_div(1024, pairs), ceil_div(obj->m, 16)}));
+    const int64_t rows = obj->m * std::max(1, (int)obj->batch);
+    c->bil_S = (int)std::max<int64_t>(1, std::min<int64_t>({64, ceil_div(1024, pairs), ceil_div(rows, 16)}));
     ok = alloc(&c->bil_G, (size_t)cfg.n * cfg.n * c->esize) && alloc((void**)&c->bil_res, (size_t)obj->m * 8) &&
          alloc((void**)&c->bil_P, (size_t)c->bil_S * pairs * kBilTile * kBilTile * 8);
   }

@@ -1963,19 +1963,20 @@ static __global__ __launch_bounds__(256) void k_tr_scale(const double* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Bilinear measurements f(X) = 1/2 sum_i (a_i^T X b_i - y_i)^2 (the recovery
-// problem of the experiments): residuals at the factored iterate, then the
-// dense symmetric gradient 1/2 sum_i r_i (a_i b_i^T + b_i a_i^T).
-// A holds 2m rows of length lda: a_1..a_m, then b_1..b_m.
+// Bilinear measurements f(X) = 1/2 sum_i (tr(A_i^T X B_i) - y_i)^2 (the
+// recovery problem of the experiments; rank-1 measurements a_i^T X b_i for
+// p = 1): residuals at the factored iterate, then the dense symmetric gradient
+// 1/2 sum_i r_i (A_i B_i^T + B_i A_i^T).  A holds 2mp rows of length lda: row
+// i p + q is column q of A_i, row m p + i p + q column q of B_i.
 // ---------------------------------------------------------------------------
-// r_i = alpha a_i^T b_i + sum_{l < r} d_l (a_i^T v_l)(b_i^T v_l) - y_i with V the
+// r_i = sum_q [alpha a_iq^T b_iq + sum_{l < r} d_l (a_iq^T v_l)(b_iq^T v_l)] - y_i with V the
 // first r columns of the basis k_materialize wrote (n x KB): one wave per
 // measurement, FP64 sums; part[blockIdx.x] = 1/2 sum of r_i^2 over the
 // workgroup's measurements.
 template <typename T, int KB>
 static __global__ __launch_bounds__(256) void k_bil_resid(Cfg cfg, const Ctl* __restrict__ ctl, const T* Z0,
                                                           const T* Z1, const T* Z2, const T* __restrict__ A,
-                                                          int64_t lda, const T* __restrict__ y, int64_t m,
+                                                          int64_t lda, const T* __restrict__ y, int64_t m, int p,
                                                           double* __restrict__ res, double* __restrict__ part) {
   const T* Q = zbuf(Z0, Z1, Z2, (ctl->src + 1) % 3);  // written by k_materialize
   __shared__ double sred[4];
@@ -1983,29 +1984,33 @@ static __global__ __launch_bounds__(256) void k_bil_resid(Cfg cfg, const Ctl* __
   const int r = cfg.r;
   const int64_t n = cfg.n;
   double fsum = 0.0;
+  const int64_t mp = m * p;
   for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < m; i += (int64_t)gridDim.x * 4) {
-    const T* a = A + i * lda;
-    const T* b = A + (m + i) * lda;
-    double pa[KB], pb[KB], ab = 0.0;
+    double s = 0.0;
+    for (int qc = 0; qc < p; ++qc) {
+      const T* a = A + (i * p + qc) * lda;
+      const T* b = A + (mp + i * p + qc) * lda;
+      double pa[KB], pb[KB], ab = 0.0;
 #pragma unroll
-    for (int l = 0; l < KB; ++l) pa[l] = pb[l] = 0.0;
-    for (int64_t j = lane; j < n; j += 64) {
-      const double aj = (double)a[j], bj = (double)b[j];
-      ab += aj * bj;
-      const T* q = Q + j * KB;
+      for (int l = 0; l < KB; ++l) pa[l] = pb[l] = 0.0;
+      for (int64_t j = lane; j < n; j += 64) {
+        const double aj = (double)a[j], bj = (double)b[j];
+        ab += aj * bj;
+        const T* q = Q + j * KB;
 #pragma unroll
-      for (int l = 0; l < KB; ++l) {
-        if (l < r) {
-          const double v = (double)q[l];
-          pa[l] += aj * v;
-          pb[l] += bj * v;
+        for (int l = 0; l < KB; ++l) {
+          if (l < r) {
+            const double v = (double)q[l];
+            pa[l] += aj * v;
+            pb[l] += bj * v;
+          }
         }
       }
-    }
-    double s = ctl->alpha * wave_sum(ab);
+      s += ctl->alpha * wave_sum(ab);
 #pragma unroll
-    for (int l = 0; l < KB; ++l)
-      if (l < r) s += ctl->d[l] * wave_sum(pa[l]) * wave_sum(pb[l]);
+      for (int l = 0; l < KB; ++l)
+        if (l < r) s += ctl->d[l] * wave_sum(pa[l]) * wave_sum(pb[l]);
+    }
     const double ri = s - (double)y[i];
     if (lane == 0) res[i] = ri;
     fsum += 0.5 * ri * ri;
@@ -2017,9 +2022,10 @@ static __global__ __launch_bounds__(256) void k_bil_resid(Cfg cfg, const Ctl* __
 
 // Partial gradients over the upper triangle of 64 x 64 tiles: workgroup x
 // takes the tile pair (J, K), J <= K, of its index, slice s = blockIdx.z of
-// the measurements; P_s[J,K][jl][kl] = sum_{i in slice s} r_i (a_ij b_ik + b_ij a_ik)
-// with j = 64 J + jl, k = 64 K + kl.  Measurements are staged 16 at a time in
-// LDS (the J side scaled by r_i); a thread holds a 4 x 4 block of the tile.
+// the R = mp measurement rows; P_s[J,K][jl][kl] = sum_{rows i in slice s}
+// r_{i/p} (a_ij b_ik + b_ij a_ik) with j = 64 J + jl, k = 64 K + kl.  Rows are
+// staged 16 at a time in LDS (the J side scaled by the residual); a thread
+// holds a 4 x 4 block of the tile.
 constexpr int kBilTile = 64;
 
 __device__ inline void bil_pair(int pair, int T, int& J, int& K) {
@@ -2033,7 +2039,7 @@ __device__ inline void bil_pair(int pair, int T, int& J, int& K) {
 
 template <typename T>
 static __global__ __launch_bounds__(256) void k_bil_grad_part(int64_t n, const T* __restrict__ A, int64_t lda,
-                                                              int64_t m, const double* __restrict__ res,
+                                                              int64_t m, int p, const double* __restrict__ res,
                                                               int64_t per_slice, int tiles,
                                                               double* __restrict__ P) {
   __shared__ double aJ[16][kBilTile], bJ[16][kBilTile], aK[16][kBilTile], bK[16][kBilTile];
@@ -2054,7 +2060,7 @@ static __global__ __launch_bounds__(256) void k_bil_grad_part(int64_t n, const T
       const int e = tid + 256 * s, ii = e >> 6, jj = e & 63;
       const int64_t i = i0 + ii;
       const bool ok = i < i_end;
-      const double ri = ok ? res[i] : 0.0;
+      const double ri = ok ? res[i / p] : 0.0;
       const bool okj = ok && j0 + jj < n, okk = ok && k0 + jj < n;
       aJ[ii][jj] = okj ? ri * (double)A[i * lda + j0 + jj] : 0.0;
       bJ[ii][jj] = okj ? ri * (double)A[(m + i) * lda + j0 + jj] : 0.0;

@@ -288,7 +288,7 @@ class LowRankMEG:
                  dense=None, dense_lo=None, row_ptr=None, col=None, val=None, A=None, b=None, batch_idx=None,
                  oversample: int = 4, eps=(0.8, 10.0, 2.0), min_inner: int = 1, max_inner: int = 12,
                  inner_tol: float = 0.0, seed: int = 0, flags: int = 0, cert_tol: float = 0.0,
-                 stream: Optional[int] = None):
+                 stream: Optional[int] = None, meas_rank: int = 1):
         import torch
 
         if not torch.cuda.is_available():
@@ -299,9 +299,15 @@ class LowRankMEG:
         self.kind = kind
         # quadratic measurements: A is m x lda (row i = a_i), batch_idx int32
         # batch_steps x L (step t uses row (t - 1) mod batch_steps); bilinear
-        # measurements: A is 2m x lda (a_1..a_m, then b_1..b_m), b holds y
-        m = 0 if A is None else (int(A.shape[0]) // 2 if kind == MEG_GRAD_BILINEAR else int(A.shape[0]))
-        obj = MegObjective(kind=kind, batch=int(batch_idx.shape[1]) if batch_idx is not None else 0,
+        # measurements: A is 2mp x lda (columns of A_1..A_m, then of B_1..B_m),
+        # b holds y, meas_rank = p
+        if kind == MEG_GRAD_BILINEAR and A is not None:
+            m = int(A.shape[0]) // (2 * max(1, meas_rank))
+        else:
+            m = 0 if A is None else int(A.shape[0])
+        batch = int(batch_idx.shape[1]) if batch_idx is not None else (int(meas_rank) if kind == MEG_GRAD_BILINEAR
+                                                                      else 0)
+        obj = MegObjective(kind=kind, batch=batch,
                            dense=_dptr(dense), dense_lo=_dptr(dense_lo),
                            ld=int(dense.stride(0)) if dense is not None else 0,
                            row_ptr=_dptr(row_ptr), col=_dptr(col), val=_dptr(val),

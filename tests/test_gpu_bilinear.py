@@ -3,12 +3,13 @@ objective kind MEG_GRAD_BILINEAR, whose steps form the residuals and the dense
 symmetric gradient on the device.
 
 Parity: from the experiments' start, GPU steps against the FP64 oracle's
-(X within 1e-8 for an FP64 state and 1e-5 for FP32 after each step, f(X_t)
-within 1e-6 plus the rounding allowance).  The FP64 bar is looser than the
-1e-9 of the other kinds: the solver's shift comes from the Gershgorin bound of
-the dense gradient, several times lambda_max(G) for these random measurement
+(X within max(1e-8, 4e-8 sigma / gap) for an FP64 state, one step from each
+oracle iterate, and 1e-5 for FP32 after each free-running step; f(X_t) within
+1e-6 plus the rounding allowance).  The FP64 bar is looser than the 1e-9 of
+the other kinds: the solver's shift sigma comes from the Gershgorin bound of
+the dense gradient, well above lambda_max(G) for these random measurement
 sums, and the Ritz residuals resolve to about 3e-8 of the shifted scale, so
-the eigenvectors are accurate to that over the eigengap.  The dual gap and the trace of
+the eigenvectors are accurate to that times sigma over the eigengap.  The dual gap and the trace of
 exp(M_t) of a bilinear context against the oracle at an oracle-built iterate.
 Then Table 1's experiment on the GPU: 20 instances per row, 200 iterations,
 the averages against the printed ones.
@@ -49,7 +50,8 @@ def make_ctx(meg, p, r, prec, **kw):
     y = torch.from_numpy(p.y_unit).to(dt).cuda()
     V0, lam0 = W.exp_init_bilinear(p, r)
     kw.setdefault("max_inner", 40)
-    return meg.LowRankMEG(p.n, r, meg.MEG_GRAD_BILINEAR, V0, lam0, prec=prec, eta=p.eta_unit, A=A, b=y, **kw), V0, lam0
+    return meg.LowRankMEG(p.n, r, meg.MEG_GRAD_BILINEAR, V0, lam0, prec=prec, eta=p.eta_unit, A=A, b=y,
+                          meas_rank=p.p, **kw), V0, lam0
 
 
 def data_in(p, prec):
@@ -61,12 +63,16 @@ def data_in(p, prec):
     return O.BilinearObjective(A, B, y)
 
 
-@pytest.mark.parametrize("prec,n,rank", [(0, 100, 1), (1, 100, 1), (1, 120, 5)])
-def test_bilinear_steps_match_the_oracle(meg, prec, n, rank):
-    print_case(test="bilinear_steps", prec=prec, n=n, rank=rank)
-    p = W.bilinear_recovery(n, rank, seed=40 + n + rank)
+@pytest.mark.parametrize("prec,n,rank,pm", [(0, 100, 1, 1), (1, 100, 1, 1), (1, 120, 5, 1), (0, 80, 2, 3),
+                                            (1, 80, 2, 3)])
+def test_bilinear_steps_match_the_oracle(meg, prec, n, rank, pm):
+    print_case(test="bilinear_steps", prec=prec, n=n, rank=rank, p=pm)
+    p = W.bilinear_recovery(n, rank, seed=40 + n + rank, p=pm)
     obj = data_in(p, prec)
-    g, V0, lam0 = make_ctx(meg, p, rank, prec, inner_tol=1e-12 if prec == 0 else 0.0)
+    # p > 1: the Gershgorin shift of these gradients is several times the Ritz
+    # gap, so the solver may use all its sweeps; X parity is the bar
+    g, V0, lam0 = make_ctx(meg, p, rank, prec, inner_tol=1e-12 if prec == 0 else 0.0,
+                           max_inner=40 if pm == 1 else 64)
     try:
         it = O.initial_iterate(V0, lam0, O.eps_schedule(0))
         assert g.objective() == pytest.approx(obj.value(it.dense()), rel=1e-6 if prec else 1e-12)
@@ -83,9 +89,12 @@ def test_bilinear_steps_match_the_oracle(meg, prec, n, rank):
             print(f"  t={info['t']}: rel X err {err:.2e}, f {info['f']:.10e} / {f_ref:.10e}, sweeps "
                   f"{info['inner_iters']}, sigma {info['sigma']:.3e}, gap {info['ritz_gap']:.3e}, cert_L "
                   f"{info['cert_L']:.3e}", flush=True)
-            assert err <= (1e-8 if prec == 0 else TOL_X[prec])
+            # FP64: the Ritz residuals are resolved to about 3e-8 of the shifted
+            # scale, so the eigenvectors (and X) to about that times sigma / gap
+            tol = max(1e-8, 4e-8 * info["sigma"] / info["ritz_gap"]) if prec == 0 else TOL_X[prec]
+            assert err <= tol
             assert abs(info["f"] - f_ref) <= ftol
-            assert info["converged"] == 1
+            assert info["converged"] == 1 or pm > 1
     finally:
         g.close()
 
@@ -220,3 +229,43 @@ def test_table1_on_the_gpu(meg, rank, n):
         assert first <= 1.2
     else:
         assert first == pytest.approx(ref["first_cert"], rel=0.35)
+
+
+def test_table3_on_the_gpu(meg):
+    """Table 3, p = 10 (measurement matrices with 10 orthonormal columns,
+    rank(M) = r = 5, n = 200, beta = 12 sqrt(r n), c = 100, T = 400) over 5
+    instances: recovery error, gradient gap and dual gap against the table's
+    averages, and the first certified iteration (pair r+1 resolved, as for
+    Table 2)."""
+    import torch
+
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table3_rank_p.json")))["rows"][0]
+    print_case(test="table3", p=ref["p"])
+    n, rank, out = 200, 5, []
+    for seed in range(5):
+        p = W.bilinear_recovery(n, rank, seed, p=ref["p"], beta_coeff=12.0)
+        g, V0, lam0 = make_ctx(meg, p, rank, 1, eps=(0.8, 100.0, 2.0), cert_tol=1e-4, max_inner=64)
+        try:
+            X0 = (V0 * lam0) @ V0.T
+            init = np.linalg.norm(n * X0 - p.M) ** 2 / np.linalg.norm(p.M) ** 2
+            first = first_certified(meg, g, n, limit=60)
+            g.solve(400 - min(first, 60))  # first_certified took min(first, 60) steps
+            dg = g.dual_gap(max_steps=200, tol=1e-10)
+            V, d, a, t = g.get_iterate()
+            assert t == 401
+            Xs = p.tau * (a * np.eye(n) + (V * d) @ V.T)
+            rec = np.linalg.norm(n / p.tau * Xs - p.M) ** 2 / np.linalg.norm(p.M) ** 2
+            G = O.BilinearObjective(p.A, p.B, p.y).grad(Xs)
+            ev = np.linalg.eigvalsh(G)
+            out.append((init, rec, ev[rank] - ev[0], p.tau ** 2 * dg["gap"], first))
+        finally:
+            g.close()
+    init, rec, gap, dual, first = np.mean(np.array(out, dtype=float), axis=0)
+    print(f"  p {ref['p']}: init {init:.4f} ({ref['init_err']}), recovery {rec:.4f} ({ref['rec_err']}), gap "
+          f"{gap:.3f} ({ref['grad_gap']}), dual gap {dual:.4f} ({ref['dual_gap']}), first certified {first:.1f} "
+          f"({ref['first_cert']})", flush=True)
+    assert rec == pytest.approx(ref["rec_err"], rel=0.35)
+    assert gap == pytest.approx(ref["grad_gap"], rel=0.2)
+    assert init == pytest.approx(ref["init_err"], rel=0.35)
+    assert ref["dual_gap"] / 2 <= dual <= 2 * ref["dual_gap"]
+    assert first == pytest.approx(ref["first_cert"], rel=0.5)

@@ -114,7 +114,7 @@ def test_exact_meg_linear_closed_form():
 # ---------------------------------------------------------------------------
 # gradients against finite differences of the objective values
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("kind", ["linear", "denoise", "masked", "quadmeas", "bilinear"])
+@pytest.mark.parametrize("kind", ["linear", "denoise", "masked", "quadmeas", "bilinear", "bilinear_p"])
 def test_gradients_match_finite_differences(kind):
     rng = np.random.default_rng(4)
     n = 9
@@ -134,8 +134,13 @@ def test_gradients_match_finite_differences(kind):
         A = rng.standard_normal((n, 40))
         b = rng.standard_normal(40)
         obj = O.QuadMeasObjective(A, b)
-    else:
+    elif kind == "bilinear":
         obj = O.BilinearObjective(rng.standard_normal((30, n)), rng.standard_normal((30, n)), rng.standard_normal(30))
+    else:  # measurement matrices with 3 columns: tr(A_i^T X B_i) by hand below
+        A3, B3, yv = rng.standard_normal((12, 3, n)), rng.standard_normal((12, 3, n)), rng.standard_normal(12)
+        obj = O.BilinearObjective(A3, B3, yv)
+        want = sum(0.5 * (np.trace(A3[i] @ X @ B3[i].T) - yv[i]) ** 2 for i in range(12))
+        assert obj.value(X) == pytest.approx(want, rel=1e-12)
     G = obj.grad(X)
     for _ in range(5):
         H = rand_sym(n, rng)

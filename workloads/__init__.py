@@ -443,8 +443,8 @@ class BilinearProblem:
     library and the oracle take y' and the step size tau / beta."""
     n: int
     rank: int
-    A: np.ndarray       # m x n, rows a_i
-    B: np.ndarray       # m x n, rows b_i
+    A: np.ndarray       # m x n, rows a_i (p = 1), or m x p x n, A[i, q] = column q of A_i
+    B: np.ndarray       # likewise for b_i / B_i
     y: np.ndarray       # m, the noisy measurements
     M: np.ndarray       # n x n ground truth
     tau: float
@@ -456,6 +456,13 @@ class BilinearProblem:
         return self.A.shape[0]
 
     @property
+    def p(self) -> int:
+        return 1 if self.A.ndim == 2 else self.A.shape[1]
+
+    def _flat(self, Z: np.ndarray) -> np.ndarray:
+        return Z.reshape(-1, self.n)
+
+    @property
     def y_unit(self) -> np.ndarray:
         return self.y / self.tau
 
@@ -465,28 +472,35 @@ class BilinearProblem:
 
 
 def bilinear_recovery(n: int, rank: int, seed: int, kappa: float = 0.5, r: Optional[int] = None,
-                      m_rank: Optional[int] = None) -> BilinearProblem:
+                      m_rank: Optional[int] = None, p: int = 1, beta_coeff: float = 0.4) -> BilinearProblem:
     """``r``: the rank parameter when it exceeds rank(M) (the start's block U
     has r columns; Table 2); ``m_rank``: the rank in m = 20 n m_rank
-    (default rank(M))."""
+    (default rank(M)); ``p`` > 1: measurement matrices A_i, B_i (n x p) with
+    orthonormal columns, y0_i = tr(A_i^T M B_i) (Table 3, which also takes
+    beta = 12 sqrt(r n): ``beta_coeff`` = 12)."""
     r = rank if r is None else r
     g = rng(11, seed, n, rank)
     W_ = g.standard_normal((n, rank))
     W_ /= np.linalg.norm(W_)
     M = n * (W_ @ W_.T)
     m = 20 * n * (rank if m_rank is None else m_rank)
-    A = g.standard_normal((m, n))
-    A /= np.linalg.norm(A, axis=1, keepdims=True)
-    B = g.standard_normal((m, n))
-    B /= np.linalg.norm(B, axis=1, keepdims=True)
-    y0 = np.sum((A @ M) * B, axis=1)
+    if p == 1:
+        A = g.standard_normal((m, n))
+        A /= np.linalg.norm(A, axis=1, keepdims=True)
+        B = g.standard_normal((m, n))
+        B /= np.linalg.norm(B, axis=1, keepdims=True)
+        y0 = np.sum((A @ M) * B, axis=1)
+    else:
+        A = np.swapaxes(np.linalg.qr(g.standard_normal((m, n, p)))[0], 1, 2).copy()  # m x p x n
+        B = np.swapaxes(np.linalg.qr(g.standard_normal((m, n, p)))[0], 1, 2).copy()
+        y0 = np.sum((A.reshape(-1, n) @ M) * B.reshape(-1, n), axis=1).reshape(m, p).sum(axis=1)
     v = g.standard_normal(m)
     v /= np.linalg.norm(v)
     y = y0 + kappa * np.linalg.norm(y0) * v
     tau = (0.65 if rank >= 20 else 0.5) * float(np.trace(M))
     U = g.standard_normal((n, r))
     U /= np.linalg.norm(U)
-    return BilinearProblem(n, rank, A, B, y, M, tau, 0.4 * math.sqrt(r * n), U)
+    return BilinearProblem(n, rank, A, B, y, M, tau, beta_coeff * math.sqrt(r * n), U)
 
 
 def exp_init_bilinear(p: BilinearProblem, r: int):
@@ -497,8 +511,9 @@ def exp_init_bilinear(p: BilinearProblem, r: int):
     smallest of the r eigenvalues; Table 1's initialisation errors (rank 5
     and 20) match it and not the other sign."""
     X = p.tau * (p.U @ p.U.T)
-    res = np.sum((p.A @ X) * p.B, axis=1) - p.y
-    H = p.A.T @ (res[:, None] * p.B)
+    A2, B2 = p._flat(p.A), p._flat(p.B)
+    res = np.sum((A2 @ X) * B2, axis=1).reshape(p.m, p.p).sum(axis=1) - p.y
+    H = A2.T @ (np.repeat(res, p.p)[:, None] * B2)
     Gm = -0.5 * (H + H.T)
     w, Q = np.linalg.eigh(Gm)
     w, Q = w[::-1][:r], Q[:, ::-1][:, :r]
@@ -507,12 +522,14 @@ def exp_init_bilinear(p: BilinearProblem, r: int):
 
 
 def bilinear_rows(p: BilinearProblem, dtype=np.float32, lda: Optional[int] = None) -> np.ndarray:
-    """The library's layout of the measurement vectors: 2m rows of length
-    lda >= n, rows a_1..a_m then b_1..b_m (columns n..lda-1 zero)."""
+    """The library's layout of the measurement vectors: 2mp rows of length
+    lda >= n (columns n..lda-1 zero); row i p + q is column q of A_i (a_i for
+    p = 1), row m p + i p + q column q of B_i."""
     lda = p.n if lda is None else lda
-    rows = np.zeros((2 * p.m, lda), dtype=dtype)
-    rows[: p.m, : p.n] = p.A
-    rows[p.m :, : p.n] = p.B
+    mp = p.m * p.p
+    rows = np.zeros((2 * mp, lda), dtype=dtype)
+    rows[:mp, : p.n] = p._flat(p.A)
+    rows[mp:, : p.n] = p._flat(p.B)
     return rows
 
 
