@@ -1985,31 +1985,36 @@ static __global__ __launch_bounds__(256) void k_bil_resid(Cfg cfg, const Ctl* __
   const int64_t n = cfg.n;
   double fsum = 0.0;
   const int64_t mp = m * p;
-  for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < m; i += (int64_t)gridDim.x * 4) {
-    double s = 0.0;
-    for (int qc = 0; qc < p; ++qc) {
-      const T* a = A + (i * p + qc) * lda;
-      const T* b = A + (mp + i * p + qc) * lda;
-      double pa[KB], pb[KB], ab = 0.0;
+  // the contribution of one column pair: alpha a^T b + sum_l d_l (a^T v_l)(b^T v_l)
+  auto pair_term = [&](const T* a, const T* b) -> double {
+    double pa[KB], pb[KB], ab = 0.0;
 #pragma unroll
-      for (int l = 0; l < KB; ++l) pa[l] = pb[l] = 0.0;
-      for (int64_t j = lane; j < n; j += 64) {
-        const double aj = (double)a[j], bj = (double)b[j];
-        ab += aj * bj;
-        const T* q = Q + j * KB;
+    for (int l = 0; l < KB; ++l) pa[l] = pb[l] = 0.0;
+    for (int64_t j = lane; j < n; j += 64) {
+      const double aj = (double)a[j], bj = (double)b[j];
+      ab += aj * bj;
+      const T* q = Q + j * KB;
 #pragma unroll
-        for (int l = 0; l < KB; ++l) {
-          if (l < r) {
-            const double v = (double)q[l];
-            pa[l] += aj * v;
-            pb[l] += bj * v;
-          }
+      for (int l = 0; l < KB; ++l) {
+        if (l < r) {
+          const double v = (double)q[l];
+          pa[l] += aj * v;
+          pb[l] += bj * v;
         }
       }
-      s += ctl->alpha * wave_sum(ab);
+    }
+    double t = ctl->alpha * wave_sum(ab);
 #pragma unroll
-      for (int l = 0; l < KB; ++l)
-        if (l < r) s += ctl->d[l] * wave_sum(pa[l]) * wave_sum(pb[l]);
+    for (int l = 0; l < KB; ++l)
+      if (l < r) t += ctl->d[l] * wave_sum(pa[l]) * wave_sum(pb[l]);
+    return t;
+  };
+  for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < m; i += (int64_t)gridDim.x * 4) {
+    double s = 0.0;
+    if (p == 1) {
+      s = pair_term(A + i * lda, A + (m + i) * lda);
+    } else {
+      for (int qc = 0; qc < p; ++qc) s += pair_term(A + (i * p + qc) * lda, A + (mp + i * p + qc) * lda);
     }
     const double ri = s - (double)y[i];
     if (lane == 0) res[i] = ri;
@@ -2020,13 +2025,14 @@ static __global__ __launch_bounds__(256) void k_bil_resid(Cfg cfg, const Ctl* __
   if (threadIdx.x == 0) part[blockIdx.x] = (sred[0] + sred[1]) + (sred[2] + sred[3]);
 }
 
-// Partial gradients over the upper triangle of 64 x 64 tiles: workgroup x
+// Partial gradients over the upper triangle of 128 x 128 tiles: workgroup x
 // takes the tile pair (J, K), J <= K, of its index, slice s = blockIdx.z of
 // the R = mp measurement rows; P_s[J,K][jl][kl] = sum_{rows i in slice s}
-// r_{i/p} (a_ij b_ik + b_ij a_ik) with j = 64 J + jl, k = 64 K + kl.  Rows are
-// staged 16 at a time in LDS (the J side scaled by the residual); a thread
-// holds a 4 x 4 block of the tile.
-constexpr int kBilTile = 64;
+// r_{i/p} (a_ij b_ik + b_ij a_ik) with j = 128 J + jl, k = 128 K + kl.  Rows
+// are staged 16 at a time in LDS (the J side scaled by the residual); a
+// thread holds rows ty + 16a and columns tx + 16b (a, b < 8) of the tile, so
+// the lanes of a wave read consecutive LDS words.
+constexpr int kBilTile = 128;
 
 __device__ inline void bil_pair(int pair, int T, int& J, int& K) {
   J = 0;
@@ -2049,15 +2055,15 @@ static __global__ __launch_bounds__(256) void k_bil_grad_part(int64_t n, const T
   const int64_t j0 = (int64_t)J * kBilTile, k0 = (int64_t)K * kBilTile;
   const int64_t i_beg = (int64_t)blockIdx.z * per_slice;
   const int64_t i_end = min(m, i_beg + per_slice);
-  double acc[4][4];
+  double acc[8][8];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 8; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
   for (int64_t i0 = i_beg; i0 < i_end; i0 += 16) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int e = tid + 256 * s, ii = e >> 6, jj = e & 63;
+    for (int s = 0; s < 8; ++s) {
+      const int e = tid + 256 * s, ii = e >> 7, jj = e & 127;
       const int64_t i = i0 + ii;
       const bool ok = i < i_end;
       const double ri = ok ? res[i / p] : 0.0;
@@ -2068,28 +2074,28 @@ static __global__ __launch_bounds__(256) void k_bil_grad_part(int64_t n, const T
       bK[ii][jj] = okk ? (double)A[(m + i) * lda + k0 + jj] : 0.0;
     }
     __syncthreads();
-#pragma unroll 4
+#pragma unroll 2
     for (int ii = 0; ii < 16; ++ii) {
-      double xa[4], xb[4], ya[4], yb[4];
+      double xa[8], xb[8], ya[8], yb[8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        xa[q] = aJ[ii][ty * 4 + q];
-        xb[q] = bJ[ii][ty * 4 + q];
-        ya[q] = aK[ii][tx * 4 + q];
-        yb[q] = bK[ii][tx * 4 + q];
+      for (int q = 0; q < 8; ++q) {
+        xa[q] = aJ[ii][ty + 16 * q];
+        xb[q] = bJ[ii][ty + 16 * q];
+        ya[q] = aK[ii][tx + 16 * q];
+        yb[q] = bK[ii][tx + 16 * q];
       }
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] += xa[a] * yb[b] + xb[a] * ya[b];
+        for (int b = 0; b < 8; ++b) acc[a][b] += xa[a] * yb[b] + xb[a] * ya[b];
     }
     __syncthreads();
   }
   double* dst = P + ((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * (kBilTile * kBilTile);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 8; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) dst[(ty * 4 + a) * kBilTile + tx * 4 + b] = acc[a][b];
+    for (int b = 0; b < 8; ++b) dst[(ty + 16 * a) * kBilTile + tx + 16 * b] = acc[a][b];
 }
 
 // G[j][k] = G[k][j] = 1/2 sum_{s < S} P_s[J,K][jl][kl] in slice order, in the
