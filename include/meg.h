@@ -118,7 +118,8 @@ typedef struct {
 
 typedef struct {
   int32_t kind;  /* meg_grad_kind */
-  int32_t batch; /* QUADMEAS: minibatch size L (>= 1)                         */
+  int32_t batch; /* QUADMEAS: minibatch size L (>= 1); BILINEAR: columns p of
+                    each measurement matrix (0 or 1: rank-1 measurements)     */
   /* dense kinds: DEVICE, n x n symmetric, row-major with leading dimension
    * ld >= n; element type double (F64) or float (F32).  F32_BF16X3: `dense`
    * is the bf16 hi plane and `dense_lo` the bf16 lo plane (hi + lo ~ M). */
