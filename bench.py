@@ -50,7 +50,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # valid only for the kernel sources it was measured on.
 TRAFFIC = {"bytes_per_launch": 943.0e6, "iterations_per_launch": 64, "applies_per_iteration": 3.0,
            "fetch_bytes": 546.5e6, "write_bytes": 396.5e6, "fetch_factor": 2.0, "write_factor": 1.0,
-           "source_hash": "f6cd16765da98e63"}
+           "source_hash": "ad9dabac6b583560"}
 KERNEL_SOURCES = ["meg_device.hpp", "meg_small.hpp", "meg_kernels.hpp", "meg_api.hip"]
 
 

@@ -1392,11 +1392,11 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
   if (ok && obj->kind == MEG_GRAD_MASKED_CSR) ok = alloc(&c->g, (size_t)std::max<int64_t>(obj->nnz, 1) * c->esize);
   if (ok && obj->kind == MEG_GRAD_QUADMEAS) ok = alloc(&c->quad, quad_layout(obj->batch, k, c->esize).bytes);
   if (ok && c->bilinear) {
-    // slices of the measurement rows: the partial-gradient grid fills one round
-    // of two resident workgroups per compute unit (256 CUs)
+    // slices of the measurement rows: about 2048 partial-gradient workgroups
+    // (eight per compute unit)
     const int64_t tiles = ceil_div(cfg.n, kBilTile), pairs = tiles * (tiles + 1) / 2;
     const int64_t rows = obj->m * std::max(1, (int)obj->batch);
-    c->bil_S = (int)std::max<int64_t>(1, std::min<int64_t>({64, 512 / pairs, ceil_div(rows, 16)}));
+    c->bil_S = (int)std::max<int64_t>(1, std::min<int64_t>({64, 2048 / pairs, ceil_div(rows, 16)}));
     ok = alloc(&c->bil_G, (size_t)cfg.n * cfg.n * c->esize) && alloc((void**)&c->bil_res, (size_t)obj->m * 8) &&
          alloc((void**)&c->bil_P, (size_t)c->bil_S * pairs * kBilTile * kBilTile * 8);
   }

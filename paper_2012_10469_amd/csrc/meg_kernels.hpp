@@ -2025,14 +2025,17 @@ static __global__ __launch_bounds__(256) void k_bil_resid(Cfg cfg, const Ctl* __
   if (threadIdx.x == 0) part[blockIdx.x] = (sred[0] + sred[1]) + (sred[2] + sred[3]);
 }
 
-// Partial gradients over the upper triangle of 128 x 128 tiles: workgroup x
+// Partial gradients over the upper triangle of 64 x 64 tiles: workgroup x
 // takes the tile pair (J, K), J <= K, of its index, slice s = blockIdx.z of
 // the R = mp measurement rows; P_s[J,K][jl][kl] = sum_{rows i in slice s}
-// r_{i/p} (a_ij b_ik + b_ij a_ik) with j = 128 J + jl, k = 128 K + kl.  Rows
-// are staged 16 at a time in LDS (the J side scaled by the residual); a
-// thread holds rows ty + 16a and columns tx + 16b (a, b < 8) of the tile, so
-// the lanes of a wave read consecutive LDS words.
-constexpr int kBilTile = 128;
+// r_{i/p} (a_ij b_ik + b_ij a_ik) with j = 64 J + jl, k = 64 K + kl.  A dense
+// contraction over the rows, on the FP64 matrix cores: rows are staged 16 at a
+// time in LDS (the J side scaled by the residual), each wave owns a 32 x 32
+// quarter of the tile as 2 x 2 blocks of 16 x 16, and every 4-row step issues
+// v_mfma_f64_16x16x4f64 twice per block (r a_J with b_K, r b_J with a_K).
+// Operand layout: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// result register v of lane l is C[l / 16 + 4 v][l % 16].
+constexpr int kBilTile = 64;
 
 __device__ inline void bil_pair(int pair, int T, int& J, int& K) {
   J = 0;
@@ -2049,21 +2052,23 @@ static __global__ __launch_bounds__(256) void k_bil_grad_part(int64_t n, const T
                                                               int64_t per_slice, int tiles,
                                                               double* __restrict__ P) {
   __shared__ double aJ[16][kBilTile], bJ[16][kBilTile], aK[16][kBilTile], bK[16][kBilTile];
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int jw = 32 * (wave >> 1), kw = 32 * (wave & 1);  // the wave's quarter of the tile
+  const int li = lane & 15, lk = lane >> 4;
   int J, K;
   bil_pair(blockIdx.x, tiles, J, K);
   const int64_t j0 = (int64_t)J * kBilTile, k0 = (int64_t)K * kBilTile;
   const int64_t i_beg = (int64_t)blockIdx.z * per_slice;
   const int64_t i_end = min(m, i_beg + per_slice);
-  double acc[8][8];
+  f64x4_t acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4_t{0.0, 0.0, 0.0, 0.0};
   for (int64_t i0 = i_beg; i0 < i_end; i0 += 16) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int e = tid + 256 * s, ii = e >> 7, jj = e & 127;
+    for (int s = 0; s < 4; ++s) {
+      const int e = tid + 256 * s, ii = e >> 6, jj = e & 63;
       const int64_t i = i0 + ii;
       const bool ok = i < i_end;
       const double ri = ok ? res[i / p] : 0.0;
@@ -2074,28 +2079,35 @@ static __global__ __launch_bounds__(256) void k_bil_grad_part(int64_t n, const T
       bK[ii][jj] = okk ? (double)A[(m + i) * lda + k0 + jj] : 0.0;
     }
     __syncthreads();
-#pragma unroll 2
-    for (int ii = 0; ii < 16; ++ii) {
-      double xa[8], xb[8], ya[8], yb[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        xa[q] = aJ[ii][ty + 16 * q];
-        xb[q] = bJ[ii][ty + 16 * q];
-        ya[q] = aK[ii][tx + 16 * q];
-        yb[q] = bK[ii][tx + 16 * q];
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kk = 4 * ks + lk;
+      double xa[2], xb[2], ya[2], yb[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        xa[t] = aJ[kk][jw + 16 * t + li];
+        xb[t] = bJ[kk][jw + 16 * t + li];
+        ya[t] = aK[kk][kw + 16 * t + li];
+        yb[t] = bK[kk][kw + 16 * t + li];
       }
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 8; ++b) acc[a][b] += xa[a] * yb[b] + xb[a] * ya[b];
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], yb[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[a], ya[b], acc[a][b], 0, 0, 0);
+        }
     }
     __syncthreads();
   }
   double* dst = P + ((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * (kBilTile * kBilTile);
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) dst[(ty + 16 * a) * kBilTile + tx + 16 * b] = acc[a][b];
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        dst[(jw + 16 * a + lk + 4 * v) * kBilTile + kw + 16 * b + li] = acc[a][b][v];
 }
 
 // G[j][k] = G[k][j] = 1/2 sum_{s < S} P_s[J,K][jl][kl] in slice order, in the
