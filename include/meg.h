@@ -107,13 +107,28 @@ typedef struct {
                          to the largest Ritz value; 0 selects 1e-10 (F64) or
                          1e-6 (F32 forms).  Residuals are estimated from FP64
                          Gram matrices, which resolve them down to about
-                         3e-8 of the scale; below that the solver runs two
-                         more sweeps after the estimate reaches that floor.   */
+                         3e-8 of the scale.  Below that, an F64 state also
+                         tests the explicit residuals ||Y q_i - theta_i q_i||
+                         of the previous sweep's pairs (formed by the next
+                         apply from its rows, down to ~1e-14 of the scale);
+                         the F32 forms run two more sweeps instead once the
+                         estimate reaches its floor.                           */
   uint64_t seed;      /* seeds the solver's extra start columns               */
-  double cert_tol;    /* absolute residual tolerance of the (r+1)-th Ritz pair,
-                         whose value enters the certificate; 0 = do not iterate
-                         for it (its Ritz value is then a lower bound of
-                         mu_{r+1}, i.e. the reported certificate is optimistic) */
+  double cert_tol;    /* the (r+1)-th Ritz pair, whose value mu_{r+1} enters the
+                         certificate (Section 3.1.1).  Its Ritz value is a lower
+                         bound of mu_{r+1} (interlacing) and cert_L does not
+                         decrease with mu_{r+1}, so cert_L from the Ritz
+                         values is a lower bound of the exact L: enough to rule
+                         a certificate out.  The pair counts as resolved when
+                         its residual rho_{r+1} meets the tolerance (cert_tol
+                         > 0, else the top pairs') and is at most a quarter of
+                         the gap to the next Ritz value; cert_L + rho_{r+1} is
+                         then an upper bound, and cert_holds and the stopping
+                         rules act on it, never on an unresolved pair.
+                         cert_tol > 0: each step iterates until the pair is
+                         resolved (or max_inner).  cert_tol <= 0: no sweeps
+                         are spent on it, except by meg_solve (and a server)
+                         while the lower bound could meet their tol.        */
 } meg_params;
 
 typedef struct {
@@ -167,17 +182,21 @@ typedef struct {
   int64_t t;          /* iteration index t of the step just taken (gradient at X_t) */
   double f;           /* f(X_t) when requested, else NaN                      */
   double eps_t;       /* approximation parameter used to form X_{t+1}         */
-  double cert_L;      /* log((n-r) lambda_{r+1}(Y_t) / (eps_t b^{r+1}_t))     */
+  double cert_L;      /* log((n-r) lambda_{r+1}(Y_t) / (eps_t b^{r+1}_t)) from
+                         the Ritz values: a lower bound of the exact value,
+                         and within resid_r1 of it when cert_resolved        */
   double cert_bound;  /* max(2 eps_t, cert_L): bound of the error lemma       */
-  int32_t cert_holds; /* cert_L <= 2 eps_t                                    */
+  int32_t cert_holds; /* cert_resolved and cert_L + resid_r1 <= 2 eps_t: the
+                         exact certificate holds                              */
   int32_t inner_iters;/* subspace sweeps used                                 */
   double ritz_gap;    /* mu_r - mu_{r+1} (eigenvalues of M_t)                 */
   double resid_max;   /* max Ritz residual over the top r pairs               */
   double mu_r1;       /* mu_{r+1}                                             */
   double sigma;       /* spectral shift used by the solver                    */
   int32_t converged;  /* inner solver met its tolerance                       */
-  int32_t reserved;
-  double resid_r1;    /* Ritz residual of the (r+1)-th pair (certificate)     */
+  int32_t cert_resolved; /* the (r+1)-th Ritz pair is resolved (cert_tol)   */
+  double resid_r1;    /* residual bound of the (r+1)-th Ritz pair; resolved:
+                         the exact L lies in [cert_L, cert_L + resid_r1]     */
 } meg_step_info;
 
 /* Block size k used for (r, oversample); returns 0 when k would exceed 32. */

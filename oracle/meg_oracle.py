@@ -548,24 +548,6 @@ def factored_frob(V: np.ndarray, d: np.ndarray, alpha: float) -> float:
     return factored_diff_frob(V, d, alpha, np.zeros((np.asarray(V).shape[0], 0)), np.zeros(0), 0.0)
 
 
-def factored_diff_frob2(Va, da, aa, Vb, db, ab) -> float:
-    Va = np.asarray(Va, dtype=np.float64)
-    Vb = np.asarray(Vb, dtype=np.float64)
-    da = np.asarray(da, dtype=np.float64)
-    db = np.asarray(db, dtype=np.float64)
-    n = Va.shape[0]
-    dA = float(aa) - float(ab)
-    Ga = Va.T @ Va
-    Gb = Vb.T @ Vb
-    C = Va.T @ Vb
-    tra = float(np.sum(da * np.diag(Ga)))
-    trb = float(np.sum(db * np.diag(Gb)))
-    naa = float(np.sum((Ga * da) * (Ga * da).T))  # tr(Da Ga Da Ga)
-    nbb = float(np.sum((Gb * db) * (Gb * db).T))
-    nab = float(np.sum((da[:, None] * C * db[None, :]) * C))  # tr(Da C Db C^T)
-    return n * dA * dA + 2.0 * dA * (tra - trb) + naa + nbb - 2.0 * nab
-
-
 def factored_diff_frob(Va, da, aa, Vb, db, ab) -> float:
     """||X_a - X_b||_F for X = alpha I + V diag(d) V^T without forming X.
 

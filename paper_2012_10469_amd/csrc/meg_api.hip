@@ -223,7 +223,9 @@ struct Launch {
   }
 
   static size_t part_need(int P) {
-    return (size_t)P * (3 * KB * KB + 2);  // Gram partials + the objective's two partials
+    // Gram partials, the objective's two partials and (FP64) the explicit
+    // residuals' column sums
+    return (size_t)P * ApplySmem<T, KB, 1, 0>::PSTRIDE;
   }
 
   static hipError_t step(meg_ctx c, int nsteps, bool stamps) {
@@ -1029,7 +1031,7 @@ void fill_info(const Ctl& h, meg_step_info* o) {
   o->mu_r1 = in.mu_r1;
   o->sigma = in.sigma;
   o->converged = in.converged;
-  o->reserved = 0;
+  o->cert_resolved = in.cert_resolved;
   o->resid_r1 = in.resid_r1;
 }
 
@@ -1065,6 +1067,7 @@ meg_status upload_iterate(meg_ctx c, const double* V, int q, const double* d, do
   h.status = 0;
   h.fvalid = 0;
   h.polish = 0;
+  h.xvalid = 0;
   h.pxvalid = 0;  // the shift falls back to the a-priori bound for the new iterate
   h.dxnorm = 0.0;
   h.solve_tol = 0.0;
@@ -1125,7 +1128,7 @@ meg_status validate(const meg_params* p, const meg_objective* o, const meg_start
   const double eps0 = p->eps_scale / std::pow(p->eps_c + 1.0, p->eps_pow);
   if (!(eps0 > 0.0 && eps0 <= 0.75)) return MEG_ERR_INVALID_ARG;
   if (p->min_inner < 1 || p->max_inner < p->min_inner || p->max_inner > 64) return MEG_ERR_INVALID_ARG;
-  if (!(p->inner_tol >= 0.0) || !(p->cert_tol >= 0.0)) return MEG_ERR_INVALID_ARG;
+  if (!(p->inner_tol >= 0.0) || !std::isfinite(p->cert_tol)) return MEG_ERR_INVALID_ARG;
   switch (o->kind) {
     case MEG_GRAD_LINEAR_DENSE:
     case MEG_GRAD_DENOISE_DENSE:
@@ -1354,6 +1357,7 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
   cfg.inner_tol = params->inner_tol > 0 ? params->inner_tol : (c->esize == 8 ? 1e-10 : 1e-6);
   cfg.unit_round = (c->esize == 8) ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
   cfg.cert_tol = params->cert_tol;
+  cfg.xres = (c->esize == 8) ? 1 : 0;  // explicit Ritz residuals in FP64
   if (obj->kind == MEG_GRAD_EXTERNAL || obj->kind == MEG_GRAD_BILINEAR) {
     // the operator family is chosen per step; dense until then (bilinear: always
     // the dense gradient the context forms)
@@ -1386,8 +1390,8 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
   auto alloc = [&](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 256)) == hipSuccess; };
   bool ok = alloc(&c->Qw, zbytes) && alloc(&c->Za, zbytes) && alloc(&c->Zb, zbytes) &&
             alloc((void**)&c->ctl, sizeof(Ctl)) && alloc((void**)&c->part, pe * 8) &&
-            alloc((void**)&c->sums, 3 * KMAX * KMAX * 8) && alloc((void**)&c->bar, kBarWords * sizeof(unsigned)) &&
-            alloc((void**)&c->gpart, (size_t)kBarMaxGroups * 3 * KMAX * KMAX * 8) &&
+            alloc((void**)&c->sums, kPartMax * 8) && alloc((void**)&c->bar, kBarWords * sizeof(unsigned)) &&
+            alloc((void**)&c->gpart, (size_t)kBarMaxGroups * kPartMax * 8) &&
             alloc((void**)&c->ts, kTsSlots * sizeof(long long));
   if (ok && obj->kind == MEG_GRAD_MASKED_CSR) ok = alloc(&c->g, (size_t)std::max<int64_t>(obj->nnz, 1) * c->esize);
   if (ok && obj->kind == MEG_GRAD_QUADMEAS) ok = alloc(&c->quad, quad_layout(obj->batch, k, c->esize).bytes);

@@ -47,11 +47,18 @@ struct Cfg {
   double eta, eps_scale, eps_c, eps_pow;
   double inner_tol;   // relative Ritz residual tolerance (top r pairs)
   double unit_round;  // 2^-24 (float state) or 2^-53 (double state)
-  double cert_tol;    // absolute residual tolerance of the (r+1)-th pair (0: none)
+  double cert_tol;    // (r+1)-th pair: > 0 always resolve it to this absolute residual;
+                      // 0 resolve it (to the top pairs' tolerance) whenever the
+                      // certificate's lower bound could pass a decision; < 0 never
   // CSR kinds: each workgroup keeps its rows' slice of the sparse data in
   // dynamic LDS (0: disabled, the data is read from global memory)
   int32_t cache_blocks;  // row blocks per workgroup the cache holds
   int32_t cache_nnz;     // stored entries per workgroup the cache holds
+  // explicit Ritz residuals (FP64 state): every Rayleigh-Ritz sweep's residual
+  // block Zout S - Zin W S Theta is formed by the next sweep's apply, one
+  // pass over its rows, instead of being estimated from Gram matrices only
+  int32_t xres;
+  int32_t pad_;
 };
 
 // Byte offsets of the per-workgroup CSR cache in dynamic LDS:
@@ -79,7 +86,7 @@ struct Info {
   double f, eps_t, cert_L, cert_bound;
   int32_t cert_holds, inner_iters;
   double ritz_gap, resid_max, mu_r1, sigma;
-  int32_t converged, reserved;
+  int32_t converged, cert_resolved;
   double resid_r1;
 };
 
@@ -115,11 +122,22 @@ struct Ctl {
   int64_t applies_done;     // operator applies performed by step launches (counter)
   int64_t jacobi_done;      // Jacobi sweeps of the Rayleigh-Ritz solves (counter)
   int64_t pause_seq;        // batched launches: the launch whose time budget this instance used up
+  // explicit residuals (Cfg::xres): the last Rayleigh-Ritz sweep's sorted
+  // Ritz vectors S and W S Theta, valid while xvalid is set (the next sweep's
+  // apply forms Zin' S - Zin (W S Theta) with Zin' = that sweep's output)
+  double XS[KMAX * KMAX];
+  double XWT[KMAX * KMAX];
+  int32_t xvalid;
+  int32_t pad_;
   Info info;
 };
 
 // Scratch of the persistent step kernel: per-workgroup partial sums, their
 // reduction, and the grid barrier words.
+// Longest per-workgroup partial record of any step kernel (Gram matrices,
+// the masked objective's two sums, the explicit residuals' column sums).
+constexpr int kPartMax = 3 * KMAX * KMAX + 2 + KMAX;
+
 struct Bufs {
   double* part;     // (workgroups of the team) x plen partial sums (FP64)
   double* gpart;    // per-barrier-group sums of the partials (FP64)

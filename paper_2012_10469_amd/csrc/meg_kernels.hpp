@@ -117,12 +117,18 @@ struct ApplySmem {
   static constexpr int T_ZO = T_U + ROWS * KB;    // ROWS x KB
   static constexpr int T_GW = T_ZO + ROWS * KB;   // GWROWS x 3 x KB, fused gradient
   static constexpr int T_END = T_GW + 3 * GWROWS * KB;
+  // explicit residuals of the previous Rayleigh-Ritz sweep (FP64 state only);
+  // its input rows go to the T_B rows once those are used up
+  static constexpr int XR = sizeof(T) == 8 ? 1 : 0;
   static constexpr int TYPED_DOUBLES = (T_END * (int)sizeof(T) + 7) / 8;
   static constexpr int PLEN = 3 * KB * KB;       // Gram accumulator (FP64)
-  static constexpr int PSTRIDE = PLEN + 2;        // per-workgroup partials: Gram, sum g^2, sum X_ij^2
+  static constexpr int XOFF = PLEN + 2;          // residual column sums in the partial record
+  // per-workgroup partials: Gram, sum g^2, sum X_ij^2, residual column sums
+  static constexpr int PSTRIDE = PLEN + 2 + XR * KB;
+  static constexpr int ACC = PLEN + XR * KB;     // accumulators: Gram, residual column sums
   static constexpr int SMALL = small_scratch<KB>();
   static constexpr int BODY = TYPED_DOUBLES > SMALL ? TYPED_DOUBLES : SMALL;
-  static constexpr int TOTAL = PLEN + BODY;
+  static constexpr int TOTAL = ACC + BODY;
 };
 
 // Operand pointers of the objective.
@@ -744,8 +750,8 @@ __device__ __noinline__ void factor_cols(int64_t n, int64_t lda, int64_t m, int 
 template <typename T, int KB, int OPK, int NT, bool GRAD, bool CACHE>
 __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, const T* __restrict__ gv,
                             T* __restrict__ gout, const T* __restrict__ B, const T* __restrict__ Zin,
-                            T* __restrict__ Zout, double* part, double* smem, const CsrCache<T>& cc,
-                            lds<char>* xs, Team tm) {
+                            T* __restrict__ Zout, const T* Zprev, double* part, double* smem,
+                            const CsrCache<T>& cc, lds<char>* xs, Team tm) {
   using SH = StepShape<T, KB, OPK, NT>;
   constexpr int ROWS = SH::ROWS, RPW = SH::RPW;
   using SM = ApplySmem<T, KB, ROWS, SH::GWROWS>;
@@ -754,10 +760,13 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
   constexpr int WAVES = NT / 64;
   constexpr int SE = (ROWS * KB + NT - 1) / NT;  // staged elements per thread
   static_assert(!GRAD || OPK == OP_CSR, "the fused gradient is the masked (CSR) objective's");
-  T* tb = reinterpret_cast<T*>(smem + SM::PLEN);
+  T* tb = reinterpret_cast<T*>(smem + SM::ACC);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r = cfg.r;
   const int64_t n = cfg.n;
+  // explicit residuals of the previous Rayleigh-Ritz sweep: this sweep's
+  // input Zin is that sweep's output, Zprev its input
+  const bool xr = SM::XR && cfg.xres && ctl->xvalid;
   // per-sweep coefficients
   for (int e = tid; e < KB * KB; e += NT) {
     const int i = e / KB, j = e % KB;
@@ -766,7 +775,7 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
     tb[SM::T_PW + e] = (i < r) ? (T)ctl->PW[e] : (T)0;
   }
   if (tid < KB) tb[SM::T_CE + tid] = (T)ctl->ceff[tid];
-  for (int e = tid; e < SM::PLEN; e += NT) smem[e] = 0.0;
+  for (int e = tid; e < SM::ACC; e += NT) smem[e] = 0.0;
   const T opscale = (T)ctl->opscale, sdiag = (T)ctl->sdiag;
   T alpha = 0, dl = 0;
   if constexpr (GRAD) {
@@ -780,16 +789,20 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
     const int64_t row0 = blk * ROWS;
     // this block's rows of Zin and B: loads issued now, stored to LDS after
     // the gathers below (their latency overlaps)
-    T pz[SE], pb[SE];
+    T pz[SE], pb[SE], pp[SE];
 #pragma unroll
     for (int u = 0; u < SE; ++u) {
       const int e = tid + u * NT;
       const int64_t i = row0 + e / KB;
       pz[u] = 0;
       pb[u] = 0;
+      pp[u] = 0;
       if (e < ROWS * KB && i < n) {
         pz[u] = Zin[i * KB + e % KB];
         pb[u] = B[i * KB + e % KB];
+        // Zprev may be the block this sweep writes (its row i is read here,
+        // before this block's rows are written, and by no other workgroup)
+        if (SM::XR && xr) pp[u] = Zprev[i * KB + e % KB];
       }
     }
     __syncthreads();  // previous block's LDS reads are done; coefficients are visible
@@ -1031,6 +1044,26 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
       tb[SM::T_U + e] = z;
     }
     __syncthreads();
+    if (SM::XR && xr) {
+      // residual block of the previous sweep's Ritz pairs, row-wise:
+      // Zin_i S - Zprev_i (W S Theta) (zero beyond n); S and W S Theta are
+      // read from the control block (L2), Zprev's rows take the T_B rows
+#pragma unroll
+      for (int u = 0; u < SE; ++u) {
+        const int e = tid + u * NT;
+        if (e < ROWS * KB) tb[SM::T_B + e] = pp[u];
+      }
+      __syncthreads();
+      for (int e = tid; e < ROWS * KB; e += NT) {
+        const int rr = e / KB, c = e % KB;
+        T v = 0;
+#pragma unroll 8
+        for (int a = 0; a < KB; ++a)
+          v += tb[SM::T_ZIN + rr * KB + a] * (T)ctl->XS[a * KB + c] - tb[SM::T_B + rr * KB + a] * (T)ctl->XWT[a * KB + c];
+        tb[SM::T_ZO + e] = v;
+      }
+      __syncthreads();
+    }
     // FP64 Gram partials (products of working-precision values are exact)
     for (int e = tid; e < KB * KB; e += NT) {
       const int a = e / KB, c = e % KB;
@@ -1045,6 +1078,14 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
       smem[e] += cz;
       smem[KB * KB + e] += gg;
       smem[2 * KB * KB + e] += p;
+      if (SM::XR && xr && e < KB) {
+        double q = 0.0;
+        for (int rr = 0; rr < ROWS; ++rr) {
+          const double v = (double)tb[SM::T_ZO + rr * KB + e];
+          q += v * v;
+        }
+        smem[SM::PLEN + e] += q;
+      }
     }
   }
   // the objective's partials, in a fixed order (waves, then lanes)
@@ -1071,6 +1112,8 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
     dst[SM::PLEN] = sg;
     dst[SM::PLEN + 1] = sx;
   }
+  if constexpr (SM::XR != 0)
+    if (tid < KB) dst[SM::XOFF + tid] = xr ? smem[SM::PLEN + tid] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1206,6 +1249,8 @@ __device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl,
       const bool grad = masked && s == 1;
       T* Zin = zbuf(Z0, Z1, Z2, in);
       T* Zout = zbuf(Z0, Z1, Z2, out);
+      // the previous sweep's input (explicit residuals; read from sweep 2 on)
+      const T* Zprev = zbuf(Z0, Z1, Z2, (s <= 2) ? src : (((s - 1) % 2 == 0) ? o1 : o2));
       stamp_wg(b, tm, s, 0);
       if constexpr (OPK == OP_FACTOR) {
         // first pass over the minibatch; in sweep 1 also the residuals and
@@ -1231,13 +1276,13 @@ __device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl,
       }
       if constexpr (OPK == OP_CSR) {
         if (grad)
-          apply_phase<T, KB, OPK, NT, true, CACHE>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc,
+          apply_phase<T, KB, OPK, NT, true, CACHE>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, Zprev, b.part, smem, cc,
                                                    (lds<char>*)xstage, tm);
         else
-          apply_phase<T, KB, OPK, NT, false, CACHE>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, b.part, smem, cc,
+          apply_phase<T, KB, OPK, NT, false, CACHE>(cfg, ctl, dat, gvals, g, Bm, Zin, Zout, Zprev, b.part, smem, cc,
                                                     (lds<char>*)xstage, tm);
       } else {
-        apply_phase<T, KB, OPK, NT, false, false>(cfg, ctl, dstep, gvals, g, Bm, Zin, Zout, b.part, smem, cc,
+        apply_phase<T, KB, OPK, NT, false, false>(cfg, ctl, dstep, gvals, g, Bm, Zin, Zout, Zprev, b.part, smem, cc,
                                                   (lds<char>*)xstage, tm);
       }
       stamp_wg(b, tm, s, 1);

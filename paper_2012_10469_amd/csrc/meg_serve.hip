@@ -256,7 +256,7 @@ meg_status setup_instance(meg_server s, const meg_request& q, const double* V0, 
   cfg.eps_pow = q.eps_pow;
   cfg.inner_tol = 1e-6;
   cfg.unit_round = 5.9604644775390625e-08;
-  cfg.cert_tol = 0.0;
+  cfg.cert_tol = 0.0;  // resolve the (r+1)-th pair when the stop rule could act on it
   // control block: X_1 = (1 - eps_0) X_0 + (eps_0 / n) I (Algorithm 2, initialisation)
   Ctl h;
   std::memset(&h, 0, sizeof(h));
@@ -534,7 +534,7 @@ meg_status retire(meg_server s) {
     o.mu_r1 = in.mu_r1;
     o.sigma = in.sigma;
     o.converged = in.converged;
-    o.reserved = 0;
+    o.cert_resolved = in.cert_resolved;
     o.resid_r1 = in.resid_r1;
     q.iters = h.t - 1;
     q.state = bad ? 3 : 2;

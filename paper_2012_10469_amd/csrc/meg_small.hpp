@@ -418,7 +418,7 @@ __device__ inline double grad_bound(const Cfg& cfg, double alpha, double dl, dou
 struct SolveScalars {
   double alpha, sigma, solve_tol, f, pxnorm, op_lmin, op_lmax, dl;  // dl: d_l of this lane (l < r)
   int64_t t, iters, applies, jacobi;
-  int fvalid, pxvalid, polish;
+  int fvalid, pxvalid, polish, xvalid;
 };
 __device__ __forceinline__ SolveScalars load_scalars(const Cfg& cfg, const gbl<Ctl>* ctl, int lane) {
   SolveScalars s;
@@ -437,6 +437,7 @@ __device__ __forceinline__ SolveScalars load_scalars(const Cfg& cfg, const gbl<C
   s.fvalid = ctl->fvalid;
   s.pxvalid = ctl->pxvalid;
   s.polish = ctl->polish;
+  s.xvalid = ctl->xvalid;
   return s;
 }
 
@@ -445,8 +446,9 @@ __device__ __forceinline__ SolveScalars load_scalars(const Cfg& cfg, const gbl<C
 // (LDS) holds the sorted Ritz values of Yhat, rho their residuals.  One
 // wavefront.
 __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<double>* theta, const lds<double>* rho,
-                                   double resid_max, int sweeps, int converged, double eps, const SolveScalars& sc,
-                                   int lane, double& d_out, double& c_out, double& alpha_out) {
+                                   double resid_max, int sweeps, int converged, int resolved, double margin,
+                                   double eps, const SolveScalars& sc, int lane, double& d_out, double& c_out,
+                                   double& alpha_out) {
   const int r = cfg.r;
   const double n = (double)cfg.n;
   const double alpha = sc.alpha, sigma = sc.sigma, solve_tol = sc.solve_tol;
@@ -488,17 +490,21 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
     in.eps_t = eps;
     in.cert_L = L;
     in.cert_bound = fmax(2.0 * eps, L);
-    in.cert_holds = (L <= 2.0 * eps) ? 1 : 0;
+    // L from the Ritz values is a lower bound of the exact L; with a resolved
+    // (r+1)-th pair L + margin is an upper one, on which claims are made.
+    const double L_up = L + margin;
+    in.cert_holds = (resolved && L_up <= 2.0 * eps) ? 1 : 0;
+    in.cert_resolved = resolved;
     in.inner_iters = sweeps;
     in.ritz_gap = mu_r - mu_r1;
     in.resid_max = resid_max;
-    in.resid_r1 = rho[r];
+    in.resid_r1 = margin;
     in.mu_r1 = mu_r1;
     in.sigma = sigma;
     in.converged = converged;
     in.f = sc.fvalid ? sc.f : __builtin_nan("");
     if (!all_ok) ctl->status = 4;  // MEG_ERR_NUMERIC
-    if (solve_tol > 0.0 && in.cert_bound <= solve_tol) ctl->stop = 1;
+    if (solve_tol > 0.0 && resolved && fmax(2.0 * eps, L_up) <= solve_tol) ctl->stop = 1;
   }
 }
 
@@ -543,6 +549,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     if (lane == 0) {
       ctl->sweep = sweep + 1;
       ctl->applies_done = applies + 1;
+      ctl->xvalid = 0;
     }
     return false;
   }
@@ -635,11 +642,20 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   // Residuals come from Ghat_ii - theta_i^2 in FP64: resolvable down to
   // ~sqrt(2^-53) of the scale; working-precision rounding sets another floor.
   const double floor_est = fmax(3e-8, 8.0 * cfg.unit_round) * scale;
-  const double thr = fmax(cfg.inner_tol * scale, floor_est);
+  const double tol_abs = cfg.inner_tol * scale;
+  const double thr = fmax(tol_abs, floor_est);
+  // Below that floor (FP64 state) the test also needs the explicit residuals
+  // ||Zout s_i - theta_i Q s_i|| of the previous sweep's pairs, which this
+  // sweep's apply formed from its rows; this sweep's pairs are one power
+  // step further on.  Their floor is the apply's rounding.
+  const bool exact = cfg.xres && tol_abs < floor_est;
+  const double xthr = fmax(tol_abs, 64.0 * cfg.unit_round * scale);
+  const double xr = (exact && sc.xvalid && lane < KB) ? sqrt(fmax(sums[3 * KB * KB + 2 + lane], 0.0))
+                                                      : __builtin_inf();
   const double rmax = wave_max(lane < r ? rh : 0.0);
   const bool finite = wave_min((lane < KB) ? ((isfinite(th) && isfinite(rh)) ? 1.0 : 0.0) : 1.0) > 0.5;
   const double rr1 = lane_f64(rh, r);
-  const bool cert_ok = !(cfg.cert_tol > 0.0) || rr1 <= fmax(cfg.cert_tol, floor_est);
+  const double xr1 = lane_f64(xr, r);
   // A top-r pair enters X_{t+1} = alpha' I + V diag(d') V^T only through
   // d'_l v_l v_l^T: even an entirely wrong v_l moves X by at most
   // sqrt(2) |d'_l|, i.e. sqrt(2) w_l of ||X||_F with w_l = |d'_l| / max |d'|.
@@ -654,11 +670,38 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   const double dl_new = (lane < r) ? (1.0 - eps_t) * ex / esum - eps_t / (double)(cfg.n - r) : 0.0;
   const double dmax = wave_max(fabs(dl_new));
   const bool light = dmax > 0.0 && fabs(dl_new) <= 0.25 * cfg.inner_tol * dmax;
-  const bool pair_ok = lane >= r || rh <= thr || light;
-  bool conv = wave_min(pair_ok ? 1.0 : 0.0) > 0.5 && cert_ok;
+  const bool pair_ok = lane >= r || light || (rh <= thr && (!exact || xr <= xthr));
+  // Certificate L_t = log(n-r) - log eps_t + mu_{r+1} - LSE(mu_1..mu_{r+1}).
+  // The Ritz values are lower bounds of the eigenvalues (interlacing) and
+  // dL/dmu_{r+1} = 1 - softmax_{r+1} lies in [0, 1] (dL/dmu_i <= 0, i <= r),
+  // so L from the Ritz values is a lower bound of the exact L.  A Ritz value
+  // is within its residual of SOME eigenvalue; inside a cluster that need not
+  // be lambda_{r+1}.  The (r+1)-th pair counts as resolved when its residual
+  // bound rho (the estimate, not below its floor, or the explicit residual of
+  // the previous sweep's pair) meets the tolerance and is at most a quarter
+  // of the gap to theta_{r+2}: the Ritz value is then isolated, and L + rho
+  // bounds the exact L from above.  Only then is a certificate claimed.
+  const double mu1 = (lane <= r) ? th + log(sc.alpha) - sc.sigma : -__builtin_inf();
+  const double m1 = wave_max(mu1);
+  const double lse1 = m1 + log(wave_sum((lane <= r) ? exp(mu1 - m1) : 0.0));
+  const double L_lo = log((double)(cfg.n - r)) - log(eps_t) + lane_f64(mu1, r) - lse1;
+  const double margin = fmin(fmax(rr1, floor_est), exact ? xr1 : __builtin_inf());
+  const double sep = (r + 2 <= KB) ? lane_f64(th, r) - lane_f64(th, r + 1 < KB ? r + 1 : r) : 0.0;
+  const double cthr = cfg.cert_tol > 0.0 ? fmax(cfg.cert_tol, exact ? 64.0 * cfg.unit_round * scale : floor_est)
+                                         : (exact ? xthr : thr);
+  const bool resolved = margin <= cthr && margin <= 0.25 * sep;
+  // The pair is iterated further, until resolved or max_inner, always for
+  // cert_tol > 0, and for a stopping rule (meg_solve's or a server's tol)
+  // while its lower bound of L could pass: otherwise the step takes no
+  // sweeps for it and claims nothing while it is unresolved.
+  const bool pending = sc.solve_tol > 0.0 && !(L_lo > fmax(2.0 * eps_t, sc.solve_tol));
+  const bool cert_ok = resolved || !(cfg.cert_tol > 0.0 || pending);
+  const bool top_ok = wave_min(pair_ok ? 1.0 : 0.0) > 0.5;
+  bool conv = top_ok && cert_ok;
   bool do_polish = false;
-  // tolerance below the resolvable floor: two more sweeps once it is reached
-  if (conv && cfg.inner_tol * scale < floor_est && polish < 2) {
+  // tolerance below the resolvable floor without explicit residuals (FP32
+  // state): two more sweeps once it is reached
+  if (conv && !cfg.xres && tol_abs < floor_est && polish < 2) {
     do_polish = true;
     conv = false;
   }
@@ -678,7 +721,8 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     const double a_old = sc.alpha;
     const double d_old = sc.dl;
     double d_new, c_new, a_new;
-    finish_step(cfg, ctl, theta, rho, rmax, sweep, conv ? 1 : 0, eps_t, sc, lane, d_new, c_new, a_new);
+    finish_step(cfg, ctl, theta, rho, rmax, sweep, (top_ok && (resolved || !(cfg.cert_tol > 0.0))) ? 1 : 0,
+                resolved ? 1 : 0, margin, eps_t, sc, lane, d_new, c_new, a_new);
     // Ritz vectors of span(Q): Q S = Zin (W S), the next warm start; its
     // first sweep uses W = Wb and PW = V^T Q = [I_r 0]
 #pragma unroll
@@ -733,6 +777,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
       ctl->done = 0;
       ctl->sweep = 1;
       ctl->polish = 0;
+      ctl->xvalid = 0;
     }
     if (cfg.kind != QUADMEAS) {  // the minibatch bound is set inside the next step's first sweep
       const double gmax =
@@ -741,6 +786,24 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     }
     if (prof) ts[kTsRR + 3] = wall_clock64();
     return true;
+  }
+  if (cfg.xres) {
+    // for the next sweep's explicit residuals: S and W S Theta
+#pragma unroll
+    for (int u = 0; u < WE; ++u) {
+      const int e = lane + 64 * u;
+      B2[(e / KB) * LD + (e % KB)] = wreg[u];
+    }
+    wsync();
+    mm_nn<KB>(B2, B1, A, lane);
+    wsync();
+    for (int e = lane; e < KB * KB; e += 64) {
+      const int i = e / KB, j = e % KB;
+      ctl->XS[e] = B1[i * LD + j];
+      ctl->XWT[e] = A[i * LD + j] * theta[j];
+    }
+    if (lane == 0) ctl->xvalid = 1;
+    wsync();
   }
   // Next basis Q' = Zout S R^{-1} with Ghat = R^T R (Cholesky QR, FP64) and
   // PW' = V^T Q' = P S R^{-1}
@@ -784,6 +847,7 @@ __device__ __noinline__ void basis_setup(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     ctl->done = 0;
     ctl->sweep = 1;
     ctl->polish = 0;
+    ctl->xvalid = 0;
   }
 }
 

@@ -86,7 +86,7 @@ class MegStepInfo(ctypes.Structure):
         ("t", ctypes.c_int64), ("f", ctypes.c_double), ("eps_t", ctypes.c_double), ("cert_L", ctypes.c_double),
         ("cert_bound", ctypes.c_double), ("cert_holds", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
         ("ritz_gap", ctypes.c_double), ("resid_max", ctypes.c_double), ("mu_r1", ctypes.c_double),
-        ("sigma", ctypes.c_double), ("converged", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("sigma", ctypes.c_double), ("converged", ctypes.c_int32), ("cert_resolved", ctypes.c_int32),
         ("resid_r1", ctypes.c_double),
     ]
 

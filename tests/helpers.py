@@ -12,6 +12,29 @@ from oracle import meg_oracle as O
 TOL_X = {0: 1e-9, 1: 1e-5, 2: 1e-3}
 TOL_F = 1e-6
 UNIT = {0: 2.0 ** -53, 1: 2.0 ** -24, 2: 2.0 ** -24}
+# |cert_L - L_oracle| once the (r+1)-th Ritz pair is resolved
+TOL_CERT = {0: 1e-8, 1: 1e-4, 2: 1e-4}
+
+
+def check_certificate(info, L_ref, eps_ref, prec):
+    """The step's certificate against the oracle's L_t (exact eigenvalues).
+
+    cert_L comes from the Ritz values: the (r+1)-th one is a lower bound of
+    mu_{r+1} (interlacing) and L does not decrease with it, so cert_L is a
+    lower bound of the oracle's L.  Resolved (r+1)-th pair: cert_L within
+    TOL_CERT of the oracle's, and cert_L + resid_r1 an upper bound.  In every
+    case a claimed certificate holds for the oracle too: cert_holds is never 1
+    where the exact L_t > 2 eps_t."""
+    tol = TOL_CERT[prec]
+    L = info["cert_L"]
+    assert L <= L_ref + tol, ("lower bound", L, L_ref)
+    if info["cert_resolved"]:
+        assert abs(L - L_ref) <= tol, ("resolved", L, L_ref)
+        assert L_ref <= L + info["resid_r1"] + tol, ("upper bound", L, info["resid_r1"], L_ref)
+    else:
+        assert not info["cert_holds"]
+    if info["cert_holds"]:
+        assert L_ref <= 2.0 * eps_ref, ("claim the oracle does not make", L, L_ref, eps_ref)
 
 
 def torch_dtype(prec):
@@ -84,3 +107,16 @@ def gapped_spiked(n, rank, seed, noise=0.01):
     V0 = V[:, ::-1][:, :rank].copy()
     lam0 = np.full(rank, 1.0 / rank)
     return M, V0, lam0
+
+
+def isolated_linear(n, r, seed):
+    """Linear objective f = <C, X>, C = U diag(c) U^T: c_1..c_r on [0, 0.5],
+    c_{r+1} = 2, the rest on [3, 4], so the (r+1)-th eigenvalue of M_t is
+    isolated (eta apart from the others) and its Ritz pair resolves; start on
+    U[:, :r] with equal weights."""
+    rng = np.random.default_rng([79, seed, n])
+    U, R = np.linalg.qr(rng.standard_normal((n, n)))
+    U = U * np.sign(np.diag(R))
+    c = np.concatenate([np.sort(0.5 * rng.random(r)), [2.0], 3.0 + np.sort(rng.random(n - r - 1))])
+    C = (U * c) @ U.T
+    return 0.5 * (C + C.T), U[:, :r].copy(), np.full(r, 1.0 / r)

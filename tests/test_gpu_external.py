@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 from oracle import meg_oracle as O
-from tests.helpers import TOL_X, dev, gapped_spiked, np_dtype, rel_x_err
+from tests.helpers import TOL_X, check_certificate, dev, gapped_spiked, np_dtype, rel_x_err
 
 pytestmark = pytest.mark.gpu
 
@@ -82,7 +82,7 @@ def test_external_dense_denoising(meg, prec, n, rank):
                   f"sigma={info['sigma']:.4f} L={info['cert_L']:.4e}/{ri['L']:.4e}", flush=True)
             assert info["t"] == t and math.isnan(info["f"])
             check_shift(info, Gq, eta, it, rank)
-            assert abs(info["cert_L"] - ri["L"]) <= (1e-8 if prec == 0 else 1e-4) + 2.0 * info["resid_r1"]
+            check_certificate(info, ri["L"], O.eps_schedule(t), prec)
             assert err <= TOL_X[prec]
     finally:
         g.close()
@@ -122,7 +122,7 @@ def test_external_masked_changing_pattern(meg, prec, n, rank, p):
             print(f"  t={t} {'csr' if t % 2 else 'dense'} nnz={int(np.count_nonzero(Gq))} err={err:.2e} "
                   f"gap={ri['gap']:.3f} sweeps={info['inner_iters']} sigma={info['sigma']:.4f}", flush=True)
             check_shift(info, Gq, eta, it, rank)
-            assert abs(info["cert_L"] - ri["L"]) <= (1e-8 if prec == 0 else 1e-4) + 2.0 * info["resid_r1"]
+            check_certificate(info, ri["L"], O.eps_schedule(t), prec)
             assert err <= TOL_X[prec]
     finally:
         g.close()

@@ -21,7 +21,7 @@ import pytest
 
 import workloads as W
 from oracle import meg_oracle as O
-from tests.helpers import TOL_X, dev, f_tol, rel_x_err
+from tests.helpers import TOL_X, check_certificate, dev, f_tol, rel_x_err
 
 pytestmark = pytest.mark.gpu
 
@@ -63,12 +63,10 @@ def test_matrix_completion_full_size(meg):
             assert abs(info["f"] - f_ref) <= f_tol(f_ref, np.linalg.norm(G), np.linalg.norm(X), 1)
             assert info["converged"] == 1
             assert err <= TOL_X[1]
-            # mu_{r+1} is the (r+1)-th Ritz value: by interlacing not above the
-            # true eigenvalue, so the GPU certificate is never more pessimistic;
-            # with r = 10 > rank 5 that eigenvalue lies in the bulk of the
-            # spectrum, known only to within the bulk's width
-            dL = info["cert_L"] - ri["L"]
-            assert -0.1 <= dL <= 1e-5 + 2.0 * info["resid_max"]
+            # with r = 10 > rank 5, lambda_{r+1} lies in the bulk of the
+            # spectrum: the certificate is far from holding, its lower bound
+            # already rules it out, and the pair is left unresolved
+            check_certificate(info, ri["L"], O.eps_schedule(t), 1)
 
         teacher_forced_step()  # from the warm start (t = 1)
         teacher_forced_step()

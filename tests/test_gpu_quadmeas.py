@@ -16,7 +16,7 @@ import pytest
 
 import workloads as W
 from oracle import meg_oracle as O
-from tests.helpers import TOL_X, UNIT, dev, f_tol, np_dtype, rel_x_err
+from tests.helpers import TOL_X, UNIT, check_certificate, dev, f_tol, np_dtype, rel_x_err
 
 pytestmark = pytest.mark.gpu
 
@@ -111,9 +111,7 @@ def test_quadmeas_teacher_forced(meg, n, lda, m, L, bsteps, r, prec):
                   f"sweeps={info['inner_iters']} conv={info['converged']} sigma={info['sigma']:.4f}", flush=True)
             assert abs(info["f"] - f_ref) <= ftol
             check_step(info, it, Fm, c, eta, n, prec, r)
-            # mu_{r+1} enters the certificate; its Ritz value is within the
-            # residual of the (r+1)-th pair when that pair stops short of cert_tol
-            assert abs(info["cert_L"] - ri["L"]) <= (1e-4 if prec else 1e-8) + 2.0 * info["resid_r1"]
+            check_certificate(info, ri["L"], O.eps_schedule(t), prec)
             assert err <= TOL_X[prec]
     finally:
         g.close()

@@ -16,7 +16,7 @@ import pytest
 
 import workloads as W
 from oracle import meg_oracle as O
-from tests.helpers import TOL_X, gapped_spiked, rel_x_err
+from tests.helpers import TOL_X, gapped_spiked, isolated_linear, rel_x_err
 
 pytestmark = pytest.mark.gpu
 
@@ -182,16 +182,28 @@ def test_serving_stop_rule_and_rejects(meg):
 
     n, r = 256, 1
     M, V, l = _instance(20, n, r)
+    # the stop rule: a linear instance whose (r+1)-th eigenvalue is isolated,
+    # so the certificate resolves (it is claimed only on a resolved pair)
+    C, VC, lC = isolated_linear(n, r, seed=20)
     with meg.MegServer(launch_steps=8) as srv:
         dM = device_f32(M)
+        dC = device_f32(C)
         torch.cuda.synchronize()
         tol = 1e-3
-        rid = srv.submit(dM, V, l, r, max_iters=300, tol=tol)
+        rid = srv.submit(dC, VC, lC, r, kind=meg.MEG_GRAD_LINEAR_DENSE, max_iters=300, tol=tol)
         drain(srv)
         st = srv.query(rid)
         print_case(test="serving_stop", iterations=st["iterations"], bound=st["last"]["cert_bound"])
-        assert st["state"] == 2 and st["iterations"] < 300
-        assert st["last"]["cert_bound"] <= tol
+        # 2 eps_t <= 1e-3 from t = 29 on
+        assert st["state"] == 2 and 29 <= st["iterations"] < 60
+        assert st["last"]["cert_resolved"] == 1 and st["last"]["cert_bound"] <= tol
+        assert st["last"]["cert_L"] + st["last"]["resid_r1"] <= tol
+        # a spiked instance (noise bulk below lambda_{r+1}): the pair stays
+        # unresolved, no certificate is claimed, the request runs to its cap
+        rid2 = srv.submit(dM, V, l, r, max_iters=40, tol=tol)
+        drain(srv)
+        st2 = srv.query(rid2)
+        assert st2["state"] == 2 and st2["iterations"] == 40 and st2["last"]["cert_holds"] == 0
         with pytest.raises(meg.MegError) as e:
             srv.submit(dM, V, l, 12)  # k = 32: not served
         assert e.value.status == meg.MEG_ERR_UNSUPPORTED

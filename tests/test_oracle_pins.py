@@ -615,14 +615,14 @@ def test_recovery_run_matches_table1_rank1_n100():
     assert ref["dual_gap"] / 1.6 <= dual <= 1.6 * ref["dual_gap"]
 
 
-def test_recovery_rank_above_matches_table2():
-    """Table 2 (n = 200, rank(M) = 1, rank parameter r = 3; m = 20 n rank(M),
+def test_recovery_rank_above_matches_table3():
+    """Table 3 (n = 200, rank(M) = 1, rank parameter r = 3; m = 20 n rank(M),
     beta = 0.4 sqrt(r n), the start's block U with r columns): the mean first
     iteration of the all-eigenvalue certificate over 10 instances is within
     35 % of the table's 2."""
     import workloads as W
 
-    ref = json.load(open(os.path.join(GOLDEN, "table2_rank_above.json")))["rows"][0]
+    ref = json.load(open(os.path.join(GOLDEN, "table3_rank_above.json")))["rows"][0]
     firsts = []
     for seed in range(10):
         p = W.bilinear_recovery(200, ref["rank"], seed, r=ref["r"])

@@ -474,9 +474,9 @@ class BilinearProblem:
 def bilinear_recovery(n: int, rank: int, seed: int, kappa: float = 0.5, r: Optional[int] = None,
                       m_rank: Optional[int] = None, p: int = 1, beta_coeff: float = 0.4) -> BilinearProblem:
     """``r``: the rank parameter when it exceeds rank(M) (the start's block U
-    has r columns; Table 2); ``m_rank``: the rank in m = 20 n m_rank
+    has r columns; Table 3); ``m_rank``: the rank in m = 20 n m_rank
     (default rank(M)); ``p`` > 1: measurement matrices A_i, B_i (n x p) with
-    orthonormal columns, y0_i = tr(A_i^T M B_i) (Table 3, which also takes
+    orthonormal columns, y0_i = tr(A_i^T M B_i) (Table 4, which also takes
     beta = 12 sqrt(r n): ``beta_coeff`` = 12)."""
     r = rank if r is None else r
     g = rng(11, seed, n, rank)
