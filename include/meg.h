@@ -186,8 +186,7 @@ typedef struct {
                          the Ritz values: a lower bound of the exact value,
                          and within resid_r1 of it when cert_resolved        */
   double cert_bound;  /* max(2 eps_t, cert_L): bound of the error lemma       */
-  int32_t cert_holds; /* cert_resolved and cert_L + resid_r1 <= 2 eps_t: the
-                         exact certificate holds                              */
+  int32_t cert_holds; /* cert_L_up <= 2 eps_t: the exact certificate holds   */
   int32_t inner_iters;/* subspace sweeps used                                 */
   double ritz_gap;    /* mu_r - mu_{r+1} (eigenvalues of M_t)                 */
   double resid_max;   /* max Ritz residual over the top r pairs               */
@@ -197,6 +196,12 @@ typedef struct {
   int32_t cert_resolved; /* the (r+1)-th Ritz pair is resolved (cert_tol)   */
   double resid_r1;    /* residual bound of the (r+1)-th Ritz pair; resolved:
                          the exact L lies in [cert_L, cert_L + resid_r1]     */
+  double cert_L_up;   /* upper bound of the exact L on which cert_holds and
+                         the stopping rules act: cert_L + resid_r1 for a
+                         resolved pair, or the bound armed by
+                         meg_certificate_bound for this step (the smaller);
+                         +inf without either                                 */
+  double mu_r1_up;    /* the upper bound of mu_{r+1} behind cert_L_up         */
 } meg_step_info;
 
 /* Block size k used for (r, oversample); returns 0 when k would exceed 32. */
@@ -338,6 +343,30 @@ typedef struct {
 
 meg_status meg_dual_gap(meg_ctx ctx, int32_t max_steps, double tol, meg_dual_gap_info* out);
 
+/* An upper bound of mu_{r+1}, the (r+1)-th eigenvalue of M_t = log X_t -
+ * eta grad f(X_t) at the CURRENT iterate (the matrix the next meg_step
+ * decomposes), for the certificate of Section 3.1.1.  log X_t = log(alpha) I
+ * + V diag(c) V^T vanishes on the orthogonal complement of V beyond the
+ * identity, so by the Courant-Fischer theorem
+ *   mu_{r+1} <= log alpha - eta lambda_min(G restricted to V's complement);
+ * that lambda_min comes from a Lanczos run on the complement (the run of
+ * meg_dual_gap with every vector also orthogonalised against V), lowered by
+ * its Ritz residual.  The bound is armed for the next step: its cert_L_up
+ * (hence cert_holds and meg_solve's stop) may use it.  It is sharp when V
+ * spans the top-r eigenvectors of M_t, i.e. once the iterates settle.
+ * Objectives as meg_dual_gap; MEG_ERR_INVALID_ARG for max_steps < 1, tol < 0
+ * or out == NULL.  Uses the context's Lanczos workspace.  Synchronises. */
+typedef struct {
+  double mu_up;           /* the bound                                          */
+  double lambda_min_defl; /* smallest Ritz value of G on V's complement          */
+  double resid;           /* its Ritz residual                                   */
+  int64_t t;              /* the iteration whose step it is armed for            */
+  int32_t steps;          /* Lanczos steps taken                                 */
+  int32_t converged;      /* resid <= tol * max |Ritz value|                     */
+} meg_cert_bound_info;
+
+meg_status meg_certificate_bound(meg_ctx ctx, int32_t max_steps, double tol, meg_cert_bound_info* out);
+
 /* Iterate until the dual gap of the current iterate is <= tol (the stopping
  * rule of Section 7's measure) or max_iters iterations are done: the gap is
  * evaluated first, then after every check_every iterations (1..64, launched
@@ -404,9 +433,11 @@ meg_status meg_trace_exp(meg_ctx ctx, const double* probes, int32_t p, double we
 /* The certificate with an estimate of b_n in place of b^{r+1} (Section 3.1.1):
  *   L_full = log((n - r) lambda_{r+1}(Y_t) / (eps_t b_n))
  *          = log(n - r) + mu_{r+1} - log eps_t - log_b,
- * from the most recent step's mu_{r+1} and eps_t and tr->log_b, which must be
- * the estimate for that step's M_t (meg_trace_exp called at the iterate the
- * step started from: tr->t equals the step's t).  *holds = L_full <= 2 eps_t.
+ * from the most recent step's mu_{r+1} (its Ritz value, a lower bound) and
+ * eps_t and tr->log_b, which must be the estimate for that step's M_t
+ * (meg_trace_exp called at the iterate the step started from: tr->t equals
+ * the step's t).  *holds = 1 when L_full with the step's upper bound of
+ * mu_{r+1} (meg_step_info.mu_r1_up) is <= 2 eps_t; never without one.
  * MEG_ERR_INVALID_ARG when no step has run since, when tr->t differs, or for
  * NULL pointers.  No kernel runs. */
 meg_status meg_certificate_full(meg_ctx ctx, const meg_trace_info* tr, double* cert_L_full, int32_t* holds);

@@ -24,7 +24,9 @@ using namespace meg;
 
 namespace {
 
+
 constexpr uint32_t kStateMagic = 0x4d454731u;  // "MEG1"
+
 constexpr int kStepNT = 512;                   // threads per persistent workgroup
 constexpr int kMaxWgPerCu = 2;
 constexpr int kMaxGrid = kBarGroupSize * kBarMaxGroups;  // barrier capacity
@@ -49,6 +51,8 @@ struct meg_ctx_s {
   Ctl* ctl = nullptr;
   double* part = nullptr;
   double* lz_prev = nullptr;  // the dual gap's last lambda_min Ritz vector (n doubles), its next start
+  double* lz_ws = nullptr;    // Lanczos workspace of the gradient's lambda_min runs (kept, grown on demand)
+  size_t lz_ws_doubles = 0;
   double* gpart = nullptr;
   double* sums = nullptr;
   unsigned* bar = nullptr;
@@ -75,6 +79,7 @@ struct meg_ctx_s {
   double* bil_P = nullptr;    // bilinear: per-slice partial gradients (bil_S x tile pairs x 64 x 64)
   int bil_S = 1;
   bool failed = false;
+  int device = 0;  // the device current at meg_init
 };
 
 namespace {
@@ -524,6 +529,29 @@ meg_status copy_ctl_to_host(meg_ctx c) {
   return MEG_OK;
 }
 
+// Workspace of a Lanczos run for the smallest eigenvalue of the gradient,
+// in doubles: the basis V ((m + 1) x n), y, w and the product input x (n
+// each; x holds n elements of the state's type), reorthogonalisation
+// coefficients h (m + 1), alpha/beta ab (2m), deflation coefficients lp (KMAX).
+struct LzWs {
+  double *V, *y, *w, *x, *h, *ab, *lp;
+};
+int lz_steps(int64_t n, int defl, int max_steps) { return (int)std::min<int64_t>(n - defl, max_steps); }
+size_t lz_ws_need(int64_t n, int m) {
+  return (size_t)(m + 1) * n + 3 * (size_t)n + (size_t)(m + 1) + 2 * (size_t)m + KMAX;
+}
+LzWs lz_ws_carve(double* base, int64_t n, int m) {
+  LzWs ws;
+  ws.V = base;
+  ws.y = ws.V + (size_t)(m + 1) * n;
+  ws.w = ws.y + n;
+  ws.x = ws.w + n;
+  ws.h = ws.x + n;
+  ws.ab = ws.h + (m + 1);
+  ws.lp = ws.ab + 2 * (size_t)m;
+  return ws;
+}
+
 // Smallest eigenvalue of the gradient G = grad f(X_t) by Lanczos with full
 // reorthogonalisation (two classical Gram-Schmidt passes).  The basis, the
 // recurrence and the products with G run on the device (products: k_matvec
@@ -531,42 +559,33 @@ meg_status copy_ctl_to_host(meg_ctx c) {
 // c->g; denoising adds alpha x + V diag(d) V^T x from the materialised
 // basis); the host only draws the start vector and, every 8 steps, solves
 // the small tridiagonal eigenproblem for the convergence test.
+// defl > 0: the run is restricted to the orthogonal complement of the first
+// defl columns of the materialised basis (the iterate's V): the start vector
+// and every new vector are orthogonalised against them too, so the result is
+// lambda_min of G on that complement.  warm: start from (and keep) the
+// context's previous lambda_min Ritz vector (plain runs only).
 template <typename T>
-meg_status lanczos_grad_min(meg_ctx c, int max_steps, double tol, meg_dual_gap_info* out) {
+meg_status lanczos_grad_min(meg_ctx c, int max_steps, double tol, const LzWs& ws, int defl, bool warm,
+                            meg_dual_gap_info* out) {
   const Cfg& cfg = c->cfg;
   const int64_t n = cfg.n;
   const int r = cfg.r, KB = cfg.k;
-  const int m = (int)std::min<int64_t>(n, max_steps);
+  const int m = lz_steps(n, defl, max_steps);
   const bool den = cfg.kind == DENOISE_DENSE;
   const bool masked = cfg.kind == MASKED_CSR;
   const T* Qm = (const T*)block(c, (c->h_ctl->src + 1) % 3);  // materialised basis (xdotg)
-  double *V = nullptr, *y = nullptr, *w = nullptr, *h = nullptr, *ab = nullptr, *lp = nullptr;
-  T* xt = nullptr;
-  auto al = [&](void** q, size_t bytes) { return hipMalloc(q, std::max<size_t>(bytes, 256)) == hipSuccess; };
-  bool ok = al((void**)&V, (size_t)(m + 1) * n * 8) && al((void**)&y, n * 8) && al((void**)&w, n * 8) &&
-            al((void**)&h, (size_t)(m + 1) * 8) && al((void**)&ab, (size_t)2 * m * 8) && al((void**)&lp, KMAX * 8) &&
-            al((void**)&xt, n * sizeof(T));
-  auto release = [&]() {
-    for (void* q : {(void*)V, (void*)y, (void*)w, (void*)h, (void*)ab, (void*)lp, (void*)xt})
-      if (q) (void)hipFree(q);
-  };
-  if (!ok) {
-    (void)hipGetLastError();
-    release();
-    return MEG_ERR_OUT_OF_MEMORY;
-  }
+  double *V = ws.V, *y = ws.y, *w = ws.w, *h = ws.h, *ab = ws.ab, *lp = ws.lp;
+  T* xt = (T*)ws.x;
+  if (m < 1) return MEG_ERR_INVALID_ARG;
   // start vector: the previous call's lambda_min Ritz vector (the gradient
   // changes little between nearby iterates) plus 1e-3 of a seeded Gaussian
   // vector, or the Gaussian vector alone; normalised on the host
   std::vector<double> v0(n);
-  SplitMix rng{c->params.seed ^ 0x6475616c67617021ull ^ (uint64_t)c->h_ctl->t};
+  SplitMix rng{c->params.seed ^ 0x6475616c67617021ull ^ (uint64_t)c->h_ctl->t ^ ((uint64_t)defl << 40)};
   for (int64_t i = 0; i < n; ++i) v0[i] = rng.normal();
-  if (c->lz_prev) {
+  if (warm && c->lz_prev) {
     std::vector<double> u(n);
-    if (hipMemcpy(u.data(), c->lz_prev, n * 8, hipMemcpyDeviceToHost) != hipSuccess) {
-      release();
-      return hip_fail(c);
-    }
+    if (hipMemcpy(u.data(), c->lz_prev, n * 8, hipMemcpyDeviceToHost) != hipSuccess) return hip_fail(c);
     double gn = 0.0;
     for (int64_t i = 0; i < n; ++i) gn += v0[i] * v0[i];
     gn = std::sqrt(gn);
@@ -583,7 +602,20 @@ meg_status lanczos_grad_min(meg_ctx c, int max_steps, double tol, meg_dual_gap_i
   bool conv = false;
   const int gv = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256));
   const hipStream_t sm = c->stream;
-  if (hipMemcpyAsync(V, v0.data(), n * 8, hipMemcpyHostToDevice, sm) != hipSuccess) st = hip_fail(c);
+  // w <- w - Q[:, :defl] (Q[:, :defl]^T w), twice
+  auto deflate = [&](double* vec) {
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL((k_lz_defl_dots<T>), dim3(defl), dim3(256), 0, sm, Qm, KB, (const double*)vec, n, lp);
+      hipLaunchKernelGGL((k_lz_defl_sub<T>), dim3(gv), dim3(256), 0, sm, Qm, KB, defl, (const double*)lp, n, vec);
+    }
+  };
+  if (defl > 0) {
+    if (hipMemcpyAsync(w, v0.data(), n * 8, hipMemcpyHostToDevice, sm) != hipSuccess) st = hip_fail(c);
+    deflate(w);
+    hipLaunchKernelGGL(k_lz_unit, dim3(1), dim3(256), 0, sm, (const double*)w, n, V);
+  } else if (hipMemcpyAsync(V, v0.data(), n * 8, hipMemcpyHostToDevice, sm) != hipSuccess) {
+    st = hip_fail(c);
+  }
   for (int j = 0; st == MEG_OK && j < m; ++j) {
     const double* vj = V + (int64_t)j * n;
     // y = G v_j
@@ -595,7 +627,8 @@ meg_status lanczos_grad_min(meg_ctx c, int max_steps, double tol, meg_dual_gap_i
       hipLaunchKernelGGL((k_lz_lr_update<T>), dim3(gv), dim3(256), 0, sm, (const Ctl*)c->ctl, Qm, KB, r,
                          (const T*)xt, (const double*)lp, n, y);
     }
-    // alpha_j, the three-term recurrence, two reorthogonalisation passes, beta_j and v_{j+1}
+    // alpha_j, the three-term recurrence, two reorthogonalisation passes
+    // (and the deflation), beta_j and v_{j+1}
     hipLaunchKernelGGL(k_lz_dots, dim3(1), dim3(256), 0, sm, vj, (const double*)y, n, ab + j);
     hipLaunchKernelGGL(k_lz_three_term, dim3(gv), dim3(256), 0, sm, (const double*)V, (const double*)y,
                        (const double*)ab, j, m, n, w);
@@ -603,6 +636,7 @@ meg_status lanczos_grad_min(meg_ctx c, int max_steps, double tol, meg_dual_gap_i
       hipLaunchKernelGGL(k_lz_dots, dim3(j + 1), dim3(256), 0, sm, (const double*)V, (const double*)w, n, h);
       hipLaunchKernelGGL(k_lz_sub, dim3(gv), dim3(256), 0, sm, (const double*)V, (const double*)h, j + 1, n, w);
     }
+    if (defl > 0) deflate(w);
     hipLaunchKernelGGL(k_lz_next, dim3(1), dim3(256), 0, sm, (const double*)w, j, m, n, ab, V);
     if (hipGetLastError() != hipSuccess) {
       st = hip_fail(c);
@@ -645,7 +679,7 @@ meg_status lanczos_grad_min(meg_ctx c, int max_steps, double tol, meg_dual_gap_i
     if (conv || invariant) break;
   }
   // keep the Ritz vector V s of lambda_min for the next call's start
-  if (st == MEG_OK && !smin.empty()) {
+  if (st == MEG_OK && warm && !smin.empty()) {
     if (!c->lz_prev && hipMalloc((void**)&c->lz_prev, std::max<size_t>(n * 8, 256)) != hipSuccess) {
       (void)hipGetLastError();
       c->lz_prev = nullptr;  // no warm start next time; not an error
@@ -660,12 +694,32 @@ meg_status lanczos_grad_min(meg_ctx c, int max_steps, double tol, meg_dual_gap_i
       }
     }
   }
-  release();
+  if (st == MEG_OK && hipStreamSynchronize(sm) != hipSuccess) st = hip_fail(c);
   if (st != MEG_OK) return st;
   out->lambda_min = theta;
   out->resid = res;
   out->steps = done;
   out->converged = conv ? 1 : 0;
+  return MEG_OK;
+}
+
+// The context's Lanczos workspace for m steps: allocated on first use and
+// kept (grown when a later call needs more), so repeated calls allocate
+// nothing.
+meg_status ctx_lz_ws(meg_ctx c, int m, LzWs* ws) {
+  const size_t need = lz_ws_need(c->cfg.n, m);
+  if (need > c->lz_ws_doubles) {
+    if (c->lz_ws) (void)hipFree(c->lz_ws);
+    c->lz_ws = nullptr;
+    c->lz_ws_doubles = 0;
+    if (hipMalloc((void**)&c->lz_ws, need * 8) != hipSuccess) {
+      (void)hipGetLastError();
+      c->lz_ws = nullptr;
+      return MEG_ERR_OUT_OF_MEMORY;
+    }
+    c->lz_ws_doubles = need;
+  }
+  *ws = lz_ws_carve(c->lz_ws, c->cfg.n, m);
   return MEG_OK;
 }
 
@@ -1033,6 +1087,8 @@ void fill_info(const Ctl& h, meg_step_info* o) {
   o->converged = in.converged;
   o->cert_resolved = in.cert_resolved;
   o->resid_r1 = in.resid_r1;
+  o->cert_L_up = in.cert_L_up;
+  o->mu_r1_up = in.mu_r1_up;
 }
 
 // Write host iterate (V n x q col-major, d, alpha, t) + fresh basis into the device.
@@ -1187,7 +1243,7 @@ meg_status validate(const meg_params* p, const meg_objective* o, const meg_start
 void free_ctx(meg_ctx c) {
   if (!c) return;
   void* bufs[] = {c->Qw,   c->Za,  c->Zb, c->g,  c->quad,    c->ctl,    c->part,     c->gpart,
-                  c->sums, c->bar, c->ts, c->lz_prev, c->bil_G, c->bil_res, c->bil_P};
+                  c->sums, c->bar, c->ts, c->lz_prev, c->lz_ws, c->bil_G, c->bil_res, c->bil_P};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
@@ -1374,6 +1430,7 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
     delete c;
     return MEG_ERR_DEVICE;
   }
+  c->device = dev;
   c->P = dispatch<DoGrid>(c);
   if (c->external) {  // a grid that both operator families can launch cooperatively
     cfg.kind = LINEAR_CSR;
@@ -1780,12 +1837,11 @@ meg_status meg_profile_step(meg_ctx c, meg_kernel_times* out) {
   return c->h_ctl->status ? (meg_status)c->h_ctl->status : MEG_OK;
 }
 
-meg_status meg_dual_gap(meg_ctx c, int32_t max_steps, double tol, meg_dual_gap_info* out) {
-  meg_status st = check_ctx(c);
-  if (st != MEG_OK) return st;
-  if (!out || max_steps < 1 || !(tol >= 0.0)) return MEG_ERR_INVALID_ARG;
-  if ((c->external && !c->bilinear) || c->cfg.kind == QUADMEAS) return MEG_ERR_UNSUPPORTED;
-  std::memset(out, 0, sizeof(*out));
+// The gradient at the current iterate made available to the Lanczos runs
+// (bilinear: formed; masked: its values on the pattern) together with
+// <X_t, G> and the materialised basis; the control block copied to the host.
+meg_status prepare_gradient(meg_ctx c, double* x_dot_g) {
+  meg_status st = MEG_OK;
   if (c->bilinear) {  // G at the current iterate, as the linear operator of the run
     st = bilinear_prepare(c, true);
     if (st != MEG_OK) return st;
@@ -1797,14 +1853,71 @@ meg_status meg_dual_gap(meg_ctx c, int32_t max_steps, double tol, meg_dual_gap_i
   HIPCHK(c, hipMemcpy(part.data(), c->part, nwg * sizeof(double), hipMemcpyDeviceToHost));
   double xg = 0.0;
   for (int w = 0; w < nwg; ++w) xg += part[w];
-  st = copy_ctl_to_host(c);
+  if (x_dot_g) *x_dot_g = xg;
+  return copy_ctl_to_host(c);
+}
+
+meg_status dual_gap_with(meg_ctx c, int32_t max_steps, double tol, const LzWs& ws, bool warm, meg_dual_gap_info* out) {
+  double xg = 0.0;
+  meg_status st = prepare_gradient(c, &xg);
   if (st != MEG_OK) return st;
-  st = (c->esize == 8) ? lanczos_grad_min<double>(c, max_steps, tol, out)
-                       : lanczos_grad_min<float>(c, max_steps, tol, out);
+  st = (c->esize == 8) ? lanczos_grad_min<double>(c, max_steps, tol, ws, 0, warm, out)
+                       : lanczos_grad_min<float>(c, max_steps, tol, ws, 0, warm, out);
   if (st != MEG_OK) return st;
   out->x_dot_g = xg;
   out->gap = xg - out->lambda_min;
   out->t = c->h_ctl->t;
+  return MEG_OK;
+}
+
+meg_status dual_gap_args(meg_ctx c, int32_t max_steps, double tol, meg_dual_gap_info* out) {
+  meg_status st = check_ctx(c);
+  if (st != MEG_OK) return st;
+  if (!out || max_steps < 1 || !(tol >= 0.0)) return MEG_ERR_INVALID_ARG;
+  if ((c->external && !c->bilinear) || c->cfg.kind == QUADMEAS) return MEG_ERR_UNSUPPORTED;
+  std::memset(out, 0, sizeof(*out));
+  return MEG_OK;
+}
+
+meg_status meg_dual_gap(meg_ctx c, int32_t max_steps, double tol, meg_dual_gap_info* out) {
+  meg_status st = dual_gap_args(c, max_steps, tol, out);
+  if (st != MEG_OK) return st;
+  LzWs ws;
+  st = ctx_lz_ws(c, lz_steps(c->cfg.n, 0, max_steps), &ws);
+  if (st != MEG_OK) return st;
+  return dual_gap_with(c, max_steps, tol, ws, true, out);
+}
+
+meg_status meg_certificate_bound(meg_ctx c, int32_t max_steps, double tol, meg_cert_bound_info* out) {
+  meg_status st = check_ctx(c);
+  if (st != MEG_OK) return st;
+  if (!out || max_steps < 1 || !(tol >= 0.0)) return MEG_ERR_INVALID_ARG;
+  if ((c->external && !c->bilinear) || c->cfg.kind == QUADMEAS) return MEG_ERR_UNSUPPORTED;
+  std::memset(out, 0, sizeof(*out));
+  const int r = c->cfg.r;
+  if (c->cfg.n - r < 1) return MEG_ERR_INVALID_ARG;
+  LzWs ws;
+  st = ctx_lz_ws(c, lz_steps(c->cfg.n, r, max_steps), &ws);
+  if (st != MEG_OK) return st;
+  st = prepare_gradient(c, nullptr);
+  if (st != MEG_OK) return st;
+  meg_dual_gap_info g{};
+  st = (c->esize == 8) ? lanczos_grad_min<double>(c, max_steps, tol, ws, r, false, &g)
+                       : lanczos_grad_min<float>(c, max_steps, tol, ws, r, false, &g);
+  if (st != MEG_OK) return st;
+  // lambda_{r+1}(M_t) <= log alpha_t - eta lambda_min(G on V_t's complement),
+  // with the Ritz value lowered by its residual
+  const Ctl& h = *c->h_ctl;
+  out->lambda_min_defl = g.lambda_min;
+  out->resid = g.resid;
+  out->steps = g.steps;
+  out->converged = g.converged;
+  out->t = h.t;
+  out->mu_up = std::log(h.alpha) - c->cfg.eta * (g.lambda_min - g.resid);
+  // arm the next step (iteration t): its certificate may use the bound
+  HIPCHK(c, hipMemcpyAsync(&c->ctl->mu_up, &out->mu_up, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&c->ctl->mu_up_t, &out->t, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return MEG_OK;
 }
 
@@ -1841,7 +1954,10 @@ meg_status meg_certificate_full(meg_ctx c, const meg_trace_info* tr, double* cer
   if (in.t != tr->t || !(in.eps_t > 0.0)) return MEG_ERR_INVALID_ARG;
   const double L = std::log((double)(c->cfg.n - c->cfg.r)) + in.mu_r1 - std::log(in.eps_t) - tr->log_b;
   *cert_L_full = L;
-  *holds = (L <= 2.0 * in.eps_t) ? 1 : 0;
+  // mu_{r+1} is the step's Ritz value, a lower bound: a claim uses the
+  // step's upper bound of it (L_full moves one for one with mu_{r+1})
+  const double L_up = L + (in.mu_r1_up - in.mu_r1);
+  *holds = (std::isfinite(L_up) && L_up <= 2.0 * in.eps_t) ? 1 : 0;
   return MEG_OK;
 }
 

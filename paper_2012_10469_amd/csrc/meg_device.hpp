@@ -88,6 +88,7 @@ struct Info {
   double ritz_gap, resid_max, mu_r1, sigma;
   int32_t converged, cert_resolved;
   double resid_r1;
+  double cert_L_up, mu_r1_up;
 };
 
 // Device control block: everything the step kernels exchange.
@@ -129,6 +130,10 @@ struct Ctl {
   double XWT[KMAX * KMAX];
   int32_t xvalid;
   int32_t pad_;
+  // an upper bound of mu_{r+1} for the step of iteration mu_up_t, from the
+  // deflated Lanczos run of meg_certificate_bound (mu_up_t = 0: none)
+  double mu_up;
+  int64_t mu_up_t;
   Info info;
 };
 

@@ -1729,6 +1729,42 @@ static __global__ __launch_bounds__(256) void k_lz_lr_update(const Ctl* __restri
   }
 }
 
+// deflation by the first r columns of the materialised basis Q (row stride
+// KB): p[l] = sum_i Q[i][l] w[i], one workgroup per column ...
+template <typename T>
+static __global__ __launch_bounds__(256) void k_lz_defl_dots(const T* __restrict__ Q, int KB,
+                                                             const double* __restrict__ w, int64_t n,
+                                                             double* __restrict__ p) {
+  __shared__ double sred[4];
+  const int l = blockIdx.x;
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) a += (double)Q[i * KB + l] * w[i];
+  a = block_sum256(a, sred);
+  if (threadIdx.x == 0) p[l] = a;
+}
+// ... then w -= Q[:, :r] p
+template <typename T>
+static __global__ __launch_bounds__(256) void k_lz_defl_sub(const T* __restrict__ Q, int KB, int r,
+                                                            const double* __restrict__ p, int64_t n,
+                                                            double* __restrict__ w) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double s = 0.0;
+    for (int l = 0; l < r; ++l) s += (double)Q[i * KB + l] * p[l];
+    w[i] -= s;
+  }
+}
+
+// v = w / ||w|| (one workgroup): the start vector after its deflation
+static __global__ __launch_bounds__(256) void k_lz_unit(const double* __restrict__ w, int64_t n,
+                                                        double* __restrict__ v) {
+  __shared__ double sred[4];
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) a += w[i] * w[i];
+  const double b = sqrt(block_sum256(a, sred));
+  const double ib = b > 0.0 ? 1.0 / b : 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) v[i] = w[i] * ib;
+}
+
 // w = y - alpha_j v_j - beta_{j-1} v_{j-1}, with alpha_j = ab[j] (from
 // k_lz_dots of v_j and y) and beta_{j-1} = ab[m + j - 1]
 static __global__ __launch_bounds__(256) void k_lz_three_term(const double* __restrict__ V, const double* __restrict__ y,

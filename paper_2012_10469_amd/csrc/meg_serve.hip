@@ -536,6 +536,8 @@ meg_status retire(meg_server s) {
     o.converged = in.converged;
     o.cert_resolved = in.cert_resolved;
     o.resid_r1 = in.resid_r1;
+    o.cert_L_up = in.cert_L_up;
+    o.mu_r1_up = in.mu_r1_up;
     q.iters = h.t - 1;
     q.state = bad ? 3 : 2;
     q.status = sm.barerr ? MEG_ERR_DEVICE : (sm.status ? sm.status : MEG_OK);

@@ -417,6 +417,7 @@ __device__ inline double grad_bound(const Cfg& cfg, double alpha, double dl, dou
 // each read would be a separate round trip to memory.
 struct SolveScalars {
   double alpha, sigma, solve_tol, f, pxnorm, op_lmin, op_lmax, dl;  // dl: d_l of this lane (l < r)
+  double mu_up;  // an upper bound of mu_{r+1} for this step (+inf: none)
   int64_t t, iters, applies, jacobi;
   int fvalid, pxvalid, polish, xvalid;
 };
@@ -431,6 +432,7 @@ __device__ __forceinline__ SolveScalars load_scalars(const Cfg& cfg, const gbl<C
   s.op_lmax = ctl->op_lmax;
   s.dl = (lane < cfg.r) ? ctl->d[lane] : 0.0;
   s.t = ctl->t;
+  s.mu_up = (ctl->mu_up_t == s.t && s.t > 0) ? ctl->mu_up : __builtin_inf();
   s.iters = ctl->iters_done;
   s.applies = ctl->applies_done;
   s.jacobi = ctl->jacobi_done;
@@ -439,6 +441,22 @@ __device__ __forceinline__ SolveScalars load_scalars(const Cfg& cfg, const gbl<C
   s.polish = ctl->polish;
   s.xvalid = ctl->xvalid;
   return s;
+}
+
+// The certificate with mu_{r+1} replaced by an upper bound of it (the
+// deflated Lanczos bound armed for this step; +inf without one).  The top r
+// Ritz values are lower bounds and L does not increase with them, so this
+// bounds the exact L from above.  Lane-uniform; evaluated by every lane.
+__device__ inline double cert_upper(const Cfg& cfg, const lds<double>* theta, const SolveScalars& sc, double eps,
+                                   double mu_up) {
+  if (!(mu_up < __builtin_inf())) return __builtin_inf();
+  const int r = cfg.r;
+  const double la = log(sc.alpha);
+  double m = mu_up;
+  for (int l = 0; l < r; ++l) m = fmax(m, theta[l] + la - sc.sigma);
+  double e = exp(mu_up - m);
+  for (int l = 0; l < r; ++l) e += exp(theta[l] + la - sc.sigma - m);
+  return log((double)(cfg.n - r)) - log(eps) + mu_up - (m + log(e));
 }
 
 // End of the inner solve: exponentiate and normalise (Definition 1), build
@@ -490,11 +508,15 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
     in.eps_t = eps;
     in.cert_L = L;
     in.cert_bound = fmax(2.0 * eps, L);
-    // L from the Ritz values is a lower bound of the exact L; with a resolved
-    // (r+1)-th pair L + margin is an upper one, on which claims are made.
-    const double L_up = L + margin;
-    in.cert_holds = (resolved && L_up <= 2.0 * eps) ? 1 : 0;
+    // L from the Ritz values is a lower bound of the exact L; upper bounds:
+    // L + margin with a resolved (r+1)-th pair, and L with mu_{r+1} replaced
+    // by the deflated bound (when armed for this step); claims use the lower
+    const double mu_up = fmin(resolved ? mu_r1 + margin : __builtin_inf(), sc.mu_up);
+    const double L_up = cert_upper(cfg, theta, sc, eps, mu_up);
+    in.cert_holds = (L_up <= 2.0 * eps) ? 1 : 0;
     in.cert_resolved = resolved;
+    in.cert_L_up = L_up;
+    in.mu_r1_up = mu_up;
     in.inner_iters = sweeps;
     in.ritz_gap = mu_r - mu_r1;
     in.resid_max = resid_max;
@@ -504,7 +526,7 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
     in.converged = converged;
     in.f = sc.fvalid ? sc.f : __builtin_nan("");
     if (!all_ok) ctl->status = 4;  // MEG_ERR_NUMERIC
-    if (solve_tol > 0.0 && resolved && fmax(2.0 * eps, L_up) <= solve_tol) ctl->stop = 1;
+    if (solve_tol > 0.0 && fmax(2.0 * eps, L_up) <= solve_tol) ctl->stop = 1;
   }
 }
 
@@ -694,7 +716,8 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   // cert_tol > 0, and for a stopping rule (meg_solve's or a server's tol)
   // while its lower bound of L could pass: otherwise the step takes no
   // sweeps for it and claims nothing while it is unresolved.
-  const bool pending = sc.solve_tol > 0.0 && !(L_lo > fmax(2.0 * eps_t, sc.solve_tol));
+  const double cut = fmax(2.0 * eps_t, sc.solve_tol);
+  const bool pending = sc.solve_tol > 0.0 && !(L_lo > cut) && !(cert_upper(cfg, theta, sc, eps_t, sc.mu_up) <= cut);
   const bool cert_ok = resolved || !(cfg.cert_tol > 0.0 || pending);
   const bool top_ok = wave_min(pair_ok ? 1.0 : 0.0) > 0.5;
   bool conv = top_ok && cert_ok;

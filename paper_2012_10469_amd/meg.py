@@ -50,7 +50,7 @@ EXPORTED = [
     "meg_block_size", "meg_init", "meg_step", "meg_solve", "meg_certificate", "meg_objective_value",
     "meg_get_iterate", "meg_set_iterate", "meg_get_state", "meg_set_state", "meg_profile_step", "meg_destroy",
     "meg_status_str", "meg_get_counters", "meg_step_external", "meg_dual_gap", "meg_solve_to_gap",
-    "meg_trace_exp", "meg_certificate_full",
+    "meg_trace_exp", "meg_certificate_full", "meg_certificate_bound",
     "meg_server_create", "meg_server_submit", "meg_server_run", "meg_server_query", "meg_server_result",
     "meg_server_release", "meg_server_team", "meg_server_get_stats", "meg_server_destroy",
 ]
@@ -87,7 +87,7 @@ class MegStepInfo(ctypes.Structure):
         ("cert_bound", ctypes.c_double), ("cert_holds", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
         ("ritz_gap", ctypes.c_double), ("resid_max", ctypes.c_double), ("mu_r1", ctypes.c_double),
         ("sigma", ctypes.c_double), ("converged", ctypes.c_int32), ("cert_resolved", ctypes.c_int32),
-        ("resid_r1", ctypes.c_double),
+        ("resid_r1", ctypes.c_double), ("cert_L_up", ctypes.c_double), ("mu_r1_up", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -106,6 +106,14 @@ class MegKernelTimes(ctypes.Structure):
 class MegCounters(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("iterations", ctypes.c_int64), ("applies", ctypes.c_int64),
                 ("workgroups", ctypes.c_int32), ("jacobi_sweeps", ctypes.c_int32), ("kernel_ms", ctypes.c_double)]
+
+
+class MegCertBoundInfo(ctypes.Structure):
+    _fields_ = [("mu_up", ctypes.c_double), ("lambda_min_defl", ctypes.c_double), ("resid", ctypes.c_double),
+                ("t", ctypes.c_int64), ("steps", ctypes.c_int32), ("converged", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class MegDualGapInfo(ctypes.Structure):
@@ -187,6 +195,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "meg_profile_step": (ctypes.c_int, [vp, P(MegKernelTimes)]),
         "meg_get_counters": (ctypes.c_int, [vp, P(MegCounters), ctypes.c_int32]),
         "meg_dual_gap": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_double, P(MegDualGapInfo)]),
+        "meg_certificate_bound": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_double, P(MegCertBoundInfo)]),
         "meg_trace_exp": (ctypes.c_int, [vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                          P(MegTraceInfo)]),
         "meg_certificate_full": (ctypes.c_int, [vp, P(MegTraceInfo), P(ctypes.c_double), P(ctypes.c_int32)]),
@@ -422,6 +431,13 @@ class LowRankMEG:
         gradient), with the Lanczos run's step count and residual; synchronises."""
         out = MegDualGapInfo()
         _check(self._lib.meg_dual_gap(self._ctx, int(max_steps), float(tol), ctypes.byref(out)), "meg_dual_gap")
+        return out.as_dict()
+
+    def certificate_bound(self, max_steps: int = 128, tol: float = 1e-10) -> dict:
+        """Upper bound of mu_{r+1} for the next step (armed for it); synchronises."""
+        out = MegCertBoundInfo()
+        _check(self._lib.meg_certificate_bound(self._ctx, int(max_steps), float(tol), ctypes.byref(out)),
+               "meg_certificate_bound")
         return out.as_dict()
 
     def trace_exp(self, probes=None, weight: Optional[float] = None, max_steps: int = 64, tol: float = 1e-10):

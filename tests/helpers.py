@@ -22,7 +22,7 @@ def check_certificate(info, L_ref, eps_ref, prec):
     cert_L comes from the Ritz values: the (r+1)-th one is a lower bound of
     mu_{r+1} (interlacing) and L does not decrease with it, so cert_L is a
     lower bound of the oracle's L.  Resolved (r+1)-th pair: cert_L within
-    TOL_CERT of the oracle's, and cert_L + resid_r1 an upper bound.  In every
+    TOL_CERT of the oracle's.  cert_L_up is an upper bound of it.  In every
     case a claimed certificate holds for the oracle too: cert_holds is never 1
     where the exact L_t > 2 eps_t."""
     tol = TOL_CERT[prec]
@@ -30,10 +30,11 @@ def check_certificate(info, L_ref, eps_ref, prec):
     assert L <= L_ref + tol, ("lower bound", L, L_ref)
     if info["cert_resolved"]:
         assert abs(L - L_ref) <= tol, ("resolved", L, L_ref)
-        assert L_ref <= L + info["resid_r1"] + tol, ("upper bound", L, info["resid_r1"], L_ref)
-    else:
-        assert not info["cert_holds"]
+    # the upper bound behind any claim (resolved pair or an armed deflated
+    # Lanczos bound; +inf without either)
+    assert L_ref <= info["cert_L_up"] + tol, ("upper bound", info["cert_L_up"], L_ref)
     if info["cert_holds"]:
+        assert info["cert_L_up"] <= 2.0 * eps_ref
         assert L_ref <= 2.0 * eps_ref, ("claim the oracle does not make", L, L_ref, eps_ref)
 
 

@@ -63,6 +63,8 @@ int main(void) {
   O(meg_objective, dense) O(meg_objective, ld) O(meg_objective, nnz) O(meg_objective, batch_idx)
   O(meg_objective, batch_steps) O(meg_start, V0) O(meg_start, lambda0)
   O(meg_step_info, cert_holds) O(meg_step_info, ritz_gap) O(meg_step_info, converged) O(meg_step_info, resid_r1)
+  O(meg_step_info, cert_resolved) O(meg_step_info, cert_L_up) O(meg_step_info, mu_r1_up)
+  P(meg_cert_bound_info) O(meg_cert_bound_info, resid) O(meg_cert_bound_info, t) O(meg_cert_bound_info, converged)
   P(meg_server_params) P(meg_request) P(meg_request_status) P(meg_server_stats)
   O(meg_server_params, max_resident) O(meg_server_params, flags) O(meg_server_params, fixed_team)
   O(meg_request, n) O(meg_request, M) O(meg_request, q) O(meg_request, V0) O(meg_request, eta)
@@ -86,7 +88,7 @@ int main(void) {
         want[k] = int(v)
     S = {"meg_params": M.MegParams, "meg_objective": M.MegObjective, "meg_start": M.MegStart,
          "meg_step_info": M.MegStepInfo, "meg_kernel_times": M.MegKernelTimes, "meg_counters": M.MegCounters, "meg_dual_gap_info": M.MegDualGapInfo,
-         "meg_trace_info": M.MegTraceInfo,
+         "meg_trace_info": M.MegTraceInfo, "meg_cert_bound_info": M.MegCertBoundInfo,
          "meg_server_params": M.MegServerParams, "meg_request": M.MegRequest,
          "meg_request_status": M.MegRequestStatus, "meg_server_stats": M.MegServerStats}
     for k, v in want.items():
