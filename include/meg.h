@@ -343,6 +343,19 @@ typedef struct {
 
 meg_status meg_dual_gap(meg_ctx ctx, int32_t max_steps, double tol, meg_dual_gap_info* out);
 
+/* meg_dual_gap for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation, with the Lanczos workspace in a fixed device array
+ * of the library (32 MiB per GPU, held until the process ends) instead of
+ * the context's workspace, and a fresh seeded start vector (no warm start
+ * from an earlier call), so calls are independent of each other.  Needs
+ * (min(n, max_steps) + 1) n + 3 n + 3 min(n, max_steps) + 33 doubles <=
+ * 4 Mi (4194304); MEG_ERR_INVALID_ARG beyond that (and as meg_dual_gap).
+ * Allocates nothing on the device.  Every call on one GPU uses that GPU's
+ * one array: calls that overlap on a GPU (from several host threads or
+ * streams) race, and must be serialised by the caller.  Synchronises. */
+meg_status meg_dual_gap_static(meg_ctx ctx, int32_t max_steps, double tol, meg_dual_gap_info* out);
+
 /* An upper bound of mu_{r+1}, the (r+1)-th eigenvalue of M_t = log X_t -
  * eta grad f(X_t) at the CURRENT iterate (the matrix the next meg_step
  * decomposes), for the certificate of Section 3.1.1.  log X_t = log(alpha) I

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -22,8 +23,32 @@
 
 using namespace meg;
 
+// Device scratch of meg_dual_gap_static, for callers that cannot allocate:
+// one file-scope array per GPU, held until the process ends.  Host code uses
+// its device address from hipGetSymbolAddress (looked up per device at
+// meg_init), never the array's name.
+constexpr size_t kStaticScratchDoubles = (size_t)4 << 20;  // 32 MiB
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
 namespace {
 
+constexpr int kMaxDevices = 64;
+double* g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// The current device's address of `scratch`, looked up once per device.
+meg_status scratch_lookup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return MEG_ERR_DEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[dev]) return MEG_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return MEG_ERR_DEVICE;
+  }
+  g_scratch[dev] = (double*)p;
+  return MEG_OK;
+}
 
 constexpr uint32_t kStateMagic = 0x4d454731u;  // "MEG1"
 
@@ -700,6 +725,14 @@ meg_status lanczos_grad_min(meg_ctx c, int max_steps, double tol, const LzWs& ws
   out->resid = res;
   out->steps = done;
   out->converged = conv ? 1 : 0;
+  return MEG_OK;
+}
+
+// meg_dual_gap_static's workspace: the context's device's copy of `scratch`.
+meg_status static_scratch(meg_ctx c, double** base) {
+  double* p = (c->device >= 0 && c->device < kMaxDevices) ? g_scratch[c->device] : nullptr;
+  if (!p) return MEG_ERR_DEVICE;
+  *base = p;
   return MEG_OK;
 }
 
@@ -1431,6 +1464,12 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
     return MEG_ERR_DEVICE;
   }
   c->device = dev;
+  // this device's address of the allocation-free entry point's scratch (once
+  // per device, with the device current)
+  if (scratch_lookup(dev) != MEG_OK) {
+    delete c;
+    return MEG_ERR_DEVICE;
+  }
   c->P = dispatch<DoGrid>(c);
   if (c->external) {  // a grid that both operator families can launch cooperatively
     cfg.kind = LINEAR_CSR;
@@ -1886,6 +1925,17 @@ meg_status meg_dual_gap(meg_ctx c, int32_t max_steps, double tol, meg_dual_gap_i
   st = ctx_lz_ws(c, lz_steps(c->cfg.n, 0, max_steps), &ws);
   if (st != MEG_OK) return st;
   return dual_gap_with(c, max_steps, tol, ws, true, out);
+}
+
+meg_status meg_dual_gap_static(meg_ctx c, int32_t max_steps, double tol, meg_dual_gap_info* out) {
+  meg_status st = dual_gap_args(c, max_steps, tol, out);
+  if (st != MEG_OK) return st;
+  const int m = lz_steps(c->cfg.n, 0, max_steps);
+  if (lz_ws_need(c->cfg.n, m) > kStaticScratchDoubles) return MEG_ERR_INVALID_ARG;
+  double* base = nullptr;
+  st = static_scratch(c, &base);
+  if (st != MEG_OK) return st;
+  return dual_gap_with(c, max_steps, tol, lz_ws_carve(base, c->cfg.n, m), false, out);
 }
 
 meg_status meg_certificate_bound(meg_ctx c, int32_t max_steps, double tol, meg_cert_bound_info* out) {

@@ -50,7 +50,7 @@ EXPORTED = [
     "meg_block_size", "meg_init", "meg_step", "meg_solve", "meg_certificate", "meg_objective_value",
     "meg_get_iterate", "meg_set_iterate", "meg_get_state", "meg_set_state", "meg_profile_step", "meg_destroy",
     "meg_status_str", "meg_get_counters", "meg_step_external", "meg_dual_gap", "meg_solve_to_gap",
-    "meg_trace_exp", "meg_certificate_full", "meg_certificate_bound",
+    "meg_trace_exp", "meg_certificate_full", "meg_dual_gap_static", "meg_certificate_bound",
     "meg_server_create", "meg_server_submit", "meg_server_run", "meg_server_query", "meg_server_result",
     "meg_server_release", "meg_server_team", "meg_server_get_stats", "meg_server_destroy",
 ]
@@ -195,6 +195,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "meg_profile_step": (ctypes.c_int, [vp, P(MegKernelTimes)]),
         "meg_get_counters": (ctypes.c_int, [vp, P(MegCounters), ctypes.c_int32]),
         "meg_dual_gap": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_double, P(MegDualGapInfo)]),
+        "meg_dual_gap_static": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_double, P(MegDualGapInfo)]),
         "meg_certificate_bound": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_double, P(MegCertBoundInfo)]),
         "meg_trace_exp": (ctypes.c_int, [vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                          P(MegTraceInfo)]),
@@ -431,6 +432,14 @@ class LowRankMEG:
         gradient), with the Lanczos run's step count and residual; synchronises."""
         out = MegDualGapInfo()
         _check(self._lib.meg_dual_gap(self._ctx, int(max_steps), float(tol), ctypes.byref(out)), "meg_dual_gap")
+        return out.as_dict()
+
+    def dual_gap_static(self, max_steps: int = 128, tol: float = 1e-10) -> dict:
+        """dual_gap through the allocation-free entry point (the library's fixed
+        device workspace, a fresh start vector every call)."""
+        out = MegDualGapInfo()
+        _check(self._lib.meg_dual_gap_static(self._ctx, int(max_steps), float(tol), ctypes.byref(out)),
+               "meg_dual_gap_static")
         return out.as_dict()
 
     def certificate_bound(self, max_steps: int = 128, tol: float = 1e-10) -> dict:
