@@ -449,7 +449,8 @@ def main() -> int:
     cnt = g.counters()
     cert = g.certificate()
     log(f"[bench] {args.steps} steps in {secs:.3f}s; last step inner sweeps {cert['inner_iters']} "
-        f"cert_L {cert['cert_L']:.4f} eps {cert['eps_t']:.3e}")
+        f"cert_L {cert['cert_L']:.4f} eps {cert['eps_t']:.3e}; {cnt['extrapolated']} of {cnt['iterations']} "
+        f"steps ended extrapolated")
     assert cnt["iterations"] == args.steps, cnt
     launches = cnt["launches"]
     avg_launch_ms = cnt["kernel_ms"] / launches
@@ -551,7 +552,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "matrix_completion_csr", "n": p.n, "r": args.r, "k": k, "nnz": p.nnz,
                    "mask_p": 0.1, "truth_rank": 5, "eta": 1.0, "eps": "0.8/(t+11)^2",
-                   "sweeps_per_step": sweeps, "steps_per_launch": args.launch_steps},
+                   "sweeps_per_step": sweeps, "extrapolated_per_step": cnt["extrapolated"] / cnt["iterations"],
+                   "steps_per_launch": args.launch_steps},
         "roofline": {"bound": "hbm", "kernel": "k_step", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_note": traffic_note,

@@ -86,6 +86,13 @@ typedef enum {
 } meg_grad_kind;
 
 #define MEG_FLAG_STRICT 1u   /* inner non-convergence -> MEG_ERR_NOT_CONVERGED */
+#define MEG_FLAG_NO_EXTRAPOLATE 4u /* F32 forms: end every step on a tested
+                                      Rayleigh-Ritz sweep (by default a step
+                                      may end on the block one power step past
+                                      its last sweep when that sweep's
+                                      residuals, contracted by the gap ratio
+                                      theta_k / theta_i <= 0.05, predict the
+                                      tolerance with a factor 2 to spare)   */
 #define MEG_FLAG_NO_LDS_CACHE 2u /* CSR kinds: read the sparse data from global
                                     memory in every sweep instead of keeping each
                                     workgroup's rows in LDS (the cache is used
@@ -309,6 +316,7 @@ typedef struct {
   int32_t jacobi_sweeps; /* Jacobi sweeps of their Rayleigh-Ritz solves
                             (saturates at INT32_MAX)                          */
   double kernel_ms;    /* GPU time of those launches, milliseconds            */
+  int64_t extrapolated; /* iterations that ended on the extrapolated block     */
 } meg_counters;
 
 meg_status meg_get_counters(meg_ctx ctx, meg_counters* out, int32_t reset);

@@ -93,7 +93,7 @@ struct meg_ctx_s {
   int ev_head = 0, ev_count = 0;
   double kernel_ms = 0.0;
   int64_t launches = 0;
-  int64_t base_iters = 0, base_applies = 0, base_jacobi = 0;  // device counters at the last reset
+  int64_t base_iters = 0, base_applies = 0, base_jacobi = 0, base_extrap = 0;  // device counters at the last reset
   int P = 1;               // persistent grid size
   int aux_nwg = 1;         // row-parallel auxiliary kernels
   Ctl* h_ctl = nullptr;    // pinned host mirror
@@ -1447,6 +1447,7 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
   cfg.unit_round = (c->esize == 8) ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
   cfg.cert_tol = params->cert_tol;
   cfg.xres = (c->esize == 8) ? 1 : 0;  // explicit Ritz residuals in FP64
+  cfg.extrap = (c->esize == 4 && !(params->flags & MEG_FLAG_NO_EXTRAPOLATE)) ? 1 : 0;
   if (obj->kind == MEG_GRAD_EXTERNAL || obj->kind == MEG_GRAD_BILINEAR) {
     // the operator family is chosen per step; dense until then (bilinear: always
     // the dense gradient the context forms)
@@ -2056,12 +2057,14 @@ meg_status meg_get_counters(meg_ctx c, meg_counters* out, int32_t reset) {
   out->workgroups = c->P;
   out->jacobi_sweeps = (int32_t)std::min<int64_t>(c->h_ctl->jacobi_done - c->base_jacobi, INT32_MAX);
   out->kernel_ms = c->kernel_ms;
+  out->extrapolated = c->h_ctl->extrap_done - c->base_extrap;
   if (reset) {
     c->launches = 0;
     c->kernel_ms = 0.0;
     c->base_iters = c->h_ctl->iters_done;
     c->base_applies = c->h_ctl->applies_done;
     c->base_jacobi = c->h_ctl->jacobi_done;
+    c->base_extrap = c->h_ctl->extrap_done;
   }
   return MEG_OK;
 }

@@ -58,7 +58,9 @@ struct Cfg {
   // block Zout S - Zin W S Theta is formed by the next sweep's apply, one
   // pass over its rows, instead of being estimated from Gram matrices only
   int32_t xres;
-  int32_t pad_;
+  // FP32 forms: a step may end on the block one power step past its last
+  // Rayleigh-Ritz sweep when the residuals predict convergence (small_sweep)
+  int32_t extrap;
 };
 
 // Byte offsets of the per-workgroup CSR cache in dynamic LDS:
@@ -134,6 +136,7 @@ struct Ctl {
   // deflated Lanczos run of meg_certificate_bound (mu_up_t = 0: none)
   double mu_up;
   int64_t mu_up_t;
+  int64_t extrap_done;  // steps that ended extrapolated (counter)
   Info info;
 };
 

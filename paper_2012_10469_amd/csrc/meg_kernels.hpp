@@ -1298,8 +1298,8 @@ __device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl,
               }
               // the step ends here when it returns true: X_{t+1}, t + 1 and
               // the scalars of step t + 1 are set
-              const bool fin = small_sweep<KB>(cfg, gc, (const gbl<double>*)b.sums, (lds<double>*)smem, s, in, tid,
-                                               (gbl<long long>*)b.ts);
+              const bool fin = small_sweep<KB>(cfg, gc, (const gbl<double>*)b.sums, (lds<double>*)smem, s, in, out,
+                                               tid, (gbl<long long>*)b.ts);
               if (fin && deadline != 0 && tid == 0 && (long long)wall_clock64() >= deadline) gc->pause_seq = seq;
             }
             stamp(b, 2 * s + 1);

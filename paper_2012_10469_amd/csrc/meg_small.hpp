@@ -541,7 +541,7 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
 // doubles.
 template <int KB>
 __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gbl<double>* sums, lds<double>* scr,
-                                         int sweep, int in_buf, int lane, gbl<long long>* ts) {
+                                         int sweep, int in_buf, int out_buf, int lane, gbl<long long>* ts) {
   constexpr int LD = KB + 1;
   constexpr int MS = KB * LD;
   lds<double>* A = scr;            // T, then diagonalised
@@ -740,35 +740,66 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     }
     return false;
   }
-  if (fin) {
+  // Extrapolated end (FP32 forms): when every top pair's residual, times the
+  // power step's contraction theta_k / theta_i (at most 0.05: a gap the
+  // prediction is reliable across) and a safety factor 2, meets the
+  // tolerance, the block Zout S after one more power step is accepted
+  // without a further sweep to test it; the Ritz values of this sweep are
+  // kept (their error is second order in the residuals).
+  bool extrap = false;
+  if (!fin && cfg.extrap && !exact && cert_ok && sweep >= cfg.min_inner) {
+    const double thk = fabs(lane_f64(th, KB - 1));
+    const double ratio = (lane < r) ? thk / fmax(fabs(th), 1e-300) : 0.0;
+    const bool ok = lane >= r || light || (ratio <= 0.05 && 2.0 * ratio * rh <= thr);
+    extrap = wave_min(ok ? 1.0 : 0.0) > 0.5;
+  }
+  if (fin || extrap) {
     const double a_old = sc.alpha;
     const double d_old = sc.dl;
     double d_new, c_new, a_new;
-    finish_step(cfg, ctl, theta, rho, rmax, sweep, (top_ok && (resolved || !(cfg.cert_tol > 0.0))) ? 1 : 0,
-                resolved ? 1 : 0, margin, eps_t, sc, lane, d_new, c_new, a_new);
-    // Ritz vectors of span(Q): Q S = Zin (W S), the next warm start; its
-    // first sweep uses W = Wb and PW = V^T Q = [I_r 0]
+    finish_step(cfg, ctl, theta, rho, rmax, sweep,
+                (extrap || (top_ok && (resolved || !(cfg.cert_tol > 0.0)))) ? 1 : 0, resolved ? 1 : 0, margin,
+                eps_t, sc, lane, d_new, c_new, a_new);
+    // The next warm start (B, Wb) and C = V_t^T V_{t+1} (first r x r) for
+    // ||X_{t+1} - X_t||_F:
+    //  - ended here: the Ritz vectors of span(Q), Q S = Zin (W S); C = PW S;
+    //  - extrapolated: Zout S R^{-1} (Cholesky QR, S^T G S = R^T R), whose first
+    //    r columns span the power step of the top pairs; C = P S R^{-1}.
+    // The next step's first sweep uses W = Wb and PW = V^T Q = [I_r 0].
+    lds<double>* Cm = B3;
+    if (extrap) {
+      chol_inv<KB>(B3, B2, lane);  // B2 = R^{-1}
+      mm_nn<KB>(B1, B2, A, lane);  // A = S R^{-1}
 #pragma unroll
-    for (int u = 0; u < WE; ++u) {
-      const int e = lane + 64 * u;
-      B2[(e / KB) * LD + (e % KB)] = wreg[u];
+      for (int m = 0; m < PE; ++m) {
+        const int e = lane + 64 * m;
+        if (e < KB * KB) S[(e / KB) * LD + (e % KB)] = pnew[m];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < WE; ++u) {
+        const int e = lane + 64 * u;
+        B2[(e / KB) * LD + (e % KB)] = wreg[u];
+      }
+      wsync();
+      mm_nn<KB>(B2, B1, A, lane);  // A = W S
+      wsync();
+#pragma unroll
+      for (int m = 0; m < PE; ++m) {
+        const int e = lane + 64 * m;
+        if (e < KB * KB) S[(e / KB) * LD + (e % KB)] = pold[m];
+      }
     }
     wsync();
-    mm_nn<KB>(B2, B1, A, lane);
+    mm_nn<KB>(S, extrap ? A : B1, Cm, lane);
     wsync();
     store_mat<KB>(A, ctl->Wb, lane);
     store_mat<KB>(A, ctl->W, lane);
     for (int e = lane; e < KB * KB; e += 64) ctl->PW[e] = (e / KB == e % KB && e / KB < r) ? 1.0 : 0.0;
     // ||X_{t+1} - X_t||_F from the factored forms (V orthonormal):
     //   n da^2 + 2 da (sum d_t - sum d_{t+1}) + |d_t|^2 + |d_{t+1}|^2
-    //   - 2 sum_ab d_t,a d_{t+1},b C_ab^2,   C = V_t^T V_{t+1} = PW S[:, :r]
-    lds<double>* Pm = S;   // free: the sorted Ritz vectors are in B1
-    lds<double>* dd = B3;  // free after the residuals: d_t, then d_{t+1}
-#pragma unroll
-    for (int m = 0; m < PE; ++m) {
-      const int e = lane + 64 * m;
-      if (e < KB * KB) Pm[(e / KB) * LD + (e % KB)] = pold[m];
-    }
+    //   - 2 sum_ab d_t,a d_{t+1},b C_ab^2
+    lds<double>* dd = vec + 2 * KB;  // the Jacobi rotations' area: d_t, then d_{t+1}
     if (lane < KB) {
       dd[lane] = d_old;
       dd[KB + lane] = d_new;
@@ -777,9 +808,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     double cross = 0.0;
     for (int e = lane; e < r * r; e += 64) {
       const int a = e / r, b = e % r;
-      double c = 0.0;
-#pragma unroll 4
-      for (int q = 0; q < KB; ++q) c += Pm[a * LD + q] * B1[q * LD + b];
+      const double c = Cm[a * LD + b];
       cross += dd[a] * dd[KB + b] * c * c;
     }
     cross = wave_sum(cross);
@@ -792,7 +821,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     // the values in registers
     if (lane == 0) {
       ctl->dxnorm = dxnorm;
-      ctl->src = in_buf;
+      ctl->src = extrap ? out_buf : in_buf;
       ctl->t = sc.t + 1;
       ctl->iters_done = sc.iters + 1;
       ctl->applies_done = sc.applies + 1;
@@ -801,6 +830,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
       ctl->sweep = 1;
       ctl->polish = 0;
       ctl->xvalid = 0;
+      ctl->extrap_done = ctl->extrap_done + (extrap ? 1 : 0);
     }
     if (cfg.kind != QUADMEAS) {  // the minibatch bound is set inside the next step's first sweep
       const double gmax =

@@ -44,6 +44,7 @@ MEG_GRAD_BILINEAR = 6
 
 MEG_FLAG_STRICT = 1
 MEG_FLAG_NO_LDS_CACHE = 2
+MEG_FLAG_NO_EXTRAPOLATE = 4
 MEG_SERVER_FLAG_GRAPH = 1
 
 EXPORTED = [
@@ -105,7 +106,8 @@ class MegKernelTimes(ctypes.Structure):
 
 class MegCounters(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("iterations", ctypes.c_int64), ("applies", ctypes.c_int64),
-                ("workgroups", ctypes.c_int32), ("jacobi_sweeps", ctypes.c_int32), ("kernel_ms", ctypes.c_double)]
+                ("workgroups", ctypes.c_int32), ("jacobi_sweeps", ctypes.c_int32), ("kernel_ms", ctypes.c_double),
+                ("extrapolated", ctypes.c_int64)]
 
 
 class MegCertBoundInfo(ctypes.Structure):
@@ -425,7 +427,8 @@ class LowRankMEG:
         out = MegCounters()
         _check(self._lib.meg_get_counters(self._ctx, ctypes.byref(out), 1 if reset else 0), "meg_get_counters")
         return {"launches": out.launches, "iterations": out.iterations, "applies": out.applies,
-                "workgroups": out.workgroups, "jacobi_sweeps": out.jacobi_sweeps, "kernel_ms": out.kernel_ms}
+                "workgroups": out.workgroups, "jacobi_sweeps": out.jacobi_sweeps, "kernel_ms": out.kernel_ms,
+                "extrapolated": out.extrapolated}
 
     def dual_gap(self, max_steps: int = 128, tol: float = 1e-10) -> dict:
         """Dual gap <X_t, G> - lambda_min(G) at the current iterate (G its
