@@ -224,9 +224,21 @@ constexpr int kRedU = 2;
 // loads in flight do not add to the register pressure of the caller.
 // Group level: gpart[g] = sum over the group's workgroups w of part[w], in
 // workgroup order; kRedU elements per thread have their loads issued together.
+// Barrier order of the workgroups of a team.  A grid launched on all
+// compute units places workgroup w on XCD w % 8; with a multiple of 8
+// workgroups the barrier enumerates them XCD by XCD (position
+// p = (w % 8) (P / 8) + w / 8), so each arrival group of kBarGroupSize
+// holds workgroups of one XCD, whose partials sit in that XCD's L2.
+__device__ __forceinline__ unsigned bar_pos(unsigned w, unsigned P, bool xcd) {
+  return xcd ? (w % 8u) * (P / 8u) + w / 8u : w;
+}
+__device__ __forceinline__ unsigned bar_wg(unsigned pos, unsigned P, bool xcd) {
+  return xcd ? (pos % (P / 8u)) * 8u + pos / (P / 8u) : pos;
+}
+
 template <int NT>
 __device__ __noinline__ void reduce_group(const gbl<double>* part, gbl<double>* gpart, int plen, unsigned g,
-                                          unsigned g0, unsigned gsize) {
+                                          unsigned g0, unsigned gsize, unsigned P, bool xcd) {
   for (int e0 = threadIdx.x; e0 < plen; e0 += NT * kRedU) {
     double v[kRedU][kBarGroupSize];
 #pragma unroll
@@ -234,7 +246,7 @@ __device__ __noinline__ void reduce_group(const gbl<double>* part, gbl<double>* 
 #pragma unroll
       for (int w = 0; w < kBarGroupSize; ++w) {
         const int e = e0 + u * NT;
-        v[u][w] = (w < (int)gsize && e < plen) ? part[(size_t)(g0 + w) * plen + e] : 0.0;
+        v[u][w] = (w < (int)gsize && e < plen) ? part[(size_t)bar_wg(g0 + w, P, xcd) * plen + e] : 0.0;
       }
 #pragma unroll
     for (int u = 0; u < kRedU; ++u) {
@@ -279,8 +291,11 @@ __device__ __noinline__ void reduce_top(const gbl<double>* gpart, gbl<double>* s
 // batched kernel splits its grid into one team per resident instance.
 struct Team {
   int wg, nwg;
+  bool xcd = false;  // whole grid: arrival groups by XCD (bar_pos)
 };
-__device__ __forceinline__ Team grid_team() { return Team{(int)blockIdx.x, (int)gridDim.x}; }
+__device__ __forceinline__ Team grid_team() {
+  return Team{(int)blockIdx.x, (int)gridDim.x, gridDim.x % 8u == 0 && gridDim.x >= 16u};
+}
 
 // Barrier over one team of a cooperatively launched grid (<= 1024 workgroups).
 // Arrivals are counted in two levels (groups of kBarGroupSize workgroups,
@@ -314,7 +329,7 @@ __device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& 
     return true;
   }
   const unsigned P = (unsigned)tm.nwg;
-  const unsigned g = (unsigned)tm.wg / kBarGroupSize;
+  const unsigned g = bar_pos((unsigned)tm.wg, P, tm.xcd) / kBarGroupSize;
   const unsigned ng = (P + kBarGroupSize - 1) / kBarGroupSize;
   const unsigned g0 = g * kBarGroupSize;
   const unsigned gsize = min((unsigned)kBarGroupSize, P - g0);
@@ -337,7 +352,7 @@ __device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& 
   if (!s_ok) return false;
   if (s_role >= 1) {
     if (plen > 0) {
-      reduce_group<NT>((const gbl<double>*)b.part, (gbl<double>*)b.gpart, plen, g, g0, gsize);
+      reduce_group<NT>((const gbl<double>*)b.part, (gbl<double>*)b.gpart, plen, g, g0, gsize, P, tm.xcd);
       __syncthreads();
     }
     if (tid == 0) {

@@ -703,10 +703,6 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   // the previous sweep's pair) meets the tolerance and is at most a quarter
   // of the gap to theta_{r+2}: the Ritz value is then isolated, and L + rho
   // bounds the exact L from above.  Only then is a certificate claimed.
-  const double mu1 = (lane <= r) ? th + log(sc.alpha) - sc.sigma : -__builtin_inf();
-  const double m1 = wave_max(mu1);
-  const double lse1 = m1 + log(wave_sum((lane <= r) ? exp(mu1 - m1) : 0.0));
-  const double L_lo = log((double)(cfg.n - r)) - log(eps_t) + lane_f64(mu1, r) - lse1;
   const double margin = fmin(fmax(rr1, floor_est), exact ? xr1 : __builtin_inf());
   const double sep = (r + 2 <= KB) ? lane_f64(th, r) - lane_f64(th, r + 1 < KB ? r + 1 : r) : 0.0;
   const double cthr = cfg.cert_tol > 0.0 ? fmax(cfg.cert_tol, exact ? 64.0 * cfg.unit_round * scale : floor_est)
@@ -716,8 +712,15 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   // cert_tol > 0, and for a stopping rule (meg_solve's or a server's tol)
   // while its lower bound of L could pass: otherwise the step takes no
   // sweeps for it and claims nothing while it is unresolved.
-  const double cut = fmax(2.0 * eps_t, sc.solve_tol);
-  const bool pending = sc.solve_tol > 0.0 && !(L_lo > cut) && !(cert_upper(cfg, theta, sc, eps_t, sc.mu_up) <= cut);
+  bool pending = false;
+  if (sc.solve_tol > 0.0) {  // only a stopping rule may ask for more sweeps here
+    const double mu1 = (lane <= r) ? th + log(sc.alpha) - sc.sigma : -__builtin_inf();
+    const double m1 = wave_max(mu1);
+    const double lse1 = m1 + log(wave_sum((lane <= r) ? exp(mu1 - m1) : 0.0));
+    const double L_lo = log((double)(cfg.n - r)) - log(eps_t) + lane_f64(mu1, r) - lse1;
+    const double cut = fmax(2.0 * eps_t, sc.solve_tol);
+    pending = !(L_lo > cut) && !(cert_upper(cfg, theta, sc, eps_t, sc.mu_up) <= cut);
+  }
   const bool cert_ok = resolved || !(cfg.cert_tol > 0.0 || pending);
   const bool top_ok = wave_min(pair_ok ? 1.0 : 0.0) > 0.5;
   bool conv = top_ok && cert_ok;
