@@ -93,6 +93,17 @@ typedef enum {
                                       residuals, contracted by the gap ratio
                                       theta_k / theta_i <= 0.05, predict the
                                       tolerance with a factor 2 to spare)   */
+#define MEG_FLAG_NO_CHEBYSHEV 8u /* plain power steps.  By default every
+                                    subspace sweep applies the Chebyshev
+                                    polynomial of degree 1 for the interval
+                                    [0, theta_k] (theta_k: the smallest Ritz
+                                    value of the block, the last sweep's, or
+                                    the last step's mu_k shifted as the new
+                                    operator), i.e. (Yhat - theta_k/2) scaled:
+                                    the unwanted part of the spectrum of the
+                                    positive semidefinite Yhat maps into
+                                    [-1, 1], halving the convergence exponent
+                                    of pairs near the edge of that part       */
 #define MEG_FLAG_NO_LDS_CACHE 2u /* CSR kinds: read the sparse data from global
                                     memory in every sweep instead of keeping each
                                     workgroup's rows in LDS (the cache is used

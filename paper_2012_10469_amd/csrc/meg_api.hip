@@ -1157,6 +1157,8 @@ meg_status upload_iterate(meg_ctx c, const double* V, int q, const double* d, do
   h.fvalid = 0;
   h.polish = 0;
   h.xvalid = 0;
+  h.mu_valid = 0;  // the first sweep after a new iterate has no Chebyshev interval yet
+  h.cheb_b = 0.0;
   h.pxvalid = 0;  // the shift falls back to the a-priori bound for the new iterate
   h.dxnorm = 0.0;
   h.solve_tol = 0.0;
@@ -1448,6 +1450,7 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
   cfg.cert_tol = params->cert_tol;
   cfg.xres = (c->esize == 8) ? 1 : 0;  // explicit Ritz residuals in FP64
   cfg.extrap = (c->esize == 4 && !(params->flags & MEG_FLAG_NO_EXTRAPOLATE)) ? 1 : 0;
+  cfg.cheb = (params->flags & MEG_FLAG_NO_CHEBYSHEV) ? 0 : 1;
   if (obj->kind == MEG_GRAD_EXTERNAL || obj->kind == MEG_GRAD_BILINEAR) {
     // the operator family is chosen per step; dense until then (bilinear: always
     // the dense gradient the context forms)

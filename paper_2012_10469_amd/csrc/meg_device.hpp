@@ -61,6 +61,8 @@ struct Cfg {
   // FP32 forms: a step may end on the block one power step past its last
   // Rayleigh-Ritz sweep when the residuals predict convergence (small_sweep)
   int32_t extrap;
+  int32_t cheb;  // Chebyshev-filtered sweeps (interval [0, theta_k])
+  int32_t pad2_;
 };
 
 // Byte offsets of the per-workgroup CSR cache in dynamic LDS:
@@ -137,6 +139,16 @@ struct Ctl {
   double mu_up;
   int64_t mu_up_t;
   int64_t extrap_done;  // steps that ended extrapolated (counter)
+  // Chebyshev filter of the current sweep: the upper end b of the interval
+  // [0, b] taken to hold the unwanted spectrum of Yhat (0: none, a plain
+  // power step); the sweep outputs Zout = (Yhat - b/2) Q / (b/2)
+  double cheb_b;
+  double xscale;  // explicit residuals: 1 / |fa| of the sweep whose pairs they test
+  // the ended step's eigenvalues mu_1 and mu_k of M_t (Ritz values), from
+  // which the next step's first interval is taken (mu_valid = 0: none)
+  double mu_1, mu_k;
+  int32_t mu_valid;
+  int32_t pad3_;
   Info info;
 };
 

@@ -774,9 +774,14 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
     tb[SM::T_WB + i * LD + j] = (T)ctl->Wb[e];
     tb[SM::T_PW + e] = (i < r) ? (T)ctl->PW[e] : (T)0;
   }
-  if (tid < KB) tb[SM::T_CE + tid] = (T)ctl->ceff[tid];
+  // Chebyshev filter of the sweep (degree 1 on the interval [0, b] of the
+  // unwanted spectrum, b = cheb_b; 0: none): Zout = fa Yhat Q + fb Q with
+  // fa = 2/b, fb = -1, folded into the operator's coefficients
+  const double chb = ctl->cheb_b;
+  const double fa = chb > 0.0 ? 2.0 / chb : 1.0, fb = chb > 0.0 ? -1.0 : 0.0;
+  if (tid < KB) tb[SM::T_CE + tid] = (T)(fa * ctl->ceff[tid]);
   for (int e = tid; e < SM::ACC; e += NT) smem[e] = 0.0;
-  const T opscale = (T)ctl->opscale, sdiag = (T)ctl->sdiag;
+  const T opscale = (T)(fa * ctl->opscale), sdiag = (T)(fa * ctl->sdiag + fb);
   T alpha = 0, dl = 0;
   if constexpr (GRAD) {
     alpha = (T)ctl->alpha;

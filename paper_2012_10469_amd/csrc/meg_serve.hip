@@ -258,6 +258,7 @@ meg_status setup_instance(meg_server s, const meg_request& q, const double* V0, 
   cfg.unit_round = 5.9604644775390625e-08;
   cfg.cert_tol = 0.0;  // resolve the (r+1)-th pair when the stop rule could act on it
   cfg.extrap = 1;
+  cfg.cheb = 1;
   // control block: X_1 = (1 - eps_0) X_0 + (eps_0 / n) I (Algorithm 2, initialisation)
   Ctl h;
   std::memset(&h, 0, sizeof(h));

@@ -389,6 +389,15 @@ __device__ inline void setup_step_v(const Cfg& cfg, gbl<Ctl>* ctl, double gmax, 
     ctl->sigma = sigma;
     ctl->sdiag = den ? sigma - cfg.eta * alpha : sigma;
     ctl->opscale = den ? cfg.eta : -cfg.eta;
+    // the first sweep's Chebyshev interval [0, b]: the last step's mu_k,
+    // shifted as this step's operator is (Yhat = M_t - log alpha + sigma)
+    double b = 0.0;
+    if (cfg.cheb && ctl->mu_valid) {
+      const double la = log(alpha);
+      const double bk = ctl->mu_k - la + sigma, b1 = ctl->mu_1 - la + sigma;
+      if (bk > 1e-3 * b1 && bk < 0.5 * b1) b = bk;
+    }
+    ctl->cheb_b = b;
   }
 }
 __device__ inline void setup_step(const Cfg& cfg, gbl<Ctl>* ctl, double gmax, int lane) {
@@ -418,6 +427,7 @@ __device__ inline double grad_bound(const Cfg& cfg, double alpha, double dl, dou
 struct SolveScalars {
   double alpha, sigma, solve_tol, f, pxnorm, op_lmin, op_lmax, dl;  // dl: d_l of this lane (l < r)
   double mu_up;  // an upper bound of mu_{r+1} for this step (+inf: none)
+  double cheb_b, xscale;
   int64_t t, iters, applies, jacobi;
   int fvalid, pxvalid, polish, xvalid;
 };
@@ -433,6 +443,8 @@ __device__ __forceinline__ SolveScalars load_scalars(const Cfg& cfg, const gbl<C
   s.dl = (lane < cfg.r) ? ctl->d[lane] : 0.0;
   s.t = ctl->t;
   s.mu_up = (ctl->mu_up_t == s.t && s.t > 0) ? ctl->mu_up : __builtin_inf();
+  s.cheb_b = ctl->cheb_b;
+  s.xscale = ctl->xscale;
   s.iters = ctl->iters_done;
   s.applies = ctl->applies_done;
   s.jacobi = ctl->jacobi_done;
@@ -601,15 +613,20 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     pold[m] = (e < KB * KB) ? ctl->PW[e] : 0.0;
   }
   const int polish = sc.polish;
+  // this sweep's filter: Zout = fa Yhat Q + fb Q (Chebyshev degree 1 on
+  // [0, cheb_b]; fa = 1, fb = 0 without one)
+  const double fa = sc.cheb_b > 0.0 ? 2.0 / sc.cheb_b : 1.0, fb = sc.cheb_b > 0.0 ? -1.0 : 0.0;
   wsync();
-  mm_tn<KB>(B1, B2, A, lane);  // T = W^T C = Q^T Yhat Q
+  mm_tn<KB>(B1, B2, A, lane);  // W^T C = Q^T Zout = fa Q^T Yhat Q + fb I
   wsync();
-  for (int e = lane; e < KB * KB; e += 64) {  // symmetrise
+  for (int e = lane; e < KB * KB; e += 64) {  // T = Q^T Yhat Q, symmetrised
     const int i = e / KB, j = e % KB;
     if (i < j) {
-      const double v = 0.5 * (A[i * LD + j] + A[j * LD + i]);
+      const double v = 0.5 * (A[i * LD + j] + A[j * LD + i]) / fa;
       A[i * LD + j] = v;
       A[j * LD + i] = v;
+    } else if (i == j) {
+      A[i * LD + i] = (A[i * LD + i] - fb) / fa;
     }
   }
   wsync();
@@ -652,9 +669,11 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   wsync();
   mm_tn<KB>(B1, B2, B3, lane);  // Ghat = S^T G S  (Gram of Zout S)
   wsync();
-  // Ritz residuals ||Yhat q s_i - theta_i q s_i||^2 = Ghat_ii - theta_i^2
+  // Ritz residuals: Zout s_i = (fa theta_i + fb) q_i + fa (Yhat q_i - theta_i q_i),
+  // so ||Yhat q_i - theta_i q_i||^2 = (Ghat_ii - (fa theta_i + fb)^2) / fa^2
   const double th = (lane < KB) ? theta[lane] : 0.0;
-  const double rh = (lane < KB) ? sqrt(fmax(B3[lane * LD + lane] - th * th, 0.0)) : 0.0;
+  const double fth = fa * th + fb;
+  const double rh = (lane < KB) ? sqrt(fmax(B3[lane * LD + lane] - fth * fth, 0.0)) / fabs(fa) : 0.0;
   if (lane < KB) {
     rho[lane] = rh;
     ctl->theta[lane] = th;
@@ -672,7 +691,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   // step further on.  Their floor is the apply's rounding.
   const bool exact = cfg.xres && tol_abs < floor_est;
   const double xthr = fmax(tol_abs, 64.0 * cfg.unit_round * scale);
-  const double xr = (exact && sc.xvalid && lane < KB) ? sqrt(fmax(sums[3 * KB * KB + 2 + lane], 0.0))
+  const double xr = (exact && sc.xvalid && lane < KB) ? sqrt(fmax(sums[3 * KB * KB + 2 + lane], 0.0)) * sc.xscale
                                                       : __builtin_inf();
   const double rmax = wave_max(lane < r ? rh : 0.0);
   const bool finite = wave_min((lane < KB) ? ((isfinite(th) && isfinite(rh)) ? 1.0 : 0.0) : 1.0) > 0.5;
@@ -751,8 +770,10 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   // kept (their error is second order in the residuals).
   bool extrap = false;
   if (!fin && cfg.extrap && !exact && cert_ok && sweep >= cfg.min_inner) {
-    const double thk = fabs(lane_f64(th, KB - 1));
-    const double ratio = (lane < r) ? thk / fmax(fabs(th), 1e-300) : 0.0;
+    // contraction of the power step just taken: the unwanted spectrum,
+    // taken to lie in [0, theta_k], maps to at most max(|fb|, |fa theta_k + fb|)
+    const double thk = fmax(fabs(fb), fabs(fa * lane_f64(th, KB - 1) + fb));
+    const double ratio = (lane < r) ? thk / fmax(fabs(fth), 1e-300) : 0.0;
     const bool ok = lane >= r || light || (ratio <= 0.05 && 2.0 * ratio * rh <= thr);
     extrap = wave_min(ok ? 1.0 : 0.0) > 0.5;
   }
@@ -834,6 +855,10 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
       ctl->polish = 0;
       ctl->xvalid = 0;
       ctl->extrap_done = ctl->extrap_done + (extrap ? 1 : 0);
+      const double la = log(sc.alpha);
+      ctl->mu_1 = theta[0] + la - sc.sigma;
+      ctl->mu_k = theta[KB - 1] + la - sc.sigma;
+      ctl->mu_valid = 1;
     }
     if (cfg.kind != QUADMEAS) {  // the minibatch bound is set inside the next step's first sweep
       const double gmax =
@@ -856,9 +881,12 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     for (int e = lane; e < KB * KB; e += 64) {
       const int i = e / KB, j = e % KB;
       ctl->XS[e] = B1[i * LD + j];
-      ctl->XWT[e] = A[i * LD + j] * theta[j];
+      ctl->XWT[e] = A[i * LD + j] * (fa * theta[j] + fb);
     }
-    if (lane == 0) ctl->xvalid = 1;
+    if (lane == 0) {
+      ctl->xvalid = 1;
+      ctl->xscale = 1.0 / fabs(fa);
+    }
     wsync();
   }
   // Next basis Q' = Zout S R^{-1} with Ghat = R^T R (Cholesky QR, FP64) and
@@ -879,6 +907,9 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     ctl->sweep = sweep + 1;
     ctl->applies_done = sc.applies + 1;
     if (do_polish) ctl->polish = polish + 1;
+    // the next sweep's Chebyshev interval: [0, theta_k] of this one
+    const double b = theta[KB - 1];
+    ctl->cheb_b = (cfg.cheb && b > 1e-3 * theta[0] && b < 0.5 * theta[0]) ? b : 0.0;
   }
   if (prof) ts[kTsRR + 3] = wall_clock64();
   return false;

@@ -45,6 +45,7 @@ MEG_GRAD_BILINEAR = 6
 MEG_FLAG_STRICT = 1
 MEG_FLAG_NO_LDS_CACHE = 2
 MEG_FLAG_NO_EXTRAPOLATE = 4
+MEG_FLAG_NO_CHEBYSHEV = 8
 MEG_SERVER_FLAG_GRAPH = 1
 
 EXPORTED = [
