@@ -104,6 +104,30 @@ typedef enum {
                                     positive semidefinite Yhat maps into
                                     [-1, 1], halving the convergence exponent
                                     of pairs near the edge of that part       */
+#define MEG_FLAG_DUAL_AVERAGE 16u /* the dual-averaging reading of the step
+                                     (the accumulate-forever form): the
+                                     log-domain matrix is kept dense and
+                                     accumulated, Y_1 = log X_1, Y_{t+1} =
+                                     Y_t - eta grad f(X_t), and X_{t+1} is
+                                     formed from the top-r eigenpairs of
+                                     Y_{t+1} as Definition 1 forms it from
+                                     those of M_t = log X_t - eta grad f(X_t)
+                                     (which rebuilds log X_t from the
+                                     factored iterate).  The two agree for
+                                     linear f with a start on eigenvectors of
+                                     C and differ otherwise.  Dense linear or
+                                     denoising objectives, F64 or F32 (n x n
+                                     of the state's type for Y, allocated by
+                                     meg_init); each step first updates Y
+                                     (one pass, with Gershgorin bounds for
+                                     the shift), then decomposes Y + sigma' I
+                                     with the dense apply.  meg_set_iterate
+                                     restarts Y at log X; meg_set_state,
+                                     meg_profile_step, meg_trace_exp,
+                                     meg_certificate_bound and
+                                     meg_solve_to_gap return
+                                     MEG_ERR_UNSUPPORTED, as meg_init does for
+                                     other objectives                        */
 #define MEG_FLAG_NO_LDS_CACHE 2u /* CSR kinds: read the sparse data from global
                                     memory in every sweep instead of keeping each
                                     workgroup's rows in LDS (the cache is used
@@ -476,6 +500,44 @@ meg_status meg_certificate_full(meg_ctx ctx, const meg_trace_info* tr, double* c
 
 void meg_destroy(meg_ctx ctx);
 const char* meg_status_str(meg_status s);
+
+/* ---------------------------------------------------------------------------
+ * Exact MEG (Algorithm 1, the mirror step of Section 2.2), the baseline the
+ * experiments compare the low-rank method with (Section 7): dense n x n FP64
+ * iterates W_{t+1} = exp(log W_t - eta grad f(W_t)) / tr(...).  With a
+ * constant step size log W_t accumulates the gradients up to multiples of
+ * I, so the library keeps Y_t (Y_1 = log W_1, Y_{t+1} = Y_t - eta grad
+ * f(W_t)) and forms W_{t+1} = exp(Y_{t+1}) / tr exp(Y_{t+1}) by scaling and
+ * squaring (Gershgorin bounds of Y for the shift and scaling, a degree-12
+ * Taylor polynomial, GEMMs).  W_1 = (1 - eps_0) X_0 + (eps_0/n) I, the
+ * low-rank method's first iterate for the same params and start.
+ * Objectives: MEG_GRAD_LINEAR_DENSE and MEG_GRAD_DENOISE_DENSE with the
+ * DEVICE FP64 matrix C or M (borrowed until meg_exact_destroy); params:
+ * n (2..8192), prec MEG_PREC_F64, eta, the eps schedule (eps_0 only).
+ * Allocates five n x n FP64 matrices.  All work on `stream`; calls
+ * synchronise.  One host thread at a time per handle.
+ * ------------------------------------------------------------------------- */
+typedef struct meg_exact_s* meg_exact;
+
+typedef struct {
+  int64_t t;  /* iteration t of the step just taken (gradient at W_t) */
+  double f;   /* f(W_t)                                                */
+} meg_exact_info;
+
+meg_status meg_exact_create(meg_exact* out, const meg_params* params, const meg_objective* obj,
+                            const meg_start* start, void* stream);
+/* One iteration t of Algorithm 1: W_t -> W_{t+1}. */
+meg_status meg_exact_step(meg_exact h, meg_exact_info* info);
+/* HOST W n x n row-major (optional) and the index t of the current W_t. */
+meg_status meg_exact_get(meg_exact h, double* W, int64_t* t);
+/* The Bregman distance of Section 2.2, B(W_t, X) = tr(W_t log W_t - W_t log X),
+ * between the current exact iterate and a factored X = alpha I + V diag(d) V^T
+ * (HOST V n x r column-major with orthonormal columns, d[r], alpha > 0, as
+ * meg_get_iterate returns it): the experiments' distance between the exact
+ * and the low-rank iterates.  log X from its closed form, tr(W log W) from
+ * Y, so no eigendecomposition runs. */
+meg_status meg_exact_bregman(meg_exact h, const double* V, int32_t r, const double* d, double alpha, double* out);
+void meg_exact_destroy(meg_exact h);
 
 /* ---------------------------------------------------------------------------
  * Batched serving: many independent instances of the dense denoising or

@@ -49,6 +49,7 @@ __all__ = [
     "lowrank_step",
     "lowrank_step_factored",
     "run_lowrank_meg",
+    "run_lowrank_meg_dual_average",
     "certificate",
     "project_spectrahedron",
     "factored_diff_frob",
@@ -435,6 +436,39 @@ def run_lowrank_meg(obj, V0, lam0, r: int, eta: float, T: int, eps_params=(0.8, 
         if keep_states:
             out["states"].append(it.copy())
     if not keep_states:
+        out["states"].append(it.copy())
+    return out
+
+
+def run_lowrank_meg_dual_average(obj, V0, lam0, r: int, eta: float, T: int, eps_params=(0.8, 10.0, 2.0)):
+    """The dual-averaging reading of the low-rank step (the accumulate-forever
+    form of the benchmark spec, reading C1 of the design): the log-domain
+    matrix is accumulated, Y_1 = log X_1 and Y_{t+1} = Y_t - eta grad f(X_t),
+    never rebuilt from the factored iterate, and X_{t+1} is formed from the
+    top-r eigenpairs of Y_{t+1} exactly as Definition 1 forms it from those of
+    M_t (softmax of the top r eigenvalues, mixed with eps_t/(n - r) on the
+    complement).  With f linear and V0 spanning eigenvectors of its C this
+    coincides with Algorithm 2 (softmax composes and ignores shifts); it
+    differs otherwise.  Returns the same dict as run_lowrank_meg (mu: the
+    eigenvalues of Y_{t+1})."""
+    V0 = np.asarray(V0, dtype=np.float64)
+    n = V0.shape[0]
+    it = initial_iterate(V0, lam0, eps_schedule(0, *eps_params), n)
+    Y = it.log_dense()
+    out = {k: [] for k in ("states", "f", "L", "gap", "eps", "mu")}
+    out["states"].append(it.copy())
+    for t in range(1, T + 1):
+        X = it.dense()
+        out["f"].append(obj.value(X))
+        Y = Y - eta * sym(obj.grad(X))
+        e = eps_schedule(t, *eps_params)
+        mu, U = eig_desc(Y, r + 1)
+        alpha_new = e / (n - r)
+        it = FactoredIterate(U[:, :r].copy(), (1.0 - e) * softmax(mu[:r]) - alpha_new, alpha_new, t + 1)
+        out["L"].append(certificate(mu, r, e, n, r + 1))
+        out["gap"].append(float(mu[r - 1] - mu[r]))
+        out["eps"].append(e)
+        out["mu"].append(mu)
         out["states"].append(it.copy())
     return out
 

@@ -23,7 +23,7 @@ DRIVER = os.path.join(HERE, "meg_bench")
 COPY = os.path.join(HERE, "meg_copy")
 ARCH = os.environ.get("MEG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["meg_api.hip", "meg_serve.hip"]
+SOURCES = ["meg_api.hip", "meg_serve.hip", "meg_exact.hip"]
 HEADERS = ["meg_device.hpp", "meg_small.hpp", "meg_kernels.hpp", "meg_host.hpp"]
 
 HIP_FLAGS = [
@@ -49,7 +49,8 @@ def build(verbose: bool = False) -> str:
     cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(ROOT, "include")]
     cmd += [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd += ["-o", tmp]
+    # rocBLAS for the plain GEMMs of the exact-MEG baseline's matrix exponential
+    cmd += ["-o", tmp, "-L", "/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

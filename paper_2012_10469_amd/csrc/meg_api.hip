@@ -105,6 +105,8 @@ struct meg_ctx_s {
   int bil_S = 1;
   bool failed = false;
   int device = 0;  // the device current at meg_init
+  bool da = false;         // dual-averaging reading (MEG_FLAG_DUAL_AVERAGE)
+  void* da_Y = nullptr;    // its accumulated log-domain matrix Y (n x n, state type, ld n)
 };
 
 namespace {
@@ -359,6 +361,31 @@ struct Launch {
     return hipGetLastError();
   }
 
+  // dual-averaging reading: Y = log X_t of the current iterate
+  static hipError_t da_init(meg_ctx c) {
+    const Cfg& cfg = c->cfg;
+    const int mwg = (int)std::min<int64_t>(4096, ceil_div(cfg.n * KB, 256));
+    hipLaunchKernelGGL((k_materialize<T, KB>), dim3(mwg), dim3(256), 0, c->stream, cfg, c->ctl, (T*)c->Qw, (T*)c->Za,
+                       (T*)c->Zb);
+    hipLaunchKernelGGL((k_da_init<T, KB>), dim3(cfg.n), dim3(256), 0, c->stream, cfg, (const Ctl*)c->ctl,
+                       (const T*)c->Qw, (const T*)c->Za, (const T*)c->Zb, (T*)c->da_Y);
+    return hipGetLastError();
+  }
+  // Y <- Y - eta grad f(X_t), its Gershgorin bounds, then the step's shift
+  // and coefficients for Y + sigma' I
+  static hipError_t da_update(meg_ctx c) {
+    const Cfg& cfg = c->cfg;
+    const int mwg = (int)std::min<int64_t>(4096, ceil_div(cfg.n * KB, 256));
+    hipLaunchKernelGGL((k_materialize<T, KB>), dim3(mwg), dim3(256), 0, c->stream, cfg, c->ctl, (T*)c->Qw, (T*)c->Za,
+                       (T*)c->Zb);
+    hipLaunchKernelGGL((k_da_update<T, KB>), dim3(cfg.n), dim3(256), 0, c->stream, cfg, (const Ctl*)c->ctl,
+                       (const T*)c->obj.dense, (const T*)c->Qw, (const T*)c->Za, (const T*)c->Zb, (T*)c->da_Y,
+                       c->part);
+    hipLaunchKernelGGL(k_da_setup, dim3(1), dim3(64), 0, c->stream, cfg, c->ctl, (const double*)c->part,
+                       (int)cfg.n);
+    return hipGetLastError();
+  }
+
   static hipError_t data_norm(meg_ctx c) {
     const Cfg& cfg = c->cfg;
     int64_t rows, cols, ld;
@@ -410,6 +437,12 @@ template <typename T, int KB> struct DoXdotG {
 };
 template <typename T, int KB> struct DoBilinear {
   static hipError_t run(meg_ctx c, bool grad) { return Launch<T, KB>::bilinear(c, grad); }
+};
+template <typename T, int KB> struct DoDaInit {
+  static hipError_t run(meg_ctx c) { return Launch<T, KB>::da_init(c); }
+};
+template <typename T, int KB> struct DoDaUpdate {
+  static hipError_t run(meg_ctx c) { return Launch<T, KB>::da_update(c); }
 };
 template <typename T, int KB> struct DoPartNeed {
   static size_t run(meg_ctx c, int P) { return Launch<T, KB>::part_need(P); }
@@ -1166,6 +1199,7 @@ meg_status upload_iterate(meg_ctx c, const double* V, int q, const double* d, do
   h.info.t = t - 1;
   HIPCHK(c, hipMemcpyAsync(c->ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, dispatch<DoBasis>(c));
+  if (c->da) HIPCHK(c, dispatch<DoDaInit>(c));  // the dual average restarts at log X
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return check_barrier(c);
 }
@@ -1278,7 +1312,7 @@ meg_status validate(const meg_params* p, const meg_objective* o, const meg_start
 void free_ctx(meg_ctx c) {
   if (!c) return;
   void* bufs[] = {c->Qw,   c->Za,  c->Zb, c->g,  c->quad,    c->ctl,    c->part,     c->gpart,
-                  c->sums, c->bar, c->ts, c->lz_prev, c->lz_ws, c->bil_G, c->bil_res, c->bil_P};
+                  c->sums, c->bar, c->ts, c->lz_prev, c->lz_ws, c->bil_G, c->bil_res, c->bil_P, c->da_Y};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
@@ -1451,6 +1485,12 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
   cfg.xres = (c->esize == 8) ? 1 : 0;  // explicit Ritz residuals in FP64
   cfg.extrap = (c->esize == 4 && !(params->flags & MEG_FLAG_NO_EXTRAPOLATE)) ? 1 : 0;
   cfg.cheb = (params->flags & MEG_FLAG_NO_CHEBYSHEV) ? 0 : 1;
+  c->da = (params->flags & MEG_FLAG_DUAL_AVERAGE) != 0;
+  if (c->da && ((obj->kind != MEG_GRAD_LINEAR_DENSE && obj->kind != MEG_GRAD_DENOISE_DENSE) ||
+                params->prec == MEG_PREC_F32_BF16X3)) {
+    delete c;
+    return MEG_ERR_UNSUPPORTED;
+  }
   if (obj->kind == MEG_GRAD_EXTERNAL || obj->kind == MEG_GRAD_BILINEAR) {
     // the operator family is chosen per step; dense until then (bilinear: always
     // the dense gradient the context forms)
@@ -1485,7 +1525,8 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
     return MEG_ERR_DEVICE;
   }
   c->aux_nwg = std::max(1024, ceil_div(cfg.n, 4));
-  const size_t pe = std::max(dispatch<DoPartNeed>(c, c->P), (size_t)c->aux_nwg);
+  // (the dual average's row bounds take n entries)
+  const size_t pe = std::max({dispatch<DoPartNeed>(c, c->P), (size_t)c->aux_nwg, (size_t)cfg.n});
   const size_t zbytes = (size_t)cfg.n * k * c->esize;
   auto alloc = [&](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 256)) == hipSuccess; };
   bool ok = alloc(&c->Qw, zbytes) && alloc(&c->Za, zbytes) && alloc(&c->Zb, zbytes) &&
@@ -1494,6 +1535,7 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
             alloc((void**)&c->gpart, (size_t)kBarMaxGroups * kPartMax * 8) &&
             alloc((void**)&c->ts, kTsSlots * sizeof(long long));
   if (ok && obj->kind == MEG_GRAD_MASKED_CSR) ok = alloc(&c->g, (size_t)std::max<int64_t>(obj->nnz, 1) * c->esize);
+  if (ok && c->da) ok = alloc(&c->da_Y, (size_t)cfg.n * cfg.n * c->esize);
   if (ok && obj->kind == MEG_GRAD_QUADMEAS) ok = alloc(&c->quad, quad_layout(obj->batch, k, c->esize).bytes);
   if (ok && c->bilinear) {
     // slices of the measurement rows: about 2048 partial-gradient workgroups
@@ -1598,10 +1640,39 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
   return MEG_OK;
 }
 
+// One step of the dual-averaging reading: f(X_t) (when asked), Y <- Y - eta
+// grad f(X_t), then the step kernel on the dense operator Y + sigma' I (a
+// launch with Y as the context's dense linear operator).
+meg_status da_step(meg_ctx c, meg_step_info* info) {
+  if (info) HIPCHK(c, dispatch<DoObjective>(c));
+  HIPCHK(c, dispatch<DoDaUpdate>(c));
+  const void* dsave = c->obj.dense;
+  const int64_t ldsave = c->obj.ld;
+  const Cfg csave = c->cfg;
+  c->obj.dense = c->da_Y;
+  c->obj.ld = c->cfg.n;
+  c->cfg.kind = LINEAR_DENSE;
+  c->cfg.ld = c->cfg.n;
+  const hipError_t e = launch_steps(c, 1);
+  c->obj.dense = dsave;
+  c->obj.ld = ldsave;
+  c->cfg = csave;
+  HIPCHK(c, e);
+  if (!info) return MEG_OK;
+  meg_status st = copy_ctl_to_host(c);
+  if (st == MEG_OK) st = check_barrier(c);
+  if (st != MEG_OK) return st;
+  fill_info(*c->h_ctl, info);
+  if (c->h_ctl->status) return (meg_status)c->h_ctl->status;
+  if ((c->params.flags & MEG_FLAG_STRICT) && !info->converged) return MEG_ERR_NOT_CONVERGED;
+  return MEG_OK;
+}
+
 meg_status meg_step(meg_ctx c, meg_step_info* info) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
   if (c->bilinear) return bilinear_step(c, info);
+  if (c->da) return da_step(c, info);
   if (c->external) return MEG_ERR_INVALID_ARG;
   // f(X_t): the masked objective's gradient phase computes it in the step
   if (info && c->cfg.kind != MASKED_CSR) HIPCHK(c, dispatch<DoObjective>(c));
@@ -1644,6 +1715,22 @@ meg_status meg_solve(meg_ctx c, int64_t max_iters, double tol, meg_step_info* la
     return st;
   }
   if (c->external) return MEG_ERR_INVALID_ARG;
+  if (c->da) {  // one launch per iteration (each updates Y first)
+    meg_step_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    bool any = false;
+    for (int64_t i = 0; i < max_iters; ++i) {
+      st = da_step(c, &inf);
+      if (st != MEG_OK) return st;
+      any = true;
+      if (tol > 0.0 && fmax(2.0 * inf.eps_t, inf.cert_L_up) <= tol) break;
+    }
+    if (last) {
+      if (any) *last = inf;
+      else st = meg_certificate(c, last);
+    }
+    return st;
+  }
   // arm the device-side stop rule
   st = copy_ctl_to_host(c);
   if (st != MEG_OK) return st;
@@ -1783,6 +1870,7 @@ meg_status meg_get_state(meg_ctx c, void* buf, size_t* bytes) {
 meg_status meg_set_state(meg_ctx c, const void* buf, size_t bytes) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
+  if (c->da) return MEG_ERR_UNSUPPORTED;  // the dual average Y is not part of the state blob
   const size_t qbytes = (size_t)c->cfg.n * c->cfg.k * c->esize;
   const size_t need = 32 + sizeof(Ctl) + qbytes;
   if (!buf || bytes != need) return MEG_ERR_STATE;
@@ -1810,6 +1898,7 @@ meg_status meg_set_state(meg_ctx c, const void* buf, size_t bytes) {
 meg_status meg_profile_step(meg_ctx c, meg_kernel_times* out) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
+  if (c->da) return MEG_ERR_UNSUPPORTED;
   if (!out || c->external) return MEG_ERR_INVALID_ARG;  // an external G_t is borrowed for one call only
   std::memset(out, 0, sizeof(*out));
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1945,6 +2034,7 @@ meg_status meg_dual_gap_static(meg_ctx c, int32_t max_steps, double tol, meg_dua
 meg_status meg_certificate_bound(meg_ctx c, int32_t max_steps, double tol, meg_cert_bound_info* out) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
+  if (c->da) return MEG_ERR_UNSUPPORTED;  // its matrix is Y, not log X_t - eta G
   if (!out || max_steps < 1 || !(tol >= 0.0)) return MEG_ERR_INVALID_ARG;
   if ((c->external && !c->bilinear) || c->cfg.kind == QUADMEAS) return MEG_ERR_UNSUPPORTED;
   std::memset(out, 0, sizeof(*out));
@@ -1979,6 +2069,7 @@ meg_status meg_trace_exp(meg_ctx c, const double* probes, int32_t p, double weig
                          meg_trace_info* out) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
+  if (c->da) return MEG_ERR_UNSUPPORTED;
   if (!out || p < 0 || (p > 0 && !probes) || !(weight > 0.0) || max_steps < 1 || !(tol >= 0.0))
     return MEG_ERR_INVALID_ARG;
   if ((c->external && !c->bilinear) || c->cfg.kind == QUADMEAS) return MEG_ERR_UNSUPPORTED;
@@ -2019,6 +2110,7 @@ meg_status meg_solve_to_gap(meg_ctx c, int64_t max_iters, double tol, int32_t ch
                             meg_dual_gap_info* gap) {
   meg_status st = check_ctx(c);
   if (st != MEG_OK) return st;
+  if (c->da) return MEG_ERR_UNSUPPORTED;
   if (max_iters < 0 || !(tol > 0.0) || check_every < 1 || check_every > kChunkSteps) return MEG_ERR_INVALID_ARG;
   if (c->external || c->cfg.kind == QUADMEAS) return MEG_ERR_UNSUPPORTED;
   meg_dual_gap_info g{};

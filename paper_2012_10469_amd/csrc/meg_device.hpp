@@ -149,6 +149,7 @@ struct Ctl {
   double mu_1, mu_k;
   int32_t mu_valid;
   int32_t pad3_;
+  double da_lmin;  // dual-averaging reading: a lower bound of lambda_min(Y_t)
   Info info;
 };
 

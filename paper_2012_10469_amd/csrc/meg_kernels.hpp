@@ -1423,6 +1423,109 @@ static __global__ __launch_bounds__(256) void k_materialize(Cfg cfg, const Ctl* 
   }
 }
 
+// sum over a 256-thread workgroup (fixed order); sred: 4 doubles of LDS
+__device__ __forceinline__ double block_sum256(double v, double* sred) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) sred[wave] = v;
+  __syncthreads();
+  return (sred[0] + sred[1]) + (sred[2] + sred[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Dual-averaging reading (MEG_FLAG_DUAL_AVERAGE): the log-domain matrix Y is
+// kept dense and accumulated, Y_1 = log X_1, Y_{t+1} = Y_t - eta grad f(X_t);
+// each step decomposes Y_{t+1} + sigma' I instead of M_t.  Q is the
+// materialised basis (V = Q[:, :r]).
+// ---------------------------------------------------------------------------
+// Y = log X = log(alpha) I + V diag(c) V^T, one workgroup per row
+template <typename T, int KB>
+static __global__ __launch_bounds__(256) void k_da_init(Cfg cfg, const Ctl* __restrict__ ctl, const T* Z0,
+                                                        const T* Z1, const T* Z2, T* __restrict__ Y) {
+  __shared__ double vc[KMAX];
+  const T* Q = zbuf(Z0, Z1, Z2, (ctl->src + 1) % 3);
+  const int64_t i = blockIdx.x, n = cfg.n;
+  const int r = cfg.r;
+  if (threadIdx.x < r) vc[threadIdx.x] = (double)Q[i * KB + threadIdx.x] * ctl->c[threadIdx.x];
+  __syncthreads();
+  const double la = log(ctl->alpha);
+  for (int64_t j = threadIdx.x; j < n; j += 256) {
+    double y = (i == j) ? la : 0.0;
+    for (int l = 0; l < r; ++l) y += vc[l] * (double)Q[j * KB + l];
+    Y[i * n + j] = (T)y;
+  }
+  // lambda_min(log X) = log alpha (c >= 0)
+  if (i == 0 && threadIdx.x == 0) ((Ctl*)ctl)->da_lmin = la;
+}
+
+// Y <- Y - eta G with G = C (linear) or X_t - M (denoising), one workgroup
+// per row; part[i] = Y_ii - sum_{j != i} |Y_ij| of the new Y (Gershgorin)
+template <typename T, int KB>
+static __global__ __launch_bounds__(256) void k_da_update(Cfg cfg, const Ctl* __restrict__ ctl, const T* __restrict__ D,
+                                                          const T* Z0, const T* Z1, const T* Z2, T* __restrict__ Y,
+                                                          double* __restrict__ part) {
+  __shared__ double vd[KMAX];
+  const T* Q = zbuf(Z0, Z1, Z2, (ctl->src + 1) % 3);
+  __shared__ double sred[4];
+  const int64_t i = blockIdx.x, n = cfg.n;
+  const int r = cfg.r;
+  const bool den = cfg.kind == DENOISE_DENSE;
+  if (threadIdx.x < r) vd[threadIdx.x] = den ? (double)Q[i * KB + threadIdx.x] * ctl->d[threadIdx.x] : 0.0;
+  __syncthreads();
+  const double alpha = ctl->alpha, eta = cfg.eta;
+  double off = 0.0, dia = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += 256) {
+    double g = (double)D[i * cfg.ld + j];
+    if (den) {
+      double x = (i == j) ? alpha : 0.0;
+      for (int l = 0; l < r; ++l) x += vd[l] * (double)Q[j * KB + l];
+      g = x - g;
+    }
+    const T y = (T)((double)Y[i * n + j] - eta * g);
+    Y[i * n + j] = y;
+    if (i == j) dia = (double)y; else off += fabs((double)y);
+  }
+  off = block_sum256(off, sred);
+  __syncthreads();
+  dia = block_sum256(dia, sred);
+  if (threadIdx.x == 0) part[i] = dia - off;
+}
+
+// the step's coefficients for Yhat = Y + sigma' I >= 0 (sigma' from the
+// smallest Gershgorin bound): no low-rank term, the operator scale 1, and
+// sigma = sigma' + log alpha so that the eigenvalues mu = theta + log alpha -
+// sigma the step forms are those of Y; the first sweep's Chebyshev interval
+// from the last step's mu_k.  One wavefront.
+static __global__ __launch_bounds__(64) void k_da_setup(Cfg cfg, Ctl* __restrict__ ctl,
+                                                        const double* __restrict__ part, int cnt) {
+  const int lane = threadIdx.x;
+  double m = __builtin_inf();
+  for (int i = lane; i < cnt; i += 64) m = fmin(m, part[i]);
+  m = wave_min(m);
+  // Weyl: lambda_min(Y_{t+1}) >= lambda_min(Y_t) - eta lambda_max(grad f(X_t)),
+  // with the objective's bound of lambda_max (the same as the step's shift
+  // uses); the larger of the two lower bounds
+  const double dl = (lane < cfg.r) ? ctl->d[lane] : 0.0;
+  const double gmax = grad_bound(cfg, ctl->alpha, dl, ctl->op_lmin, ctl->op_lmax, 0, 0.0, 0.0, lane);
+  m = fmax(m, ctl->da_lmin - cfg.eta * gmax);
+  if (lane == 0) ctl->da_lmin = m;
+  const double sp = -m + 1e-3 * (fabs(m) + 1.0);
+  if (lane < KMAX) ctl->ceff[lane] = 0.0;
+  if (lane == 0) {
+    const double la = log(ctl->alpha);
+    ctl->gmax = 0.0;
+    ctl->sigma = sp + la;
+    ctl->sdiag = sp;
+    ctl->opscale = 1.0;
+    double b = 0.0;
+    if (cfg.cheb && ctl->mu_valid) {
+      const double bk = ctl->mu_k + sp, b1 = ctl->mu_1 + sp;
+      if (bk > 1e-3 * b1 && bk < 0.5 * b1) b = bk;
+    }
+    ctl->cheb_b = b;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // auxiliary kernels (ordinary launches; per-workgroup partials, then k_finish)
 // ---------------------------------------------------------------------------
@@ -1662,13 +1765,6 @@ static __global__ __launch_bounds__(256) void k_matvec(Cfg cfg, DenseSrc<T> D, c
 // (V: the basis, row l = vector l of length n).  Reductions are per workgroup
 // (256 threads) in a fixed order.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double block_sum256(double v, double* sred) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  v = wave_sum(v);
-  if (lane == 0) sred[wave] = v;
-  __syncthreads();
-  return (sred[0] + sred[1]) + (sred[2] + sred[3]);
-}
 
 // out[l] = V[l] . w for l < cnt: one workgroup per vector
 static __global__ __launch_bounds__(256) void k_lz_dots(const double* __restrict__ V, const double* __restrict__ w,

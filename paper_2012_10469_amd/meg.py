@@ -46,6 +46,7 @@ MEG_FLAG_STRICT = 1
 MEG_FLAG_NO_LDS_CACHE = 2
 MEG_FLAG_NO_EXTRAPOLATE = 4
 MEG_FLAG_NO_CHEBYSHEV = 8
+MEG_FLAG_DUAL_AVERAGE = 16
 MEG_SERVER_FLAG_GRAPH = 1
 
 EXPORTED = [
@@ -53,6 +54,7 @@ EXPORTED = [
     "meg_get_iterate", "meg_set_iterate", "meg_get_state", "meg_set_state", "meg_profile_step", "meg_destroy",
     "meg_status_str", "meg_get_counters", "meg_step_external", "meg_dual_gap", "meg_solve_to_gap",
     "meg_trace_exp", "meg_certificate_full", "meg_dual_gap_static", "meg_certificate_bound",
+    "meg_exact_create", "meg_exact_step", "meg_exact_get", "meg_exact_bregman", "meg_exact_destroy",
     "meg_server_create", "meg_server_submit", "meg_server_run", "meg_server_query", "meg_server_result",
     "meg_server_release", "meg_server_team", "meg_server_get_stats", "meg_server_destroy",
 ]
@@ -117,6 +119,10 @@ class MegCertBoundInfo(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class MegExactInfo(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("f", ctypes.c_double)]
 
 
 class MegDualGapInfo(ctypes.Structure):
@@ -206,6 +212,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "meg_solve_to_gap": (ctypes.c_int, [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, P(MegStepInfo),
                                             P(MegDualGapInfo)]),
         "meg_destroy": (None, [vp]),
+        "meg_exact_create": (ctypes.c_int, [P(vp), P(MegParams), P(MegObjective), P(MegStart), vp]),
+        "meg_exact_step": (ctypes.c_int, [vp, P(MegExactInfo)]),
+        "meg_exact_get": (ctypes.c_int, [vp, P(ctypes.c_double), P(ctypes.c_int64)]),
+        "meg_exact_bregman": (ctypes.c_int, [vp, P(ctypes.c_double), ctypes.c_int32, P(ctypes.c_double),
+                                             ctypes.c_double, P(ctypes.c_double)]),
+        "meg_exact_destroy": (None, [vp]),
         "meg_status_str": (ctypes.c_char_p, [ctypes.c_int]),
         "meg_server_create": (ctypes.c_int, [P(vp), P(MegServerParams), vp]),
         "meg_server_submit": (ctypes.c_int, [vp, P(MegRequest), P(ctypes.c_int64)]),
@@ -285,6 +297,76 @@ def meg_init(params: MegParams, obj: MegObjective, V0, lam0, stream: Optional[in
     st = lib.meg_init(ctypes.byref(ctx), ctypes.byref(params), ctypes.byref(obj), ctypes.byref(start),
                       ctypes.c_void_p(stream) if stream else None)
     return st, ctx
+
+
+class ExactMEG:
+    """Exact MEG (Algorithm 1) on the GPU: dense FP64 iterates W_t from the
+    low-rank method's first iterate for the same start (meg_exact_*).
+    ``dense`` is the float64 device matrix C (linear) or M (denoising)."""
+
+    def __init__(self, n: int, kind: int, V0, lam0, dense, *, eta: float = 1.0, eps=(0.8, 10.0, 2.0),
+                 stream: Optional[int] = None):
+        import torch
+
+        self._lib = load_library()
+        self._keep = [dense]
+        self.n = int(n)
+        obj = MegObjective(kind=kind, dense=_dptr(dense), ld=int(dense.stride(0)))
+        params = make_params(n, 1, MEG_PREC_F64, eta, 0, eps, 1, 1, 0.0, 0, 0, 0.0)
+        V0 = np.asarray(V0, dtype=np.float64)
+        if V0.ndim == 1:
+            V0 = V0[:, None]
+        Vc = np.asfortranarray(V0)
+        lam = _f64(lam0)
+        start = MegStart(q=Vc.shape[1], reserved=0, V0=Vc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         lambda0=_dblp(lam))
+        if stream is None:
+            self._torch_stream = torch.cuda.Stream()
+            stream = self._torch_stream.cuda_stream
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        _check(self._lib.meg_exact_create(ctypes.byref(h), ctypes.byref(params), ctypes.byref(obj),
+                                          ctypes.byref(start), ctypes.c_void_p(stream)), "meg_exact_create")
+        self._h = h
+
+    def step(self) -> dict:
+        out = MegExactInfo()
+        _check(self._lib.meg_exact_step(self._h, ctypes.byref(out)), "meg_exact_step")
+        return {"t": out.t, "f": out.f}
+
+    def get(self):
+        W = np.empty((self.n, self.n), dtype=np.float64)
+        t = ctypes.c_int64()
+        _check(self._lib.meg_exact_get(self._h, W.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       ctypes.byref(t)), "meg_exact_get")
+        return W, t.value
+
+    def bregman(self, V, d, alpha) -> float:
+        """B(W_t, X) for the factored X = alpha I + V diag(d) V^T."""
+        Vc = np.asfortranarray(np.asarray(V, dtype=np.float64))
+        dd = _f64(d)
+        out = ctypes.c_double()
+        _check(self._lib.meg_exact_bregman(self._h, Vc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           int(Vc.shape[1]), _dblp(dd), float(alpha), ctypes.byref(out)),
+               "meg_exact_bregman")
+        return out.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.meg_exact_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class LowRankMEG:

@@ -210,6 +210,49 @@ def test_lowrank_meg_linear_closed_form(n, r):
         np.testing.assert_allclose(st.V @ st.V.T, P, atol=1e-8)
 
 
+@pytest.mark.parametrize("n,r", [(12, 2), (30, 4)])
+def test_dual_average_reading_equals_closed_form_for_linear_aligned(n, r):
+    """The accumulate-forever (dual-averaging) reading for linear f with V0 on
+    C's bottom eigenvectors: the same closed form as Algorithm 2 (softmax
+    composes), so the two readings agree there."""
+    rng = np.random.default_rng(7 + n)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    c = np.concatenate([np.sort(rng.random(r)), 6.0 + np.sort(rng.random(n - r))])
+    C = (Q * c) @ Q.T
+    lam0 = rng.random(r) + 0.2; lam0 /= lam0.sum()
+    eta, T = 0.7, 12
+    V0 = Q[:, :r]
+    run = O.run_lowrank_meg_dual_average(O.LinearObjective(C), V0, lam0, r, eta, T)
+    want = _closed_form_linear(n, r, eta, c, lam0, T)
+    for t in range(1, T + 1):
+        d, alpha, L = want[t - 1]
+        np.testing.assert_allclose(run["states"][t].dense(), alpha * np.eye(n) + (V0 * d) @ V0.T, atol=1e-12)
+
+
+def test_dual_average_reading_differs_for_denoising():
+    """For a non-linear f the two readings differ: the paper rebuilds log X_t
+    from the factored iterate (flat on the complement of V_t), the dual
+    average keeps every past gradient there."""
+    n, r = 40, 2
+    rng = np.random.default_rng(41)
+    U, _ = np.linalg.qr(rng.standard_normal((n, 2)))
+    G = rng.standard_normal((n, n))
+    M = (U * np.array([2.0, 1.6])) @ U.T + 0.01 * (G + G.T) / np.sqrt(2 * n)
+    # a start off M's eigenvectors (from one on them the iterates commute with
+    # M and the two readings coincide)
+    V0, _ = np.linalg.qr(U + 0.3 * rng.standard_normal((n, 2)))
+    lam0 = np.array([0.5, 0.5])
+    obj = O.DenoiseObjective(M)
+    a = O.run_lowrank_meg(obj, V0, lam0, r, 1.0, 8)
+    b = O.run_lowrank_meg_dual_average(obj, V0, lam0, r, 1.0, 8)
+    diff = [O.factored_diff_frob(x.V, x.d, x.alpha, y.V, y.d, y.alpha) for x, y in zip(a["states"], b["states"])]
+    assert diff[0] < 1e-12 and diff[1] < 1e-12  # the same first step (Y_1 = log X_1)
+    assert max(diff[2:]) > 1e-3
+    # both keep the invariants of the factored iterate
+    for st in b["states"]:
+        assert np.trace(st.dense()) == pytest.approx(1.0, abs=1e-12)
+
+
 # ---------------------------------------------------------------------------
 # P3: the approximation-error lemma of Section 3.1.1 (one step, small n)
 # ---------------------------------------------------------------------------
