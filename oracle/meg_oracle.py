@@ -48,6 +48,7 @@ __all__ = [
     "initial_iterate",
     "lowrank_step",
     "lowrank_step_factored",
+    "lowrank_step_operator",
     "run_lowrank_meg",
     "run_lowrank_meg_dual_average",
     "certificate",
@@ -355,6 +356,37 @@ def lowrank_step(it: FactoredIterate, G: np.ndarray, eta: float, eps: float, r: 
     if full:
         info["Zplus"] = (U * softmax(mu)) @ U.T
     return new, info
+
+
+def lowrank_step_operator(it: FactoredIterate, grad_mv: Callable[[np.ndarray], np.ndarray], eta: float,
+                          eps: float, r: int, tol: float = 1e-13):
+    """lowrank_step with the gradient given only as its action x -> G x (for
+    sizes where a dense eigendecomposition of M_t is out of reach): the top
+    r + 1 eigenpairs of M_t = log X_t - eta G (log X_t from the factored form,
+    Section 3) by a Lanczos eigensolver (ARPACK, residual tolerance ``tol``),
+    then the same exponentiation, normalisation and certificate (Definition 1,
+    Section 3.1.1).  Returns (new FactoredIterate, info with mu (top r + 1),
+    gap, L)."""
+    from scipy.sparse.linalg import LinearOperator, eigsh
+
+    n = it.n
+    la = math.log(it.alpha)
+    c = np.log(it.alpha + it.d) - la
+    V = it.V
+
+    def mv(x):
+        x = np.asarray(x, dtype=np.float64).reshape(n, -1)
+        y = la * x + V @ (c[:, None] * (V.T @ x)) - eta * grad_mv(x)
+        return y if y.shape[1] > 1 else y.reshape(-1)
+
+    op = LinearOperator((n, n), matvec=mv, matmat=mv, dtype=np.float64)
+    v0 = np.random.default_rng([93, n]).standard_normal(n)
+    w, U = eigsh(op, k=r + 1, which="LA", tol=tol, v0=v0, maxiter=100 * n, ncv=min(n, max(4 * (r + 1), 40)))
+    order = np.argsort(w)[::-1]
+    mu, U = w[order], U[:, order]
+    alpha_new = eps / (n - r)
+    new = FactoredIterate(U[:, :r].copy(), (1.0 - eps) * softmax(mu[:r]) - alpha_new, alpha_new, it.t + 1)
+    return new, {"mu": mu, "gap": float(mu[r - 1] - mu[r]), "L": certificate(mu, r, eps, n, r + 1), "eps": eps}
 
 
 def lowrank_step_factored(it: FactoredIterate, F: np.ndarray, c: np.ndarray, eta: float, eps: float, r: int):

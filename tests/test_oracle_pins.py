@@ -210,6 +210,26 @@ def test_lowrank_meg_linear_closed_form(n, r):
         np.testing.assert_allclose(st.V @ st.V.T, P, atol=1e-8)
 
 
+@pytest.mark.parametrize("n,r", [(60, 3), (150, 6)])
+def test_operator_step_equals_the_dense_step(n, r):
+    """The step with the gradient given as an action (Lanczos eigensolver on
+    M_t) equals the dense-eigh step: X_{t+1} and the certificate."""
+    rng = np.random.default_rng(300 + n)
+    M = rand_sym(n, rng, scale=1.0)
+    U, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    M = M + 3.0 * U @ U.T
+    V, _ = np.linalg.qr(U + 0.2 * rng.standard_normal((n, r)))
+    lam = rng.random(r) + 0.2; lam /= lam.sum()
+    it = O.FactoredIterate(V, (1 - 0.3) * lam - 0.3 / (n - r), 0.3 / (n - r), 4)
+    X = it.dense()
+    G = X - M
+    a, ia = O.lowrank_step(it, G, 1.0, 0.01, r, full=False)
+    b, ib = O.lowrank_step_operator(it, lambda x: X @ x - M @ x, 1.0, 0.01, r)
+    assert O.factored_diff_frob(a.V, a.d, a.alpha, b.V, b.d, b.alpha) <= 1e-10 * O.factored_frob(a.V, a.d, a.alpha)
+    assert ib["L"] == pytest.approx(ia["L"], abs=1e-10)
+    np.testing.assert_allclose(ib["mu"], ia["mu"][: r + 1], atol=1e-10)
+
+
 @pytest.mark.parametrize("n,r", [(12, 2), (30, 4)])
 def test_dual_average_reading_equals_closed_form_for_linear_aligned(n, r):
     """The accumulate-forever (dual-averaging) reading for linear f with V0 on
