@@ -23,6 +23,15 @@ problem from bilinear measurements, full gradients, FP32 state) at Table 1's
 largest rank-5 size, n = 600 (m = 60000 measurement pairs), against the FP64
 oracle on a sample of iterations (`--no-recovery` skips it).
 
+Three more objects cover the other configurations: "config1" (the plain
+method, FP64, n = 200, r = 5, 100 iterations: iterations/s and the FP64
+error against the oracle), "config3" (stochastic gradients, n = 8192, a pool
+of 10^6 measurements on the device, L = 256, r = 8: iterations/s with the
+count of steps whose inner solve did not converge) and "precision" (n = 16384
+dense denoising, r = 16: the BF16x3 matrix-core apply against the plain FP32
+apply, each with its FP64 error against the FP64 path on the same matrix);
+`--no-configs` skips them.
+
 `--write-workload PATH` only writes the workload for the native driver
 paper_2012_10469_amd/meg_bench (used under rocprofv3) and exits;
 `--write-dense-workload PATH` writes the precision-form workload of the same
@@ -222,6 +231,191 @@ def recovery_bench(meg, torch, steps: int = 50, cpu_samples: int = 2, n: int = 6
     return out
 
 
+def _threads() -> int:
+    try:
+        from threadpoolctl import threadpool_info
+
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [1]))
+    except Exception:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def config1_bench(meg, torch, T: int = 100):
+    """The plain configuration: FP64, n = 200, M = u u^T + 0.01 (G + G^T)/sqrt(2n),
+    r = 5, eta = 1, T = 100 iterations from the top eigenvector of M.  GPU
+    iterations/s of the whole run (one 100-iteration meg_solve after a warmup
+    context), its FP64 error against the oracle (every step from the oracle's
+    iterate; the free-running final iterate), and the oracle's own time."""
+    import numpy as np
+
+    import workloads as W
+    from oracle import meg_oracle as O
+
+    n, r = 200, 5
+    prob = W.spiked_denoise(n, seed=1, start="top1")
+    M = torch.from_numpy(np.ascontiguousarray(prob.M)).cuda()
+    kw = dict(prec=meg.MEG_PREC_F64, eta=1.0, dense=M, max_inner=64)
+    with meg.LowRankMEG(n, r, meg.MEG_GRAD_DENOISE_DENSE, prob.V0, prob.lam0, **kw) as w:
+        w.solve(5)
+    with meg.LowRankMEG(n, r, meg.MEG_GRAD_DENOISE_DENSE, prob.V0, prob.lam0, **kw) as g:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.solve(T)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        cnt = g.counters()
+        final = g.get_iterate()
+        c0 = time.perf_counter()
+        run = O.run_lowrank_meg(O.DenoiseObjective(prob.M), prob.V0, prob.lam0, r, 1.0, T)
+        cpu_s = time.perf_counter() - c0
+        tf = []
+        for t in range(1, T + 1):
+            st = run["states"][t - 1]
+            g.set_iterate(st.V, st.d, st.alpha, t)
+            g.step(info=False)
+            V, d, a, _ = g.get_iterate()
+            ref = run["states"][t]
+            rel_gap = run["gap"][t - 1] / max(1.0, abs(run["mu"][t - 1][0] - run["mu"][t - 1][-1]))
+            e = O.factored_diff_frob(V, d, a, ref.V, ref.d, ref.alpha) / O.factored_frob(ref.V, ref.d, ref.alpha)
+            tf.append((e, rel_gap))
+    ref = run["states"][T]
+    fr = O.factored_diff_frob(*final[:3], ref.V, ref.d, ref.alpha) / O.factored_frob(ref.V, ref.d, ref.alpha)
+    out = {"workload": "spiked_denoise_fp64", "n": n, "r": r, "iterations": T, "dtype": "f64",
+           "iter_per_s": T / secs, "ms_per_iter": secs * 1e3 / T,
+           "applies_per_iter": cnt["applies"] / cnt["iterations"], "unconverged": cnt["unconverged"],
+           "error_vs_oracle": {"teacher_forced_max": max(e for e, gp in tf if gp >= 1e-3),
+                               "steps_with_relative_gap_below_1e-3": sum(1 for _, gp in tf if gp < 1e-3),
+                               "free_running_final": fr},
+           "cpu_baseline": {"value": T / cpu_s, "unit": "iter/s", "cores": _threads(), "kind": "oracle",
+                            "sample": f"the whole {T}-iteration run"}}
+    log(f"[config1] n={n} r={r} FP64: {out['iter_per_s']:.0f} iter/s over {T} iterations "
+        f"({out['applies_per_iter']:.2f} applies/iter); teacher-forced error {out['error_vs_oracle']['teacher_forced_max']:.1e}, "
+        f"free-running {fr:.1e}; oracle {T / cpu_s:.1f} iter/s")
+    return out
+
+
+def config3_bench(meg, torch, steps: int = 200):
+    """Stochastic gradients: n = 8192, pool of m = 10^6 Gaussian measurements
+    (drawn on the device), minibatch L = 256, r = 8, eta = 1/(3 + n/L), from
+    the experiments' warm start.  GPU iterations/s over `steps` iterations
+    after 10 warmup, with the number of steps whose inner solve did not
+    converge (max_inner 12); the oracle's time on one iteration."""
+    import numpy as np
+
+    import workloads as W
+    from oracle import meg_oracle as O
+
+    n, m, L, r, bsteps, seed = 8192, 1_000_000, 256, 8, 64, 3
+    t0 = time.time()
+    A, b, F = W.quadmeas_pool_device(n, m, seed)
+    bi = W.quadmeas_batches(m, L, bsteps, seed)
+    sample = A[:1024].cpu().numpy()
+    V0, lam0 = W.exp_init_quadmeas(sample, b[:1024].cpu().numpy(), n, r, seed)
+    eta = 1.0 / (3.0 + n / L)
+    idx = torch.as_tensor(bi.astype(np.int32)).cuda()
+    log(f"[config3] pool of {m} measurements (n={n}) and warm start in {time.time() - t0:.1f}s")
+    try:
+        g = meg.LowRankMEG(n, r, meg.MEG_GRAD_QUADMEAS, V0, lam0, prec=meg.MEG_PREC_F32, eta=eta, A=A, b=b,
+                           batch_idx=idx, max_inner=12)
+        g.solve(10)
+        torch.cuda.synchronize()
+        g.counters(reset=True)
+        t0 = time.perf_counter()
+        g.solve(steps)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        cnt = g.counters()
+        V, d, a, t = g.get_iterate()
+        g.close()
+        # the oracle on one iteration (factored minibatch gradient, invariant-subspace eigensolve)
+        it = O.FactoredIterate(V, d, a, t)
+        rows = A[torch.as_tensor(bi[(t - 1) % bsteps].astype(np.int64)).cuda()].cpu().numpy().astype(np.float64)
+        local = O.QuadMeasObjective(rows.T, b[torch.as_tensor(bi[(t - 1) % bsteps].astype(np.int64)).cuda()]
+                                    .cpu().numpy().astype(np.float64))
+        c0 = time.perf_counter()
+        Fm, c = local.grad_factor(it, np.arange(L))
+        O.lowrank_step_factored(it, Fm, c, eta, O.eps_schedule(t), r)
+        cpu_s = time.perf_counter() - c0
+    finally:
+        del A, b
+        torch.cuda.empty_cache()
+    out = {"workload": "quadmeas_stochastic", "n": n, "m": m, "L": L, "r": r, "dtype": "f32", "steps": steps,
+           "iter_per_s": steps / secs, "ms_per_iter": secs * 1e3 / steps,
+           "applies_per_iter": cnt["applies"] / cnt["iterations"], "unconverged_steps": cnt["unconverged"],
+           "converged": cnt["unconverged"] == 0,
+           "cpu_baseline": {"value": 1.0 / cpu_s, "unit": "iter/s", "cores": _threads(), "kind": "oracle",
+                            "sample": "1 iteration (factored gradient, exact invariant-subspace eigensolve)"}}
+    log(f"[config3] {out['iter_per_s']:.0f} iter/s over {steps} iterations, {out['applies_per_iter']:.2f} "
+        f"applies/iter, {cnt['unconverged']} unconverged steps; oracle {1.0 / cpu_s:.2f} iter/s")
+    return out
+
+
+def precision_bench(meg, torch, T: int = 20):
+    """The precision form: n = 16384 dense denoising (M = rank-8 + 1e-3 noise),
+    r = 16 (k = 32), T iterations from the top eigenvector of M, three ways:
+    BF16x3 apply (the bf16 planes of M, FP32 state), the plain FP32 dense
+    apply, and the FP64 path on the same matrix (the planes' value).  Reports
+    iterations/s of the first two and their FP64 errors against the third
+    (relative Frobenius of X_{T+1}, relative f, absolute cert_L)."""
+    import numpy as np
+
+    import workloads as W
+    from oracle import meg_oracle as O
+
+    n, r = 16384, 16
+    t0 = time.time()
+    prob = W.lowrank_noise_denoise(n, rank=8, seed=1, noise=1e-3, r=r, dtype=np.float32, start="top1")
+    hi, lo = W.bf16_planes(prob.M)
+    del prob.M
+    Mp = W.planes_value(hi, lo, n)
+    log(f"[precision] n={n} workload in {time.time() - t0:.1f}s")
+    dhi = torch.from_numpy(hi.view(np.int16)).cuda()
+    dlo = torch.from_numpy(lo.view(np.int16)).cuda()
+    del hi, lo
+    res = {}
+    for name, kw in (("bf16x3", dict(prec=meg.MEG_PREC_F32_BF16X3, dense=dhi, dense_lo=dlo)),
+                     ("f32", dict(prec=meg.MEG_PREC_F32, dense=torch.from_numpy(Mp.astype(np.float32)).cuda())),
+                     ("f64", dict(prec=meg.MEG_PREC_F64, dense=torch.from_numpy(Mp).cuda()))):
+        torch.cuda.synchronize()
+        g = meg.LowRankMEG(n, r, meg.MEG_GRAD_DENOISE_DENSE, prob.V0, prob.lam0, eta=1.0, max_inner=40, **kw)
+        try:
+            g.solve(2)  # first iterations, kernels loaded
+            torch.cuda.synchronize()
+            g.counters(reset=True)
+            t1 = time.perf_counter()
+            g.solve(T - 2)
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t1
+            cnt = g.counters()
+            last = g.certificate()
+            f = g.objective()
+            res[name] = {"iter_per_s": (T - 2) / secs, "applies_per_iter": cnt["applies"] / cnt["iterations"],
+                         "unconverged": cnt["unconverged"], "state": g.get_iterate(), "f": f,
+                         "cert_L": last["cert_L"]}
+        finally:
+            g.close()
+            del kw["dense"]
+            torch.cuda.empty_cache()
+    del dhi, dlo, Mp
+    ref = res["f64"]
+    Vr, dr, ar, _ = ref["state"]
+    out = {"workload": "lowrank_noise_denoise_dense", "n": n, "r": r, "k": 32, "iterations": T,
+           "reference": "the FP64 path on the same matrix (parity-tested against the oracle)"}
+    for name in ("bf16x3", "f32"):
+        V, d, a, _ = res[name]["state"]
+        ex = O.factored_diff_frob(V, d, a, Vr, dr, ar) / O.factored_frob(Vr, dr, ar)
+        out[name] = {"iter_per_s": res[name]["iter_per_s"], "applies_per_iter": res[name]["applies_per_iter"],
+                     "unconverged": res[name]["unconverged"],
+                     "fp64_error": {"X": ex, "f": abs(res[name]["f"] - ref["f"]) / abs(ref["f"]),
+                                    "cert_L": abs(res[name]["cert_L"] - ref["cert_L"])}}
+    out["f64"] = {"iter_per_s": ref["iter_per_s"], "applies_per_iter": ref["applies_per_iter"]}
+    out["speedup_bf16x3_vs_f32"] = out["bf16x3"]["iter_per_s"] / out["f32"]["iter_per_s"]
+    log(f"[precision] BF16x3 {out['bf16x3']['iter_per_s']:.0f} iter/s (X err {out['bf16x3']['fp64_error']['X']:.1e}), "
+        f"FP32 {out['f32']['iter_per_s']:.0f} iter/s (X err {out['f32']['fp64_error']['X']:.1e}), "
+        f"FP64 {ref['iter_per_s']:.0f} iter/s")
+    return out
+
+
 def cpu_baseline(p, r: int, samples: int):
     """The FP64 oracle as it stands, on the same problem: `samples` iterations
     (dense gradient, top-(r+1) LAPACK eigendecomposition)."""
@@ -378,6 +572,8 @@ def main() -> int:
                     help="iterations per launch of the persistent step kernel (1: one meg_step per iteration)")
     ap.add_argument("--no-serving", action="store_true", help="skip the batched-serving measurement")
     ap.add_argument("--no-recovery", action="store_true", help="skip the recovery-problem measurement")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the plain (n=200 FP64), stochastic (n=8192) and precision-form (n=16384) objects")
     ap.add_argument("--serve-count", type=int, default=2048)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-launch-steps", type=int, default=8)
@@ -529,6 +725,9 @@ def main() -> int:
     g.close()
     serving = None if args.no_serving else serving_bench(meg, torch, args)
     recovery = None if args.no_recovery else recovery_bench(meg, torch)
+    config1 = None if args.no_configs else config1_bench(meg, torch)
+    config3 = None if args.no_configs else config3_bench(meg, torch)
+    precision = None if args.no_configs else precision_bench(meg, torch)
     # measured HBM bytes per launch (counter runs), only for the kernel they were taken on
     traffic, traffic_note = None, "kernel sources changed since the counter runs"
     if kernel_source_hash() == TRAFFIC["source_hash"] and args.launch_steps == TRAFFIC["iterations_per_launch"]:
@@ -566,6 +765,9 @@ def main() -> int:
         "cpu_baseline": base,
         "serving": serving,
         "recovery": recovery,
+        "config1": config1,
+        "config3": config3,
+        "precision": precision,
     }
     print(json.dumps(out), flush=True)
     return 0

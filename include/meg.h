@@ -352,6 +352,8 @@ typedef struct {
                             (saturates at INT32_MAX)                          */
   double kernel_ms;    /* GPU time of those launches, milliseconds            */
   int64_t extrapolated; /* iterations that ended on the extrapolated block     */
+  int64_t unconverged;  /* iterations whose top pairs missed the tolerance at
+                           max_inner                                        */
 } meg_counters;
 
 meg_status meg_get_counters(meg_ctx ctx, meg_counters* out, int32_t reset);

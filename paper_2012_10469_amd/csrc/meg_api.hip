@@ -93,7 +93,7 @@ struct meg_ctx_s {
   int ev_head = 0, ev_count = 0;
   double kernel_ms = 0.0;
   int64_t launches = 0;
-  int64_t base_iters = 0, base_applies = 0, base_jacobi = 0, base_extrap = 0;  // device counters at the last reset
+  int64_t base_iters = 0, base_applies = 0, base_jacobi = 0, base_extrap = 0, base_unconv = 0;  // at the last reset
   int P = 1;               // persistent grid size
   int aux_nwg = 1;         // row-parallel auxiliary kernels
   Ctl* h_ctl = nullptr;    // pinned host mirror
@@ -2153,6 +2153,7 @@ meg_status meg_get_counters(meg_ctx c, meg_counters* out, int32_t reset) {
   out->jacobi_sweeps = (int32_t)std::min<int64_t>(c->h_ctl->jacobi_done - c->base_jacobi, INT32_MAX);
   out->kernel_ms = c->kernel_ms;
   out->extrapolated = c->h_ctl->extrap_done - c->base_extrap;
+  out->unconverged = c->h_ctl->unconv_done - c->base_unconv;
   if (reset) {
     c->launches = 0;
     c->kernel_ms = 0.0;
@@ -2160,6 +2161,7 @@ meg_status meg_get_counters(meg_ctx c, meg_counters* out, int32_t reset) {
     c->base_applies = c->h_ctl->applies_done;
     c->base_jacobi = c->h_ctl->jacobi_done;
     c->base_extrap = c->h_ctl->extrap_done;
+    c->base_unconv = c->h_ctl->unconv_done;
   }
   return MEG_OK;
 }

@@ -139,6 +139,7 @@ struct Ctl {
   double mu_up;
   int64_t mu_up_t;
   int64_t extrap_done;  // steps that ended extrapolated (counter)
+  int64_t unconv_done;  // steps whose inner solve hit max_inner unconverged (counter)
   // Chebyshev filter of the current sweep: the upper end b of the interval
   // [0, b] taken to hold the unwanted spectrum of Yhat (0: none, a plain
   // power step); the sweep outputs Zout = (Yhat - b/2) Q / (b/2)

@@ -855,6 +855,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
       ctl->polish = 0;
       ctl->xvalid = 0;
       ctl->extrap_done = ctl->extrap_done + (extrap ? 1 : 0);
+      ctl->unconv_done = ctl->unconv_done + ((extrap || top_ok) ? 0 : 1);
       const double la = log(sc.alpha);
       ctl->mu_1 = theta[0] + la - sc.sigma;
       ctl->mu_k = theta[KB - 1] + la - sc.sigma;

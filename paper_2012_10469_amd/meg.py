@@ -110,7 +110,7 @@ class MegKernelTimes(ctypes.Structure):
 class MegCounters(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("iterations", ctypes.c_int64), ("applies", ctypes.c_int64),
                 ("workgroups", ctypes.c_int32), ("jacobi_sweeps", ctypes.c_int32), ("kernel_ms", ctypes.c_double),
-                ("extrapolated", ctypes.c_int64)]
+                ("extrapolated", ctypes.c_int64), ("unconverged", ctypes.c_int64)]
 
 
 class MegCertBoundInfo(ctypes.Structure):
@@ -511,7 +511,7 @@ class LowRankMEG:
         _check(self._lib.meg_get_counters(self._ctx, ctypes.byref(out), 1 if reset else 0), "meg_get_counters")
         return {"launches": out.launches, "iterations": out.iterations, "applies": out.applies,
                 "workgroups": out.workgroups, "jacobi_sweeps": out.jacobi_sweeps, "kernel_ms": out.kernel_ms,
-                "extrapolated": out.extrapolated}
+                "extrapolated": out.extrapolated, "unconverged": out.unconverged}
 
     def dual_gap(self, max_steps: int = 128, tol: float = 1e-10) -> dict:
         """Dual gap <X_t, G> - lambda_min(G) at the current iterate (G its

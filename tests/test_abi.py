@@ -58,7 +58,7 @@ int main(void) {
   O(meg_kernel_times, wg_apply_ms) O(meg_kernel_times, wg_skew_ms) O(meg_kernel_times, reduce_ms)
   O(meg_kernel_times, rr_ms) O(meg_kernel_times, rr_tail_ms) O(meg_kernel_times, jacobi_sweeps)
   O(meg_counters, applies) O(meg_counters, workgroups) O(meg_counters, jacobi_sweeps) O(meg_counters, kernel_ms)
-  O(meg_counters, extrapolated)
+  O(meg_counters, extrapolated) O(meg_counters, unconverged)
   O(meg_dual_gap_info, lambda_min) O(meg_dual_gap_info, t) O(meg_dual_gap_info, steps) O(meg_dual_gap_info, converged)
   O(meg_params, eta) O(meg_params, seed) O(meg_params, flags) O(meg_params, inner_tol)
   O(meg_objective, dense) O(meg_objective, ld) O(meg_objective, nnz) O(meg_objective, batch_idx)

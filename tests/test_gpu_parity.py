@@ -226,10 +226,10 @@ def test_resume_and_batched_launch_bitwise(meg):
         assert ca["iterations"] == cb["iterations"] == 6
         assert ca["applies"] == cb["applies"] and 6 <= ca["applies"] <= 6 * 64
         assert ca["jacobi_sweeps"] == cb["jacobi_sweeps"] > 0
-        assert ca["extrapolated"] == cb["extrapolated"]
+        assert ca["extrapolated"] == cb["extrapolated"] and ca["unconverged"] == cb["unconverged"]
         assert ca["kernel_ms"] > 0 and cb["kernel_ms"] > 0
         assert b.counters() == {"launches": 0, "iterations": 0, "applies": 0, "workgroups": cb["workgroups"],
-                                "jacobi_sweeps": 0, "kernel_ms": 0.0, "extrapolated": 0}
+                                "jacobi_sweeps": 0, "kernel_ms": 0.0, "extrapolated": 0, "unconverged": 0}
         blob = a.get_state()
         for _ in range(3):
             a.step(info=False)
