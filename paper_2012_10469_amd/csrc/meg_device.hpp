@@ -160,6 +160,28 @@ struct Ctl {
 // the masked objective's two sums, the explicit residuals' column sums).
 constexpr int kPartMax = 3 * KMAX * KMAX + 2 + KMAX;
 
+// The record a sweep reduces over the grid (FP64), for block width KB and
+// rank r, with Zout the sweep's output and Zin its input:
+//   [0, KB^2)            C = Zin^T Zout
+//   [KB^2, KB^2 + KT)    G = Zout^T Zout, upper triangle by rows
+//   [KB^2 + KT, f)       P = V^T Zout, its r rows (V = the iterate's basis)
+//   f, f + 1             the masked objective's sum of g^2 and of X_ij^2
+//   f + 2 ...            (FP64 state) the explicit residuals' column sums
+// G travels as a triangle and P without its zero rows: the barrier's
+// reduction reads every word of every workgroup's record.
+template <int KB>
+struct PartRec {
+  static constexpr int KT = KB * (KB + 1) / 2;
+  static constexpr int G_OFF = KB * KB;
+  static constexpr int P_OFF = KB * KB + KT;
+  // position of (a, c), a <= c, in a triangle
+  __host__ __device__ static constexpr int tri(int a, int c) { return a * KB - a * (a - 1) / 2 + (c - a); }
+  __host__ __device__ static constexpr int f_off(int r) { return P_OFF + r * KB; }
+  __host__ __device__ static constexpr int x_off(int r) { return f_off(r) + 2; }
+  __host__ __device__ static constexpr int len(int r, bool xres) { return x_off(r) + (xres ? KB : 0); }
+};
+static_assert(PartRec<KMAX>::len(KMAX - 1, true) <= kPartMax, "partial record buffers");
+
 struct Bufs {
   double* part;     // (workgroups of the team) x plen partial sums (FP64)
   double* gpart;    // per-barrier-group sums of the partials (FP64)
@@ -350,10 +372,13 @@ __device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& 
   unsigned* gc = &b.bar[kBarGroup0 + kBarStride * g];
   __syncthreads();
   if (tid == 0) {
-    s_ok = __hip_atomic_load(&b.bar[kBarErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     s_role = 0;
+    // the error flag and the generation are read together
+    const unsigned err = __hip_atomic_load(&b.bar[kBarErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned gen = __hip_atomic_load(&b.bar[kBarGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_ok = err == 0;
+    s_gen = gen;
     if (s_ok) {
-      s_gen = __hip_atomic_load(&b.bar[kBarGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const unsigned prev = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       if (prev == gsize - 1) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the group's writes

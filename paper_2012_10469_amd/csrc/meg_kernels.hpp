@@ -84,7 +84,7 @@ __device__ __forceinline__ T group_sum(T v) {
 
 // Scratch doubles the small solves need (they reuse the apply's LDS).
 template <int KB>
-constexpr int small_scratch() { return 5 * KB * (KB + 1) + 8 * KB; }
+constexpr int small_scratch() { return 5 * KB * (KB + 1) + 12 * KB; }
 
 // Rows per wave of the dense apply: keep RPW * KB accumulators per lane modest.
 template <typename T, int KB>
@@ -121,10 +121,9 @@ struct ApplySmem {
   // its input rows go to the T_B rows once those are used up
   static constexpr int XR = sizeof(T) == 8 ? 1 : 0;
   static constexpr int TYPED_DOUBLES = (T_END * (int)sizeof(T) + 7) / 8;
-  static constexpr int PLEN = 3 * KB * KB;       // Gram accumulator (FP64)
-  static constexpr int XOFF = PLEN + 2;          // residual column sums in the partial record
-  // per-workgroup partials: Gram, sum g^2, sum X_ij^2, residual column sums
-  static constexpr int PSTRIDE = PLEN + 2 + XR * KB;
+  static constexpr int PLEN = 3 * KB * KB;       // Gram accumulators (FP64): Zin^T Zout, G, P
+  // longest per-workgroup partial record (PartRec; its length depends on r)
+  static constexpr int PSTRIDE = PartRec<KB>::len(KB - 1, XR != 0);
   static constexpr int ACC = PLEN + XR * KB;     // accumulators: Gram, residual column sums
   static constexpr int SMALL = small_scratch<KB>();
   static constexpr int BODY = TYPED_DOUBLES > SMALL ? TYPED_DOUBLES : SMALL;
@@ -212,7 +211,7 @@ __device__ inline void step_scalars(const Cfg& cfg, gbl<Ctl>* ctl, int lane) {
   const double alpha = ctl->alpha, dl = act ? ctl->d[lane] : 0.0, cl = act ? ctl->c[lane] : 0.0;
   const double gmax =
       grad_bound(cfg, alpha, dl, ctl->op_lmin, ctl->op_lmax, ctl->pxvalid, ctl->pxnorm, ctl->dxnorm, lane);
-  setup_step_v(cfg, ctl, gmax, alpha, dl, cl, lane);
+  setup_step_v(cfg, ctl, gmax, alpha, dl, cl, ctl->mu_1, ctl->mu_k, ctl->mu_valid, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1105,8 +1104,16 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
     }
   }
   __syncthreads();
-  double* dst = part + (size_t)tm.wg * SM::PSTRIDE;
-  for (int e = tid; e < SM::PLEN; e += NT) dst[e] = smem[e];
+  // the record (PartRec): C, G's upper triangle, P's r rows, the
+  // objective's two sums, the residuals' column sums
+  using PR = PartRec<KB>;
+  double* dst = part + (size_t)tm.wg * PR::len(r, SM::XR != 0);
+  for (int e = tid; e < KB * KB; e += NT) {
+    dst[e] = smem[e];
+    const int a = e / KB, c = e % KB;
+    if (a <= c) dst[PR::G_OFF + PR::tri(a, c)] = smem[KB * KB + e];
+  }
+  for (int e = tid; e < r * KB; e += NT) dst[PR::P_OFF + e] = smem[2 * KB * KB + e];
   if (tid == 0) {
     double sg = 0.0, sx = 0.0;
     if constexpr (GRAD)
@@ -1114,11 +1121,11 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
         sg += sred[w];
         sx += sred[WAVES + w];
       }
-    dst[SM::PLEN] = sg;
-    dst[SM::PLEN + 1] = sx;
+    dst[PR::f_off(r)] = sg;
+    dst[PR::f_off(r) + 1] = sx;
   }
   if constexpr (SM::XR != 0)
-    if (tid < KB) dst[SM::XOFF + tid] = xr ? smem[SM::PLEN + tid] : 0.0;
+    if (tid < KB) dst[PR::x_off(r) + tid] = xr ? smem[SM::PLEN + tid] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1291,22 +1298,15 @@ __device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl,
                                                   (lds<char>*)xstage, tm);
       }
       stamp_wg(b, tm, s, 1);
-      if (!grid_sync<NT>(b, tm, SM::PSTRIDE, [&] {
+      if (!grid_sync<NT>(b, tm, PartRec<KB>::len(cfg.r, SM::XR != 0), [&] {
             stamp(b, 2 * s);
-            if (tid < 64) {
-              gbl<Ctl>* gc = (gbl<Ctl>*)ctl;
-              if (grad && tid == 0) {  // f(X_t) = 1/2 sum_Omega g^2, ||P_Omega X_t||_F
-                gc->f = 0.5 * b.sums[SM::PLEN];
-                gc->fvalid = 1;
-                gc->pxnorm = sqrt(b.sums[SM::PLEN + 1]);
-                gc->pxvalid = 1;
-              }
-              // the step ends here when it returns true: X_{t+1}, t + 1 and
-              // the scalars of step t + 1 are set
-              const bool fin = small_sweep<KB>(cfg, gc, (const gbl<double>*)b.sums, (lds<double>*)smem, s, in, out,
-                                               tid, (gbl<long long>*)b.ts);
-              if (fin && deadline != 0 && tid == 0 && (long long)wall_clock64() >= deadline) gc->pause_seq = seq;
-            }
+            gbl<Ctl>* gc = (gbl<Ctl>*)ctl;
+            // every thread calls it (it runs on two wavefronts); the step
+            // ends here when it returns true: X_{t+1}, t + 1 and the scalars
+            // of step t + 1 are set
+            const bool fin = small_sweep<KB>(cfg, gc, (const gbl<double>*)b.sums, (lds<double>*)smem, s, in, out,
+                                             grad, tid, (gbl<long long>*)b.ts);
+            if (fin && deadline != 0 && tid == 0 && (long long)wall_clock64() >= deadline) gc->pause_seq = seq;
             stamp(b, 2 * s + 1);
           }))
         return;

@@ -73,6 +73,24 @@ __device__ __forceinline__ void load_mat(const gbl<double>* src, lds<double>* ds
   }
 }
 
+// symmetric KB x KB from its upper triangle by rows (PartRec) -> LDS
+// stride KB + 1, both triangles; all loads issued before any is stored
+template <int KB>
+__device__ __forceinline__ void load_sym(const gbl<double>* src, lds<double>* dst, int lane) {
+  constexpr int IT = KB * KB / 64;
+  double v[IT];
+#pragma unroll
+  for (int u = 0; u < IT; ++u) {
+    const int e = lane + 64 * u, i = e / KB, j = e % KB;
+    v[u] = src[i <= j ? PartRec<KB>::tri(i, j) : PartRec<KB>::tri(j, i)];
+  }
+#pragma unroll
+  for (int u = 0; u < IT; ++u) {
+    const int e = lane + 64 * u;
+    dst[(e / KB) * (KB + 1) + (e % KB)] = v[u];
+  }
+}
+
 template <int KB>
 __device__ __forceinline__ void store_mat(const lds<double>* src, gbl<double>* dst, int lane) {
 #pragma unroll
@@ -320,18 +338,24 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 }
 
 // Cholesky A = R^T R (R upper) of the symmetric positive definite A (LDS,
-// upper triangle read), then Rinv = R^{-1} (upper, LDS).  Lane c holds
-// column c in registers; every value another lane needs is a readlane of a
-// compile-time lane index, so the factorisation touches no memory.  Tiny
-// pivots are floored to keep R invertible.
+// upper triangle read), R written to LDS (stride KB + 1, zero below the
+// diagonal) and the reciprocals of its diagonal to rdiag[0, KB).  Lane c
+// holds column c in registers; every value another lane needs is a readlane
+// of a compile-time lane index, so the factorisation touches no memory until
+// R is stored.  Tiny pivots are floored to keep R invertible.
 template <int KB>
-__device__ __noinline__ void chol_inv(const lds<double>* A, lds<double>* Rinv, int lane) {
+__device__ __noinline__ void chol_factor(const lds<double>* A, lds<double>* R, lds<double>* rdiag, int lane) {
   constexpr int LD = KB + 1;
+  const int col = lane < KB ? lane : KB - 1;
   double a[KB];  // column `lane` of A, overwritten by column `lane` of R
 #pragma unroll
-  for (int i = 0; i < KB; ++i) a[i] = (lane < KB && i <= lane) ? A[i * LD + lane] : 0.0;
-  const double scale = wave_max(lane < KB ? A[lane * LD + lane] : 0.0);
+  for (int i = 0; i < KB; ++i) {
+    const double v = A[i * LD + col];
+    a[i] = (lane < KB && i <= lane) ? v : 0.0;
+  }
+  const double scale = wave_max(lane < KB ? A[col * LD + col] : 0.0);
   const double floor_piv = fmax(scale, 1e-300) * 1e-28;
+  double rd = 0.0;  // 1 / R_cc in lane c
 #pragma unroll
   for (int j = 0; j < KB; ++j) {
     double dj = readlane_d(a[j], j);
@@ -339,26 +363,71 @@ __device__ __noinline__ void chol_inv(const lds<double>* A, lds<double>* Rinv, i
     const double rinv = rsqrt_nr(dj);
     // row j of R: R_jj = sqrt(dj) (lane j), R_jc = A_jc / R_jj (lanes c > j)
     a[j] = (lane == j) ? dj * rinv : a[j] * rinv;
+    rd = (lane == j) ? rinv : rd;
 #pragma unroll
     for (int i = j + 1; i < KB; ++i) {
-      const double rji = readlane_d(a[j], i);  // R_ji, held by lane i
-      if (lane >= i) a[i] -= rji * a[j];      // A_ic -= R_ji R_jc, i <= c
+      // A_ic -= R_ji R_jc (R_ji held by lane i).  Done in every lane: the
+      // entries below a lane's diagonal (i > c) are never read.
+      a[i] -= readlane_d(a[j], i) * a[j];
     }
-  }
-  // R X = I, column `lane` of X by back substitution; R_il is a[i] of lane l
-  double x[KB];
-#pragma unroll
-  for (int i = KB - 1; i >= 0; --i) {
-    double s = (i == lane) ? 1.0 : 0.0;
-#pragma unroll
-    for (int l = i + 1; l < KB; ++l) s -= readlane_d(a[i], l) * x[l];
-    x[i] = (i > lane) ? 0.0 : s * rcp_nr(readlane_d(a[i], i));
   }
   if (lane < KB) {
 #pragma unroll
-    for (int i = 0; i < KB; ++i) Rinv[i * LD + lane] = x[i];
+    for (int i = 0; i < KB; ++i) R[i * LD + lane] = (i <= lane) ? a[i] : 0.0;
+    rdiag[lane] = rd;
   }
   wsync();
+}
+
+// Y = X R^{-1} for the first `rows` (<= 64) rows of X (LDS, stride KB + 1; Y
+// may be X) with R upper triangular (LDS, as chol_factor leaves it): lane i
+// solves y R = x_i by forward substitution, y_j = (x_ij - sum_{m<j} y_m R_mj)
+// / R_jj, subtracting each y_j from the later columns as soon as it is known.
+// Every lane reads the same entries of R at the same time (LDS broadcasts).
+template <int KB>
+__device__ __noinline__ void rsolve(const lds<double>* X, lds<double>* Y, const lds<double>* R,
+                                    const lds<double>* rdiag, int rows, int lane) {
+  constexpr int LD = KB + 1;
+  const bool act = lane < rows;
+  const int row = act ? lane : rows - 1;  // lanes past the rows solve a copy of the last one
+  double y[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) y[j] = X[row * LD + j];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) {
+    // R is consumed two rows at a time: the running values are pinned and
+    // memory is fenced for the compiler here, so later rows are not read
+    // ahead into registers (all of R would not fit)
+    if (j % 2 == 0) {
+#pragma unroll
+      for (int i = 0; i < KB; ++i) __asm__ volatile("" : "+v"(y[i])::"memory");
+    }
+    y[j] *= rdiag[j];
+#pragma unroll
+    for (int i = j + 1; i < KB; ++i) y[i] -= y[j] * R[j * LD + i];
+  }
+  wsync();  // every lane has read its row before any row is written (Y may be X)
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < KB; ++j) Y[lane * LD + j] = y[j];
+  }
+  wsync();
+}
+
+// Rows [X1; X2] (2 KB rows from X1, X2 = X1 + KB * (KB + 1)) times R^{-1}
+// in place, for R the Cholesky factor of the Gram matrix A: the
+// orthonormalising transform applied to two KB x KB blocks at once.  Rscr:
+// KB * (KB + 1) doubles for R, rdiag: KB doubles.
+template <int KB>
+__device__ __forceinline__ void chol_apply2(const lds<double>* A, lds<double>* X1, lds<double>* Rscr,
+                                            lds<double>* rdiag, int lane) {
+  chol_factor<KB>(A, Rscr, rdiag, lane);
+  if constexpr (2 * KB <= 64) {
+    rsolve<KB>(X1, X1, Rscr, rdiag, 2 * KB, lane);
+  } else {
+    rsolve<KB>(X1, X1, Rscr, rdiag, KB, lane);
+    rsolve<KB>(X1 + KB * (KB + 1), X1 + KB * (KB + 1), Rscr, rdiag, KB, lane);
+  }
 }
 
 // Per-step operator coefficients: Yhat = V diag(ceff) V^T + opscale*Op + sdiag*I
@@ -371,8 +440,10 @@ __device__ __noinline__ void chol_inv(const lds<double>* A, lds<double>* Rinv, i
 // the (r+1)-th pair converge.  One wavefront (all 64 lanes call it).
 // setup_step_v takes the iterate's alpha, d_l and c_l (lane l < r; zero
 // elsewhere) from the caller, setup_step reads them from ctl.
+// mu_1, mu_k: the last step's extreme Ritz values as eigenvalues of M
+// (mu_valid 0: none), for the first sweep's Chebyshev interval.
 __device__ inline void setup_step_v(const Cfg& cfg, gbl<Ctl>* ctl, double gmax, double alpha, double dl, double cl,
-                                    int lane) {
+                                    double mu_1, double mu_k, int mu_valid, int lane) {
   const int r = cfg.r;
   const bool act = lane < r;
   const double cmin = wave_min(act ? fmin(cl, 0.0) : 0.0);
@@ -392,9 +463,9 @@ __device__ inline void setup_step_v(const Cfg& cfg, gbl<Ctl>* ctl, double gmax, 
     // the first sweep's Chebyshev interval [0, b]: the last step's mu_k,
     // shifted as this step's operator is (Yhat = M_t - log alpha + sigma)
     double b = 0.0;
-    if (cfg.cheb && ctl->mu_valid) {
+    if (cfg.cheb && mu_valid) {
       const double la = log(alpha);
-      const double bk = ctl->mu_k - la + sigma, b1 = ctl->mu_1 - la + sigma;
+      const double bk = mu_k - la + sigma, b1 = mu_1 - la + sigma;
       if (bk > 1e-3 * b1 && bk < 0.5 * b1) b = bk;
     }
     ctl->cheb_b = b;
@@ -402,7 +473,8 @@ __device__ inline void setup_step_v(const Cfg& cfg, gbl<Ctl>* ctl, double gmax, 
 }
 __device__ inline void setup_step(const Cfg& cfg, gbl<Ctl>* ctl, double gmax, int lane) {
   const bool act = lane < cfg.r;
-  setup_step_v(cfg, ctl, gmax, ctl->alpha, act ? ctl->d[lane] : 0.0, act ? ctl->c[lane] : 0.0, lane);
+  setup_step_v(cfg, ctl, gmax, ctl->alpha, act ? ctl->d[lane] : 0.0, act ? ctl->c[lane] : 0.0, ctl->mu_1, ctl->mu_k,
+               ctl->mu_valid, lane);
 }
 
 // gmax >= lambda_max(grad f(X_t)) for the objectives whose bound needs no pass
@@ -428,7 +500,7 @@ struct SolveScalars {
   double alpha, sigma, solve_tol, f, pxnorm, op_lmin, op_lmax, dl;  // dl: d_l of this lane (l < r)
   double mu_up;  // an upper bound of mu_{r+1} for this step (+inf: none)
   double cheb_b, xscale;
-  int64_t t, iters, applies, jacobi;
+  int64_t t, iters, applies, jacobi, extrap_n, unconv_n;
   int fvalid, pxvalid, polish, xvalid;
 };
 __device__ __forceinline__ SolveScalars load_scalars(const Cfg& cfg, const gbl<Ctl>* ctl, int lane) {
@@ -448,6 +520,8 @@ __device__ __forceinline__ SolveScalars load_scalars(const Cfg& cfg, const gbl<C
   s.iters = ctl->iters_done;
   s.applies = ctl->applies_done;
   s.jacobi = ctl->jacobi_done;
+  s.extrap_n = ctl->extrap_done;
+  s.unconv_n = ctl->unconv_done;
   s.fvalid = ctl->fvalid;
   s.pxvalid = ctl->pxvalid;
   s.polish = ctl->polish;
@@ -542,377 +616,465 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
   }
 }
 
-// One Rayleigh-Ritz / orthonormalisation step.  `sums` (global) holds, stride KB:
-//   C = Zin^T Zout, G = Zout^T Zout, P = V^T Zout (first r rows)
-// where Zout = Yhat Q and Q = Zin W is orthonormal.  Sets the next sweep's
-// W and PW = V^T Q', or ends the step: the Ritz basis Zin (W S) becomes the
-// next warm start (B, Wb) = (Zin, W S), advances t and sets the next step's
-// shift and coefficients.  Counts the apply (and the Jacobi sweeps) in ctl.
-// Returns true when the step ended.
-// One wavefront (lanes 0..63).  `scr` (LDS) needs 5 * KB * (KB + 1) + 8 * KB
-// doubles.
+// One Rayleigh-Ritz / orthonormalisation step.  `sums` (global) holds the
+// reduced record of PartRec: C = Zin^T Zout, G = Zout^T Zout (triangle),
+// P = V^T Zout (r rows), where Zout = Yhat Q and Q = Zin W is orthonormal.
+// Sets the next sweep's W and PW = V^T Q', or ends the step: the Ritz basis
+// Zin (W S) becomes the next warm start (B, Wb) = (Zin, W S), advances t and
+// sets the next step's shift and coefficients.  Counts the apply (and the
+// Jacobi sweeps) in ctl.  `grad`: this sweep formed the masked gradient (its
+// objective sums are in the record).  Returns true when the step ended.
+// Called by every thread of the workgroup (tid); the work runs on two
+// wavefronts, wave-synchronously within each: wavefront 0 solves, wavefront
+// 1 meanwhile forms eps_t and, when the step ends here, the new iterate and
+// its certificate while wavefront 0 forms the next basis.  `scr` (LDS)
+// needs 5 * KB * (KB + 1) + 12 * KB doubles.
 template <int KB>
 __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gbl<double>* sums, lds<double>* scr,
-                                         int sweep, int in_buf, int out_buf, int lane, gbl<long long>* ts) {
+                                         int sweep, int in_buf, int out_buf, bool grad, int tid,
+                                         gbl<long long>* ts) {
   constexpr int LD = KB + 1;
   constexpr int MS = KB * LD;
+  const int lane = tid & 63, wave = tid >> 6;
   lds<double>* A = scr;            // T, then diagonalised
   lds<double>* S = scr + MS;       // Ritz vectors (unsorted)
   lds<double>* B1 = scr + 2 * MS;  // W, then sorted S
-  lds<double>* B2 = scr + 3 * MS;  // C, then G S, then Rinv
+  lds<double>* B2 = scr + 3 * MS;  // C, then G S, then P S
   lds<double>* B3 = scr + 4 * MS;  // G, then Ghat = S^T G S
-  lds<double>* vec = scr + 5 * MS; // 8 * KB
+  lds<double>* vec = scr + 5 * MS; // 12 * KB
   lds<double>* theta = vec;
   lds<double>* rho = vec + KB;
   lds<double>* jrot = vec + 2 * KB;  // 2 * KB: rotations of a Jacobi round (KB > 16)
+  lds<double>* rdiag = vec + 4 * KB;  // reciprocal diagonal of a Cholesky factor
   lds<int>* perm = reinterpret_cast<lds<int>*>(vec + 6 * KB);
+  lds<double>* xch = vec + 8 * KB;   // 4 * KB: what the two wavefronts exchange
   const int r = cfg.r;
+  using PR = PartRec<KB>;
+  const int fo = PR::f_off(r);
 
   if (sweep < cfg.rr_from && sweep < cfg.max_inner) {
-    // early sweep of a warm-started step: orthonormalise only,
-    // Q' = Zout R^{-1} with Zout^T Zout = R^T R;  PW' = V^T Zout R^{-1}
-    const int64_t applies = ctl->applies_done;
-    load_mat<KB>(sums + KB * KB, B3, lane);
-    load_mat<KB>(sums + 2 * KB * KB, S, lane);
-    wsync();
-    chol_inv<KB>(B3, B2, lane);
-    mm_nn<KB>(S, B2, A, lane);
-    wsync();
-    store_mat<KB>(B2, ctl->W, lane);
-    store_mat<KB>(A, ctl->PW, lane);
-    if (lane == 0) {
-      ctl->sweep = sweep + 1;
-      ctl->applies_done = applies + 1;
-      ctl->xvalid = 0;
+    if (wave == 0) {
+      // early sweep of a warm-started step: orthonormalise only,
+      // Q' = Zout R^{-1} with Zout^T Zout = R^T R;  PW' = V^T Zout R^{-1}
+      const int64_t applies = ctl->applies_done;
+      const double fs = grad ? sums[fo] : 0.0, px2 = grad ? sums[fo + 1] : 0.0;
+      load_sym<KB>(sums + PR::G_OFF, B3, lane);
+      for (int e = lane; e < KB * KB; e += 64) {
+        const int i = e / KB, j = e % KB;
+        B1[i * LD + j] = (i < r) ? sums[PR::P_OFF + e] : 0.0;  // P (its r rows)
+        S[i * LD + j] = (i == j) ? 1.0 : 0.0;
+      }
+      wsync();
+      chol_apply2<KB>(B3, S, B2, rdiag, lane);  // S = R^{-1}, B1 = P R^{-1}
+      store_mat<KB>(S, ctl->W, lane);
+      store_mat<KB>(B1, ctl->PW, lane);
+      if (lane == 0) {
+        if (grad) {  // f(X_t) = 1/2 sum_Omega g^2, ||P_Omega X_t||_F
+          ctl->f = 0.5 * fs;
+          ctl->fvalid = 1;
+          ctl->pxnorm = sqrt(px2);
+          ctl->pxvalid = 1;
+        }
+        ctl->sweep = sweep + 1;
+        ctl->applies_done = applies + 1;
+        ctl->xvalid = 0;
+      }
     }
     return false;
   }
 
-  const SolveScalars sc = load_scalars(cfg, ctl, lane);
-  // W stays in registers too: the step's end forms W S from it
+  // Rayleigh-Ritz sweep.  Both wavefronts load the step's scalars.
+  SolveScalars sc{};
+  if (wave < 2) {
+    sc = load_scalars(cfg, ctl, lane);
+    if (grad) {
+      sc.f = 0.5 * sums[fo];
+      sc.fvalid = 1;
+      sc.pxnorm = sqrt(sums[fo + 1]);
+      sc.pxvalid = 1;
+    }
+  }
+  if (wave == 1 && lane == 0) xch[0] = eps_at(cfg, sc.t);
+  // wavefront 0's state across the sections below
   constexpr int WE = KB * KB / 64;
-  double wreg[WE];
-#pragma unroll
-  for (int u = 0; u < WE; ++u) wreg[u] = ctl->W[lane + 64 * u];
-#pragma unroll
-  for (int u = 0; u < WE; ++u) {
-    const int e = lane + 64 * u;
-    B1[(e / KB) * LD + (e % KB)] = wreg[u];
-  }
-  load_mat<KB>(sums, B2, lane);
-  load_mat<KB>(sums + KB * KB, B3, lane);
-  // P = V^T Zout (for the next sweep's PW) and this sweep's PW = V^T Q, held
-  // in registers: the first is used only if another sweep follows, the
-  // second gives V_t^T V_{t+1} = PW S[:, :r] when the step ends here
   constexpr int PE = (KB * KB + 63) / 64;
-  double pnew[PE], pold[PE];
+  double wreg[WE], pnew[PE], pold[PE];
+  double fa = 1.0, fb = 0.0, th = 0.0, fth = 0.0, rh = 0.0, thr = 0.0, rmax = 0.0, margin = 0.0;
+  double floor_est = 0.0, tol_abs = 0.0, scale = 1.0, xr = 0.0, xthr = 0.0, rr1 = 0.0, xr1 = 0.0;
+  bool exact = false, finite = true, resolved = false, light = false, cert_ok = false, top_ok = false;
+  bool fin = false, extrap = false, do_polish = false;
+  int jsweeps = 0, polish = 0;
+  const bool prof = ts != nullptr && tid == 0 && sweep == cfg.rr_from;
+  if (wave == 0) {
+    // W stays in registers too: the step's end forms W S from it.  All of
+    // the solve's global reads are issued before any is stored.
+    double cv[WE], gv[WE];
 #pragma unroll
-  for (int m = 0; m < PE; ++m) {
-    const int e = lane + 64 * m;
-    pnew[m] = (e < KB * KB) ? sums[2 * KB * KB + e] : 0.0;
-    pold[m] = (e < KB * KB) ? ctl->PW[e] : 0.0;
-  }
-  const int polish = sc.polish;
-  // this sweep's filter: Zout = fa Yhat Q + fb Q (Chebyshev degree 1 on
-  // [0, cheb_b]; fa = 1, fb = 0 without one)
-  const double fa = sc.cheb_b > 0.0 ? 2.0 / sc.cheb_b : 1.0, fb = sc.cheb_b > 0.0 ? -1.0 : 0.0;
-  wsync();
-  mm_tn<KB>(B1, B2, A, lane);  // W^T C = Q^T Zout = fa Q^T Yhat Q + fb I
-  wsync();
-  for (int e = lane; e < KB * KB; e += 64) {  // T = Q^T Yhat Q, symmetrised
-    const int i = e / KB, j = e % KB;
-    if (i < j) {
-      const double v = 0.5 * (A[i * LD + j] + A[j * LD + i]) / fa;
-      A[i * LD + j] = v;
-      A[j * LD + i] = v;
-    } else if (i == j) {
-      A[i * LD + i] = (A[i * LD + i] - fb) / fa;
+    for (int u = 0; u < WE; ++u) {
+      const int e = lane + 64 * u, i = e / KB, j = e % KB;
+      wreg[u] = ctl->W[e];
+      cv[u] = sums[e];  // C
+      gv[u] = sums[PR::G_OFF + (i <= j ? PR::tri(i, j) : PR::tri(j, i))];
     }
-  }
-  wsync();
-  // profiled launches: stamps of the first Rayleigh-Ritz sweep's parts
-  const bool prof = ts != nullptr && lane == 0 && sweep == cfg.rr_from;
-  if (prof) ts[kTsRR] = wall_clock64();
-  // Off-diagonal mass left by Jacobi, relative: 1e-8 for an FP32 state
-  // (below its unit roundoff 6e-8; the eigenvectors then carry errors of
-  // off/gap, and the residual test sees at most 1e-8 of the scale), 1e-15
-  // for FP64.  The tolerance is on squared norms.
-  const int jsweeps = jacobi<KB>(A, S, cfg.unit_round < 1e-10 ? 1e-30 : 1e-16, lane, jrot);
-  if (lane == 0) ctl->jacobi_done = sc.jacobi + jsweeps;
-  if (prof) {
-    ts[kTsRR + 1] = wall_clock64();
-    ts[kTsRR + 4] = jsweeps;
-  }
-  // sort eigenvalues descending: rank of each diagonal entry, ties broken by
-  // index; NaN ranks as -inf so the ranks always form a permutation (the NaN
-  // itself is caught by the finiteness check below)
-  if (lane < KB) {
-    const double v0 = A[lane * LD + lane];
-    const double v = isnan(v0) ? -__builtin_inf() : v0;
-    int rank = 0;
+    // P = V^T Zout (for the next sweep's PW) and this sweep's PW = V^T Q, held
+    // in registers: the first is used only if another sweep follows, the
+    // second gives V_t^T V_{t+1} = PW S[:, :r] when the step ends here
 #pragma unroll
-    for (int j = 0; j < KB; ++j) {
-      const double w0 = A[j * LD + j];
-      const double w = isnan(w0) ? -__builtin_inf() : w0;
-      rank += (w > v || (w == v && j < lane)) ? 1 : 0;
+    for (int m = 0; m < PE; ++m) {
+      const int e = lane + 64 * m;
+      pnew[m] = (e < r * KB) ? sums[PR::P_OFF + e] : 0.0;
+      pold[m] = (e < KB * KB) ? ctl->PW[e] : 0.0;
     }
-    perm[rank] = lane;
-    theta[rank] = v0;
+#pragma unroll
+    for (int u = 0; u < WE; ++u) {
+      const int e = lane + 64 * u, o = (e / KB) * LD + (e % KB);
+      B1[o] = wreg[u];
+      B2[o] = cv[u];
+      B3[o] = gv[u];
+    }
+    polish = sc.polish;
+    // this sweep's filter: Zout = fa Yhat Q + fb Q (Chebyshev degree 1 on
+    // [0, cheb_b]; fa = 1, fb = 0 without one)
+    fa = sc.cheb_b > 0.0 ? 2.0 / sc.cheb_b : 1.0;
+    fb = sc.cheb_b > 0.0 ? -1.0 : 0.0;
+    wsync();
+    mm_tn<KB>(B1, B2, A, lane);  // W^T C = Q^T Zout = fa Q^T Yhat Q + fb I
+    wsync();
+    for (int e = lane; e < KB * KB; e += 64) {  // T = Q^T Yhat Q, symmetrised
+      const int i = e / KB, j = e % KB;
+      if (i < j) {
+        const double v = 0.5 * (A[i * LD + j] + A[j * LD + i]) / fa;
+        A[i * LD + j] = v;
+        A[j * LD + i] = v;
+      } else if (i == j) {
+        A[i * LD + i] = (A[i * LD + i] - fb) / fa;
+      }
+    }
+    wsync();
+    // profiled launches: stamps of the first Rayleigh-Ritz sweep's parts
+    if (prof) ts[kTsRR] = wall_clock64();
+    // Off-diagonal mass left by Jacobi, relative: 1e-8 for an FP32 state
+    // (below its unit roundoff 6e-8; the eigenvectors then carry errors of
+    // off/gap, and the residual test sees at most 1e-8 of the scale), 1e-15
+    // for FP64.  The tolerance is on squared norms.
+    jsweeps = jacobi<KB>(A, S, cfg.unit_round < 1e-10 ? 1e-30 : 1e-16, lane, jrot);
+    if (lane == 0) ctl->jacobi_done = sc.jacobi + jsweeps;
+    if (prof) {
+      ts[kTsRR + 1] = wall_clock64();
+      ts[kTsRR + 4] = jsweeps;
+    }
+    // sort eigenvalues descending: rank of each diagonal entry, ties broken by
+    // index; NaN ranks as -inf so the ranks always form a permutation (the NaN
+    // itself is caught by the finiteness check below)
+    if (lane < KB) {
+      const double v0 = A[lane * LD + lane];
+      const double v = isnan(v0) ? -__builtin_inf() : v0;
+      int rank = 0;
+  #pragma unroll
+      for (int j = 0; j < KB; ++j) {
+        const double w0 = A[j * LD + j];
+        const double w = isnan(w0) ? -__builtin_inf() : w0;
+        rank += (w > v || (w == v && j < lane)) ? 1 : 0;
+      }
+      perm[rank] = lane;
+      theta[rank] = v0;
+    }
+    wsync();
+    for (int e = lane; e < KB * KB; e += 64) {  // B1 <- sorted S
+      const int i = e / KB, j = e % KB;
+      B1[i * LD + j] = S[i * LD + perm[j]];
+    }
+    wsync();
+    mm_nn<KB>(B3, B1, B2, lane);  // G S
+    wsync();
+    mm_tn<KB>(B1, B2, B3, lane);  // Ghat = S^T G S  (Gram of Zout S)
+    wsync();
+    // Ritz residuals: Zout s_i = (fa theta_i + fb) q_i + fa (Yhat q_i - theta_i q_i),
+    // so ||Yhat q_i - theta_i q_i||^2 = (Ghat_ii - (fa theta_i + fb)^2) / fa^2
+    th = (lane < KB) ? theta[lane] : 0.0;
+    fth = fa * th + fb;
+    rh = (lane < KB) ? sqrt(fmax(B3[lane * LD + lane] - fth * fth, 0.0)) / fabs(fa) : 0.0;
+    if (lane < KB) {
+      rho[lane] = rh;
+      ctl->theta[lane] = th;
+      ctl->resid[lane] = rh;
+    }
+    scale = fmax(fabs(lane_f64(th, 0)), 1e-300);
+    // Residuals come from Ghat_ii - theta_i^2 in FP64: resolvable down to
+    // ~sqrt(2^-53) of the scale; working-precision rounding sets another floor.
+    floor_est = fmax(3e-8, 8.0 * cfg.unit_round) * scale;
+    tol_abs = cfg.inner_tol * scale;
+    thr = fmax(tol_abs, floor_est);
+    // Below that floor (FP64 state) the test also needs the explicit residuals
+    // ||Zout s_i - theta_i Q s_i|| of the previous sweep's pairs, which this
+    // sweep's apply formed from its rows; this sweep's pairs are one power
+    // step further on.  Their floor is the apply's rounding.
+    exact = cfg.xres && tol_abs < floor_est;
+    xthr = fmax(tol_abs, 64.0 * cfg.unit_round * scale);
+    xr = (exact && sc.xvalid && lane < KB) ? sqrt(fmax(sums[PR::x_off(r) + lane], 0.0)) * sc.xscale
+                                                        : __builtin_inf();
+    rmax = wave_max(lane < r ? rh : 0.0);
+    finite = wave_min((lane < KB) ? ((isfinite(th) && isfinite(rh)) ? 1.0 : 0.0) : 1.0) > 0.5;
+    rr1 = lane_f64(rh, r);
+    xr1 = lane_f64(xr, r);
   }
-  wsync();
-  for (int e = lane; e < KB * KB; e += 64) {  // B1 <- sorted S
-    const int i = e / KB, j = e % KB;
-    B1[i * LD + j] = S[i * LD + perm[j]];
-  }
-  wsync();
-  mm_nn<KB>(B3, B1, B2, lane);  // G S
-  wsync();
-  mm_tn<KB>(B1, B2, B3, lane);  // Ghat = S^T G S  (Gram of Zout S)
-  wsync();
-  // Ritz residuals: Zout s_i = (fa theta_i + fb) q_i + fa (Yhat q_i - theta_i q_i),
-  // so ||Yhat q_i - theta_i q_i||^2 = (Ghat_ii - (fa theta_i + fb)^2) / fa^2
-  const double th = (lane < KB) ? theta[lane] : 0.0;
-  const double fth = fa * th + fb;
-  const double rh = (lane < KB) ? sqrt(fmax(B3[lane * LD + lane] - fth * fth, 0.0)) / fabs(fa) : 0.0;
-  if (lane < KB) {
-    rho[lane] = rh;
-    ctl->theta[lane] = th;
-    ctl->resid[lane] = rh;
-  }
-  const double scale = fmax(fabs(lane_f64(th, 0)), 1e-300);
-  // Residuals come from Ghat_ii - theta_i^2 in FP64: resolvable down to
-  // ~sqrt(2^-53) of the scale; working-precision rounding sets another floor.
-  const double floor_est = fmax(3e-8, 8.0 * cfg.unit_round) * scale;
-  const double tol_abs = cfg.inner_tol * scale;
-  const double thr = fmax(tol_abs, floor_est);
-  // Below that floor (FP64 state) the test also needs the explicit residuals
-  // ||Zout s_i - theta_i Q s_i|| of the previous sweep's pairs, which this
-  // sweep's apply formed from its rows; this sweep's pairs are one power
-  // step further on.  Their floor is the apply's rounding.
-  const bool exact = cfg.xres && tol_abs < floor_est;
-  const double xthr = fmax(tol_abs, 64.0 * cfg.unit_round * scale);
-  const double xr = (exact && sc.xvalid && lane < KB) ? sqrt(fmax(sums[3 * KB * KB + 2 + lane], 0.0)) * sc.xscale
-                                                      : __builtin_inf();
-  const double rmax = wave_max(lane < r ? rh : 0.0);
-  const bool finite = wave_min((lane < KB) ? ((isfinite(th) && isfinite(rh)) ? 1.0 : 0.0) : 1.0) > 0.5;
-  const double rr1 = lane_f64(rh, r);
-  const double xr1 = lane_f64(xr, r);
-  // A top-r pair enters X_{t+1} = alpha' I + V diag(d') V^T only through
-  // d'_l v_l v_l^T: even an entirely wrong v_l moves X by at most
-  // sqrt(2) |d'_l|, i.e. sqrt(2) w_l of ||X||_F with w_l = |d'_l| / max |d'|.
-  // Pairs with w_l <= inner_tol / 4 therefore need no residual test (in the
-  // noise bulk of M_t such pairs converge slowly and carry no weight).
-  // d' follows from the Ritz values exactly as finish_step forms it.
-  const double mu = (lane < r) ? th + log(sc.alpha) - sc.sigma : -__builtin_inf();
-  const double mmax = wave_max(mu);
-  const double ex = (lane < r) ? exp(mu - mmax) : 0.0;
-  const double esum = wave_sum(ex);
-  const double eps_t = eps_at(cfg, sc.t);  // once per sweep: finish_step reuses it
-  const double dl_new = (lane < r) ? (1.0 - eps_t) * ex / esum - eps_t / (double)(cfg.n - r) : 0.0;
-  const double dmax = wave_max(fabs(dl_new));
-  const bool light = dmax > 0.0 && fabs(dl_new) <= 0.25 * cfg.inner_tol * dmax;
-  const bool pair_ok = lane >= r || light || (rh <= thr && (!exact || xr <= xthr));
-  // Certificate L_t = log(n-r) - log eps_t + mu_{r+1} - LSE(mu_1..mu_{r+1}).
-  // The Ritz values are lower bounds of the eigenvalues (interlacing) and
-  // dL/dmu_{r+1} = 1 - softmax_{r+1} lies in [0, 1] (dL/dmu_i <= 0, i <= r),
-  // so L from the Ritz values is a lower bound of the exact L.  A Ritz value
-  // is within its residual of SOME eigenvalue; inside a cluster that need not
-  // be lambda_{r+1}.  The (r+1)-th pair counts as resolved when its residual
-  // bound rho (the estimate, not below its floor, or the explicit residual of
-  // the previous sweep's pair) meets the tolerance and is at most a quarter
-  // of the gap to theta_{r+2}: the Ritz value is then isolated, and L + rho
-  // bounds the exact L from above.  Only then is a certificate claimed.
-  const double margin = fmin(fmax(rr1, floor_est), exact ? xr1 : __builtin_inf());
-  const double sep = (r + 2 <= KB) ? lane_f64(th, r) - lane_f64(th, r + 1 < KB ? r + 1 : r) : 0.0;
-  const double cthr = cfg.cert_tol > 0.0 ? fmax(cfg.cert_tol, exact ? 64.0 * cfg.unit_round * scale : floor_est)
-                                         : (exact ? xthr : thr);
-  const bool resolved = margin <= cthr && margin <= 0.25 * sep;
-  // The pair is iterated further, until resolved or max_inner, always for
-  // cert_tol > 0, and for a stopping rule (meg_solve's or a server's tol)
-  // while its lower bound of L could pass: otherwise the step takes no
-  // sweeps for it and claims nothing while it is unresolved.
-  bool pending = false;
-  if (sc.solve_tol > 0.0) {  // only a stopping rule may ask for more sweeps here
-    const double mu1 = (lane <= r) ? th + log(sc.alpha) - sc.sigma : -__builtin_inf();
-    const double m1 = wave_max(mu1);
-    const double lse1 = m1 + log(wave_sum((lane <= r) ? exp(mu1 - m1) : 0.0));
-    const double L_lo = log((double)(cfg.n - r)) - log(eps_t) + lane_f64(mu1, r) - lse1;
-    const double cut = fmax(2.0 * eps_t, sc.solve_tol);
-    pending = !(L_lo > cut) && !(cert_upper(cfg, theta, sc, eps_t, sc.mu_up) <= cut);
-  }
-  const bool cert_ok = resolved || !(cfg.cert_tol > 0.0 || pending);
-  const bool top_ok = wave_min(pair_ok ? 1.0 : 0.0) > 0.5;
-  bool conv = top_ok && cert_ok;
-  bool do_polish = false;
-  // tolerance below the resolvable floor without explicit residuals (FP32
-  // state): two more sweeps once it is reached
-  if (conv && !cfg.xres && tol_abs < floor_est && polish < 2) {
-    do_polish = true;
-    conv = false;
-  }
-  wsync();
-  if (prof) ts[kTsRR + 2] = wall_clock64();
-  const bool fin = !finite || (conv && sweep >= cfg.min_inner) || sweep >= cfg.max_inner;
-  if (!finite) {
-    if (lane == 0) {
+  __syncthreads();  // eps_t from wavefront 1
+  const double eps_t = xch[0];
+  if (wave == 0) {
+    // A top-r pair enters X_{t+1} = alpha' I + V diag(d') V^T only through
+    // d'_l v_l v_l^T: even an entirely wrong v_l moves X by at most
+    // sqrt(2) |d'_l|, i.e. sqrt(2) w_l of ||X||_F with w_l = |d'_l| / max |d'|.
+    // Pairs with w_l <= inner_tol / 4 therefore need no residual test (in the
+    // noise bulk of M_t such pairs converge slowly and carry no weight).
+    // d' follows from the Ritz values exactly as finish_step forms it.
+    const double mu = (lane < r) ? th + log(sc.alpha) - sc.sigma : -__builtin_inf();
+    const double mmax = wave_max(mu);
+    const double ex = (lane < r) ? exp(mu - mmax) : 0.0;
+    const double esum = wave_sum(ex);
+    const double dl_new = (lane < r) ? (1.0 - eps_t) * ex / esum - eps_t / (double)(cfg.n - r) : 0.0;
+    const double dmax = wave_max(fabs(dl_new));
+    light = dmax > 0.0 && fabs(dl_new) <= 0.25 * cfg.inner_tol * dmax;
+    const bool pair_ok = lane >= r || light || (rh <= thr && (!exact || xr <= xthr));
+    // Certificate L_t = log(n-r) - log eps_t + mu_{r+1} - LSE(mu_1..mu_{r+1}).
+    // The Ritz values are lower bounds of the eigenvalues (interlacing) and
+    // dL/dmu_{r+1} = 1 - softmax_{r+1} lies in [0, 1] (dL/dmu_i <= 0, i <= r),
+    // so L from the Ritz values is a lower bound of the exact L.  A Ritz value
+    // is within its residual of SOME eigenvalue; inside a cluster that need not
+    // be lambda_{r+1}.  The (r+1)-th pair counts as resolved when its residual
+    // bound rho (the estimate, not below its floor, or the explicit residual of
+    // the previous sweep's pair) meets the tolerance and is at most a quarter
+    // of the gap to theta_{r+2}: the Ritz value is then isolated, and L + rho
+    // bounds the exact L from above.  Only then is a certificate claimed.
+    margin = fmin(fmax(rr1, floor_est), exact ? xr1 : __builtin_inf());
+    const double sep = (r + 2 <= KB) ? lane_f64(th, r) - lane_f64(th, r + 1 < KB ? r + 1 : r) : 0.0;
+    const double cthr = cfg.cert_tol > 0.0 ? fmax(cfg.cert_tol, exact ? 64.0 * cfg.unit_round * scale : floor_est)
+                                           : (exact ? xthr : thr);
+    resolved = margin <= cthr && margin <= 0.25 * sep;
+    // The pair is iterated further, until resolved or max_inner, always for
+    // cert_tol > 0, and for a stopping rule (meg_solve's or a server's tol)
+    // while its lower bound of L could pass: otherwise the step takes no
+    // sweeps for it and claims nothing while it is unresolved.
+    bool pending = false;
+    if (sc.solve_tol > 0.0) {  // only a stopping rule may ask for more sweeps here
+      const double mu1 = (lane <= r) ? th + log(sc.alpha) - sc.sigma : -__builtin_inf();
+      const double m1 = wave_max(mu1);
+      const double lse1 = m1 + log(wave_sum((lane <= r) ? exp(mu1 - m1) : 0.0));
+      const double L_lo = log((double)(cfg.n - r)) - log(eps_t) + lane_f64(mu1, r) - lse1;
+      const double cut = fmax(2.0 * eps_t, sc.solve_tol);
+      pending = !(L_lo > cut) && !(cert_upper(cfg, theta, sc, eps_t, sc.mu_up) <= cut);
+    }
+    cert_ok = resolved || !(cfg.cert_tol > 0.0 || pending);
+    top_ok = wave_min(pair_ok ? 1.0 : 0.0) > 0.5;
+    bool conv = top_ok && cert_ok;
+    // tolerance below the resolvable floor without explicit residuals (FP32
+    // state): two more sweeps once it is reached
+    if (conv && !cfg.xres && tol_abs < floor_est && polish < 2) {
+      do_polish = true;
+      conv = false;
+    }
+    wsync();
+    if (prof) ts[kTsRR + 2] = wall_clock64();
+    fin = !finite || (conv && sweep >= cfg.min_inner) || sweep >= cfg.max_inner;
+    if (!finite && lane == 0) {
       ctl->status = 4;  // MEG_ERR_NUMERIC
       ctl->stop = 1;
       ctl->done = 1;
       ctl->applies_done = sc.applies + 1;
     }
-    return false;
-  }
-  // Extrapolated end (FP32 forms): when every top pair's residual, times the
-  // power step's contraction theta_k / theta_i (at most 0.05: a gap the
-  // prediction is reliable across) and a safety factor 2, meets the
-  // tolerance, the block Zout S after one more power step is accepted
-  // without a further sweep to test it; the Ritz values of this sweep are
-  // kept (their error is second order in the residuals).
-  bool extrap = false;
-  if (!fin && cfg.extrap && !exact && cert_ok && sweep >= cfg.min_inner) {
-    // contraction of the power step just taken: the unwanted spectrum,
-    // taken to lie in [0, theta_k], maps to at most max(|fb|, |fa theta_k + fb|)
-    const double thk = fmax(fabs(fb), fabs(fa * lane_f64(th, KB - 1) + fb));
-    const double ratio = (lane < r) ? thk / fmax(fabs(fth), 1e-300) : 0.0;
-    const bool ok = lane >= r || light || (ratio <= 0.05 && 2.0 * ratio * rh <= thr);
-    extrap = wave_min(ok ? 1.0 : 0.0) > 0.5;
-  }
-  if (fin || extrap) {
-    const double a_old = sc.alpha;
-    const double d_old = sc.dl;
-    double d_new, c_new, a_new;
-    finish_step(cfg, ctl, theta, rho, rmax, sweep,
-                (extrap || (top_ok && (resolved || !(cfg.cert_tol > 0.0)))) ? 1 : 0, resolved ? 1 : 0, margin,
-                eps_t, sc, lane, d_new, c_new, a_new);
-    // The next warm start (B, Wb) and C = V_t^T V_{t+1} (first r x r) for
-    // ||X_{t+1} - X_t||_F:
-    //  - ended here: the Ritz vectors of span(Q), Q S = Zin (W S); C = PW S;
-    //  - extrapolated: Zout S R^{-1} (Cholesky QR, S^T G S = R^T R), whose first
-    //    r columns span the power step of the top pairs; C = P S R^{-1}.
-    // The next step's first sweep uses W = Wb and PW = V^T Q = [I_r 0].
-    lds<double>* Cm = B3;
-    if (extrap) {
-      chol_inv<KB>(B3, B2, lane);  // B2 = R^{-1}
-      mm_nn<KB>(B1, B2, A, lane);  // A = S R^{-1}
-#pragma unroll
-      for (int m = 0; m < PE; ++m) {
-        const int e = lane + 64 * m;
-        if (e < KB * KB) S[(e / KB) * LD + (e % KB)] = pnew[m];
+    // Extrapolated end (FP32 forms): when every top pair's residual, times the
+    // power step's contraction theta_k / theta_i (at most 0.05: a gap the
+    // prediction is reliable across) and a safety factor 2, meets the
+    // tolerance, the block Zout S after one more power step is accepted
+    // without a further sweep to test it; the Ritz values of this sweep are
+    // kept (their error is second order in the residuals).
+    if (!fin && cfg.extrap && !exact && cert_ok && sweep >= cfg.min_inner) {
+      // contraction of the power step just taken: the unwanted spectrum,
+      // taken to lie in [0, theta_k], maps to at most max(|fb|, |fa theta_k + fb|)
+      const double thk = fmax(fabs(fb), fabs(fa * lane_f64(th, KB - 1) + fb));
+      const double ratio = (lane < r) ? thk / fmax(fabs(fth), 1e-300) : 0.0;
+      const bool ok = lane >= r || light || (ratio <= 0.05 && 2.0 * ratio * rh <= thr);
+      extrap = wave_min(ok ? 1.0 : 0.0) > 0.5;
+    }
+    const int code = !finite ? 4 : (fin ? 1 : (extrap ? 2 : 0));
+    if (lane == 0) {
+      xch[1] = code;
+      xch[2] = rmax;
+      xch[3] = (extrap || (top_ok && (resolved || !(cfg.cert_tol > 0.0)))) ? 1.0 : 0.0;  // converged
+      xch[4] = resolved ? 1.0 : 0.0;
+      xch[5] = margin;
+      if (grad) {
+        ctl->f = sc.f;
+        ctl->fvalid = 1;
+        ctl->pxnorm = sc.pxnorm;
+        ctl->pxvalid = 1;
       }
-    } else {
-#pragma unroll
+    }
+  }
+  __syncthreads();  // the decision
+  const int code = (int)xch[1];
+  if (code == 4) return false;
+  if (code != 0) {
+    // the step ends here: wavefront 1 exponentiates and normalises and
+    // forms the certificate, wavefront 0 the next basis
+    if (wave == 1) {
+      double d_new, c_new, a_new;
+      finish_step(cfg, ctl, theta, rho, xch[2], sweep, (int)xch[3], (int)xch[4], xch[5], eps_t, sc, lane, d_new,
+                  c_new, a_new);
+      if (lane < KB) {
+        xch[8 + lane] = d_new;
+        xch[8 + KB + lane] = c_new;
+      }
+      if (lane == 0) xch[8 + 2 * KB] = a_new;
+    }
+    lds<double>* Cm = B3;
+    if (wave == 0) {
+      extrap = code == 2;
+      // The next warm start (B, Wb) and C = V_t^T V_{t+1} (first r x r) for
+      // ||X_{t+1} - X_t||_F:
+      //  - ended here: the Ritz vectors of span(Q), Q S = Zin (W S); C = PW S;
+      //  - extrapolated: Zout S R^{-1} (Cholesky QR, S^T G S = R^T R), whose first
+      //    r columns span the power step of the top pairs; C = P S R^{-1}.
+      // The next step's first sweep uses W = Wb and PW = V^T Q = [I_r 0].
+      lds<double>* Wn;  // the next W = Wb
+      if (extrap) {
+  #pragma unroll
+        for (int m = 0; m < PE; ++m) {
+          const int e = lane + 64 * m;
+          if (e < KB * KB) S[(e / KB) * LD + (e % KB)] = pnew[m];
+        }
+        wsync();
+        mm_nn<KB>(S, B1, B2, lane);  // B2 = P S
+        wsync();
+        chol_apply2<KB>(B3, B1, A, rdiag, lane);  // B1 = S R^{-1}, B2 = P S R^{-1}
+        Wn = B1;
+        Cm = B2;
+      } else {
+  #pragma unroll
+        for (int u = 0; u < WE; ++u) {
+          const int e = lane + 64 * u;
+          B2[(e / KB) * LD + (e % KB)] = wreg[u];
+        }
+  #pragma unroll
+        for (int m = 0; m < PE; ++m) {
+          const int e = lane + 64 * m;
+          if (e < KB * KB) S[(e / KB) * LD + (e % KB)] = pold[m];
+        }
+        wsync();
+        mm_nn<KB>(B2, B1, A, lane);  // A = W S
+        mm_nn<KB>(S, B1, B3, lane);  // PW S
+        wsync();
+        Wn = A;
+        Cm = B3;
+      }
+      store_mat<KB>(Wn, ctl->Wb, lane);
+      store_mat<KB>(Wn, ctl->W, lane);
+      for (int e = lane; e < KB * KB; e += 64) ctl->PW[e] = (e / KB == e % KB && e / KB < r) ? 1.0 : 0.0;
+    }
+    __syncthreads();  // the new iterate from wavefront 1
+    if (wave == 0) {
+      const double a_old = sc.alpha;
+      const double d_old = sc.dl;
+      const double d_new = (lane < KB) ? xch[8 + lane] : 0.0;
+      const double c_new = (lane < KB) ? xch[8 + KB + lane] : 0.0;
+      const double a_new = xch[8 + 2 * KB];
+      // ||X_{t+1} - X_t||_F from the factored forms (V orthonormal):
+      //   n da^2 + 2 da (sum d_t - sum d_{t+1}) + |d_t|^2 + |d_{t+1}|^2
+      //   - 2 sum_ab d_t,a d_{t+1},b C_ab^2
+      lds<double>* dd = vec + 2 * KB;  // the Jacobi rotations' area: d_t, then d_{t+1}
+      if (lane < KB) {
+        dd[lane] = d_old;
+        dd[KB + lane] = d_new;
+      }
+      wsync();
+      double cross = 0.0;
+      for (int e = lane; e < r * r; e += 64) {
+        const int a = e / r, b = e % r;
+        const double c = Cm[a * LD + b];
+        cross += dd[a] * dd[KB + b] * c * c;
+      }
+      cross = wave_sum(cross);
+      const double sd = wave_sum(d_old - d_new);
+      const double s2 = wave_sum(d_old * d_old + d_new * d_new);
+      const double da = a_old - a_new;
+      const double dx2 = (double)cfg.n * da * da + 2.0 * da * sd + s2 - 2.0 * cross;
+      const double dxnorm = sqrt(fmax(dx2, 0.0));
+      // step t + 1 begins: its counters, then its shift and coefficients from
+      // the values in registers
+      if (lane == 0) {
+        ctl->dxnorm = dxnorm;
+        ctl->src = extrap ? out_buf : in_buf;
+        ctl->t = sc.t + 1;
+        ctl->iters_done = sc.iters + 1;
+        ctl->applies_done = sc.applies + 1;
+        ctl->fvalid = 0;
+        ctl->done = 0;
+        ctl->sweep = 1;
+        ctl->polish = 0;
+        ctl->xvalid = 0;
+        ctl->extrap_done = sc.extrap_n + (extrap ? 1 : 0);
+        ctl->unconv_done = sc.unconv_n + ((extrap || top_ok) ? 0 : 1);
+      }
+      const double la = log(sc.alpha);
+      const double mu_1 = theta[0] + la - sc.sigma, mu_k = theta[KB - 1] + la - sc.sigma;
+      if (lane == 0) {
+        ctl->mu_1 = mu_1;
+        ctl->mu_k = mu_k;
+        ctl->mu_valid = 1;
+      }
+      if (cfg.kind != QUADMEAS) {  // the minibatch bound is set inside the next step's first sweep
+        const double gmax =
+            grad_bound(cfg, a_new, d_new, sc.op_lmin, sc.op_lmax, sc.pxvalid, sc.pxnorm, dxnorm, lane);
+        setup_step_v(cfg, ctl, gmax, a_new, d_new, c_new, mu_1, mu_k, 1, lane);
+      }
+      if (prof) ts[kTsRR + 3] = wall_clock64();
+    }
+    return true;
+  }
+  if (wave == 0) {
+    if (cfg.xres) {
+      // for the next sweep's explicit residuals: S and W S Theta
+  #pragma unroll
       for (int u = 0; u < WE; ++u) {
         const int e = lane + 64 * u;
         B2[(e / KB) * LD + (e % KB)] = wreg[u];
       }
       wsync();
-      mm_nn<KB>(B2, B1, A, lane);  // A = W S
+      mm_nn<KB>(B2, B1, A, lane);
       wsync();
-#pragma unroll
-      for (int m = 0; m < PE; ++m) {
-        const int e = lane + 64 * m;
-        if (e < KB * KB) S[(e / KB) * LD + (e % KB)] = pold[m];
+      for (int e = lane; e < KB * KB; e += 64) {
+        const int i = e / KB, j = e % KB;
+        ctl->XS[e] = B1[i * LD + j];
+        ctl->XWT[e] = A[i * LD + j] * (fa * theta[j] + fb);
       }
+      if (lane == 0) {
+        ctl->xvalid = 1;
+        ctl->xscale = 1.0 / fabs(fa);
+      }
+      wsync();
+    }
+    // Next basis Q' = Zout S R^{-1} with Ghat = R^T R (Cholesky QR, FP64) and
+    // PW' = V^T Q' = P S R^{-1}
+  #pragma unroll
+    for (int m = 0; m < PE; ++m) {
+      const int e = lane + 64 * m;
+      if (e < KB * KB) S[(e / KB) * LD + (e % KB)] = pnew[m];
     }
     wsync();
-    mm_nn<KB>(S, extrap ? A : B1, Cm, lane);
+    mm_nn<KB>(S, B1, B2, lane);  // B2 = P S
     wsync();
-    store_mat<KB>(A, ctl->Wb, lane);
-    store_mat<KB>(A, ctl->W, lane);
-    for (int e = lane; e < KB * KB; e += 64) ctl->PW[e] = (e / KB == e % KB && e / KB < r) ? 1.0 : 0.0;
-    // ||X_{t+1} - X_t||_F from the factored forms (V orthonormal):
-    //   n da^2 + 2 da (sum d_t - sum d_{t+1}) + |d_t|^2 + |d_{t+1}|^2
-    //   - 2 sum_ab d_t,a d_{t+1},b C_ab^2
-    lds<double>* dd = vec + 2 * KB;  // the Jacobi rotations' area: d_t, then d_{t+1}
-    if (lane < KB) {
-      dd[lane] = d_old;
-      dd[KB + lane] = d_new;
-    }
-    wsync();
-    double cross = 0.0;
-    for (int e = lane; e < r * r; e += 64) {
-      const int a = e / r, b = e % r;
-      const double c = Cm[a * LD + b];
-      cross += dd[a] * dd[KB + b] * c * c;
-    }
-    cross = wave_sum(cross);
-    const double sd = wave_sum(d_old - d_new);
-    const double s2 = wave_sum(d_old * d_old + d_new * d_new);
-    const double da = a_old - a_new;
-    const double dx2 = (double)cfg.n * da * da + 2.0 * da * sd + s2 - 2.0 * cross;
-    const double dxnorm = sqrt(fmax(dx2, 0.0));
-    // step t + 1 begins: its counters, then its shift and coefficients from
-    // the values in registers
+    chol_apply2<KB>(B3, B1, A, rdiag, lane);  // B1 = W' = S R^{-1}, B2 = PW' = P S R^{-1}
+    store_mat<KB>(B1, ctl->W, lane);
+    store_mat<KB>(B2, ctl->PW, lane);
     if (lane == 0) {
-      ctl->dxnorm = dxnorm;
-      ctl->src = extrap ? out_buf : in_buf;
-      ctl->t = sc.t + 1;
-      ctl->iters_done = sc.iters + 1;
+      ctl->sweep = sweep + 1;
       ctl->applies_done = sc.applies + 1;
-      ctl->fvalid = 0;
-      ctl->done = 0;
-      ctl->sweep = 1;
-      ctl->polish = 0;
-      ctl->xvalid = 0;
-      ctl->extrap_done = ctl->extrap_done + (extrap ? 1 : 0);
-      ctl->unconv_done = ctl->unconv_done + ((extrap || top_ok) ? 0 : 1);
-      const double la = log(sc.alpha);
-      ctl->mu_1 = theta[0] + la - sc.sigma;
-      ctl->mu_k = theta[KB - 1] + la - sc.sigma;
-      ctl->mu_valid = 1;
-    }
-    if (cfg.kind != QUADMEAS) {  // the minibatch bound is set inside the next step's first sweep
-      const double gmax =
-          grad_bound(cfg, a_new, d_new, sc.op_lmin, sc.op_lmax, sc.pxvalid, sc.pxnorm, dxnorm, lane);
-      setup_step_v(cfg, ctl, gmax, a_new, d_new, c_new, lane);
+      if (do_polish) ctl->polish = polish + 1;
+      // the next sweep's Chebyshev interval: [0, theta_k] of this one
+      const double b = theta[KB - 1];
+      ctl->cheb_b = (cfg.cheb && b > 1e-3 * theta[0] && b < 0.5 * theta[0]) ? b : 0.0;
     }
     if (prof) ts[kTsRR + 3] = wall_clock64();
-    return true;
   }
-  if (cfg.xres) {
-    // for the next sweep's explicit residuals: S and W S Theta
-#pragma unroll
-    for (int u = 0; u < WE; ++u) {
-      const int e = lane + 64 * u;
-      B2[(e / KB) * LD + (e % KB)] = wreg[u];
-    }
-    wsync();
-    mm_nn<KB>(B2, B1, A, lane);
-    wsync();
-    for (int e = lane; e < KB * KB; e += 64) {
-      const int i = e / KB, j = e % KB;
-      ctl->XS[e] = B1[i * LD + j];
-      ctl->XWT[e] = A[i * LD + j] * (fa * theta[j] + fb);
-    }
-    if (lane == 0) {
-      ctl->xvalid = 1;
-      ctl->xscale = 1.0 / fabs(fa);
-    }
-    wsync();
-  }
-  // Next basis Q' = Zout S R^{-1} with Ghat = R^T R (Cholesky QR, FP64) and
-  // PW' = V^T Q' = P S R^{-1}
-  chol_inv<KB>(B3, B2, lane);
-  mm_nn<KB>(B1, B2, A, lane);  // W' = S R^{-1}
-#pragma unroll
-  for (int m = 0; m < PE; ++m) {
-    const int e = lane + 64 * m;
-    if (e < KB * KB) S[(e / KB) * LD + (e % KB)] = pnew[m];
-  }
-  wsync();
-  mm_nn<KB>(S, A, B3, lane);
-  wsync();
-  store_mat<KB>(A, ctl->W, lane);
-  store_mat<KB>(B3, ctl->PW, lane);
-  if (lane == 0) {
-    ctl->sweep = sweep + 1;
-    ctl->applies_done = sc.applies + 1;
-    if (do_polish) ctl->polish = polish + 1;
-    // the next sweep's Chebyshev interval: [0, theta_k] of this one
-    const double b = theta[KB - 1];
-    ctl->cheb_b = (cfg.cheb && b > 1e-3 * theta[0] && b < 0.5 * theta[0]) ? b : 0.0;
-  }
-  if (prof) ts[kTsRR + 3] = wall_clock64();
   return false;
 }
 
@@ -923,11 +1085,16 @@ template <int KB>
 __device__ __noinline__ void basis_setup(const Cfg& cfg, gbl<Ctl>* ctl, const gbl<double>* gram, lds<double>* scr,
                                          int lane) {
   constexpr int MS = KB * (KB + 1);
+  constexpr int LD = KB + 1;
   lds<double>* A = scr;
   lds<double>* Rinv = scr + MS;
+  lds<double>* R = scr + 2 * MS;
+  lds<double>* rdiag = scr + 3 * MS;
   load_mat<KB>(gram, A, lane);
+  for (int e = lane; e < KB * KB; e += 64) Rinv[(e / KB) * LD + (e % KB)] = (e / KB == e % KB) ? 1.0 : 0.0;
   wsync();
-  chol_inv<KB>(A, Rinv, lane);
+  chol_factor<KB>(A, R, rdiag, lane);
+  rsolve<KB>(Rinv, Rinv, R, rdiag, KB, lane);
   store_mat<KB>(Rinv, ctl->W, lane);
   store_mat<KB>(Rinv, ctl->Wb, lane);
   for (int e = lane; e < KB * KB; e += 64) ctl->PW[e] = (e / KB == e % KB && e / KB < cfg.r) ? 1.0 : 0.0;
