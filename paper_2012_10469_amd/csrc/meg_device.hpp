@@ -12,6 +12,7 @@
 // Rows are 64 B (k = 16, float) or 128 B apart, so a row is read by one
 // aligned vector load per lane group and Gram partials stay row-local.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -348,20 +349,34 @@ __device__ __forceinline__ Team grid_team() {
 // arriver of each group adds its group's partials (in workgroup order) into
 // gpart, the last group adds the group sums (in group order).  The order is
 // fixed, so the sums are bitwise reproducible.  All threads call it.
+// A serial part that returns an int passes it, a tag in [0, 4), to every
+// workgroup of the team through the generation word itself (the last
+// arrival advances it by 1 + 4 tag), so no workgroup reads it back from
+// memory: *tag receives it (0 for a serial part that returns nothing).
 template <int NT, typename F>
-__device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& serial) {
+__device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& serial, int* tag = nullptr) {
   __shared__ int s_role;  // 0: plain arrival, 1: last of its group, 2: last overall
   __shared__ unsigned s_gen;
   __shared__ int s_ok;
+  __shared__ int s_tag;
   const int tid = threadIdx.x;
+  auto run_serial = [&]() -> int {
+    if constexpr (std::is_void<decltype(serial())>::value) {
+      serial();
+      return 0;
+    } else {
+      return serial();
+    }
+  };
   if (tm.nwg == 1) {  // a team of one workgroup: its partials are the sums
     __syncthreads();
     if (plen > 0 && b.sums != b.part) {
       for (int e = tid; e < plen; e += NT) b.sums[e] = b.part[e];
       __syncthreads();
     }
-    serial();
+    const int tg = run_serial();
     __syncthreads();
+    if (tag) *tag = tg;
     return true;
   }
   const unsigned P = (unsigned)tm.nwg;
@@ -408,15 +423,16 @@ __device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& 
       reduce_top<NT>((const gbl<double>*)b.gpart, (gbl<double>*)b.sums, plen, ng);
       __syncthreads();
     }
-    serial();
+    const int tg = run_serial();  // uniform over the workgroup
     __syncthreads();
     if (threadIdx.x == 0) {
+      s_tag = tg;
       __hip_atomic_store(&b.bar[kBarTop], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&b.bar[kBarGen], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&b.bar[kBarGen], 1u + 4u * (unsigned)tg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
   } else if (tid == 0) {
-    unsigned spins = 0;
-    while (__hip_atomic_load(&b.bar[kBarGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == s_gen) {
+    unsigned spins = 0, gen;
+    while ((gen = __hip_atomic_load(&b.bar[kBarGen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == s_gen) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > kSpinLimit || __hip_atomic_load(&b.bar[kBarErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         __hip_atomic_fetch_or(&b.bar[kBarErr], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -424,9 +440,11 @@ __device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& 
         break;
       }
     }
+    s_tag = (int)(((gen - s_gen) - 1u) >> 2);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
+  if (tag) *tag = s_tag;
   return s_ok != 0;
 }
 

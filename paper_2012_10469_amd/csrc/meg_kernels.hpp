@@ -1237,16 +1237,19 @@ __device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl,
     load_csr_cache<T, SH::ROWS, NT>(cfg, dat, cc, tm);
   }
   for (int st = 0; st < nsteps; ++st) {
-    if (ldi(&ctl->stop) | ldi(&ctl->status)) break;
-    if (deadline != 0 && ldi64(&ctl->pause_seq) == seq) break;
+    // the control words read together (one round trip): the step scalars
+    // (shift, coefficients) and the basis (B, Wb) were set at the end of the
+    // previous iteration
+    const int stop = ldi(&ctl->stop), status = ldi(&ctl->status);
+    const int64_t t0 = ldi64(&ctl->t);
+    const int src = ldi(&ctl->src);
+    const int64_t pause = deadline != 0 ? ldi64(&ctl->pause_seq) : seq - 1;
+    if (stop | status) break;
+    if (pause == seq) break;
     if (tm.wg == 0) {
       stamp(b, 0);
       stamp(b, 1);  // no separate gradient phase: it is part of sweep 1
     }
-    // the step scalars (shift, coefficients) and the basis (B, Wb) were set
-    // at the end of the previous iteration
-    const int64_t t0 = ldi64(&ctl->t);
-    const int src = ldi(&ctl->src);
     const int o1 = (src + 1) % 3, o2 = (src + 2) % 3;
     const T* Bm = zbuf(Z0, Z1, Z2, src);
     const T* gvals = masked ? g : dat.val;
@@ -1298,21 +1301,26 @@ __device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl,
                                                   (lds<char>*)xstage, tm);
       }
       stamp_wg(b, tm, s, 1);
-      if (!grid_sync<NT>(b, tm, PartRec<KB>::len(cfg.r, SM::XR != 0), [&] {
-            stamp(b, 2 * s);
-            gbl<Ctl>* gc = (gbl<Ctl>*)ctl;
-            // every thread calls it (it runs on two wavefronts); the step
-            // ends here when it returns true: X_{t+1}, t + 1 and the scalars
-            // of step t + 1 are set
-            const bool fin = small_sweep<KB>(cfg, gc, (const gbl<double>*)b.sums, (lds<double>*)smem, s, in, out,
-                                             grad, tid, (gbl<long long>*)b.ts);
-            if (fin && deadline != 0 && tid == 0 && (long long)wall_clock64() >= deadline) gc->pause_seq = seq;
-            stamp(b, 2 * s + 1);
-          }))
+      int ended = 0;
+      if (!grid_sync<NT>(
+              b, tm, PartRec<KB>::len(cfg.r, SM::XR != 0),
+              [&]() -> int {
+                stamp(b, 2 * s);
+                gbl<Ctl>* gc = (gbl<Ctl>*)ctl;
+                // every thread calls it (it runs on two wavefronts); the step
+                // ends here when it returns 1 (X_{t+1}, t + 1 and the scalars
+                // of step t + 1 are set), fails when it returns 2
+                const int res = small_sweep<KB>(cfg, gc, (const gbl<double>*)b.sums, (lds<double>*)smem, s, in, out,
+                                                grad, tid, (gbl<long long>*)b.ts);
+                if (res == 1 && deadline != 0 && tid == 0 && (long long)wall_clock64() >= deadline)
+                  gc->pause_seq = seq;
+                stamp(b, 2 * s + 1);
+                return res;
+              },
+              &ended))
         return;
-      if ((ldi64(&ctl->t) != t0) | ldi(&ctl->status)) break;
+      if (ended) break;  // the next step (or, after a failure, the loop's first check) reads ctl
     }
-    if (ldi(&ctl->status)) break;
   }
 }
 

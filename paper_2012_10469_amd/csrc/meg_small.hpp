@@ -140,6 +140,28 @@ __device__ __forceinline__ void jacobi_rot(double app, double aqq, double apq, d
   s = t * c;
 }
 
+// The same rotation with its angle from FP32 arithmetic (hardware square
+// root and reciprocal, no refinement): t carries a relative error of ~1e-7,
+// which leaves |A_pq| ~ 1e-7 |A_pq| after the rotation (the next sweep
+// removes it; an FP32 state's tolerance is 1e-8 relative), while c and s
+// are formed from that t in FP64, so c^2 + s^2 = 1 to FP64 rounding and S
+// stays orthogonal to FP64 accuracy.  The pair's entries are far inside the
+// FP32 range here (eigenvalues of the shifted step operator).
+__device__ __forceinline__ void jacobi_rot_f32angle(double app, double aqq, double apq, double& c, double& s) {
+  const bool act = apq * apq > 1e-36 * fabs(app * aqq) && fabs(apq) > 1e-300;
+  const float bf = act ? (float)apq : 0.0f;
+  const float df = (float)(aqq - app);
+  const float rf = __builtin_amdgcn_sqrtf(fmaf(df, df, 4.0f * bf * bf));
+  const float den = fmaxf(fabsf(df) + rf, 1e-37f);
+  const double t = (double)(2.0f * (df >= 0.0f ? bf : -bf) * __builtin_amdgcn_rcpf(den));
+  c = rsqrt_nr(1.0 + t * t);
+  s = t * c;
+}
+template <bool F32ANGLE>
+__device__ __forceinline__ void jacobi_rot_sel(double app, double aqq, double apq, double& c, double& s) {
+  if constexpr (F32ANGLE) jacobi_rot_f32angle(app, aqq, apq, c, s); else jacobi_rot(app, aqq, apq, c, s);
+}
+
 // Circle-method ordering: slot j sits at position j in round 0; slot 0 stays
 // at 0, the others move up by one position per round, wrapping from KB - 1 to
 // 1.  Rotation m pairs the positions of slots m and KB - 1 - m.
@@ -153,7 +175,7 @@ __device__ __forceinline__ int jacobi_next(int pos) { return pos == 0 ? 0 : (pos
 // m2 = l % (KB/2) and m1 = l / (KB/2) + (64 / (KB/2)) b, so it reads rotation
 // m2 once per round.  Blocks are disjoint, so all of a lane's reads precede
 // its writes.
-template <int KB>
+template <int KB, bool F32ANGLE>
 __device__ __noinline__ int jacobi_shared_rot(lds<double>* A, lds<double>* S, double off2_tol, int lane,
                                               lds<double>* rot) {
   constexpr int LD = KB + 1;
@@ -178,7 +200,7 @@ __device__ __noinline__ int jacobi_shared_rot(lds<double>* A, lds<double>* S, do
       if (lane < NP) {
         const int p = min(am, bm), q = max(am, bm);
         double c, s;
-        jacobi_rot(A[p * LD + p], A[q * LD + q], A[p * LD + q], c, s);
+        jacobi_rot_sel<F32ANGLE>(A[p * LD + p], A[q * LD + q], A[p * LD + q], c, s);
         rot[2 * lane] = c;
         rot[2 * lane + 1] = s;
         rot[KB + 2 * lane] = p;  // indices kept beside the rotation (exact in FP64)
@@ -243,13 +265,13 @@ __device__ __noinline__ int jacobi_shared_rot(lds<double>* A, lds<double>* S, do
 // diagonal block (the same inputs and operations in every lane, so every lane
 // derives the same rotation), so a round needs no cross-lane exchange.  All
 // loads of a round precede its stores.
-template <int KB>
+template <int KB, bool F32ANGLE>
 __device__ __noinline__ int jacobi(lds<double>* A, lds<double>* S, double off2_tol, int lane, lds<double>* rot) {
   constexpr int LD = KB + 1;
   constexpr int NP = KB / 2;
   static_assert((NP * NP) % 64 == 0, "2 x 2 blocks must fill the wavefront");
   constexpr int BPL = NP * NP / 64;  // 2 x 2 blocks per lane
-  if constexpr (BPL > 1) return jacobi_shared_rot<KB>(A, S, off2_tol, lane, rot);
+  if constexpr (BPL > 1) return jacobi_shared_rot<KB, F32ANGLE>(A, S, off2_tol, lane, rot);
   for (int e = lane; e < KB * KB; e += 64) S[(e / KB) * LD + (e % KB)] = (e / KB == e % KB) ? 1.0 : 0.0;
   wsync();
   int sweep = 0;
@@ -307,8 +329,8 @@ __device__ __noinline__ int jacobi(lds<double>* A, lds<double>* S, double off2_t
       for (int bi = 0; bi < BPL; ++bi) {
         const int m2 = (lane + 64 * bi) % NP;
         double c1, s1, c2, s2;
-        jacobi_rot(r1[bi][0], r1[bi][1], r1[bi][2], c1, s1);
-        jacobi_rot(r2[bi][0], r2[bi][1], r2[bi][2], c2, s2);
+        jacobi_rot_sel<F32ANGLE>(r1[bi][0], r1[bi][1], r1[bi][2], c1, s1);
+        jacobi_rot_sel<F32ANGLE>(r2[bi][0], r2[bi][1], r2[bi][2], c2, s2);
         const double a = blk[bi][0], b = blk[bi][1], cc = blk[bi][2], d = blk[bi][3];
         const double ra = c1 * a - s1 * cc, rb = c1 * b - s1 * d;  // rows: J1^T
         const double rc = s1 * a + c1 * cc, rd = s1 * b + c1 * d;
@@ -623,14 +645,15 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
 // Zin (W S) becomes the next warm start (B, Wb) = (Zin, W S), advances t and
 // sets the next step's shift and coefficients.  Counts the apply (and the
 // Jacobi sweeps) in ctl.  `grad`: this sweep formed the masked gradient (its
-// objective sums are in the record).  Returns true when the step ended.
+// objective sums are in the record).  Returns 1 when the step ended, 2 when
+// it failed (status set), 0 otherwise (uniform over the workgroup).
 // Called by every thread of the workgroup (tid); the work runs on two
 // wavefronts, wave-synchronously within each: wavefront 0 solves, wavefront
 // 1 meanwhile forms eps_t and, when the step ends here, the new iterate and
 // its certificate while wavefront 0 forms the next basis.  `scr` (LDS)
 // needs 5 * KB * (KB + 1) + 12 * KB doubles.
 template <int KB>
-__device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gbl<double>* sums, lds<double>* scr,
+__device__ __noinline__ int small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gbl<double>* sums, lds<double>* scr,
                                          int sweep, int in_buf, int out_buf, bool grad, int tid,
                                          gbl<long long>* ts) {
   constexpr int LD = KB + 1;
@@ -680,7 +703,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
         ctl->xvalid = 0;
       }
     }
-    return false;
+    return 0;
   }
 
   // Rayleigh-Ritz sweep.  Both wavefronts load the step's scalars.
@@ -757,7 +780,9 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     // (below its unit roundoff 6e-8; the eigenvectors then carry errors of
     // off/gap, and the residual test sees at most 1e-8 of the scale), 1e-15
     // for FP64.  The tolerance is on squared norms.
-    jsweeps = jacobi<KB>(A, S, cfg.unit_round < 1e-10 ? 1e-30 : 1e-16, lane, jrot);
+    // (FP32 state: rotation angles from FP32 arithmetic, see jacobi_rot_f32angle)
+    jsweeps = cfg.unit_round < 1e-10 ? jacobi<KB, false>(A, S, 1e-30, lane, jrot)
+                                     : jacobi<KB, true>(A, S, 1e-16, lane, jrot);
     if (lane == 0) ctl->jacobi_done = sc.jacobi + jsweeps;
     if (prof) {
       ts[kTsRR + 1] = wall_clock64();
@@ -912,7 +937,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
   }
   __syncthreads();  // the decision
   const int code = (int)xch[1];
-  if (code == 4) return false;
+  if (code == 4) return 2;
   if (code != 0) {
     // the step ends here: wavefront 1 exponentiates and normalises and
     // forms the certificate, wavefront 0 the next basis
@@ -1028,7 +1053,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
       }
       if (prof) ts[kTsRR + 3] = wall_clock64();
     }
-    return true;
+    return 1;
   }
   if (wave == 0) {
     if (cfg.xres) {
@@ -1075,7 +1100,7 @@ __device__ __noinline__ bool small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gb
     }
     if (prof) ts[kTsRR + 3] = wall_clock64();
   }
-  return false;
+  return 0;
 }
 
 // Orthonormalising transform of a fresh basis B with Gram H = B^T B:
