@@ -536,7 +536,9 @@ __device__ __forceinline__ SolveScalars load_scalars(const Cfg& cfg, const gbl<C
   s.op_lmax = ctl->op_lmax;
   s.dl = (lane < cfg.r) ? ctl->d[lane] : 0.0;
   s.t = ctl->t;
-  s.mu_up = (ctl->mu_up_t == s.t && s.t > 0) ? ctl->mu_up : __builtin_inf();
+  const double mu_up = ctl->mu_up;  // read unconditionally: one round trip with the rest
+  const int64_t mu_up_t = ctl->mu_up_t;
+  s.mu_up = (mu_up_t == s.t && s.t > 0) ? mu_up : __builtin_inf();
   s.cheb_b = ctl->cheb_b;
   s.xscale = ctl->xscale;
   s.iters = ctl->iters_done;
@@ -679,12 +681,22 @@ __device__ __noinline__ int small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gbl
     if (wave == 0) {
       // early sweep of a warm-started step: orthonormalise only,
       // Q' = Zout R^{-1} with Zout^T Zout = R^T R;  PW' = V^T Zout R^{-1}
+      // every global read issued before any is used (one round trip)
       const int64_t applies = ctl->applies_done;
-      const double fs = grad ? sums[fo] : 0.0, px2 = grad ? sums[fo + 1] : 0.0;
-      load_sym<KB>(sums + PR::G_OFF, B3, lane);
-      for (int e = lane; e < KB * KB; e += 64) {
-        const int i = e / KB, j = e % KB;
-        B1[i * LD + j] = (i < r) ? sums[PR::P_OFF + e] : 0.0;  // P (its r rows)
+      const double fs = sums[fo], px2 = sums[fo + 1];
+      constexpr int IT = KB * KB / 64;
+      double gv[IT], pv[IT];
+#pragma unroll
+      for (int u = 0; u < IT; ++u) {
+        const int e = lane + 64 * u, i = e / KB, j = e % KB;
+        gv[u] = sums[PR::G_OFF + (i <= j ? PR::tri(i, j) : PR::tri(j, i))];
+        pv[u] = sums[PR::P_OFF + (i < r ? e : 0)];  // P (its r rows)
+      }
+#pragma unroll
+      for (int u = 0; u < IT; ++u) {
+        const int e = lane + 64 * u, i = e / KB, j = e % KB;
+        B3[i * LD + j] = gv[u];
+        B1[i * LD + j] = (i < r) ? pv[u] : 0.0;
         S[i * LD + j] = (i == j) ? 1.0 : 0.0;
       }
       wsync();
@@ -720,7 +732,7 @@ __device__ __noinline__ int small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gbl
   if (wave == 1 && lane == 0) xch[0] = eps_at(cfg, sc.t);
   // wavefront 0's state across the sections below
   constexpr int WE = KB * KB / 64;
-  constexpr int PE = (KB * KB + 63) / 64;
+  constexpr int PE = KB * KB / 64;
   double wreg[WE], pnew[PE], pold[PE];
   double fa = 1.0, fb = 0.0, th = 0.0, fth = 0.0, rh = 0.0, thr = 0.0, rmax = 0.0, margin = 0.0;
   double floor_est = 0.0, tol_abs = 0.0, scale = 1.0, xr = 0.0, xthr = 0.0, rr1 = 0.0, xr1 = 0.0;
@@ -744,9 +756,10 @@ __device__ __noinline__ int small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gbl
     // second gives V_t^T V_{t+1} = PW S[:, :r] when the step ends here
 #pragma unroll
     for (int m = 0; m < PE; ++m) {
-      const int e = lane + 64 * m;
-      pnew[m] = (e < r * KB) ? sums[PR::P_OFF + e] : 0.0;
-      pold[m] = (e < KB * KB) ? ctl->PW[e] : 0.0;
+      const int e = lane + 64 * m;  // < KB * KB (PE = KB * KB / 64)
+      const double pn = sums[PR::P_OFF + (e < r * KB ? e : 0)];
+      pnew[m] = (e < r * KB) ? pn : 0.0;
+      pold[m] = ctl->PW[e];
     }
 #pragma unroll
     for (int u = 0; u < WE; ++u) {
