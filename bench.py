@@ -53,13 +53,14 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
-# HBM traffic of one 64-iteration launch of the step kernel on the default
-# workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a plain
-# copy's readings (profiles/k_step_matrix_completion_n4096_r10_traffic.md);
-# valid only for the kernel sources it was measured on.
-TRAFFIC = {"bytes_per_launch": 943.0e6, "iterations_per_launch": 64, "applies_per_iteration": 3.0,
-           "fetch_bytes": 546.5e6, "write_bytes": 396.5e6, "fetch_factor": 2.0, "write_factor": 1.0,
-           "source_hash": "ad9dabac6b583560"}
+# HBM traffic of the timed launch of the step kernel on the default workload
+# in the default launch configuration (20 iterations in one launch after 5
+# warmup iterations), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
+# plain copy's readings (profiles/k_step_matrix_completion_n4096_r10_traffic.md);
+# valid only for the kernel sources and the launch it was measured on.
+TRAFFIC = {"bytes_per_launch": 171.8e6, "iterations_per_launch": 20, "warmup": 5, "applies_per_iteration": 2.0,
+           "fetch_bytes": 91.0e6, "write_bytes": 80.8e6, "fetch_factor": 2.0, "write_factor": 1.0,
+           "source_hash": "d8b347206bdef00e"}
 KERNEL_SOURCES = ["meg_device.hpp", "meg_small.hpp", "meg_kernels.hpp", "meg_api.hip"]
 
 
@@ -730,11 +731,15 @@ def main() -> int:
     precision = None if args.no_configs else precision_bench(meg, torch)
     # measured HBM bytes per launch (counter runs), only for the kernel they were taken on
     traffic, traffic_note = None, "kernel sources changed since the counter runs"
-    if kernel_source_hash() == TRAFFIC["source_hash"] and args.launch_steps == TRAFFIC["iterations_per_launch"]:
-        traffic = TRAFFIC["bytes_per_launch"]
-        traffic_note = (f"HBM bytes per {TRAFFIC['iterations_per_launch']}-iteration launch "
-                        f"(FETCH_SIZE x {TRAFFIC['fetch_factor']} + WRITE_SIZE x {TRAFFIC['write_factor']}, "
-                        f"first timed launch, {TRAFFIC['applies_per_iteration']} applies per iteration)")
+    if kernel_source_hash() == TRAFFIC["source_hash"]:
+        traffic_note = "counters were taken on another launch configuration"
+        if (launches == 1 and cnt["iterations"] == TRAFFIC["iterations_per_launch"]
+                and args.warmup == TRAFFIC["warmup"]):
+            traffic = TRAFFIC["bytes_per_launch"]
+            traffic_note = (f"HBM bytes of this launch configuration ({TRAFFIC['iterations_per_launch']} iterations "
+                            f"in one launch after {TRAFFIC['warmup']}; FETCH_SIZE x {TRAFFIC['fetch_factor']} + "
+                            f"WRITE_SIZE x {TRAFFIC['write_factor']}, {TRAFFIC['applies_per_iteration']} applies "
+                            f"per iteration when measured)")
 
     out = {
         "metric": "low-rank MEG iterations/s (matrix completion, n=4096, r=10, FP32)",
