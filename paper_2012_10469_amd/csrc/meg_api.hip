@@ -97,6 +97,16 @@ struct meg_ctx_s {
   int P = 1;               // persistent grid size
   int aux_nwg = 1;         // row-parallel auxiliary kernels
   Ctl* h_ctl = nullptr;    // pinned host mirror
+  // pinned host words: the barrier error flag's copy, the stopping rule's
+  // (tol, stop) and zeros for the asynchronous arm / disarm of meg_solve
+  struct HostWords {
+    unsigned bar_err;
+    int32_t zero_i;
+    double tol;
+    double zero_d;
+    int32_t stop;
+  };
+  HostWords* h_w = nullptr;
   bool external = false;   // the caller supplies G_t every step (meg_step_external)
   bool bilinear = false;   // bilinear measurements: the context forms G_t itself (external step path)
   void* bil_G = nullptr;   // bilinear: dense symmetric gradient n x n (state type, ld n)
@@ -584,6 +594,16 @@ void* block(meg_ctx c, int i) { return i == 0 ? c->Qw : (i == 1 ? c->Za : c->Zb)
 meg_status copy_ctl_to_host(meg_ctx c) {
   HIPCHK(c, hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return MEG_OK;
+}
+
+// The control block and the barrier's error flag copied to the host with
+// one synchronisation; MEG_ERR_DEVICE when a grid barrier did not complete.
+meg_status sync_ctl(meg_ctx c) {
+  HIPCHK(c, hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&c->h_w->bar_err, c->bar + kBarErr, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->h_w->bar_err) return hip_fail(c);
   return MEG_OK;
 }
 
@@ -1316,6 +1336,7 @@ void free_ctx(meg_ctx c) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+  if (c->h_w) (void)hipHostFree(c->h_w);
   for (int i = 0; i < meg_ctx_s::kEvRing; ++i) {
     if (c->ev_a[i]) (void)hipEventDestroy(c->ev_a[i]);
     if (c->ev_b[i]) (void)hipEventDestroy(c->ev_b[i]);
@@ -1386,8 +1407,7 @@ meg_status external_step_core(meg_ctx c, const meg_objective* grad, meg_step_inf
   HIPCHK(c, launch_steps(c, 1));
   // the caller's arrays are read during the call only
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  st = copy_ctl_to_host(c);
-  if (st == MEG_OK) st = check_barrier(c);
+  st = sync_ctl(c);
   if (st != MEG_OK) return st;
   if (info) {
     fill_info(*c->h_ctl, info);
@@ -1547,6 +1567,8 @@ meg_status meg_init(meg_ctx* out, const meg_params* params, const meg_objective*
          alloc((void**)&c->bil_P, (size_t)c->bil_S * pairs * kBilTile * kBilTile * 8);
   }
   if (ok) ok = hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl)) == hipSuccess;
+  if (ok) ok = hipHostMalloc((void**)&c->h_w, sizeof(meg_ctx_s::HostWords)) == hipSuccess;
+  if (ok) std::memset(c->h_w, 0, sizeof(meg_ctx_s::HostWords));
   for (int i = 0; ok && i < meg_ctx_s::kEvRing; ++i)
     ok = hipEventCreate(&c->ev_a[i]) == hipSuccess && hipEventCreate(&c->ev_b[i]) == hipSuccess;
   if (!ok) {
@@ -1659,8 +1681,7 @@ meg_status da_step(meg_ctx c, meg_step_info* info) {
   c->cfg = csave;
   HIPCHK(c, e);
   if (!info) return MEG_OK;
-  meg_status st = copy_ctl_to_host(c);
-  if (st == MEG_OK) st = check_barrier(c);
+  meg_status st = sync_ctl(c);
   if (st != MEG_OK) return st;
   fill_info(*c->h_ctl, info);
   if (c->h_ctl->status) return (meg_status)c->h_ctl->status;
@@ -1678,8 +1699,7 @@ meg_status meg_step(meg_ctx c, meg_step_info* info) {
   if (info && c->cfg.kind != MASKED_CSR) HIPCHK(c, dispatch<DoObjective>(c));
   HIPCHK(c, launch_steps(c, 1));
   if (!info) return MEG_OK;
-  st = copy_ctl_to_host(c);
-  if (st == MEG_OK) st = check_barrier(c);
+  st = sync_ctl(c);
   if (st != MEG_OK) return st;
   fill_info(*c->h_ctl, info);
   if (c->h_ctl->status) return (meg_status)c->h_ctl->status;
@@ -1731,14 +1751,16 @@ meg_status meg_solve(meg_ctx c, int64_t max_iters, double tol, meg_step_info* la
     }
     return st;
   }
-  // arm the device-side stop rule
-  st = copy_ctl_to_host(c);
-  if (st != MEG_OK) return st;
-  c->h_ctl->solve_tol = tol > 0 ? tol : 0.0;
-  c->h_ctl->stop = 0;
-  HIPCHK(c, hipMemcpyAsync(&c->ctl->solve_tol, &c->h_ctl->solve_tol, sizeof(double), hipMemcpyHostToDevice,
-                           c->stream));
-  HIPCHK(c, hipMemcpyAsync(&c->ctl->stop, &c->h_ctl->stop, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  // Outside this call the device's stop rule is disarmed (solve_tol = 0,
+  // stop = 0): only a tolerance arms it, by asynchronous copies from pinned
+  // words; the host mirror is refreshed after the launches.
+  const bool arm = tol > 0;
+  if (arm) {
+    c->h_w->tol = tol;
+    c->h_w->stop = 0;
+    HIPCHK(c, hipMemcpyAsync(&c->ctl->solve_tol, &c->h_w->tol, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&c->ctl->stop, &c->h_w->stop, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  }
   int64_t done = 0;
   while (done < max_iters) {
     const int m = (int)std::min<int64_t>(kChunkSteps, max_iters - done);
@@ -1750,21 +1772,20 @@ meg_status meg_solve(meg_ctx c, int64_t max_iters, double tol, meg_step_info* la
       if (c->h_ctl->stop || c->h_ctl->status) break;
     }
   }
-  st = copy_ctl_to_host(c);
-  if (st == MEG_OK) st = check_barrier(c);
+  st = sync_ctl(c);
   if (st != MEG_OK) return st;
   const int32_t status = c->h_ctl->status;
   if (last) {
     fill_info(*c->h_ctl, last);
     last->f = __builtin_nan("");
   }
-  // disarm
-  c->h_ctl->solve_tol = 0.0;
-  c->h_ctl->stop = 0;
-  HIPCHK(c, hipMemcpyAsync(&c->ctl->solve_tol, &c->h_ctl->solve_tol, sizeof(double), hipMemcpyHostToDevice,
-                           c->stream));
-  HIPCHK(c, hipMemcpyAsync(&c->ctl->stop, &c->h_ctl->stop, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (arm) {  // disarm: ordered before any later work on the stream, no wait here
+    c->h_ctl->solve_tol = 0.0;
+    c->h_ctl->stop = 0;
+    HIPCHK(c, hipMemcpyAsync(&c->ctl->solve_tol, &c->h_w->zero_d, sizeof(double), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(&c->ctl->stop, &c->h_w->zero_i, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  }
   return status ? (meg_status)status : MEG_OK;
 }
 
@@ -1919,8 +1940,7 @@ meg_status meg_profile_step(meg_ctx c, meg_kernel_times* out) {
   ++c->launches;
   std::vector<long long> ts(kTsSlots);
   HIPCHK(c, hipMemcpy(ts.data(), c->ts, kTsSlots * sizeof(long long), hipMemcpyDeviceToHost));
-  st = copy_ctl_to_host(c);
-  if (st == MEG_OK) st = check_barrier(c);
+  st = sync_ctl(c);
   if (st != MEG_OK) return st;
   int dev = 0, khz = 100000;
   (void)hipGetDevice(&dev);
@@ -2120,8 +2140,7 @@ meg_status meg_solve_to_gap(meg_ctx c, int64_t max_iters, double tol, int32_t ch
     const int m = (int)std::min<int64_t>(check_every, max_iters - done);
     HIPCHK(c, launch_steps(c, m));
     done += m;
-    st = copy_ctl_to_host(c);
-    if (st == MEG_OK) st = check_barrier(c);
+    st = sync_ctl(c);
     if (st != MEG_OK) return st;
     if (c->h_ctl->status) return (meg_status)c->h_ctl->status;
     st = meg_dual_gap(c, 256, 1e-8, &g);
