@@ -296,9 +296,10 @@ __device__ __noinline__ void reduce_group(const gbl<double>* part, gbl<double>* 
   }
 }
 
-// Top level: sums = sum over the ng groups of gpart, in group order.
-template <int NT>
-__device__ __noinline__ void reduce_top(const gbl<double>* gpart, gbl<double>* sums, int plen, unsigned ng) {
+// Top level: sums = sum over the ng groups of gpart, in group order (sums
+// in global memory or in the workgroup's LDS).
+template <int NT, typename DP>
+__device__ __noinline__ void reduce_top(const gbl<double>* gpart, DP sums, int plen, unsigned ng) {
   for (int e0 = threadIdx.x; e0 < plen; e0 += NT * kRedU) {
     double s[kRedU];
 #pragma unroll
@@ -353,8 +354,12 @@ __device__ __forceinline__ Team grid_team() {
 // workgroup of the team through the generation word itself (the last
 // arrival advances it by 1 + 4 tag), so no workgroup reads it back from
 // memory: *tag receives it (0 for a serial part that returns nothing).
+// With lsums (LDS of the calling workgroup) the sums go there instead of to
+// b.sums: only the workgroup that runs `serial` holds them, with no global
+// write and read-back between the reduction and the serial part.
 template <int NT, typename F>
-__device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& serial, int* tag = nullptr) {
+__device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& serial, int* tag = nullptr,
+                                          lds<double>* lsums = nullptr) {
   __shared__ int s_role;  // 0: plain arrival, 1: last of its group, 2: last overall
   __shared__ unsigned s_gen;
   __shared__ int s_ok;
@@ -370,7 +375,10 @@ __device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& 
   };
   if (tm.nwg == 1) {  // a team of one workgroup: its partials are the sums
     __syncthreads();
-    if (plen > 0 && b.sums != b.part) {
+    if (plen > 0 && lsums) {
+      for (int e = tid; e < plen; e += NT) lsums[e] = b.part[e];
+      __syncthreads();
+    } else if (plen > 0 && b.sums != b.part) {
       for (int e = tid; e < plen; e += NT) b.sums[e] = b.part[e];
       __syncthreads();
     }
@@ -420,7 +428,10 @@ __device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& 
   }
   if (s_role == 2) {
     if (plen > 0) {
-      reduce_top<NT>((const gbl<double>*)b.gpart, (gbl<double>*)b.sums, plen, ng);
+      if (lsums)
+        reduce_top<NT>((const gbl<double>*)b.gpart, lsums, plen, ng);
+      else
+        reduce_top<NT>((const gbl<double>*)b.gpart, (gbl<double>*)b.sums, plen, ng);
       __syncthreads();
     }
     const int tg = run_serial();  // uniform over the workgroup

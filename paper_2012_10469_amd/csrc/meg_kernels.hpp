@@ -127,7 +127,10 @@ struct ApplySmem {
   static constexpr int ACC = PLEN + XR * KB;     // accumulators: Gram, residual column sums
   static constexpr int SMALL = small_scratch<KB>();
   static constexpr int BODY = TYPED_DOUBLES > SMALL ? TYPED_DOUBLES : SMALL;
-  static constexpr int TOTAL = ACC + BODY;
+  // the reduced record, summed into LDS by the barrier's last arrival for
+  // the small solve (after its scratch)
+  static constexpr int SUMS = SMALL;
+  static constexpr int TOTAL = ACC + BODY > SUMS + PSTRIDE ? ACC + BODY : SUMS + PSTRIDE;
 };
 
 // Operand pointers of the objective.
@@ -1226,6 +1229,13 @@ __device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl,
   const int tid = threadIdx.x;
 
   const bool masked = cfg.kind == MASKED_CSR;
+  lds<double>* lsums = (lds<double>*)(smem + SM::SUMS);  // the barrier's reduced record
+  // the configuration in LDS for the small solve, a function of its own that
+  // would otherwise read each field from argument memory, one round trip at
+  // a time
+  __shared__ Cfg s_cfg;
+  if (tid == 0) s_cfg = cfg;
+  __syncthreads();
   CsrCache<T> cc{};
   if constexpr (CACHE) {
     const CacheLayout L = cache_layout(cfg.cache_blocks, SH::ROWS, cfg.cache_nnz, (int)sizeof(T), masked);
@@ -1310,14 +1320,14 @@ __device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl,
                 // every thread calls it (it runs on two wavefronts); the step
                 // ends here when it returns 1 (X_{t+1}, t + 1 and the scalars
                 // of step t + 1 are set), fails when it returns 2
-                const int res = small_sweep<KB>(cfg, gc, (const gbl<double>*)b.sums, (lds<double>*)smem, s, in, out,
-                                                grad, tid, (gbl<long long>*)b.ts);
+                const int res = small_sweep<KB>((const lds<Cfg>*)&s_cfg, gc, (const lds<double>*)lsums, (lds<double>*)smem, s, in,
+                                                out, grad, tid, (gbl<long long>*)b.ts);
                 if (res == 1 && deadline != 0 && tid == 0 && (long long)wall_clock64() >= deadline)
                   gc->pause_seq = seq;
                 stamp(b, 2 * s + 1);
                 return res;
               },
-              &ended))
+              &ended, lsums))
         return;
       if (ended) break;  // the next step (or, after a failure, the loop's first check) reads ctl
     }

@@ -520,10 +520,13 @@ __device__ inline double grad_bound(const Cfg& cfg, double alpha, double dl, dou
 // each read would be a separate round trip to memory.
 struct SolveScalars {
   double alpha, sigma, solve_tol, f, pxnorm, op_lmin, op_lmax, dl;  // dl: d_l of this lane (l < r)
-  double mu_up;  // an upper bound of mu_{r+1} for this step (+inf: none)
+  double mu_up_raw;  // an upper bound of mu_{r+1} armed for step mu_up_t (see up_bound)
   double cheb_b, xscale;
-  int64_t t, iters, applies, jacobi, extrap_n, unconv_n;
+  int64_t t, iters, applies, jacobi, extrap_n, unconv_n, mu_up_t;
   int fvalid, pxvalid, polish, xvalid;
+  // the bound of mu_{r+1} for this step (+inf: none armed for it); decided at
+  // the point of use, so that loading the scalars waits for none of them
+  __device__ double up_bound() const { return (mu_up_t == t && t > 0) ? mu_up_raw : __builtin_inf(); }
 };
 __device__ __forceinline__ SolveScalars load_scalars(const Cfg& cfg, const gbl<Ctl>* ctl, int lane) {
   SolveScalars s;
@@ -536,9 +539,8 @@ __device__ __forceinline__ SolveScalars load_scalars(const Cfg& cfg, const gbl<C
   s.op_lmax = ctl->op_lmax;
   s.dl = (lane < cfg.r) ? ctl->d[lane] : 0.0;
   s.t = ctl->t;
-  const double mu_up = ctl->mu_up;  // read unconditionally: one round trip with the rest
-  const int64_t mu_up_t = ctl->mu_up_t;
-  s.mu_up = (mu_up_t == s.t && s.t > 0) ? mu_up : __builtin_inf();
+  s.mu_up_raw = ctl->mu_up;  // read unconditionally: one round trip with the rest
+  s.mu_up_t = ctl->mu_up_t;
   s.cheb_b = ctl->cheb_b;
   s.xscale = ctl->xscale;
   s.iters = ctl->iters_done;
@@ -621,7 +623,7 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
     // L from the Ritz values is a lower bound of the exact L; upper bounds:
     // L + margin with a resolved (r+1)-th pair, and L with mu_{r+1} replaced
     // by the deflated bound (when armed for this step); claims use the lower
-    const double mu_up = fmin(resolved ? mu_r1 + margin : __builtin_inf(), sc.mu_up);
+    const double mu_up = fmin(resolved ? mu_r1 + margin : __builtin_inf(), sc.up_bound());
     const double L_up = cert_upper(cfg, theta, sc, eps, mu_up);
     in.cert_holds = (L_up <= 2.0 * eps) ? 1 : 0;
     in.cert_resolved = resolved;
@@ -640,7 +642,7 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
   }
 }
 
-// One Rayleigh-Ritz / orthonormalisation step.  `sums` (global) holds the
+// One Rayleigh-Ritz / orthonormalisation step.  `sums` (LDS or global) holds the
 // reduced record of PartRec: C = Zin^T Zout, G = Zout^T Zout (triangle),
 // P = V^T Zout (r rows), where Zout = Yhat Q and Q = Zin W is orthonormal.
 // Sets the next sweep's W and PW = V^T Q', or ends the step: the Ritz basis
@@ -654,10 +656,11 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
 // 1 meanwhile forms eps_t and, when the step ends here, the new iterate and
 // its certificate while wavefront 0 forms the next basis.  `scr` (LDS)
 // needs 5 * KB * (KB + 1) + 12 * KB doubles.
-template <int KB>
-__device__ __noinline__ int small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gbl<double>* sums, lds<double>* scr,
+template <int KB, typename SP>
+__device__ __noinline__ int small_sweep(const lds<Cfg>* cfg_l, gbl<Ctl>* ctl, SP sums, lds<double>* scr,
                                          int sweep, int in_buf, int out_buf, bool grad, int tid,
                                          gbl<long long>* ts) {
+  const Cfg& cfg = *(const Cfg*)cfg_l;  // LDS: its fields are read without a memory round trip
   constexpr int LD = KB + 1;
   constexpr int MS = KB * LD;
   const int lane = tid & 63, wave = tid >> 6;
@@ -899,7 +902,7 @@ __device__ __noinline__ int small_sweep(const Cfg& cfg, gbl<Ctl>* ctl, const gbl
       const double lse1 = m1 + log(wave_sum((lane <= r) ? exp(mu1 - m1) : 0.0));
       const double L_lo = log((double)(cfg.n - r)) - log(eps_t) + lane_f64(mu1, r) - lse1;
       const double cut = fmax(2.0 * eps_t, sc.solve_tol);
-      pending = !(L_lo > cut) && !(cert_upper(cfg, theta, sc, eps_t, sc.mu_up) <= cut);
+      pending = !(L_lo > cut) && !(cert_upper(cfg, theta, sc, eps_t, sc.up_bound()) <= cut);
     }
     cert_ok = resolved || !(cfg.cert_tol > 0.0 || pending);
     top_ok = wave_min(pair_ok ? 1.0 : 0.0) > 0.5;
