@@ -255,100 +255,106 @@ __device__ __noinline__ int jacobi_shared_rot(lds<double>* A, lds<double>* S, do
   return sweep;
 }
 
+// Storage slot of circle position x: the pair of positions m and KB - 1 - m
+// (rotation m of every round) is kept in slots 2m and 2m + 1.
+// jacobi_slot_move(s): the slot that the entry in slot s moves to for the
+// next round, the slot of the position before its own (the inverse of
+// jacobi_next), so that round t pairs the indices next^t(m) and
+// next^t(KB - 1 - m), the pairs of the ordering above.  A full sweep of
+// KB - 1 rounds moves every entry once around its cycle, back to its slot.
+template <int KB>
+__device__ __forceinline__ int jacobi_slot(int x) { return x < KB / 2 ? 2 * x : 2 * (KB - 1 - x) + 1; }
+template <int KB>
+__device__ __forceinline__ int jacobi_slot_move(int s) {
+  const int m = s >> 1;
+  const int x = (s & 1) ? KB - 1 - m : m;
+  return jacobi_slot<KB>(x == 0 ? 0 : (x == 1 ? KB - 1 : x - 1));
+}
+
 // Cyclic parallel Jacobi (round-robin ordering) for symmetric A in LDS.
 // On return A is (numerically) diagonal and A_in = S diag(A) S^T.  Stops
 // when the off-diagonal mass is below off2_tol of the total (squared norms);
 // returns the number of sweeps taken.  Each round applies KB/2 disjoint
-// rotations J_m.  A lane owns whole 2 x 2 blocks (m1, m2) of A, updated as
-// J_m1^T A_{m1 m2} J_m2, and the S entries of rotation m1 in rows 2 m2 and
-// 2 m2 + 1; it computes the two rotations it needs itself from the pair's
-// diagonal block (the same inputs and operations in every lane, so every lane
-// derives the same rotation), so a round needs no cross-lane exchange.  All
-// loads of a round precede its stores.
+// rotations J_m, rotation m on the indices held in slots 2m and 2m + 1.  A
+// lane owns the 2 x 2 block (m1, m2) of A, updated as J_m1^T A_{m1 m2} J_m2,
+// and the S entries of rotation m1 in rows 2 m2 and 2 m2 + 1; it computes
+// the two rotations it needs itself from the pairs' diagonal blocks (the same
+// inputs and operations in every lane, so every lane derives the same
+// rotation), so a round needs no cross-lane exchange.  Index x starts in
+// slot jacobi_slot(x) (A permuted on entry, S the matching permutation, so
+// A_in = S A S^T throughout), and the rotated entries are stored where the
+// next round's pairing wants them (rows and columns of A, columns of S moved
+// by jacobi_slot_move): every lane reads and writes the same LDS locations
+// in every round.  All loads of a round precede its stores (in-order LDS
+// queue of the wavefront).
 template <int KB, bool F32ANGLE>
 __device__ __noinline__ int jacobi(lds<double>* A, lds<double>* S, double off2_tol, int lane, lds<double>* rot) {
   constexpr int LD = KB + 1;
   constexpr int NP = KB / 2;
   static_assert((NP * NP) % 64 == 0, "2 x 2 blocks must fill the wavefront");
   constexpr int BPL = NP * NP / 64;  // 2 x 2 blocks per lane
-  if constexpr (BPL > 1) return jacobi_shared_rot<KB, F32ANGLE>(A, S, off2_tol, lane, rot);
-  for (int e = lane; e < KB * KB; e += 64) S[(e / KB) * LD + (e % KB)] = (e / KB == e % KB) ? 1.0 : 0.0;
-  wsync();
-  int sweep = 0;
-  for (; sweep < 30; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int e = lane; e < KB * KB; e += 64) {
-      const double v = A[(e / KB) * LD + (e % KB)];
-      if (e / KB == e % KB) dia += v * v; else off += v * v;
+  if constexpr (BPL > 1) {
+    return jacobi_shared_rot<KB, F32ANGLE>(A, S, off2_tol, lane, rot);
+  } else {
+    constexpr int IT = KB * KB / 64;
+    double v[IT];
+#pragma unroll
+    for (int u = 0; u < IT; ++u) {
+      const int e = lane + 64 * u;
+      v[u] = A[(e / KB) * LD + (e % KB)];
     }
-    off = wave_sum(off);
-    dia = wave_sum(dia);
-    if (!(off > off2_tol * (off + dia))) break;  // also exits on NaN
-    int a1[BPL], b1[BPL], a2[BPL], b2[BPL];  // positions of the four slots
+    __asm__ volatile("" ::: "memory");  // every entry read before any is moved
 #pragma unroll
-    for (int bi = 0; bi < BPL; ++bi) {
-      const int bl = lane + 64 * bi;
-      const int m1 = bl / NP, m2 = bl % NP;
-      a1[bi] = m1;
-      b1[bi] = KB - 1 - m1;
-      a2[bi] = m2;
-      b2[bi] = KB - 1 - m2;
+    for (int u = 0; u < IT; ++u) {
+      const int e = lane + 64 * u, i = e / KB, j = e % KB;
+      A[jacobi_slot<KB>(i) * LD + jacobi_slot<KB>(j)] = v[u];
+      S[i * LD + j] = (j == jacobi_slot<KB>(i)) ? 1.0 : 0.0;
     }
-    for (int round = 0; round < KB - 1; ++round) {
-      int p1[BPL], q1[BPL], p2[BPL], q2[BPL];
-      double blk[BPL][4], r1[BPL][3], r2[BPL][3], sx[BPL][2], sy[BPL][2];
-#pragma unroll
-      for (int bi = 0; bi < BPL; ++bi) {
-        const int m2 = (lane + 64 * bi) % NP;
-        p1[bi] = min(a1[bi], b1[bi]);
-        q1[bi] = max(a1[bi], b1[bi]);
-        p2[bi] = min(a2[bi], b2[bi]);
-        q2[bi] = max(a2[bi], b2[bi]);
-        a1[bi] = jacobi_next<KB>(a1[bi]);
-        b1[bi] = jacobi_next<KB>(b1[bi]);
-        a2[bi] = jacobi_next<KB>(a2[bi]);
-        b2[bi] = jacobi_next<KB>(b2[bi]);
-        blk[bi][0] = A[p1[bi] * LD + p2[bi]];
-        blk[bi][1] = A[p1[bi] * LD + q2[bi]];
-        blk[bi][2] = A[q1[bi] * LD + p2[bi]];
-        blk[bi][3] = A[q1[bi] * LD + q2[bi]];
-        r1[bi][0] = A[p1[bi] * LD + p1[bi]];
-        r1[bi][1] = A[q1[bi] * LD + q1[bi]];
-        r1[bi][2] = A[p1[bi] * LD + q1[bi]];
-        r2[bi][0] = A[p2[bi] * LD + p2[bi]];
-        r2[bi][1] = A[q2[bi] * LD + q2[bi]];
-        r2[bi][2] = A[p2[bi] * LD + q2[bi]];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int row = 2 * m2 + h;
-          sx[bi][h] = S[row * LD + p1[bi]];
-          sy[bi][h] = S[row * LD + q1[bi]];
-        }
+    const unsigned m1 = (unsigned)lane / NP, m2 = (unsigned)lane % NP;
+    // read locations (fixed): the block, the two diagonal blocks, S
+    const unsigned rb = (2 * m1) * LD + 2 * m2;
+    const unsigned d1 = (2 * m1) * (LD + 1), d2 = (2 * m2) * (LD + 1);
+    const unsigned sr = (2 * m2) * LD + 2 * m1;
+    // write locations: the block's rows and columns, S's columns, moved on
+    const unsigned r0 = jacobi_slot_move<KB>(2 * m1), r1 = jacobi_slot_move<KB>(2 * m1 + 1);
+    const unsigned c0 = jacobi_slot_move<KB>(2 * m2), c1 = jacobi_slot_move<KB>(2 * m2 + 1);
+    const unsigned w00 = r0 * LD + c0, w01 = r0 * LD + c1, w10 = r1 * LD + c0, w11 = r1 * LD + c1;
+    const unsigned s0 = (2 * m2) * LD + r0, s1 = (2 * m2) * LD + r1;
+    wsync();
+    int sweep = 0;
+    for (; sweep < 30; ++sweep) {
+      double off = 0.0, dia = 0.0;
+      for (int e = lane; e < KB * KB; e += 64) {
+        const double v = A[(e / KB) * LD + (e % KB)];
+        if (e / KB == e % KB) dia += v * v; else off += v * v;
       }
-#pragma unroll
-      for (int bi = 0; bi < BPL; ++bi) {
-        const int m2 = (lane + 64 * bi) % NP;
-        double c1, s1, c2, s2;
-        jacobi_rot_sel<F32ANGLE>(r1[bi][0], r1[bi][1], r1[bi][2], c1, s1);
-        jacobi_rot_sel<F32ANGLE>(r2[bi][0], r2[bi][1], r2[bi][2], c2, s2);
-        const double a = blk[bi][0], b = blk[bi][1], cc = blk[bi][2], d = blk[bi][3];
-        const double ra = c1 * a - s1 * cc, rb = c1 * b - s1 * d;  // rows: J1^T
-        const double rc = s1 * a + c1 * cc, rd = s1 * b + c1 * d;
-        A[p1[bi] * LD + p2[bi]] = c2 * ra - s2 * rb;               // columns: J2
-        A[p1[bi] * LD + q2[bi]] = s2 * ra + c2 * rb;
-        A[q1[bi] * LD + p2[bi]] = c2 * rc - s2 * rd;
-        A[q1[bi] * LD + q2[bi]] = s2 * rc + c2 * rd;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {  // S <- S J1 in rows 2 m2, 2 m2 + 1
-          const int row = 2 * m2 + h;
-          S[row * LD + p1[bi]] = c1 * sx[bi][h] - s1 * sy[bi][h];
-          S[row * LD + q1[bi]] = s1 * sx[bi][h] + c1 * sy[bi][h];
-        }
+      off = wave_sum(off);
+      dia = wave_sum(dia);
+      if (!(off > off2_tol * (off + dia))) break;  // also exits on NaN
+      for (int round = 0; round < KB - 1; ++round) {
+        const double a = A[rb], b = A[rb + 1], cc = A[rb + LD], d = A[rb + LD + 1];
+        const double p1 = A[d1], q1 = A[d1 + LD + 1], o1 = A[d1 + 1];
+        const double p2 = A[d2], q2 = A[d2 + LD + 1], o2 = A[d2 + 1];
+        const double sx0 = S[sr], sy0 = S[sr + 1], sx1 = S[sr + LD], sy1 = S[sr + LD + 1];
+        __asm__ volatile("" ::: "memory");  // this round's loads, then its stores
+        double cs1, sn1, cs2, sn2;
+        jacobi_rot_sel<F32ANGLE>(p1, q1, o1, cs1, sn1);
+        jacobi_rot_sel<F32ANGLE>(p2, q2, o2, cs2, sn2);
+        const double ra = cs1 * a - sn1 * cc, rbv = cs1 * b - sn1 * d;  // rows: J1^T
+        const double rc = sn1 * a + cs1 * cc, rd = sn1 * b + cs1 * d;
+        A[w00] = cs2 * ra - sn2 * rbv;                                  // columns: J2
+        A[w01] = sn2 * ra + cs2 * rbv;
+        A[w10] = cs2 * rc - sn2 * rd;
+        A[w11] = sn2 * rc + cs2 * rd;
+        S[s0] = cs1 * sx0 - sn1 * sy0;  // S <- S J1 in rows 2 m2, 2 m2 + 1
+        S[s1] = sn1 * sx0 + cs1 * sy0;
+        S[s0 + LD] = cs1 * sx1 - sn1 * sy1;
+        S[s1 + LD] = sn1 * sx1 + cs1 * sy1;
+        wsync();
       }
-      wsync();
     }
+    return sweep;
   }
-  return sweep;
 }
 
 // Value of v in lane l (l uniform across the wavefront), as a scalar.
