@@ -365,6 +365,22 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Value of v in lane l (0 <= l < 16, a compile-time constant once unrolled)
+// of this lane's row of 16 lanes: one 64-bit DPP move (row_newbcast).
+__device__ __forceinline__ double row_bcast_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  long long x = b;
+  switch (l) {
+#define MEG_ROW_BCAST(n) \
+  case n: x = __builtin_amdgcn_mov_dpp(b, 0x150 + n, 0xF, 0xF, false); break;
+    MEG_ROW_BCAST(0) MEG_ROW_BCAST(1) MEG_ROW_BCAST(2) MEG_ROW_BCAST(3) MEG_ROW_BCAST(4) MEG_ROW_BCAST(5)
+    MEG_ROW_BCAST(6) MEG_ROW_BCAST(7) MEG_ROW_BCAST(8) MEG_ROW_BCAST(9) MEG_ROW_BCAST(10) MEG_ROW_BCAST(11)
+    MEG_ROW_BCAST(12) MEG_ROW_BCAST(13) MEG_ROW_BCAST(14) MEG_ROW_BCAST(15)
+#undef MEG_ROW_BCAST
+  }
+  return __longlong_as_double(x);
+}
+
 // Cholesky A = R^T R (R upper) of the symmetric positive definite A (LDS,
 // upper triangle read), R written to LDS (stride KB + 1, zero below the
 // diagonal) and the reciprocals of its diagonal to rdiag[0, KB).  Lane c
@@ -375,34 +391,67 @@ template <int KB>
 __device__ __noinline__ void chol_factor(const lds<double>* A, lds<double>* R, lds<double>* rdiag, int lane) {
   constexpr int LD = KB + 1;
   const int col = lane < KB ? lane : KB - 1;
-  double a[KB];  // column `lane` of A, overwritten by column `lane` of R
+  // column `lane` of A, overwritten by column `lane` of R; its entries below
+  // the diagonal (i > lane) are loaded too (one batch of loads, no select
+  // the compiler could turn into a branch per load) but never read, and
+  // lanes past KB hold a copy of the last column
+  double a[KB];
 #pragma unroll
-  for (int i = 0; i < KB; ++i) {
-    const double v = A[i * LD + col];
-    a[i] = (lane < KB && i <= lane) ? v : 0.0;
-  }
+  for (int i = 0; i < KB; ++i) a[i] = A[i * LD + col];
   const double scale = wave_max(lane < KB ? A[col * LD + col] : 0.0);
   const double floor_piv = fmax(scale, 1e-300) * 1e-28;
-  double rd = 0.0;  // 1 / R_cc in lane c
+  if constexpr (KB == 16) {
+    // The 16 columns are the lanes of one DPP row: row j of the trailing
+    // matrix reaches every lane by 64-bit row broadcasts, taken before row j
+    // is scaled, so they do not wait for the pivot's square root.  Step j
+    // subtracts A_ji A_jc / d_j (d_j the pivot) from A_ic, then scales row j
+    // into R (R_jc = A_jc / sqrt(d_j), R_jj = sqrt(d_j)).
+    double rd = 0.0;  // 1 / R_cc in lane c
 #pragma unroll
-  for (int j = 0; j < KB; ++j) {
-    double dj = readlane_d(a[j], j);
-    if (!(dj > floor_piv)) dj = floor_piv;
-    const double rinv = rsqrt_nr(dj);
-    // row j of R: R_jj = sqrt(dj) (lane j), R_jc = A_jc / R_jj (lanes c > j)
-    a[j] = (lane == j) ? dj * rinv : a[j] * rinv;
-    rd = (lane == j) ? rinv : rd;
+    for (int j = 0; j < KB; ++j) {
+      double bj[KB];
 #pragma unroll
-    for (int i = j + 1; i < KB; ++i) {
-      // A_ic -= R_ji R_jc (R_ji held by lane i).  Done in every lane: the
-      // entries below a lane's diagonal (i > c) are never read.
-      a[i] -= readlane_d(a[j], i) * a[j];
+      for (int i = j; i < KB; ++i) bj[i] = row_bcast_f64(a[j], i);
+      double dj = bj[j];
+      if (!(dj > floor_piv)) dj = floor_piv;
+      const double rinv = rsqrt_nr(dj);
+      const double f = a[j] * (rinv * rinv);
+#pragma unroll
+      for (int i = j + 1; i < KB; ++i) {
+        // A_ic -= A_ji A_jc / d_j (A_ji held by lane i).  Done in every lane:
+        // the entries below a lane's diagonal (i > c) are never read.
+        a[i] -= bj[i] * f;
+      }
+      a[j] = (lane == j) ? dj * rinv : a[j] * rinv;
+      rd = (lane == j) ? rinv : rd;
     }
-  }
-  if (lane < KB) {
+    if (lane < KB) {
 #pragma unroll
-    for (int i = 0; i < KB; ++i) R[i * LD + lane] = (i <= lane) ? a[i] : 0.0;
-    rdiag[lane] = rd;
+      for (int i = 0; i < KB; ++i) R[i * LD + lane] = (i <= lane) ? a[i] : 0.0;
+      rdiag[lane] = rd;
+    }
+  } else {
+    double rd = 0.0;  // 1 / R_cc in lane c
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      double dj = readlane_d(a[j], j);
+      if (!(dj > floor_piv)) dj = floor_piv;
+      const double rinv = rsqrt_nr(dj);
+      // row j of R: R_jj = sqrt(dj) (lane j), R_jc = A_jc / R_jj (lanes c > j)
+      a[j] = (lane == j) ? dj * rinv : a[j] * rinv;
+      rd = (lane == j) ? rinv : rd;
+#pragma unroll
+      for (int i = j + 1; i < KB; ++i) {
+        // A_ic -= R_ji R_jc (R_ji held by lane i).  Done in every lane: the
+        // entries below a lane's diagonal (i > c) are never read.
+        a[i] -= readlane_d(a[j], i) * a[j];
+      }
+    }
+    if (lane < KB) {
+#pragma unroll
+      for (int i = 0; i < KB; ++i) R[i * LD + lane] = (i <= lane) ? a[i] : 0.0;
+      rdiag[lane] = rd;
+    }
   }
   wsync();
 }
