@@ -491,19 +491,73 @@ __device__ __noinline__ void rsolve(const lds<double>* X, lds<double>* Y, const 
   wsync();
 }
 
+// The 16 x 16 case of chol_apply2 in one pass over the factorisation: every
+// row of 16 lanes factors A = R^T R (lane c of the row holding column c, as
+// chol_factor does) and lane l < 32 carries row l of [X1; X2] through the
+// forward substitution y R = x alongside it.  Step j's row broadcasts of the
+// trailing matrix (A_ji, lane i) serve both: R_ji = A_ji / sqrt(d_j), so
+// y_i -= y_j R_ji needs no further exchange.  R itself is not stored.
+__device__ __noinline__ void chol_solve16(const lds<double>* A, lds<double>* X1, int lane) {
+  constexpr int KB = 16, LD = KB + 1;
+  const int col = lane & (KB - 1);
+  const int row = lane < 2 * KB ? lane : 2 * KB - 1;  // lanes past the rows solve a copy of the last one
+  double a[KB], y[KB];
+#pragma unroll
+  for (int i = 0; i < KB; ++i) {
+    a[i] = A[i * LD + col];  // entries below the diagonal (i > col) are never read
+    y[i] = X1[row * LD + i];
+  }
+  const double scale = wave_max(A[col * LD + col]);
+  const double floor_piv = fmax(scale, 1e-300) * 1e-28;
+#pragma unroll
+  for (int j = 0; j < KB; ++j) {
+    double bj[KB];
+#pragma unroll
+    for (int i = j; i < KB; ++i) bj[i] = row_bcast_f64(a[j], i);
+    double dj = bj[j];
+    if (!(dj > floor_piv)) dj = floor_piv;
+    const double rinv = rsqrt_nr(dj);
+    const double f = a[j] * (rinv * rinv);  // A_jc / d_j
+    const double yj = y[j] * rinv;          // y_j = (x_j - sum_{m<j} y_m R_mj) / R_jj
+    const double g = yj * rinv;
+    y[j] = yj;
+#pragma unroll
+    for (int i = j + 1; i < KB; ++i) {
+      a[i] -= bj[i] * f;  // trailing update (entries below a lane's diagonal unused)
+      y[i] -= bj[i] * g;  // y_j R_ji
+    }
+    // both recurrences advance together, one step at a time: otherwise the
+    // compiler runs the factorisation ahead of the substitution and holds
+    // every step's broadcasts in registers
+#pragma unroll
+    for (int i = j; i < KB; ++i) __asm__ volatile("" : "+v"(a[i]), "+v"(y[i]));
+  }
+  wsync();  // every lane has read its row (and A) before any row is written
+  if (lane < 2 * KB) {
+#pragma unroll
+    for (int i = 0; i < KB; ++i) X1[lane * LD + i] = y[i];
+  }
+  wsync();
+}
+
 // Rows [X1; X2] (2 KB rows from X1, X2 = X1 + KB * (KB + 1)) times R^{-1}
 // in place, for R the Cholesky factor of the Gram matrix A: the
 // orthonormalising transform applied to two KB x KB blocks at once.  Rscr:
-// KB * (KB + 1) doubles for R, rdiag: KB doubles.
+// KB * (KB + 1) doubles for R, rdiag: KB doubles (scratch; not written for
+// KB = 16).
 template <int KB>
 __device__ __forceinline__ void chol_apply2(const lds<double>* A, lds<double>* X1, lds<double>* Rscr,
                                             lds<double>* rdiag, int lane) {
-  chol_factor<KB>(A, Rscr, rdiag, lane);
-  if constexpr (2 * KB <= 64) {
-    rsolve<KB>(X1, X1, Rscr, rdiag, 2 * KB, lane);
+  if constexpr (KB == 16) {
+    chol_solve16(A, X1, lane);
   } else {
-    rsolve<KB>(X1, X1, Rscr, rdiag, KB, lane);
-    rsolve<KB>(X1 + KB * (KB + 1), X1 + KB * (KB + 1), Rscr, rdiag, KB, lane);
+    chol_factor<KB>(A, Rscr, rdiag, lane);
+    if constexpr (2 * KB <= 64) {
+      rsolve<KB>(X1, X1, Rscr, rdiag, 2 * KB, lane);
+    } else {
+      rsolve<KB>(X1, X1, Rscr, rdiag, KB, lane);
+      rsolve<KB>(X1 + KB * (KB + 1), X1 + KB * (KB + 1), Rscr, rdiag, KB, lane);
+    }
   }
 }
 
