@@ -350,9 +350,9 @@ __device__ __forceinline__ Team grid_team() {
 // arriver of each group adds its group's partials (in workgroup order) into
 // gpart, the last group adds the group sums (in group order).  The order is
 // fixed, so the sums are bitwise reproducible.  All threads call it.
-// A serial part that returns an int passes it, a tag in [0, 4), to every
+// A serial part that returns an int passes thread 0's value, a tag in [0, 8), to every
 // workgroup of the team through the generation word itself (the last
-// arrival advances it by 1 + 4 tag), so no workgroup reads it back from
+// arrival advances it by 1 + 8 tag), so no workgroup reads it back from
 // memory: *tag receives it (0 for a serial part that returns nothing).
 // With lsums (LDS of the calling workgroup) the sums go there instead of to
 // b.sums: only the workgroup that runs `serial` holds them, with no global
@@ -383,8 +383,9 @@ __device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& 
       __syncthreads();
     }
     const int tg = run_serial();
+    if (tid == 0) s_tag = tg;  // thread 0's value is the tag, as below
     __syncthreads();
-    if (tag) *tag = tg;
+    if (tag) *tag = s_tag;
     return true;
   }
   const unsigned P = (unsigned)tm.nwg;
@@ -439,7 +440,7 @@ __device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& 
     if (threadIdx.x == 0) {
       s_tag = tg;
       __hip_atomic_store(&b.bar[kBarTop], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&b.bar[kBarGen], 1u + 4u * (unsigned)tg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&b.bar[kBarGen], 1u + 8u * (unsigned)tg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
   } else if (tid == 0) {
     unsigned spins = 0, gen;
@@ -451,7 +452,7 @@ __device__ __forceinline__ bool grid_sync(const Bufs& b, Team tm, int plen, F&& 
         break;
       }
     }
-    s_tag = (int)(((gen - s_gen) - 1u) >> 2);
+    s_tag = (int)(((gen - s_gen) - 1u) >> 3);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();

@@ -769,19 +769,41 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
   // explicit residuals of the previous Rayleigh-Ritz sweep: this sweep's
   // input Zin is that sweep's output, Zprev its input
   const bool xr = SM::XR && cfg.xres && ctl->xvalid;
-  // per-sweep coefficients
-  for (int e = tid; e < KB * KB; e += NT) {
-    const int i = e / KB, j = e % KB;
-    tb[SM::T_W + i * LD + j] = (T)ctl->W[e];
-    tb[SM::T_WB + i * LD + j] = (T)ctl->Wb[e];
-    tb[SM::T_PW + e] = (i < r) ? (T)ctl->PW[e] : (T)0;
+  // per-sweep coefficients: loaded into registers here, stored to LDS with
+  // the first row block's loads in flight (before that block's barrier, the
+  // first point of use), so the two round trips to memory overlap
+  constexpr int CPT = (KB * KB + NT - 1) / NT;  // coefficient entries per thread
+  T cw[CPT], cwb[CPT], cpw[CPT];
+#pragma unroll
+  for (int u = 0; u < CPT; ++u) {
+    const int e = tid + u * NT;
+    cw[u] = 0;
+    cwb[u] = 0;
+    cpw[u] = 0;
+    if (e < KB * KB) {
+      cw[u] = (T)ctl->W[e];
+      cwb[u] = (T)ctl->Wb[e];
+      cpw[u] = (e / KB < r) ? (T)ctl->PW[e] : (T)0;
+    }
   }
   // Chebyshev filter of the sweep (degree 1 on the interval [0, b] of the
   // unwanted spectrum, b = cheb_b; 0: none): Zout = fa Yhat Q + fb Q with
   // fa = 2/b, fb = -1, folded into the operator's coefficients
   const double chb = ctl->cheb_b;
   const double fa = chb > 0.0 ? 2.0 / chb : 1.0, fb = chb > 0.0 ? -1.0 : 0.0;
-  if (tid < KB) tb[SM::T_CE + tid] = (T)(fa * ctl->ceff[tid]);
+  const double ce = tid < KB ? ctl->ceff[tid] : 0.0;
+  auto store_coefs = [&]() {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int e = tid + u * NT, i = e / KB, j = e % KB;
+      if (e < KB * KB) {
+        tb[SM::T_W + i * LD + j] = cw[u];
+        tb[SM::T_WB + i * LD + j] = cwb[u];
+        tb[SM::T_PW + e] = cpw[u];
+      }
+    }
+    if (tid < KB) tb[SM::T_CE + tid] = (T)(fa * ce);
+  };
   for (int e = tid; e < SM::ACC; e += NT) smem[e] = 0.0;
   const T opscale = (T)(fa * ctl->opscale), sdiag = (T)(fa * ctl->sdiag + fb);
   T alpha = 0, dl = 0;
@@ -812,6 +834,7 @@ __device__ void apply_phase(const Cfg& cfg, const Ctl* ctl, const Data<T>& dat, 
         if (SM::XR && xr) pp[u] = Zprev[i * KB + e % KB];
       }
     }
+    if (jb == 0) store_coefs();
     __syncthreads();  // previous block's LDS reads are done; coefficients are visible
     if constexpr (OPK == OP_CSR) {
       // RPW rows per wave, gathered together; a row's nonzeros are split over
@@ -1246,16 +1269,21 @@ __device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl,
     cc.gv = masked ? cc.g : cc.val;
     load_csr_cache<T, SH::ROWS, NT>(cfg, dat, cc, tm);
   }
-  for (int st = 0; st < nsteps; ++st) {
-    // the control words read together (one round trip): the step scalars
-    // (shift, coefficients) and the basis (B, Wb) were set at the end of the
-    // previous iteration
+  // The launch's first step reads the control words (read together, one
+  // round trip); every later step takes them from the tag of the barrier
+  // that ended the previous one (kSweep*: its input block, and whether the
+  // team stops), so no step waits on a read of ctl before its first loads.
+  int src = ldi(&ctl->src);
+  {
     const int stop = ldi(&ctl->stop), status = ldi(&ctl->status);
-    const int64_t t0 = ldi64(&ctl->t);
-    const int src = ldi(&ctl->src);
     const int64_t pause = deadline != 0 ? ldi64(&ctl->pause_seq) : seq - 1;
-    if (stop | status) break;
-    if (pause == seq) break;
+    if ((stop | status) != 0 || pause == seq) return;
+  }
+  for (int st = 0; st < nsteps; ++st) {
+    // the step scalars (shift, coefficients) and the basis (B, Wb) were set
+    // at the end of the previous iteration
+    int64_t t0 = 0;
+    if constexpr (OPK == OP_FACTOR) t0 = ldi64(&ctl->t);
     if (tm.wg == 0) {
       stamp(b, 0);
       stamp(b, 1);  // no separate gradient phase: it is part of sweep 1
@@ -1311,25 +1339,31 @@ __device__ __forceinline__ void step_loop(const Cfg& cfg, Ctl* __restrict__ ctl,
                                                   (lds<char>*)xstage, tm);
       }
       stamp_wg(b, tm, s, 1);
-      int ended = 0;
+      int outcome = 0;
       if (!grid_sync<NT>(
               b, tm, PartRec<KB>::len(cfg.r, SM::XR != 0),
               [&]() -> int {
                 stamp(b, 2 * s);
                 gbl<Ctl>* gc = (gbl<Ctl>*)ctl;
-                // every thread calls it (it runs on two wavefronts); the step
-                // ends here when it returns 1 (X_{t+1}, t + 1 and the scalars
-                // of step t + 1 are set), fails when it returns 2
-                const int res = small_sweep<KB>((const lds<Cfg>*)&s_cfg, gc, (const lds<double>*)lsums, (lds<double>*)smem, s, in,
-                                                out, grad, tid, (gbl<long long>*)b.ts);
-                if (res == 1 && deadline != 0 && tid == 0 && (long long)wall_clock64() >= deadline)
+                // every thread calls it (it runs on two wavefronts); with
+                // kSweepEnded X_{t+1}, t + 1 and the scalars of step t + 1
+                // are set.  Thread 0's value is the barrier's tag.
+                int res = small_sweep<KB>((const lds<Cfg>*)&s_cfg, gc, (const lds<double>*)lsums,
+                                          (lds<double>*)smem, s, in, out, grad, tid, (gbl<long long>*)b.ts);
+                if ((res & kSweepEnded) && deadline != 0 && tid == 0 && (long long)wall_clock64() >= deadline) {
                   gc->pause_seq = seq;
+                  res |= kSweepHalt;
+                }
                 stamp(b, 2 * s + 1);
                 return res;
               },
-              &ended, lsums))
+              &outcome, lsums))
         return;
-      if (ended) break;  // the next step (or, after a failure, the loop's first check) reads ctl
+      if (outcome & kSweepHalt) return;  // failure, stopping rule or pause: ctl records which
+      if (outcome & kSweepEnded) {
+        src = (outcome & kSweepExtrap) ? out : in;
+        break;
+      }
     }
   }
 }

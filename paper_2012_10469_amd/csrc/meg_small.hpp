@@ -687,7 +687,7 @@ __device__ inline double cert_upper(const Cfg& cfg, const lds<double>* theta, co
 __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<double>* theta, const lds<double>* rho,
                                    double resid_max, int sweeps, int converged, int resolved, double margin,
                                    double eps, const SolveScalars& sc, int lane, double& d_out, double& c_out,
-                                   double& alpha_out) {
+                                   double& alpha_out, int& halt_out) {
   const int r = cfg.r;
   const double n = (double)cfg.n;
   const double alpha = sc.alpha, sigma = sc.sigma, solve_tol = sc.solve_tol;
@@ -721,6 +721,7 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
   c_out = cl;
   alpha_out = alpha_n;
   const bool all_ok = wave_min(ok ? 1.0 : 0.0) > 0.5 && isfinite(lse_r1);
+  halt_out = all_ok ? 0 : 1;
   if (lane == 0) {
     ctl->alpha = alpha_n;
     const double L = log(n - r) - log(eps) + mu_r1 - lse_r1;
@@ -747,9 +748,18 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
     in.converged = converged;
     in.f = sc.fvalid ? sc.f : __builtin_nan("");
     if (!all_ok) ctl->status = 4;  // MEG_ERR_NUMERIC
-    if (solve_tol > 0.0 && fmax(2.0 * eps, L_up) <= solve_tol) ctl->stop = 1;
+    if (solve_tol > 0.0 && fmax(2.0 * eps, L_up) <= solve_tol) {
+      ctl->stop = 1;
+      halt_out = 1;  // lane 0's value is the one used
+    }
   }
 }
+
+// small_sweep's outcome, the tag of the barrier it ends: the step ended
+// (X_{t+1} and the next step's scalars are set); its next warm start is this
+// sweep's output block (extrapolated end; otherwise its input block); the
+// team stops here (a failure, a met stopping rule or a pause; ctl says which).
+constexpr int kSweepEnded = 1, kSweepExtrap = 2, kSweepHalt = 4;
 
 // One Rayleigh-Ritz / orthonormalisation step.  `sums` (LDS or global) holds the
 // reduced record of PartRec: C = Zin^T Zout, G = Zout^T Zout (triangle),
@@ -758,8 +768,8 @@ __device__ inline void finish_step(const Cfg& cfg, gbl<Ctl>* ctl, const lds<doub
 // Zin (W S) becomes the next warm start (B, Wb) = (Zin, W S), advances t and
 // sets the next step's shift and coefficients.  Counts the apply (and the
 // Jacobi sweeps) in ctl.  `grad`: this sweep formed the masked gradient (its
-// objective sums are in the record).  Returns 1 when the step ended, 2 when
-// it failed (status set), 0 otherwise (uniform over the workgroup).
+// objective sums are in the record).  Returns 0 when another sweep follows,
+// else the kSweep* bits of the outcome (uniform over the workgroup).
 // Called by every thread of the workgroup (tid); the work runs on two
 // wavefronts, wave-synchronously within each: wavefront 0 solves, wavefront
 // 1 meanwhile forms eps_t and, when the step ends here, the new iterate and
@@ -1062,19 +1072,23 @@ __device__ __noinline__ int small_sweep(const lds<Cfg>* cfg_l, gbl<Ctl>* ctl, SP
   }
   __syncthreads();  // the decision
   const int code = (int)xch[1];
-  if (code == 4) return 2;
+  if (code == 4) return kSweepHalt;
   if (code != 0) {
     // the step ends here: wavefront 1 exponentiates and normalises and
     // forms the certificate, wavefront 0 the next basis
     if (wave == 1) {
       double d_new, c_new, a_new;
+      int halt;
       finish_step(cfg, ctl, theta, rho, xch[2], sweep, (int)xch[3], (int)xch[4], xch[5], eps_t, sc, lane, d_new,
-                  c_new, a_new);
+                  c_new, a_new, halt);
       if (lane < KB) {
         xch[8 + lane] = d_new;
         xch[8 + KB + lane] = c_new;
       }
-      if (lane == 0) xch[8 + 2 * KB] = a_new;
+      if (lane == 0) {
+        xch[8 + 2 * KB] = a_new;
+        xch[8 + 2 * KB + 1] = halt;
+      }
     }
     lds<double>* Cm = B3;
     if (wave == 0) {
@@ -1178,7 +1192,7 @@ __device__ __noinline__ int small_sweep(const lds<Cfg>* cfg_l, gbl<Ctl>* ctl, SP
       }
       if (prof) ts[kTsRR + 3] = wall_clock64();
     }
-    return 1;
+    return kSweepEnded | (code == 2 ? kSweepExtrap : 0) | (xch[8 + 2 * KB + 1] != 0.0 ? kSweepHalt : 0);
   }
   if (wave == 0) {
     if (cfg.xres) {
