@@ -58,9 +58,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # warmup iterations), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
 # plain copy's readings (profiles/k_step_matrix_completion_n4096_r10_traffic.md);
 # valid only for the kernel sources and the launch it was measured on.
-TRAFFIC = {"bytes_per_launch": 171.8e6, "iterations_per_launch": 20, "warmup": 5, "applies_per_iteration": 2.0,
-           "fetch_bytes": 91.0e6, "write_bytes": 80.8e6, "fetch_factor": 2.0, "write_factor": 1.0,
-           "source_hash": "d8b347206bdef00e"}
+TRAFFIC = {"bytes_per_launch": 151.1e6, "iterations_per_launch": 20, "warmup": 5, "applies_per_iteration": 2.0,
+           "fetch_bytes": 90.6e6, "write_bytes": 60.5e6, "fetch_factor": 2.0, "write_factor": 1.0,
+           "source_hash": "dc45fad571101bd0"}
 KERNEL_SOURCES = ["meg_device.hpp", "meg_small.hpp", "meg_kernels.hpp", "meg_api.hip"]
 
 
