@@ -468,8 +468,11 @@ meg_status meg_solve_to_gap(meg_ctx ctx, int64_t max_iters, double tol, int32_t 
  * masked kind's stored gradient values, which the next step recomputes);
  * MEG_ERR_UNSUPPORTED for the minibatch and external kinds;
  * MEG_ERR_INVALID_ARG for p < 0, p > 0 with probes == NULL, weight <= 0,
- * max_steps < 1, tol < 0 or out == NULL.  Allocates five blocks of 64 x n
- * doubles (and 2 x 64 x max_steps) for the call.  Synchronises; HOST output. */
+ * max_steps < 1, tol < 0 or out == NULL.  Its device workspace (five blocks
+ * of 64 x n doubles, 2 x 64 x max_steps and small buffers) belongs to the
+ * context: allocated by the first call, grown when a later call needs more,
+ * freed by meg_destroy (MEG_ERR_OUT_OF_MEMORY when it cannot be allocated).
+ * Synchronises; HOST output. */
 typedef struct {
   double log_b;           /* log of the estimate of b_n = tr exp(M_t)          */
   double log_b_defl;      /* log tr(Q^T exp(M_t) Q)                             */

@@ -78,6 +78,8 @@ struct meg_ctx_s {
   double* lz_prev = nullptr;  // the dual gap's last lambda_min Ritz vector (n doubles), its next start
   double* lz_ws = nullptr;    // Lanczos workspace of the gradient's lambda_min runs (kept, grown on demand)
   size_t lz_ws_doubles = 0;
+  char* tr_ws = nullptr;      // the trace estimate's device buffers (kept, grown on demand)
+  size_t tr_ws_bytes = 0;
   double* gpart = nullptr;
   double* sums = nullptr;
   unsigned* bar = nullptr;
@@ -974,19 +976,32 @@ meg_status trace_exp_run(meg_ctx c, const double* probes, int p, double weight, 
   double *Qd = nullptr, *B0 = nullptr, *B1 = nullptr, *B2 = nullptr, *Y = nullptr, *al = nullptr, *bb = nullptr;
   double *P = nullptr, *Mx = nullptr, *dcv = nullptr, *sm1 = nullptr, *sm2 = nullptr, *part = nullptr;
   const int GR = (int)std::min<int64_t>(kTrRedWG, ceil_div(n, 4));
-  auto alloc = [&](double** q, size_t bytes) { return hipMalloc((void**)q, std::max<size_t>(bytes, 256)) == hipSuccess; };
-  bool ok = alloc(&Qd, vbytes) && alloc(&B0, vbytes) && alloc(&B1, vbytes) && alloc(&B2, vbytes) &&
-            alloc(&Y, vbytes) && alloc(&al, (size_t)m * kTrW * 8) && alloc(&bb, (size_t)m * kTrW * 8) &&
-            alloc(&P, (size_t)kTrW * kTrW * 8) && alloc(&Mx, (size_t)kTrW * kTrW * 8) && alloc(&dcv, KMAX * 8) &&
-            alloc(&sm1, kTrW * 8) && alloc(&sm2, kTrW * 8) && alloc(&part, (size_t)GR * 32 * kTrW * 8);
-  auto release = [&]() {
-    for (double* q : {Qd, B0, B1, B2, Y, al, bb, P, Mx, dcv, sm1, sm2, part})
-      if (q) (void)hipFree(q);
-  };
-  if (!ok) {
-    (void)hipGetLastError();
-    release();
-    return MEG_ERR_OUT_OF_MEMORY;
+  // the buffers are carved from one context workspace, allocated on first
+  // use and kept (grown when a later call needs more): repeated calls
+  // allocate nothing
+  double** bufs[] = {&Qd, &B0, &B1, &B2, &Y, &al, &bb, &P, &Mx, &dcv, &sm1, &sm2, &part};
+  const size_t sizes[] = {vbytes, vbytes, vbytes, vbytes, vbytes, (size_t)m * kTrW * 8, (size_t)m * kTrW * 8,
+                          (size_t)kTrW * kTrW * 8, (size_t)kTrW * kTrW * 8, (size_t)KMAX * 8, (size_t)kTrW * 8,
+                          (size_t)kTrW * 8, (size_t)GR * 32 * kTrW * 8};
+  size_t need = 0;
+  for (size_t b : sizes) need += (b + 255) / 256 * 256;
+  if (need > c->tr_ws_bytes) {
+    if (c->tr_ws) (void)hipFree(c->tr_ws);
+    c->tr_ws = nullptr;
+    c->tr_ws_bytes = 0;
+    if (hipMalloc((void**)&c->tr_ws, need) != hipSuccess) {
+      (void)hipGetLastError();
+      c->tr_ws = nullptr;
+      return MEG_ERR_OUT_OF_MEMORY;
+    }
+    c->tr_ws_bytes = need;
+  }
+  {
+    size_t off = 0;
+    for (size_t i = 0; i < sizeof(sizes) / sizeof(sizes[0]); ++i) {
+      *bufs[i] = reinterpret_cast<double*>(c->tr_ws + off);
+      off += (sizes[i] + 255) / 256 * 256;
+    }
   }
   const hipStream_t sm = c->stream;
   const int ge = (int)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n * kTrW, 256)));
@@ -994,7 +1009,6 @@ meg_status trace_exp_run(meg_ctx c, const double* probes, int p, double weight, 
   meg_status st = MEG_OK;
   auto fail = [&]() {
     st = hip_fail(c);
-    release();
     return st;
   };
   if (hipMemcpyAsync(dcv, cv.data(), KMAX * 8, hipMemcpyHostToDevice, sm) != hipSuccess) return fail();
@@ -1117,7 +1131,6 @@ meg_status trace_exp_run(meg_ctx c, const double* probes, int p, double weight, 
       tail[next_probe + b - nq] = nsq[b] > 0.0 ? lq[b] : -std::numeric_limits<double>::infinity();
     next_probe += np_b;
   }
-  release();
   const double ninf = -std::numeric_limits<double>::infinity();
   const double lb_defl = defl.empty() ? ninf : log_sum_exp(defl);
   const double lb_tail = p > 0 ? std::log(weight) + log_sum_exp(tail) : ninf;
@@ -1332,7 +1345,8 @@ meg_status validate(const meg_params* p, const meg_objective* o, const meg_start
 void free_ctx(meg_ctx c) {
   if (!c) return;
   void* bufs[] = {c->Qw,   c->Za,  c->Zb, c->g,  c->quad,    c->ctl,    c->part,     c->gpart,
-                  c->sums, c->bar, c->ts, c->lz_prev, c->lz_ws, c->bil_G, c->bil_res, c->bil_P, c->da_Y};
+                  c->sums, c->bar, c->ts, c->lz_prev, c->lz_ws, c->tr_ws, c->bil_G, c->bil_res, c->bil_P,
+                  c->da_Y};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
