@@ -2264,7 +2264,7 @@ static __global__ __launch_bounds__(256) void k_bil_resid(Cfg cfg, const Ctl* __
 // the R = mp measurement rows; P_s[J,K][jl][kl] = sum_{rows i in slice s}
 // r_{i/p} (a_ij b_ik + b_ij a_ik) with j = 64 J + jl, k = 64 K + kl.  A dense
 // contraction over the rows, on the FP64 matrix cores: rows are staged 16 at a
-// time in LDS (the J side scaled by the residual), each wave owns a 32 x 32
+// time in LDS (the J side scaled by the residual as it is read), each wave owns a 32 x 32
 // quarter of the tile as 2 x 2 blocks of 16 x 16, and every 4-row step issues
 // v_mfma_f64_16x16x4f64 twice per block (r a_J with b_K, r b_J with a_K).
 // Operand layout: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
@@ -2285,7 +2285,13 @@ static __global__ __launch_bounds__(256) void k_bil_grad_part(int64_t n, const T
                                                               int64_t m, int p, const double* __restrict__ res,
                                                               int64_t per_slice, int tiles,
                                                               double* __restrict__ P) {
-  __shared__ double aJ[16][kBilTile], bJ[16][kBilTile], aK[16][kBilTile], bK[16][kBilTile];
+  // Rows staged in the state's type, double-buffered: the next 16 rows are
+  // loaded into registers before this stage's matrix-core work and stored to
+  // the other buffer after it, so their latency overlaps the products; one
+  // barrier per stage.  The J side is scaled by the residual as it is read
+  // (the same FP64 product r_i a_ij as staging it scaled).
+  __shared__ T sJa[2][16][kBilTile], sJb[2][16][kBilTile], sKa[2][16][kBilTile], sKb[2][16][kBilTile];
+  __shared__ double sr[2][16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int jw = 32 * (wave >> 1), kw = 32 * (wave & 1);  // the wave's quarter of the tile
   const int li = lane & 15, lk = lane >> 4;
@@ -2299,30 +2305,54 @@ static __global__ __launch_bounds__(256) void k_bil_grad_part(int64_t n, const T
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4_t{0.0, 0.0, 0.0, 0.0};
-  for (int64_t i0 = i_beg; i0 < i_end; i0 += 16) {
+  // thread tid stages column jj = tid % 64 of rows ii = tid / 64 + 4 s
+  const int jj = tid & 63, ib = tid >> 6;
+  const bool okj = j0 + jj < n, okk = k0 + jj < n;
+  T va[4], vb[4], wa[4], wb[4];
+  double rv[4];
+  auto gload = [&](int64_t i0) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int e = tid + 256 * s, ii = e >> 6, jj = e & 63;
-      const int64_t i = i0 + ii;
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int64_t i = i0 + ib + 4 * s4;
       const bool ok = i < i_end;
-      const double ri = ok ? res[i / p] : 0.0;
-      const bool okj = ok && j0 + jj < n, okk = ok && k0 + jj < n;
-      aJ[ii][jj] = okj ? ri * (double)A[i * lda + j0 + jj] : 0.0;
-      bJ[ii][jj] = okj ? ri * (double)A[(m + i) * lda + j0 + jj] : 0.0;
-      aK[ii][jj] = okk ? (double)A[i * lda + k0 + jj] : 0.0;
-      bK[ii][jj] = okk ? (double)A[(m + i) * lda + k0 + jj] : 0.0;
+      rv[s4] = ok ? res[i / p] : 0.0;
+      va[s4] = ok && okj ? A[i * lda + j0 + jj] : (T)0;
+      vb[s4] = ok && okj ? A[(m + i) * lda + j0 + jj] : (T)0;
+      wa[s4] = ok && okk ? A[i * lda + k0 + jj] : (T)0;
+      wb[s4] = ok && okk ? A[(m + i) * lda + k0 + jj] : (T)0;
     }
-    __syncthreads();
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int ii = ib + 4 * s4;
+      sJa[buf][ii][jj] = va[s4];
+      sJb[buf][ii][jj] = vb[s4];
+      sKa[buf][ii][jj] = wa[s4];
+      sKb[buf][ii][jj] = wb[s4];
+      if (jj == 0) sr[buf][ii] = rv[s4];
+    }
+  };
+  if (i_beg < i_end) {
+    gload(i_beg);
+    lstore(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t i0 = i_beg; i0 < i_end; i0 += 16, buf ^= 1) {
+    const bool more = i0 + 16 < i_end;
+    if (more) gload(i0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int kk = 4 * ks + lk;
+      const double rk = sr[buf][kk];
       double xa[2], xb[2], ya[2], yb[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        xa[t] = aJ[kk][jw + 16 * t + li];
-        xb[t] = bJ[kk][jw + 16 * t + li];
-        ya[t] = aK[kk][kw + 16 * t + li];
-        yb[t] = bK[kk][kw + 16 * t + li];
+        xa[t] = rk * (double)sJa[buf][kk][jw + 16 * t + li];
+        xb[t] = rk * (double)sJb[buf][kk][jw + 16 * t + li];
+        ya[t] = (double)sKa[buf][kk][kw + 16 * t + li];
+        yb[t] = (double)sKb[buf][kk][kw + 16 * t + li];
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -2332,6 +2362,9 @@ static __global__ __launch_bounds__(256) void k_bil_grad_part(int64_t n, const T
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[a], ya[b], acc[a][b], 0, 0, 0);
         }
     }
+    // the other buffer was last read in the previous stage, before the
+    // barrier that ended it
+    if (more) lstore(buf ^ 1);
     __syncthreads();
   }
   double* dst = P + ((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * (kBilTile * kBilTile);
