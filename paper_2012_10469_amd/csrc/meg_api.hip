@@ -355,9 +355,12 @@ struct Launch {
     hipLaunchKernelGGL((k_materialize<T, KB>), dim3(mwg), dim3(256), 0, c->stream, cfg, c->ctl, (T*)c->Qw, (T*)c->Za,
                        (T*)c->Zb);
     const int rg = (int)std::min<int64_t>(1024, ceil_div(m, 4));
-    hipLaunchKernelGGL((k_bil_resid<T, KB>), dim3(rg), dim3(256), 0, c->stream, cfg, (const Ctl*)c->ctl,
-                       (const T*)c->Qw, (const T*)c->Za, (const T*)c->Zb, (const T*)c->obj.A, c->obj.lda,
-                       (const T*)c->obj.b, m, p, c->bil_res, c->part);
+    // V staged in LDS when it fits in 48 KB (read from the basis otherwise)
+    const size_t vbytes = (size_t)cfg.r * (size_t)n * sizeof(T);
+    const int qlds = vbytes <= 48 * 1024 ? 1 : 0;
+    hipLaunchKernelGGL((k_bil_resid<T, KB>), dim3(rg), dim3(256), qlds ? vbytes : 0, c->stream, cfg,
+                       (const Ctl*)c->ctl, (const T*)c->Qw, (const T*)c->Za, (const T*)c->Zb, (const T*)c->obj.A,
+                       c->obj.lda, (const T*)c->obj.b, m, p, c->bil_res, c->part, qlds);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, c->stream, c->ctl, c->part, rg, 0);
     if (grad) {
       const int tiles = (int)ceil_div(n, kBilTile), pairs = tiles * (tiles + 1) / 2;

@@ -2211,12 +2211,22 @@ template <typename T, int KB>
 static __global__ __launch_bounds__(256) void k_bil_resid(Cfg cfg, const Ctl* __restrict__ ctl, const T* Z0,
                                                           const T* Z1, const T* Z2, const T* __restrict__ A,
                                                           int64_t lda, const T* __restrict__ y, int64_t m, int p,
-                                                          double* __restrict__ res, double* __restrict__ part) {
+                                                          double* __restrict__ res, double* __restrict__ part,
+                                                          int qlds) {
   const T* Q = zbuf(Z0, Z1, Z2, (ctl->src + 1) % 3);  // written by k_materialize
   __shared__ double sred[4];
+  // qlds: V (the r used columns of Q) staged transposed in dynamic LDS,
+  // Vt[l n + j] = Q[j][l], so a wave's reads of V_l are contiguous (Q's rows
+  // are KB wide: reading Q[j][l] across lanes strides by a row)
+  extern __shared__ __attribute__((aligned(16))) char dyn[];
+  T* Vt = reinterpret_cast<T*>(dyn);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = cfg.r;
   const int64_t n = cfg.n;
+  if (qlds) {
+    for (int64_t e = threadIdx.x; e < (int64_t)r * n; e += 256) Vt[e] = Q[(e % n) * KB + e / n];
+    __syncthreads();
+  }
   double fsum = 0.0;
   const int64_t mp = m * p;
   // the contribution of one column pair: alpha a^T b + sum_l d_l (a^T v_l)(b^T v_l)
@@ -2224,6 +2234,7 @@ static __global__ __launch_bounds__(256) void k_bil_resid(Cfg cfg, const Ctl* __
     double pa[KB], pb[KB], ab = 0.0;
 #pragma unroll
     for (int l = 0; l < KB; ++l) pa[l] = pb[l] = 0.0;
+#pragma unroll 2
     for (int64_t j = lane; j < n; j += 64) {
       const double aj = (double)a[j], bj = (double)b[j];
       ab += aj * bj;
@@ -2231,7 +2242,7 @@ static __global__ __launch_bounds__(256) void k_bil_resid(Cfg cfg, const Ctl* __
 #pragma unroll
       for (int l = 0; l < KB; ++l) {
         if (l < r) {
-          const double v = (double)q[l];
+          const double v = (double)(qlds ? Vt[l * n + j] : q[l]);
           pa[l] += aj * v;
           pb[l] += bj * v;
         }
