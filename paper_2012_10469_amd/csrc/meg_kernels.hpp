@@ -2234,17 +2234,32 @@ static __global__ __launch_bounds__(256) void k_bil_resid(Cfg cfg, const Ctl* __
     double pa[KB], pb[KB], ab = 0.0;
 #pragma unroll
     for (int l = 0; l < KB; ++l) pa[l] = pb[l] = 0.0;
-#pragma unroll 2
-    for (int64_t j = lane; j < n; j += 64) {
-      const double aj = (double)a[j], bj = (double)b[j];
-      ab += aj * bj;
-      const T* q = Q + j * KB;
+    // columns in chunks of 8 x 64: the chunk's loads are issued together,
+    // then its sums (the same per-lane order as one column at a time)
+    constexpr int CH = 8;
+    for (int64_t j0 = lane; j0 < n; j0 += 64 * CH) {
+      T av[CH], bv[CH];
 #pragma unroll
-      for (int l = 0; l < KB; ++l) {
-        if (l < r) {
-          const double v = (double)(qlds ? Vt[l * n + j] : q[l]);
-          pa[l] += aj * v;
-          pb[l] += bj * v;
+      for (int u = 0; u < CH; ++u) {
+        const int64_t j = j0 + 64 * u;
+        av[u] = j < n ? a[j] : (T)0;
+        bv[u] = j < n ? b[j] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int64_t j = j0 + 64 * u;
+        if (j < n) {
+          const double aj = (double)av[u], bj = (double)bv[u];
+          ab += aj * bj;
+          const T* q = Q + j * KB;
+#pragma unroll
+          for (int l = 0; l < KB; ++l) {
+            if (l < r) {
+              const double v = (double)(qlds ? Vt[l * n + j] : q[l]);
+              pa[l] += aj * v;
+              pb[l] += bj * v;
+            }
+          }
         }
       }
     }
