@@ -122,6 +122,22 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return y * (2.0 - x * y);
 }
 
+// Value of v in lane l (0 <= l < 16, a compile-time constant once unrolled)
+// of this lane's row of 16 lanes: one 64-bit DPP move (row_newbcast).
+__device__ __forceinline__ double row_bcast_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  long long x = b;
+  switch (l) {
+#define MEG_ROW_BCAST(n) \
+  case n: x = __builtin_amdgcn_mov_dpp(b, 0x150 + n, 0xF, 0xF, false); break;
+    MEG_ROW_BCAST(0) MEG_ROW_BCAST(1) MEG_ROW_BCAST(2) MEG_ROW_BCAST(3) MEG_ROW_BCAST(4) MEG_ROW_BCAST(5)
+    MEG_ROW_BCAST(6) MEG_ROW_BCAST(7) MEG_ROW_BCAST(8) MEG_ROW_BCAST(9) MEG_ROW_BCAST(10) MEG_ROW_BCAST(11)
+    MEG_ROW_BCAST(12) MEG_ROW_BCAST(13) MEG_ROW_BCAST(14) MEG_ROW_BCAST(15)
+#undef MEG_ROW_BCAST
+  }
+  return __longlong_as_double(x);
+}
+
 // Jacobi rotation zeroing A_pq of the 2 x 2 block [[app, apq], [apq, aqq]]:
 //   t = tan(angle) = 2 apq sign(delta) / (|delta| + sqrt(delta^2 + 4 apq^2)),
 //   delta = aqq - app, c = 1/sqrt(1 + t^2), s = t c
@@ -277,10 +293,13 @@ __device__ __forceinline__ int jacobi_slot_move(int s) {
 // returns the number of sweeps taken.  Each round applies KB/2 disjoint
 // rotations J_m, rotation m on the indices held in slots 2m and 2m + 1.  A
 // lane owns the 2 x 2 block (m1, m2) of A, updated as J_m1^T A_{m1 m2} J_m2,
-// and the S entries of rotation m1 in rows 2 m2 and 2 m2 + 1; it computes
-// the two rotations it needs itself from the pairs' diagonal blocks (the same
+// and the S entries of rotation m1 in rows 2 m2 and 2 m2 + 1.  It computes
+// its column rotation m2 itself from that pair's diagonal block (the same
 // inputs and operations in every lane, so every lane derives the same
-// rotation), so a round needs no cross-lane exchange.  Index x starts in
+// rotation); its row rotation m1 is the column rotation of lane 8 m1, which
+// owns the block (m1, m1) (lane = 8 m1 + (m2 - m1) mod 8 puts it at position
+// 0 or 8 of the row of 16 lanes that holds all of pair m1's blocks), and
+// arrives by two fixed row broadcasts.  Index x starts in
 // slot jacobi_slot(x) (A permuted on entry, S the matching permutation, so
 // A_in = S A S^T throughout), and the rotated entries are stored where the
 // next round's pairing wants them (rows and columns of A, columns of S moved
@@ -310,10 +329,11 @@ __device__ __noinline__ int jacobi(lds<double>* A, lds<double>* S, double off2_t
       A[jacobi_slot<KB>(i) * LD + jacobi_slot<KB>(j)] = v[u];
       S[i * LD + j] = (j == jacobi_slot<KB>(i)) ? 1.0 : 0.0;
     }
-    const unsigned m1 = (unsigned)lane / NP, m2 = (unsigned)lane % NP;
-    // read locations (fixed): the block, the two diagonal blocks, S
+    const unsigned m1 = (unsigned)lane / NP, m2 = ((unsigned)lane % NP + m1) % NP;
+    const bool odd = (m1 & 1u) != 0;  // lane 8 m1 sits at position 8 of its row
+    // read locations (fixed): the block, the column pair's diagonal block, S
     const unsigned rb = (2 * m1) * LD + 2 * m2;
-    const unsigned d1 = (2 * m1) * (LD + 1), d2 = (2 * m2) * (LD + 1);
+    const unsigned d2 = (2 * m2) * (LD + 1);
     const unsigned sr = (2 * m2) * LD + 2 * m1;
     // write locations: the block's rows and columns, S's columns, moved on
     const unsigned r0 = jacobi_slot_move<KB>(2 * m1), r1 = jacobi_slot_move<KB>(2 * m1 + 1);
@@ -333,13 +353,14 @@ __device__ __noinline__ int jacobi(lds<double>* A, lds<double>* S, double off2_t
       if (!(off > off2_tol * (off + dia))) break;  // also exits on NaN
       for (int round = 0; round < KB - 1; ++round) {
         const double a = A[rb], b = A[rb + 1], cc = A[rb + LD], d = A[rb + LD + 1];
-        const double p1 = A[d1], q1 = A[d1 + LD + 1], o1 = A[d1 + 1];
         const double p2 = A[d2], q2 = A[d2 + LD + 1], o2 = A[d2 + 1];
         const double sx0 = S[sr], sy0 = S[sr + 1], sx1 = S[sr + LD], sy1 = S[sr + LD + 1];
         __asm__ volatile("" ::: "memory");  // this round's loads, then its stores
-        double cs1, sn1, cs2, sn2;
-        jacobi_rot_sel<F32ANGLE>(p1, q1, o1, cs1, sn1);
+        double cs2, sn2;
         jacobi_rot_sel<F32ANGLE>(p2, q2, o2, cs2, sn2);
+        const double ce = row_bcast_f64(cs2, 0), co = row_bcast_f64(cs2, 8);
+        const double se = row_bcast_f64(sn2, 0), so = row_bcast_f64(sn2, 8);
+        const double cs1 = odd ? co : ce, sn1 = odd ? so : se;
         const double ra = cs1 * a - sn1 * cc, rbv = cs1 * b - sn1 * d;  // rows: J1^T
         const double rc = sn1 * a + cs1 * cc, rd = sn1 * b + cs1 * d;
         A[w00] = cs2 * ra - sn2 * rbv;                                  // columns: J2
@@ -363,22 +384,6 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   const int lo = __builtin_amdgcn_readlane((int)b, l);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Value of v in lane l (0 <= l < 16, a compile-time constant once unrolled)
-// of this lane's row of 16 lanes: one 64-bit DPP move (row_newbcast).
-__device__ __forceinline__ double row_bcast_f64(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  long long x = b;
-  switch (l) {
-#define MEG_ROW_BCAST(n) \
-  case n: x = __builtin_amdgcn_mov_dpp(b, 0x150 + n, 0xF, 0xF, false); break;
-    MEG_ROW_BCAST(0) MEG_ROW_BCAST(1) MEG_ROW_BCAST(2) MEG_ROW_BCAST(3) MEG_ROW_BCAST(4) MEG_ROW_BCAST(5)
-    MEG_ROW_BCAST(6) MEG_ROW_BCAST(7) MEG_ROW_BCAST(8) MEG_ROW_BCAST(9) MEG_ROW_BCAST(10) MEG_ROW_BCAST(11)
-    MEG_ROW_BCAST(12) MEG_ROW_BCAST(13) MEG_ROW_BCAST(14) MEG_ROW_BCAST(15)
-#undef MEG_ROW_BCAST
-  }
-  return __longlong_as_double(x);
 }
 
 // Cholesky A = R^T R (R upper) of the symmetric positive definite A (LDS,
