@@ -60,7 +60,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # valid only for the kernel sources and the launch it was measured on.
 TRAFFIC = {"bytes_per_launch": 151.1e6, "iterations_per_launch": 20, "warmup": 5, "applies_per_iteration": 2.0,
            "fetch_bytes": 90.6e6, "write_bytes": 60.5e6, "fetch_factor": 2.0, "write_factor": 1.0,
-           "source_hash": "4c74d8327f15a7a2"}
+           "source_hash": "3a81338834665f7d"}
 KERNEL_SOURCES = ["meg_device.hpp", "meg_small.hpp", "meg_kernels.hpp", "meg_api.hip"]
 
 
